@@ -1,0 +1,186 @@
+/*
+ * h4dgs.h - C ABI of the MI355X (gfx950) hybrid 3D/4D Gaussian rasterizer.
+ *
+ * The library renders a scene made of two Gaussian sets - static 3D Gaussians
+ * and dynamic 4D Gaussians - at given cameras and timestamps, differentiates
+ * the images with respect to every raw parameter, converts temporally
+ * invariant 4D Gaussians to 3D ones and applies Adam steps.  It follows the
+ * rasterization problem statement of "Hybrid 3D-4D Gaussian Splatting for Fast
+ * Dynamic Scene Representation" (Alg. 1: Rasterize(w, h, M4D, S4D, M3D, S3D,
+ * A, V, s)) and its conversion pass (Sec. 4.1-4.2).
+ *
+ * Conventions shared by every entry point
+ *  - All parameter, image and gradient arrays are DEVICE pointers to float32,
+ *    structure-of-arrays, component-major: component c of Gaussian i is at
+ *    a[c * n + i].  Arrays marked "host" are host memory.
+ *  - The caller owns every buffer.  The library never allocates device memory:
+ *    it reports the sizes it needs (h4dgs_workspace_size) and works inside the
+ *    caller's `state` and `scratch` buffers.  Device buffers must be 256-byte
+ *    aligned (any hipMalloc / PyTorch allocation is).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and returns before it completes, except where a call says it synchronises.
+ *  - Errors are return codes; nothing is thrown across the ABI.
+ *    h4dgs_last_error() gives a message for the last failing call on a context.
+ *    Argument errors are found on the host before anything is enqueued.
+ *  - A context is a small host object (tuning cache, error text); use one
+ *    context from one host thread at a time.
+ */
+#ifndef H4DGS_H
+#define H4DGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define H4DGS_MAX_VIEWS 32
+#define H4DGS_SH_ROWS 48 /* degree-3 SH: 16 coefficients x RGB, row k*3 + channel */
+
+typedef enum {
+    H4D_OK = 0,
+    H4D_ERR_INVALID_ARG = 1, /* bad pointer, size, tile size, view ... (host-side check) */
+    H4D_ERR_CAPACITY = 2,    /* the (Gaussian, tile) pairs did not fit: see h4dgs_check */
+    H4D_ERR_HIP = 3,         /* a HIP runtime call failed */
+    H4D_ERR_NONFINITE = 4,   /* reserved */
+    H4D_ERR_UNSUPPORTED = 5  /* valid request this build does not handle */
+} h4d_status;
+
+typedef struct h4d_ctx h4d_ctx;
+
+/* Static 3D Gaussians (Sec. 3.1): mean[3][n], log_scale[3][n] (scale = exp),
+ * quat[4][n] (w,x,y,z, any norm > 0: normalised inside), opacity[n] (logit:
+ * sigmoid inside), sh[48][n]. */
+typedef struct {
+    int32_t n;
+    const float *mean, *log_scale, *quat, *opacity, *sh;
+} h4d_g3d;
+
+/* Dynamic 4D Gaussians (Sec. 3.2, Eq. 4-7): spatial mean[3][n], temporal
+ * mean mean_t[n], log_scale[4][n] (x, y, z, t), quat_l[4][n] = (a,b,c,d) and
+ * quat_r[4][n] = (p,q,r,s) of the left/right isoclinic rotations, opacity[n]
+ * (logit), sh[48][n]. */
+typedef struct {
+    int32_t n;
+    const float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+} h4d_g4d;
+
+/* Writable mirrors: gradients (overwritten by h4dgs_render_bwd) and the
+ * outputs of h4dgs_convert_static.  Field meaning and layout as above. */
+typedef struct {
+    int32_t n;
+    float *mean, *log_scale, *quat, *opacity, *sh;
+} h4d_g3d_mut;
+typedef struct {
+    int32_t n;
+    float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+} h4d_g4d_mut;
+
+/* One rendered view (host struct): pinhole camera, world -> camera [R | t]
+ * row-major (camera x right, y down, z forward), focal lengths and principal
+ * point in pixels, image size, timestamp t at which the 4D set is sliced, and
+ * the background colour.  Pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
+typedef struct {
+    float world_to_cam[12];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float t;
+    float bg[3];
+} h4d_view;
+
+/* Launch configuration.  tile: tile edge in pixels (8, 16 or 32); chunk:
+ * list entries staged in LDS per round of the blending kernels (128, 256 or
+ * 512, and at least tile*tile); batched: 0 = views processed one after another,
+ * 1 = all views of a call in one pass per stage; pair_capacity: number of
+ * (Gaussian, tile) pairs the workspace holds, summed over the call's views.
+ * Images do not depend on tile or chunk (a pixel's contributors are fixed by
+ * its own square test), so these are pure performance knobs. */
+typedef struct {
+    int32_t tile;
+    int32_t chunk;
+    int32_t batched;
+    int32_t reserved;
+    int64_t pair_capacity;
+} h4d_config;
+
+h4d_status h4dgs_create(h4d_ctx **out);
+h4d_status h4dgs_destroy(h4d_ctx *ctx);
+const char *h4dgs_last_error(const h4d_ctx *ctx);
+/* Build identification string (static storage). */
+const char *h4dgs_version(void);
+
+/* Bytes of `state` (kept unchanged from render_fwd to render_bwd) and of
+ * `scratch` (free between calls) for n3 + n4 Gaussians, the given host array of
+ * n_views views and the configuration.  Pure host arithmetic. */
+h4d_status h4dgs_workspace_size(h4d_ctx *ctx, int32_t n3, int32_t n4, const h4d_view *views, int32_t n_views,
+                                const h4d_config *cfg, size_t *state_bytes, size_t *scratch_bytes);
+
+/* Forward (Alg. 1, Sec. 4.3): per view, slice every 4D Gaussian at the view's t
+ * (Eq. 5-6, opacity times the temporal marginal), merge with the 3D set
+ * (index order [4D | 3D]), cull, EWA-project, colour by SH, duplicate into
+ * (tile, depth) keys, sort, find tile ranges and blend front to back (Eq. 3).
+ * images: host array of n_views device pointers, each float[3][H][W] (planar
+ * RGB, written).  A (Gaussian, tile) pair-capacity overflow is not reported by
+ * the return code (it is known only on the device): call h4dgs_check. */
+h4d_status h4dgs_render_fwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
+                            int32_t n_views, const h4d_config *cfg, float *const *images, void *state,
+                            size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Backward: the exact adjoint of render_fwd.  dl_dimages: host array of
+ * n_views device pointers to float[3][H][W] (dL/dC, loss weighting included).
+ * The gradients of every raw parameter are OVERWRITTEN with
+ * sum_v J_v^T dl_dimages_v.  Same g3, g4, views and cfg as the forward; state
+ * as the forward left it. */
+h4d_status h4dgs_render_bwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
+                            int32_t n_views, const h4d_config *cfg, const float *const *dl_dimages,
+                            const void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
+                            h4d_g3d_mut *grad3, h4d_g4d_mut *grad4, void *stream);
+
+/* Synchronises `stream`, then reads the status the last render_fwd left in
+ * `state`.  Returns H4D_OK or H4D_ERR_CAPACITY; *pairs_needed (host, may be
+ * NULL) receives the number of pairs the call needed. */
+h4d_status h4dgs_check(h4d_ctx *ctx, const void *state, size_t state_bytes, int64_t *pairs_needed, void *stream);
+
+/* Alg. 1 lines 7-17 alone, on given screen-space splats: n splats with centre
+ * u[n], v[n], conic[3][n] (inverse 2D covariance entries 00, 01, 11), effective
+ * opacity[n], rgb[3][n], integer radius[n], depth key[n] and visible[n] (uint8).
+ * Splat i covers pixel (x, y) iff |x + 0.5 - u| <= r and |y + 0.5 - v| <= r.
+ * Writes image[3][H][W], T_final[H][W] (may be NULL) and, if sorted_ids is not
+ * NULL, the per-tile sorted splat ids (sorted_ids[pair_capacity]) and tile
+ * ranges (ranges[2 * tiles]: start, end).  Uses the same kernels as render_fwd.
+ * Workspace: h4dgs_workspace_size(n3 = n, n4 = 0, one view of W x H). */
+h4d_status h4dgs_rasterize_splats(h4d_ctx *ctx, int32_t n, const float *u, const float *v, const float *conic,
+                                  const float *opacity, const float *rgb, const int32_t *radius,
+                                  const float *depth, const uint8_t *visible, int32_t width, int32_t height,
+                                  const float *bg /* host, 3 */, const h4d_config *cfg, float *image,
+                                  float *T_final, uint32_t *sorted_ids, int64_t *ranges, void *state,
+                                  size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Static identification and 4D -> 3D conversion (Sec. 4.1-4.2, Eq. 7-9).
+ * Row i of in4 is static iff (double)log_scale_t[i] > log((double)tau).  out4
+ * receives the non-static rows in their order (capacity in4->n); out3
+ * receives the rows of in3 followed by the converted rows in ascending 4D
+ * index (capacity in3->n + in4->n).  A converted row keeps mean, the three
+ * spatial log-scales, opacity and SH bit-exactly and gets the Eq. 9
+ * quaternion of the top-left 3x3 block of R_l R_r (not renormalised).
+ * perm[n4] (device, int32): new 4D row, or -(1 + new 3D row).  Synchronises
+ * `stream`; *n4_out and *n3_out are host pointers.  out3/out4 must not alias
+ * in3/in4.  scratch: at least h4dgs_convert_scratch_bytes(n4). */
+size_t h4dgs_convert_scratch_bytes(int32_t n4);
+h4d_status h4dgs_convert_static(h4d_ctx *ctx, const h4d_g4d *in4, const h4d_g3d *in3, float tau,
+                                h4d_g4d_mut *out4, h4d_g3d_mut *out3, int32_t *perm, int32_t *n4_out,
+                                int32_t *n3_out, void *scratch, size_t scratch_bytes, void *stream);
+
+/* One bias-corrected Adam step (Kingma & Ba) over up to 16 float32 segments:
+ * p -= lr * m_hat / (sqrt(v_hat) + eps) with m, v updated in place.  Host
+ * arrays of n_seg device pointers / sizes / learning rates. */
+h4d_status h4dgs_adam(h4d_ctx *ctx, int32_t n_seg, float *const *params, const float *const *grads,
+                      float *const *m, float *const *v, const int64_t *sizes, const float *lrs, float beta1,
+                      float beta2, float eps, int32_t step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H4DGS_H */

@@ -482,26 +482,29 @@ void blend_pixel(int i, int j, const int32_t* list, int64_t len, const std::vect
         prev = g;
         const S dx = S(x) - r.u, dy = S(y) - r.v;
         const S power = S(-0.5) * (r.Q[0] * dx * dx + S(2.0) * r.Q[1] * dx * dy + r.Q[2] * dy * dy);
-        // error bound of an FP32 evaluation of power and alpha (guard band)
+        // Error bound of an FP32 evaluation of power and alpha (guard band), with
+        // u = 2^-24: float32 conic and centre fraction (u each), at most three
+        // roundings per term of the quadratic form, the offsets' rounding
+        // u (1 + |d|), exp2 within 2 ulp, two more roundings for op * G.
         const double qa = val(r.Q[0]), qb = val(r.Q[1]), qc = val(r.Q[2]), ddx = val(dx), ddy = val(dy);
         const double terms = 0.5 * (std::fabs(qa) * ddx * ddx + 2 * std::fabs(qb * ddx * ddy) + std::fabs(qc) * ddy * ddy);
-        const double grad = std::fabs(qa * ddx + qb * ddy) + std::fabs(qb * ddx + qc * ddy);
-        const double epow = 8 * kEps32 * terms + grad * kEps32 * (std::fabs(ddx) + std::fabs(ddy) + 2.0) +
-                            4 * kEps32 * std::fabs(val(power));
-        const double ealpha = epow + 6 * kEps32;
+        const double epow = 4 * kEps32 * terms + std::fabs(qa * ddx + qb * ddy) * kEps32 * (1.0 + std::fabs(ddx)) +
+                            std::fabs(qb * ddx + qc * ddy) * kEps32 * (1.0 + std::fabs(ddy)) +
+                            kEps32 * std::fabs(val(power));
+        const double ealpha = epow + 4 * kEps32;
         if (val(power) > 0.0) {
-            if (val(r.op) >= kMinAlpha && epow * 4 > val(power)) amb = true;
+            if (val(r.op) >= kMinAlpha && 2 * epow > val(power)) amb = true;
             continue;
         }
         const S Gk = exp(power);
         const S ap = r.op * Gk;
-        if (std::fabs(std::log(val(ap) / kMinAlpha)) < 4 * ealpha + 1e-7) amb = true;
+        if (std::fabs(std::log(val(ap) / kMinAlpha)) < 2 * ealpha + 1e-7) amb = true;
         const bool clamped = val(ap) > kMaxAlpha;
         const S alpha = clamped ? S(kMaxAlpha) : ap;
         if (val(alpha) < kMinAlpha) continue;
         const S Tn = T * (S(1.0) - alpha);
         const double eTn = eT + (clamped ? 0.0 : val(alpha) * ealpha / (1.0 - val(alpha))) + 2 * kEps32;
-        if (std::fabs(std::log(val(Tn) / kMinT)) < 4 * eTn + 1e-7) amb = true;
+        if (std::fabs(std::log(val(Tn) / kMinT)) < 2 * eTn + 1e-7) amb = true;
         if (val(Tn) < kMinT) break;  // this Gaussian is not blended
         for (int c = 0; c < 3; ++c) C[c] += r.rgb[c] * alpha * T;
         if (keep) keep->push_back(Blended{g, val(alpha), val(T), val(Gk), val(dx), val(dy), clamped});

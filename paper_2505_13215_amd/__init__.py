@@ -1,0 +1,12 @@
+"""MI355X-native hybrid 3D/4D Gaussian rasterizer.
+
+The HIP library ``libh4dgs.so`` (C ABI in ``include/h4dgs.h``) does all of
+the work; ``render.py`` binds it to PyTorch tensors and autograd.
+"""
+from . import _lib
+from ._lib import H4DError, version
+from .render import (G3_KEYS, G4_KEYS, H4DGSRender, Rasterizer, adam_step, convert_static, rasterize_splats,
+                     render, to_device)
+
+__all__ = ["H4DError", "version", "G3_KEYS", "G4_KEYS", "H4DGSRender", "Rasterizer", "adam_step", "convert_static",
+           "rasterize_splats", "render", "to_device", "_lib"]

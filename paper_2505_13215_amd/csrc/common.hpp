@@ -1,0 +1,112 @@
+// Shared device-side definitions of the gfx950 rasterizer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace h4d {
+
+// Rasterizer constants (the 3DGS-lineage constants the paper inherits by
+// building on that implementation, Sec. 4.3).
+constexpr double kNear = 0.2;
+constexpr double kDilate = 0.3;
+constexpr double kClampFov = 1.3;
+constexpr double kEigFloor = 0.1;
+constexpr double kSigmas = 3.0;
+constexpr double kShOffset = 0.5;
+constexpr float kMinAlpha = 1.0f / 255.0f;
+constexpr double kMinAlphaD = 1.0 / 255.0;
+constexpr float kMaxAlpha = 0.99f;
+constexpr float kMinT = 1e-4f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+constexpr int kMaxViews = 32;
+constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
+
+// Per-view constants kept in device memory (written once per call).
+struct ViewParams {
+    double R[9];
+    double T[3];
+    double campos[3];  // camera centre in world coordinates, -R^T t
+    double fx, fy, cx, cy, time;
+    float bg[3];
+    int32_t W, H;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_base;   // first global tile id of this view
+    int64_t pix_base;    // first pixel of this view in the concatenated pixel arrays
+};
+
+// Screen-space record of one (Gaussian, view): 64 bytes, one half cache line.
+//   a: (u - floor(u), v - floor(v), Q00', Q01')
+//   b: (Q11', opacity, r, g)
+//   c: (b, floor(u), floor(v), depth)         (floor values stored as float, exact)
+//   d: (x0 | x1 << 16, y0 | y1 << 16, radius, 1 if covered else 0)
+// Q' = Q * (-log2(e) / 2) with Q01' = Q01 * (-log2(e)), so that
+// exp(power) = exp2(Q00' dx^2 + Q01' dx dy + Q11' dy^2).
+struct __align__(16) Rec {
+    float4 a, b, c;
+    uint4 d;
+};
+static_assert(sizeof(Rec) == 64, "record is 64 bytes");
+
+// Status words at the head of `state`.
+struct Status {
+    unsigned long long flags;        // bit 0: pair capacity overflow
+    unsigned long long pairs_needed; // sum over views of the pairs the call needed
+    unsigned long long pad[6];
+};
+
+constexpr unsigned long long kFlagOverflow = 1ull;
+
+// Parameter views (device pointers) as the kernels see them.
+struct G3Ptr {
+    int32_t n;
+    const float *mean, *log_scale, *quat, *opacity, *sh;
+};
+struct G4Ptr {
+    int32_t n;
+    const float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+};
+struct G3Grad {
+    int32_t n;
+    float *mean, *log_scale, *quat, *opacity, *sh;
+};
+struct G4Grad {
+    int32_t n;
+    float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// One front-to-back blending step, shared bit-for-bit by the forward and the
+// backward kernels (the backward recomputes transmittance instead of storing it,
+// so both must take every decision identically).  Inputs are the LDS copy of a
+// record; dx, dy are pixel-centre minus splat-centre offsets.
+struct Splat {
+    float ui, vi, uf, vf;  // integer and fractional parts of the centre
+    float qa, qb, qc;      // scaled conic (see Rec)
+    float op;              // effective opacity
+    float cr, cg, cb;
+    int32_t x0, x1, y0, y1;
+};
+
+#pragma clang fp contract(off)
+// power2 = log2(e) * power; returns false when the splat is skipped at this pixel
+// (outside its square, power > 0 or alpha < 1/255).  alpha is min(0.99, op * G).
+__device__ __forceinline__ bool eval_splat(const Splat& s, int px, int py, float pxc, float pyc, float& dx, float& dy,
+                                           float& G, float& alpha, bool& clamped) {
+    if (px < s.x0 || px > s.x1 || py < s.y0 || py > s.y1) return false;
+    dx = (pxc - s.ui) - s.uf;
+    dy = (pyc - s.vi) - s.vf;
+    const float t = __builtin_fmaf(s.qb, dy, s.qa * dx);
+    const float p2 = __builtin_fmaf(s.qc * dy, dy, dx * t);
+    if (p2 > 0.0f) return false;
+    G = __builtin_amdgcn_exp2f(p2);
+    const float ap = s.op * G;
+    clamped = ap > kMaxAlpha;
+    alpha = clamped ? kMaxAlpha : ap;
+    return alpha >= kMinAlpha;
+}
+#pragma clang fp contract(on)
+
+}  // namespace h4d

@@ -1,0 +1,92 @@
+// Host-side launchers of the gfx950 kernels (one translation unit per stage).
+#pragma once
+
+#include "common.hpp"
+
+namespace h4d {
+
+// Mirror of h4d_view (kept free of the public header so kernels see plain PODs).
+struct ViewIn {
+    float M[12];
+    float fx, fy, cx, cy;
+    int32_t W, H;
+    float t;
+    float bg[3];
+};
+struct ViewTableIn {
+    int32_t n;
+    int32_t tile;
+    ViewIn v[kMaxViews];
+};
+
+// preprocess.hip
+void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st);
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, int tile, Rec* recs,
+                       uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
+void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
+                           const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st);
+void launch_splats_to_records(int n, const float* u, const float* v, const float* conic, const float* opacity,
+                              const float* rgb, const int32_t* radius, const float* depth, const uint8_t* visible,
+                              int W, int H, int tile, Rec* recs, uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals,
+                              hipStream_t st);
+
+// sort.hip
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kScanTile = 2048;
+
+int radix_blocks(uint64_t capacity);
+size_t radix_hist_words(uint64_t capacity);
+// One stable LSD pass over `nbits` (<= 8) bits at `shift`.  Count from *dcount
+// when dcount != null, else hcount.  vals_out index is offset by *out_offset
+// when out_offset != null.
+void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+                       const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
+                       uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st);
+int scan_blocks(int n);
+// out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
+void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigned long long* out,
+                         unsigned long long* partials, hipStream_t st);
+void launch_finalize_pairs(const unsigned long long* offsets, int n, unsigned long long* pair_base, int view,
+                           uint64_t capacity, Status* status, unsigned long long* eff_count, hipStream_t st);
+void launch_emit(const uint32_t* sorted_gid, const unsigned long long* offsets, int n, const Rec* recs, int tile,
+                 int tiles_x, const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st);
+void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,
+                   int64_t* ranges, hipStream_t st);
+void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
+void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
+void launch_zero_status(Status* s, unsigned long long* pair_base, int n_views, hipStream_t st);
+
+// composite.hip
+bool composite_supported(int tile, int chunk);
+void launch_composite_fwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
+                          const ViewParams* views, int view, int n_tiles, float* image, float* Tfin,
+                          uint32_t* ncontrib, float* Cout, hipStream_t st);
+void launch_composite_bwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
+                          const ViewParams* views, int view, int n_tiles, const float* dl, const float* Tfin,
+                          const uint32_t* ncontrib, const float* Cout, float* g2, int N, hipStream_t st);
+
+// convert.hip
+void launch_convert_static(const G4Ptr& in4, const G3Ptr& in3, double log_tau, const G4Grad& out4,
+                           const G3Grad& out3, int32_t* perm, uint32_t* flags, unsigned long long* scan,
+                           unsigned long long* partials, int32_t* counts, hipStream_t st);
+
+// adam.hip
+struct AdamSeg {
+    float* p;
+    const float* g;
+    float* m;
+    float* v;
+    int64_t n;
+    float lr;
+};
+constexpr int kMaxAdamSeg = 16;
+struct AdamTable {
+    int32_t n_seg;
+    float b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
+    AdamSeg seg[kMaxAdamSeg];
+};
+void launch_adam(const AdamTable& t, hipStream_t st);
+
+}  // namespace h4d

@@ -1,0 +1,644 @@
+// Per-Gaussian stages of the rasterizer on gfx950, forward and backward:
+// activations, covariance (Eq. 2, Eq. 4), slicing of 4D Gaussians at t (Eq. 5-6)
+// with the temporal marginal opacity, culling, EWA projection, SH colour and
+// the screen-space record that the binning and blending kernels consume.
+//
+// Geometry runs in FP64: CDNA4 issues FP64 vector FMAs at the FP32 (non-packed)
+// rate, the stage is bound by its 236-260 B/Gaussian of parameter reads, and in
+// FP64 every discrete decision of the stage (cull, radius, pixel square, depth
+// key) lands exactly where the FP64 definition puts it.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace h4d {
+
+// ---------------------------------------------------------------------------
+// Real SH basis of degree 3 (Condon-Shortley phase), evaluated as polynomials of
+// the unit viewing direction, and its gradient.
+// ---------------------------------------------------------------------------
+namespace sh {
+constexpr double C0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+constexpr double C1 = 0.4886025119029199;    // sqrt(3/(4 pi))
+constexpr double C4 = 1.0925484305920792;    // sqrt(15/pi)/2
+constexpr double C6 = 0.31539156525252005;   // sqrt(5/pi)/4
+constexpr double C8 = 0.5462742152960396;    // sqrt(15/pi)/4
+constexpr double C9 = 0.5900435899266435;    // sqrt(35/(2 pi))/4
+constexpr double C10 = 2.890611442640554;    // sqrt(105/pi)/2
+constexpr double C11 = 0.4570457994644658;   // sqrt(21/(2 pi))/4
+constexpr double C12 = 0.3731763325901154;   // sqrt(7/pi)/4
+constexpr double C14 = 1.445305721320277;    // sqrt(105/pi)/4
+}  // namespace sh
+
+__device__ inline void sh_eval(double x, double y, double z, double Y[16]) {
+    using namespace sh;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = C0;
+    Y[1] = -C1 * y;
+    Y[2] = C1 * z;
+    Y[3] = -C1 * x;
+    Y[4] = C4 * x * y;
+    Y[5] = -C4 * y * z;
+    Y[6] = C6 * (2.0 * zz - xx - yy);
+    Y[7] = -C4 * x * z;
+    Y[8] = C8 * (xx - yy);
+    Y[9] = -C9 * y * (3.0 * xx - yy);
+    Y[10] = C10 * x * y * z;
+    Y[11] = -C11 * y * (4.0 * zz - xx - yy);
+    Y[12] = C12 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = -C11 * x * (4.0 * zz - xx - yy);
+    Y[14] = C14 * z * (xx - yy);
+    Y[15] = -C9 * x * (xx - 3.0 * yy);
+}
+
+// w . dY/d(x,y,z) for a weight vector w[16] over the basis
+__device__ inline void sh_grad_dot(double x, double y, double z, const double w[16], double g[3]) {
+    using namespace sh;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    double gx = 0, gy = 0, gz = 0;
+    gy += w[1] * (-C1);
+    gz += w[2] * C1;
+    gx += w[3] * (-C1);
+    gx += w[4] * C4 * y;            gy += w[4] * C4 * x;
+    gy += w[5] * (-C4 * z);         gz += w[5] * (-C4 * y);
+    gx += w[6] * (-2.0 * C6 * x);   gy += w[6] * (-2.0 * C6 * y);  gz += w[6] * (4.0 * C6 * z);
+    gx += w[7] * (-C4 * z);         gz += w[7] * (-C4 * x);
+    gx += w[8] * (2.0 * C8 * x);    gy += w[8] * (-2.0 * C8 * y);
+    gx += w[9] * (-6.0 * C9 * x * y);              gy += w[9] * (-C9 * (3.0 * xx - 3.0 * yy));
+    gx += w[10] * C10 * y * z;      gy += w[10] * C10 * x * z;     gz += w[10] * C10 * x * y;
+    gx += w[11] * (2.0 * C11 * x * y);             gy += w[11] * (-C11 * (4.0 * zz - xx - 3.0 * yy));
+    gz += w[11] * (-8.0 * C11 * y * z);
+    gx += w[12] * (-6.0 * C12 * x * z);            gy += w[12] * (-6.0 * C12 * y * z);
+    gz += w[12] * (C12 * (6.0 * zz - 3.0 * xx - 3.0 * yy));
+    gx += w[13] * (-C11 * (4.0 * zz - 3.0 * xx - yy)); gy += w[13] * (2.0 * C11 * x * y);
+    gz += w[13] * (-8.0 * C11 * x * z);
+    gx += w[14] * (2.0 * C14 * x * z);             gy += w[14] * (-2.0 * C14 * y * z);
+    gz += w[14] * (C14 * (xx - yy));
+    gx += w[15] * (-C9 * (3.0 * xx - 3.0 * yy));   gy += w[15] * (6.0 * C9 * x * y);
+    g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+// ---------------------------------------------------------------------------
+// World stage (view independent except for the timestamp of a 4D Gaussian).
+// ---------------------------------------------------------------------------
+struct WorldF {
+    double mu[3];
+    double S[3][3];  // covariance at time t
+    double op;       // sigmoid(o) * p(t)
+};
+
+struct Rot4 {
+    double L[4][4], Rr[4][4], R[4][4];
+};
+
+__device__ inline void rot_left(const double q[4], double M[4][4]) {
+    const double a = q[0], b = q[1], c = q[2], d = q[3];
+    M[0][0] = a; M[0][1] = -b; M[0][2] = -c; M[0][3] = -d;
+    M[1][0] = b; M[1][1] = a;  M[1][2] = -d; M[1][3] = c;
+    M[2][0] = c; M[2][1] = d;  M[2][2] = a;  M[2][3] = -b;
+    M[3][0] = d; M[3][1] = -c; M[3][2] = b;  M[3][3] = a;
+}
+__device__ inline void rot_right(const double q[4], double M[4][4]) {
+    const double p = q[0], qq = q[1], r = q[2], s = q[3];
+    M[0][0] = p;  M[0][1] = -qq; M[0][2] = -r;  M[0][3] = -s;
+    M[1][0] = qq; M[1][1] = p;   M[1][2] = s;   M[1][3] = -r;
+    M[2][0] = r;  M[2][1] = -s;  M[2][2] = p;   M[2][3] = qq;
+    M[3][0] = s;  M[3][1] = r;   M[3][2] = -qq; M[3][3] = p;
+}
+
+__device__ inline double load_unit4(const float* q, int n, int i, double out[4]) {
+    double a[4];
+    for (int k = 0; k < 4; ++k) a[k] = (double)q[(size_t)k * n + i];
+    const double nrm = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+    const double inv = 1.0 / nrm;
+    for (int k = 0; k < 4; ++k) out[k] = a[k] * inv;
+    return nrm;
+}
+
+__device__ inline void quat_rot3(const double q[4], double R[3][3]) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0][0] = 1.0 - 2.0 * (y * y + z * z); R[0][1] = 2.0 * (x * y - w * z); R[0][2] = 2.0 * (x * z + w * y);
+    R[1][0] = 2.0 * (x * y + w * z); R[1][1] = 1.0 - 2.0 * (x * x + z * z); R[1][2] = 2.0 * (y * z - w * x);
+    R[2][0] = 2.0 * (x * z - w * y); R[2][1] = 2.0 * (y * z + w * x); R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__device__ inline double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+// 4D Gaussian i at time t.  Fills the 4D intermediates the adjoint needs.
+struct Slice4 {
+    double s[4], ql[4], qr[4], nl, nr;
+    Rot4 rot;
+    double S4[4][4];
+    double b[3], c, delta, pt, sig;
+};
+
+__device__ inline void world4(const G4Ptr& g, int i, double time, WorldF& w, Slice4& z) {
+    const int n = g.n;
+    for (int k = 0; k < 4; ++k) z.s[k] = exp((double)g.log_scale[(size_t)k * n + i]);
+    z.nl = load_unit4(g.quat_l, n, i, z.ql);
+    z.nr = load_unit4(g.quat_r, n, i, z.qr);
+    rot_left(z.ql, z.rot.L);
+    rot_right(z.qr, z.rot.Rr);
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 4; ++k) acc += z.rot.L[r][k] * z.rot.Rr[k][c];
+            z.rot.R[r][c] = acc;
+        }
+    double s2[4];
+    for (int k = 0; k < 4; ++k) s2[k] = z.s[k] * z.s[k];
+    for (int r = 0; r < 4; ++r)
+        for (int c = r; c < 4; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 4; ++k) acc += z.rot.R[r][k] * s2[k] * z.rot.R[c][k];
+            z.S4[r][c] = acc;
+            z.S4[c][r] = acc;
+        }
+    // Eq. 5-6: condition the spatial block on time
+    z.c = z.S4[3][3];
+    z.delta = time - (double)g.mean_t[i];
+    const double ic = 1.0 / z.c;
+    for (int k = 0; k < 3; ++k) z.b[k] = z.S4[k][3];
+    for (int k = 0; k < 3; ++k) w.mu[k] = (double)g.mean[(size_t)k * n + i] + z.b[k] * ic * z.delta;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) w.S[r][c] = z.S4[r][c] - z.b[r] * z.b[c] * ic;
+    z.pt = exp(-(z.delta * z.delta) * 0.5 * ic);
+    z.sig = sigmoid((double)g.opacity[i]);
+    w.op = z.sig * z.pt;
+}
+
+struct Cov3 {
+    double s[3], q[4], nq, R[3][3], sig;
+};
+
+__device__ inline void world3(const G3Ptr& g, int i, WorldF& w, Cov3& z) {
+    const int n = g.n;
+    for (int k = 0; k < 3; ++k) z.s[k] = exp((double)g.log_scale[(size_t)k * n + i]);
+    z.nq = load_unit4(g.quat, n, i, z.q);
+    quat_rot3(z.q, z.R);
+    for (int r = 0; r < 3; ++r)
+        for (int c = r; c < 3; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += z.R[r][k] * z.s[k] * z.s[k] * z.R[c][k];
+            w.S[r][c] = acc;
+            w.S[c][r] = acc;
+        }
+    for (int k = 0; k < 3; ++k) w.mu[k] = (double)g.mean[(size_t)k * n + i];
+    z.sig = sigmoid((double)g.opacity[i]);
+    w.op = z.sig;
+}
+
+// ---------------------------------------------------------------------------
+// Projection stage.
+// ---------------------------------------------------------------------------
+struct ProjF {
+    bool culled, covered;
+    double pc[3], x, y, xt, yt;
+    bool clx, cly;
+    double M[2][3];
+    double a, b, d, det;
+    double u, v;
+    int r, x0, x1, y0, y1;
+    double dir[3], en;
+};
+
+__device__ inline void project(const ViewParams& V, const WorldF& w, ProjF& p) {
+    p.culled = true;
+    p.covered = false;
+    for (int i = 0; i < 3; ++i)
+        p.pc[i] = V.R[3 * i] * w.mu[0] + V.R[3 * i + 1] * w.mu[1] + V.R[3 * i + 2] * w.mu[2] + V.T[i];
+    if (p.pc[2] <= kNear || w.op < kMinAlphaD) return;
+    const double iz = 1.0 / p.pc[2];
+    p.x = p.pc[0] * iz;
+    p.y = p.pc[1] * iz;
+    const double limx = kClampFov * (0.5 * V.W / V.fx), limy = kClampFov * (0.5 * V.H / V.fy);
+    p.clx = p.x > limx || p.x < -limx;
+    p.cly = p.y > limy || p.y < -limy;
+    p.xt = fmin(fmax(p.x, -limx), limx);
+    p.yt = fmin(fmax(p.y, -limy), limy);
+    const double J00 = V.fx * iz, J02 = -V.fx * p.xt * iz, J11 = V.fy * iz, J12 = -V.fy * p.yt * iz;
+    for (int j = 0; j < 3; ++j) {
+        p.M[0][j] = J00 * V.R[j] + J02 * V.R[6 + j];
+        p.M[1][j] = J11 * V.R[3 + j] + J12 * V.R[6 + j];
+    }
+    // 2D covariance M S M^T (+ dilation)
+    double MS[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) MS[r][c] = p.M[r][0] * w.S[0][c] + p.M[r][1] * w.S[1][c] + p.M[r][2] * w.S[2][c];
+    p.a = MS[0][0] * p.M[0][0] + MS[0][1] * p.M[0][1] + MS[0][2] * p.M[0][2] + kDilate;
+    p.b = MS[0][0] * p.M[1][0] + MS[0][1] * p.M[1][1] + MS[0][2] * p.M[1][2];
+    p.d = MS[1][0] * p.M[1][0] + MS[1][1] * p.M[1][1] + MS[1][2] * p.M[1][2] + kDilate;
+    p.det = p.a * p.d - p.b * p.b;
+    if (p.det <= 0.0) return;
+    const double mid = 0.5 * (p.a + p.d);
+    const double lam = mid + sqrt(fmax(kEigFloor, mid * mid - p.det));
+    p.r = (int)ceil(kSigmas * sqrt(lam));
+    p.u = V.fx * p.x + V.cx;
+    p.v = V.fy * p.y + V.cy;
+    // pixel square |i + 0.5 - u| <= r, clipped to the image
+    p.x0 = max(0, (int)ceil(p.u - p.r - 0.5));
+    p.x1 = min(V.W - 1, (int)floor(p.u + p.r - 0.5));
+    p.y0 = max(0, (int)ceil(p.v - p.r - 0.5));
+    p.y1 = min(V.H - 1, (int)floor(p.v + p.r - 0.5));
+    p.culled = false;
+    p.covered = p.x0 <= p.x1 && p.y0 <= p.y1;
+    double e[3] = {w.mu[0] - V.campos[0], w.mu[1] - V.campos[1], w.mu[2] - V.campos[2]};
+    p.en = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    const double ie = 1.0 / p.en;
+    for (int k = 0; k < 3; ++k) p.dir[k] = e[k] * ie;
+}
+
+// raw (unclamped) colour of channel ch: 0.5 + sum_k sh[k][ch] Y_k
+__device__ inline void colour(const float* shp, int n, int i, const double Y[16], double raw[3]) {
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = kShOffset;
+        for (int k = 0; k < 16; ++k) acc += (double)shp[(size_t)(k * 3 + ch) * n + i] * Y[k];
+        raw[ch] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward kernel: one thread per Gaussian of the merged list [4D | 3D].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const ViewParams* __restrict__ views,
+                                                    int view, int tile, Rec* __restrict__ recs,
+                                                    uint32_t* __restrict__ ntiles, uint32_t* __restrict__ dkeys,
+                                                    uint32_t* __restrict__ dvals) {
+    const int N = g3.n + g4.n;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const ViewParams& V = views[view];
+    WorldF w;
+    const float* shp;
+    int shn, shi;
+    if (g < g4.n) {
+        Slice4 z;
+        world4(g4, g, V.time, w, z);
+        shp = g4.sh; shn = g4.n; shi = g;
+    } else {
+        Cov3 z;
+        world3(g3, g - g4.n, w, z);
+        shp = g3.sh; shn = g3.n; shi = g - g4.n;
+    }
+    ProjF p;
+    project(V, w, p);
+    Rec rec;
+    uint32_t nt = 0;
+    uint32_t key = kCulledKey;
+    if (!p.culled && p.covered) {
+        const double iD = 1.0 / p.det;
+        const double Qa = p.d * iD, Qb = -p.b * iD, Qc = p.a * iD;
+        const double s = -0.5 * 1.4426950408889634;  // -log2(e)/2
+        double Y[16], raw[3];
+        sh_eval(p.dir[0], p.dir[1], p.dir[2], Y);
+        colour(shp, shn, shi, Y, raw);
+        const double fu = floor(p.u), fv = floor(p.v);
+        rec.a = make_float4((float)(p.u - fu), (float)(p.v - fv), (float)(Qa * s), (float)(Qb * 2.0 * s));
+        rec.b = make_float4((float)(Qc * s), (float)w.op, (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0));
+        const float depth = (float)p.pc[2];
+        rec.c = make_float4((float)fmax(raw[2], 0.0), (float)fu, (float)fv, depth);
+        rec.d = make_uint4((uint32_t)p.x0 | ((uint32_t)p.x1 << 16), (uint32_t)p.y0 | ((uint32_t)p.y1 << 16),
+                           (uint32_t)p.r, 1u);
+        nt = (uint32_t)((p.x1 / tile - p.x0 / tile + 1) * (p.y1 / tile - p.y0 / tile + 1));
+        key = __float_as_uint(depth);
+    } else {
+        rec.a = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec.b = rec.a;
+        rec.c = rec.a;
+        rec.d = make_uint4(0u, 0u, 0u, 0u);
+    }
+    recs[g] = rec;
+    ntiles[g] = nt;
+    dkeys[g] = key;
+    dvals[g] = (uint32_t)g;
+}
+
+// ---------------------------------------------------------------------------
+// Backward kernel: one thread per Gaussian, looping over the views of the call
+// (no atomics: every view's contribution to a Gaussian lands in one lane).
+// g2: per (view, Gaussian) screen-space gradients from the blending adjoint,
+// layout [view][9][N]: du dv dQ00 dQ01 dQ11 dop dr dg db (w.r.t. the unscaled
+// conic entries, Q01 counted once).
+// ---------------------------------------------------------------------------
+struct Acc {
+    double mu[3], mt, ls[4], q[4], q2[4], op, sh[48];
+};
+
+__device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const ProjF& p, const float* shp, int shn,
+                                int shi, const float* g2, size_t gstride, double gmu[3], double Sb[3][3],
+                                double& gop, double* gsh) {
+    const double gu = g2[0], gv = g2[gstride], gQa = g2[2 * gstride], gQb = g2[3 * gstride],
+                 gQc = g2[4 * gstride];
+    gop = g2[5 * gstride];
+    const double grgb[3] = {g2[6 * gstride], g2[7 * gstride], g2[8 * gstride]};
+    // colour
+    double Y[16], raw[3];
+    sh_eval(p.dir[0], p.dir[1], p.dir[2], Y);
+    colour(shp, shn, shi, Y, raw);
+    double wY[16];
+    for (int k = 0; k < 16; ++k) wY[k] = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+        const double gc = raw[ch] > 0.0 ? grgb[ch] : 0.0;
+        for (int k = 0; k < 16; ++k) {
+            gsh[k * 3 + ch] += gc * Y[k];
+            wY[k] += gc * (double)shp[(size_t)(k * 3 + ch) * shn + shi];
+        }
+    }
+    double gd[3];
+    sh_grad_dot(p.dir[0], p.dir[1], p.dir[2], wY, gd);
+    const double dd = p.dir[0] * gd[0] + p.dir[1] * gd[1] + p.dir[2] * gd[2];
+    const double ie = 1.0 / p.en;
+    for (int k = 0; k < 3; ++k) gmu[k] = (gd[k] - p.dir[k] * dd) * ie;
+    // conic -> 2D covariance: S2bar = -Q Gbar Q, Gbar = [[gQa, gQb/2], [gQb/2, gQc]]
+    const double iD = 1.0 / p.det;
+    const double Q00 = p.d * iD, Q01 = -p.b * iD, Q11 = p.a * iD;
+    const double G00 = gQa, G01 = 0.5 * gQb, G11 = gQc;
+    const double T00 = Q00 * G00 + Q01 * G01, T01 = Q00 * G01 + Q01 * G11;
+    const double T10 = Q01 * G00 + Q11 * G01, T11 = Q01 * G01 + Q11 * G11;
+    const double B00 = -(T00 * Q00 + T01 * Q01), B01 = -(T00 * Q01 + T01 * Q11);
+    const double B11 = -(T10 * Q01 + T11 * Q11);
+    const double Bm[2][2] = {{B00, B01}, {B01, B11}};
+    // Sigma_c bar = M^T B M
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l) acc += p.M[k][i] * Bm[k][l] * p.M[l][j];
+            Sb[i][j] = acc;
+        }
+    // M bar = 2 B M Sigma_c ; J bar = M bar R^T
+    double MS[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) MS[r][c] = p.M[r][0] * w.S[0][c] + p.M[r][1] * w.S[1][c] + p.M[r][2] * w.S[2][c];
+    double Mb[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) Mb[r][c] = 2.0 * (Bm[r][0] * MS[0][c] + Bm[r][1] * MS[1][c]);
+    double Jb[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k) Jb[r][k] = Mb[r][0] * V.R[3 * k] + Mb[r][1] * V.R[3 * k + 1] + Mb[r][2] * V.R[3 * k + 2];
+    const double z = p.pc[2], iz = 1.0 / z, iz2 = iz * iz;
+    double pb[3] = {0, 0, 0};
+    pb[2] += -Jb[0][0] * V.fx * iz2 + Jb[0][2] * V.fx * p.xt * iz2 - Jb[1][1] * V.fy * iz2 + Jb[1][2] * V.fy * p.yt * iz2;
+    double xb = gu * V.fx, yb = gv * V.fy;
+    if (!p.clx) xb += -Jb[0][2] * V.fx * iz;
+    if (!p.cly) yb += -Jb[1][2] * V.fy * iz;
+    pb[0] += xb * iz;
+    pb[1] += yb * iz;
+    pb[2] += -(xb * p.pc[0] + yb * p.pc[1]) * iz2;
+    for (int k = 0; k < 3; ++k) gmu[k] += V.R[k] * pb[0] + V.R[3 + k] * pb[1] + V.R[6 + k] * pb[2];
+}
+
+// Sigma = Lm Lm^T, Lm = R diag(s): returns Rbar and accumulates dlog_scale.
+template <int D>
+__device__ inline void cov_bwd(const double Sb[D][D], const double R[D][D], const double s[D], double Rb[D][D],
+                               double* gls) {
+    double Lb[D][D];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            double acc = 0;
+            for (int k = 0; k < D; ++k) acc += (Sb[i][k] + Sb[k][i]) * R[k][j] * s[j];
+            Lb[i][j] = acc;
+        }
+    for (int j = 0; j < D; ++j) {
+        double acc = 0;
+        for (int i = 0; i < D; ++i) acc += R[i][j] * Lb[i][j];
+        gls[j] += acc * s[j];
+    }
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) Rb[i][j] = Lb[i][j] * s[j];
+}
+
+__device__ inline void unit_bwd(const double qh[4], double nrm, const double gqh[4], double* gq) {
+    const double dq = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
+    const double in = 1.0 / nrm;
+    for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - qh[k] * dq) * in;
+}
+
+__global__ void __launch_bounds__(128) k_preprocess_bwd(G3Ptr g3, G4Ptr g4, const ViewParams* __restrict__ views,
+                                                        int n_views, const Rec* __restrict__ recs,
+                                                        const float* __restrict__ g2, G3Grad gr3, G4Grad gr4) {
+    const int N = g3.n + g4.n;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const bool is4 = g < g4.n;
+    Acc acc;
+    for (int k = 0; k < 3; ++k) acc.mu[k] = 0;
+    acc.mt = 0; acc.op = 0;
+    for (int k = 0; k < 4; ++k) { acc.ls[k] = 0; acc.q[k] = 0; acc.q2[k] = 0; }
+    for (int k = 0; k < 48; ++k) acc.sh[k] = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (recs[(size_t)v * N + g].d.w == 0u) continue;  // not covering any pixel in this view
+        const ViewParams& V = views[v];
+        const float* gv = g2 + (size_t)v * 9 * N + g;
+        WorldF w;
+        ProjF p;
+        double gmu[3], Sb[3][3], gop;
+        if (is4) {
+            Slice4 z;
+            world4(g4, g, V.time, w, z);
+            project(V, w, p);
+            proj_bwd(V, w, p, g4.sh, g4.n, g, gv, (size_t)N, gmu, Sb, gop, acc.sh);
+            // effective opacity sigma * p(t)
+            const double gsig = gop * z.pt, gpt = gop * z.sig;
+            acc.op += gsig * z.sig * (1.0 - z.sig);
+            const double ic = 1.0 / z.c;
+            double gmt = gpt * z.pt * z.delta * ic;
+            double gc = gpt * z.pt * z.delta * z.delta * 0.5 * ic * ic;
+            const double mub = gmu[0] * z.b[0] + gmu[1] * z.b[1] + gmu[2] * z.b[2];
+            double gb[3];
+            for (int k = 0; k < 3; ++k) {
+                acc.mu[k] += gmu[k];
+                gb[k] = gmu[k] * z.delta * ic;
+            }
+            gmt -= mub * ic;
+            gc -= mub * z.delta * ic * ic;
+            double bSb = 0;
+            for (int i = 0; i < 3; ++i) {
+                double r = 0;
+                for (int j = 0; j < 3; ++j) {
+                    bSb += z.b[i] * Sb[i][j] * z.b[j];
+                    r += (Sb[i][j] + Sb[j][i]) * z.b[j];
+                }
+                gb[i] -= r * ic;
+            }
+            gc += bSb * ic * ic;
+            acc.mt += gmt;
+            double S4b[4][4];
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) S4b[i][j] = Sb[i][j];
+                S4b[i][3] = gb[i];
+                S4b[3][i] = 0.0;
+            }
+            S4b[3][3] = gc;
+            double Rb[4][4];
+            cov_bwd<4>(S4b, z.rot.R, z.s, Rb, acc.ls);
+            // R = L Rr: Lbar = Rbar Rr^T, Rrbar = L^T Rbar
+            double Lb[4][4], Rrb[4][4];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    double a1 = 0, a2 = 0;
+                    for (int k = 0; k < 4; ++k) {
+                        a1 += Rb[i][k] * z.rot.Rr[j][k];
+                        a2 += z.rot.L[k][i] * Rb[k][j];
+                    }
+                    Lb[i][j] = a1;
+                    Rrb[i][j] = a2;
+                }
+            double gl[4], grr[4];
+            gl[0] = Lb[0][0] + Lb[1][1] + Lb[2][2] + Lb[3][3];
+            gl[1] = -Lb[0][1] + Lb[1][0] - Lb[2][3] + Lb[3][2];
+            gl[2] = -Lb[0][2] + Lb[1][3] + Lb[2][0] - Lb[3][1];
+            gl[3] = -Lb[0][3] - Lb[1][2] + Lb[2][1] + Lb[3][0];
+            grr[0] = Rrb[0][0] + Rrb[1][1] + Rrb[2][2] + Rrb[3][3];
+            grr[1] = -Rrb[0][1] + Rrb[1][0] + Rrb[2][3] - Rrb[3][2];
+            grr[2] = -Rrb[0][2] - Rrb[1][3] + Rrb[2][0] + Rrb[3][1];
+            grr[3] = -Rrb[0][3] + Rrb[1][2] - Rrb[2][1] + Rrb[3][0];
+            unit_bwd(z.ql, z.nl, gl, acc.q);
+            unit_bwd(z.qr, z.nr, grr, acc.q2);
+        } else {
+            Cov3 z;
+            const int i = g - g4.n;
+            world3(g3, i, w, z);
+            project(V, w, p);
+            proj_bwd(V, w, p, g3.sh, g3.n, i, gv, (size_t)N, gmu, Sb, gop, acc.sh);
+            acc.op += gop * z.sig * (1.0 - z.sig);
+            for (int k = 0; k < 3; ++k) acc.mu[k] += gmu[k];
+            double Rb[3][3];
+            cov_bwd<3>(Sb, z.R, z.s, Rb, acc.ls);
+            const double qw = z.q[0], qx = z.q[1], qy = z.q[2], qz = z.q[3];
+            double gq[4];
+            gq[0] = 2.0 * (-qz * Rb[0][1] + qy * Rb[0][2] + qz * Rb[1][0] - qx * Rb[1][2] - qy * Rb[2][0] + qx * Rb[2][1]);
+            gq[1] = 2.0 * (qy * Rb[0][1] + qz * Rb[0][2] + qy * Rb[1][0] - 2.0 * qx * Rb[1][1] - qw * Rb[1][2] +
+                           qz * Rb[2][0] + qw * Rb[2][1] - 2.0 * qx * Rb[2][2]);
+            gq[2] = 2.0 * (-2.0 * qy * Rb[0][0] + qx * Rb[0][1] + qw * Rb[0][2] + qx * Rb[1][0] + qz * Rb[1][2] -
+                           qw * Rb[2][0] + qz * Rb[2][1] - 2.0 * qy * Rb[2][2]);
+            gq[3] = 2.0 * (-2.0 * qz * Rb[0][0] - qw * Rb[0][1] + qx * Rb[0][2] + qw * Rb[1][0] - 2.0 * qz * Rb[1][1] +
+                           qy * Rb[1][2] + qx * Rb[2][0] + qy * Rb[2][1]);
+            unit_bwd(z.q, z.nq, gq, acc.q);
+        }
+    }
+    if (is4) {
+        const size_t n = (size_t)g4.n, i = (size_t)g;
+        for (int k = 0; k < 3; ++k) gr4.mean[k * n + i] = (float)acc.mu[k];
+        gr4.mean_t[i] = (float)acc.mt;
+        for (int k = 0; k < 4; ++k) gr4.log_scale[k * n + i] = (float)acc.ls[k];
+        for (int k = 0; k < 4; ++k) gr4.quat_l[k * n + i] = (float)acc.q[k];
+        for (int k = 0; k < 4; ++k) gr4.quat_r[k * n + i] = (float)acc.q2[k];
+        gr4.opacity[i] = (float)acc.op;
+        for (int k = 0; k < 48; ++k) gr4.sh[k * n + i] = (float)acc.sh[k];
+    } else {
+        const size_t n = (size_t)g3.n, i = (size_t)(g - g4.n);
+        for (int k = 0; k < 3; ++k) gr3.mean[k * n + i] = (float)acc.mu[k];
+        for (int k = 0; k < 3; ++k) gr3.log_scale[k * n + i] = (float)acc.ls[k];
+        for (int k = 0; k < 4; ++k) gr3.quat[k * n + i] = (float)acc.q[k];
+        gr3.opacity[i] = (float)acc.op;
+        for (int k = 0; k < 48; ++k) gr3.sh[k * n + i] = (float)acc.sh[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-call view table: widened to FP64, camera centre -R^T t, tile bookkeeping.
+// ---------------------------------------------------------------------------
+__global__ void k_write_views(ViewTableIn in, ViewParams* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int tile_base = 0;
+    long long pix_base = 0;
+    for (int v = 0; v < in.n; ++v) {
+        const ViewIn& s = in.v[v];
+        ViewParams p;
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) p.R[3 * i + j] = (double)s.M[4 * i + j];
+            p.T[i] = (double)s.M[4 * i + 3];
+        }
+        for (int j = 0; j < 3; ++j) p.campos[j] = -(p.R[j] * p.T[0] + p.R[3 + j] * p.T[1] + p.R[6 + j] * p.T[2]);
+        p.fx = s.fx; p.fy = s.fy; p.cx = s.cx; p.cy = s.cy; p.time = s.t;
+        for (int c = 0; c < 3; ++c) p.bg[c] = s.bg[c];
+        p.W = s.W; p.H = s.H;
+        p.tiles_x = ceil_div(s.W, in.tile);
+        p.tiles_y = ceil_div(s.H, in.tile);
+        p.tile_base = tile_base;
+        p.pix_base = pix_base;
+        tile_base += p.tiles_x * p.tiles_y;
+        pix_base += (long long)s.W * s.H;
+        out[v] = p;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st) {
+    k_write_views<<<1, 1, 0, st>>>(in, out);
+}
+
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, int tile, Rec* recs,
+                       uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
+    const int N = g3.n + g4.n;
+    if (N == 0) return;
+    k_preprocess<<<ceil_div(N, 256), 256, 0, st>>>(g3, g4, views, view, tile, recs, ntiles, dkeys, dvals);
+}
+
+void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
+                           const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st) {
+    const int N = g3.n + g4.n;
+    if (N == 0) return;
+    k_preprocess_bwd<<<ceil_div(N, 128), 128, 0, st>>>(g3, g4, views, n_views, recs, g2, gr3, gr4);
+}
+
+}  // namespace h4d
+
+namespace h4d {
+
+// Screen-space splats given directly (Alg. 1 lines 7-17 without projection):
+// the same record format, pixel square computed in FP64 from (u, v, r).
+__global__ void __launch_bounds__(256) k_splats_to_records(int n, const float* __restrict__ u,
+                                                           const float* __restrict__ v,
+                                                           const float* __restrict__ conic,
+                                                           const float* __restrict__ opacity,
+                                                           const float* __restrict__ rgb,
+                                                           const int32_t* __restrict__ radius,
+                                                           const float* __restrict__ depth,
+                                                           const uint8_t* __restrict__ visible, int W, int H,
+                                                           int tile, Rec* __restrict__ recs,
+                                                           uint32_t* __restrict__ ntiles,
+                                                           uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Rec rec;
+    rec.a = make_float4(0.f, 0.f, 0.f, 0.f);
+    rec.b = rec.a;
+    rec.c = rec.a;
+    rec.d = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t nt = 0, key = kCulledKey;
+    const int r = radius[i];
+    if (visible[i] && r >= 0) {
+        const double uu = u[i], vv = v[i];
+        const int x0 = max(0, (int)ceil(uu - r - 0.5)), x1 = min(W - 1, (int)floor(uu + r - 0.5));
+        const int y0 = max(0, (int)ceil(vv - r - 0.5)), y1 = min(H - 1, (int)floor(vv + r - 0.5));
+        if (x0 <= x1 && y0 <= y1) {
+            const double s = -0.5 * 1.4426950408889634;
+            const double fu = floor(uu), fv = floor(vv);
+            rec.a = make_float4((float)(uu - fu), (float)(vv - fv), (float)((double)conic[i] * s),
+                                (float)((double)conic[(size_t)n + i] * 2.0 * s));
+            rec.b = make_float4((float)((double)conic[2 * (size_t)n + i] * s), opacity[i], rgb[i], rgb[(size_t)n + i]);
+            rec.c = make_float4(rgb[2 * (size_t)n + i], (float)fu, (float)fv, depth[i]);
+            rec.d = make_uint4((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16), (uint32_t)r, 1u);
+            nt = (uint32_t)((x1 / tile - x0 / tile + 1) * (y1 / tile - y0 / tile + 1));
+            key = __float_as_uint(depth[i]);
+        }
+    }
+    recs[i] = rec;
+    ntiles[i] = nt;
+    dkeys[i] = key;
+    dvals[i] = (uint32_t)i;
+}
+
+void launch_splats_to_records(int n, const float* u, const float* v, const float* conic, const float* opacity,
+                              const float* rgb, const int32_t* radius, const float* depth, const uint8_t* visible,
+                              int W, int H, int tile, Rec* recs, uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals,
+                              hipStream_t st) {
+    if (n == 0) return;
+    k_splats_to_records<<<ceil_div(n, 256), 256, 0, st>>>(n, u, v, conic, opacity, rgb, radius, depth, visible, W, H,
+                                                          tile, recs, ntiles, dkeys, dvals);
+}
+
+}  // namespace h4d

@@ -1,0 +1,265 @@
+"""PyTorch front end: device memory, streams and one ``torch.autograd.Function``.
+
+PyTorch only allocates buffers and supplies the current HIP stream; every
+stage of the rasterizer runs inside ``libh4dgs.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+G3_KEYS = ("mean", "log_scale", "quat", "opacity", "sh")
+G4_KEYS = ("mean", "mean_t", "log_scale", "quat_l", "quat_r", "opacity", "sh")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+def _chk(t: torch.Tensor, name: str) -> torch.Tensor:
+    if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor, got {t.dtype} on {t.device}")
+    return t
+
+
+def g3_struct(g3: dict, mut=False):
+    n = int(g3["opacity"].shape[0])
+    for k in G3_KEYS:
+        _chk(g3[k], "g3." + k)
+    return L.G3D(n, *[_ptr(g3[k]) for k in G3_KEYS])
+
+
+def g4_struct(g4: dict):
+    n = int(g4["opacity"].shape[0])
+    for k in G4_KEYS:
+        _chk(g4[k], "g4." + k)
+    return L.G4D(n, *[_ptr(g4[k]) for k in G4_KEYS])
+
+
+def to_device(d: dict, device="cuda") -> dict:
+    return {k: torch.as_tensor(v, dtype=torch.float32, device=device).contiguous() for k, v in d.items()}
+
+
+@dataclass
+class FwdHandle:
+    generation: int
+    views: object      # ctypes View array
+    n_views: int
+    cfg: L.Config
+    n3: int
+    n4: int
+    state: torch.Tensor
+    images: list
+
+
+class Rasterizer:
+    """Owns a context, the launch configuration and the workspace tensors.
+
+    ``check`` selects when the pair-capacity status is read back: "eager" (after
+    every forward, one stream synchronisation, re-rendering with a larger
+    capacity on overflow) or "deferred" (read back by ``verify()``; a forward
+    whose pairs did not fit raises there)."""
+
+    def __init__(self, tile: int = 16, chunk: int = 256, pair_capacity: int = 1 << 22, growth: float = 1.3,
+                 check: str = "eager"):
+        self.ctx = L.Context()
+        self.tile, self.chunk = int(tile), int(chunk)
+        self.capacity = int(pair_capacity)
+        self.growth = float(growth)
+        self.check_mode = check
+        self._state = None
+        self._scratch = None
+        self._gen = 0
+        self._pending = None
+        self.last_pairs = 0
+
+    # -- workspace -------------------------------------------------------------
+    def config(self) -> L.Config:
+        return L.Config(self.tile, self.chunk, 0, 0, self.capacity)
+
+    def sizes(self, n3: int, n4: int, views_arr, n_views: int):
+        st, sc = C.c_size_t(), C.c_size_t()
+        cfg = self.config()
+        self.ctx.check(self.ctx.L.h4dgs_workspace_size(self.ctx.h, n3, n4, views_arr, n_views, C.byref(cfg),
+                                                       C.byref(st), C.byref(sc)))
+        return int(st.value), int(sc.value)
+
+    def _ensure(self, n3, n4, views_arr, n_views):
+        st, sc = self.sizes(n3, n4, views_arr, n_views)
+        if self._state is None or self._state.numel() < st:
+            self._state = torch.empty(max(st, 256), dtype=torch.uint8, device="cuda")
+        if self._scratch is None or self._scratch.numel() < sc:
+            self._scratch = torch.empty(max(sc, 256), dtype=torch.uint8, device="cuda")
+
+    # -- forward / backward -----------------------------------------------------
+    def forward(self, g3: dict, g4: dict, views) -> FwdHandle:
+        if self._pending is not None and self.check_mode == "eager":
+            self._pending = None
+        s3, s4 = g3_struct(g3), g4_struct(g4)
+        n_views = len(views)
+        va = L.view_array(views)
+        images = [torch.empty((3, v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
+        for _attempt in range(3):
+            self._ensure(s3.n, s4.n, va, n_views)
+            cfg = self.config()
+            imgs = L.ptr_array([im.data_ptr() for im in images])
+            self.ctx.check(self.ctx.L.h4dgs_render_fwd(
+                self.ctx.h, C.byref(s3), C.byref(s4), va, n_views, C.byref(cfg), imgs, _ptr(self._state),
+                self._state.numel(), _ptr(self._scratch), self._scratch.numel(), _stream()))
+            self._gen += 1
+            h = FwdHandle(self._gen, va, n_views, cfg, s3.n, s4.n, self._state, images)
+            if self.check_mode != "eager":
+                self._pending = h
+                return h
+            need = C.c_int64()
+            rc = self.ctx.L.h4dgs_check(self.ctx.h, _ptr(self._state), self._state.numel(), C.byref(need), _stream())
+            self.last_pairs = int(need.value)
+            if rc == L.H4D_OK:
+                return h
+            if rc != L.H4D_ERR_CAPACITY:
+                self.ctx.check(rc)
+            self.capacity = int(need.value * self.growth) + 1024
+        raise L.H4DError(L.H4D_ERR_CAPACITY, "pair capacity kept overflowing")
+
+    def verify(self) -> int:
+        """Synchronise and read the status of the last forward; returns its pair count."""
+        if self._state is None:
+            return 0
+        need = C.c_int64()
+        rc = self.ctx.L.h4dgs_check(self.ctx.h, _ptr(self._state), self._state.numel(), C.byref(need), _stream())
+        self.last_pairs = int(need.value)
+        if rc == L.H4D_ERR_CAPACITY:
+            self.capacity = int(need.value * self.growth) + 1024
+        self.ctx.check(rc)
+        return self.last_pairs
+
+    def backward(self, h: FwdHandle, g3: dict, g4: dict, dl_images) -> tuple:
+        if h.generation != self._gen:
+            raise RuntimeError("backward must follow its own forward (the workspace was reused)")
+        s3, s4 = g3_struct(g3), g4_struct(g4)
+        gr3 = {k: torch.empty_like(g3[k]) for k in G3_KEYS}
+        gr4 = {k: torch.empty_like(g4[k]) for k in G4_KEYS}
+        m3 = L.G3D(s3.n, *[_ptr(gr3[k]) for k in G3_KEYS])
+        m4 = L.G4D(s4.n, *[_ptr(gr4[k]) for k in G4_KEYS])
+        dl = [_chk(d, "dl_dimage") for d in dl_images]
+        arr = L.ptr_array([d.data_ptr() for d in dl])
+        self.ctx.check(self.ctx.L.h4dgs_render_bwd(
+            self.ctx.h, C.byref(s3), C.byref(s4), h.views, h.n_views, C.byref(h.cfg), arr, _ptr(h.state),
+            h.state.numel(), _ptr(self._scratch), self._scratch.numel(), C.byref(m3), C.byref(m4), _stream()))
+        return gr3, gr4
+
+
+class H4DGSRender(torch.autograd.Function):
+    """images = render(parameters); backward calls the library's adjoint."""
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, views, *params):
+        g3 = dict(zip(G3_KEYS, params[:5]))
+        g4 = dict(zip(G4_KEYS, params[5:]))
+        h = rast.forward(g3, g4, views)
+        ctx.rast, ctx.h = rast, h
+        ctx.save_for_backward(*params)
+        return tuple(h.images)
+
+    @staticmethod
+    def backward(ctx, *dl):
+        params = ctx.saved_tensors
+        g3 = dict(zip(G3_KEYS, params[:5]))
+        g4 = dict(zip(G4_KEYS, params[5:]))
+        dls = [d.contiguous() if d is not None else torch.zeros_like(im) for d, im in zip(dl, ctx.h.images)]
+        gr3, gr4 = ctx.rast.backward(ctx.h, g3, g4, dls)
+        return (None, None, *[gr3[k] for k in G3_KEYS], *[gr4[k] for k in G4_KEYS])
+
+
+def render(rast: Rasterizer, g3: dict, g4: dict, views) -> tuple:
+    """Differentiable render of ``views``; returns one [3, H, W] image per view."""
+    return H4DGSRender.apply(rast, list(views), *[g3[k] for k in G3_KEYS], *[g4[k] for k in G4_KEYS])
+
+
+# -- other entry points ------------------------------------------------------------
+
+def rasterize_splats(rast: Rasterizer, sp: dict, width: int, height: int, bg=(0.0, 0.0, 0.0)):
+    """Binning, sorting and blending of given screen-space splats.  Returns
+    (image[3,H,W], T[H,W], sorted_ids[P], ranges[tiles, 2])."""
+    n = int(sp["u"].shape[0])
+    dev = "cuda"
+    t = {k: torch.as_tensor(v, device=dev).contiguous() for k, v in sp.items()}
+    t["radius"] = t["radius"].to(torch.int32)
+    t["visible"] = t["visible"].to(torch.uint8)
+    image = torch.empty((3, height, width), dtype=torch.float32, device=dev)
+    T = torch.empty((height, width), dtype=torch.float32, device=dev)
+    bgv = (C.c_float * 3)(*[float(b) for b in bg])
+    from scenegen import View  # a plain camera container (no rendering arithmetic)
+    import numpy as np
+    v = View(np.eye(3, 4, dtype=np.float32), 1.0, 1.0, 0.0, 0.0, width, height, 0.0, tuple(bg))
+    va = L.view_array([v])
+    for _ in range(3):
+        rast._ensure(n, 0, va, 1)
+        cfg = rast.config()
+        ids = torch.empty(max(1, rast.capacity), dtype=torch.int32, device=dev)
+        tiles = ((width + rast.tile - 1) // rast.tile) * ((height + rast.tile - 1) // rast.tile)
+        ranges = torch.empty((tiles, 2), dtype=torch.int64, device=dev)
+        rast.ctx.check(rast.ctx.L.h4dgs_rasterize_splats(
+            rast.ctx.h, n, _ptr(t["u"]), _ptr(t["v"]), _ptr(t["conic"]), _ptr(t["opacity"]), _ptr(t["rgb"]),
+            _ptr(t["radius"]), _ptr(t["depth"]), _ptr(t["visible"]), width, height, bgv, C.byref(cfg), _ptr(image),
+            _ptr(T), _ptr(ids), _ptr(ranges), _ptr(rast._state), rast._state.numel(), _ptr(rast._scratch),
+            rast._scratch.numel(), _stream()))
+        need = C.c_int64()
+        rc = rast.ctx.L.h4dgs_check(rast.ctx.h, _ptr(rast._state), rast._state.numel(), C.byref(need), _stream())
+        if rc == L.H4D_OK:
+            return image, T, ids[: int(need.value)], ranges
+        if rc != L.H4D_ERR_CAPACITY:
+            rast.ctx.check(rc)
+        rast.capacity = int(need.value * rast.growth) + 1024
+    raise L.H4DError(L.H4D_ERR_CAPACITY, "pair capacity kept overflowing")
+
+
+def convert_static(rast: Rasterizer, g3: dict, g4: dict, tau: float):
+    """Static identification + 4D->3D conversion.  Returns (g3', g4', perm)."""
+    s3, s4 = g3_struct(g3), g4_struct(g4)
+    n3, n4 = s3.n, s4.n
+    dev = "cuda"
+    cap3 = n3 + n4
+    o3 = {"mean": torch.empty((3, cap3), device=dev), "log_scale": torch.empty((3, cap3), device=dev),
+          "quat": torch.empty((4, cap3), device=dev), "opacity": torch.empty(cap3, device=dev),
+          "sh": torch.empty((48, cap3), device=dev)}
+    o4 = {"mean": torch.empty((3, n4), device=dev), "mean_t": torch.empty(n4, device=dev),
+          "log_scale": torch.empty((4, n4), device=dev), "quat_l": torch.empty((4, n4), device=dev),
+          "quat_r": torch.empty((4, n4), device=dev), "opacity": torch.empty(n4, device=dev),
+          "sh": torch.empty((48, n4), device=dev)}
+    m3 = L.G3D(cap3, *[_ptr(o3[k]) for k in G3_KEYS])
+    m4 = L.G4D(n4, *[_ptr(o4[k]) for k in G4_KEYS])
+    perm = torch.empty(max(1, n4), dtype=torch.int32, device=dev)
+    nsc = int(rast.ctx.L.h4dgs_convert_scratch_bytes(n4))
+    scratch = torch.empty(max(256, nsc), dtype=torch.uint8, device=dev)
+    n4o, n3o = C.c_int32(), C.c_int32()
+    rast.ctx.check(rast.ctx.L.h4dgs_convert_static(
+        rast.ctx.h, C.byref(s4), C.byref(s3), C.c_float(tau), C.byref(m4), C.byref(m3), _ptr(perm), C.byref(n4o),
+        C.byref(n3o), _ptr(scratch), scratch.numel(), _stream()))
+    k3, k4 = n3o.value, n4o.value
+    g3n = {k: (v[..., :k3] if v.dim() == 2 else v[:k3]).contiguous() for k, v in o3.items()}
+    g4n = {k: (v[..., :k4] if v.dim() == 2 else v[:k4]).contiguous() for k, v in o4.items()}
+    return g3n, g4n, perm[:n4]
+
+
+def adam_step(rast: Rasterizer, params, grads, ms, vs, lrs, step: int, betas=(0.9, 0.999), eps=1e-8):
+    """One Adam step over lists of float32 CUDA tensors (in place on params, ms, vs)."""
+    n = len(params)
+    for i in range(0, n, 16):
+        sl = slice(i, min(n, i + 16))
+        P, G, M, V = params[sl], grads[sl], ms[sl], vs[sl]
+        k = len(P)
+        sizes = (C.c_int64 * k)(*[int(p.numel()) for p in P])
+        lr = (C.c_float * k)(*[float(x) for x in lrs[sl]])
+        rast.ctx.check(rast.ctx.L.h4dgs_adam(
+            rast.ctx.h, k, L.ptr_array([p.data_ptr() for p in P]), L.ptr_array([g.data_ptr() for g in G]),
+            L.ptr_array([m.data_ptr() for m in M]), L.ptr_array([v.data_ptr() for v in V]), sizes, lr,
+            C.c_float(betas[0]), C.c_float(betas[1]), C.c_float(eps), int(step), _stream()))

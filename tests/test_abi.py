@@ -1,0 +1,190 @@
+"""The C-ABI library on the host: it loads, exports every declared entry point,
+sizes workspaces and rejects bad arguments before touching a GPU (no GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "h4dgs.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2505_13215_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2505_13215_amd import build
+        build.build()
+    return _lib
+
+
+def declared_entry_points():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(h4dgs_\w+)\s*\(", txt)))
+
+
+def test_header_declares_the_expected_calls():
+    names = declared_entry_points()
+    for must in ("h4dgs_render_fwd", "h4dgs_render_bwd", "h4dgs_convert_static", "h4dgs_workspace_size"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.load()
+    for name in declared_entry_points():
+        assert hasattr(lib, name), name
+    assert set(declared_entry_points()) == set(L.EXPORTS)
+
+
+def test_version(L):
+    assert "gfx950" in L.version()
+
+
+def _cfg(L, tile=16, chunk=256, batched=0, cap=1 << 20):
+    return L.Config(tile, chunk, batched, 0, cap)
+
+
+def _ctx(L):
+    return L.Context()
+
+
+def _views(L, n=1, W=128, H=96):
+    v = sg.tiny_scene(n3=1, n4=1, width=W, height=H).views[0]
+    return L.view_array([v] * n)
+
+
+def test_workspace_size_grows_with_inputs(L):
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    va = _views(L)
+    cfg = _cfg(L)
+    assert c.L.h4dgs_workspace_size(c.h, 1000, 1000, va, 1, C.byref(cfg), C.byref(st), C.byref(sc)) == 0
+    s1, k1 = st.value, sc.value
+    assert c.L.h4dgs_workspace_size(c.h, 4000, 1000, va, 1, C.byref(cfg), C.byref(st), C.byref(sc)) == 0
+    assert st.value > s1 and sc.value > k1
+    cfg2 = _cfg(L, cap=1 << 22)
+    assert c.L.h4dgs_workspace_size(c.h, 1000, 1000, va, 1, C.byref(cfg2), C.byref(st), C.byref(sc)) == 0
+    assert st.value > s1
+    va2 = _views(L, 2)
+    assert c.L.h4dgs_workspace_size(c.h, 1000, 1000, va2, 2, C.byref(cfg), C.byref(st), C.byref(sc)) == 0
+    # per view: 64 B records for every Gaussian, 20 B of per-pixel state
+    assert st.value >= s1 + 2000 * 64 + 128 * 96 * 20
+
+
+@pytest.mark.parametrize("tile,chunk", [(7, 256), (16, 100), (64, 256), (0, 0)])
+def test_bad_tile_or_chunk_rejected(L, tile, chunk):
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    cfg = _cfg(L, tile, chunk)
+    rc = c.L.h4dgs_workspace_size(c.h, 10, 10, _views(L), 1, C.byref(cfg), C.byref(st), C.byref(sc))
+    assert rc == L.H4D_ERR_INVALID_ARG
+    assert b"tile" in c.L.h4dgs_last_error(c.h)
+
+
+@pytest.mark.parametrize("nv", [0, 33])
+def test_view_count_rejected(L, nv):
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    cfg = _cfg(L)
+    va = _views(L, max(nv, 1))
+    assert c.L.h4dgs_workspace_size(c.h, 10, 10, va, nv, C.byref(cfg), C.byref(st), C.byref(sc)) == 1
+
+
+def test_bad_view_rejected(L):
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    cfg = _cfg(L)
+    va = _views(L)
+    va[0].width = 0
+    assert c.L.h4dgs_workspace_size(c.h, 10, 10, va, 1, C.byref(cfg), C.byref(st), C.byref(sc)) == 1
+    va = _views(L)
+    va[0].fx = float("nan")
+    assert c.L.h4dgs_workspace_size(c.h, 10, 10, va, 1, C.byref(cfg), C.byref(st), C.byref(sc)) == 1
+
+
+def _sets(L, n3=4, n4=4, null=False):
+    fake = C.c_void_p(0 if null else 0x1000)  # never dereferenced: argument checks fail first
+    g3 = L.G3D(n3, fake, fake, fake, fake, fake)
+    g4 = L.G4D(n4, fake, fake, fake, fake, fake, fake, fake)
+    return g3, g4
+
+
+def test_render_fwd_rejects_null_arrays_on_the_host(L):
+    c = _ctx(L)
+    g3, g4 = _sets(L, null=True)
+    cfg = _cfg(L)
+    imgs = L.ptr_array([0x1000])
+    rc = c.L.h4dgs_render_fwd(c.h, C.byref(g3), C.byref(g4), _views(L), 1, C.byref(cfg), imgs, C.c_void_p(0x1000),
+                              1 << 30, C.c_void_p(0x1000), 1 << 30, None)
+    assert rc == L.H4D_ERR_INVALID_ARG
+
+
+def test_render_fwd_rejects_small_workspace(L):
+    c = _ctx(L)
+    g3, g4 = _sets(L)
+    cfg = _cfg(L)
+    imgs = L.ptr_array([0x1000])
+    rc = c.L.h4dgs_render_fwd(c.h, C.byref(g3), C.byref(g4), _views(L), 1, C.byref(cfg), imgs, C.c_void_p(0x1000),
+                              16, C.c_void_p(0x1000), 1 << 30, None)
+    assert rc == L.H4D_ERR_INVALID_ARG and b"state too small" in c.L.h4dgs_last_error(c.h)
+
+
+def test_render_bwd_rejects_mismatched_gradient_counts(L):
+    c = _ctx(L)
+    g3, g4 = _sets(L)
+    gr3, gr4 = _sets(L, n3=5)
+    cfg = _cfg(L)
+    dls = L.ptr_array([0x1000])
+    rc = c.L.h4dgs_render_bwd(c.h, C.byref(g3), C.byref(g4), _views(L), 1, C.byref(cfg), dls, C.c_void_p(0x1000),
+                              1 << 30, C.c_void_p(0x1000), 1 << 30, C.byref(gr3), C.byref(gr4), None)
+    assert rc == L.H4D_ERR_INVALID_ARG
+
+
+def test_negative_counts_rejected(L):
+    c = _ctx(L)
+    g3, g4 = _sets(L, n3=-1)
+    cfg = _cfg(L)
+    rc = c.L.h4dgs_render_fwd(c.h, C.byref(g3), C.byref(g4), _views(L), 1, C.byref(cfg), L.ptr_array([0x1000]),
+                              C.c_void_p(0x1000), 1 << 30, C.c_void_p(0x1000), 1 << 30, None)
+    assert rc == L.H4D_ERR_INVALID_ARG
+
+
+def test_convert_static_argument_checks(L):
+    c = _ctx(L)
+    g3, g4 = _sets(L)
+    o3, o4 = _sets(L, n3=8, n4=4)
+    n4o, n3o = C.c_int32(), C.c_int32()
+    rc = c.L.h4dgs_convert_static(c.h, C.byref(g4), C.byref(g3), C.c_float(0.0), C.byref(o4), C.byref(o3),
+                                  C.c_void_p(0x1000), C.byref(n4o), C.byref(n3o), C.c_void_p(0x1000), 1 << 20, None)
+    assert rc == L.H4D_ERR_INVALID_ARG  # tau must be > 0
+    small3, _ = _sets(L, n3=7)
+    rc = c.L.h4dgs_convert_static(c.h, C.byref(g4), C.byref(g3), C.c_float(0.5), C.byref(o4), C.byref(small3),
+                                  C.c_void_p(0x1000), C.byref(n4o), C.byref(n3o), C.c_void_p(0x1000), 1 << 20, None)
+    assert rc == L.H4D_ERR_CAPACITY
+
+
+def test_convert_scratch_bytes_monotone(L):
+    lib = L.load()
+    assert lib.h4dgs_convert_scratch_bytes(1000) < lib.h4dgs_convert_scratch_bytes(100000)
+
+
+def test_adam_argument_checks(L):
+    c = _ctx(L)
+    one = (C.c_int64 * 1)(10)
+    lr = (C.c_float * 1)(1e-3)
+    arr = L.ptr_array([0x1000])
+    assert c.L.h4dgs_adam(c.h, 17, arr, arr, arr, arr, one, lr, 0.9, 0.999, 1e-8, 1, None) == 1
+    assert c.L.h4dgs_adam(c.h, 1, arr, arr, arr, arr, one, lr, 0.9, 0.999, 1e-8, 0, None) == 1
+    assert c.L.h4dgs_adam(c.h, 1, arr, arr, arr, arr, one, lr, 1.0, 0.999, 1e-8, 1, None) == 1
+
+
+def test_null_context(L):
+    lib = L.load()
+    st, sc = C.c_size_t(), C.c_size_t()
+    assert lib.h4dgs_workspace_size(None, 1, 1, None, 1, None, C.byref(st), C.byref(sc)) == 1
+    assert lib.h4dgs_last_error(None) == b"null context"

@@ -1,0 +1,339 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (from the method's arithmetic, see the design notes):
+  * images: max |C_gpu - C_oracle| <= 1e-4 over pixels whose oracle decisions
+    are all outside the FP32 guard band; flagged pixels < 1e-3 of the image;
+  * gradients: per parameter group ||g - g_ref|| <= 1e-3 ||g_ref||, and per
+    element |g - g_ref| <= 1e-3 |g_ref| + 1e-3 rms(g_ref) for every Gaussian whose
+    square holds no flagged pixel;
+  * tile lists, sort order, ranges and the static conversion: bit-exact on the
+    same inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def h4d():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_13215_amd as m
+    m._lib.load()
+    return m
+
+
+def _render(h4d, scene, views, tile=16, chunk=256, cap=1 << 20):
+    rast = h4d.Rasterizer(tile=tile, chunk=chunk, pair_capacity=cap)
+    g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+    h = rast.forward(g3, g4, views)
+    torch.cuda.synchronize()
+    return rast, g3, g4, h
+
+
+def _check_image(gpu, ref, amb, tol=IMG_TOL):
+    assert amb.mean() < 1e-3, f"guard band flags {amb.mean():.2e} of the pixels"
+    err = np.abs(gpu - ref)[:, ~amb]
+    assert err.size == 0 or err.max() <= tol, f"max error {err.max():.3e} on unflagged pixels"
+    return float(err.max()) if err.size else 0.0
+
+
+def _flagged_gaussians(scene, view, amb):
+    pr = oracle.project(scene, view)
+    ys, xs = np.nonzero(amb)
+    bad = np.zeros(scene.n3 + scene.n4, bool)
+    if len(xs) == 0:
+        return bad
+    for g in np.nonzero(pr["visible"] > 0)[0]:
+        x0, x1, y0, y1 = pr["x0"][g], pr["x1"][g], pr["y0"][g], pr["y1"][g]
+        if np.any((xs >= x0) & (xs <= x1) & (ys >= y0) & (ys <= y1)):
+            bad[g] = True
+    return bad
+
+
+def _check_grads(scene, gr3, gr4, r3, r4, bad):
+    n4 = scene.n4
+    for which, gr, rf, keys in (("4", gr4, r4, sg_keys4()), ("3", gr3, r3, sg_keys3())):
+        ok_cols = ~bad[:n4] if which == "4" else ~bad[n4:]
+        for k in keys:
+            g = gr[k].detach().cpu().numpy().astype(np.float64)
+            r = rf[k]
+            nr = np.linalg.norm(r)
+            if nr == 0:
+                assert np.abs(g).max() == 0
+                continue
+            rel = np.linalg.norm(g - r) / nr
+            assert rel <= GRAD_TOL, f"{which}D {k}: relative L2 error {rel:.2e}"
+            gs, rs = g[..., ok_cols], r[..., ok_cols]
+            rms = np.sqrt(np.mean(r * r))
+            viol = np.abs(gs - rs) > GRAD_TOL * np.abs(rs) + GRAD_TOL * rms
+            assert viol.sum() == 0, f"{which}D {k}: {viol.sum()} elements out of tolerance"
+
+
+def sg_keys3():
+    return ("mean", "log_scale", "quat", "opacity", "sh")
+
+
+def sg_keys4():
+    return ("mean", "mean_t", "log_scale", "quat_l", "quat_r", "opacity", "sh")
+
+
+# ---------------------------------------------------------------------------
+# forward
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(128, 96), (77, 45), (200, 150)])
+def test_forward_matches_oracle(h4d, shape):
+    W, H = shape
+    print(f"[forward parity] {W}x{H}", flush=True)
+    scene = sg.tiny_scene(width=W, height=H)
+    v = scene.views[0]
+    _, _, _, h = _render(h4d, scene, [v])
+    ref = oracle.render(scene, v)
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+
+
+def test_forward_mid_scene_many_tiles(h4d):
+    print("[forward parity] 20k Gaussians, 333x250", flush=True)
+    scene = sg.multiview_scene(n_total=20_000, width=333, height=250, seed=3)
+    v = scene.views[7].with_time(0.41)
+    rast, g3, g4, h = _render(h4d, scene, [v])
+    ref = oracle.render(scene, v)
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+
+
+def test_forward_background_and_time(h4d):
+    scene = sg.tiny_scene(n3=400, n4=600, width=96, height=64, seed=4)
+    v0 = scene.views[0]
+    v = sg.View(v0.world_to_cam, v0.fx, v0.fy, v0.cx, v0.cy, v0.width, v0.height, 0.23, (0.2, 0.6, 1.0))
+    _, _, _, h = _render(h4d, scene, [v])
+    ref = oracle.render(scene, v)
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+
+
+@pytest.mark.parametrize("n3,n4", [(0, 500), (500, 0), (0, 0)])
+def test_forward_single_set_and_empty(h4d, n3, n4):
+    scene = sg.tiny_scene(n3=n3, n4=n4, width=64, height=48, seed=2)
+    v = sg.View(scene.views[0].world_to_cam, scene.views[0].fx, scene.views[0].fy, 32.0, 24.0, 64, 48, 0.5,
+                (0.1, 0.2, 0.3))
+    _, _, _, h = _render(h4d, scene, [v])
+    ref = oracle.render(scene, v)
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+
+
+def test_forward_everything_behind_camera(h4d):
+    scene = sg.tiny_scene(n3=200, n4=200, width=64, height=48, seed=6)
+    v0 = scene.views[0]
+    M = v0.world_to_cam.copy()
+    M[:, :3] = -M[:, :3]  # look away from the scene
+    M[2, 3] = -3.0
+    v = sg.View(M, v0.fx, v0.fy, v0.cx, v0.cy, 64, 48, 0.5, (0.3, 0.3, 0.3))
+    _, _, _, h = _render(h4d, scene, [v])
+    img = h.images[0].cpu().numpy()
+    assert np.array_equal(img, np.broadcast_to(np.float32([0.3, 0.3, 0.3])[:, None, None], img.shape))
+
+
+def test_forward_is_deterministic(h4d):
+    scene = sg.tiny_scene()
+    v = scene.views[0]
+    rast, g3, g4, h1 = _render(h4d, scene, [v])
+    a = h1.images[0].clone()
+    h2 = rast.forward(g3, g4, [v])
+    assert torch.equal(a, h2.images[0])
+
+
+def test_images_do_not_depend_on_tile_or_chunk(h4d):
+    scene = sg.tiny_scene(width=111, height=70, seed=8)
+    v = scene.views[0]
+    base = None
+    for tile in (8, 16, 32):
+        for chunk in (128, 256, 512):
+            _, _, _, h = _render(h4d, scene, [v], tile=tile, chunk=chunk)
+            img = h.images[0].cpu()
+            if base is None:
+                base = img
+            else:
+                assert torch.equal(img, base), (tile, chunk)
+
+
+def test_capacity_overflow_is_detected_and_recovered(h4d):
+    scene = sg.tiny_scene()
+    v = scene.views[0]
+    rast, g3, g4, h = _render(h4d, scene, [v], cap=64)
+    assert rast.capacity > 64 and rast.last_pairs > 64
+    ref = oracle.render(scene, v)
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+
+
+# ---------------------------------------------------------------------------
+# stages on identical screen-space inputs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_tile_lists_and_ranges_bit_exact(h4d, tile):
+    W, H = 203, 131
+    rec = sg.synthetic_records(3000, W, H, seed=21, max_radius=40)
+    rast = h4d.Rasterizer(tile=tile, chunk=256, pair_capacity=1 << 20)
+    img, T, ids, ranges = h4d.rasterize_splats(rast, rec, W, H)
+    start, ref_ids = oracle.tile_lists(rec, W, H, tile)
+    ids = ids.cpu().numpy()
+    rg = ranges.cpu().numpy()
+    assert len(ids) == len(ref_ids)
+    assert np.array_equal(ids, ref_ids)
+    tiles = len(start) - 1
+    for t in range(tiles):
+        if start[t + 1] > start[t]:
+            assert rg[t, 0] == start[t] and rg[t, 1] == start[t + 1], t
+        else:
+            assert rg[t, 0] == rg[t, 1]
+
+
+def test_composite_on_shared_splats(h4d):
+    W, H = 150, 100
+    rec = sg.synthetic_records(2500, W, H, seed=22, max_radius=30)
+    rast = h4d.Rasterizer(tile=16, chunk=256, pair_capacity=1 << 20)
+    img, T, _, _ = h4d.rasterize_splats(rast, rec, W, H, bg=(0.5, 0.25, 0.125))
+    ref, Tref, amb = oracle.composite_records(rec, W, H, tile=16, bg=(0.5, 0.25, 0.125))
+    _check_image(img.cpu().numpy(), ref, amb)
+    assert np.abs(T.cpu().numpy() - Tref)[~amb].max() <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# backward
+# ---------------------------------------------------------------------------
+
+def _grads_gpu(h4d, scene, views, dls, tile=16, chunk=256):
+    rast = h4d.Rasterizer(tile=tile, chunk=chunk, pair_capacity=1 << 20)
+    g3 = {k: v.requires_grad_(True) for k, v in h4d.to_device(scene.g3).items()}
+    g4 = {k: v.requires_grad_(True) for k, v in h4d.to_device(scene.g4).items()}
+    imgs = h4d.render(rast, g3, g4, views)
+    loss = sum((im * torch.as_tensor(d, device="cuda")).sum() for im, d in zip(imgs, dls))
+    loss.backward()
+    torch.cuda.synchronize()
+    return {k: g3[k].grad for k in g3}, {k: g4[k].grad for k in g4}
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_backward_matches_oracle(h4d, seed):
+    print(f"[backward parity] tiny seed {seed}", flush=True)
+    scene = sg.tiny_scene(seed=seed)
+    v = scene.views[0]
+    dl = sg.upstream_grads([v], seed=10 + seed)
+    gr3, gr4 = _grads_gpu(h4d, scene, [v], dl)
+    r3, r4 = oracle.render_bwd(scene, [v], dl)
+    amb = oracle.render(scene, v)["amb"]
+    _check_grads(scene, gr3, gr4, r3, r4, _flagged_gaussians(scene, v, amb))
+
+
+def test_backward_l1_loss_and_background(h4d):
+    scene = sg.tiny_scene(n3=700, n4=900, width=100, height=80, seed=5)
+    v0 = scene.views[0]
+    v = sg.View(v0.world_to_cam, v0.fx, v0.fy, 50.0, 40.0, 100, 80, 0.7, (0.3, 0.1, 0.9))
+    ref = oracle.render(scene, v)
+    target = sg.target_images([v], seed=1)[0]
+    # the L1 gradient sign is taken from the oracle image, so both sides get the same dL/dC
+    dl = (np.sign(ref["img"] - target) / (3 * v.width * v.height)).astype(np.float32)
+    gr3, gr4 = _grads_gpu(h4d, scene, [v], [dl])
+    r3, r4 = oracle.render_bwd(scene, [v], [dl])
+    _check_grads(scene, gr3, gr4, r3, r4, _flagged_gaussians(scene, v, ref["amb"]))
+
+
+def test_multi_view_gradients_are_sums(h4d):
+    scene = sg.tiny_scene(seed=3)
+    v0 = scene.views[0]
+    views = [v0.with_time(0.2), v0.with_time(0.7)]
+    dls = sg.upstream_grads(views, seed=4)
+    both3, both4 = _grads_gpu(h4d, scene, views, dls)
+    a3, a4 = _grads_gpu(h4d, scene, views[:1], dls[:1])
+    b3, b4 = _grads_gpu(h4d, scene, views[1:], dls[1:])
+    for k in both4:
+        s = (a4[k] + b4[k]).double()
+        assert torch.allclose(both4[k].double(), s, rtol=1e-5, atol=1e-6 * float(s.abs().max()) + 1e-12), k
+    for k in both3:
+        s = (a3[k] + b3[k]).double()
+        assert torch.allclose(both3[k].double(), s, rtol=1e-5, atol=1e-6 * float(s.abs().max()) + 1e-12), k
+
+
+@pytest.mark.parametrize("tile,chunk", [(8, 128), (32, 512)])
+def test_backward_other_tile_shapes(h4d, tile, chunk):
+    scene = sg.tiny_scene(seed=7, width=90, height=70)
+    v = scene.views[0]
+    dl = sg.upstream_grads([v], seed=5)
+    gr3, gr4 = _grads_gpu(h4d, scene, [v], dl, tile=tile, chunk=chunk)
+    r3, r4 = oracle.render_bwd(scene, [v], dl)
+    amb = oracle.render(scene, v)["amb"]
+    _check_grads(scene, gr3, gr4, r3, r4, _flagged_gaussians(scene, v, amb))
+
+
+# ---------------------------------------------------------------------------
+# static conversion and Adam
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("frac", [0.0, 0.5, 0.9, 1.0])
+def test_convert_static_bit_exact(h4d, frac):
+    rng = np.random.default_rng(int(frac * 10))
+    g4 = sg.draw_4d(rng, 3000, 2.0, static_fraction=frac, tau=0.5)
+    g3 = sg.draw_3d(rng, 1000, 2.0)
+    scene = sg.Scene(g3, g4)
+    rast = h4d.Rasterizer()
+    n3, n4, perm = None, None, None
+    o3, o4, perm = h4d.convert_static(rast, h4d.to_device(g3), h4d.to_device(g4), 0.5)
+    rperm, rn4, rn3, rq = oracle.convert_static(scene, 0.5)
+    assert np.array_equal(perm.cpu().numpy(), rperm)
+    assert o4["opacity"].shape[0] == rn4 and o3["opacity"].shape[0] == rn3
+    keep = np.nonzero(rperm >= 0)[0]
+    conv = np.nonzero(rperm < 0)[0]
+    for k in ("mean", "mean_t", "log_scale", "quat_l", "quat_r", "opacity", "sh"):
+        assert np.array_equal(o4[k].cpu().numpy(), g4[k][..., keep]), k
+    for k in ("mean", "log_scale", "quat", "opacity", "sh"):
+        assert np.array_equal(o3[k].cpu().numpy()[..., :1000], g3[k]), k
+    assert np.array_equal(o3["mean"].cpu().numpy()[:, 1000:], g4["mean"][:, conv])
+    assert np.array_equal(o3["log_scale"].cpu().numpy()[:, 1000:], g4["log_scale"][:3, conv])
+    assert np.array_equal(o3["opacity"].cpu().numpy()[1000:], g4["opacity"][conv])
+    assert np.array_equal(o3["sh"].cpu().numpy()[:, 1000:], g4["sh"][:, conv])
+    q = o3["quat"].cpu().numpy()[:, 1000:].astype(np.float64)
+    if q.shape[1]:
+        qn = q / np.linalg.norm(q, axis=0)
+        rn = rq / np.linalg.norm(rq, axis=0)
+        assert np.abs(qn - rn).max() <= 1e-6
+
+
+def test_convert_static_empty_sets(h4d):
+    rast = h4d.Rasterizer()
+    g3 = sg.draw_3d(np.random.default_rng(0), 10, 1.0)
+    o3, o4, perm = h4d.convert_static(rast, h4d.to_device(g3), h4d.to_device(sg.empty_4d()), 0.5)
+    assert o4["opacity"].shape[0] == 0 and o3["opacity"].shape[0] == 10
+    assert torch.equal(o3["sh"].cpu(), torch.as_tensor(g3["sh"]))
+
+
+def test_adam_matches_oracle(h4d):
+    rng = np.random.default_rng(1)
+    rast = h4d.Rasterizer()
+    sizes = [1000, 3, 4096, 77]
+    P = [rng.normal(size=n).astype(np.float32) for n in sizes]
+    M = [np.zeros(n, np.float32) for n in sizes]
+    V = [np.zeros(n, np.float32) for n in sizes]
+    lrs = [1e-3, 5e-2, 2.5e-3, 1.6e-4]
+    tp = [torch.as_tensor(p, device="cuda") for p in P]
+    tm = [torch.as_tensor(m, device="cuda") for m in M]
+    tv = [torch.as_tensor(v, device="cuda") for v in V]
+    for step in range(1, 4):
+        G = [rng.normal(size=n).astype(np.float32) for n in sizes]
+        tg = [torch.as_tensor(g, device="cuda") for g in G]
+        refs = [oracle.adam(tp[i].cpu().numpy(), G[i], tm[i].cpu().numpy(), tv[i].cpu().numpy(), lrs[i], 0.9, 0.999,
+                            1e-8, step) for i in range(len(sizes))]
+        h4d.adam_step(rast, tp, tg, tm, tv, lrs, step)
+        torch.cuda.synchronize()
+        for i in range(len(sizes)):
+            po, mo, vo = refs[i]
+            assert np.allclose(tp[i].cpu().numpy(), po, rtol=1e-6, atol=1e-6)
+            assert np.allclose(tm[i].cpu().numpy(), mo, rtol=1e-6, atol=1e-9)
+            assert np.allclose(tv[i].cpu().numpy(), vo, rtol=1e-6, atol=1e-12)
