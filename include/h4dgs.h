@@ -93,7 +93,9 @@ typedef struct {
  * list entries staged in LDS per round of the blending kernels (128, 256 or
  * 512, and at least tile*tile); batched: 0 = views processed one after another,
  * 1 = all views of a call in one pass per stage; pair_capacity: number of
- * (Gaussian, tile) pairs the workspace holds, summed over the call's views.
+ * tile-list slots the workspace holds, summed over the call's views (a tile's
+ * slots number the splats touching its 64-pixel super-tile, so this is a
+ * little more than the number of (Gaussian, tile) pairs).
  * Images do not depend on tile or chunk (a pixel's contributors are fixed by
  * its own square test), so these are pure performance knobs. */
 typedef struct {
@@ -142,13 +144,15 @@ h4d_status h4dgs_render_bwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, 
  * NULL) receives the number of pairs the call needed. */
 h4d_status h4dgs_check(h4d_ctx *ctx, const void *state, size_t state_bytes, int64_t *pairs_needed, void *stream);
 
-/* Alg. 1 lines 7-17 alone, on given screen-space splats: n splats with centre
+/* Alg. 1 from CreateTiles to BlendInOrder alone, on given screen-space splats: n splats with centre
  * u[n], v[n], conic[3][n] (inverse 2D covariance entries 00, 01, 11), effective
  * opacity[n], rgb[3][n], integer radius[n], depth key[n] and visible[n] (uint8).
  * Splat i covers pixel (x, y) iff |x + 0.5 - u| <= r and |y + 0.5 - v| <= r.
  * Writes image[3][H][W], T_final[H][W] (may be NULL) and, if sorted_ids is not
- * NULL, the per-tile sorted splat ids (sorted_ids[pair_capacity]) and tile
- * ranges (ranges[2 * tiles]: start, end).  Uses the same kernels as render_fwd.
+ * NULL, the per-tile depth-ordered splat ids (sorted_ids[pair_capacity]) with
+ * tile ranges (ranges[2 * tiles]: start, end): tile t's list is
+ * sorted_ids[ranges[2t] .. ranges[2t+1]); lists of different tiles need not be
+ * adjacent.  Uses the same kernels as render_fwd.
  * Workspace: h4dgs_workspace_size(n3 = n, n4 = 0, one view of W x H). */
 h4d_status h4dgs_rasterize_splats(h4d_ctx *ctx, int32_t n, const float *u, const float *v, const float *conic,
                                   const float *opacity, const float *rgb, const int32_t *radius,
@@ -173,11 +177,52 @@ h4d_status h4dgs_convert_static(h4d_ctx *ctx, const h4d_g4d *in4, const h4d_g3d 
                                 int32_t *n3_out, void *scratch, size_t scratch_bytes, void *stream);
 
 /* One bias-corrected Adam step (Kingma & Ba) over up to 16 float32 segments:
- * p -= lr * m_hat / (sqrt(v_hat) + eps) with m, v updated in place.  Host
- * arrays of n_seg device pointers / sizes / learning rates. */
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2, p -= lr * m_hat / (sqrt(v_hat)
+ * + eps), in place.  Host arrays of n_seg device pointers / sizes / learning
+ * rates; the constants are taken in double so that 1 - b is formed exactly
+ * before rounding to float32.  step >= 1 is the 1-based step count. */
 h4d_status h4dgs_adam(h4d_ctx *ctx, int32_t n_seg, float *const *params, const float *const *grads,
-                      float *const *m, float *const *v, const int64_t *sizes, const float *lrs, float beta1,
-                      float beta2, float eps, int32_t step, void *stream);
+                      float *const *m, float *const *v, const int64_t *sizes, const float *lrs, double beta1,
+                      double beta2, double eps, int32_t step, void *stream);
+
+/* L1 photometric loss of n_views images against targets (both float[3][H][W]
+ * per view, host arrays of device pointers): dl_dimages_v = sign(C - target) /
+ * (3 W H n_views) (sign(0) = 0), the gradient of the mean over views of the
+ * per-view mean absolute error.  loss (device float, may be NULL) receives that
+ * mean.  Reading: the paper does not state its loss; L1 is the plain choice. */
+h4d_status h4dgs_l1_loss_grad(h4d_ctx *ctx, int32_t n_views, const float *const *images,
+                              const float *const *targets, const h4d_view *views, float *const *dl_dimages,
+                              float *loss, void *stream);
+
+/* ---- instrumentation ---------------------------------------------------- */
+typedef enum {
+    H4D_STAGE_PREPROCESS = 0,     /* per-Gaussian FP64 geometry, records, depth keys */
+    H4D_STAGE_DEPTH_SORT = 1,     /* radix sort of the depth keys */
+    H4D_STAGE_BINNING = 2,        /* pair offsets, emission, tile sort, tile ranges */
+    H4D_STAGE_BLEND_FWD = 3,      /* front-to-back blending */
+    H4D_STAGE_BLEND_BWD = 4,      /* blending adjoint */
+    H4D_STAGE_PREPROCESS_BWD = 5, /* per-Gaussian FP64 adjoint */
+    H4D_STAGE_ADAM = 6,
+    H4D_STAGE_LOSS = 7,
+    H4D_STAGE_COUNT = 8
+} h4d_stage;
+
+/* enable != 0: every later call brackets each stage's kernels with HIP events
+ * recorded on the call's stream (events are host objects; no device memory). */
+h4d_status h4dgs_profile(h4d_ctx *ctx, int32_t enable);
+/* Waits for the recorded events and writes, per stage, the summed milliseconds
+ * and the number of bracketed launches since the previous read (arrays of
+ * H4D_STAGE_COUNT entries), then forgets them. */
+h4d_status h4dgs_profile_read(h4d_ctx *ctx, double *ms, int64_t *launches);
+
+/* enable != 0: later render calls use counting variants of the blending
+ * kernels (slower; for measurement only).  h4dgs_stats_read synchronises
+ * `stream` and reads, from the state the last forward/backward used:
+ * out[0] (pixel, splat) evaluations of the forward blend (pixel inside the
+ * splat's square, before the pixel stopped), out[1] blended ones,
+ * out[2] evaluations of the backward blend, out[3] blended ones. */
+h4d_status h4dgs_stats(h4d_ctx *ctx, int32_t enable);
+h4d_status h4dgs_stats_read(h4d_ctx *ctx, const void *state, size_t state_bytes, int64_t *out, void *stream);
 
 #ifdef __cplusplus
 }

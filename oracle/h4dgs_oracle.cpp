@@ -1149,7 +1149,7 @@ int orc_pixels(const OScene* sc, const OView* V, int npx, const int32_t* px, con
     return 0;
 }
 
-// Alg. 1 lines 7-10 on given screen-space splats (u, v, integer radius, depth
+// Alg. 1 CreateTiles to IdentifyTileRanges on given screen-space splats (u, v, integer radius, depth
 // key, visibility): exact tile lists.  First call with ids == null returns the
 // pair count in *npairs; second call fills start[tiles+1] and ids[npairs].
 int orc_tile_lists(int n, const float* u, const float* v, const int32_t* radius, const float* depth,
@@ -1174,7 +1174,7 @@ int orc_tile_lists(int n, const float* u, const float* v, const int32_t* radius,
     return 0;
 }
 
-// Alg. 1 lines 7-17 on given screen-space splats: image [3][H][W] and T [H][W].
+// Alg. 1 CreateTiles to BlendInOrder on given screen-space splats: image [3][H][W] and T [H][W].
 int orc_composite_records(int n, const float* u, const float* v, const float* conic /*[3][n]*/, const float* op,
                           const float* rgb /*[3][n]*/, const int32_t* radius, const float* depth,
                           const uint8_t* visible, int W, int H, int B, const double* bg, double* img, double* Tfin,

@@ -26,8 +26,11 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "CAPACITY", 3: "HIP", 4: "NONFINIT
 EXPORTS = (
     "h4dgs_create", "h4dgs_destroy", "h4dgs_last_error", "h4dgs_version", "h4dgs_workspace_size",
     "h4dgs_render_fwd", "h4dgs_render_bwd", "h4dgs_check", "h4dgs_rasterize_splats",
-    "h4dgs_convert_scratch_bytes", "h4dgs_convert_static", "h4dgs_adam",
+    "h4dgs_convert_scratch_bytes", "h4dgs_convert_static", "h4dgs_adam", "h4dgs_l1_loss_grad",
+    "h4dgs_profile", "h4dgs_profile_read", "h4dgs_stats", "h4dgs_stats_read",
 )
+
+STAGES = ("preprocess", "depth_sort", "binning", "blend_fwd", "blend_bwd", "preprocess_bwd", "adam", "loss")
 
 
 class H4DError(RuntimeError):
@@ -84,7 +87,12 @@ def load(path: str = LIB_PATH):
     L.h4dgs_convert_scratch_bytes.argtypes = [i32]
     L.h4dgs_convert_scratch_bytes.restype = sz
     L.h4dgs_convert_static.argtypes = [vp, vp, vp, f32, vp, vp, vp, P(i32), P(i32), vp, sz, vp]
-    L.h4dgs_adam.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, f32, f32, f32, i32, vp]
+    L.h4dgs_adam.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, i32, vp]
+    L.h4dgs_l1_loss_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.h4dgs_profile.argtypes = [vp, i32]
+    L.h4dgs_profile_read.argtypes = [vp, vp, vp]
+    L.h4dgs_stats.argtypes = [vp, i32]
+    L.h4dgs_stats_read.argtypes = [vp, vp, sz, vp, vp]
     for name in EXPORTS:
         if name not in ("h4dgs_last_error", "h4dgs_version", "h4dgs_convert_scratch_bytes"):
             getattr(L, name).restype = i32

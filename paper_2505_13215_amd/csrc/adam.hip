@@ -6,10 +6,10 @@
 
 namespace h4d {
 
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1, float b2, float eps,
-                                         float c1, float c2) {
-    m = b1 * m + (1.0f - b1) * g;
-    v = b2 * v + (1.0f - b2) * g * g;
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, const AdamTable& t) {
+    const float b1 = t.b1, b2 = t.b2, eps = t.eps, c1 = t.c1, c2 = t.c2;
+    m = b1 * m + t.omb1 * g;
+    v = b2 * v + t.omb2 * g * g;
     const float mh = m / c1, vh = v / c2;
     p -= lr * mh / (sqrtf(vh) + eps);
 }
@@ -29,16 +29,16 @@ __global__ void __launch_bounds__(256) k_adam(AdamTable t) {
         for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
             float4 p = P[i], m = M[i], v = Vv[i];
             const float4 g = G[i];
-            adam_one(p.x, g.x, m.x, v.x, s.lr, t.b1, t.b2, t.eps, t.c1, t.c2);
-            adam_one(p.y, g.y, m.y, v.y, s.lr, t.b1, t.b2, t.eps, t.c1, t.c2);
-            adam_one(p.z, g.z, m.z, v.z, s.lr, t.b1, t.b2, t.eps, t.c1, t.c2);
-            adam_one(p.w, g.w, m.w, v.w, s.lr, t.b1, t.b2, t.eps, t.c1, t.c2);
+            adam_one(p.x, g.x, m.x, v.x, s.lr, t);
+            adam_one(p.y, g.y, m.y, v.y, s.lr, t);
+            adam_one(p.z, g.z, m.z, v.z, s.lr, t);
+            adam_one(p.w, g.w, m.w, v.w, s.lr, t);
             P[i] = p; M[i] = m; Vv[i] = v;
         }
     } else {
         for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)s.n; i += stride) {
             float p = s.p[i], m = s.m[i], v = s.v[i];
-            adam_one(p, s.g[i], m, v, s.lr, t.b1, t.b2, t.eps, t.c1, t.c2);
+            adam_one(p, s.g[i], m, v, s.lr, t);
             s.p[i] = p; s.m[i] = m; s.v[i] = v;
         }
     }

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/h4dgs.h"
 #include "common.hpp"
@@ -13,6 +14,31 @@
 
 struct h4d_ctx {
     std::string err;
+    bool profile = false;
+    bool stats = false;
+    struct Mark {
+        hipEvent_t a, b;
+        int stage;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Mark> marks;
+    hipEvent_t event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~h4d_ctx() {
+        for (auto& m : marks) {
+            if (m.a) (void)hipEventDestroy(m.a);
+            if (m.b) (void)hipEventDestroy(m.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace h4d {
@@ -27,6 +53,31 @@ h4d_status fail(h4d_ctx* c, h4d_status s, const char* fmt, ...) {
     if (c) c->err = buf;
     return s;
 }
+
+// Brackets one stage's launches with events when profiling is enabled.
+struct StageScope {
+    h4d_ctx* c;
+    hipStream_t st;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageScope(h4d_ctx* c_, hipStream_t st_, int stage_) : c(c_), st(st_), stage(stage_) {
+        if (c && c->profile) {
+            a = c->event();
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~StageScope() {
+        if (c && c->profile && a) {
+            hipEvent_t b = c->event();
+            if (b) {
+                (void)hipEventRecord(b, st);
+                c->marks.push_back(h4d_ctx::Mark{a, b, stage});
+            } else {
+                c->pool.push_back(a);
+            }
+        }
+    }
+};
 
 h4d_status hip_check(h4d_ctx* c, const char* where) {
     const hipError_t e = hipGetLastError();
@@ -46,8 +97,12 @@ struct Carve {
     }
 };
 
+// Super-tiles are 64 x 64 pixels: S x S tiles.
+inline int super_factor(int tile) { return 64 / tile; }
+
 struct ViewGeom {
     int tiles_x, tiles_y, tile_base;
+    int sx, sy;  // super-tile grid
     int64_t pix_base;
 };
 
@@ -59,8 +114,9 @@ struct Layout {
     // state
     size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_T, st_nc, st_C, state_bytes;
     // scratch, forward use
-    size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_ntiles, sc_offsets, sc_partials, sc_eff, sc_pkeys, sc_pvals,
-        sc_pkeys2, sc_pvals2, sc_hist, sc_totals, fwd_bytes;
+    size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_eff2,
+        sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges, sc_tsizes, sc_toff, sc_tpart,
+        fwd_bytes;
     // scratch, backward use
     size_t sc_g2, bwd_bytes;
     size_t scratch_bytes;
@@ -71,15 +127,21 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.N = N;
     L.V = V;
     L.cap = (uint64_t)std::max<int64_t>(0, cfg->pair_capacity);
-    int tb = 0;
+    int tb = 0, max_tiles = 0, max_super = 0;
     int64_t pb = 0;
+    const int S = super_factor(cfg->tile);
     for (int v = 0; v < V; ++v) {
-        L.vg[v].tiles_x = ceil_div(views[v].width, cfg->tile);
-        L.vg[v].tiles_y = ceil_div(views[v].height, cfg->tile);
-        L.vg[v].tile_base = tb;
-        L.vg[v].pix_base = pb;
-        tb += L.vg[v].tiles_x * L.vg[v].tiles_y;
+        ViewGeom& g = L.vg[v];
+        g.tiles_x = ceil_div(views[v].width, cfg->tile);
+        g.tiles_y = ceil_div(views[v].height, cfg->tile);
+        g.sx = ceil_div(g.tiles_x, S);
+        g.sy = ceil_div(g.tiles_y, S);
+        g.tile_base = tb;
+        g.pix_base = pb;
+        tb += g.tiles_x * g.tiles_y;
         pb += (int64_t)views[v].width * views[v].height;
+        max_tiles = std::max(max_tiles, g.tiles_x * g.tiles_y);
+        max_super = std::max(max_super, g.sx * g.sy);
     }
     L.total_tiles = tb;
     L.total_pix = pb;
@@ -100,16 +162,22 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_dvals = f.take(4 * n);
     L.sc_dkeys2 = f.take(4 * n);
     L.sc_dvals2 = f.take(4 * n);
-    L.sc_ntiles = f.take(4 * n);
+    L.sc_cnt = f.take(4 * n);
+    L.sc_rect = f.take(8 * n);
     L.sc_offsets = f.take(8 * (n + 1));
     L.sc_partials = f.take(8 * ((size_t)scan_blocks(N) + 2));
     L.sc_eff = f.take(8);
+    L.sc_eff2 = f.take(8);
     L.sc_pkeys = f.take(4 * (size_t)L.cap);
     L.sc_pvals = f.take(4 * (size_t)L.cap);
     L.sc_pkeys2 = f.take(4 * (size_t)L.cap);
     L.sc_pvals2 = f.take(4 * (size_t)L.cap);
     L.sc_hist = f.take(4 * radix_hist_words(std::max<uint64_t>(L.cap, n)));
     L.sc_totals = f.take(4 * 256);
+    L.sc_cranges = f.take(16 * (size_t)max_super);
+    L.sc_tsizes = f.take(4 * (size_t)max_tiles);
+    L.sc_toff = f.take(8 * ((size_t)max_tiles + 1));
+    L.sc_tpart = f.take(8 * ((size_t)scan_blocks(max_tiles) + 2));
     L.fwd_bytes = f.off;
     Carve b;
     L.sc_g2 = b.take(4 * 9 * n * V_);
@@ -192,9 +260,13 @@ int bits_for(int tiles) {
 }
 
 // Binning, sorting and blending of one view whose records are in place
-// (recs_v, ntiles, dkeys, dvals filled): Alg. 1 lines 7-17.
-void bin_and_blend(const Layout& L, int v, int tile, int chunk, void* state, void* scratch, const Rec* recs_v,
-                   float* image, hipStream_t st) {
+// (recs_v, ntiles, dkeys, dvals filled): Alg. 1 from CreateTiles to BlendInOrder.
+unsigned long long* stat_counters(h4d_ctx* c, void* state, const Layout& L) {
+    return c->stats ? reinterpret_cast<unsigned long long*>(&at<Status>(state, L.st_status)->pad[0]) : nullptr;
+}
+
+void bin_and_blend(h4d_ctx* c, const Layout& L, int v, int tile, int chunk, void* state, void* scratch,
+                   const Rec* recs_v, float* image, hipStream_t st) {
     const int N = L.N;
     uint32_t* dk = at<uint32_t>(scratch, L.sc_dkeys);
     uint32_t* dv = at<uint32_t>(scratch, L.sc_dvals);
@@ -202,51 +274,74 @@ void bin_and_blend(const Layout& L, int v, int tile, int chunk, void* state, voi
     uint32_t* dv2 = at<uint32_t>(scratch, L.sc_dvals2);
     uint32_t* hist = at<uint32_t>(scratch, L.sc_hist);
     uint32_t* totals = at<uint32_t>(scratch, L.sc_totals);
-    // depth order over the Gaussians: 4 stable 8-bit passes over the float32 depth bits
-    for (int pass = 0; pass < 4; ++pass) {
-        const bool even = (pass % 2) == 0;
-        launch_radix_pass(even ? dk : dk2, even ? dv : dv2, even ? dk2 : dk, even ? dv2 : dv, nullptr, (uint64_t)N,
-                          (uint64_t)N, 8 * pass, 8, hist, totals, nullptr, st);
+    {
+        // depth order over the Gaussians: 4 stable 8-bit passes over the float32 depth bits
+        StageScope sc(c, st, H4D_STAGE_DEPTH_SORT);
+        for (int pass = 0; pass < 4; ++pass) {
+            const bool even = (pass % 2) == 0;
+            launch_radix_pass(even ? dk : dk2, even ? dv : dv2, even ? dk2 : dk, even ? dv2 : dv, nullptr,
+                              (uint64_t)N, (uint64_t)N, 8 * pass, 8, hist, totals, nullptr, st);
+        }
     }
-    // per depth-ordered Gaussian: offsets of its (Gaussian, tile) pairs
-    unsigned long long* offsets = at<unsigned long long>(scratch, L.sc_offsets);
-    unsigned long long* partials = at<unsigned long long>(scratch, L.sc_partials);
-    unsigned long long* eff = at<unsigned long long>(scratch, L.sc_eff);
-    uint32_t* ntiles = at<uint32_t>(scratch, L.sc_ntiles);
-    launch_scan_u32_u64(ntiles, dv, N, offsets, partials, st);
     Status* status = at<Status>(state, L.st_status);
     unsigned long long* pair_base = at<unsigned long long>(state, L.st_pair_base);
-    launch_finalize_pairs(offsets, N, pair_base, v, L.cap, status, eff, st);
-    uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
-    uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
-    uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
-    uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
-    const ViewGeom& g = L.vg[v];
-    launch_emit(dv, offsets, N, recs_v, tile, g.tiles_x, eff, pk, pv, st);
-    // stable sort of the tile ids; the last pass writes the ids to their final place
-    const int tiles = g.tiles_x * g.tiles_y;
-    const int bits = bits_for(tiles);
-    const int passes = (bits + 7) / 8;
     uint32_t* ids = at<uint32_t>(state, L.st_ids);
-    uint32_t* kin = pk;
-    uint32_t* vin = pv;
-    int shift = 0;
-    for (int p = 0; p < passes; ++p) {
-        const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
-        const bool last = p == passes - 1;
-        uint32_t* kout = (kin == pk) ? pk2 : pk;
-        uint32_t* vout = last ? ids : ((vin == pv) ? pv2 : pv);
-        launch_radix_pass(kin, vin, kout, vout, eff, 0, L.cap, shift, nb, hist, totals, last ? pair_base + v : nullptr,
+    const ViewGeom& g = L.vg[v];
+    const int tiles = g.tiles_x * g.tiles_y;
+    const int S = super_factor(tile);
+    {
+        StageScope sc(c, st, H4D_STAGE_BINNING);
+        unsigned long long* eff_c = at<unsigned long long>(scratch, L.sc_eff);
+        unsigned long long* eff_r = at<unsigned long long>(scratch, L.sc_eff2);
+        uint32_t* cnt = at<uint32_t>(scratch, L.sc_cnt);
+        uint64_t* rect = at<uint64_t>(scratch, L.sc_rect);
+        unsigned long long* offsets = at<unsigned long long>(scratch, L.sc_offsets);
+        // coarse entries: one per (depth-ordered Gaussian, 64-px super-tile)
+        launch_coarse_count(dv, N, recs_v, tile, S, cnt, rect, st);
+        launch_scan_u32_u64(cnt, nullptr, N, offsets, at<unsigned long long>(scratch, L.sc_partials), st);
+        launch_finalize_coarse(offsets, N, L.cap, S, status, eff_c, st);
+        uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
+        uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
+        uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
+        uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
+        launch_coarse_emit(offsets, N, rect, S, g.sx, eff_c, pk, pv, st);
+        // stable sort of the coarse entries by super-tile (depth order kept inside each)
+        const int bits = bits_for(g.sx * g.sy);
+        const int passes = (bits + 7) / 8;
+        uint32_t* kin = pk;
+        uint32_t* vin = pv;
+        int shift = 0;
+        for (int p = 0; p < passes; ++p) {
+            const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
+            uint32_t* kout = (kin == pk) ? pk2 : pk;
+            uint32_t* vout = (vin == pv) ? pv2 : pv;
+            launch_radix_pass(kin, vin, kout, vout, eff_c, 0, L.cap, shift, nb, hist, totals, nullptr, st);
+            kin = kout;
+            vin = vout;
+            shift += nb;
+        }
+        int64_t* cranges = at<int64_t>(scratch, L.sc_cranges);
+        launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)(g.sx * g.sy), 0ull, st);
+        launch_ranges(kin, eff_c, nullptr, cranges, st);
+        // per-tile regions sized by the super-tile list, then ordered compaction
+        uint32_t* tsizes = at<uint32_t>(scratch, L.sc_tsizes);
+        unsigned long long* toff = at<unsigned long long>(scratch, L.sc_toff);
+        launch_tile_sizes(cranges, tiles, g.tiles_x, S, g.sx, eff_c, tsizes, st);
+        launch_scan_u32_u64(tsizes, nullptr, tiles, toff, at<unsigned long long>(scratch, L.sc_tpart), st);
+        launch_finalize_regions(toff, tiles, pair_base, v, L.cap, status, eff_c, eff_r, st);
+        // the buffer pair the sort did not end in receives (id, local rectangle) per coarse entry
+        uint32_t* cgid = (kin == pk) ? pk2 : pk;
+        uint32_t* crect = (kin == pk) ? pv2 : pv;
+        launch_coarse_gather(kin, vin, rect, dv, S, g.sx, eff_c, cgid, crect, st);
+        int64_t* ranges = at<int64_t>(state, L.st_ranges) + 2 * (size_t)g.tile_base;
+        launch_tile_write(cgid, crect, cranges, toff, pair_base + v, eff_r, tiles, g.tiles_x, S, g.sx, ids, ranges,
                           st);
-        kin = kout;
-        vin = vout;
-        shift += nb;
     }
-    int64_t* ranges = at<int64_t>(state, L.st_ranges) + 2 * (size_t)g.tile_base;
-    launch_ranges(kin, eff, pair_base + v, ranges, st);
+    StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
     const ViewParams* vp = at<ViewParams>(state, L.st_views);
     launch_composite_fwd(tile, chunk, recs_v, ids, at<int64_t>(state, L.st_ranges), vp, v, tiles, image,
-                         at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc), at<float>(state, L.st_C), st);
+                         at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc), at<float>(state, L.st_C),
+                         stat_counters(c, state, L), st);
 }
 
 }  // namespace
@@ -312,9 +407,12 @@ h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     launch_fill_u64(at<unsigned long long>(state, L.st_ranges), 2 * (size_t)L.total_tiles, 0ull, st);
     for (int v = 0; v < n_views; ++v) {
         Rec* recs_v = at<Rec>(state, L.st_recs) + (size_t)v * N;
-        launch_preprocess(p3, p4, vp, v, cfg->tile, recs_v, at<uint32_t>(scratch, L.sc_ntiles),
-                          at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
-        bin_and_blend(L, v, cfg->tile, cfg->chunk, state, scratch, recs_v, images[v], st);
+        {
+            StageScope sc(ctx, st, H4D_STAGE_PREPROCESS);
+            launch_preprocess(p3, p4, vp, v, recs_v, at<uint32_t>(scratch, L.sc_dkeys),
+                              at<uint32_t>(scratch, L.sc_dvals), st);
+        }
+        bin_and_blend(ctx, L, v, cfg->tile, cfg->chunk, state, scratch, recs_v, images[v], st);
     }
     return hip_check(ctx, "render_fwd");
 }
@@ -350,16 +448,23 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     float* g2 = at<float>(scratch, L.sc_g2);
     launch_fill_f32(g2, (size_t)9 * N * n_views, 0.f, st);
     const ViewParams* vp = at<ViewParams>(stt, L.st_views);
-    for (int v = 0; v < n_views; ++v) {
-        const int tiles = L.vg[v].tiles_x * L.vg[v].tiles_y;
-        launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs) + (size_t)v * N, at<uint32_t>(stt, L.st_ids),
-                             at<int64_t>(stt, L.st_ranges), vp, v, tiles, dl_dimages[v], at<float>(stt, L.st_T),
-                             at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), g2 + (size_t)v * 9 * N, N, st);
+    {
+        StageScope sc(ctx, st, H4D_STAGE_BLEND_BWD);
+        for (int v = 0; v < n_views; ++v) {
+            const int tiles = L.vg[v].tiles_x * L.vg[v].tiles_y;
+            launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs) + (size_t)v * N,
+                                 at<uint32_t>(stt, L.st_ids), at<int64_t>(stt, L.st_ranges), vp, v, tiles,
+                                 dl_dimages[v], at<float>(stt, L.st_T), at<uint32_t>(stt, L.st_nc),
+                                 at<float>(stt, L.st_C), g2 + (size_t)v * 9 * N, N, stat_counters(ctx, stt, L), st);
+        }
     }
     const G3Grad r3{grad3->n, grad3->mean, grad3->log_scale, grad3->quat, grad3->opacity, grad3->sh};
     const G4Grad r4{grad4->n, grad4->mean, grad4->mean_t, grad4->log_scale, grad4->quat_l, grad4->quat_r,
                     grad4->opacity, grad4->sh};
-    launch_preprocess_bwd(to_ptr(g3), to_ptr(g4), vp, n_views, at<Rec>(stt, L.st_recs), g2, r3, r4, st);
+    {
+        StageScope sc(ctx, st, H4D_STAGE_PREPROCESS_BWD);
+        launch_preprocess_bwd(to_ptr(g3), to_ptr(g4), vp, n_views, at<Rec>(stt, L.st_recs), g2, r3, r4, st);
+    }
     return hip_check(ctx, "render_bwd");
 }
 
@@ -407,10 +512,9 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     launch_zero_status(at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base), 1, st);
     launch_fill_u64(at<unsigned long long>(state, L.st_ranges), 2 * (size_t)L.total_tiles, 0ull, st);
     Rec* recs = at<Rec>(state, L.st_recs);
-    launch_splats_to_records(n, u, v, conic, opacity, rgb, radius, depth, visible, width, height, cfg->tile, recs,
-                             at<uint32_t>(scratch, L.sc_ntiles), at<uint32_t>(scratch, L.sc_dkeys),
-                             at<uint32_t>(scratch, L.sc_dvals), st);
-    bin_and_blend(L, 0, cfg->tile, cfg->chunk, state, scratch, recs, image, st);
+    launch_splats_to_records(n, u, v, conic, opacity, rgb, radius, depth, visible, width, height, recs,
+                             at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
+    bin_and_blend(ctx, L, 0, cfg->tile, cfg->chunk, state, scratch, recs, image, st);
     const size_t hw = (size_t)width * height;
     if (T_final) (void)hipMemcpyAsync(T_final, at<float>(state, L.st_T), 4 * hw, hipMemcpyDeviceToDevice, st);
     if (sorted_ids && L.cap > 0)
@@ -443,7 +547,8 @@ h4d_status h4dgs_convert_static(h4d_ctx* ctx, const h4d_g4d* in4, const h4d_g3d*
         return fail(ctx, H4D_ERR_INVALID_ARG, "null 4D output array");
     if (out3->n > 0 && (!out3->mean || !out3->log_scale || !out3->quat || !out3->opacity || !out3->sh))
         return fail(ctx, H4D_ERR_INVALID_ARG, "null 3D output array");
-    if ((const void*)out3->mean == (const void*)in3->mean || (const void*)out4->mean == (const void*)in4->mean)
+    if ((in3->n > 0 && (const void*)out3->mean == (const void*)in3->mean) ||
+        (in4->n > 0 && (const void*)out4->mean == (const void*)in4->mean))
         return fail(ctx, H4D_ERR_INVALID_ARG, "outputs must not alias inputs");
     const int n4 = in4->n;
     const size_t need = h4dgs_convert_scratch_bytes(n4);
@@ -474,30 +579,99 @@ h4d_status h4dgs_convert_static(h4d_ctx* ctx, const h4d_g4d* in4, const h4d_g3d*
 }
 
 h4d_status h4dgs_adam(h4d_ctx* ctx, int32_t n_seg, float* const* params, const float* const* grads, float* const* m,
-                      float* const* v, const int64_t* sizes, const float* lrs, float beta1, float beta2, float eps,
-                      int32_t step, void* stream) {
+                      float* const* v, const int64_t* sizes, const float* lrs, double beta1, double beta2,
+                      double eps, int32_t step, void* stream) {
     if (!ctx) return H4D_ERR_INVALID_ARG;
     if (n_seg < 0 || n_seg > kMaxAdamSeg)
         return fail(ctx, H4D_ERR_INVALID_ARG, "n_seg must be in [0, %d]", kMaxAdamSeg);
     if (n_seg > 0 && (!params || !grads || !m || !v || !sizes || !lrs))
         return fail(ctx, H4D_ERR_INVALID_ARG, "null segment table");
     if (step < 1) return fail(ctx, H4D_ERR_INVALID_ARG, "step must be >= 1");
-    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0))
         return fail(ctx, H4D_ERR_INVALID_ARG, "bad Adam constants");
     AdamTable t;
     std::memset(&t, 0, sizeof(t));
     t.n_seg = n_seg;
-    t.b1 = beta1; t.b2 = beta2; t.eps = eps;
-    t.c1 = (float)(1.0 - std::pow((double)beta1, step));
-    t.c2 = (float)(1.0 - std::pow((double)beta2, step));
+    t.b1 = (float)beta1; t.b2 = (float)beta2; t.eps = (float)eps;
+    t.omb1 = (float)(1.0 - beta1);
+    t.omb2 = (float)(1.0 - beta2);
+    t.c1 = (float)(1.0 - std::pow(beta1, step));
+    t.c2 = (float)(1.0 - std::pow(beta2, step));
     for (int i = 0; i < n_seg; ++i) {
         if (sizes[i] < 0) return fail(ctx, H4D_ERR_INVALID_ARG, "segment %d: negative size", i);
         if (sizes[i] > 0 && (!params[i] || !grads[i] || !m[i] || !v[i]))
             return fail(ctx, H4D_ERR_INVALID_ARG, "segment %d: null pointer", i);
         t.seg[i] = AdamSeg{params[i], grads[i], m[i], v[i], sizes[i], lrs[i]};
     }
-    launch_adam(t, static_cast<hipStream_t>(stream));
+    {
+        StageScope sc(ctx, static_cast<hipStream_t>(stream), H4D_STAGE_ADAM);
+        launch_adam(t, static_cast<hipStream_t>(stream));
+    }
     return hip_check(ctx, "adam");
+}
+
+h4d_status h4dgs_l1_loss_grad(h4d_ctx* ctx, int32_t n_views, const float* const* images, const float* const* targets,
+                              const h4d_view* views, float* const* dl_dimages, float* loss, void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    h4d_status s;
+    if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
+    if (!images || !targets || !dl_dimages) return fail(ctx, H4D_ERR_INVALID_ARG, "null image table");
+    for (int v = 0; v < n_views; ++v)
+        if (!images[v] || !targets[v] || !dl_dimages[v]) return fail(ctx, H4D_ERR_INVALID_ARG, "null image %d", v);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StageScope sc(ctx, st, H4D_STAGE_LOSS);
+    if (loss) launch_fill_f32(loss, 1, 0.f, st);  // a fill kernel: safe under graph capture
+    for (int v = 0; v < n_views; ++v) {
+        const size_t n = (size_t)3 * views[v].width * views[v].height;
+        const float scale = (float)(1.0 / ((double)n * n_views));
+        launch_l1_loss_grad(images[v], targets[v], dl_dimages[v], n, scale, loss, st);
+    }
+    return hip_check(ctx, "l1_loss_grad");
+}
+
+h4d_status h4dgs_profile(h4d_ctx* ctx, int32_t enable) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    ctx->profile = enable != 0;
+    return H4D_OK;
+}
+
+h4d_status h4dgs_profile_read(h4d_ctx* ctx, double* ms, int64_t* launches) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    if (!ms || !launches) return fail(ctx, H4D_ERR_INVALID_ARG, "null output");
+    for (int k = 0; k < H4D_STAGE_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    h4d_status rc = H4D_OK;
+    for (auto& m : ctx->marks) {
+        float t = 0.f;
+        if (hipEventSynchronize(m.b) != hipSuccess || hipEventElapsedTime(&t, m.a, m.b) != hipSuccess)
+            rc = fail(ctx, H4D_ERR_HIP, "profile_read: event query failed");
+        if (m.stage >= 0 && m.stage < H4D_STAGE_COUNT) {
+            ms[m.stage] += t;
+            launches[m.stage] += 1;
+        }
+        ctx->pool.push_back(m.a);
+        ctx->pool.push_back(m.b);
+    }
+    ctx->marks.clear();
+    return rc;
+}
+
+h4d_status h4dgs_stats(h4d_ctx* ctx, int32_t enable) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    ctx->stats = enable != 0;
+    return H4D_OK;
+}
+
+h4d_status h4dgs_stats_read(h4d_ctx* ctx, const void* state, size_t state_bytes, int64_t* out, void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    if (!state || state_bytes < sizeof(Status) || !out) return fail(ctx, H4D_ERR_INVALID_ARG, "bad arguments");
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return hip_check(ctx, "stats_read");
+    Status hs;
+    if (hipMemcpy(&hs, state, sizeof(Status), hipMemcpyDeviceToHost) != hipSuccess) return hip_check(ctx, "stats_read");
+    for (int k = 0; k < 4; ++k) out[k] = (int64_t)hs.pad[k];
+    return H4D_OK;
 }
 
 }  // extern "C"

@@ -9,9 +9,9 @@
 // The backward recomputes transmittance front to back with the very same
 // blending step as the forward (eval_splat), takes the colour behind a splat as
 // C_out minus the running prefix, reduces the nine per-splat gradients across the
-// wave with DPP row operations, skips the reduction when no lane of the wave
-// blended the splat, accumulates the wave sums in LDS and flushes one global
-// atomic per (splat, component, tile).
+// wave with DPP, skips that when no lane of the wave blended the splat, adds the
+// wave sums into LDS from one lane and flushes one global atomic per (splat,
+// component, tile).  Each wave stops at its own last contributor.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -46,12 +46,19 @@ __device__ __forceinline__ float next_T(float T, float alpha) {
     return T * oma;
 }
 
-template <int B, int CHUNK>
+__device__ __forceinline__ bool in_square(const Splat& s, int px, int py) {
+    return px >= s.x0 && px <= s.x1 && py >= s.y0 && py <= s.y1;
+}
+
+// STATS = true is a measurement-only instantiation that also counts (pixel,
+// splat) evaluations and blends into counters[0..1].
+template <int B, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(B * B) k_composite_fwd(const Rec* __restrict__ recs, const uint32_t* __restrict__ ids,
                                                          const int64_t* __restrict__ ranges,
                                                          const ViewParams* __restrict__ views, int view,
                                                          float* __restrict__ image, float* __restrict__ Tfin,
-                                                         uint32_t* __restrict__ ncontrib, float* __restrict__ Cout) {
+                                                         uint32_t* __restrict__ ncontrib, float* __restrict__ Cout,
+                                                         unsigned long long* counters) {
     constexpr int NT = B * B;
     __shared__ LSplat s_sp[CHUNK];
     const ViewParams& V = views[view];
@@ -64,6 +71,7 @@ __global__ void __launch_bounds__(B * B) k_composite_fwd(const Rec* __restrict__
     const int64_t end = ranges[2 * (size_t)(V.tile_base + tile) + 1];
     float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
     uint32_t last = 0;
+    unsigned long long n_eval = 0, n_blend = 0;
     bool done = !inside;
     for (int64_t base = start; base < end; base += CHUNK) {
         if (__syncthreads_count(done) == NT) break;
@@ -75,12 +83,14 @@ __global__ void __launch_bounds__(B * B) k_composite_fwd(const Rec* __restrict__
                 const Splat s = to_splat(s_sp[j]);
                 float dx, dy, G, alpha;
                 bool clamped;
+                if (STATS && in_square(s, px, py)) ++n_eval;
                 if (!eval_splat(s, px, py, pxc, pyc, dx, dy, G, alpha, clamped)) continue;
                 const float Tn = next_T(T, alpha);
                 if (Tn < kMinT) {
                     done = true;
                     break;
                 }
+                if (STATS) ++n_blend;
                 const float w = alpha * T;
                 cr = __builtin_fmaf(s.cr, w, cr);
                 cg = __builtin_fmaf(s.cg, w, cg);
@@ -105,33 +115,47 @@ __global__ void __launch_bounds__(B * B) k_composite_fwd(const Rec* __restrict__
         Cout[3 * (size_t)V.pix_base + HW + p] = o1;
         Cout[3 * (size_t)V.pix_base + 2 * HW + p] = o2;
     }
+    if (STATS) {
+        atomicAdd(&counters[0], n_eval);
+        atomicAdd(&counters[1], n_blend);
+    }
 }
 
-// Sum over the 64 lanes of a wave; the total is returned in every lane.
-// quad xor1, quad xor2, half-row mirror, row mirror give each row of 16 its sum;
-// two row broadcasts fold the rows into lane 63, which is then read back.
-__device__ __forceinline__ float wave_sum(float v) {
+// Sum over the 64 lanes of a wave, complete in lane 63: quad xor1, quad xor2,
+// half-row mirror and row mirror give every lane its row's sum, then two row
+// broadcasts fold rows 0-2 into row 3.
+__device__ __forceinline__ float wave_sum_to_63(float v) {
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    return v;
 }
 
-template <int B, int CHUNK>
+// Largest value over the wave.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    return v;
+}
+
+template <int B, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(B * B) k_composite_bwd(const Rec* __restrict__ recs, const uint32_t* __restrict__ ids,
                                                          const int64_t* __restrict__ ranges,
                                                          const ViewParams* __restrict__ views, int view,
                                                          const float* __restrict__ dl, const float* __restrict__ Tfin,
                                                          const uint32_t* __restrict__ ncontrib,
                                                          const float* __restrict__ Cout, float* __restrict__ g2,
-                                                         int N) {
+                                                         int N, unsigned long long* counters) {
     constexpr int NT = B * B;
     __shared__ LSplat s_sp[CHUNK];
     __shared__ uint32_t s_gid[CHUNK];
-    __shared__ float s_acc[9][CHUNK];
+    // wave sums of the chunk's splats (one LDS atomic per wave and component);
+    // a single slot keeps the block's LDS small and its occupancy high
+    constexpr int NW = NT / 64;
+    constexpr int SLOTS = 1;
+    __shared__ float s_acc[SLOTS][9][CHUNK];
     __shared__ uint32_t s_max;
     const ViewParams& V = views[view];
     const int tile = blockIdx.x;
@@ -157,8 +181,10 @@ __global__ void __launch_bounds__(B * B) k_composite_bwd(const Rec* __restrict__
     if (nc) atomicMax(&s_max, nc);
     __syncthreads();
     const int64_t end = start + (int64_t)s_max;
+    const uint32_t wave_nc = wave_max_u32(nc);
     float T = 1.0f, pr = 0.f, pg = 0.f, pb = 0.f;
     const float kinv = -1.0f / kLog2e;
+    unsigned long long n_eval = 0, n_blend = 0;
     for (int64_t base = start; base < end; base += CHUNK) {
         const int cnt = (int)min((int64_t)CHUNK, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) {
@@ -166,14 +192,20 @@ __global__ void __launch_bounds__(B * B) k_composite_bwd(const Rec* __restrict__
             s_gid[k] = gid;
             stage_splat(recs[gid], s_sp[k]);
         }
-        for (int k = threadIdx.x; k < 9 * CHUNK; k += NT) (&s_acc[0][0])[k] = 0.f;
+        for (int k = threadIdx.x; k < SLOTS * 9 * CHUNK; k += NT) (&s_acc[0][0][0])[k] = 0.f;
         __syncthreads();
         const uint32_t rel0 = (uint32_t)(base - start);
-        for (int j = 0; j < cnt; ++j) {
+        // entries past this wave's last contributor need no work
+        const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
+        for (int j = 0; j < jend; ++j) {
             const Splat s = to_splat(s_sp[j]);
             float dx = 0.f, dy = 0.f, Gk = 0.f, alpha = 0.f;
             bool clamped = false;
             const bool bl = (rel0 + (uint32_t)j < nc) && eval_splat(s, px, py, pxc, pyc, dx, dy, Gk, alpha, clamped);
+            if (STATS) {
+                n_eval += (rel0 + (uint32_t)j < nc) && in_square(s, px, py);
+                n_blend += bl;
+            }
             if (__ballot(bl) == 0ull) continue;  // wave-uniform skip
             float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
             if (bl) {
@@ -202,28 +234,36 @@ __global__ void __launch_bounds__(B * B) k_composite_bwd(const Rec* __restrict__
                 }
                 T = next_T(T, alpha);
             }
-            const float r0 = wave_sum(v0), r1 = wave_sum(v1), r2 = wave_sum(v2), r3 = wave_sum(v3),
-                        r4 = wave_sum(v4), r5 = wave_sum(v5), r6 = wave_sum(v6), r7 = wave_sum(v7),
-                        r8 = wave_sum(v8);
-            if (__lane_id() == 0) {
-                atomicAdd(&s_acc[0][j], r0);
-                atomicAdd(&s_acc[1][j], r1);
-                atomicAdd(&s_acc[2][j], r2);
-                atomicAdd(&s_acc[3][j], r3);
-                atomicAdd(&s_acc[4][j], r4);
-                atomicAdd(&s_acc[5][j], r5);
-                atomicAdd(&s_acc[6][j], r6);
-                atomicAdd(&s_acc[7][j], r7);
-                atomicAdd(&s_acc[8][j], r8);
+            const float r0 = wave_sum_to_63(v0), r1 = wave_sum_to_63(v1), r2 = wave_sum_to_63(v2),
+                        r3 = wave_sum_to_63(v3), r4 = wave_sum_to_63(v4), r5 = wave_sum_to_63(v5),
+                        r6 = wave_sum_to_63(v6), r7 = wave_sum_to_63(v7), r8 = wave_sum_to_63(v8);
+            if (__lane_id() == 63) {
+                if (NW == 1) {
+                    float* a = &s_acc[0][0][j];
+                    a[0 * CHUNK] = r0; a[1 * CHUNK] = r1; a[2 * CHUNK] = r2;
+                    a[3 * CHUNK] = r3; a[4 * CHUNK] = r4; a[5 * CHUNK] = r5;
+                    a[6 * CHUNK] = r6; a[7 * CHUNK] = r7; a[8 * CHUNK] = r8;
+                } else {
+                    atomicAdd(&s_acc[0][0][j], r0); atomicAdd(&s_acc[0][1][j], r1);
+                    atomicAdd(&s_acc[0][2][j], r2); atomicAdd(&s_acc[0][3][j], r3);
+                    atomicAdd(&s_acc[0][4][j], r4); atomicAdd(&s_acc[0][5][j], r5);
+                    atomicAdd(&s_acc[0][6][j], r6); atomicAdd(&s_acc[0][7][j], r7);
+                    atomicAdd(&s_acc[0][8][j], r8);
+                }
             }
         }
         __syncthreads();
         for (int k = threadIdx.x; k < 9 * cnt; k += NT) {
             const int c = k / cnt, j = k - c * cnt;
-            const float val = s_acc[c][j];
+            float val = s_acc[0][c][j];
+            for (int w = 1; w < SLOTS; ++w) val += s_acc[w][c][j];
             if (val != 0.f) atomicAdd(&g2[(size_t)c * N + s_gid[j]], val);
         }
         __syncthreads();
+    }
+    if (STATS) {
+        atomicAdd(&counters[2], n_eval);
+        atomicAdd(&counters[3], n_blend);
     }
 }
 
@@ -233,14 +273,25 @@ bool composite_supported(int tile, int chunk) {
 
 template <int B, int C>
 static void fwd_t(const Rec* recs, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int view,
-                  int n_tiles, float* image, float* Tfin, uint32_t* ncontrib, float* Cout, hipStream_t st) {
-    k_composite_fwd<B, C><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, image, Tfin, ncontrib, Cout);
+                  int n_tiles, float* image, float* Tfin, uint32_t* ncontrib, float* Cout, unsigned long long* counters,
+                  hipStream_t st) {
+    if (counters)
+        k_composite_fwd<B, C, true><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, image, Tfin, ncontrib,
+                                                               Cout, counters);
+    else
+        k_composite_fwd<B, C, false><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, image, Tfin, ncontrib,
+                                                                Cout, nullptr);
 }
 template <int B, int C>
 static void bwd_t(const Rec* recs, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int view,
                   int n_tiles, const float* dl, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
-                  float* g2, int N, hipStream_t st) {
-    k_composite_bwd<B, C><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, dl, Tfin, ncontrib, Cout, g2, N);
+                  float* g2, int N, unsigned long long* counters, hipStream_t st) {
+    if (counters)
+        k_composite_bwd<B, C, true><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, dl, Tfin, ncontrib, Cout,
+                                                               g2, N, counters);
+    else
+        k_composite_bwd<B, C, false><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, dl, Tfin, ncontrib,
+                                                                Cout, g2, N, nullptr);
 }
 
 #define H4D_DISPATCH(FN, ...)                                                   \
@@ -258,16 +309,17 @@ static void bwd_t(const Rec* recs, const uint32_t* ids, const int64_t* ranges, c
 
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int view, int n_tiles, float* image, float* Tfin,
-                          uint32_t* ncontrib, float* Cout, hipStream_t st) {
+                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(fwd_t, recs, ids, ranges, views, view, n_tiles, image, Tfin, ncontrib, Cout, st);
+    H4D_DISPATCH(fwd_t, recs, ids, ranges, views, view, n_tiles, image, Tfin, ncontrib, Cout, counters, st);
 }
 
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int view, int n_tiles, const float* dl, const float* Tfin,
-                          const uint32_t* ncontrib, const float* Cout, float* g2, int N, hipStream_t st) {
+                          const uint32_t* ncontrib, const float* Cout, float* g2, int N, unsigned long long* counters,
+                          hipStream_t st) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(bwd_t, recs, ids, ranges, views, view, n_tiles, dl, Tfin, ncontrib, Cout, g2, N, st);
+    H4D_DISPATCH(bwd_t, recs, ids, ranges, views, view, n_tiles, dl, Tfin, ncontrib, Cout, g2, N, counters, st);
 }
 
 }  // namespace h4d

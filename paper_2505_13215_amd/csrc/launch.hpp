@@ -21,14 +21,13 @@ struct ViewTableIn {
 
 // preprocess.hip
 void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st);
-void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, int tile, Rec* recs,
-                       uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, Rec* recs,
+                       uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
                            const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st);
 void launch_splats_to_records(int n, const float* u, const float* v, const float* conic, const float* opacity,
                               const float* rgb, const int32_t* radius, const float* depth, const uint8_t* visible,
-                              int W, int H, int tile, Rec* recs, uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals,
-                              hipStream_t st);
+                              int W, int H, Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
 
 // sort.hip
 constexpr int kSortThreads = 256;
@@ -48,10 +47,25 @@ int scan_blocks(int n);
 // out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
 void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigned long long* out,
                          unsigned long long* partials, hipStream_t st);
-void launch_finalize_pairs(const unsigned long long* offsets, int n, unsigned long long* pair_base, int view,
-                           uint64_t capacity, Status* status, unsigned long long* eff_count, hipStream_t st);
-void launch_emit(const uint32_t* sorted_gid, const unsigned long long* offsets, int n, const Rec* recs, int tile,
-                 int tiles_x, const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st);
+void launch_coarse_count(const uint32_t* sorted_gid, int n, const Rec* recs, int tile, int S, uint32_t* cnt,
+                         uint64_t* rect_sorted, hipStream_t st);
+void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
+                            unsigned long long* eff_count, hipStream_t st);
+void launch_coarse_emit(const unsigned long long* offsets, int n, const uint64_t* rect_sorted, int S, int SX,
+                        const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st);
+void launch_tile_sizes(const int64_t* cranges, int tiles, int tiles_x, int S, int SX,
+                       const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st);
+void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int view,
+                             uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
+                             unsigned long long* eff_regions, hipStream_t st);
+void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
+                          const uint32_t* sorted_gid, int S, int SX, const unsigned long long* eff_count,
+                          uint32_t* cgid, uint32_t* crect, hipStream_t st);
+void launch_tile_write(const uint32_t* cgid, const uint32_t* crect, const int64_t* cranges,
+                       const unsigned long long* region_off, const unsigned long long* base_ptr,
+                       const unsigned long long* eff_regions, int tiles, int tiles_x, int S, int SX, uint32_t* ids,
+                       int64_t* ranges, hipStream_t st);
+// ranges of sorted keys: ranges[2k], ranges[2k+1] = [first, last+1) + *base (base may be null)
 void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,
                    int64_t* ranges, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
@@ -62,10 +76,14 @@ void launch_zero_status(Status* s, unsigned long long* pair_base, int n_views, h
 bool composite_supported(int tile, int chunk);
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int view, int n_tiles, float* image, float* Tfin,
-                          uint32_t* ncontrib, float* Cout, hipStream_t st);
+                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st);
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int view, int n_tiles, const float* dl, const float* Tfin,
-                          const uint32_t* ncontrib, const float* Cout, float* g2, int N, hipStream_t st);
+                          const uint32_t* ncontrib, const float* Cout, float* g2, int N, unsigned long long* counters,
+                          hipStream_t st);
+// L1 loss gradient (loss.hip)
+void launch_l1_loss_grad(const float* img, const float* target, float* dl, size_t n, float scale, float* loss,
+                         hipStream_t st);
 
 // convert.hip
 void launch_convert_static(const G4Ptr& in4, const G3Ptr& in3, double log_tau, const G4Grad& out4,
@@ -84,7 +102,7 @@ struct AdamSeg {
 constexpr int kMaxAdamSeg = 16;
 struct AdamTable {
     int32_t n_seg;
-    float b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
+    float b1, b2, omb1, omb2, eps, c1, c2;  // omb = 1 - b, c1 = 1 - b1^t, c2 = 1 - b2^t
     AdamSeg seg[kMaxAdamSeg];
 };
 void launch_adam(const AdamTable& t, hipStream_t st);

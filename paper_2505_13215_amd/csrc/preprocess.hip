@@ -260,9 +260,8 @@ __device__ inline void colour(const float* shp, int n, int i, const double Y[16]
 // Forward kernel: one thread per Gaussian of the merged list [4D | 3D].
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const ViewParams* __restrict__ views,
-                                                    int view, int tile, Rec* __restrict__ recs,
-                                                    uint32_t* __restrict__ ntiles, uint32_t* __restrict__ dkeys,
-                                                    uint32_t* __restrict__ dvals) {
+                                                    int view, Rec* __restrict__ recs,
+                                                    uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
     const int N = g3.n + g4.n;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
@@ -282,7 +281,6 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
     ProjF p;
     project(V, w, p);
     Rec rec;
-    uint32_t nt = 0;
     uint32_t key = kCulledKey;
     if (!p.culled && p.covered) {
         const double iD = 1.0 / p.det;
@@ -298,7 +296,6 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
         rec.c = make_float4((float)fmax(raw[2], 0.0), (float)fu, (float)fv, depth);
         rec.d = make_uint4((uint32_t)p.x0 | ((uint32_t)p.x1 << 16), (uint32_t)p.y0 | ((uint32_t)p.y1 << 16),
                            (uint32_t)p.r, 1u);
-        nt = (uint32_t)((p.x1 / tile - p.x0 / tile + 1) * (p.y1 / tile - p.y0 / tile + 1));
         key = __float_as_uint(depth);
     } else {
         rec.a = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -307,7 +304,6 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
         rec.d = make_uint4(0u, 0u, 0u, 0u);
     }
     recs[g] = rec;
-    ntiles[g] = nt;
     dkeys[g] = key;
     dvals[g] = (uint32_t)g;
 }
@@ -318,14 +314,15 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
 // g2: per (view, Gaussian) screen-space gradients from the blending adjoint,
 // layout [view][9][N]: du dv dQ00 dQ01 dQ11 dop dr dg db (w.r.t. the unscaled
 // conic entries, Q01 counted once).
+//
+// Per view the projection adjoint gives mu_c-bar, Sigma_c-bar and op-bar; the
+// slicing adjoint maps them to the spatial/temporal means and to the symmetric
+// part of Sigma4-bar, which is summed over views so that the covariance and
+// rotation adjoints run once per Gaussian.
 // ---------------------------------------------------------------------------
-struct Acc {
-    double mu[3], mt, ls[4], q[4], q2[4], op, sh[48];
-};
-
 __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const ProjF& p, const float* shp, int shn,
                                 int shi, const float* g2, size_t gstride, double gmu[3], double Sb[3][3],
-                                double& gop, double* gsh) {
+                                double& gop, float* gsh) {
     const double gu = g2[0], gv = g2[gstride], gQa = g2[2 * gstride], gQb = g2[3 * gstride],
                  gQc = g2[4 * gstride];
     gop = g2[5 * gstride];
@@ -334,14 +331,16 @@ __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const Proj
     double Y[16], raw[3];
     sh_eval(p.dir[0], p.dir[1], p.dir[2], Y);
     colour(shp, shn, shi, Y, raw);
+    double gc[3];
+    for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] > 0.0 ? grgb[ch] : 0.0;
     double wY[16];
-    for (int k = 0; k < 16; ++k) wY[k] = 0.0;
-    for (int ch = 0; ch < 3; ++ch) {
-        const double gc = raw[ch] > 0.0 ? grgb[ch] : 0.0;
-        for (int k = 0; k < 16; ++k) {
-            gsh[k * 3 + ch] += gc * Y[k];
-            wY[k] += gc * (double)shp[(size_t)(k * 3 + ch) * shn + shi];
+    for (int k = 0; k < 16; ++k) {
+        double acc = 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+            gsh[k * 3 + ch] += (float)(gc[ch] * Y[k]);
+            acc += gc[ch] * (double)shp[(size_t)(k * 3 + ch) * shn + shi];
         }
+        wY[k] = acc;
     }
     double gd[3];
     sh_grad_dot(p.dir[0], p.dir[1], p.dir[2], wY, gd);
@@ -356,183 +355,229 @@ __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const Proj
     const double T10 = Q01 * G00 + Q11 * G01, T11 = Q01 * G01 + Q11 * G11;
     const double B00 = -(T00 * Q00 + T01 * Q01), B01 = -(T00 * Q01 + T01 * Q11);
     const double B11 = -(T10 * Q01 + T11 * Q11);
-    const double Bm[2][2] = {{B00, B01}, {B01, B11}};
-    // Sigma_c bar = M^T B M
+    // Sigma_c bar = M^T B M (symmetric)
+    double BM[2][3];
+    for (int c = 0; c < 3; ++c) {
+        BM[0][c] = B00 * p.M[0][c] + B01 * p.M[1][c];
+        BM[1][c] = B01 * p.M[0][c] + B11 * p.M[1][c];
+    }
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double acc = 0;
-            for (int k = 0; k < 2; ++k)
-                for (int l = 0; l < 2; ++l) acc += p.M[k][i] * Bm[k][l] * p.M[l][j];
-            Sb[i][j] = acc;
+        for (int j = i; j < 3; ++j) {
+            const double v = p.M[0][i] * BM[0][j] + p.M[1][i] * BM[1][j];
+            Sb[i][j] = v;
+            Sb[j][i] = v;
         }
-    // M bar = 2 B M Sigma_c ; J bar = M bar R^T
-    double MS[2][3];
-    for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 3; ++c) MS[r][c] = p.M[r][0] * w.S[0][c] + p.M[r][1] * w.S[1][c] + p.M[r][2] * w.S[2][c];
+    // M bar = 2 B M Sigma_c ; J bar = M bar R^T (only the four non-zero J entries matter)
     double Mb[2][3];
     for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 3; ++c) Mb[r][c] = 2.0 * (Bm[r][0] * MS[0][c] + Bm[r][1] * MS[1][c]);
-    double Jb[2][3];
-    for (int r = 0; r < 2; ++r)
-        for (int k = 0; k < 3; ++k) Jb[r][k] = Mb[r][0] * V.R[3 * k] + Mb[r][1] * V.R[3 * k + 1] + Mb[r][2] * V.R[3 * k + 2];
+        for (int c = 0; c < 3; ++c)
+            Mb[r][c] = 2.0 * (BM[r][0] * w.S[0][c] + BM[r][1] * w.S[1][c] + BM[r][2] * w.S[2][c]);
+    const double Jb00 = Mb[0][0] * V.R[0] + Mb[0][1] * V.R[1] + Mb[0][2] * V.R[2];
+    const double Jb02 = Mb[0][0] * V.R[6] + Mb[0][1] * V.R[7] + Mb[0][2] * V.R[8];
+    const double Jb11 = Mb[1][0] * V.R[3] + Mb[1][1] * V.R[4] + Mb[1][2] * V.R[5];
+    const double Jb12 = Mb[1][0] * V.R[6] + Mb[1][1] * V.R[7] + Mb[1][2] * V.R[8];
     const double z = p.pc[2], iz = 1.0 / z, iz2 = iz * iz;
-    double pb[3] = {0, 0, 0};
-    pb[2] += -Jb[0][0] * V.fx * iz2 + Jb[0][2] * V.fx * p.xt * iz2 - Jb[1][1] * V.fy * iz2 + Jb[1][2] * V.fy * p.yt * iz2;
+    double pb0, pb1, pb2;
+    pb2 = -Jb00 * V.fx * iz2 + Jb02 * V.fx * p.xt * iz2 - Jb11 * V.fy * iz2 + Jb12 * V.fy * p.yt * iz2;
     double xb = gu * V.fx, yb = gv * V.fy;
-    if (!p.clx) xb += -Jb[0][2] * V.fx * iz;
-    if (!p.cly) yb += -Jb[1][2] * V.fy * iz;
-    pb[0] += xb * iz;
-    pb[1] += yb * iz;
-    pb[2] += -(xb * p.pc[0] + yb * p.pc[1]) * iz2;
-    for (int k = 0; k < 3; ++k) gmu[k] += V.R[k] * pb[0] + V.R[3 + k] * pb[1] + V.R[6 + k] * pb[2];
+    if (!p.clx) xb += -Jb02 * V.fx * iz;
+    if (!p.cly) yb += -Jb12 * V.fy * iz;
+    pb0 = xb * iz;
+    pb1 = yb * iz;
+    pb2 += -(xb * p.pc[0] + yb * p.pc[1]) * iz2;
+    for (int k = 0; k < 3; ++k) gmu[k] += V.R[k] * pb0 + V.R[3 + k] * pb1 + V.R[6 + k] * pb2;
 }
 
-// Sigma = Lm Lm^T, Lm = R diag(s): returns Rbar and accumulates dlog_scale.
-template <int D>
-__device__ inline void cov_bwd(const double Sb[D][D], const double R[D][D], const double s[D], double Rb[D][D],
-                               double* gls) {
-    double Lb[D][D];
-    for (int i = 0; i < D; ++i)
-        for (int j = 0; j < D; ++j) {
-            double acc = 0;
-            for (int k = 0; k < D; ++k) acc += (Sb[i][k] + Sb[k][i]) * R[k][j] * s[j];
-            Lb[i][j] = acc;
-        }
-    for (int j = 0; j < D; ++j) {
-        double acc = 0;
-        for (int i = 0; i < D; ++i) acc += R[i][j] * Lb[i][j];
-        gls[j] += acc * s[j];
-    }
-    for (int i = 0; i < D; ++i)
-        for (int j = 0; j < D; ++j) Rb[i][j] = Lb[i][j] * s[j];
-}
-
-__device__ inline void unit_bwd(const double qh[4], double nrm, const double gqh[4], double* gq) {
+__device__ inline void unit_bwd(const double qh[4], double nrm, const double gqh[4], float* out, size_t stride) {
     const double dq = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
     const double in = 1.0 / nrm;
-    for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - qh[k] * dq) * in;
+    for (int k = 0; k < 4; ++k) out[k * stride] = (float)((gqh[k] - qh[k] * dq) * in);
 }
 
-__global__ void __launch_bounds__(128) k_preprocess_bwd(G3Ptr g3, G4Ptr g4, const ViewParams* __restrict__ views,
-                                                        int n_views, const Rec* __restrict__ recs,
-                                                        const float* __restrict__ g2, G3Grad gr3, G4Grad gr4) {
-    const int N = g3.n + g4.n;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= N) return;
-    const bool is4 = g < g4.n;
-    Acc acc;
-    for (int k = 0; k < 3; ++k) acc.mu[k] = 0;
-    acc.mt = 0; acc.op = 0;
-    for (int k = 0; k < 4; ++k) { acc.ls[k] = 0; acc.q[k] = 0; acc.q2[k] = 0; }
-    for (int k = 0; k < 48; ++k) acc.sh[k] = 0;
+__device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restrict__ views, int n_views, int N,
+                              const Rec* __restrict__ recs, const float* __restrict__ g2, const G4Grad& gr) {
+    const size_t n = (size_t)g4.n;
+    double s[4], ql[4], qr[4];
+    for (int k = 0; k < 4; ++k) s[k] = exp((double)g4.log_scale[k * n + i]);
+    const double nl = load_unit4(g4.quat_l, g4.n, i, ql);
+    const double nr = load_unit4(g4.quat_r, g4.n, i, qr);
+    double R[4][4];
+    {
+        double L[4][4], Rr[4][4];
+        rot_left(ql, L);
+        rot_right(qr, Rr);
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c)
+                R[r][c] = L[r][0] * Rr[0][c] + L[r][1] * Rr[1][c] + L[r][2] * Rr[2][c] + L[r][3] * Rr[3][c];
+    }
+    double S4[4][4];
+    for (int r = 0; r < 4; ++r)
+        for (int c = r; c < 4; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 4; ++k) acc += R[r][k] * s[k] * s[k] * R[c][k];
+            S4[r][c] = acc;
+            S4[c][r] = acc;
+        }
+    const double c = S4[3][3], ic = 1.0 / c;
+    const double b[3] = {S4[0][3], S4[1][3], S4[2][3]};
+    const double mu0[3] = {(double)g4.mean[i], (double)g4.mean[n + i], (double)g4.mean[2 * n + i]};
+    const double mt = (double)g4.mean_t[i];
+    const double sig = sigmoid((double)g4.opacity[i]);
+    double gmu[3] = {0, 0, 0}, gmt = 0, gsig = 0;
+    double Ss[4][4];  // accumulated Sigma4-bar + Sigma4-bar^T
+    for (int r = 0; r < 4; ++r)
+        for (int k = 0; k < 4; ++k) Ss[r][k] = 0.0;
+    float gsh[48];
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
     for (int v = 0; v < n_views; ++v) {
-        if (recs[(size_t)v * N + g].d.w == 0u) continue;  // not covering any pixel in this view
+        if (recs[(size_t)v * N + i].d.w == 0u) continue;  // covers no pixel in this view
         const ViewParams& V = views[v];
-        const float* gv = g2 + (size_t)v * 9 * N + g;
+        const double delta = V.time - mt;
+        const double pt = exp(-(delta * delta) * 0.5 * ic);
         WorldF w;
+        for (int k = 0; k < 3; ++k) w.mu[k] = mu0[k] + b[k] * ic * delta;
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) w.S[r][k] = S4[r][k] - b[r] * b[k] * ic;
+        w.op = sig * pt;
         ProjF p;
-        double gmu[3], Sb[3][3], gop;
-        if (is4) {
-            Slice4 z;
-            world4(g4, g, V.time, w, z);
-            project(V, w, p);
-            proj_bwd(V, w, p, g4.sh, g4.n, g, gv, (size_t)N, gmu, Sb, gop, acc.sh);
-            // effective opacity sigma * p(t)
-            const double gsig = gop * z.pt, gpt = gop * z.sig;
-            acc.op += gsig * z.sig * (1.0 - z.sig);
-            const double ic = 1.0 / z.c;
-            double gmt = gpt * z.pt * z.delta * ic;
-            double gc = gpt * z.pt * z.delta * z.delta * 0.5 * ic * ic;
-            const double mub = gmu[0] * z.b[0] + gmu[1] * z.b[1] + gmu[2] * z.b[2];
-            double gb[3];
-            for (int k = 0; k < 3; ++k) {
-                acc.mu[k] += gmu[k];
-                gb[k] = gmu[k] * z.delta * ic;
-            }
-            gmt -= mub * ic;
-            gc -= mub * z.delta * ic * ic;
-            double bSb = 0;
-            for (int i = 0; i < 3; ++i) {
-                double r = 0;
-                for (int j = 0; j < 3; ++j) {
-                    bSb += z.b[i] * Sb[i][j] * z.b[j];
-                    r += (Sb[i][j] + Sb[j][i]) * z.b[j];
-                }
-                gb[i] -= r * ic;
-            }
-            gc += bSb * ic * ic;
-            acc.mt += gmt;
-            double S4b[4][4];
-            for (int i = 0; i < 3; ++i) {
-                for (int j = 0; j < 3; ++j) S4b[i][j] = Sb[i][j];
-                S4b[i][3] = gb[i];
-                S4b[3][i] = 0.0;
-            }
-            S4b[3][3] = gc;
-            double Rb[4][4];
-            cov_bwd<4>(S4b, z.rot.R, z.s, Rb, acc.ls);
-            // R = L Rr: Lbar = Rbar Rr^T, Rrbar = L^T Rbar
-            double Lb[4][4], Rrb[4][4];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) {
-                    double a1 = 0, a2 = 0;
-                    for (int k = 0; k < 4; ++k) {
-                        a1 += Rb[i][k] * z.rot.Rr[j][k];
-                        a2 += z.rot.L[k][i] * Rb[k][j];
-                    }
-                    Lb[i][j] = a1;
-                    Rrb[i][j] = a2;
-                }
-            double gl[4], grr[4];
-            gl[0] = Lb[0][0] + Lb[1][1] + Lb[2][2] + Lb[3][3];
-            gl[1] = -Lb[0][1] + Lb[1][0] - Lb[2][3] + Lb[3][2];
-            gl[2] = -Lb[0][2] + Lb[1][3] + Lb[2][0] - Lb[3][1];
-            gl[3] = -Lb[0][3] - Lb[1][2] + Lb[2][1] + Lb[3][0];
-            grr[0] = Rrb[0][0] + Rrb[1][1] + Rrb[2][2] + Rrb[3][3];
-            grr[1] = -Rrb[0][1] + Rrb[1][0] + Rrb[2][3] - Rrb[3][2];
-            grr[2] = -Rrb[0][2] - Rrb[1][3] + Rrb[2][0] + Rrb[3][1];
-            grr[3] = -Rrb[0][3] + Rrb[1][2] - Rrb[2][1] + Rrb[3][0];
-            unit_bwd(z.ql, z.nl, gl, acc.q);
-            unit_bwd(z.qr, z.nr, grr, acc.q2);
-        } else {
-            Cov3 z;
-            const int i = g - g4.n;
-            world3(g3, i, w, z);
-            project(V, w, p);
-            proj_bwd(V, w, p, g3.sh, g3.n, i, gv, (size_t)N, gmu, Sb, gop, acc.sh);
-            acc.op += gop * z.sig * (1.0 - z.sig);
-            for (int k = 0; k < 3; ++k) acc.mu[k] += gmu[k];
-            double Rb[3][3];
-            cov_bwd<3>(Sb, z.R, z.s, Rb, acc.ls);
-            const double qw = z.q[0], qx = z.q[1], qy = z.q[2], qz = z.q[3];
-            double gq[4];
-            gq[0] = 2.0 * (-qz * Rb[0][1] + qy * Rb[0][2] + qz * Rb[1][0] - qx * Rb[1][2] - qy * Rb[2][0] + qx * Rb[2][1]);
-            gq[1] = 2.0 * (qy * Rb[0][1] + qz * Rb[0][2] + qy * Rb[1][0] - 2.0 * qx * Rb[1][1] - qw * Rb[1][2] +
-                           qz * Rb[2][0] + qw * Rb[2][1] - 2.0 * qx * Rb[2][2]);
-            gq[2] = 2.0 * (-2.0 * qy * Rb[0][0] + qx * Rb[0][1] + qw * Rb[0][2] + qx * Rb[1][0] + qz * Rb[1][2] -
-                           qw * Rb[2][0] + qz * Rb[2][1] - 2.0 * qy * Rb[2][2]);
-            gq[3] = 2.0 * (-2.0 * qz * Rb[0][0] - qw * Rb[0][1] + qx * Rb[0][2] + qw * Rb[1][0] - 2.0 * qz * Rb[1][1] +
-                           qy * Rb[1][2] + qx * Rb[2][0] + qy * Rb[2][1]);
-            unit_bwd(z.q, z.nq, gq, acc.q);
+        project(V, w, p);
+        double gmc[3], Sb[3][3], gop;
+        proj_bwd(V, w, p, g4.sh, g4.n, i, g2 + (size_t)v * 9 * N + i, (size_t)N, gmc, Sb, gop, gsh);
+        // effective opacity sigma * p(t); p(t) = exp(-delta^2 / (2 c))
+        gsig += gop * pt;
+        const double gpt = gop * sig;
+        const double mub = gmc[0] * b[0] + gmc[1] * b[1] + gmc[2] * b[2];
+        gmt += gpt * pt * delta * ic - mub * ic;
+        double gc = gpt * pt * delta * delta * 0.5 * ic * ic - mub * delta * ic * ic;
+        double bSb = 0.0;
+        for (int r = 0; r < 3; ++r) {
+            double row = 0.0;
+            for (int k = 0; k < 3; ++k) row += Sb[r][k] * b[k];
+            bSb += b[r] * row;
+            // b-bar (mean and covariance terms); Sb is symmetric
+            const double gb = gmc[r] * delta * ic - 2.0 * row * ic;
+            Ss[r][3] += gb;
+            Ss[3][r] += gb;
+            gmu[r] += gmc[r];
+        }
+        gc += bSb * ic * ic;
+        Ss[3][3] += 2.0 * gc;
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) Ss[r][k] += 2.0 * Sb[r][k];
+    }
+    // Sigma4 = Lm Lm^T, Lm = R diag(s): Lbar = Ss Lm, Rbar = Lbar diag(s), sbar_j = (R^T Lbar)_jj
+    double Rb[4][4];
+    for (int r = 0; r < 4; ++r)
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 4; ++k) acc += Ss[r][k] * R[k][j];
+            Rb[r][j] = acc * s[j] * s[j];  // = Lbar * s
+        }
+    for (int j = 0; j < 4; ++j) {
+        double acc = 0.0;
+        for (int r = 0; r < 4; ++r) acc += R[r][j] * Rb[r][j];
+        gr.log_scale[j * n + i] = (float)acc;  // sbar_j s_j = sum_r R_rj Lbar_rj s_j
+    }
+    // R = L Rr: Lbar = Rbar Rr^T, Rrbar = L^T Rbar; each entry is +/- one quaternion component
+    double gl[4], grr[4];
+    {
+        double Rr[4][4];
+        rot_right(qr, Rr);
+        double Lb[4][4];
+        for (int r = 0; r < 4; ++r)
+            for (int c2 = 0; c2 < 4; ++c2)
+                Lb[r][c2] = Rb[r][0] * Rr[c2][0] + Rb[r][1] * Rr[c2][1] + Rb[r][2] * Rr[c2][2] + Rb[r][3] * Rr[c2][3];
+        gl[0] = Lb[0][0] + Lb[1][1] + Lb[2][2] + Lb[3][3];
+        gl[1] = -Lb[0][1] + Lb[1][0] - Lb[2][3] + Lb[3][2];
+        gl[2] = -Lb[0][2] + Lb[1][3] + Lb[2][0] - Lb[3][1];
+        gl[3] = -Lb[0][3] - Lb[1][2] + Lb[2][1] + Lb[3][0];
+    }
+    {
+        double L[4][4];
+        rot_left(ql, L);
+        double Rrb[4][4];
+        for (int r = 0; r < 4; ++r)
+            for (int c2 = 0; c2 < 4; ++c2)
+                Rrb[r][c2] = L[0][r] * Rb[0][c2] + L[1][r] * Rb[1][c2] + L[2][r] * Rb[2][c2] + L[3][r] * Rb[3][c2];
+        grr[0] = Rrb[0][0] + Rrb[1][1] + Rrb[2][2] + Rrb[3][3];
+        grr[1] = -Rrb[0][1] + Rrb[1][0] + Rrb[2][3] - Rrb[3][2];
+        grr[2] = -Rrb[0][2] - Rrb[1][3] + Rrb[2][0] + Rrb[3][1];
+        grr[3] = -Rrb[0][3] + Rrb[1][2] - Rrb[2][1] + Rrb[3][0];
+    }
+    unit_bwd(ql, nl, gl, gr.quat_l + i, n);
+    unit_bwd(qr, nr, grr, gr.quat_r + i, n);
+    for (int k = 0; k < 3; ++k) gr.mean[k * n + i] = (float)gmu[k];
+    gr.mean_t[i] = (float)gmt;
+    gr.opacity[i] = (float)(gsig * sig * (1.0 - sig));
+    for (int k = 0; k < 48; ++k) gr.sh[k * n + i] = gsh[k];
+}
+
+__device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams* __restrict__ views, int n_views,
+                              int N, const Rec* __restrict__ recs, const float* __restrict__ g2, const G3Grad& gr) {
+    const size_t n = (size_t)g3.n;
+    WorldF w;
+    Cov3 z;
+    world3(g3, i, w, z);
+    double gmu[3] = {0, 0, 0}, gsig = 0;
+    double Ss[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    float gsh[48];
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    for (int v = 0; v < n_views; ++v) {
+        if (recs[(size_t)v * N + gidx].d.w == 0u) continue;
+        const ViewParams& V = views[v];
+        ProjF p;
+        project(V, w, p);
+        double gmc[3], Sb[3][3], gop;
+        proj_bwd(V, w, p, g3.sh, g3.n, i, g2 + (size_t)v * 9 * N + gidx, (size_t)N, gmc, Sb, gop, gsh);
+        gsig += gop;
+        for (int r = 0; r < 3; ++r) {
+            gmu[r] += gmc[r];
+            for (int k = 0; k < 3; ++k) Ss[r][k] += 2.0 * Sb[r][k];
         }
     }
-    if (is4) {
-        const size_t n = (size_t)g4.n, i = (size_t)g;
-        for (int k = 0; k < 3; ++k) gr4.mean[k * n + i] = (float)acc.mu[k];
-        gr4.mean_t[i] = (float)acc.mt;
-        for (int k = 0; k < 4; ++k) gr4.log_scale[k * n + i] = (float)acc.ls[k];
-        for (int k = 0; k < 4; ++k) gr4.quat_l[k * n + i] = (float)acc.q[k];
-        for (int k = 0; k < 4; ++k) gr4.quat_r[k * n + i] = (float)acc.q2[k];
-        gr4.opacity[i] = (float)acc.op;
-        for (int k = 0; k < 48; ++k) gr4.sh[k * n + i] = (float)acc.sh[k];
-    } else {
-        const size_t n = (size_t)g3.n, i = (size_t)(g - g4.n);
-        for (int k = 0; k < 3; ++k) gr3.mean[k * n + i] = (float)acc.mu[k];
-        for (int k = 0; k < 3; ++k) gr3.log_scale[k * n + i] = (float)acc.ls[k];
-        for (int k = 0; k < 4; ++k) gr3.quat[k * n + i] = (float)acc.q[k];
-        gr3.opacity[i] = (float)acc.op;
-        for (int k = 0; k < 48; ++k) gr3.sh[k * n + i] = (float)acc.sh[k];
+    double Rb[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += Ss[r][k] * z.R[k][j];
+            Rb[r][j] = acc * z.s[j] * z.s[j];
+        }
+    for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int r = 0; r < 3; ++r) acc += z.R[r][j] * Rb[r][j];
+        gr.log_scale[j * n + i] = (float)acc;
     }
+    const double qw = z.q[0], qx = z.q[1], qy = z.q[2], qz = z.q[3];
+    double gq[4];
+    gq[0] = 2.0 * (-qz * Rb[0][1] + qy * Rb[0][2] + qz * Rb[1][0] - qx * Rb[1][2] - qy * Rb[2][0] + qx * Rb[2][1]);
+    gq[1] = 2.0 * (qy * Rb[0][1] + qz * Rb[0][2] + qy * Rb[1][0] - 2.0 * qx * Rb[1][1] - qw * Rb[1][2] +
+                   qz * Rb[2][0] + qw * Rb[2][1] - 2.0 * qx * Rb[2][2]);
+    gq[2] = 2.0 * (-2.0 * qy * Rb[0][0] + qx * Rb[0][1] + qw * Rb[0][2] + qx * Rb[1][0] + qz * Rb[1][2] -
+                   qw * Rb[2][0] + qz * Rb[2][1] - 2.0 * qy * Rb[2][2]);
+    gq[3] = 2.0 * (-2.0 * qz * Rb[0][0] - qw * Rb[0][1] + qx * Rb[0][2] + qw * Rb[1][0] - 2.0 * qz * Rb[1][1] +
+                   qy * Rb[1][2] + qx * Rb[2][0] + qy * Rb[2][1]);
+    unit_bwd(z.q, z.nq, gq, gr.quat + i, n);
+    for (int k = 0; k < 3; ++k) gr.mean[k * n + i] = (float)gmu[k];
+    gr.opacity[i] = (float)(gsig * z.sig * (1.0 - z.sig));
+    for (int k = 0; k < 48; ++k) gr.sh[k * n + i] = gsh[k];
+}
+
+// Two kernels so that the lighter 3D path is not compiled for the 4D path's
+// register footprint.
+__global__ void __launch_bounds__(128) k_preprocess_bwd4(G4Ptr g4, int N, const ViewParams* __restrict__ views,
+                                                         int n_views, const Rec* __restrict__ recs,
+                                                         const float* __restrict__ g2, G4Grad gr4) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= g4.n) return;
+    bwd_4d(g4, g, views, n_views, N, recs, g2, gr4);
+}
+
+__global__ void __launch_bounds__(128) k_preprocess_bwd3(G3Ptr g3, int n4, int N, const ViewParams* __restrict__ views,
+                                                         int n_views, const Rec* __restrict__ recs,
+                                                         const float* __restrict__ g2, G3Grad gr3) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g3.n) return;
+    bwd_3d(g3, i, n4 + i, views, n_views, N, recs, g2, gr3);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,25 +615,27 @@ void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st) 
     k_write_views<<<1, 1, 0, st>>>(in, out);
 }
 
-void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, int tile, Rec* recs,
-                       uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, Rec* recs,
+                       uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
     const int N = g3.n + g4.n;
     if (N == 0) return;
-    k_preprocess<<<ceil_div(N, 256), 256, 0, st>>>(g3, g4, views, view, tile, recs, ntiles, dkeys, dvals);
+    k_preprocess<<<ceil_div(N, 256), 256, 0, st>>>(g3, g4, views, view, recs, dkeys, dvals);
 }
 
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
                            const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st) {
     const int N = g3.n + g4.n;
     if (N == 0) return;
-    k_preprocess_bwd<<<ceil_div(N, 128), 128, 0, st>>>(g3, g4, views, n_views, recs, g2, gr3, gr4);
+    if (g4.n > 0) k_preprocess_bwd4<<<ceil_div(g4.n, 128), 128, 0, st>>>(g4, N, views, n_views, recs, g2, gr4);
+    if (g3.n > 0)
+        k_preprocess_bwd3<<<ceil_div(g3.n, 128), 128, 0, st>>>(g3, g4.n, N, views, n_views, recs, g2, gr3);
 }
 
 }  // namespace h4d
 
 namespace h4d {
 
-// Screen-space splats given directly (Alg. 1 lines 7-17 without projection):
+// Screen-space splats given directly (Alg. 1 without the projection steps):
 // the same record format, pixel square computed in FP64 from (u, v, r).
 __global__ void __launch_bounds__(256) k_splats_to_records(int n, const float* __restrict__ u,
                                                            const float* __restrict__ v,
@@ -598,9 +645,8 @@ __global__ void __launch_bounds__(256) k_splats_to_records(int n, const float* _
                                                            const int32_t* __restrict__ radius,
                                                            const float* __restrict__ depth,
                                                            const uint8_t* __restrict__ visible, int W, int H,
-                                                           int tile, Rec* __restrict__ recs,
-                                                           uint32_t* __restrict__ ntiles,
-                                                           uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
+                                                           Rec* __restrict__ recs, uint32_t* __restrict__ dkeys,
+                                                           uint32_t* __restrict__ dvals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     Rec rec;
@@ -608,7 +654,7 @@ __global__ void __launch_bounds__(256) k_splats_to_records(int n, const float* _
     rec.b = rec.a;
     rec.c = rec.a;
     rec.d = make_uint4(0u, 0u, 0u, 0u);
-    uint32_t nt = 0, key = kCulledKey;
+    uint32_t key = kCulledKey;
     const int r = radius[i];
     if (visible[i] && r >= 0) {
         const double uu = u[i], vv = v[i];
@@ -622,23 +668,20 @@ __global__ void __launch_bounds__(256) k_splats_to_records(int n, const float* _
             rec.b = make_float4((float)((double)conic[2 * (size_t)n + i] * s), opacity[i], rgb[i], rgb[(size_t)n + i]);
             rec.c = make_float4(rgb[2 * (size_t)n + i], (float)fu, (float)fv, depth[i]);
             rec.d = make_uint4((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16), (uint32_t)r, 1u);
-            nt = (uint32_t)((x1 / tile - x0 / tile + 1) * (y1 / tile - y0 / tile + 1));
             key = __float_as_uint(depth[i]);
         }
     }
     recs[i] = rec;
-    ntiles[i] = nt;
     dkeys[i] = key;
     dvals[i] = (uint32_t)i;
 }
 
 void launch_splats_to_records(int n, const float* u, const float* v, const float* conic, const float* opacity,
                               const float* rgb, const int32_t* radius, const float* depth, const uint8_t* visible,
-                              int W, int H, int tile, Rec* recs, uint32_t* ntiles, uint32_t* dkeys, uint32_t* dvals,
-                              hipStream_t st) {
+                              int W, int H, Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
     if (n == 0) return;
     k_splats_to_records<<<ceil_div(n, 256), 256, 0, st>>>(n, u, v, conic, opacity, rgb, radius, depth, visible, W, H,
-                                                          tile, recs, ntiles, dkeys, dvals);
+                                                          recs, dkeys, dvals);
 }
 
 }  // namespace h4d

@@ -3,10 +3,16 @@
 //
 // Design: the per-view depth order is established once over the N Gaussians
 // (LSD radix sort of the float32 depth bits, stable, so equal depths keep
-// ascending id), pairs are then emitted in that order and only the tile id is
-// sorted (a stable LSD radix sort over ceil(log2(tiles)) bits).  Stability makes
-// the final order exactly (tile, depth bits, id) while moving 8 bytes per pair
-// per pass instead of sorting 64-bit (tile, depth) keys.
+// ascending id).  Binning is then two-level: every depth-ordered Gaussian emits
+// one coarse entry per 64-pixel super-tile its square touches; a stable sort of
+// the coarse entries by super-tile keeps depth order inside each super-tile's
+// list; finally one workgroup per tile walks its super-tile's list and compacts
+// (64-lane ballot + prefix) the entries whose tile rectangle contains the tile
+// into that tile's region.  Every tile list is therefore exactly its (depth
+// bits, id)-ordered set of overlapping splats - the order a global
+// (tile, depth, id) sort gives - without sorting (Gaussian, tile) pairs at all.
+// Tile regions are sized by their super-tile's list length, so lists are not
+// contiguous across tiles; ranges give each list's [start, end).
 //
 // Every LSD pass is: per-block digit histogram -> per-digit scan across blocks
 // -> stable scatter.  The stable scatter ranks keys inside a wave with ballots
@@ -59,29 +65,40 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* 
     __syncthreads();
     const uint64_t n = read_count(dcount, hcount);
     const uint64_t begin = (uint64_t)blockIdx.x * kSortTile;
-    if (begin < n) {
-        for (int k = 0; k < kSortItems; ++k) {
-            const uint64_t idx = begin + (uint64_t)k * kSortThreads + tid;
-            if (idx < n) atomicAdd(&s_hist[w][(keys[idx] >> shift) & mask], 1u);
-        }
+    if (begin >= n) return;  // blocks past the live count are never scanned (uniform)
+    for (int k = 0; k < kSortItems; ++k) {
+        const uint64_t idx = begin + (uint64_t)k * kSortThreads + tid;
+        if (idx < n) atomicAdd(&s_hist[w][(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int d = tid; d < radix; d += kSortThreads)
         hist[(size_t)d * nblocks + blockIdx.x] = s_hist[0][d] + s_hist[1][d] + s_hist[2][d] + s_hist[3][d];
 }
 
-// one block per digit: exclusive scan of that digit's per-block counts
+// one block per digit: exclusive scan of that digit's per-block counts over the
+// blocks that hold live keys (4 counts per thread per round)
 __global__ void __launch_bounds__(256) k_radix_digit_scan(uint32_t* __restrict__ hist, int nblocks,
-                                                          uint32_t* __restrict__ totals) {
+                                                          uint32_t* __restrict__ totals,
+                                                          const unsigned long long* dcount, uint64_t hcount) {
     __shared__ uint32_t s_buf[256];
+    const uint64_t n = read_count(dcount, hcount);
+    const int live = (int)min((uint64_t)nblocks, (n + kSortTile - 1) / kSortTile);
     uint32_t* h = hist + (size_t)blockIdx.x * nblocks;
     uint32_t carry = 0;
-    for (int start = 0; start < nblocks; start += 256) {
-        const int i = start + threadIdx.x;
-        const uint32_t v = i < nblocks ? h[i] : 0u;
+    for (int start = 0; start < live; start += 1024) {
+        const int i0 = start + 4 * (int)threadIdx.x;
+        uint32_t v[4];
+        uint32_t sum = 0;
+        for (int q = 0; q < 4; ++q) {
+            v[q] = i0 + q < live ? h[i0 + q] : 0u;
+            sum += v[q];
+        }
         uint32_t tot;
-        const uint32_t ex = block_exclusive_scan_256<uint32_t>(v, s_buf, tot);
-        if (i < nblocks) h[i] = carry + ex;
+        uint32_t ex = block_exclusive_scan_256<uint32_t>(sum, s_buf, tot) + carry;
+        for (int q = 0; q < 4; ++q) {
+            if (i0 + q < live) h[i0 + q] = ex;
+            ex += v[q];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
@@ -181,7 +198,7 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
     const int nb = radix_blocks(capacity);
     if (nb == 0) return;
     k_radix_upsweep<<<nb, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb);
-    k_radix_digit_scan<<<1 << nbits, 256, 0, st>>>(hist, nb, totals);
+    k_radix_digit_scan<<<1 << nbits, 256, 0, st>>>(hist, nb, totals, dcount, hcount);
     k_radix_downsweep<<<nb, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount, shift, nbits,
                                                     hist, totals, nb, out_offset);
 }
@@ -250,73 +267,207 @@ void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigne
 }
 
 // ---------------------------------------------------------------------------
-// Pair bookkeeping, emission, ranges.
+// Two-level binning.
 // ---------------------------------------------------------------------------
-__global__ void k_finalize_pairs(const unsigned long long* offsets, int n, unsigned long long* pair_base, int view,
-                                 uint64_t capacity, Status* status, unsigned long long* eff_count) {
+__device__ __forceinline__ uint64_t pack_rect(uint32_t x0, uint32_t x1, uint32_t y0, uint32_t y1) {
+    return (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) | ((uint64_t)y1 << 48);
+}
+
+// Per depth-ordered Gaussian j: its tile rectangle and its super-tile count.
+__global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n,
+                                                      const Rec* __restrict__ recs, int tile, int S,
+                                                      uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint4 d = recs[sorted_gid[j]].d;
+    if (d.w == 0u) {
+        cnt[j] = 0u;
+        rect_sorted[j] = 0ull;
+        return;
+    }
+    const uint32_t t = (uint32_t)tile, s = (uint32_t)S;
+    const uint32_t tx0 = (d.x & 0xFFFFu) / t, tx1 = (d.x >> 16) / t, ty0 = (d.y & 0xFFFFu) / t, ty1 = (d.y >> 16) / t;
+    rect_sorted[j] = pack_rect(tx0, tx1, ty0, ty1);
+    cnt[j] = (tx1 / s - tx0 / s + 1u) * (ty1 / s - ty0 / s + 1u);
+}
+
+__global__ void k_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
+                                  unsigned long long* eff_count) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long P = offsets[n];
-    const unsigned long long base = pair_base[view];
-    status->pairs_needed += P;
-    if (base + P > capacity) {
+    const unsigned long long C = offsets[n];
+    if (C > capacity) {
         status->flags |= kFlagOverflow;
+        status->pairs_needed += C * (unsigned long long)(S * S);  // regions hold at most S*S copies
         *eff_count = 0ull;
-        pair_base[view + 1] = base;
     } else {
-        *eff_count = P;
-        pair_base[view + 1] = base + P;
+        *eff_count = C;
     }
 }
 
-// One block per 256 depth-ordered Gaussians; threads stride over the block's
-// contiguous pair range and find their Gaussian by binary search in LDS, so the
-// key/value writes are coalesced.
-__global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ sorted_gid,
-                                              const unsigned long long* __restrict__ offsets, int n,
-                                              const Rec* __restrict__ recs, int tile, int tiles_x,
-                                              const unsigned long long* eff_count, uint32_t* __restrict__ keys,
-                                              uint32_t* __restrict__ vals) {
+// Coarse entries (super-tile id, depth rank j), written in depth order.  One
+// block per 256 depth-ordered Gaussians; threads stride over the block's
+// contiguous output range and find their Gaussian by binary search in LDS.
+__global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* __restrict__ offsets, int n,
+                                                     const uint64_t* __restrict__ rect_sorted, int S, int SX,
+                                                     const unsigned long long* eff_count, uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals) {
     __shared__ unsigned long long s_off[257];
-    __shared__ uint32_t s_gid[256], s_tx0[256], s_ty0[256], s_tw[256];
+    __shared__ uint32_t s_sx0[256], s_sy0[256], s_sw[256];
     if (*eff_count == 0ull) return;
     const int tid = threadIdx.x;
     const int j0 = blockIdx.x * 256;
     const int j = j0 + tid;
     if (j < n) {
-        const uint32_t g = sorted_gid[j];
-        s_gid[tid] = g;
+        const uint64_t r = rect_sorted[j];
+        const uint32_t s = (uint32_t)S;
+        const uint32_t sx0 = (uint32_t)(r & 0xFFFFu) / s, sx1 = (uint32_t)((r >> 16) & 0xFFFFu) / s;
         s_off[tid] = offsets[j];
-        const uint4 d = recs[g].d;
-        const uint32_t x0 = d.x & 0xFFFFu, x1 = d.x >> 16, y0 = d.y & 0xFFFFu;
-        s_tx0[tid] = x0 / (uint32_t)tile;
-        s_tw[tid] = x1 / (uint32_t)tile - x0 / (uint32_t)tile + 1u;
-        s_ty0[tid] = y0 / (uint32_t)tile;
+        s_sx0[tid] = sx0;
+        s_sw[tid] = sx1 - sx0 + 1u;
+        s_sy0[tid] = (uint32_t)((r >> 32) & 0xFFFFu) / s;
     } else {
         s_off[tid] = offsets[n];
-        s_gid[tid] = 0; s_tx0[tid] = 0; s_tw[tid] = 1; s_ty0[tid] = 0;
+        s_sx0[tid] = 0; s_sw[tid] = 1; s_sy0[tid] = 0;
     }
     if (tid == 0) s_off[256] = offsets[min(j0 + 256, n)];
     __syncthreads();
     const unsigned long long start = s_off[0], end = s_off[256];
     for (unsigned long long p = start + tid; p < end; p += 256) {
-        // last k with s_off[k] <= p
-        int lo = 0, hi = 256;
+        int lo = 0, hi = 256;  // last k with s_off[k] <= p
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (s_off[mid] <= p) lo = mid; else hi = mid;
         }
         const uint32_t local = (uint32_t)(p - s_off[lo]);
-        const uint32_t tw = s_tw[lo];
-        const uint32_t ty = local / tw, tx = local - ty * tw;
-        keys[p] = (s_ty0[lo] + ty) * (uint32_t)tiles_x + s_tx0[lo] + tx;
-        vals[p] = s_gid[lo];
+        const uint32_t sw = s_sw[lo];
+        const uint32_t sy = local / sw, sx = local - sy * sw;
+        keys[p] = (s_sy0[lo] + sy) * (uint32_t)SX + s_sx0[lo] + sx;
+        vals[p] = (uint32_t)(j0 + lo);
+    }
+}
+
+// Region size of every tile = length of its super-tile's list.
+__global__ void __launch_bounds__(256) k_tile_sizes(const int64_t* __restrict__ cranges, int tiles, int tiles_x, int S,
+                                                    int SX, const unsigned long long* eff_count,
+                                                    uint32_t* __restrict__ sizes) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    if (*eff_count == 0ull) {
+        sizes[t] = 0u;
+        return;
+    }
+    const int st = ((t / tiles_x) / S) * SX + (t % tiles_x) / S;
+    sizes[t] = (uint32_t)(cranges[2 * st + 1] - cranges[2 * st]);
+}
+
+__global__ void k_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int view,
+                                   uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
+                                   unsigned long long* eff_regions) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long base = pair_base[view];
+    if (*eff_coarse == 0ull && (status->flags & kFlagOverflow)) {
+        *eff_regions = 0ull;
+        pair_base[view + 1] = base;
+        return;
+    }
+    const unsigned long long R = region_off[tiles];
+    status->pairs_needed += R;
+    if (base + R > capacity) {
+        status->flags |= kFlagOverflow;
+        *eff_regions = 0ull;
+        pair_base[view + 1] = base;
+    } else {
+        *eff_regions = 1ull;
+        pair_base[view + 1] = base + R;
+    }
+}
+
+// After the coarse sort: per coarse entry k (super-tile st, depth rank j) the
+// splat id and its tile rectangle clipped to the super-tile, in super-tile-local
+// coordinates (4 bits each), so that the per-tile pass streams 8 bytes per entry.
+__global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ ckeys,
+                                                       const uint32_t* __restrict__ cvals,
+                                                       const uint64_t* __restrict__ rect_sorted,
+                                                       const uint32_t* __restrict__ sorted_gid, int S, int SX,
+                                                       const unsigned long long* eff_count, uint32_t* __restrict__ cgid,
+                                                       uint32_t* __restrict__ crect) {
+    const uint64_t n = *eff_count;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t st = ckeys[k], j = cvals[k];
+        const uint64_t r = rect_sorted[j];
+        const uint32_t bx = (st % (uint32_t)SX) * (uint32_t)S, by = (st / (uint32_t)SX) * (uint32_t)S;
+        const uint32_t x0 = (uint32_t)(r & 0xFFFFu), x1 = (uint32_t)((r >> 16) & 0xFFFFu);
+        const uint32_t y0 = (uint32_t)((r >> 32) & 0xFFFFu), y1 = (uint32_t)(r >> 48);
+        const uint32_t lx0 = max(x0, bx) - bx, lx1 = min(x1, bx + (uint32_t)S - 1u) - bx;
+        const uint32_t ly0 = max(y0, by) - by, ly1 = min(y1, by + (uint32_t)S - 1u) - by;
+        cgid[k] = sorted_gid[j];
+        crect[k] = lx0 | (lx1 << 4) | (ly0 << 8) | (ly1 << 12);
+    }
+}
+
+// One workgroup per tile: compact, in order, the entries of its super-tile's
+// list whose tile rectangle contains the tile; write the tile's range.  Each
+// round streams 1024 entries (4 per thread, striped) and orders them with wave
+// ballots and one barrier.
+__global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__ cgid,
+                                                    const uint32_t* __restrict__ crect,
+                                                    const int64_t* __restrict__ cranges,
+                                                    const unsigned long long* __restrict__ region_off,
+                                                    const unsigned long long* base_ptr,
+                                                    const unsigned long long* eff_regions, int tiles_x, int S, int SX,
+                                                    uint32_t* __restrict__ ids, int64_t* __restrict__ ranges) {
+    __shared__ uint32_t s_wc[2][4][4];  // [parity][round][wave]
+    if (*eff_regions == 0ull) return;
+    const int t = blockIdx.x;
+    const uint32_t tx = (uint32_t)(t % tiles_x), ty = (uint32_t)(t / tiles_x);
+    const int st = (int)(ty / (uint32_t)S) * SX + (int)(tx / (uint32_t)S);
+    const uint32_t lx = tx % (uint32_t)S, ly = ty % (uint32_t)S;
+    const int64_t cs = cranges[2 * st], ce = cranges[2 * st + 1];
+    const uint64_t out = (uint64_t)*base_ptr + (uint64_t)region_off[t];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const unsigned long long lt = lanemask_lt();
+    uint64_t run = 0;
+    int parity = 0;
+    for (int64_t k0 = cs; k0 < ce; k0 += 1024, parity ^= 1) {
+        uint32_t gid[4];
+        unsigned long long bal[4];
+        bool ov[4];
+        for (int r = 0; r < 4; ++r) {
+            const int64_t k = k0 + r * 256 + tid;
+            ov[r] = false;
+            gid[r] = 0;
+            if (k < ce) {
+                const uint32_t rc = crect[k];
+                ov[r] = lx >= (rc & 15u) && lx <= ((rc >> 4) & 15u) && ly >= ((rc >> 8) & 15u) && ly <= (rc >> 12);
+                if (ov[r]) gid[r] = cgid[k];
+            }
+            bal[r] = __ballot(ov[r]);
+            if ((tid & 63) == 0) s_wc[parity][r][w] = (uint32_t)__popcll(bal[r]);
+        }
+        __syncthreads();
+        uint32_t base_r = 0;
+        for (int r = 0; r < 4; ++r) {
+            uint32_t woff = 0, tot = 0;
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t c = s_wc[parity][r][q];
+                woff += q < w ? c : 0u;
+                tot += c;
+            }
+            if (ov[r]) ids[out + run + base_r + woff + (uint32_t)__popcll(bal[r] & lt)] = gid[r];
+            base_r += tot;
+        }
+        run += base_r;
+    }
+    if (tid == 0) {
+        ranges[2 * (size_t)t] = (int64_t)out;
+        ranges[2 * (size_t)t + 1] = (int64_t)(out + run);
     }
 }
 
 __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ keys, const unsigned long long* eff_count,
                                                 const unsigned long long* base_ptr, int64_t* __restrict__ ranges) {
     const uint64_t n = *eff_count;
-    const int64_t base = (int64_t)*base_ptr;
+    const int64_t base = base_ptr ? (int64_t)*base_ptr : 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t t = keys[i];
         if (i == 0 || keys[i - 1] != t) ranges[2 * (size_t)t] = base + (int64_t)i;
@@ -336,14 +487,42 @@ __global__ void k_zero_status(Status* s, unsigned long long* pair_base, int n_vi
     for (int v = t; v <= n_views; v += blockDim.x) pair_base[v] = 0ull;
 }
 
-void launch_finalize_pairs(const unsigned long long* offsets, int n, unsigned long long* pair_base, int view,
-                           uint64_t capacity, Status* status, unsigned long long* eff_count, hipStream_t st) {
-    k_finalize_pairs<<<1, 1, 0, st>>>(offsets, n, pair_base, view, capacity, status, eff_count);
-}
-void launch_emit(const uint32_t* sorted_gid, const unsigned long long* offsets, int n, const Rec* recs, int tile,
-                 int tiles_x, const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st) {
+void launch_coarse_count(const uint32_t* sorted_gid, int n, const Rec* recs, int tile, int S, uint32_t* cnt,
+                         uint64_t* rect_sorted, hipStream_t st) {
     if (n == 0) return;
-    k_emit<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, offsets, n, recs, tile, tiles_x, eff_count, keys, vals);
+    k_coarse_count<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, n, recs, tile, S, cnt, rect_sorted);
+}
+void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
+                            unsigned long long* eff_count, hipStream_t st) {
+    k_finalize_coarse<<<1, 1, 0, st>>>(offsets, n, capacity, S, status, eff_count);
+}
+void launch_coarse_emit(const unsigned long long* offsets, int n, const uint64_t* rect_sorted, int S, int SX,
+                        const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st) {
+    if (n == 0) return;
+    k_coarse_emit<<<ceil_div(n, 256), 256, 0, st>>>(offsets, n, rect_sorted, S, SX, eff_count, keys, vals);
+}
+void launch_tile_sizes(const int64_t* cranges, int tiles, int tiles_x, int S, int SX,
+                       const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st) {
+    if (tiles == 0) return;
+    k_tile_sizes<<<ceil_div(tiles, 256), 256, 0, st>>>(cranges, tiles, tiles_x, S, SX, eff_count, sizes);
+}
+void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int view,
+                             uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
+                             unsigned long long* eff_regions, hipStream_t st) {
+    k_finalize_regions<<<1, 1, 0, st>>>(region_off, tiles, pair_base, view, capacity, status, eff_coarse, eff_regions);
+}
+void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
+                          const uint32_t* sorted_gid, int S, int SX, const unsigned long long* eff_count,
+                          uint32_t* cgid, uint32_t* crect, hipStream_t st) {
+    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, S, SX, eff_count, cgid, crect);
+}
+void launch_tile_write(const uint32_t* cgid, const uint32_t* crect, const int64_t* cranges,
+                       const unsigned long long* region_off, const unsigned long long* base_ptr,
+                       const unsigned long long* eff_regions, int tiles, int tiles_x, int S, int SX, uint32_t* ids,
+                       int64_t* ranges, hipStream_t st) {
+    if (tiles == 0) return;
+    k_tile_write<<<tiles, 256, 0, st>>>(cgid, crect, cranges, region_off, base_ptr, eff_regions, tiles_x, S, SX, ids,
+                                        ranges);
 }
 void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,
                    int64_t* ranges, hipStream_t st) {

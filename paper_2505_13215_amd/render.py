@@ -141,12 +141,20 @@ class Rasterizer:
         self.ctx.check(rc)
         return self.last_pairs
 
-    def backward(self, h: FwdHandle, g3: dict, g4: dict, dl_images) -> tuple:
+    def backward(self, h: FwdHandle, g3: dict, g4: dict, dl_images, out=None) -> tuple:
+        """Gradients of every raw parameter; ``out`` = (gr3, gr4) dicts to fill in place."""
         if h.generation != self._gen:
             raise RuntimeError("backward must follow its own forward (the workspace was reused)")
         s3, s4 = g3_struct(g3), g4_struct(g4)
-        gr3 = {k: torch.empty_like(g3[k]) for k in G3_KEYS}
-        gr4 = {k: torch.empty_like(g4[k]) for k in G4_KEYS}
+        if out is None:
+            gr3 = {k: torch.empty_like(g3[k]) for k in G3_KEYS}
+            gr4 = {k: torch.empty_like(g4[k]) for k in G4_KEYS}
+        else:
+            gr3, gr4 = out
+            for k in G3_KEYS:
+                _chk(gr3[k], "grad3." + k)
+            for k in G4_KEYS:
+                _chk(gr4[k], "grad4." + k)
         m3 = L.G3D(s3.n, *[_ptr(gr3[k]) for k in G3_KEYS])
         m4 = L.G4D(s4.n, *[_ptr(gr4[k]) for k in G4_KEYS])
         dl = [_chk(d, "dl_dimage") for d in dl_images]
@@ -155,6 +163,40 @@ class Rasterizer:
             self.ctx.h, C.byref(s3), C.byref(s4), h.views, h.n_views, C.byref(h.cfg), arr, _ptr(h.state),
             h.state.numel(), _ptr(self._scratch), self._scratch.numel(), C.byref(m3), C.byref(m4), _stream()))
         return gr3, gr4
+
+
+    # -- instrumentation -----------------------------------------------------------
+    def profile(self, enable: bool = True):
+        self.ctx.check(self.ctx.L.h4dgs_profile(self.ctx.h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        """{stage: (total_ms, launches)} since the previous read (synchronises)."""
+        n = len(L.STAGES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        self.ctx.check(self.ctx.L.h4dgs_profile_read(self.ctx.h, ms, cnt))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(L.STAGES)}
+
+    def stats(self, enable: bool = True):
+        self.ctx.check(self.ctx.L.h4dgs_stats(self.ctx.h, int(bool(enable))))
+
+    def stats_read(self) -> dict:
+        out = (C.c_int64 * 4)()
+        self.ctx.check(self.ctx.L.h4dgs_stats_read(self.ctx.h, _ptr(self._state), self._state.numel(), out,
+                                                   _stream()))
+        return dict(fwd_eval=int(out[0]), fwd_blend=int(out[1]), bwd_eval=int(out[2]), bwd_blend=int(out[3]))
+
+
+def l1_loss_grad(rast: Rasterizer, images, targets, views, dl_out, loss: torch.Tensor = None):
+    """dl_out[v] = sign(images[v] - targets[v]) / (3 W H n_views); loss (1-element
+    float32 CUDA tensor, optional) = mean over views of the mean absolute error."""
+    n = len(images)
+    va = L.view_array(views)
+    rast.ctx.check(rast.ctx.L.h4dgs_l1_loss_grad(
+        rast.ctx.h, n, L.ptr_array([_chk(i, "image").data_ptr() for i in images]),
+        L.ptr_array([_chk(t, "target").data_ptr() for t in targets]), va,
+        L.ptr_array([_chk(d, "dl").data_ptr() for d in dl_out]), _ptr(loss) if loss is not None else None,
+        _stream()))
 
 
 class H4DGSRender(torch.autograd.Function):
@@ -188,7 +230,8 @@ def render(rast: Rasterizer, g3: dict, g4: dict, views) -> tuple:
 
 def rasterize_splats(rast: Rasterizer, sp: dict, width: int, height: int, bg=(0.0, 0.0, 0.0)):
     """Binning, sorting and blending of given screen-space splats.  Returns
-    (image[3,H,W], T[H,W], sorted_ids[P], ranges[tiles, 2])."""
+    (image[3,H,W], T[H,W], ids, ranges[tiles, 2]); tile t's depth-ordered list
+    is ids[ranges[t, 0]:ranges[t, 1]]."""
     n = int(sp["u"].shape[0])
     dev = "cuda"
     t = {k: torch.as_tensor(v, device=dev).contiguous() for k, v in sp.items()}
@@ -215,7 +258,7 @@ def rasterize_splats(rast: Rasterizer, sp: dict, width: int, height: int, bg=(0.
         need = C.c_int64()
         rc = rast.ctx.L.h4dgs_check(rast.ctx.h, _ptr(rast._state), rast._state.numel(), C.byref(need), _stream())
         if rc == L.H4D_OK:
-            return image, T, ids[: int(need.value)], ranges
+            return image, T, ids, ranges
         if rc != L.H4D_ERR_CAPACITY:
             rast.ctx.check(rc)
         rast.capacity = int(need.value * rast.growth) + 1024
@@ -262,4 +305,4 @@ def adam_step(rast: Rasterizer, params, grads, ms, vs, lrs, step: int, betas=(0.
         rast.ctx.check(rast.ctx.L.h4dgs_adam(
             rast.ctx.h, k, L.ptr_array([p.data_ptr() for p in P]), L.ptr_array([g.data_ptr() for g in G]),
             L.ptr_array([m.data_ptr() for m in M]), L.ptr_array([v.data_ptr() for v in V]), sizes, lr,
-            C.c_float(betas[0]), C.c_float(betas[1]), C.c_float(eps), int(step), _stream()))
+            C.c_double(betas[0]), C.c_double(betas[1]), C.c_double(eps), int(step), _stream()))

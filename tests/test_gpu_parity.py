@@ -186,14 +186,11 @@ def test_tile_lists_and_ranges_bit_exact(h4d, tile):
     start, ref_ids = oracle.tile_lists(rec, W, H, tile)
     ids = ids.cpu().numpy()
     rg = ranges.cpu().numpy()
-    assert len(ids) == len(ref_ids)
-    assert np.array_equal(ids, ref_ids)
     tiles = len(start) - 1
+    assert rg.shape[0] == tiles
     for t in range(tiles):
-        if start[t + 1] > start[t]:
-            assert rg[t, 0] == start[t] and rg[t, 1] == start[t + 1], t
-        else:
-            assert rg[t, 0] == rg[t, 1]
+        got = ids[rg[t, 0]:rg[t, 1]]
+        assert np.array_equal(got, ref_ids[start[t]:start[t + 1]]), t
 
 
 def test_composite_on_shared_splats(h4d):
@@ -325,15 +322,25 @@ def test_adam_matches_oracle(h4d):
     tp = [torch.as_tensor(p, device="cuda") for p in P]
     tm = [torch.as_tensor(m, device="cuda") for m in M]
     tv = [torch.as_tensor(v, device="cuda") for v in V]
+    eps32 = 2.0 ** -24
     for step in range(1, 4):
         G = [rng.normal(size=n).astype(np.float32) for n in sizes]
         tg = [torch.as_tensor(g, device="cuda") for g in G]
+        prev = [(tp[i].cpu().numpy().astype(np.float64), tm[i].cpu().numpy().astype(np.float64),
+                 tv[i].cpu().numpy().astype(np.float64)) for i in range(len(sizes))]
         refs = [oracle.adam(tp[i].cpu().numpy(), G[i], tm[i].cpu().numpy(), tv[i].cpu().numpy(), lrs[i], 0.9, 0.999,
                             1e-8, step) for i in range(len(sizes))]
         h4d.adam_step(rast, tp, tg, tm, tv, lrs, step)
         torch.cuda.synchronize()
         for i in range(len(sizes)):
             po, mo, vo = refs[i]
-            assert np.allclose(tp[i].cpu().numpy(), po, rtol=1e-6, atol=1e-6)
-            assert np.allclose(tm[i].cpu().numpy(), mo, rtol=1e-6, atol=1e-9)
-            assert np.allclose(tv[i].cpu().numpy(), vo, rtol=1e-6, atol=1e-12)
+            p0, m0, v0 = prev[i]
+            g = G[i].astype(np.float64)
+            # float32 rounding bounds of each update (m may cancel, v cannot)
+            mtol = 4 * eps32 * (0.9 * np.abs(m0) + 0.1 * np.abs(g)) + 1e-30
+            assert (np.abs(tm[i].cpu().numpy() - mo) <= mtol).all()
+            assert np.allclose(tv[i].cpu().numpy(), vo, rtol=8 * eps32, atol=0)
+            c1, c2 = 1 - 0.9 ** step, 1 - 0.999 ** step
+            upd = lrs[i] * (np.abs(mo) / c1) / (np.sqrt(vo / c2) + 1e-8)
+            ptol = 4 * eps32 * np.abs(p0) + 8 * eps32 * upd + lrs[i] * mtol / c1 / (np.sqrt(vo / c2) + 1e-8)
+            assert (np.abs(tp[i].cpu().numpy() - po) <= ptol + 1e-12).all()
