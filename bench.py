@@ -65,17 +65,100 @@ def cpu_baseline(scene, views, adam_scalars: int) -> dict:
                       f"+ one Adam step over {n} scalars, {dt:.1f} s"}
 
 
+def convert_leg(h4d, torch, rast, g3, g4, reps: int = 5) -> dict:
+    """Median wall time of convert_static(0.5) (mask, compaction, Eq. 9 on the
+    converted rows, copies), which ends in a host read of the two counts."""
+    for _ in range(2):
+        h4d.convert_static(rast, g3, g4, 0.5)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        o3, o4, _ = h4d.convert_static(rast, g3, g4, 0.5)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return {"ms": round(1e3 * float(np.median(ts)), 4), "n4_in": int(g4["opacity"].numel()),
+            "n3_in": int(g3["opacity"].numel()), "n4_out": int(o4["opacity"].numel()),
+            "n3_out": int(o3["opacity"].numel())}
+
+
+def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
+    """fwd + L1 + bwd over 32 views per call (1M Gaussians, 80 % static; 8 arc
+    cameras, four at 1352x1014 and four at 2704x2028, times 0.125 ... 0.875):
+    views one after another (eager launches), against all views in one launch
+    per stage replayed from a HIP graph.  Adam is not part of this step."""
+    scene = sg.batched_scene()
+    views = sg.batched_views(scene)
+    g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+    del scene
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    targets = [torch.rand((3, v.height, v.width), generator=gen, device="cuda") for v in views]
+    gr3 = {k: torch.empty_like(v) for k, v in g3.items()}
+    gr4 = {k: torch.empty_like(v) for k, v in g4.items()}
+    mpix = sum(v.width * v.height for v in views) / 1e6
+    out = {"workload": "batched_1M_32views", "views": len(views), "mpix_per_step": round(mpix, 3),
+           "gaussians": int(g3["opacity"].numel() + g4["opacity"].numel())}
+
+    # views one after another, eager
+    rast = h4d.Rasterizer()
+    dls = [torch.empty_like(t) for t in targets]
+    loss = torch.zeros(1, device="cuda")
+
+    def eager_step():
+        h = rast.forward(g3, g4, views)
+        h4d.l1_loss_grad(rast, h.images, targets, views, dls, loss)
+        rast.backward(h, g3, g4, dls, out=(gr3, gr4))
+
+    rast.check_mode = "eager"
+    eager_step()
+    torch.cuda.synchronize()
+    out["pairs_per_step"] = rast.last_pairs
+    rast.check_mode = "deferred"
+    for _ in range(warmup):
+        eager_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        eager_step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    rast.verify()
+    out["single_view"] = {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
+    del rast, dls
+    torch.cuda.empty_cache()
+
+    # batched, captured once, replayed
+    step = h4d.CapturedStep(h4d.Rasterizer(batched=True), g3, g4, views, targets, (gr3, gr4))
+    for _ in range(warmup):
+        step.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    step.verify()
+    out["batched_graph"] = {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
+    out["speedup"] = round(out["single_view"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--chunk", type=int, default=256)
+    ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--gaussians", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=8)
     ap.add_argument("--stats-views", type=int, default=8)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched vs single-view leg")
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, run one plain device copy of MIB MiB (a known-size reference for counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -88,6 +171,8 @@ def main():
     import paper_2505_13215_amd as h4d
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    args.tile = args.tile or h4d.DEFAULT_TILE
+    args.chunk = args.chunk or h4d.DEFAULT_CHUNK
     torch.cuda.set_device(0)
     log("building the synthetic scene")
     scene = sg.multiview_scene(n_total=args.gaussians)
@@ -184,6 +269,33 @@ def main():
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": f"k_composite_{dom[6:]}",
                 "kernel_ms": round(dom_ms, 4), "flops_per_launch": dom_flops}
 
+    # static conversion (Sec. 4.1-4.2): on the workload's sets, and on 500k all-4D
+    # Gaussians of which half are static
+    log("timing convert_static")
+    conv = {"workload": convert_leg(h4d, torch, rast, g3, g4)}
+    rng4 = np.random.default_rng(5)
+    half = h4d.to_device(sg.draw_4d(rng4, 500_000, 2.0, static_fraction=0.5, tau=0.5))
+    conv["all4d_500k_half_static"] = convert_leg(h4d, torch, rast, h4d.to_device(sg.empty_3d()), half)
+    del half
+
+    batched = None
+    if not args.no_batched:
+        log("batched vs single-view: 1M Gaussians, 32 views per step")
+        del rast
+        torch.cuda.empty_cache()
+        batched = batched_leg(h4d, torch, sg, args.batched_steps, 1)
+        log(f"batched vs single-view: {batched}")
+
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} written")
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU baseline: FP64 oracle on {args.cpu_views} view(s)")
@@ -202,6 +314,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "blend_evals_per_view": {k: int(v) for k, v in cnt.items()},
         "pairs_per_view_max": peak_pairs,
+        "convert_static": conv,
+        "batched_vs_single": batched,
     }
     print(json.dumps(out), flush=True)
 

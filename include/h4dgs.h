@@ -90,8 +90,8 @@ typedef struct {
 } h4d_view;
 
 /* Launch configuration.  tile: tile edge in pixels (8, 16 or 32); chunk:
- * list entries staged in LDS per round of the blending kernels (128, 256 or
- * 512, and at least tile*tile); batched: 0 = views processed one after another,
+ * list entries staged in LDS per round of the blending kernels (64, 128, 256
+ * or 512); batched: 0 = views processed one after another,
  * 1 = all views of a call in one pass per stage; pair_capacity: number of
  * tile-list slots the workspace holds, summed over the call's views (a tile's
  * slots number the splats touching its 64-pixel super-tile, so this is a

@@ -98,18 +98,26 @@ struct Carve {
 };
 
 // Super-tiles are 64 x 64 pixels: S x S tiles.
-inline int super_factor(int tile) { return 64 / tile; }
+inline int super_factor(int tile) { return kSuperPixels / tile; }
 
 struct ViewGeom {
     int tiles_x, tiles_y, tile_base;
-    int sx, sy;  // super-tile grid
+    int sx, sy, super_base;
     int64_t pix_base;
 };
 
+// One pass of binning + blending covers the views [v0, v1): every view alone
+// (views processed one after another), or all views of the call (batched).
+struct Pass {
+    int v0, v1, tiles, supers;
+};
+
 struct Layout {
-    int N = 0, V = 0, total_tiles = 0;
+    int N = 0, V = 0, total_tiles = 0, total_supers = 0;
+    int per_pass = 1;  // views per pass
     int64_t total_pix = 0;
-    uint64_t cap = 0;
+    uint64_t cap = 0;    // tile-list slots
+    uint64_t ccap = 0;   // coarse (Gaussian, super-tile) entries: cap / S^2 suffices
     ViewGeom vg[kMaxViews];
     // state
     size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_T, st_nc, st_C, state_bytes;
@@ -120,16 +128,30 @@ struct Layout {
     // scratch, backward use
     size_t sc_g2, bwd_bytes;
     size_t scratch_bytes;
+
+    int n_passes() const { return V / per_pass; }
+    Pass pass(int k) const {
+        Pass p;
+        p.v0 = k * per_pass;
+        p.v1 = p.v0 + per_pass;
+        const int tb_end = p.v1 < V ? vg[p.v1].tile_base : total_tiles;
+        const int sb_end = p.v1 < V ? vg[p.v1].super_base : total_supers;
+        p.tiles = tb_end - vg[p.v0].tile_base;
+        p.supers = sb_end - vg[p.v0].super_base;
+        return p;
+    }
 };
 
 Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     Layout L;
     L.N = N;
     L.V = V;
+    L.per_pass = cfg->batched ? V : 1;
     L.cap = (uint64_t)std::max<int64_t>(0, cfg->pair_capacity);
-    int tb = 0, max_tiles = 0, max_super = 0;
+    int tb = 0, sb = 0;
     int64_t pb = 0;
     const int S = super_factor(cfg->tile);
+    L.ccap = (L.cap + (uint64_t)(S * S) - 1) / (uint64_t)(S * S);
     for (int v = 0; v < V; ++v) {
         ViewGeom& g = L.vg[v];
         g.tiles_x = ceil_div(views[v].width, cfg->tile);
@@ -137,15 +159,23 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
         g.sx = ceil_div(g.tiles_x, S);
         g.sy = ceil_div(g.tiles_y, S);
         g.tile_base = tb;
+        g.super_base = sb;
         g.pix_base = pb;
         tb += g.tiles_x * g.tiles_y;
+        sb += g.sx * g.sy;
         pb += (int64_t)views[v].width * views[v].height;
-        max_tiles = std::max(max_tiles, g.tiles_x * g.tiles_y);
-        max_super = std::max(max_super, g.sx * g.sy);
     }
     L.total_tiles = tb;
+    L.total_supers = sb;
     L.total_pix = pb;
+    int max_tiles = 0, max_super = 0;
+    for (int k = 0; k < L.n_passes(); ++k) {
+        const Pass p = L.pass(k);
+        max_tiles = std::max(max_tiles, p.tiles);
+        max_super = std::max(max_super, p.supers);
+    }
     const size_t n = (size_t)N, V_ = (size_t)V;
+    const size_t np = n * (size_t)L.per_pass;  // Gaussians x views of one pass
     Carve s;
     L.st_status = s.take(sizeof(Status));
     L.st_pair_base = s.take(8 * (V_ + 1));
@@ -158,22 +188,22 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.st_C = s.take(12 * (size_t)pb);
     L.state_bytes = s.off;
     Carve f;
-    L.sc_dkeys = f.take(4 * n);
-    L.sc_dvals = f.take(4 * n);
-    L.sc_dkeys2 = f.take(4 * n);
-    L.sc_dvals2 = f.take(4 * n);
-    L.sc_cnt = f.take(4 * n);
-    L.sc_rect = f.take(8 * n);
-    L.sc_offsets = f.take(8 * (n + 1));
-    L.sc_partials = f.take(8 * ((size_t)scan_blocks(N) + 2));
+    L.sc_dkeys = f.take(4 * np);
+    L.sc_dvals = f.take(4 * np);
+    L.sc_dkeys2 = f.take(4 * np);
+    L.sc_dvals2 = f.take(4 * np);
+    L.sc_cnt = f.take(4 * np);
+    L.sc_rect = f.take(8 * np);
+    L.sc_offsets = f.take(8 * (np + 1));
+    L.sc_partials = f.take(8 * ((size_t)scan_blocks((int)std::min<size_t>(np, 0x7FFFFFFF)) + 2));
     L.sc_eff = f.take(8);
     L.sc_eff2 = f.take(8);
-    L.sc_pkeys = f.take(4 * (size_t)L.cap);
-    L.sc_pvals = f.take(4 * (size_t)L.cap);
-    L.sc_pkeys2 = f.take(4 * (size_t)L.cap);
-    L.sc_pvals2 = f.take(4 * (size_t)L.cap);
-    L.sc_hist = f.take(4 * radix_hist_words(std::max<uint64_t>(L.cap, n)));
-    L.sc_totals = f.take(4 * 256);
+    L.sc_pkeys = f.take(4 * (size_t)L.ccap);
+    L.sc_pvals = f.take(4 * (size_t)L.ccap);
+    L.sc_pkeys2 = f.take(4 * (size_t)L.ccap);
+    L.sc_pvals2 = f.take(4 * (size_t)L.ccap);
+    L.sc_hist = f.take(4 * std::max(radix_hist_words(L.ccap, 1), radix_hist_words(n, L.per_pass)));
+    L.sc_totals = f.take(4 * 256 * (size_t)L.per_pass);
     L.sc_cranges = f.take(16 * (size_t)max_super);
     L.sc_tsizes = f.take(4 * (size_t)max_tiles);
     L.sc_toff = f.take(8 * ((size_t)max_tiles + 1));
@@ -194,12 +224,21 @@ T* at(void* base, size_t off) {
 h4d_status check_config(h4d_ctx* c, const h4d_config* cfg) {
     if (!cfg) return fail(c, H4D_ERR_INVALID_ARG, "config is null");
     if (!composite_supported(cfg->tile, cfg->chunk))
-        return fail(c, H4D_ERR_INVALID_ARG, "tile must be 8, 16 or 32 and chunk 128, 256 or 512 (got %d, %d)",
+        return fail(c, H4D_ERR_INVALID_ARG, "tile must be 8, 16 or 32 and chunk 64, 128, 256 or 512 (got %d, %d)",
                     cfg->tile, cfg->chunk);
     if (cfg->pair_capacity < 0) return fail(c, H4D_ERR_INVALID_ARG, "pair_capacity < 0");
     if (cfg->pair_capacity > (int64_t)0xFFFFFFFFll * 4)
         return fail(c, H4D_ERR_INVALID_ARG, "pair_capacity too large");
     if (cfg->batched != 0 && cfg->batched != 1) return fail(c, H4D_ERR_INVALID_ARG, "batched must be 0 or 1");
+    return H4D_OK;
+}
+
+// A pass indexes its (view, Gaussian) pairs with 32-bit integers.
+h4d_status check_pass_size(h4d_ctx* c, const h4d_config* cfg, int64_t N, int n_views) {
+    const int64_t per = cfg->batched ? n_views : 1;
+    if (N * per > (int64_t)0x7FFFFFFF)
+        return fail(c, H4D_ERR_INVALID_ARG, "batched pass too large: %lld Gaussians x %lld views >= 2^31",
+                    (long long)N, (long long)per);
     return H4D_OK;
 }
 
@@ -265,9 +304,13 @@ unsigned long long* stat_counters(h4d_ctx* c, void* state, const Layout& L) {
     return c->stats ? reinterpret_cast<unsigned long long*>(&at<Status>(state, L.st_status)->pad[0]) : nullptr;
 }
 
-void bin_and_blend(h4d_ctx* c, const Layout& L, int v, int tile, int chunk, void* state, void* scratch,
-                   const Rec* recs_v, float* image, hipStream_t st) {
+void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chunk, void* state, void* scratch,
+                   const PtrTable& images, hipStream_t st) {
     const int N = L.N;
+    const int nv = P.v1 - P.v0;
+    const int n = nv * N;  // depth-ordered Gaussians of the pass, view-major
+    const Rec* recs = at<Rec>(state, L.st_recs);
+    const ViewParams* vp = at<ViewParams>(state, L.st_views);
     uint32_t* dk = at<uint32_t>(scratch, L.sc_dkeys);
     uint32_t* dv = at<uint32_t>(scratch, L.sc_dvals);
     uint32_t* dk2 = at<uint32_t>(scratch, L.sc_dkeys2);
@@ -275,19 +318,18 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, int v, int tile, int chunk, void
     uint32_t* hist = at<uint32_t>(scratch, L.sc_hist);
     uint32_t* totals = at<uint32_t>(scratch, L.sc_totals);
     {
-        // depth order over the Gaussians: 4 stable 8-bit passes over the float32 depth bits
+        // depth order per view: 4 stable 8-bit passes over the float32 depth bits,
+        // each view of the pass a segment of its own
         StageScope sc(c, st, H4D_STAGE_DEPTH_SORT);
         for (int pass = 0; pass < 4; ++pass) {
             const bool even = (pass % 2) == 0;
             launch_radix_pass(even ? dk : dk2, even ? dv : dv2, even ? dk2 : dk, even ? dv2 : dv, nullptr,
-                              (uint64_t)N, (uint64_t)N, 8 * pass, 8, hist, totals, nullptr, st);
+                              (uint64_t)N, (uint64_t)N, 8 * pass, 8, hist, totals, nullptr, st, nv, (uint64_t)N);
         }
     }
     Status* status = at<Status>(state, L.st_status);
     unsigned long long* pair_base = at<unsigned long long>(state, L.st_pair_base);
     uint32_t* ids = at<uint32_t>(state, L.st_ids);
-    const ViewGeom& g = L.vg[v];
-    const int tiles = g.tiles_x * g.tiles_y;
     const int S = super_factor(tile);
     {
         StageScope sc(c, st, H4D_STAGE_BINNING);
@@ -297,16 +339,16 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, int v, int tile, int chunk, void
         uint64_t* rect = at<uint64_t>(scratch, L.sc_rect);
         unsigned long long* offsets = at<unsigned long long>(scratch, L.sc_offsets);
         // coarse entries: one per (depth-ordered Gaussian, 64-px super-tile)
-        launch_coarse_count(dv, N, recs_v, tile, S, cnt, rect, st);
-        launch_scan_u32_u64(cnt, nullptr, N, offsets, at<unsigned long long>(scratch, L.sc_partials), st);
-        launch_finalize_coarse(offsets, N, L.cap, S, status, eff_c, st);
+        launch_coarse_count(dv, n, N, recs, P.v0, tile, S, cnt, rect, st);
+        launch_scan_u32_u64(cnt, nullptr, n, offsets, at<unsigned long long>(scratch, L.sc_partials), st);
+        launch_finalize_coarse(offsets, n, L.ccap, S, status, eff_c, st);
         uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
         uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
         uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
         uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
-        launch_coarse_emit(offsets, N, rect, S, g.sx, eff_c, pk, pv, st);
+        launch_coarse_emit(offsets, n, N, rect, vp, P.v0, S, eff_c, pk, pv, st);
         // stable sort of the coarse entries by super-tile (depth order kept inside each)
-        const int bits = bits_for(g.sx * g.sy);
+        const int bits = bits_for(P.supers);
         const int passes = (bits + 7) / 8;
         uint32_t* kin = pk;
         uint32_t* vin = pv;
@@ -315,31 +357,29 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, int v, int tile, int chunk, void
             const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
             uint32_t* kout = (kin == pk) ? pk2 : pk;
             uint32_t* vout = (vin == pv) ? pv2 : pv;
-            launch_radix_pass(kin, vin, kout, vout, eff_c, 0, L.cap, shift, nb, hist, totals, nullptr, st);
+            launch_radix_pass(kin, vin, kout, vout, eff_c, 0, L.ccap, shift, nb, hist, totals, nullptr, st);
             kin = kout;
             vin = vout;
             shift += nb;
         }
         int64_t* cranges = at<int64_t>(scratch, L.sc_cranges);
-        launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)(g.sx * g.sy), 0ull, st);
+        launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
         launch_ranges(kin, eff_c, nullptr, cranges, st);
         // per-tile regions sized by the super-tile list, then ordered compaction
         uint32_t* tsizes = at<uint32_t>(scratch, L.sc_tsizes);
         unsigned long long* toff = at<unsigned long long>(scratch, L.sc_toff);
-        launch_tile_sizes(cranges, tiles, g.tiles_x, S, g.sx, eff_c, tsizes, st);
-        launch_scan_u32_u64(tsizes, nullptr, tiles, toff, at<unsigned long long>(scratch, L.sc_tpart), st);
-        launch_finalize_regions(toff, tiles, pair_base, v, L.cap, status, eff_c, eff_r, st);
+        launch_tile_sizes(cranges, P.tiles, vp, P.v0, P.v1, S, eff_c, tsizes, st);
+        launch_scan_u32_u64(tsizes, nullptr, P.tiles, toff, at<unsigned long long>(scratch, L.sc_tpart), st);
+        launch_finalize_regions(toff, P.tiles, pair_base, P.v0, P.v1, L.cap, status, eff_c, eff_r, st);
         // the buffer pair the sort did not end in receives (id, local rectangle) per coarse entry
         uint32_t* cgid = (kin == pk) ? pk2 : pk;
         uint32_t* crect = (kin == pk) ? pv2 : pv;
-        launch_coarse_gather(kin, vin, rect, dv, S, g.sx, eff_c, cgid, crect, st);
-        int64_t* ranges = at<int64_t>(state, L.st_ranges) + 2 * (size_t)g.tile_base;
-        launch_tile_write(cgid, crect, cranges, toff, pair_base + v, eff_r, tiles, g.tiles_x, S, g.sx, ids, ranges,
-                          st);
+        launch_coarse_gather(kin, vin, rect, dv, N, vp, P.v0, S, eff_c, cgid, crect, st);
+        launch_tile_write(cgid, crect, cranges, toff, pair_base + P.v0, eff_r, P.tiles, vp, P.v0, P.v1, S, ids,
+                          at<int64_t>(state, L.st_ranges), st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
-    const ViewParams* vp = at<ViewParams>(state, L.st_views);
-    launch_composite_fwd(tile, chunk, recs_v, ids, at<int64_t>(state, L.st_ranges), vp, v, tiles, image,
+    launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles, images,
                          at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc), at<float>(state, L.st_C),
                          stat_counters(c, state, L), st);
 }
@@ -373,6 +413,7 @@ h4d_status h4dgs_workspace_size(h4d_ctx* ctx, int32_t n3, int32_t n4, const h4d_
     if ((s = check_config(ctx, cfg)) != H4D_OK) return s;
     if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
     if (n3 < 0 || n4 < 0 || (int64_t)n3 + n4 > 0x7FFFFFFF) return fail(ctx, H4D_ERR_INVALID_ARG, "bad Gaussian counts");
+    if ((s = check_pass_size(ctx, cfg, (int64_t)n3 + n4, n_views)) != H4D_OK) return s;
     if (!state_bytes || !scratch_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "null size output");
     const Layout L = make_layout(n3 + n4, views, n_views, cfg);
     *state_bytes = L.state_bytes;
@@ -388,7 +429,7 @@ h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     if ((s = check_sets(ctx, g3, g4)) != H4D_OK) return s;
     if ((s = check_config(ctx, cfg)) != H4D_OK) return s;
     if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
-    if (cfg->batched) return fail(ctx, H4D_ERR_UNSUPPORTED, "batched mode is not available in this build");
+    if ((s = check_pass_size(ctx, cfg, (int64_t)g3->n + g4->n, n_views)) != H4D_OK) return s;
     if (!images) return fail(ctx, H4D_ERR_INVALID_ARG, "images is null");
     for (int v = 0; v < n_views; ++v)
         if (!images[v]) return fail(ctx, H4D_ERR_INVALID_ARG, "image %d is null", v);
@@ -405,14 +446,17 @@ h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     launch_write_views(view_table(views, n_views, cfg->tile), vp, st);
     launch_zero_status(at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base), n_views, st);
     launch_fill_u64(at<unsigned long long>(state, L.st_ranges), 2 * (size_t)L.total_tiles, 0ull, st);
-    for (int v = 0; v < n_views; ++v) {
-        Rec* recs_v = at<Rec>(state, L.st_recs) + (size_t)v * N;
+    PtrTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int v = 0; v < n_views; ++v) tab.p[v] = images[v];
+    for (int k = 0; k < L.n_passes(); ++k) {
+        const Pass P = L.pass(k);
         {
             StageScope sc(ctx, st, H4D_STAGE_PREPROCESS);
-            launch_preprocess(p3, p4, vp, v, recs_v, at<uint32_t>(scratch, L.sc_dkeys),
-                              at<uint32_t>(scratch, L.sc_dvals), st);
+            launch_preprocess(p3, p4, vp, P.v0, P.v1 - P.v0, at<Rec>(state, L.st_recs),
+                              at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
         }
-        bin_and_blend(ctx, L, v, cfg->tile, cfg->chunk, state, scratch, recs_v, images[v], st);
+        bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, state, scratch, tab, st);
     }
     return hip_check(ctx, "render_fwd");
 }
@@ -426,7 +470,7 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     if ((s = check_sets(ctx, g3, g4)) != H4D_OK) return s;
     if ((s = check_config(ctx, cfg)) != H4D_OK) return s;
     if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
-    if (cfg->batched) return fail(ctx, H4D_ERR_UNSUPPORTED, "batched mode is not available in this build");
+    if ((s = check_pass_size(ctx, cfg, (int64_t)g3->n + g4->n, n_views)) != H4D_OK) return s;
     if (!dl_dimages) return fail(ctx, H4D_ERR_INVALID_ARG, "dl_dimages is null");
     for (int v = 0; v < n_views; ++v)
         if (!dl_dimages[v]) return fail(ctx, H4D_ERR_INVALID_ARG, "dl_dimage %d is null", v);
@@ -450,12 +494,15 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     const ViewParams* vp = at<ViewParams>(stt, L.st_views);
     {
         StageScope sc(ctx, st, H4D_STAGE_BLEND_BWD);
-        for (int v = 0; v < n_views; ++v) {
-            const int tiles = L.vg[v].tiles_x * L.vg[v].tiles_y;
-            launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs) + (size_t)v * N,
-                                 at<uint32_t>(stt, L.st_ids), at<int64_t>(stt, L.st_ranges), vp, v, tiles,
-                                 dl_dimages[v], at<float>(stt, L.st_T), at<uint32_t>(stt, L.st_nc),
-                                 at<float>(stt, L.st_C), g2 + (size_t)v * 9 * N, N, stat_counters(ctx, stt, L), st);
+        CPtrTable tab;
+        std::memset(&tab, 0, sizeof(tab));
+        for (int v = 0; v < n_views; ++v) tab.p[v] = dl_dimages[v];
+        for (int k = 0; k < L.n_passes(); ++k) {
+            const Pass P = L.pass(k);
+            launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs), N, at<uint32_t>(stt, L.st_ids),
+                                 at<int64_t>(stt, L.st_ranges), vp, P.v0, P.v1, P.tiles, tab, at<float>(stt, L.st_T),
+                                 at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), g2, stat_counters(ctx, stt, L),
+                                 st);
         }
     }
     const G3Grad r3{grad3->n, grad3->mean, grad3->log_scale, grad3->quat, grad3->opacity, grad3->sh};
@@ -491,7 +538,6 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     if (!ctx) return H4D_ERR_INVALID_ARG;
     h4d_status s;
     if ((s = check_config(ctx, cfg)) != H4D_OK) return s;
-    if (cfg->batched) return fail(ctx, H4D_ERR_UNSUPPORTED, "batched mode is not available in this build");
     if (n < 0) return fail(ctx, H4D_ERR_INVALID_ARG, "n < 0");
     if (n > 0 && (!u || !v || !conic || !opacity || !rgb || !radius || !depth || !visible))
         return fail(ctx, H4D_ERR_INVALID_ARG, "null splat array");
@@ -514,7 +560,10 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     Rec* recs = at<Rec>(state, L.st_recs);
     launch_splats_to_records(n, u, v, conic, opacity, rgb, radius, depth, visible, width, height, recs,
                              at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
-    bin_and_blend(ctx, L, 0, cfg->tile, cfg->chunk, state, scratch, recs, image, st);
+    PtrTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    tab.p[0] = image;
+    bin_and_blend(ctx, L, L.pass(0), cfg->tile, cfg->chunk, state, scratch, tab, st);
     const size_t hw = (size_t)width * height;
     if (T_final) (void)hipMemcpyAsync(T_final, at<float>(state, L.st_T), 4 * hw, hipMemcpyDeviceToDevice, st);
     if (sorted_ids && L.cap > 0)

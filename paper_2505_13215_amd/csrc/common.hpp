@@ -34,6 +34,27 @@ struct ViewParams {
     int32_t tiles_x, tiles_y;
     int32_t tile_base;   // first global tile id of this view
     int64_t pix_base;    // first pixel of this view in the concatenated pixel arrays
+    int32_t sx, sy;      // 64-pixel super-tile grid
+    int32_t super_base;  // first global super-tile id of this view
+    int32_t pad;
+};
+
+// Pixels per super-tile edge (binning groups tiles into 64 x 64 pixel blocks).
+constexpr int kSuperPixels = 64;
+
+// The view of global tile `gt` among views [v0, v1) (tile ids ascend with the view).
+__device__ __forceinline__ int find_view_of_tile(const ViewParams* views, int v0, int v1, int gt) {
+    int v = v0;
+    while (v + 1 < v1 && views[v + 1].tile_base <= gt) ++v;
+    return v;
+}
+
+// Per-view device pointers passed by value to the batched kernels.
+struct PtrTable {
+    float* p[kMaxViews];
+};
+struct CPtrTable {
+    const float* p[kMaxViews];
 };
 
 // Screen-space record of one (Gaussian, view): 64 bytes, one half cache line.
@@ -90,23 +111,30 @@ struct Splat {
     int32_t x0, x1, y0, y1;
 };
 
-#pragma clang fp contract(off)
-// power2 = log2(e) * power; returns false when the splat is skipped at this pixel
-// (outside its square, power > 0 or alpha < 1/255).  alpha is min(0.99, op * G).
+// The blending step of one (pixel, splat) pair, branch-free, shared bit-for-bit by
+// the forward and backward kernels (the backward recomputes transmittance
+// instead of storing it, so both must take every decision identically).
+// power2 = log2(e) * power.  Returns whether the pair passes the square test,
+// power <= 0 and alpha >= 1/255; alpha = min(0.99, op * exp(power)).
 __device__ __forceinline__ bool eval_splat(const Splat& s, int px, int py, float pxc, float pyc, float& dx, float& dy,
                                            float& G, float& alpha, bool& clamped) {
-    if (px < s.x0 || px > s.x1 || py < s.y0 || py > s.y1) return false;
+#pragma clang fp contract(off)
+    const bool in = px >= s.x0 && px <= s.x1 && py >= s.y0 && py <= s.y1;
     dx = (pxc - s.ui) - s.uf;
     dy = (pyc - s.vi) - s.vf;
     const float t = __builtin_fmaf(s.qb, dy, s.qa * dx);
     const float p2 = __builtin_fmaf(s.qc * dy, dy, dx * t);
-    if (p2 > 0.0f) return false;
     G = __builtin_amdgcn_exp2f(p2);
     const float ap = s.op * G;
     clamped = ap > kMaxAlpha;
     alpha = clamped ? kMaxAlpha : ap;
-    return alpha >= kMinAlpha;
+    return in && !(p2 > 0.0f) && alpha >= kMinAlpha;
 }
-#pragma clang fp contract(on)
+
+__device__ __forceinline__ float next_T(float T, float alpha) {
+#pragma clang fp contract(off)
+    const float oma = 1.0f - alpha;
+    return T * oma;
+}
 
 }  // namespace h4d

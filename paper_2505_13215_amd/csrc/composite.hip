@@ -1,119 +1,155 @@
 // Front-to-back blending on gfx950 (Eq. 3; Alg. 1 BlendInOrder) and its adjoint.
 //
-// One workgroup per B x B tile, one lane per pixel (B = 8: one wave64; 16: four;
-// 32: sixteen).  The tile's depth-ordered list is walked in chunks: each chunk of
-// records is gathered once from HBM into LDS and broadcast to every lane.
+// One workgroup per B x B tile (B = 8 and 16: one wave64; 32: four waves), one or
+// four pixels per lane.  The tile's depth-ordered list is walked in chunks: each
+// chunk of records is gathered once from HBM into LDS and broadcast to every lane.
 // A pixel's contributors are exactly the splats whose pixel square contains it,
 // so the image does not depend on B or on the chunk size.
 //
 // The backward recomputes transmittance front to back with the very same
 // blending step as the forward (eval_splat), takes the colour behind a splat as
-// C_out minus the running prefix, reduces the nine per-splat gradients across the
-// wave with DPP, skips that when no lane of the wave blended the splat, adds the
-// wave sums into LDS from one lane and flushes one global atomic per (splat,
-// component, tile).  Each wave stops at its own last contributor.
+// C_out minus the running prefix, sums each lane's pixels in registers, reduces
+// the nine per-splat gradients across the wave with DPP (skipped when no lane
+// blended the splat), parks the wave sums in the register file and flushes them
+// with one global atomic per (splat, component, wave).  Each wave stops at its
+// own last contributor.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace h4d {
 
-struct __align__(16) LSplat {
-    int4 rect;     // x0, x1, y0, y1
-    float4 pos;    // ui, uf, vi, vf
-    float4 conic;  // qa, qb, qc, op
-    float4 col;    // r, g, b, (unused)
+// LDS copy of one record (52 bytes): packed pixel square, centre split into
+// integer and fractional parts, scaled conic, opacity, colour.
+struct LSplat {
+    uint32_t rx, ry;              // x0 | x1 << 16, y0 | y1 << 16
+    float ui, uf, vi, vf;
+    float qa, qb, qc, op;
+    float cr, cg, cb;
 };
 
 __device__ __forceinline__ void stage_splat(const Rec& r, LSplat& s) {
-    s.rect = make_int4((int)(r.d.x & 0xFFFFu), (int)(r.d.x >> 16), (int)(r.d.y & 0xFFFFu), (int)(r.d.y >> 16));
-    s.pos = make_float4(r.c.y, r.a.x, r.c.z, r.a.y);
-    s.conic = make_float4(r.a.z, r.a.w, r.b.x, r.b.y);
-    s.col = make_float4(r.b.z, r.b.w, r.c.x, 0.f);
+    s.rx = r.d.x; s.ry = r.d.y;
+    s.ui = r.c.y; s.uf = r.a.x; s.vi = r.c.z; s.vf = r.a.y;
+    s.qa = r.a.z; s.qb = r.a.w; s.qc = r.b.x; s.op = r.b.y;
+    s.cr = r.b.z; s.cg = r.b.w; s.cb = r.c.x;
 }
 
 __device__ __forceinline__ Splat to_splat(const LSplat& l) {
     Splat s;
-    s.x0 = l.rect.x; s.x1 = l.rect.y; s.y0 = l.rect.z; s.y1 = l.rect.w;
-    s.ui = l.pos.x; s.uf = l.pos.y; s.vi = l.pos.z; s.vf = l.pos.w;
-    s.qa = l.conic.x; s.qb = l.conic.y; s.qc = l.conic.z; s.op = l.conic.w;
-    s.cr = l.col.x; s.cg = l.col.y; s.cb = l.col.z;
+    s.x0 = (int)(l.rx & 0xFFFFu); s.x1 = (int)(l.rx >> 16); s.y0 = (int)(l.ry & 0xFFFFu); s.y1 = (int)(l.ry >> 16);
+    s.ui = l.ui; s.uf = l.uf; s.vi = l.vi; s.vf = l.vf;
+    s.qa = l.qa; s.qb = l.qb; s.qc = l.qc; s.op = l.op;
+    s.cr = l.cr; s.cg = l.cg; s.cb = l.cb;
     return s;
-}
-
-__device__ __forceinline__ float next_T(float T, float alpha) {
-#pragma clang fp contract(off)
-    const float oma = 1.0f - alpha;
-    return T * oma;
 }
 
 __device__ __forceinline__ bool in_square(const Splat& s, int px, int py) {
     return px >= s.x0 && px <= s.x1 && py >= s.y0 && py <= s.y1;
 }
 
+// Lane layout: a 16 x 16 tile is one wave, every lane holding four pixels
+// (rows r, r + 4, r + 8, r + 12 of its column); 8 x 8 is one wave with one pixel
+// per lane; 32 x 32 is four waves with four pixels per lane.  The per-splat LDS
+// reads, loop control and (backward) cross-lane reductions are shared by all of
+// a lane's pixels.
+template <int B>
+struct Shape {
+    static constexpr int NT = (B == 32) ? 256 : 64;  // threads per tile
+    static constexpr int PPL = B * B / NT;           // pixels per lane
+};
+
 // STATS = true is a measurement-only instantiation that also counts (pixel,
 // splat) evaluations and blends into counters[0..1].
 template <int B, int CHUNK, bool STATS>
-__global__ void __launch_bounds__(B * B) k_composite_fwd(const Rec* __restrict__ recs, const uint32_t* __restrict__ ids,
-                                                         const int64_t* __restrict__ ranges,
-                                                         const ViewParams* __restrict__ views, int view,
-                                                         float* __restrict__ image, float* __restrict__ Tfin,
-                                                         uint32_t* __restrict__ ncontrib, float* __restrict__ Cout,
-                                                         unsigned long long* counters) {
-    constexpr int NT = B * B;
+__global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
+    const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
+    const ViewParams* __restrict__ views, int v0, int v1, PtrTable images, float* __restrict__ Tfin,
+    uint32_t* __restrict__ ncontrib, float* __restrict__ Cout, unsigned long long* counters) {
+    constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
+    const int gt = views[v0].tile_base + (int)blockIdx.x;
+    const int view = find_view_of_tile(views, v0, v1, gt);
     const ViewParams& V = views[view];
-    const int tile = blockIdx.x;
+    const int tile = gt - V.tile_base;
+    recs += (size_t)view * N;
+    float* __restrict__ image = images.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
-    const int px = tx * B + (int)(threadIdx.x % B), py = ty * B + (int)(threadIdx.x / B);
-    const bool inside = px < V.W && py < V.H;
-    const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+    int px[PPL], py[PPL];
+    float pxc[PPL], pyc[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
+    uint32_t last[PPL];
+    bool done[PPL];
+    bool lane_done = true;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int p = (int)threadIdx.x + k * NT;
+        px[k] = tx * B + p % B;
+        py[k] = ty * B + p / B;
+        pxc[k] = (float)px[k] + 0.5f;
+        pyc[k] = (float)py[k] + 0.5f;
+        T[k] = 1.0f;
+        cr[k] = cg[k] = cb[k] = 0.f;
+        last[k] = 0u;
+        done[k] = !(px[k] < V.W && py[k] < V.H);
+        lane_done = lane_done && done[k];
+    }
     const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
     const int64_t end = ranges[2 * (size_t)(V.tile_base + tile) + 1];
-    float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
-    uint32_t last = 0;
     unsigned long long n_eval = 0, n_blend = 0;
-    bool done = !inside;
     for (int64_t base = start; base < end; base += CHUNK) {
-        if (__syncthreads_count(done) == NT) break;
+        if (__syncthreads_count(lane_done) == NT) break;
         const int cnt = (int)min((int64_t)CHUNK, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) stage_splat(recs[ids[base + k]], s_sp[k]);
         __syncthreads();
-        if (!done) {
+        if (!lane_done) {
+            const uint32_t rel0 = (uint32_t)(base - start);
             for (int j = 0; j < cnt; ++j) {
                 const Splat s = to_splat(s_sp[j]);
-                float dx, dy, G, alpha;
-                bool clamped;
-                if (STATS && in_square(s, px, py)) ++n_eval;
-                if (!eval_splat(s, px, py, pxc, pyc, dx, dy, G, alpha, clamped)) continue;
-                const float Tn = next_T(T, alpha);
-                if (Tn < kMinT) {
-                    done = true;
+                bool all = true;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    float dx, dy, G, alpha;
+                    bool clamped;
+                    const bool ok = eval_splat(s, px[k], py[k], pxc[k], pyc[k], dx, dy, G, alpha, clamped) && !done[k];
+                    const float Tn = next_T(T[k], alpha);
+                    const bool stop = ok && Tn < kMinT;
+                    const bool bl = ok && !stop;
+                    const float w = bl ? alpha * T[k] : 0.0f;
+                    cr[k] = __builtin_fmaf(s.cr, w, cr[k]);
+                    cg[k] = __builtin_fmaf(s.cg, w, cg[k]);
+                    cb[k] = __builtin_fmaf(s.cb, w, cb[k]);
+                    T[k] = bl ? Tn : T[k];
+                    last[k] = bl ? rel0 + (uint32_t)j + 1u : last[k];
+                    if (STATS) {
+                        n_eval += (!done[k] && in_square(s, px[k], py[k])) ? 1u : 0u;
+                        n_blend += bl ? 1u : 0u;
+                    }
+                    done[k] = done[k] || stop;
+                    all = all && done[k];
+                }
+                if (all) {
+                    lane_done = true;
                     break;
                 }
-                if (STATS) ++n_blend;
-                const float w = alpha * T;
-                cr = __builtin_fmaf(s.cr, w, cr);
-                cg = __builtin_fmaf(s.cg, w, cg);
-                cb = __builtin_fmaf(s.cb, w, cb);
-                T = Tn;
-                last = (uint32_t)(base - start) + (uint32_t)j + 1u;
             }
         }
     }
-    if (inside) {
-        const size_t HW = (size_t)V.W * V.H;
-        const size_t p = (size_t)py * V.W + px;
-        const float o0 = __builtin_fmaf(T, V.bg[0], cr), o1 = __builtin_fmaf(T, V.bg[1], cg),
-                    o2 = __builtin_fmaf(T, V.bg[2], cb);
-        image[p] = o0;
-        image[HW + p] = o1;
-        image[2 * HW + p] = o2;
-        const size_t q = (size_t)V.pix_base + p;
-        Tfin[q] = T;
-        ncontrib[q] = last;
-        Cout[3 * (size_t)V.pix_base + p] = o0;
-        Cout[3 * (size_t)V.pix_base + HW + p] = o1;
-        Cout[3 * (size_t)V.pix_base + 2 * HW + p] = o2;
+    const size_t HW = (size_t)V.W * V.H;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        if (px[k] < V.W && py[k] < V.H) {
+            const size_t p = (size_t)py[k] * V.W + px[k];
+            const float o0 = __builtin_fmaf(T[k], V.bg[0], cr[k]), o1 = __builtin_fmaf(T[k], V.bg[1], cg[k]),
+                        o2 = __builtin_fmaf(T[k], V.bg[2], cb[k]);
+            image[p] = o0;
+            image[HW + p] = o1;
+            image[2 * HW + p] = o2;
+            const size_t q = (size_t)V.pix_base + p;
+            Tfin[q] = T[k];
+            ncontrib[q] = last[k];
+            Cout[3 * (size_t)V.pix_base + p] = o0;
+            Cout[3 * (size_t)V.pix_base + HW + p] = o1;
+            Cout[3 * (size_t)V.pix_base + 2 * HW + p] = o2;
+        }
     }
     if (STATS) {
         atomicAdd(&counters[0], n_eval);
@@ -140,126 +176,147 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+// Per-splat gradient sums of the current group of 64 splats live in the
+// register file: the wave sum of splat j is written into lane j % 64 of nine
+// accumulator registers; every 64 splats (and at the end of a chunk) all lanes
+// flush their sums with parallel global atomics.
 template <int B, int CHUNK, bool STATS>
-__global__ void __launch_bounds__(B * B) k_composite_bwd(const Rec* __restrict__ recs, const uint32_t* __restrict__ ids,
-                                                         const int64_t* __restrict__ ranges,
-                                                         const ViewParams* __restrict__ views, int view,
-                                                         const float* __restrict__ dl, const float* __restrict__ Tfin,
-                                                         const uint32_t* __restrict__ ncontrib,
-                                                         const float* __restrict__ Cout, float* __restrict__ g2,
-                                                         int N, unsigned long long* counters) {
-    constexpr int NT = B * B;
+__global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
+    const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
+    const ViewParams* __restrict__ views, int v0, int v1, CPtrTable dls, const float* __restrict__ Tfin,
+    const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout, float* __restrict__ g2,
+    unsigned long long* counters) {
+    constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
     __shared__ uint32_t s_gid[CHUNK];
-    // wave sums of the chunk's splats (one LDS atomic per wave and component);
-    // a single slot keeps the block's LDS small and its occupancy high
-    constexpr int NW = NT / 64;
-    constexpr int SLOTS = 1;
-    __shared__ float s_acc[SLOTS][9][CHUNK];
     __shared__ uint32_t s_max;
+    const int gt = views[v0].tile_base + (int)blockIdx.x;
+    const int view = find_view_of_tile(views, v0, v1, gt);
     const ViewParams& V = views[view];
-    const int tile = blockIdx.x;
+    const int tile = gt - V.tile_base;
+    recs += (size_t)view * N;
+    g2 += (size_t)view * 9 * N;
+    const float* __restrict__ dl = dls.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
-    const int px = tx * B + (int)(threadIdx.x % B), py = ty * B + (int)(threadIdx.x / B);
-    const bool inside = px < V.W && py < V.H;
-    const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
     const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
     const size_t HW = (size_t)V.W * V.H;
-    const size_t p = inside ? (size_t)py * V.W + px : 0;
-    const size_t q = (size_t)V.pix_base + p;
-    float G0 = 0.f, G1 = 0.f, G2 = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t nc = 0;
-    if (inside) {
-        G0 = dl[p]; G1 = dl[HW + p]; G2 = dl[2 * HW + p];
-        C0 = Cout[3 * (size_t)V.pix_base + p];
-        C1 = Cout[3 * (size_t)V.pix_base + HW + p];
-        C2 = Cout[3 * (size_t)V.pix_base + 2 * HW + p];
-        nc = ncontrib[q];
+    const int lane = __lane_id();
+    int px[PPL], py[PPL];
+    float pxc[PPL], pyc[PPL], G0[PPL], G1[PPL], G2[PPL], C0[PPL], C1[PPL], C2[PPL];
+    float T[PPL], pr[PPL], pg[PPL], pb[PPL];
+    uint32_t nc[PPL];
+    uint32_t lane_nc = 0;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int p = (int)threadIdx.x + k * NT;
+        px[k] = tx * B + p % B;
+        py[k] = ty * B + p / B;
+        pxc[k] = (float)px[k] + 0.5f;
+        pyc[k] = (float)py[k] + 0.5f;
+        G0[k] = G1[k] = G2[k] = C0[k] = C1[k] = C2[k] = 0.f;
+        nc[k] = 0u;
+        if (px[k] < V.W && py[k] < V.H) {
+            const size_t q = (size_t)py[k] * V.W + px[k];
+            G0[k] = dl[q]; G1[k] = dl[HW + q]; G2[k] = dl[2 * HW + q];
+            C0[k] = Cout[3 * (size_t)V.pix_base + q];
+            C1[k] = Cout[3 * (size_t)V.pix_base + HW + q];
+            C2[k] = Cout[3 * (size_t)V.pix_base + 2 * HW + q];
+            nc[k] = ncontrib[(size_t)V.pix_base + q];
+        }
+        T[k] = 1.0f;
+        pr[k] = pg[k] = pb[k] = 0.f;
+        lane_nc = max(lane_nc, nc[k]);
     }
     if (threadIdx.x == 0) s_max = 0u;
     __syncthreads();
-    if (nc) atomicMax(&s_max, nc);
+    if (lane_nc) atomicMax(&s_max, lane_nc);
     __syncthreads();
     const int64_t end = start + (int64_t)s_max;
-    const uint32_t wave_nc = wave_max_u32(nc);
-    float T = 1.0f, pr = 0.f, pg = 0.f, pb = 0.f;
+    const uint32_t wave_nc = wave_max_u32(lane_nc);
     const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
     for (int64_t base = start; base < end; base += CHUNK) {
         const int cnt = (int)min((int64_t)CHUNK, end - base);
+        __syncthreads();  // the previous chunk's LDS is no longer read
         for (int k = threadIdx.x; k < cnt; k += NT) {
             const uint32_t gid = ids[base + k];
             s_gid[k] = gid;
             stage_splat(recs[gid], s_sp[k]);
         }
-        for (int k = threadIdx.x; k < SLOTS * 9 * CHUNK; k += NT) (&s_acc[0][0][0])[k] = 0.f;
         __syncthreads();
         const uint32_t rel0 = (uint32_t)(base - start);
         // entries past this wave's last contributor need no work
         const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
         for (int j = 0; j < jend; ++j) {
             const Splat s = to_splat(s_sp[j]);
-            float dx = 0.f, dy = 0.f, Gk = 0.f, alpha = 0.f;
-            bool clamped = false;
-            const bool bl = (rel0 + (uint32_t)j < nc) && eval_splat(s, px, py, pxc, pyc, dx, dy, Gk, alpha, clamped);
-            if (STATS) {
-                n_eval += (rel0 + (uint32_t)j < nc) && in_square(s, px, py);
-                n_blend += bl;
-            }
-            if (__ballot(bl) == 0ull) continue;  // wave-uniform skip
             float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
-            if (bl) {
-                const float w = alpha * T;
-                pr = __builtin_fmaf(s.cr, w, pr);
-                pg = __builtin_fmaf(s.cg, w, pg);
-                pb = __builtin_fmaf(s.cb, w, pb);
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                float dx, dy, Gk, alpha;
+                bool clamped;
+                const bool live = rel0 + (uint32_t)j < nc[k];
+                const bool ok = live && eval_splat(s, px[k], py[k], pxc[k], pyc[k], dx, dy, Gk, alpha, clamped);
+                if (STATS) {
+                    n_eval += (live && in_square(s, px[k], py[k])) ? 1u : 0u;
+                    n_blend += ok ? 1u : 0u;
+                }
+                any = any || ok;
+                const float w = ok ? alpha * T[k] : 0.0f;
+                pr[k] = __builtin_fmaf(s.cr, w, pr[k]);
+                pg[k] = __builtin_fmaf(s.cg, w, pg[k]);
+                pb[k] = __builtin_fmaf(s.cb, w, pb[k]);
+                // colour behind this splat: C_out - prefix (includes T_final * bg)
                 const float oma = 1.0f - alpha;
                 const float ioma = 1.0f / oma;
-                // colour behind this splat: C_out - prefix (includes T_final * bg)
-                const float Sr = C0 - pr, Sg = C1 - pg, Sb = C2 - pb;
-                const float da = G0 * (s.cr * T - Sr * ioma) + G1 * (s.cg * T - Sg * ioma) + G2 * (s.cb * T - Sb * ioma);
-                v6 = G0 * w;
-                v7 = G1 * w;
-                v8 = G2 * w;
-                if (!clamped) {
-                    v5 = da * Gk;
-                    const float dpn = da * alpha;  // dL/dpower (natural log domain)
-                    // power = -1/2 (Q00 dx^2 + 2 Q01 dx dy + Q11 dy^2); (qa, qb, qc) = log2(e) * (-Q00/2, -Q01, -Q11/2)
-                    const float kk = dpn * kinv;
-                    v0 = kk * (2.0f * s.qa * dx + s.qb * dy);  // dL/du
-                    v1 = kk * (s.qb * dx + 2.0f * s.qc * dy);  // dL/dv
-                    v2 = -0.5f * dpn * dx * dx;                // dL/dQ00
-                    v3 = -dpn * dx * dy;                       // dL/dQ01
-                    v4 = -0.5f * dpn * dy * dy;                // dL/dQ11
-                }
-                T = next_T(T, alpha);
+                const float Tk = T[k];
+                const float da = G0[k] * (s.cr * Tk - (C0[k] - pr[k]) * ioma) +
+                                 G1[k] * (s.cg * Tk - (C1[k] - pg[k]) * ioma) +
+                                 G2[k] * (s.cb * Tk - (C2[k] - pb[k]) * ioma);
+                v6 += G0[k] * w;
+                v7 += G1[k] * w;
+                v8 += G2[k] * w;
+                const bool soft = ok && !clamped;
+                const float dpn = soft ? da * alpha : 0.0f;  // dL/dpower (natural log domain)
+                v5 += soft ? da * Gk : 0.0f;
+                // power = -1/2 (Q00 dx^2 + 2 Q01 dx dy + Q11 dy^2); (qa, qb, qc) = log2(e) * (-Q00/2, -Q01, -Q11/2)
+                const float kk = dpn * kinv;
+                const float ddx = soft ? dx : 0.0f, ddy = soft ? dy : 0.0f;
+                v0 += kk * (2.0f * s.qa * ddx + s.qb * ddy);  // dL/du
+                v1 += kk * (s.qb * ddx + 2.0f * s.qc * ddy);  // dL/dv
+                v2 += -0.5f * dpn * ddx * ddx;                // dL/dQ00
+                v3 += -dpn * ddx * ddy;                       // dL/dQ01
+                v4 += -0.5f * dpn * ddy * ddy;                // dL/dQ11
+                T[k] = ok ? next_T(Tk, alpha) : Tk;
             }
-            const float r0 = wave_sum_to_63(v0), r1 = wave_sum_to_63(v1), r2 = wave_sum_to_63(v2),
-                        r3 = wave_sum_to_63(v3), r4 = wave_sum_to_63(v4), r5 = wave_sum_to_63(v5),
-                        r6 = wave_sum_to_63(v6), r7 = wave_sum_to_63(v7), r8 = wave_sum_to_63(v8);
-            if (__lane_id() == 63) {
-                if (NW == 1) {
-                    float* a = &s_acc[0][0][j];
-                    a[0 * CHUNK] = r0; a[1 * CHUNK] = r1; a[2 * CHUNK] = r2;
-                    a[3 * CHUNK] = r3; a[4 * CHUNK] = r4; a[5 * CHUNK] = r5;
-                    a[6 * CHUNK] = r6; a[7 * CHUNK] = r7; a[8 * CHUNK] = r8;
-                } else {
-                    atomicAdd(&s_acc[0][0][j], r0); atomicAdd(&s_acc[0][1][j], r1);
-                    atomicAdd(&s_acc[0][2][j], r2); atomicAdd(&s_acc[0][3][j], r3);
-                    atomicAdd(&s_acc[0][4][j], r4); atomicAdd(&s_acc[0][5][j], r5);
-                    atomicAdd(&s_acc[0][6][j], r6); atomicAdd(&s_acc[0][7][j], r7);
-                    atomicAdd(&s_acc[0][8][j], r8);
+            if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
+                const int slot = j & 63;
+                const bool mine = lane == slot;
+#define H4D_PARK(acc, v) \
+    acc = mine ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(v)), 63)) : acc
+                H4D_PARK(a0, v0); H4D_PARK(a1, v1); H4D_PARK(a2, v2);
+                H4D_PARK(a3, v3); H4D_PARK(a4, v4); H4D_PARK(a5, v5);
+                H4D_PARK(a6, v6); H4D_PARK(a7, v7); H4D_PARK(a8, v8);
+#undef H4D_PARK
+            }
+            if ((j & 63) == 63 || j == jend - 1) {  // flush the group of up to 64 splats
+                const int j0 = j & ~63;
+                if (lane <= (j & 63)) {
+                    const uint32_t gid = s_gid[j0 + lane];
+                    if (a0 != 0.f) atomicAdd(&g2[(size_t)0 * N + gid], a0);
+                    if (a1 != 0.f) atomicAdd(&g2[(size_t)1 * N + gid], a1);
+                    if (a2 != 0.f) atomicAdd(&g2[(size_t)2 * N + gid], a2);
+                    if (a3 != 0.f) atomicAdd(&g2[(size_t)3 * N + gid], a3);
+                    if (a4 != 0.f) atomicAdd(&g2[(size_t)4 * N + gid], a4);
+                    if (a5 != 0.f) atomicAdd(&g2[(size_t)5 * N + gid], a5);
+                    if (a6 != 0.f) atomicAdd(&g2[(size_t)6 * N + gid], a6);
+                    if (a7 != 0.f) atomicAdd(&g2[(size_t)7 * N + gid], a7);
+                    if (a8 != 0.f) atomicAdd(&g2[(size_t)8 * N + gid], a8);
                 }
+                a0 = a1 = a2 = a3 = a4 = a5 = a6 = a7 = a8 = 0.f;
             }
         }
-        __syncthreads();
-        for (int k = threadIdx.x; k < 9 * cnt; k += NT) {
-            const int c = k / cnt, j = k - c * cnt;
-            float val = s_acc[0][c][j];
-            for (int w = 1; w < SLOTS; ++w) val += s_acc[w][c][j];
-            if (val != 0.f) atomicAdd(&g2[(size_t)c * N + s_gid[j]], val);
-        }
-        __syncthreads();
     }
     if (STATS) {
         atomicAdd(&counters[2], n_eval);
@@ -268,35 +325,40 @@ __global__ void __launch_bounds__(B * B) k_composite_bwd(const Rec* __restrict__
 }
 
 bool composite_supported(int tile, int chunk) {
-    return (tile == 8 || tile == 16 || tile == 32) && (chunk == 128 || chunk == 256 || chunk == 512);
+    return (tile == 8 || tile == 16 || tile == 32) && (chunk == 64 || chunk == 128 || chunk == 256 || chunk == 512);
 }
 
 template <int B, int C>
-static void fwd_t(const Rec* recs, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int view,
-                  int n_tiles, float* image, float* Tfin, uint32_t* ncontrib, float* Cout, unsigned long long* counters,
-                  hipStream_t st) {
+static void fwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
+                  int v1, int n_tiles, const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout,
+                  unsigned long long* counters, hipStream_t st) {
+    constexpr int NT = Shape<B>::NT;
     if (counters)
-        k_composite_fwd<B, C, true><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, image, Tfin, ncontrib,
-                                                               Cout, counters);
+        k_composite_fwd<B, C, true><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, images, Tfin,
+                                                            ncontrib, Cout, counters);
     else
-        k_composite_fwd<B, C, false><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, image, Tfin, ncontrib,
-                                                                Cout, nullptr);
+        k_composite_fwd<B, C, false><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, images, Tfin,
+                                                             ncontrib, Cout, nullptr);
 }
 template <int B, int C>
-static void bwd_t(const Rec* recs, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int view,
-                  int n_tiles, const float* dl, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
-                  float* g2, int N, unsigned long long* counters, hipStream_t st) {
+static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
+                  int v1, int n_tiles, const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib,
+                  const float* Cout, float* g2, unsigned long long* counters, hipStream_t st) {
+    constexpr int NT = Shape<B>::NT;
     if (counters)
-        k_composite_bwd<B, C, true><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, dl, Tfin, ncontrib, Cout,
-                                                               g2, N, counters);
+        k_composite_bwd<B, C, true><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, dls, Tfin, ncontrib,
+                                                            Cout, g2, counters);
     else
-        k_composite_bwd<B, C, false><<<n_tiles, B * B, 0, st>>>(recs, ids, ranges, views, view, dl, Tfin, ncontrib,
-                                                                Cout, g2, N, nullptr);
+        k_composite_bwd<B, C, false><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, dls, Tfin,
+                                                             ncontrib, Cout, g2, nullptr);
 }
 
 #define H4D_DISPATCH(FN, ...)                                                   \
     do {                                                                        \
-        if (tile == 8 && chunk == 128) FN<8, 128>(__VA_ARGS__);                 \
+        if (tile == 8 && chunk == 64) FN<8, 64>(__VA_ARGS__);                   \
+        else if (tile == 16 && chunk == 64) FN<16, 64>(__VA_ARGS__);            \
+        else if (tile == 32 && chunk == 64) FN<32, 64>(__VA_ARGS__);            \
+        else if (tile == 8 && chunk == 128) FN<8, 128>(__VA_ARGS__);            \
         else if (tile == 8 && chunk == 256) FN<8, 256>(__VA_ARGS__);            \
         else if (tile == 8 && chunk == 512) FN<8, 512>(__VA_ARGS__);            \
         else if (tile == 16 && chunk == 128) FN<16, 128>(__VA_ARGS__);          \
@@ -307,19 +369,19 @@ static void bwd_t(const Rec* recs, const uint32_t* ids, const int64_t* ranges, c
         else if (tile == 32 && chunk == 512) FN<32, 512>(__VA_ARGS__);          \
     } while (0)
 
-void launch_composite_fwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int view, int n_tiles, float* image, float* Tfin,
+void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+                          const ViewParams* views, int v0, int v1, int n_tiles, const PtrTable& images, float* Tfin,
                           uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(fwd_t, recs, ids, ranges, views, view, n_tiles, image, Tfin, ncontrib, Cout, counters, st);
+    H4D_DISPATCH(fwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, images, Tfin, ncontrib, Cout, counters, st);
 }
 
-void launch_composite_bwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int view, int n_tiles, const float* dl, const float* Tfin,
-                          const uint32_t* ncontrib, const float* Cout, float* g2, int N, unsigned long long* counters,
-                          hipStream_t st) {
+void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+                          const ViewParams* views, int v0, int v1, int n_tiles, const CPtrTable& dls,
+                          const float* Tfin, const uint32_t* ncontrib, const float* Cout, float* g2,
+                          unsigned long long* counters, hipStream_t st) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(bwd_t, recs, ids, ranges, views, view, n_tiles, dl, Tfin, ncontrib, Cout, g2, N, counters, st);
+    H4D_DISPATCH(bwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, dls, Tfin, ncontrib, Cout, g2, counters, st);
 }
 
 }  // namespace h4d

@@ -21,7 +21,9 @@ struct ViewTableIn {
 
 // preprocess.hip
 void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st);
-void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, Rec* recs,
+// Records of views [v0, v0 + nv) (recs: all views, [view][N]); depth keys and
+// ids of view v0 + r at dkeys/dvals + r * N.
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,
                        uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
                            const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st);
@@ -36,35 +38,42 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kScanTile = 2048;
 
 int radix_blocks(uint64_t capacity);
-size_t radix_hist_words(uint64_t capacity);
-// One stable LSD pass over `nbits` (<= 8) bits at `shift`.  Count from *dcount
-// when dcount != null, else hcount.  vals_out index is offset by *out_offset
-// when out_offset != null.
+size_t radix_hist_words(uint64_t capacity, int n_seg);
+// One stable LSD pass over `nbits` (<= 8) bits at `shift`, independently on
+// n_seg segments that start seg_stride elements apart (all arrays).  Count
+// (per segment) from *dcount when dcount != null, else hcount; capacity bounds
+// the count.  vals_out index is offset by *out_offset when out_offset != null.
+// hist holds radix_hist_words(capacity, n_seg) words, totals 256 * n_seg.
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
-                       uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st);
+                       uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
+                       int n_seg = 1, uint64_t seg_stride = 0);
 int scan_blocks(int n);
 // out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
 void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigned long long* out,
                          unsigned long long* partials, hipStream_t st);
-void launch_coarse_count(const uint32_t* sorted_gid, int n, const Rec* recs, int tile, int S, uint32_t* cnt,
-                         uint64_t* rect_sorted, hipStream_t st);
+// Two-level binning over the views [v0, v1) of one pass; j = r * N + rank
+// indexes the depth-ordered Gaussians of view v0 + r (n = (v1 - v0) * N).
+// Super-tile ids are relative to view v0, tile ids t to its first tile.
+void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
+                         uint32_t* cnt, uint64_t* rect_sorted, hipStream_t st);
 void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
                             unsigned long long* eff_count, hipStream_t st);
-void launch_coarse_emit(const unsigned long long* offsets, int n, const uint64_t* rect_sorted, int S, int SX,
-                        const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st);
-void launch_tile_sizes(const int64_t* cranges, int tiles, int tiles_x, int S, int SX,
+void launch_coarse_emit(const unsigned long long* offsets, int n, int N, const uint64_t* rect_sorted,
+                        const ViewParams* views, int v0, int S, const unsigned long long* eff_count, uint32_t* keys,
+                        uint32_t* vals, hipStream_t st);
+void launch_tile_sizes(const int64_t* cranges, int tiles, const ViewParams* views, int v0, int v1, int S,
                        const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st);
-void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int view,
-                             uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
+void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int v0,
+                             int v1, uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
                              unsigned long long* eff_regions, hipStream_t st);
 void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int S, int SX, const unsigned long long* eff_count,
-                          uint32_t* cgid, uint32_t* crect, hipStream_t st);
+                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S,
+                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* crect, hipStream_t st);
 void launch_tile_write(const uint32_t* cgid, const uint32_t* crect, const int64_t* cranges,
                        const unsigned long long* region_off, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_regions, int tiles, int tiles_x, int S, int SX, uint32_t* ids,
-                       int64_t* ranges, hipStream_t st);
+                       const unsigned long long* eff_regions, int tiles, const ViewParams* views, int v0, int v1,
+                       int S, uint32_t* ids, int64_t* ranges, hipStream_t st);
 // ranges of sorted keys: ranges[2k], ranges[2k+1] = [first, last+1) + *base (base may be null)
 void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,
                    int64_t* ranges, hipStream_t st);
@@ -74,13 +83,16 @@ void launch_zero_status(Status* s, unsigned long long* pair_base, int n_views, h
 
 // composite.hip
 bool composite_supported(int tile, int chunk);
-void launch_composite_fwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int view, int n_tiles, float* image, float* Tfin,
+// One launch over the tiles of views [v0, v1) (n_tiles = their total): recs
+// holds every view's records ([view][N]), images/dls are indexed by view and
+// g2 is laid out [view][9][N].
+void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+                          const ViewParams* views, int v0, int v1, int n_tiles, const PtrTable& images, float* Tfin,
                           uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st);
-void launch_composite_bwd(int tile, int chunk, const Rec* recs, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int view, int n_tiles, const float* dl, const float* Tfin,
-                          const uint32_t* ncontrib, const float* Cout, float* g2, int N, unsigned long long* counters,
-                          hipStream_t st);
+void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+                          const ViewParams* views, int v0, int v1, int n_tiles, const CPtrTable& dls,
+                          const float* Tfin, const uint32_t* ncontrib, const float* Cout, float* g2,
+                          unsigned long long* counters, hipStream_t st);
 // L1 loss gradient (loss.hip)
 void launch_l1_loss_grad(const float* img, const float* target, float* dl, size_t n, float scale, float* loss,
                          hipStream_t st);

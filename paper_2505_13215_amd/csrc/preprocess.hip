@@ -259,13 +259,19 @@ __device__ inline void colour(const float* shp, int n, int i, const double Y[16]
 // ---------------------------------------------------------------------------
 // Forward kernel: one thread per Gaussian of the merged list [4D | 3D].
 // ---------------------------------------------------------------------------
+// grid.y runs over the views [v0, v0 + gridDim.y): records go to recs[view][N]
+// (absolute), depth keys and ids to dkeys/dvals[view - v0][N].
 __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const ViewParams* __restrict__ views,
-                                                    int view, Rec* __restrict__ recs,
+                                                    int v0, Rec* __restrict__ recs,
                                                     uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
     const int N = g3.n + g4.n;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
+    const int view = v0 + (int)blockIdx.y;
     const ViewParams& V = views[view];
+    recs += (size_t)view * N;
+    dkeys += (size_t)blockIdx.y * N;
+    dvals += (size_t)blockIdx.y * N;
     WorldF w;
     const float* shp;
     int shn, shi;
@@ -585,8 +591,9 @@ __global__ void __launch_bounds__(128) k_preprocess_bwd3(G3Ptr g3, int n4, int N
 // ---------------------------------------------------------------------------
 __global__ void k_write_views(ViewTableIn in, ViewParams* out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int tile_base = 0;
+    int tile_base = 0, super_base = 0;
     long long pix_base = 0;
+    const int S = kSuperPixels / in.tile;
     for (int v = 0; v < in.n; ++v) {
         const ViewIn& s = in.v[v];
         ViewParams p;
@@ -602,6 +609,11 @@ __global__ void k_write_views(ViewTableIn in, ViewParams* out) {
         p.tiles_y = ceil_div(s.H, in.tile);
         p.tile_base = tile_base;
         p.pix_base = pix_base;
+        p.sx = ceil_div(p.tiles_x, S);
+        p.sy = ceil_div(p.tiles_y, S);
+        p.super_base = super_base;
+        p.pad = 0;
+        super_base += p.sx * p.sy;
         tile_base += p.tiles_x * p.tiles_y;
         pix_base += (long long)s.W * s.H;
         out[v] = p;
@@ -615,11 +627,11 @@ void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st) 
     k_write_views<<<1, 1, 0, st>>>(in, out);
 }
 
-void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int view, Rec* recs,
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,
                        uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
     const int N = g3.n + g4.n;
-    if (N == 0) return;
-    k_preprocess<<<ceil_div(N, 256), 256, 0, st>>>(g3, g4, views, view, recs, dkeys, dvals);
+    if (N == 0 || nv == 0) return;
+    k_preprocess<<<dim3(ceil_div(N, 256), nv), 256, 0, st>>>(g3, g4, views, v0, recs, dkeys, dvals);
 }
 
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,

@@ -56,8 +56,10 @@ __device__ inline T block_exclusive_scan_256(T v, T* s_buf, T& total) {
 __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                                 const unsigned long long* dcount, uint64_t hcount,
                                                                 int shift, int nbits, uint32_t* __restrict__ hist,
-                                                                int nblocks) {
+                                                                int nblocks, uint64_t seg_stride) {
     __shared__ uint32_t s_hist[4][256];
+    keys += (size_t)blockIdx.y * seg_stride;
+    hist += (size_t)blockIdx.y * 256 * nblocks;
     const int radix = 1 << nbits;
     const uint32_t mask = (uint32_t)radix - 1u;
     const int tid = threadIdx.x, w = tid >> 6;
@@ -83,7 +85,8 @@ __global__ void __launch_bounds__(256) k_radix_digit_scan(uint32_t* __restrict__
     __shared__ uint32_t s_buf[256];
     const uint64_t n = read_count(dcount, hcount);
     const int live = (int)min((uint64_t)nblocks, (n + kSortTile - 1) / kSortTile);
-    uint32_t* h = hist + (size_t)blockIdx.x * nblocks;
+    uint32_t* h = hist + (size_t)blockIdx.y * 256 * nblocks + (size_t)blockIdx.x * nblocks;
+    totals += (size_t)blockIdx.y * 256;
     uint32_t carry = 0;
     for (int start = 0; start < live; start += 1024) {
         const int i0 = start + 4 * (int)threadIdx.x;
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const unsigned long long* dcount, uint64_t hcount, int shift, int nbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int nblocks,
-    const unsigned long long* out_offset) {
+    const unsigned long long* out_offset, uint64_t seg_stride) {
     __shared__ uint32_t s_wcount[4][256];
     __shared__ uint32_t s_dstart[256];
     __shared__ uint32_t s_gbase[256];
@@ -119,6 +122,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint64_t n = read_count(dcount, hcount);
     const uint64_t begin = (uint64_t)blockIdx.x * kSortTile;
     if (begin >= n) return;  // uniform over the block
+    {
+        const size_t so = (size_t)blockIdx.y * seg_stride;
+        keys_in += so; vals_in += so; keys_out += so; vals_out += so;
+        hist += (size_t)blockIdx.y * 256 * nblocks;
+        totals += (size_t)blockIdx.y * 256;
+    }
     const int radix = 1 << nbits;
     const uint32_t mask = (uint32_t)radix - 1u;
     const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
@@ -190,17 +199,22 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
 }
 
 int radix_blocks(uint64_t capacity) { return (int)((capacity + kSortTile - 1) / kSortTile); }
-size_t radix_hist_words(uint64_t capacity) { return (size_t)256 * (size_t)std::max(1, radix_blocks(capacity)); }
+size_t radix_hist_words(uint64_t capacity, int n_seg) {
+    return (size_t)256 * (size_t)std::max(1, radix_blocks(capacity)) * (size_t)std::max(1, n_seg);
+}
 
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
-                       uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st) {
+                       uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
+                       int n_seg, uint64_t seg_stride) {
     const int nb = radix_blocks(capacity);
-    if (nb == 0) return;
-    k_radix_upsweep<<<nb, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb);
-    k_radix_digit_scan<<<1 << nbits, 256, 0, st>>>(hist, nb, totals, dcount, hcount);
-    k_radix_downsweep<<<nb, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount, shift, nbits,
-                                                    hist, totals, nb, out_offset);
+    if (nb == 0 || n_seg == 0) return;
+    k_radix_upsweep<<<dim3(nb, n_seg), kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,
+                                                               seg_stride);
+    k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, totals, dcount, hcount);
+    k_radix_downsweep<<<dim3(nb, n_seg), kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount,
+                                                                 shift, nbits, hist, totals, nb, out_offset,
+                                                                 seg_stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,13 +287,15 @@ __device__ __forceinline__ uint64_t pack_rect(uint32_t x0, uint32_t x1, uint32_t
     return (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) | ((uint64_t)y1 << 48);
 }
 
-// Per depth-ordered Gaussian j: its tile rectangle and its super-tile count.
-__global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n,
-                                                      const Rec* __restrict__ recs, int tile, int S,
+// Per depth-ordered Gaussian j of the view range (j = r * N + rank, view
+// v0 + r): its tile rectangle and its super-tile count.
+__global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n, int N,
+                                                      const Rec* __restrict__ recs, int v0, int tile, int S,
                                                       uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const uint4 d = recs[sorted_gid[j]].d;
+    const int view = v0 + j / N;
+    const uint4 d = recs[(size_t)view * N + sorted_gid[j]].d;
     if (d.w == 0u) {
         cnt[j] = 0u;
         rect_sorted[j] = 0ull;
@@ -304,30 +320,34 @@ __global__ void k_finalize_coarse(const unsigned long long* offsets, int n, uint
     }
 }
 
-// Coarse entries (super-tile id, depth rank j), written in depth order.  One
-// block per 256 depth-ordered Gaussians; threads stride over the block's
-// contiguous output range and find their Gaussian by binary search in LDS.
-__global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* __restrict__ offsets, int n,
-                                                     const uint64_t* __restrict__ rect_sorted, int S, int SX,
+// Coarse entries (super-tile id relative to the range's first view, depth
+// rank j), written in (view, depth) order.  One block per 256 depth-ordered
+// Gaussians; threads stride over the block's contiguous output range and find
+// their Gaussian by binary search in LDS.
+__global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* __restrict__ offsets, int n, int N,
+                                                     const uint64_t* __restrict__ rect_sorted,
+                                                     const ViewParams* __restrict__ views, int v0, int S,
                                                      const unsigned long long* eff_count, uint32_t* __restrict__ keys,
                                                      uint32_t* __restrict__ vals) {
     __shared__ unsigned long long s_off[257];
-    __shared__ uint32_t s_sx0[256], s_sy0[256], s_sw[256];
+    __shared__ uint32_t s_kb[256], s_sxv[256], s_sw[256];
     if (*eff_count == 0ull) return;
     const int tid = threadIdx.x;
     const int j0 = blockIdx.x * 256;
     const int j = j0 + tid;
     if (j < n) {
+        const ViewParams& V = views[v0 + j / N];
         const uint64_t r = rect_sorted[j];
         const uint32_t s = (uint32_t)S;
         const uint32_t sx0 = (uint32_t)(r & 0xFFFFu) / s, sx1 = (uint32_t)((r >> 16) & 0xFFFFu) / s;
+        const uint32_t sy0 = (uint32_t)((r >> 32) & 0xFFFFu) / s;
         s_off[tid] = offsets[j];
-        s_sx0[tid] = sx0;
         s_sw[tid] = sx1 - sx0 + 1u;
-        s_sy0[tid] = (uint32_t)((r >> 32) & 0xFFFFu) / s;
+        s_sxv[tid] = (uint32_t)V.sx;
+        s_kb[tid] = (uint32_t)(V.super_base - views[v0].super_base) + sy0 * (uint32_t)V.sx + sx0;
     } else {
         s_off[tid] = offsets[n];
-        s_sx0[tid] = 0; s_sw[tid] = 1; s_sy0[tid] = 0;
+        s_sw[tid] = 1; s_sxv[tid] = 0; s_kb[tid] = 0;
     }
     if (tid == 0) s_off[256] = offsets[min(j0 + 256, n)];
     __syncthreads();
@@ -341,14 +361,34 @@ __global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* _
         const uint32_t local = (uint32_t)(p - s_off[lo]);
         const uint32_t sw = s_sw[lo];
         const uint32_t sy = local / sw, sx = local - sy * sw;
-        keys[p] = (s_sy0[lo] + sy) * (uint32_t)SX + s_sx0[lo] + sx;
+        keys[p] = s_kb[lo] + sy * s_sxv[lo] + sx;
         vals[p] = (uint32_t)(j0 + lo);
     }
 }
 
+// Global tile id of tile t (relative to the range) -> its view, local tile
+// coordinates and super-tile id relative to the range.
+struct TileLoc {
+    int view, gt;
+    uint32_t tx, ty;
+    int st;
+};
+__device__ __forceinline__ TileLoc locate_tile(const ViewParams* views, int v0, int v1, int t, int S) {
+    TileLoc L;
+    L.gt = views[v0].tile_base + t;
+    L.view = find_view_of_tile(views, v0, v1, L.gt);
+    const ViewParams& V = views[L.view];
+    const int lt = L.gt - V.tile_base;
+    L.tx = (uint32_t)(lt % V.tiles_x);
+    L.ty = (uint32_t)(lt / V.tiles_x);
+    L.st = (V.super_base - views[v0].super_base) + (int)(L.ty / (uint32_t)S) * V.sx + (int)(L.tx / (uint32_t)S);
+    return L;
+}
+
 // Region size of every tile = length of its super-tile's list.
-__global__ void __launch_bounds__(256) k_tile_sizes(const int64_t* __restrict__ cranges, int tiles, int tiles_x, int S,
-                                                    int SX, const unsigned long long* eff_count,
+__global__ void __launch_bounds__(256) k_tile_sizes(const int64_t* __restrict__ cranges, int tiles,
+                                                    const ViewParams* __restrict__ views, int v0, int v1, int S,
+                                                    const unsigned long long* eff_count,
                                                     uint32_t* __restrict__ sizes) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= tiles) return;
@@ -356,18 +396,19 @@ __global__ void __launch_bounds__(256) k_tile_sizes(const int64_t* __restrict__ 
         sizes[t] = 0u;
         return;
     }
-    const int st = ((t / tiles_x) / S) * SX + (t % tiles_x) / S;
-    sizes[t] = (uint32_t)(cranges[2 * st + 1] - cranges[2 * st]);
+    const TileLoc L = locate_tile(views, v0, v1, t, S);
+    sizes[t] = (uint32_t)(cranges[2 * L.st + 1] - cranges[2 * L.st]);
 }
 
-__global__ void k_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int view,
-                                   uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
-                                   unsigned long long* eff_regions) {
+// Regions of the range start at pair_base[v0]; their end goes to pair_base[v1].
+__global__ void k_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base,
+                                   int v0, int v1, uint64_t capacity, Status* status,
+                                   const unsigned long long* eff_coarse, unsigned long long* eff_regions) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long base = pair_base[view];
+    const unsigned long long base = pair_base[v0];
     if (*eff_coarse == 0ull && (status->flags & kFlagOverflow)) {
         *eff_regions = 0ull;
-        pair_base[view + 1] = base;
+        pair_base[v1] = base;
         return;
     }
     const unsigned long long R = region_off[tiles];
@@ -375,10 +416,10 @@ __global__ void k_finalize_regions(const unsigned long long* region_off, int til
     if (base + R > capacity) {
         status->flags |= kFlagOverflow;
         *eff_regions = 0ull;
-        pair_base[view + 1] = base;
+        pair_base[v1] = base;
     } else {
         *eff_regions = 1ull;
-        pair_base[view + 1] = base + R;
+        pair_base[v1] = base + R;
     }
 }
 
@@ -388,14 +429,18 @@ __global__ void k_finalize_regions(const unsigned long long* region_off, int til
 __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ ckeys,
                                                        const uint32_t* __restrict__ cvals,
                                                        const uint64_t* __restrict__ rect_sorted,
-                                                       const uint32_t* __restrict__ sorted_gid, int S, int SX,
+                                                       const uint32_t* __restrict__ sorted_gid, int N,
+                                                       const ViewParams* __restrict__ views, int v0, int S,
                                                        const unsigned long long* eff_count, uint32_t* __restrict__ cgid,
                                                        uint32_t* __restrict__ crect) {
     const uint64_t n = *eff_count;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t st = ckeys[k], j = cvals[k];
+        const uint32_t j = cvals[k];
+        const ViewParams& V = views[v0 + (int)(j / (uint32_t)N)];
+        const uint32_t st = ckeys[k] - (uint32_t)(V.super_base - views[v0].super_base);
         const uint64_t r = rect_sorted[j];
-        const uint32_t bx = (st % (uint32_t)SX) * (uint32_t)S, by = (st / (uint32_t)SX) * (uint32_t)S;
+        const uint32_t SX = (uint32_t)V.sx;
+        const uint32_t bx = (st % SX) * (uint32_t)S, by = (st / SX) * (uint32_t)S;
         const uint32_t x0 = (uint32_t)(r & 0xFFFFu), x1 = (uint32_t)((r >> 16) & 0xFFFFu);
         const uint32_t y0 = (uint32_t)((r >> 32) & 0xFFFFu), y1 = (uint32_t)(r >> 48);
         const uint32_t lx0 = max(x0, bx) - bx, lx1 = min(x1, bx + (uint32_t)S - 1u) - bx;
@@ -414,14 +459,15 @@ __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__
                                                     const int64_t* __restrict__ cranges,
                                                     const unsigned long long* __restrict__ region_off,
                                                     const unsigned long long* base_ptr,
-                                                    const unsigned long long* eff_regions, int tiles_x, int S, int SX,
+                                                    const unsigned long long* eff_regions,
+                                                    const ViewParams* __restrict__ views, int v0, int v1, int S,
                                                     uint32_t* __restrict__ ids, int64_t* __restrict__ ranges) {
     __shared__ uint32_t s_wc[2][4][4];  // [parity][round][wave]
     if (*eff_regions == 0ull) return;
     const int t = blockIdx.x;
-    const uint32_t tx = (uint32_t)(t % tiles_x), ty = (uint32_t)(t / tiles_x);
-    const int st = (int)(ty / (uint32_t)S) * SX + (int)(tx / (uint32_t)S);
-    const uint32_t lx = tx % (uint32_t)S, ly = ty % (uint32_t)S;
+    const TileLoc loc = locate_tile(views, v0, v1, t, S);
+    const int st = loc.st;
+    const uint32_t lx = loc.tx % (uint32_t)S, ly = loc.ty % (uint32_t)S;
     const int64_t cs = cranges[2 * st], ce = cranges[2 * st + 1];
     const uint64_t out = (uint64_t)*base_ptr + (uint64_t)region_off[t];
     const int tid = threadIdx.x, w = tid >> 6;
@@ -459,8 +505,8 @@ __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__
         run += base_r;
     }
     if (tid == 0) {
-        ranges[2 * (size_t)t] = (int64_t)out;
-        ranges[2 * (size_t)t + 1] = (int64_t)(out + run);
+        ranges[2 * (size_t)loc.gt] = (int64_t)out;
+        ranges[2 * (size_t)loc.gt + 1] = (int64_t)(out + run);
     }
 }
 
@@ -487,41 +533,44 @@ __global__ void k_zero_status(Status* s, unsigned long long* pair_base, int n_vi
     for (int v = t; v <= n_views; v += blockDim.x) pair_base[v] = 0ull;
 }
 
-void launch_coarse_count(const uint32_t* sorted_gid, int n, const Rec* recs, int tile, int S, uint32_t* cnt,
-                         uint64_t* rect_sorted, hipStream_t st) {
+void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
+                         uint32_t* cnt, uint64_t* rect_sorted, hipStream_t st) {
     if (n == 0) return;
-    k_coarse_count<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, n, recs, tile, S, cnt, rect_sorted);
+    k_coarse_count<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, n, N, recs, v0, tile, S, cnt, rect_sorted);
 }
 void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
                             unsigned long long* eff_count, hipStream_t st) {
     k_finalize_coarse<<<1, 1, 0, st>>>(offsets, n, capacity, S, status, eff_count);
 }
-void launch_coarse_emit(const unsigned long long* offsets, int n, const uint64_t* rect_sorted, int S, int SX,
-                        const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st) {
+void launch_coarse_emit(const unsigned long long* offsets, int n, int N, const uint64_t* rect_sorted,
+                        const ViewParams* views, int v0, int S, const unsigned long long* eff_count, uint32_t* keys,
+                        uint32_t* vals, hipStream_t st) {
     if (n == 0) return;
-    k_coarse_emit<<<ceil_div(n, 256), 256, 0, st>>>(offsets, n, rect_sorted, S, SX, eff_count, keys, vals);
+    k_coarse_emit<<<ceil_div(n, 256), 256, 0, st>>>(offsets, n, N, rect_sorted, views, v0, S, eff_count, keys, vals);
 }
-void launch_tile_sizes(const int64_t* cranges, int tiles, int tiles_x, int S, int SX,
+void launch_tile_sizes(const int64_t* cranges, int tiles, const ViewParams* views, int v0, int v1, int S,
                        const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st) {
     if (tiles == 0) return;
-    k_tile_sizes<<<ceil_div(tiles, 256), 256, 0, st>>>(cranges, tiles, tiles_x, S, SX, eff_count, sizes);
+    k_tile_sizes<<<ceil_div(tiles, 256), 256, 0, st>>>(cranges, tiles, views, v0, v1, S, eff_count, sizes);
 }
-void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int view,
-                             uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
+void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int v0,
+                             int v1, uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
                              unsigned long long* eff_regions, hipStream_t st) {
-    k_finalize_regions<<<1, 1, 0, st>>>(region_off, tiles, pair_base, view, capacity, status, eff_coarse, eff_regions);
+    k_finalize_regions<<<1, 1, 0, st>>>(region_off, tiles, pair_base, v0, v1, capacity, status, eff_coarse,
+                                        eff_regions);
 }
 void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int S, int SX, const unsigned long long* eff_count,
-                          uint32_t* cgid, uint32_t* crect, hipStream_t st) {
-    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, S, SX, eff_count, cgid, crect);
+                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S,
+                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* crect, hipStream_t st) {
+    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, N, views, v0, S, eff_count, cgid,
+                                          crect);
 }
 void launch_tile_write(const uint32_t* cgid, const uint32_t* crect, const int64_t* cranges,
                        const unsigned long long* region_off, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_regions, int tiles, int tiles_x, int S, int SX, uint32_t* ids,
-                       int64_t* ranges, hipStream_t st) {
+                       const unsigned long long* eff_regions, int tiles, const ViewParams* views, int v0, int v1,
+                       int S, uint32_t* ids, int64_t* ranges, hipStream_t st) {
     if (tiles == 0) return;
-    k_tile_write<<<tiles, 256, 0, st>>>(cgid, crect, cranges, region_off, base_ptr, eff_regions, tiles_x, S, SX, ids,
+    k_tile_write<<<tiles, 256, 0, st>>>(cgid, crect, cranges, region_off, base_ptr, eff_regions, views, v0, v1, S, ids,
                                         ranges);
 }
 void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,

@@ -60,18 +60,27 @@ class FwdHandle:
     images: list
 
 
+# Launch configuration of the training step (tile edge in pixels, splats staged
+# per LDS chunk); images do not depend on either.
+DEFAULT_TILE = 16
+DEFAULT_CHUNK = 128
+
+
 class Rasterizer:
     """Owns a context, the launch configuration and the workspace tensors.
 
     ``check`` selects when the pair-capacity status is read back: "eager" (after
     every forward, one stream synchronisation, re-rendering with a larger
     capacity on overflow) or "deferred" (read back by ``verify()``; a forward
-    whose pairs did not fit raises there)."""
+    whose pairs did not fit raises there).  ``batched`` processes all views of
+    a call in one launch per stage instead of one view after another (same
+    kernels, bit-identical images)."""
 
-    def __init__(self, tile: int = 16, chunk: int = 256, pair_capacity: int = 1 << 22, growth: float = 1.3,
-                 check: str = "eager"):
+    def __init__(self, tile: int = DEFAULT_TILE, chunk: int = DEFAULT_CHUNK, pair_capacity: int = 1 << 22,
+                 growth: float = 1.3, check: str = "eager", batched: bool = False):
         self.ctx = L.Context()
         self.tile, self.chunk = int(tile), int(chunk)
+        self.batched = bool(batched)
         self.capacity = int(pair_capacity)
         self.growth = float(growth)
         self.check_mode = check
@@ -83,7 +92,7 @@ class Rasterizer:
 
     # -- workspace -------------------------------------------------------------
     def config(self) -> L.Config:
-        return L.Config(self.tile, self.chunk, 0, 0, self.capacity)
+        return L.Config(self.tile, self.chunk, int(self.batched), 0, self.capacity)
 
     def sizes(self, n3: int, n4: int, views_arr, n_views: int):
         st, sc = C.c_size_t(), C.c_size_t()
@@ -291,6 +300,47 @@ def convert_static(rast: Rasterizer, g3: dict, g4: dict, tau: float):
     g3n = {k: (v[..., :k3] if v.dim() == 2 else v[:k3]).contiguous() for k, v in o3.items()}
     g4n = {k: (v[..., :k4] if v.dim() == 2 else v[:k4]).contiguous() for k, v in o4.items()}
     return g3n, g4n, perm[:n4]
+
+
+class CapturedStep:
+    """forward -> L1 loss gradient -> backward over a fixed view set, captured
+    once in a HIP graph and replayed.  Parameters, targets and gradient
+    buffers are read and written in place, so a replay sees their current
+    contents.  The workspace is sized by one eager step first; the capacity
+    status of a replay is read by ``verify()`` (a replay whose pairs did not
+    fit raises there: capture again)."""
+
+    def __init__(self, rast: Rasterizer, g3: dict, g4: dict, views, targets, grads):
+        self.rast, self.g3, self.g4, self.views = rast, g3, g4, list(views)
+        self.targets = list(targets)
+        self.gr3, self.gr4 = grads
+        self.dls = [torch.empty((3, v.height, v.width), dtype=torch.float32, device="cuda") for v in self.views]
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        rast.check_mode = "eager"
+        self._body()  # sizes the workspace and the capacity
+        torch.cuda.synchronize()
+        rast.check_mode = "deferred"
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self._body()  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self.graph):
+            self.images = self._body()
+
+    def _body(self):
+        h = self.rast.forward(self.g3, self.g4, self.views)
+        l1_loss_grad(self.rast, h.images, self.targets, self.views, self.dls, self.loss)
+        self.rast.backward(h, self.g3, self.g4, self.dls, out=(self.gr3, self.gr4))
+        return h.images
+
+    def replay(self):
+        self.graph.replay()
+
+    def verify(self) -> int:
+        return self.rast.verify()
 
 
 def adam_step(rast: Rasterizer, params, grads, ms, vs, lrs, step: int, betas=(0.9, 0.999), eps=1e-8):

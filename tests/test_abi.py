@@ -76,6 +76,36 @@ def test_workspace_size_grows_with_inputs(L):
     assert st.value >= s1 + 2000 * 64 + 128 * 96 * 20
 
 
+def test_batched_workspace(L):
+    """Batched mode keeps the same state (kept from forward to backward) and
+    needs per-pass scratch for every view of the call at once."""
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    va = _views(L, 4)
+    assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, va, 4, C.byref(_cfg(L)), C.byref(st), C.byref(sc)) == 0
+    s_single, k_single = st.value, sc.value
+    assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, va, 4, C.byref(_cfg(L, batched=1)), C.byref(st),
+                                    C.byref(sc)) == 0
+    assert st.value == s_single
+    assert sc.value >= k_single
+    # depth keys, ids and their sort buffers for all four views
+    assert sc.value >= 4 * 4000 * 16
+
+
+def test_batched_pass_size_limit(L):
+    """A batched pass indexes (view, Gaussian) pairs with 32-bit integers."""
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    va = _views(L, 3)
+    n = 1 << 30
+    assert c.L.h4dgs_workspace_size(c.h, n, 0, va, 3, C.byref(_cfg(L)), C.byref(st), C.byref(sc)) == 0
+    rc = c.L.h4dgs_workspace_size(c.h, n, 0, va, 3, C.byref(_cfg(L, batched=1)), C.byref(st), C.byref(sc))
+    assert rc == L.H4D_ERR_INVALID_ARG
+    assert b"batched" in c.L.h4dgs_last_error(c.h)
+    rc = c.L.h4dgs_workspace_size(c.h, 10, 0, va, 3, C.byref(_cfg(L, batched=2)), C.byref(st), C.byref(sc))
+    assert rc == L.H4D_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("tile,chunk", [(7, 256), (16, 100), (64, 256), (0, 0)])
 def test_bad_tile_or_chunk_rejected(L, tile, chunk):
     c = _ctx(L)

@@ -18,8 +18,8 @@ import scenegen as sg
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-IMG_TOL = 1e-4
-GRAD_TOL = 1e-3
+from parity_util import IMG_TOL, GRAD_TOL, check_image as _check_image, flagged_gaussians as _flagged_gaussians
+from parity_util import check_grads as _check_grads, mask_flagged
 
 
 @pytest.fixture(scope="module")
@@ -37,53 +37,6 @@ def _render(h4d, scene, views, tile=16, chunk=256, cap=1 << 20):
     h = rast.forward(g3, g4, views)
     torch.cuda.synchronize()
     return rast, g3, g4, h
-
-
-def _check_image(gpu, ref, amb, tol=IMG_TOL):
-    assert amb.mean() < 1e-3, f"guard band flags {amb.mean():.2e} of the pixels"
-    err = np.abs(gpu - ref)[:, ~amb]
-    assert err.size == 0 or err.max() <= tol, f"max error {err.max():.3e} on unflagged pixels"
-    return float(err.max()) if err.size else 0.0
-
-
-def _flagged_gaussians(scene, view, amb):
-    pr = oracle.project(scene, view)
-    ys, xs = np.nonzero(amb)
-    bad = np.zeros(scene.n3 + scene.n4, bool)
-    if len(xs) == 0:
-        return bad
-    for g in np.nonzero(pr["visible"] > 0)[0]:
-        x0, x1, y0, y1 = pr["x0"][g], pr["x1"][g], pr["y0"][g], pr["y1"][g]
-        if np.any((xs >= x0) & (xs <= x1) & (ys >= y0) & (ys <= y1)):
-            bad[g] = True
-    return bad
-
-
-def _check_grads(scene, gr3, gr4, r3, r4, bad):
-    n4 = scene.n4
-    for which, gr, rf, keys in (("4", gr4, r4, sg_keys4()), ("3", gr3, r3, sg_keys3())):
-        ok_cols = ~bad[:n4] if which == "4" else ~bad[n4:]
-        for k in keys:
-            g = gr[k].detach().cpu().numpy().astype(np.float64)
-            r = rf[k]
-            nr = np.linalg.norm(r)
-            if nr == 0:
-                assert np.abs(g).max() == 0
-                continue
-            rel = np.linalg.norm(g - r) / nr
-            assert rel <= GRAD_TOL, f"{which}D {k}: relative L2 error {rel:.2e}"
-            gs, rs = g[..., ok_cols], r[..., ok_cols]
-            rms = np.sqrt(np.mean(r * r))
-            viol = np.abs(gs - rs) > GRAD_TOL * np.abs(rs) + GRAD_TOL * rms
-            assert viol.sum() == 0, f"{which}D {k}: {viol.sum()} elements out of tolerance"
-
-
-def sg_keys3():
-    return ("mean", "log_scale", "quat", "opacity", "sh")
-
-
-def sg_keys4():
-    return ("mean", "mean_t", "log_scale", "quat_l", "quat_r", "opacity", "sh")
 
 
 # ---------------------------------------------------------------------------
@@ -125,6 +78,19 @@ def test_forward_single_set_and_empty(h4d, n3, n4):
     v = sg.View(scene.views[0].world_to_cam, scene.views[0].fx, scene.views[0].fy, 32.0, 24.0, 64, 48, 0.5,
                 (0.1, 0.2, 0.3))
     _, _, _, h = _render(h4d, scene, [v])
+    ref = oracle.render(scene, v)
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+
+
+@pytest.mark.parametrize("shape", [(32767, 7), (5, 32767), (1, 1), (17, 1)])
+def test_forward_extreme_image_sizes(h4d, shape):
+    """Largest accepted image edge (32767), one-pixel images, ragged single tiles."""
+    W, H = shape
+    print(f"[forward parity] {W}x{H}", flush=True)
+    scene = sg.tiny_scene(n3=600, n4=600, seed=11)
+    v0 = scene.views[0]
+    v = sg.View(v0.world_to_cam, 300.0, 300.0, W / 2.0, H / 2.0, W, H, 0.5, (0.2, 0.3, 0.4))
+    _, _, _, h = _render(h4d, scene, [v], cap=1 << 22)
     ref = oracle.render(scene, v)
     _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
 
@@ -228,6 +194,18 @@ def test_backward_matches_oracle(h4d, seed):
     r3, r4 = oracle.render_bwd(scene, [v], dl)
     amb = oracle.render(scene, v)["amb"]
     _check_grads(scene, gr3, gr4, r3, r4, _flagged_gaussians(scene, v, amb))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_backward_all_gaussians_masked_upstream(h4d, seed):
+    """Upstream gradients zeroed at guard-band pixels: every Gaussian is checked."""
+    scene = sg.tiny_scene(seed=seed)
+    v = scene.views[0]
+    amb = oracle.render(scene, v)["amb"]
+    dl = [mask_flagged(sg.upstream_grads([v], seed=20 + seed)[0], amb)]
+    gr3, gr4 = _grads_gpu(h4d, scene, [v], dl)
+    r3, r4 = oracle.render_bwd(scene, [v], dl)
+    _check_grads(scene, gr3, gr4, r3, r4, np.zeros(scene.n3 + scene.n4, bool))
 
 
 def test_backward_l1_loss_and_background(h4d):
