@@ -18,14 +18,17 @@
 
 namespace h4d {
 
-// LDS copy of one record (52 bytes): packed pixel square, centre split into
-// integer and fractional parts, scaled conic, opacity, colour.
-struct LSplat {
+// LDS copy of one record (64 bytes, 16-byte aligned so that a lane reads it
+// with four 128-bit LDS loads): packed pixel square, centre split into integer
+// and fractional parts, scaled conic, opacity, colour.
+struct __align__(16) LSplat {
     uint32_t rx, ry;              // x0 | x1 << 16, y0 | y1 << 16
     float ui, uf, vi, vf;
     float qa, qb, qc, op;
     float cr, cg, cb;
+    uint32_t pad[3];
 };
+static_assert(sizeof(LSplat) == 64, "LDS splat is 64 bytes");
 
 __device__ __forceinline__ void stage_splat(const Rec& r, LSplat& s) {
     s.rx = r.d.x; s.ry = r.d.y;
@@ -250,7 +253,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
         for (int j = 0; j < jend; ++j) {
             const Splat s = to_splat(s_sp[j]);
-            float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f, v8 = 0.f;
+            float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f, e4 = 0.f, e5 = 0.f, e6 = 0.f, e7 = 0.f, e8 = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
@@ -274,31 +277,48 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 const float da = G0[k] * (s.cr * Tk - (C0[k] - pr[k]) * ioma) +
                                  G1[k] * (s.cg * Tk - (C1[k] - pg[k]) * ioma) +
                                  G2[k] * (s.cb * Tk - (C2[k] - pb[k]) * ioma);
-                v6 += G0[k] * w;
-                v7 += G1[k] * w;
-                v8 += G2[k] * w;
+                e6 += G0[k] * w;
+                e7 += G1[k] * w;
+                e8 += G2[k] * w;
                 const bool soft = ok && !clamped;
                 const float dpn = soft ? da * alpha : 0.0f;  // dL/dpower (natural log domain)
-                v5 += soft ? da * Gk : 0.0f;
+                e5 += soft ? da * Gk : 0.0f;
                 // power = -1/2 (Q00 dx^2 + 2 Q01 dx dy + Q11 dy^2); (qa, qb, qc) = log2(e) * (-Q00/2, -Q01, -Q11/2)
                 const float kk = dpn * kinv;
                 const float ddx = soft ? dx : 0.0f, ddy = soft ? dy : 0.0f;
-                v0 += kk * (2.0f * s.qa * ddx + s.qb * ddy);  // dL/du
-                v1 += kk * (s.qb * ddx + 2.0f * s.qc * ddy);  // dL/dv
-                v2 += -0.5f * dpn * ddx * ddx;                // dL/dQ00
-                v3 += -dpn * ddx * ddy;                       // dL/dQ01
-                v4 += -0.5f * dpn * ddy * ddy;                // dL/dQ11
+                e0 += kk * (2.0f * s.qa * ddx + s.qb * ddy);  // dL/du
+                e1 += kk * (s.qb * ddx + 2.0f * s.qc * ddy);  // dL/dv
+                e2 += -0.5f * dpn * ddx * ddx;                // dL/dQ00
+                e3 += -dpn * ddx * ddy;                       // dL/dQ01
+                e4 += -0.5f * dpn * ddy * ddy;                // dL/dQ11
                 T[k] = ok ? next_T(Tk, alpha) : Tk;
             }
             if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
+                // The reductions and the reads of lane 63 must run with the
+                // whole wave active: the empty asm statement consumes the nine
+                // wave sums here, so they cannot be moved into the lane-divergent
+                // selects below that park them in lane j % 64.
                 const int slot = j & 63;
+                const int r0 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e0)), 63);
+                const int r1 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e1)), 63);
+                const int r2 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e2)), 63);
+                const int r3 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e3)), 63);
+                const int r4 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e4)), 63);
+                const int r5 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e5)), 63);
+                const int r6 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e6)), 63);
+                const int r7 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e7)), 63);
+                const int r8 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e8)), 63);
+                asm volatile("" ::"s"(r0), "s"(r1), "s"(r2), "s"(r3), "s"(r4), "s"(r5), "s"(r6), "s"(r7), "s"(r8));
                 const bool mine = lane == slot;
-#define H4D_PARK(acc, v) \
-    acc = mine ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(v)), 63)) : acc
-                H4D_PARK(a0, v0); H4D_PARK(a1, v1); H4D_PARK(a2, v2);
-                H4D_PARK(a3, v3); H4D_PARK(a4, v4); H4D_PARK(a5, v5);
-                H4D_PARK(a6, v6); H4D_PARK(a7, v7); H4D_PARK(a8, v8);
-#undef H4D_PARK
+                a0 = mine ? __int_as_float(r0) : a0;
+                a1 = mine ? __int_as_float(r1) : a1;
+                a2 = mine ? __int_as_float(r2) : a2;
+                a3 = mine ? __int_as_float(r3) : a3;
+                a4 = mine ? __int_as_float(r4) : a4;
+                a5 = mine ? __int_as_float(r5) : a5;
+                a6 = mine ? __int_as_float(r6) : a6;
+                a7 = mine ? __int_as_float(r7) : a7;
+                a8 = mine ? __int_as_float(r8) : a8;
             }
             if ((j & 63) == 63 || j == jend - 1) {  // flush the group of up to 64 splats
                 const int j0 = j & ~63;
