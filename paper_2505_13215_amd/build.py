@@ -17,6 +17,9 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-munsafe-fp-atomics",  # hardware float atomics (global_atomic_add_f32) instead of CAS loops
+    # no wave-level rewriting of atomics with uniform addresses (the blending
+    # adjoint issues them from single lanes after its own reduction)
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     # no packed-FP32 instruction forms in the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

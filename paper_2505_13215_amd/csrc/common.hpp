@@ -111,19 +111,37 @@ struct Splat {
     int32_t x0, x1, y0, y1;
 };
 
-// The blending step of one (pixel, splat) pair, branch-free, shared bit-for-bit by
-// the forward and backward kernels (the backward recomputes transmittance
-// instead of storing it, so both must take every decision identically).
-// power2 = log2(e) * power.  Returns whether the pair passes the square test,
-// power <= 0 and alpha >= 1/255; alpha = min(0.99, op * exp(power)).
-__device__ __forceinline__ bool eval_splat(const Splat& s, int px, int py, float pxc, float pyc, float& dx, float& dy,
-                                           float& G, float& alpha, bool& clamped) {
+// The blending test of one (pixel, splat) pair, branch-free, shared bit-for-bit
+// by the forward and backward kernels (the backward recomputes transmittance
+// instead of storing it, so both must take every decision identically).  It is
+// split into a column part, computed once for all pixels a lane holds in one
+// column, and a per-pixel part.  power2 = log2(e) * power.
+
+// Column part: pixel-centre x minus splat-centre x, its conic term and the
+// x half of the square test.
+struct ColTerm {
+    float dx, qadx;
+    bool inx;
+};
+
+__device__ __forceinline__ ColTerm eval_col(const Splat& s, int px, float pxc) {
 #pragma clang fp contract(off)
-    const bool in = px >= s.x0 && px <= s.x1 && py >= s.y0 && py <= s.y1;
-    dx = (pxc - s.ui) - s.uf;
+    ColTerm c;
+    c.inx = px >= s.x0 && px <= s.x1;
+    c.dx = (pxc - s.ui) - s.uf;
+    c.qadx = s.qa * c.dx;
+    return c;
+}
+
+// Per-pixel part: returns whether the pair passes the square test, power <= 0
+// and alpha >= 1/255; alpha = min(0.99, op * exp(power)).
+__device__ __forceinline__ bool eval_pix(const Splat& s, const ColTerm& c, int py, float pyc, float& dy, float& G,
+                                         float& alpha, bool& clamped) {
+#pragma clang fp contract(off)
+    const bool in = c.inx && py >= s.y0 && py <= s.y1;
     dy = (pyc - s.vi) - s.vf;
-    const float t = __builtin_fmaf(s.qb, dy, s.qa * dx);
-    const float p2 = __builtin_fmaf(s.qc * dy, dy, dx * t);
+    const float t = __builtin_fmaf(s.qb, dy, c.qadx);
+    const float p2 = __builtin_fmaf(s.qc * dy, dy, c.dx * t);
     G = __builtin_amdgcn_exp2f(p2);
     const float ap = s.op * G;
     clamped = ap > kMaxAlpha;

@@ -1,18 +1,22 @@
 // Front-to-back blending on gfx950 (Eq. 3; Alg. 1 BlendInOrder) and its adjoint.
 //
 // One workgroup per B x B tile (B = 8 and 16: one wave64; 32: four waves), one or
-// four pixels per lane.  The tile's depth-ordered list is walked in chunks: each
-// chunk of records is gathered once from HBM into LDS and broadcast to every lane.
-// A pixel's contributors are exactly the splats whose pixel square contains it,
-// so the image does not depend on B or on the chunk size.
+// four pixels per lane, all of a lane's pixels in one column.  The tile's
+// depth-ordered list is walked in chunks: each chunk of records is gathered
+// once from HBM into LDS and broadcast to every lane.  A pixel's contributors
+// are exactly the splats whose pixel square contains it, so the image does not
+// depend on B or on the chunk size.
 //
 // The backward recomputes transmittance front to back with the very same
-// blending step as the forward (eval_splat), takes the colour behind a splat as
-// C_out minus the running prefix, sums each lane's pixels in registers, reduces
-// the nine per-splat gradients across the wave with DPP (skipped when no lane
-// blended the splat), parks the wave sums in the register file and flushes them
-// with one global atomic per (splat, component, wave).  Each wave stops at its
-// own last contributor.
+// blending test as the forward (eval_col / eval_pix, next_T).  The colour behind
+// a splat enters dL/dalpha only through its dot product with dL/dC, kept per
+// pixel as dot(dL/dC, C_out) minus a running dot(dL/dC, prefix).  Each lane sums
+// its pixels in registers; the nine per-splat gradients are reduced across the
+// wave by reduce-scatter (lane-half and row swaps, then DPP row sums; skipped
+// when no lane blended the splat) and added to HBM with one global atomic per
+// (splat, component, wave).  Constant factors of the conic and centre
+// gradients are applied once per splat after the reduction.  Each wave stops
+// at its own last contributor.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -26,11 +30,13 @@ struct __align__(16) LSplat {
     float ui, uf, vi, vf;
     float qa, qb, qc, op;
     float cr, cg, cb;
-    uint32_t pad[3];
+    uint32_t gid;                 // splat id (used by the backward)
+    uint32_t pad[2];
 };
 static_assert(sizeof(LSplat) == 64, "LDS splat is 64 bytes");
 
-__device__ __forceinline__ void stage_splat(const Rec& r, LSplat& s) {
+__device__ __forceinline__ void stage_splat(const Rec& r, uint32_t gid, LSplat& s) {
+    s.gid = gid;
     s.rx = r.d.x; s.ry = r.d.y;
     s.ui = r.c.y; s.uf = r.a.x; s.vi = r.c.z; s.vf = r.a.y;
     s.qa = r.a.z; s.qb = r.a.w; s.qc = r.b.x; s.op = r.b.y;
@@ -77,22 +83,23 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     recs += (size_t)view * N;
     float* __restrict__ image = images.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
-    int px[PPL], py[PPL];
-    float pxc[PPL], pyc[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
+    // all pixels of a lane share one column (NT is a multiple of B)
+    const int px = tx * B + (int)threadIdx.x % B;
+    const float pxc = (float)px + 0.5f;
+    int py[PPL];
+    float pyc[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
     uint32_t last[PPL];
     bool done[PPL];
     bool lane_done = true;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int p = (int)threadIdx.x + k * NT;
-        px[k] = tx * B + p % B;
         py[k] = ty * B + p / B;
-        pxc[k] = (float)px[k] + 0.5f;
         pyc[k] = (float)py[k] + 0.5f;
         T[k] = 1.0f;
         cr[k] = cg[k] = cb[k] = 0.f;
         last[k] = 0u;
-        done[k] = !(px[k] < V.W && py[k] < V.H);
+        done[k] = !(px < V.W && py[k] < V.H);
         lane_done = lane_done && done[k];
     }
     const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
@@ -101,18 +108,22 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     for (int64_t base = start; base < end; base += CHUNK) {
         if (__syncthreads_count(lane_done) == NT) break;
         const int cnt = (int)min((int64_t)CHUNK, end - base);
-        for (int k = threadIdx.x; k < cnt; k += NT) stage_splat(recs[ids[base + k]], s_sp[k]);
+        for (int k = threadIdx.x; k < cnt; k += NT) {
+            const uint32_t gid = ids[base + k];
+            stage_splat(recs[gid], gid, s_sp[k]);
+        }
         __syncthreads();
         if (!lane_done) {
             const uint32_t rel0 = (uint32_t)(base - start);
             for (int j = 0; j < cnt; ++j) {
                 const Splat s = to_splat(s_sp[j]);
+                const ColTerm c = eval_col(s, px, pxc);
                 bool all = true;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    float dx, dy, G, alpha;
+                    float dy, G, alpha;
                     bool clamped;
-                    const bool ok = eval_splat(s, px[k], py[k], pxc[k], pyc[k], dx, dy, G, alpha, clamped) && !done[k];
+                    const bool ok = eval_pix(s, c, py[k], pyc[k], dy, G, alpha, clamped) && !done[k];
                     const float Tn = next_T(T[k], alpha);
                     const bool stop = ok && Tn < kMinT;
                     const bool bl = ok && !stop;
@@ -123,7 +134,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
                     T[k] = bl ? Tn : T[k];
                     last[k] = bl ? rel0 + (uint32_t)j + 1u : last[k];
                     if (STATS) {
-                        n_eval += (!done[k] && in_square(s, px[k], py[k])) ? 1u : 0u;
+                        n_eval += (!done[k] && in_square(s, px, py[k])) ? 1u : 0u;
                         n_blend += bl ? 1u : 0u;
                     }
                     done[k] = done[k] || stop;
@@ -139,8 +150,8 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     const size_t HW = (size_t)V.W * V.H;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
-        if (px[k] < V.W && py[k] < V.H) {
-            const size_t p = (size_t)py[k] * V.W + px[k];
+        if (px < V.W && py[k] < V.H) {
+            const size_t p = (size_t)py[k] * V.W + px;
             const float o0 = __builtin_fmaf(T[k], V.bg[0], cr[k]), o1 = __builtin_fmaf(T[k], V.bg[1], cg[k]),
                         o2 = __builtin_fmaf(T[k], V.bg[2], cb[k]);
             image[p] = o0;
@@ -160,17 +171,40 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     }
 }
 
-// Sum over the 64 lanes of a wave, complete in lane 63: quad xor1, quad xor2,
-// half-row mirror and row mirror give every lane its row's sum, then two row
-// broadcasts fold rows 0-2 into row 3.
-__device__ __forceinline__ float wave_sum_to_63(float v) {
+// Cross-lane building blocks of the backward's reduction (gfx950).
+// swap32_add(a, b): lanes 0-31 get a[l] + a[l + 32], lanes 32-63 get b[l - 32] + b[l].
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// swap16_add(a, b): with rows of 16 lanes, row 0 gets a.r0 + a.r1, row 1 b.r0 + b.r1,
+// row 2 a.r2 + a.r3, row 3 b.r2 + b.r3 (lane by lane within the rows).
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// Sum over the 16 lanes of each row, in every lane of the row: quad xor 1,
+// quad xor 2, half-row mirror, row mirror.
+__device__ __forceinline__ float row_sum(float v) {
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
     return v;
+}
+
+// Wave sums of nine values by reduce-scatter: after two swap levels three
+// registers hold, per 16-lane row, one value summed over 4 lanes; a row sum
+// completes them.  Result layout (rows 0..3):
+//   h0: e0, e2, e1, e3    h1: e4, e6, e5, e7    h2: e8 (row 0 only)
+__device__ __forceinline__ void wave_sum9(float e0, float e1, float e2, float e3, float e4, float e5, float e6,
+                                          float e7, float e8, float& h0, float& h1, float& h2) {
+    const float f0 = swap32_add(e0, e1), f1 = swap32_add(e2, e3), f2 = swap32_add(e4, e5), f3 = swap32_add(e6, e7);
+    const float f4 = swap32_add(e8, 0.0f);
+    const float g0 = swap16_add(f0, f1), g1 = swap16_add(f2, f3), g2 = swap16_add(f4, 0.0f);
+    h0 = row_sum(g0);
+    h1 = row_sum(g1);
+    h2 = row_sum(g2);
 }
 
 // Largest value over the wave.
@@ -191,7 +225,6 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     unsigned long long* counters) {
     constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
-    __shared__ uint32_t s_gid[CHUNK];
     __shared__ uint32_t s_max;
     const int gt = views[v0].tile_base + (int)blockIdx.x;
     const int view = find_view_of_tile(views, v0, v1, gt);
@@ -204,30 +237,31 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
     const size_t HW = (size_t)V.W * V.H;
     const int lane = __lane_id();
-    int px[PPL], py[PPL];
-    float pxc[PPL], pyc[PPL], G0[PPL], G1[PPL], G2[PPL], C0[PPL], C1[PPL], C2[PPL];
-    float T[PPL], pr[PPL], pg[PPL], pb[PPL];
+    // all pixels of a lane share one column (NT is a multiple of B)
+    const int px = tx * B + (int)threadIdx.x % B;
+    const float pxc = (float)px + 0.5f;
+    int py[PPL];
+    float pyc[PPL], G0[PPL], G1[PPL], G2[PPL], D[PPL], P[PPL], T[PPL];
     uint32_t nc[PPL];
     uint32_t lane_nc = 0;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int p = (int)threadIdx.x + k * NT;
-        px[k] = tx * B + p % B;
         py[k] = ty * B + p / B;
-        pxc[k] = (float)px[k] + 0.5f;
         pyc[k] = (float)py[k] + 0.5f;
-        G0[k] = G1[k] = G2[k] = C0[k] = C1[k] = C2[k] = 0.f;
+        G0[k] = G1[k] = G2[k] = D[k] = 0.f;
         nc[k] = 0u;
-        if (px[k] < V.W && py[k] < V.H) {
-            const size_t q = (size_t)py[k] * V.W + px[k];
+        if (px < V.W && py[k] < V.H) {
+            const size_t q = (size_t)py[k] * V.W + px;
             G0[k] = dl[q]; G1[k] = dl[HW + q]; G2[k] = dl[2 * HW + q];
-            C0[k] = Cout[3 * (size_t)V.pix_base + q];
-            C1[k] = Cout[3 * (size_t)V.pix_base + HW + q];
-            C2[k] = Cout[3 * (size_t)V.pix_base + 2 * HW + q];
+            const float c0 = Cout[3 * (size_t)V.pix_base + q];
+            const float c1 = Cout[3 * (size_t)V.pix_base + HW + q];
+            const float c2 = Cout[3 * (size_t)V.pix_base + 2 * HW + q];
+            D[k] = G0[k] * c0 + G1[k] * c1 + G2[k] * c2;  // dot(dL/dC, C_out)
             nc[k] = ncontrib[(size_t)V.pix_base + q];
         }
         T[k] = 1.0f;
-        pr[k] = pg[k] = pb[k] = 0.f;
+        P[k] = 0.f;  // dot(dL/dC, colour blended so far)
         lane_nc = max(lane_nc, nc[k]);
     }
     if (threadIdx.x == 0) s_max = 0u;
@@ -235,17 +269,26 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     if (lane_nc) atomicMax(&s_max, lane_nc);
     __syncthreads();
     const int64_t end = start + (int64_t)s_max;
-    const uint32_t wave_nc = wave_max_u32(lane_nc);
+    const uint32_t wave_nc = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_nc));
     const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f, a8 = 0.f;
+    // after wave_sum9, lanes 0, 16, 32, 48 hold (in h0 and h1) the components
+    // 0 2 1 3 and 4 6 5 7 of g2, lane 0 (in h2) component 8; their constant
+    // factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1
+    const int row = lane >> 4;
+    const bool lead = (lane & 15) == 0;
+    const int comp0 = ((row & 1) << 1) | (row >> 1);
+    const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
+    const float fac1 = comp0 == 0 ? -0.5f : 1.0f;
+    float* const g2c0 = g2 + (size_t)comp0 * N;
+    float* const g2c1 = g2 + (size_t)(4 + comp0) * N;
+    float* const g2c8 = g2 + (size_t)8 * N;
     for (int64_t base = start; base < end; base += CHUNK) {
         const int cnt = (int)min((int64_t)CHUNK, end - base);
         __syncthreads();  // the previous chunk's LDS is no longer read
         for (int k = threadIdx.x; k < cnt; k += NT) {
             const uint32_t gid = ids[base + k];
-            s_gid[k] = gid;
-            stage_splat(recs[gid], s_sp[k]);
+            stage_splat(recs[gid], gid, s_sp[k]);
         }
         __syncthreads();
         const uint32_t rel0 = (uint32_t)(base - start);
@@ -253,88 +296,57 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
         for (int j = 0; j < jend; ++j) {
             const Splat s = to_splat(s_sp[j]);
+            const ColTerm c = eval_col(s, px, pxc);
+            const float twoqadx = 2.0f * c.qadx, qbdx = s.qb * c.dx, dx2 = c.dx * c.dx, twoqc = 2.0f * s.qc;
+            // per-splat sums of this lane's pixels; conic and centre terms without
+            // their constant factors (applied at the flush)
             float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f, e4 = 0.f, e5 = 0.f, e6 = 0.f, e7 = 0.f, e8 = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                float dx, dy, Gk, alpha;
+                float dy, Gk, alpha;
                 bool clamped;
                 const bool live = rel0 + (uint32_t)j < nc[k];
-                const bool ok = live && eval_splat(s, px[k], py[k], pxc[k], pyc[k], dx, dy, Gk, alpha, clamped);
+                const bool pass = eval_pix(s, c, py[k], pyc[k], dy, Gk, alpha, clamped);
+                const bool ok = pass && live;
                 if (STATS) {
-                    n_eval += (live && in_square(s, px[k], py[k])) ? 1u : 0u;
+                    n_eval += (live && in_square(s, px, py[k])) ? 1u : 0u;
                     n_blend += ok ? 1u : 0u;
                 }
                 any = any || ok;
                 const float w = ok ? alpha * T[k] : 0.0f;
-                pr[k] = __builtin_fmaf(s.cr, w, pr[k]);
-                pg[k] = __builtin_fmaf(s.cg, w, pg[k]);
-                pb[k] = __builtin_fmaf(s.cb, w, pb[k]);
-                // colour behind this splat: C_out - prefix (includes T_final * bg)
-                const float oma = 1.0f - alpha;
-                const float ioma = 1.0f / oma;
-                const float Tk = T[k];
-                const float da = G0[k] * (s.cr * Tk - (C0[k] - pr[k]) * ioma) +
-                                 G1[k] * (s.cg * Tk - (C1[k] - pg[k]) * ioma) +
-                                 G2[k] * (s.cb * Tk - (C2[k] - pb[k]) * ioma);
-                e6 += G0[k] * w;
-                e7 += G1[k] * w;
-                e8 += G2[k] * w;
-                const bool soft = ok && !clamped;
-                const float dpn = soft ? da * alpha : 0.0f;  // dL/dpower (natural log domain)
-                e5 += soft ? da * Gk : 0.0f;
-                // power = -1/2 (Q00 dx^2 + 2 Q01 dx dy + Q11 dy^2); (qa, qb, qc) = log2(e) * (-Q00/2, -Q01, -Q11/2)
-                const float kk = dpn * kinv;
-                const float ddx = soft ? dx : 0.0f, ddy = soft ? dy : 0.0f;
-                e0 += kk * (2.0f * s.qa * ddx + s.qb * ddy);  // dL/du
-                e1 += kk * (s.qb * ddx + 2.0f * s.qc * ddy);  // dL/dv
-                e2 += -0.5f * dpn * ddx * ddx;                // dL/dQ00
-                e3 += -dpn * ddx * ddy;                       // dL/dQ01
-                e4 += -0.5f * dpn * ddy * ddy;                // dL/dQ11
-                T[k] = ok ? next_T(Tk, alpha) : Tk;
+                const float gc = G0[k] * s.cr + G1[k] * s.cg + G2[k] * s.cb;
+                P[k] = __builtin_fmaf(w, gc, P[k]);
+                // dL/dalpha = T dot(dL/dC, c) - dot(dL/dC, colour behind) / (1 - alpha),
+                // colour behind = C_out - prefix (includes T_final * bg)
+                const float ioma = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float da = __builtin_fmaf(T[k], gc, -((D[k] - P[k]) * ioma));
+                e6 = __builtin_fmaf(G0[k], w, e6);
+                e7 = __builtin_fmaf(G1[k], w, e7);
+                e8 = __builtin_fmaf(G2[k], w, e8);
+                const float das = (ok && !clamped) ? da : 0.0f;  // no gradient through the 0.99 clamp
+                e5 = __builtin_fmaf(das, Gk, e5);
+                const float dpn = das * alpha;  // dL/dpower (natural log domain)
+                e0 = __builtin_fmaf(dpn, __builtin_fmaf(s.qb, dy, twoqadx), e0);
+                e1 = __builtin_fmaf(dpn, __builtin_fmaf(twoqc, dy, qbdx), e1);
+                e2 = __builtin_fmaf(dpn, dx2, e2);
+                const float dpy = dpn * dy;
+                e3 = __builtin_fmaf(dpy, c.dx, e3);
+                e4 = __builtin_fmaf(dpy, dy, e4);
+                T[k] = ok ? next_T(T[k], alpha) : T[k];
             }
             if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
-                // The reductions and the reads of lane 63 must run with the
-                // whole wave active: the empty asm statement consumes the nine
-                // wave sums here, so they cannot be moved into the lane-divergent
-                // selects below that park them in lane j % 64.
-                const int slot = j & 63;
-                const int r0 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e0)), 63);
-                const int r1 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e1)), 63);
-                const int r2 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e2)), 63);
-                const int r3 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e3)), 63);
-                const int r4 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e4)), 63);
-                const int r5 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e5)), 63);
-                const int r6 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e6)), 63);
-                const int r7 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e7)), 63);
-                const int r8 = __builtin_amdgcn_readlane(__float_as_int(wave_sum_to_63(e8)), 63);
-                asm volatile("" ::"s"(r0), "s"(r1), "s"(r2), "s"(r3), "s"(r4), "s"(r5), "s"(r6), "s"(r7), "s"(r8));
-                const bool mine = lane == slot;
-                a0 = mine ? __int_as_float(r0) : a0;
-                a1 = mine ? __int_as_float(r1) : a1;
-                a2 = mine ? __int_as_float(r2) : a2;
-                a3 = mine ? __int_as_float(r3) : a3;
-                a4 = mine ? __int_as_float(r4) : a4;
-                a5 = mine ? __int_as_float(r5) : a5;
-                a6 = mine ? __int_as_float(r6) : a6;
-                a7 = mine ? __int_as_float(r7) : a7;
-                a8 = mine ? __int_as_float(r8) : a8;
-            }
-            if ((j & 63) == 63 || j == jend - 1) {  // flush the group of up to 64 splats
-                const int j0 = j & ~63;
-                if (lane <= (j & 63)) {
-                    const uint32_t gid = s_gid[j0 + lane];
-                    if (a0 != 0.f) atomicAdd(&g2[(size_t)0 * N + gid], a0);
-                    if (a1 != 0.f) atomicAdd(&g2[(size_t)1 * N + gid], a1);
-                    if (a2 != 0.f) atomicAdd(&g2[(size_t)2 * N + gid], a2);
-                    if (a3 != 0.f) atomicAdd(&g2[(size_t)3 * N + gid], a3);
-                    if (a4 != 0.f) atomicAdd(&g2[(size_t)4 * N + gid], a4);
-                    if (a5 != 0.f) atomicAdd(&g2[(size_t)5 * N + gid], a5);
-                    if (a6 != 0.f) atomicAdd(&g2[(size_t)6 * N + gid], a6);
-                    if (a7 != 0.f) atomicAdd(&g2[(size_t)7 * N + gid], a7);
-                    if (a8 != 0.f) atomicAdd(&g2[(size_t)8 * N + gid], a8);
+                float h0, h1, h2;
+                wave_sum9(e0, e1, e2, e3, e4, e5, e6, e7, e8, h0, h1, h2);
+                // the cross-lane operations need the whole wave: consume their
+                // results here, before the lane-divergent atomics below
+                asm volatile("" ::"v"(h0), "v"(h1), "v"(h2));
+                if (lead) {
+                    const uint32_t gid = s_sp[j].gid;
+                    atomicAdd(&g2c0[gid], h0 * fac0);
+                    atomicAdd(&g2c1[gid], h1 * fac1);
+                    if (row == 0) atomicAdd(&g2c8[gid], h2);
                 }
-                a0 = a1 = a2 = a3 = a4 = a5 = a6 = a7 = a8 = 0.f;
             }
         }
     }

@@ -63,7 +63,7 @@ class FwdHandle:
 # Launch configuration of the training step (tile edge in pixels, splats staged
 # per LDS chunk); images do not depend on either.
 DEFAULT_TILE = 16
-DEFAULT_CHUNK = 128
+DEFAULT_CHUNK = 64
 
 
 class Rasterizer:
