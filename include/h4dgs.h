@@ -92,17 +92,22 @@ typedef struct {
 /* Launch configuration.  tile: tile edge in pixels (8, 16 or 32); chunk:
  * list entries staged in LDS per round of the blending kernels (64, 128, 256
  * or 512); batched: 0 = views processed one after another,
- * 1 = all views of a call in one pass per stage; pair_capacity: number of
- * tile-list slots the workspace holds, summed over the call's views (a tile's
- * slots number the splats touching its 64-pixel super-tile, so this is a
- * little more than the number of (Gaussian, tile) pairs).
- * Images do not depend on tile or chunk (a pixel's contributors are fixed by
- * its own square test), so these are pure performance knobs. */
+ * 1 = all views of a call in one pass per stage; cull: 0 = a tile's list holds
+ * every splat whose pixel square overlaps the tile (Alg. 1), 1 = in addition a
+ * splat is left out of tiles in which no pixel centre can reach
+ * alpha >= 1/255 (tested in FP64 with a margin far above the FP32 evaluation
+ * error, so no pixel's blending changes); pair_capacity: number of tile-list
+ * slots the workspace holds, summed over the call's views (a tile's slots
+ * number the splats touching its super-tile of 4 x 4 tiles (2 x 2 for
+ * 32-pixel tiles), so this exceeds the number of (Gaussian, tile) pairs).
+ * Images do not depend on tile, chunk or cull (a pixel's contributors are
+ * fixed by its own square and alpha tests), so these are pure performance
+ * knobs. */
 typedef struct {
     int32_t tile;
     int32_t chunk;
     int32_t batched;
-    int32_t reserved;
+    int32_t cull;
     int64_t pair_capacity;
 } h4d_config;
 

@@ -55,7 +55,7 @@ class View(C.Structure):
 
 
 class Config(C.Structure):
-    _fields_ = [("tile", C.c_int32), ("chunk", C.c_int32), ("batched", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("tile", C.c_int32), ("chunk", C.c_int32), ("batched", C.c_int32), ("cull", C.c_int32),
                 ("pair_capacity", C.c_int64)]
 
 

@@ -97,8 +97,6 @@ struct Carve {
     }
 };
 
-// Super-tiles are 64 x 64 pixels: S x S tiles.
-inline int super_factor(int tile) { return kSuperPixels / tile; }
 
 struct ViewGeom {
     int tiles_x, tiles_y, tile_base;
@@ -230,6 +228,7 @@ h4d_status check_config(h4d_ctx* c, const h4d_config* cfg) {
     if (cfg->pair_capacity > (int64_t)0xFFFFFFFFll * 4)
         return fail(c, H4D_ERR_INVALID_ARG, "pair_capacity too large");
     if (cfg->batched != 0 && cfg->batched != 1) return fail(c, H4D_ERR_INVALID_ARG, "batched must be 0 or 1");
+    if (cfg->cull != 0 && cfg->cull != 1) return fail(c, H4D_ERR_INVALID_ARG, "cull must be 0 or 1");
     return H4D_OK;
 }
 
@@ -304,8 +303,8 @@ unsigned long long* stat_counters(h4d_ctx* c, void* state, const Layout& L) {
     return c->stats ? reinterpret_cast<unsigned long long*>(&at<Status>(state, L.st_status)->pad[0]) : nullptr;
 }
 
-void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chunk, void* state, void* scratch,
-                   const PtrTable& images, hipStream_t st) {
+void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chunk, int cull, void* state,
+                   void* scratch, const PtrTable& images, hipStream_t st) {
     const int N = L.N;
     const int nv = P.v1 - P.v0;
     const int n = nv * N;  // depth-ordered Gaussians of the pass, view-major
@@ -371,11 +370,11 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         launch_tile_sizes(cranges, P.tiles, vp, P.v0, P.v1, S, eff_c, tsizes, st);
         launch_scan_u32_u64(tsizes, nullptr, P.tiles, toff, at<unsigned long long>(scratch, L.sc_tpart), st);
         launch_finalize_regions(toff, P.tiles, pair_base, P.v0, P.v1, L.cap, status, eff_c, eff_r, st);
-        // the buffer pair the sort did not end in receives (id, local rectangle) per coarse entry
+        // the buffer pair the sort did not end in receives (id, tile mask) per coarse entry
         uint32_t* cgid = (kin == pk) ? pk2 : pk;
-        uint32_t* crect = (kin == pk) ? pv2 : pv;
-        launch_coarse_gather(kin, vin, rect, dv, N, vp, P.v0, S, eff_c, cgid, crect, st);
-        launch_tile_write(cgid, crect, cranges, toff, pair_base + P.v0, eff_r, P.tiles, vp, P.v0, P.v1, S, ids,
+        uint32_t* cmask = (kin == pk) ? pv2 : pv;
+        launch_coarse_gather(kin, vin, rect, dv, N, recs, vp, P.v0, tile, S, cull, eff_c, cgid, cmask, st);
+        launch_tile_write(cgid, cmask, cranges, toff, pair_base + P.v0, eff_r, P.tiles, vp, P.v0, P.v1, S, ids,
                           at<int64_t>(state, L.st_ranges), st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
@@ -456,7 +455,7 @@ h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
             launch_preprocess(p3, p4, vp, P.v0, P.v1 - P.v0, at<Rec>(state, L.st_recs),
                               at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
         }
-        bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, state, scratch, tab, st);
+        bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st);
     }
     return hip_check(ctx, "render_fwd");
 }
@@ -563,7 +562,7 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     PtrTable tab;
     std::memset(&tab, 0, sizeof(tab));
     tab.p[0] = image;
-    bin_and_blend(ctx, L, L.pass(0), cfg->tile, cfg->chunk, state, scratch, tab, st);
+    bin_and_blend(ctx, L, L.pass(0), cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st);
     const size_t hw = (size_t)width * height;
     if (T_final) (void)hipMemcpyAsync(T_final, at<float>(state, L.st_T), 4 * hw, hipMemcpyDeviceToDevice, st);
     if (sorted_ids && L.cap > 0)
@@ -665,8 +664,11 @@ h4d_status h4dgs_l1_loss_grad(h4d_ctx* ctx, int32_t n_views, const float* const*
     h4d_status s;
     if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
     if (!images || !targets || !dl_dimages) return fail(ctx, H4D_ERR_INVALID_ARG, "null image table");
-    for (int v = 0; v < n_views; ++v)
+    for (int v = 0; v < n_views; ++v) {
         if (!images[v] || !targets[v] || !dl_dimages[v]) return fail(ctx, H4D_ERR_INVALID_ARG, "null image %d", v);
+        if (((uintptr_t)images[v] | (uintptr_t)targets[v] | (uintptr_t)dl_dimages[v]) % 16 != 0)
+            return fail(ctx, H4D_ERR_INVALID_ARG, "image %d: buffers must be 16-byte aligned", v);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     StageScope sc(ctx, st, H4D_STAGE_LOSS);
     if (loss) launch_fill_f32(loss, 1, 0.f, st);  // a fill kernel: safe under graph capture

@@ -39,8 +39,10 @@ struct ViewParams {
     int32_t pad;
 };
 
-// Pixels per super-tile edge (binning groups tiles into 64 x 64 pixel blocks).
-constexpr int kSuperPixels = 64;
+// Tiles per super-tile edge: binning groups tiles into S x S blocks (S = 4 for
+// 8- and 16-pixel tiles, 2 for 32-pixel tiles), so that a super-tile holds at
+// most 16 tiles and a splat's tiles within it fit a 16-bit mask.
+__host__ __device__ constexpr int super_factor(int tile) { return tile == 32 ? 2 : 4; }
 
 // The view of global tile `gt` among views [v0, v1) (tile ids ascend with the view).
 __device__ __forceinline__ int find_view_of_tile(const ViewParams* views, int v0, int v1, int gt) {

@@ -67,10 +67,14 @@ void launch_tile_sizes(const int64_t* cranges, int tiles, const ViewParams* view
 void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int v0,
                              int v1, uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
                              unsigned long long* eff_regions, hipStream_t st);
+// Per coarse entry: the splat id and the 16-bit mask of the super-tile's tiles
+// (bit ly * S + lx) that its pixel square overlaps, less (cull = 1) the tiles in
+// which no pixel centre can reach alpha >= 1/255.
 void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S,
-                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* crect, hipStream_t st);
-void launch_tile_write(const uint32_t* cgid, const uint32_t* crect, const int64_t* cranges,
+                          const uint32_t* sorted_gid, int N, const Rec* recs, const ViewParams* views, int v0,
+                          int tile, int S, int cull, const unsigned long long* eff_count, uint32_t* cgid,
+                          uint32_t* cmask, hipStream_t st);
+void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
                        const unsigned long long* region_off, const unsigned long long* base_ptr,
                        const unsigned long long* eff_regions, int tiles, const ViewParams* views, int v0, int v1,
                        int S, uint32_t* ids, int64_t* ranges, hipStream_t st);

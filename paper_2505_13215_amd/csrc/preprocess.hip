@@ -593,7 +593,7 @@ __global__ void k_write_views(ViewTableIn in, ViewParams* out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int tile_base = 0, super_base = 0;
     long long pix_base = 0;
-    const int S = kSuperPixels / in.tile;
+    const int S = super_factor(in.tile);
     for (int v = 0; v < in.n; ++v) {
         const ViewIn& s = in.v[v];
         ViewParams p;

@@ -423,20 +423,49 @@ __global__ void k_finalize_regions(const unsigned long long* region_off, int til
     }
 }
 
+// Largest value of the log2-domain exponent p2(d) = qa dx^2 + qb dx dy + qc dy^2
+// (negative definite) over the rectangle [X0, X1] x [Y0, Y1] of offsets d = p - mu:
+// 0 if the rectangle holds mu, else the best of the four edges (each a 1-D
+// concave quadratic maximised at a clamped stationary point).
+__device__ inline double max_p2_rect(double qa, double qb, double qc, double X0, double X1, double Y0, double Y1) {
+    if (X0 <= 0.0 && 0.0 <= X1 && Y0 <= 0.0 && 0.0 <= Y1) return 0.0;
+    double best = -INFINITY;
+    const double xs[2] = {X0, X1}, ys[2] = {Y0, Y1};
+    for (int e = 0; e < 2; ++e) {
+        const double X = xs[e];
+        const double t = fmin(fmax(-qb * X / (2.0 * qc), Y0), Y1);
+        best = fmax(best, qa * X * X + qb * X * t + qc * t * t);
+        const double Y = ys[e];
+        const double u = fmin(fmax(-qb * Y / (2.0 * qa), X0), X1);
+        best = fmax(best, qa * u * u + qb * u * Y + qc * Y * Y);
+    }
+    return best;
+}
+
+// Margin (log2 units) between the FP64 tile test and the FP32 per-pixel test:
+// the FP32 exponent of a pixel is within about 1e-5 of its exact value, so a
+// tile whose best exact exponent is this far below the threshold has no pixel
+// with alpha >= 1/255.
+constexpr double kCullMargin = 1e-3;
+
 // After the coarse sort: per coarse entry k (super-tile st, depth rank j) the
-// splat id and its tile rectangle clipped to the super-tile, in super-tile-local
-// coordinates (4 bits each), so that the per-tile pass streams 8 bytes per entry.
+// splat id and the mask of the super-tile's tiles (bit ly * S + lx) its pixel
+// square overlaps; with cull, tiles whose pixel centres (inside the square) all
+// stay below alpha = 1/255 are cleared.  The per-tile pass then streams 8
+// bytes per entry.
 __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ ckeys,
                                                        const uint32_t* __restrict__ cvals,
                                                        const uint64_t* __restrict__ rect_sorted,
                                                        const uint32_t* __restrict__ sorted_gid, int N,
-                                                       const ViewParams* __restrict__ views, int v0, int S,
-                                                       const unsigned long long* eff_count, uint32_t* __restrict__ cgid,
-                                                       uint32_t* __restrict__ crect) {
+                                                       const Rec* __restrict__ recs,
+                                                       const ViewParams* __restrict__ views, int v0, int tile, int S,
+                                                       int cull, const unsigned long long* eff_count,
+                                                       uint32_t* __restrict__ cgid, uint32_t* __restrict__ cmask) {
     const uint64_t n = *eff_count;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t j = cvals[k];
-        const ViewParams& V = views[v0 + (int)(j / (uint32_t)N)];
+        const int view = v0 + (int)(j / (uint32_t)N);
+        const ViewParams& V = views[view];
         const uint32_t st = ckeys[k] - (uint32_t)(V.super_base - views[v0].super_base);
         const uint64_t r = rect_sorted[j];
         const uint32_t SX = (uint32_t)V.sx;
@@ -445,8 +474,39 @@ __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restric
         const uint32_t y0 = (uint32_t)((r >> 32) & 0xFFFFu), y1 = (uint32_t)(r >> 48);
         const uint32_t lx0 = max(x0, bx) - bx, lx1 = min(x1, bx + (uint32_t)S - 1u) - bx;
         const uint32_t ly0 = max(y0, by) - by, ly1 = min(y1, by + (uint32_t)S - 1u) - by;
-        cgid[k] = sorted_gid[j];
-        crect[k] = lx0 | (lx1 << 4) | (ly0 << 8) | (ly1 << 12);
+        const uint32_t gid = sorted_gid[j];
+        uint32_t mask = 0u;
+        if (!cull) {
+            for (uint32_t ly = ly0; ly <= ly1; ++ly)
+                for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
+        } else {
+            const Rec rec = recs[(size_t)view * N + gid];
+            const double qa = rec.a.z, qb = rec.a.w, qc = rec.b.x, op = rec.b.y;
+            const double mu = (double)rec.c.y + (double)rec.a.x, mv = (double)rec.c.z + (double)rec.a.y;
+            const int px0 = (int)(rec.d.x & 0xFFFFu), px1 = (int)(rec.d.x >> 16);
+            const int py0 = (int)(rec.d.y & 0xFFFFu), py1 = (int)(rec.d.y >> 16);
+            // usable only for a negative definite form and a positive opacity;
+            // otherwise keep every overlapped tile
+            const bool ok = qa < 0.0 && qc < 0.0 && 4.0 * qa * qc - qb * qb > 0.0 && op > 0.0;
+            const double thr = ok ? -log2(255.0 * op) - kCullMargin : 0.0;
+            for (uint32_t ly = ly0; ly <= ly1; ++ly) {
+                const int ty = (int)(by + ly);
+                const int ya = max(ty * tile, py0), yb = min(ty * tile + tile - 1, py1);
+                for (uint32_t lx = lx0; lx <= lx1; ++lx) {
+                    const int tx = (int)(bx + lx);
+                    const int xa = max(tx * tile, px0), xb = min(tx * tile + tile - 1, px1);
+                    bool keep = true;
+                    if (ok) {
+                        const double m = max_p2_rect(qa, qb, qc, xa + 0.5 - mu, xb + 0.5 - mu, ya + 0.5 - mv,
+                                                     yb + 0.5 - mv);
+                        keep = m >= thr;
+                    }
+                    if (keep) mask |= 1u << (ly * (uint32_t)S + lx);
+                }
+            }
+        }
+        cgid[k] = gid;
+        cmask[k] = mask;
     }
 }
 
@@ -455,7 +515,7 @@ __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restric
 // round streams 1024 entries (4 per thread, striped) and orders them with wave
 // ballots and one barrier.
 __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__ cgid,
-                                                    const uint32_t* __restrict__ crect,
+                                                    const uint32_t* __restrict__ cmask,
                                                     const int64_t* __restrict__ cranges,
                                                     const unsigned long long* __restrict__ region_off,
                                                     const unsigned long long* base_ptr,
@@ -467,7 +527,7 @@ __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__
     const int t = blockIdx.x;
     const TileLoc loc = locate_tile(views, v0, v1, t, S);
     const int st = loc.st;
-    const uint32_t lx = loc.tx % (uint32_t)S, ly = loc.ty % (uint32_t)S;
+    const uint32_t bit = (loc.ty % (uint32_t)S) * (uint32_t)S + loc.tx % (uint32_t)S;
     const int64_t cs = cranges[2 * st], ce = cranges[2 * st + 1];
     const uint64_t out = (uint64_t)*base_ptr + (uint64_t)region_off[t];
     const int tid = threadIdx.x, w = tid >> 6;
@@ -483,8 +543,7 @@ __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__
             ov[r] = false;
             gid[r] = 0;
             if (k < ce) {
-                const uint32_t rc = crect[k];
-                ov[r] = lx >= (rc & 15u) && lx <= ((rc >> 4) & 15u) && ly >= ((rc >> 8) & 15u) && ly <= (rc >> 12);
+                ov[r] = (cmask[k] >> bit) & 1u;
                 if (ov[r]) gid[r] = cgid[k];
             }
             bal[r] = __ballot(ov[r]);
@@ -560,17 +619,18 @@ void launch_finalize_regions(const unsigned long long* region_off, int tiles, un
                                         eff_regions);
 }
 void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S,
-                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* crect, hipStream_t st) {
-    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, N, views, v0, S, eff_count, cgid,
-                                          crect);
+                          const uint32_t* sorted_gid, int N, const Rec* recs, const ViewParams* views, int v0,
+                          int tile, int S, int cull, const unsigned long long* eff_count, uint32_t* cgid,
+                          uint32_t* cmask, hipStream_t st) {
+    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, N, recs, views, v0, tile, S, cull,
+                                          eff_count, cgid, cmask);
 }
-void launch_tile_write(const uint32_t* cgid, const uint32_t* crect, const int64_t* cranges,
+void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
                        const unsigned long long* region_off, const unsigned long long* base_ptr,
                        const unsigned long long* eff_regions, int tiles, const ViewParams* views, int v0, int v1,
                        int S, uint32_t* ids, int64_t* ranges, hipStream_t st) {
     if (tiles == 0) return;
-    k_tile_write<<<tiles, 256, 0, st>>>(cgid, crect, cranges, region_off, base_ptr, eff_regions, views, v0, v1, S, ids,
+    k_tile_write<<<tiles, 256, 0, st>>>(cgid, cmask, cranges, region_off, base_ptr, eff_regions, views, v0, v1, S, ids,
                                         ranges);
 }
 void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,

@@ -74,13 +74,15 @@ class Rasterizer:
     capacity on overflow) or "deferred" (read back by ``verify()``; a forward
     whose pairs did not fit raises there).  ``batched`` processes all views of
     a call in one launch per stage instead of one view after another (same
-    kernels, bit-identical images)."""
+    kernels, bit-identical images).  ``cull`` leaves a splat out of the tiles
+    in which no pixel can reach alpha >= 1/255 (images unchanged)."""
 
     def __init__(self, tile: int = DEFAULT_TILE, chunk: int = DEFAULT_CHUNK, pair_capacity: int = 1 << 22,
-                 growth: float = 1.3, check: str = "eager", batched: bool = False):
+                 growth: float = 1.3, check: str = "eager", batched: bool = False, cull: bool = True):
         self.ctx = L.Context()
         self.tile, self.chunk = int(tile), int(chunk)
         self.batched = bool(batched)
+        self.cull = bool(cull)
         self.capacity = int(pair_capacity)
         self.growth = float(growth)
         self.check_mode = check
@@ -92,7 +94,7 @@ class Rasterizer:
 
     # -- workspace -------------------------------------------------------------
     def config(self) -> L.Config:
-        return L.Config(self.tile, self.chunk, int(self.batched), 0, self.capacity)
+        return L.Config(self.tile, self.chunk, int(self.batched), int(self.cull), self.capacity)
 
     def sizes(self, n3: int, n4: int, views_arr, n_views: int):
         st, sc = C.c_size_t(), C.c_size_t()

@@ -104,6 +104,10 @@ def test_batched_pass_size_limit(L):
     assert b"batched" in c.L.h4dgs_last_error(c.h)
     rc = c.L.h4dgs_workspace_size(c.h, 10, 0, va, 3, C.byref(_cfg(L, batched=2)), C.byref(st), C.byref(sc))
     assert rc == L.H4D_ERR_INVALID_ARG
+    cfg = _cfg(L)
+    cfg.cull = 2
+    assert c.L.h4dgs_workspace_size(c.h, 10, 0, va, 3, C.byref(cfg), C.byref(st), C.byref(sc)) == L.H4D_ERR_INVALID_ARG
+    assert b"cull" in c.L.h4dgs_last_error(c.h)
 
 
 @pytest.mark.parametrize("tile,chunk", [(7, 256), (16, 100), (64, 256), (0, 0)])

@@ -116,18 +116,20 @@ def test_forward_is_deterministic(h4d):
     assert torch.equal(a, h2.images[0])
 
 
-def test_images_do_not_depend_on_tile_or_chunk(h4d):
+def test_images_do_not_depend_on_tile_chunk_or_cull(h4d):
     scene = sg.tiny_scene(width=111, height=70, seed=8)
     v = scene.views[0]
+    g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
     base = None
     for tile in (8, 16, 32):
-        for chunk in (128, 256, 512):
-            _, _, _, h = _render(h4d, scene, [v], tile=tile, chunk=chunk)
-            img = h.images[0].cpu()
-            if base is None:
-                base = img
-            else:
-                assert torch.equal(img, base), (tile, chunk)
+        for chunk in (64, 128, 256, 512):
+            for cull in (False, True):
+                rast = h4d.Rasterizer(tile=tile, chunk=chunk, pair_capacity=1 << 20, cull=cull)
+                img = rast.forward(g3, g4, [v]).images[0].cpu()
+                if base is None:
+                    base = img
+                else:
+                    assert torch.equal(img, base), (tile, chunk, cull)
 
 
 def test_capacity_overflow_is_detected_and_recovered(h4d):
@@ -147,7 +149,7 @@ def test_capacity_overflow_is_detected_and_recovered(h4d):
 def test_tile_lists_and_ranges_bit_exact(h4d, tile):
     W, H = 203, 131
     rec = sg.synthetic_records(3000, W, H, seed=21, max_radius=40)
-    rast = h4d.Rasterizer(tile=tile, chunk=256, pair_capacity=1 << 20)
+    rast = h4d.Rasterizer(tile=tile, chunk=256, pair_capacity=1 << 20, cull=False)
     img, T, ids, ranges = h4d.rasterize_splats(rast, rec, W, H)
     start, ref_ids = oracle.tile_lists(rec, W, H, tile)
     ids = ids.cpu().numpy()
@@ -157,6 +159,48 @@ def test_tile_lists_and_ranges_bit_exact(h4d, tile):
     for t in range(tiles):
         got = ids[rg[t, 0]:rg[t, 1]]
         assert np.array_equal(got, ref_ids[start[t]:start[t + 1]]), t
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_culled_tile_lists_drop_only_tiles_without_blending(h4d, tile):
+    """With cull, each tile's list is an order-preserving subset of the
+    square-overlap list, every dropped splat stays below alpha = 1/255 at
+    every pixel centre of the tile inside its square (checked in FP64), and the
+    image is bit-identical to the unculled one."""
+    W, H = 203, 131
+    rec = sg.synthetic_records(3000, W, H, seed=23, max_radius=40)
+    full = h4d.Rasterizer(tile=tile, chunk=128, pair_capacity=1 << 20, cull=False)
+    img0, T0, _, _ = h4d.rasterize_splats(full, rec, W, H)
+    rast = h4d.Rasterizer(tile=tile, chunk=128, pair_capacity=1 << 20, cull=True)
+    img1, T1, ids, ranges = h4d.rasterize_splats(rast, rec, W, H)
+    assert torch.equal(img0, img1) and torch.equal(T0, T1)
+    start, ref_ids = oracle.tile_lists(rec, W, H, tile)
+    ids = ids.cpu().numpy()
+    rg = ranges.cpu().numpy()
+    u, v = rec["u"].astype(np.float64), rec["v"].astype(np.float64)
+    c0, c1, c2 = (rec["conic"][i].astype(np.float64) for i in range(3))
+    op, r = rec["opacity"].astype(np.float64), rec["radius"].astype(np.int64)
+    tiles_x = (W + tile - 1) // tile
+    kept = dropped = 0
+    for t in range(len(start) - 1):
+        got = ids[rg[t, 0]:rg[t, 1]]
+        ref = ref_ids[start[t]:start[t + 1]]
+        # order-preserving subset: matching ids appear in the same relative order
+        where = {g: i for i, g in enumerate(ref)}
+        idx = np.array([where[g] for g in got], dtype=np.int64)
+        assert np.all(np.diff(idx) > 0), t
+        kept += len(got)
+        tx, ty = t % tiles_x, t // tiles_x
+        for g in np.setdiff1d(ref, got):
+            dropped += 1
+            xa = max(tx * tile, int(np.ceil(u[g] - r[g] - 0.5)), 0)
+            xb = min(tx * tile + tile - 1, int(np.floor(u[g] + r[g] - 0.5)), W - 1)
+            ya = max(ty * tile, int(np.ceil(v[g] - r[g] - 0.5)), 0)
+            yb = min(ty * tile + tile - 1, int(np.floor(v[g] + r[g] - 0.5)), H - 1)
+            X, Y = np.meshgrid(np.arange(xa, xb + 1) + 0.5 - u[g], np.arange(ya, yb + 1) + 0.5 - v[g])
+            alpha = op[g] * np.exp(-0.5 * (c0[g] * X * X + 2.0 * c1[g] * X * Y + c2[g] * Y * Y))
+            assert alpha.max() < 1.0 / 255.0, (t, g)
+    assert dropped > 0.05 * (kept + dropped), "culling removed almost nothing"
 
 
 def test_composite_on_shared_splats(h4d):
@@ -322,3 +366,34 @@ def test_adam_matches_oracle(h4d):
             upd = lrs[i] * (np.abs(mo) / c1) / (np.sqrt(vo / c2) + 1e-8)
             ptol = 4 * eps32 * np.abs(p0) + 8 * eps32 * upd + lrs[i] * mtol / c1 / (np.sqrt(vo / c2) + 1e-8)
             assert (np.abs(tp[i].cpu().numpy() - po) <= ptol + 1e-12).all()
+
+
+@pytest.mark.parametrize("sizes", [[(128, 96)], [(77, 45), (31, 17), (1, 1)], [(1352, 1014)]])
+def test_l1_loss_gradient(h4d, sizes):
+    """dL/dC = sign(C - target) / (3 W H V) exactly (sign(0) = 0, including the
+    scalar tail of an odd pixel count); the loss is the mean over views of the
+    per-view mean absolute error."""
+    rng = np.random.default_rng(len(sizes))
+    rast = h4d.Rasterizer()
+    views, imgs, tgts = [], [], []
+    for (W, H) in sizes:
+        views.append(sg.look_at((0.0, 0.0, -3.0), (0.0, 0.0, 0.0), W, H))
+        img = rng.uniform(0, 1, size=(3, H, W)).astype(np.float32)
+        tgt = rng.uniform(0, 1, size=(3, H, W)).astype(np.float32)
+        tgt.reshape(-1)[::7] = img.reshape(-1)[::7]  # ties
+        imgs.append(img)
+        tgts.append(tgt)
+    ti = [torch.as_tensor(a, device="cuda") for a in imgs]
+    tt = [torch.as_tensor(a, device="cuda") for a in tgts]
+    dl = [torch.empty_like(a) for a in ti]
+    loss = torch.full((1,), 123.0, device="cuda")
+    h4d.l1_loss_grad(rast, ti, tt, views, dl, loss)
+    torch.cuda.synchronize()
+    V = len(sizes)
+    ref_loss = 0.0
+    for a, b, d in zip(imgs, tgts, dl):
+        scale = np.float32(1.0 / (a.size * V))
+        expect = np.sign(a - b).astype(np.float32) * scale
+        assert np.array_equal(d.cpu().numpy(), expect)
+        ref_loss += np.abs(a.astype(np.float64) - b).mean() / V
+    assert abs(float(loss) - ref_loss) <= 1e-5 * ref_loss
