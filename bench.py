@@ -41,6 +41,32 @@ LR3 = dict(mean=1.6e-4, log_scale=5e-3, quat=1e-3, opacity=5e-2, sh=2.5e-3)
 LR4 = dict(mean=1.6e-4, mean_t=1.6e-4, log_scale=5e-3, quat_l=1e-3, quat_r=1e-3, opacity=5e-2, sh=2.5e-3)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_train_step_250k_1352x1014.md")
+KERNEL_SOURCES = ("paper_2505_13215_amd/csrc/composite.hip", "paper_2505_13215_amd/csrc/common.hpp")
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), or None when
+    the blending sources changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = [ln.split() for ln in fh if ln.strip().startswith("traffic ")]
+    except OSError:
+        return None
+    for parts in lines:
+        if len(parts) >= 5 and parts[1] == kernel:
+            kv = dict(p.split("=", 1) for p in parts[2:])
+            if kv.get("source_sha256") == h.hexdigest():
+                return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -265,8 +291,9 @@ def main():
     dom_ms = stages[dom]
     dom_flops = flops_bwd if dom == "blend_bwd" else flops_fwd
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    kname = f"k_composite_{dom[6:]}"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": f"k_composite_{dom[6:]}",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": recorded_traffic(kname), "kernel": kname,
                 "kernel_ms": round(dom_ms, 4), "flops_per_launch": dom_flops}
 
     # static conversion (Sec. 4.1-4.2): on the workload's sets, and on 500k all-4D

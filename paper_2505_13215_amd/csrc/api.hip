@@ -104,6 +104,19 @@ struct ViewGeom {
     int64_t pix_base;
 };
 
+int bits_for(int n) {
+    int b = 1;
+    while ((1ll << b) < (long long)n) ++b;
+    return b;
+}
+
+// LSD passes for a key of `bits` bits with digits of at most `width` bits, of
+// near-equal width.  The depth sort uses 8-bit digits (its blocks are few and a
+// wide digit's per-block cost dominates); the super-tile sort up to 11.
+constexpr int kDepthDigitBits = 8;
+int n_passes_for(int bits, int width) { return (bits + width - 1) / width; }
+int pass_bits(int bits, int width) { return (bits + n_passes_for(bits, width) - 1) / n_passes_for(bits, width); }
+
 // One pass of binning + blending covers the views [v0, v1): every view alone
 // (views processed one after another), or all views of the call (batched).
 struct Pass {
@@ -200,8 +213,10 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_pvals = f.take(4 * (size_t)L.ccap);
     L.sc_pkeys2 = f.take(4 * (size_t)L.ccap);
     L.sc_pvals2 = f.take(4 * (size_t)L.ccap);
-    L.sc_hist = f.take(4 * std::max(radix_hist_words(L.ccap, 1), radix_hist_words(n, L.per_pass)));
-    L.sc_totals = f.take(4 * 256 * (size_t)L.per_pass);
+    const int cbits = pass_bits(bits_for(max_super), kMaxRadixBits);
+    L.sc_hist = f.take(4 * std::max(radix_hist_words(L.ccap, 1, cbits),
+                                    radix_hist_words(n, L.per_pass, kDepthDigitBits)));
+    L.sc_totals = f.take(4 * (size_t)kMaxRadix * (size_t)L.per_pass);
     L.sc_cranges = f.take(16 * (size_t)max_super);
     L.sc_tsizes = f.take(4 * (size_t)max_tiles);
     L.sc_toff = f.take(8 * ((size_t)max_tiles + 1));
@@ -291,11 +306,6 @@ ViewTableIn view_table(const h4d_view* views, int V, int tile) {
     return t;
 }
 
-int bits_for(int tiles) {
-    int b = 1;
-    while ((1ll << b) < (long long)tiles) ++b;
-    return b;
-}
 
 // Binning, sorting and blending of one view whose records are in place
 // (recs_v, ntiles, dkeys, dvals filled): Alg. 1 from CreateTiles to BlendInOrder.
@@ -317,15 +327,21 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     uint32_t* hist = at<uint32_t>(scratch, L.sc_hist);
     uint32_t* totals = at<uint32_t>(scratch, L.sc_totals);
     {
-        // depth order per view: 4 stable 8-bit passes over the float32 depth bits,
+        // depth order per view: stable LSD passes over the float32 depth bits,
         // each view of the pass a segment of its own
         StageScope sc(c, st, H4D_STAGE_DEPTH_SORT);
-        for (int pass = 0; pass < 4; ++pass) {
-            const bool even = (pass % 2) == 0;
-            launch_radix_pass(even ? dk : dk2, even ? dv : dv2, even ? dk2 : dk, even ? dv2 : dv, nullptr,
-                              (uint64_t)N, (uint64_t)N, 8 * pass, 8, hist, totals, nullptr, st, nv, (uint64_t)N);
+        const int passes = n_passes_for(32, kDepthDigitBits);
+        int shift = 0;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int nb = (32 - shift + (passes - pass) - 1) / (passes - pass);
+            launch_radix_pass(dk, dv, dk2, dv2, nullptr, (uint64_t)N, (uint64_t)N, shift, nb, hist, totals, nullptr,
+                              st, nv, (uint64_t)N);
+            std::swap(dk, dk2);
+            std::swap(dv, dv2);
+            shift += nb;
         }
     }
+    // dk / dv now hold the depth-ordered keys and ids
     Status* status = at<Status>(state, L.st_status);
     unsigned long long* pair_base = at<unsigned long long>(state, L.st_pair_base);
     uint32_t* ids = at<uint32_t>(state, L.st_ids);
@@ -348,7 +364,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         launch_coarse_emit(offsets, n, N, rect, vp, P.v0, S, eff_c, pk, pv, st);
         // stable sort of the coarse entries by super-tile (depth order kept inside each)
         const int bits = bits_for(P.supers);
-        const int passes = (bits + 7) / 8;
+        const int passes = n_passes_for(bits, kMaxRadixBits);
         uint32_t* kin = pk;
         uint32_t* vin = pv;
         int shift = 0;

@@ -67,6 +67,12 @@ struct Shape {
     static constexpr int PPL = B * B / NT;           // pixels per lane
 };
 
+// Sum over the wave (measurement counters only).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += (unsigned long long)__shfl_xor((long long)v, off);
+    return v;
+}
+
 // STATS = true is a measurement-only instantiation that also counts (pixel,
 // splat) evaluations and blends into counters[0..1].
 template <int B, int CHUNK, bool STATS>
@@ -166,8 +172,11 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
         }
     }
     if (STATS) {
-        atomicAdd(&counters[0], n_eval);
-        atomicAdd(&counters[1], n_blend);
+        const unsigned long long e = wave_sum_u64(n_eval), b = wave_sum_u64(n_blend);
+        if (__lane_id() == 0) {
+            atomicAdd(&counters[0], e);
+            atomicAdd(&counters[1], b);
+        }
     }
 }
 
@@ -298,9 +307,10 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
             const Splat s = to_splat(s_sp[j]);
             const ColTerm c = eval_col(s, px, pxc);
             const float twoqadx = 2.0f * c.qadx, qbdx = s.qb * c.dx, dx2 = c.dx * c.dx, twoqc = 2.0f * s.qc;
-            // per-splat sums of this lane's pixels; conic and centre terms without
-            // their constant factors (applied at the flush)
-            float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f, e4 = 0.f, e5 = 0.f, e6 = 0.f, e7 = 0.f, e8 = 0.f;
+            // per-splat sums of this lane's pixels: dL/dopacity, dL/drgb, and the
+            // moments sum d, sum d dy, sum d dy^2 of d = dL/dpower (the lane's pixels
+            // share dx, so the centre and conic terms follow from them below)
+            float e5 = 0.f, e6 = 0.f, e7 = 0.f, e8 = 0.f, sd = 0.f, sdy = 0.f, syy = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
@@ -327,14 +337,18 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 const float das = (ok && !clamped) ? da : 0.0f;  // no gradient through the 0.99 clamp
                 e5 = __builtin_fmaf(das, Gk, e5);
                 const float dpn = das * alpha;  // dL/dpower (natural log domain)
-                e0 = __builtin_fmaf(dpn, __builtin_fmaf(s.qb, dy, twoqadx), e0);
-                e1 = __builtin_fmaf(dpn, __builtin_fmaf(twoqc, dy, qbdx), e1);
-                e2 = __builtin_fmaf(dpn, dx2, e2);
                 const float dpy = dpn * dy;
-                e3 = __builtin_fmaf(dpy, c.dx, e3);
-                e4 = __builtin_fmaf(dpy, dy, e4);
+                sd += dpn;
+                sdy += dpy;
+                syy = __builtin_fmaf(dpy, dy, syy);
                 T[k] = ok ? next_T(T[k], alpha) : T[k];
             }
+            // conic and centre terms without their constant factors (applied after
+            // the reduction): sum d (2 qa dx + qb dy), sum d (qb dx + 2 qc dy),
+            // sum d dx^2, sum d dx dy, sum d dy^2
+            const float e0 = __builtin_fmaf(sd, twoqadx, s.qb * sdy);
+            const float e1 = __builtin_fmaf(sd, qbdx, twoqc * sdy);
+            const float e2 = dx2 * sd, e3 = c.dx * sdy, e4 = syy;
             if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
                 float h0, h1, h2;
                 wave_sum9(e0, e1, e2, e3, e4, e5, e6, e7, e8, h0, h1, h2);
@@ -351,8 +365,11 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         }
     }
     if (STATS) {
-        atomicAdd(&counters[2], n_eval);
-        atomicAdd(&counters[3], n_blend);
+        const unsigned long long e = wave_sum_u64(n_eval), b = wave_sum_u64(n_blend);
+        if (__lane_id() == 0) {
+            atomicAdd(&counters[2], e);
+            atomicAdd(&counters[3], b);
+        }
     }
 }
 

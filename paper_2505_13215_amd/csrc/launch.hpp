@@ -37,13 +37,18 @@ constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kScanTile = 2048;
 
+constexpr int kMaxRadixBits = 11;
+constexpr int kMaxRadix = 1 << kMaxRadixBits;
+
 int radix_blocks(uint64_t capacity);
-size_t radix_hist_words(uint64_t capacity, int n_seg);
-// One stable LSD pass over `nbits` (<= 8) bits at `shift`, independently on
+// words of `hist` for passes of up to max_bits bits
+size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits);
+// One stable LSD pass over `nbits` (<= 11) bits at `shift`, independently on
 // n_seg segments that start seg_stride elements apart (all arrays).  Count
 // (per segment) from *dcount when dcount != null, else hcount; capacity bounds
 // the count.  vals_out index is offset by *out_offset when out_offset != null.
-// hist holds radix_hist_words(capacity, n_seg) words, totals 256 * n_seg.
+// hist holds radix_hist_words(capacity, n_seg, nbits) words, totals
+// 2^nbits * n_seg.
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,

@@ -64,7 +64,9 @@ void launch_l1_loss_grad(const float* img, const float* target, float* dl, size_
                          hipStream_t st) {
     if (n == 0) return;
     const size_t n4 = n / 4;
-    const int nb = (int)std::max<size_t>(1, std::min<size_t>(1024, (n4 + 4 * 256 - 1) / (4 * 256)));
+    // one block per compute unit at most: the blocks end with an atomic on one
+    // word, which serialises
+    const int nb = (int)std::max<size_t>(1, std::min<size_t>(256, (n4 + 4 * 256 - 1) / (4 * 256)));
     k_l1_loss_grad<<<nb, 256, 0, st>>>(img, target, dl, n, scale, loss);
 }
 

@@ -51,23 +51,47 @@ __device__ inline T block_exclusive_scan_256(T v, T* s_buf, T& total) {
 }
 
 // ---------------------------------------------------------------------------
-// Radix sort pass
+// Radix sort pass (up to 11 bits per pass)
 // ---------------------------------------------------------------------------
+constexpr int kDigitsPerThread = kMaxRadix / kSortThreads;  // 8
+
+// In-place exclusive scan of s[0 .. radix) (radix <= kMaxRadix) by the block's
+// 256 threads, each owning kDigitsPerThread consecutive digits; returns the total.
+__device__ inline uint32_t block_scan_digits(uint32_t* s, int radix, uint32_t* s_buf) {
+    const int d0 = threadIdx.x * kDigitsPerThread;
+    uint32_t v[kDigitsPerThread];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kDigitsPerThread; ++q) {
+        v[q] = d0 + q < radix ? s[d0 + q] : 0u;
+        sum += v[q];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan_256<uint32_t>(sum, s_buf, total);
+#pragma unroll
+    for (int q = 0; q < kDigitsPerThread; ++q) {
+        if (d0 + q < radix) s[d0 + q] = run;
+        run += v[q];
+    }
+    __syncthreads();
+    return total;
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                                 const unsigned long long* dcount, uint64_t hcount,
                                                                 int shift, int nbits, uint32_t* __restrict__ hist,
                                                                 int nblocks, uint64_t seg_stride) {
-    __shared__ uint32_t s_hist[4][256];
-    keys += (size_t)blockIdx.y * seg_stride;
-    hist += (size_t)blockIdx.y * 256 * nblocks;
+    __shared__ uint32_t s_hist[4][kMaxRadix];
     const int radix = 1 << nbits;
+    keys += (size_t)blockIdx.y * seg_stride;
+    hist += (size_t)blockIdx.y * radix * nblocks;
     const uint32_t mask = (uint32_t)radix - 1u;
     const int tid = threadIdx.x, w = tid >> 6;
-    for (int d = tid; d < 4 * 256; d += kSortThreads) (&s_hist[0][0])[d] = 0;
-    __syncthreads();
     const uint64_t n = read_count(dcount, hcount);
     const uint64_t begin = (uint64_t)blockIdx.x * kSortTile;
     if (begin >= n) return;  // blocks past the live count are never scanned (uniform)
+    for (int d = tid; d < 4 * radix; d += kSortThreads) s_hist[d / radix][d % radix] = 0;
+    __syncthreads();
     for (int k = 0; k < kSortItems; ++k) {
         const uint64_t idx = begin + (uint64_t)k * kSortThreads + tid;
         if (idx < n) atomicAdd(&s_hist[w][(keys[idx] >> shift) & mask], 1u);
@@ -77,16 +101,16 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* 
         hist[(size_t)d * nblocks + blockIdx.x] = s_hist[0][d] + s_hist[1][d] + s_hist[2][d] + s_hist[3][d];
 }
 
-// one block per digit: exclusive scan of that digit's per-block counts over the
-// blocks that hold live keys (4 counts per thread per round)
-__global__ void __launch_bounds__(256) k_radix_digit_scan(uint32_t* __restrict__ hist, int nblocks,
+// one block per (digit, segment): exclusive scan of that digit's per-block
+// counts over the blocks that hold live keys (4 counts per thread per round)
+__global__ void __launch_bounds__(256) k_radix_digit_scan(uint32_t* __restrict__ hist, int nblocks, int radix,
                                                           uint32_t* __restrict__ totals,
                                                           const unsigned long long* dcount, uint64_t hcount) {
     __shared__ uint32_t s_buf[256];
     const uint64_t n = read_count(dcount, hcount);
     const int live = (int)min((uint64_t)nblocks, (n + kSortTile - 1) / kSortTile);
-    uint32_t* h = hist + (size_t)blockIdx.y * 256 * nblocks + (size_t)blockIdx.x * nblocks;
-    totals += (size_t)blockIdx.y * 256;
+    uint32_t* h = hist + (size_t)blockIdx.y * radix * nblocks + (size_t)blockIdx.x * nblocks;
+    totals += (size_t)blockIdx.y * radix;
     uint32_t carry = 0;
     for (int start = 0; start < live; start += 1024) {
         const int i0 = start + 4 * (int)threadIdx.x;
@@ -112,33 +136,32 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     uint32_t* __restrict__ vals_out, const unsigned long long* dcount, uint64_t hcount, int shift, int nbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int nblocks,
     const unsigned long long* out_offset, uint64_t seg_stride) {
-    __shared__ uint32_t s_wcount[4][256];
-    __shared__ uint32_t s_dstart[256];
-    __shared__ uint32_t s_gbase[256];
-    __shared__ uint32_t s_scan[256];
+    __shared__ uint32_t s_wcount[4][kMaxRadix];
+    __shared__ uint32_t s_dstart[kMaxRadix];
+    __shared__ uint32_t s_gbase[kMaxRadix];
+    __shared__ uint32_t s_buf[256];
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
 
     const uint64_t n = read_count(dcount, hcount);
     const uint64_t begin = (uint64_t)blockIdx.x * kSortTile;
     if (begin >= n) return;  // uniform over the block
+    const int radix = 1 << nbits;
     {
         const size_t so = (size_t)blockIdx.y * seg_stride;
         keys_in += so; vals_in += so; keys_out += so; vals_out += so;
-        hist += (size_t)blockIdx.y * 256 * nblocks;
-        totals += (size_t)blockIdx.y * 256;
+        hist += (size_t)blockIdx.y * radix * nblocks;
+        totals += (size_t)blockIdx.y * radix;
     }
-    const int radix = 1 << nbits;
     const uint32_t mask = (uint32_t)radix - 1u;
     const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
 
-    for (int d = tid; d < 4 * 256; d += kSortThreads) (&s_wcount[0][0])[d] = 0;
+    for (int d = tid; d < 4 * radix; d += kSortThreads) s_wcount[d / radix][d % radix] = 0;
     // global base of digit d = (exclusive scan of totals)[d] + this block's scanned count
-    uint32_t tot;
-    const uint32_t tv = tid < radix ? totals[tid] : 0u;
-    const uint32_t dbase = block_exclusive_scan_256<uint32_t>(tv, s_scan, tot);
-    if (tid < radix) s_gbase[tid] = dbase + hist[(size_t)tid * nblocks + blockIdx.x];
+    for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] = totals[d];
     __syncthreads();
+    block_scan_digits(s_gbase, radix, s_buf);
+    for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] += hist[(size_t)d * nblocks + blockIdx.x];
 
     // wave w owns items [begin + w*512, begin + (w+1)*512), 8 rounds of 64
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
@@ -162,21 +185,19 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         if (valid && before == 0) s_wcount[w][d] = base + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // per digit: prefix over waves; block total per digit
-    uint32_t dt = 0;
-    if (tid < radix) {
+    // per digit: prefix over waves, block total per digit, then start of each
+    // digit's run in the block-sorted tile
+    for (int d = tid; d < radix; d += kSortThreads) {
         uint32_t run = 0;
         for (int q = 0; q < 4; ++q) {
-            const uint32_t c = s_wcount[q][tid];
-            s_wcount[q][tid] = run;
+            const uint32_t c = s_wcount[q][d];
+            s_wcount[q][d] = run;
             run += c;
         }
-        dt = run;
+        s_dstart[d] = run;
     }
-    uint32_t blk_tot;
-    const uint32_t ds = block_exclusive_scan_256<uint32_t>(dt, s_scan, blk_tot);
-    if (tid < radix) s_dstart[tid] = ds;
     __syncthreads();
+    block_scan_digits(s_dstart, radix, s_buf);
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t idx = begin + (uint64_t)w * (kSortItems * 64) + (uint64_t)r * 64 + lane;
         if (idx < n) {
@@ -199,8 +220,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
 }
 
 int radix_blocks(uint64_t capacity) { return (int)((capacity + kSortTile - 1) / kSortTile); }
-size_t radix_hist_words(uint64_t capacity, int n_seg) {
-    return (size_t)256 * (size_t)std::max(1, radix_blocks(capacity)) * (size_t)std::max(1, n_seg);
+size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits) {
+    return ((size_t)1 << max_bits) * (size_t)std::max(1, radix_blocks(capacity)) * (size_t)std::max(1, n_seg);
 }
 
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
@@ -211,7 +232,7 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
     if (nb == 0 || n_seg == 0) return;
     k_radix_upsweep<<<dim3(nb, n_seg), kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,
                                                                seg_stride);
-    k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, totals, dcount, hcount);
+    k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount);
     k_radix_downsweep<<<dim3(nb, n_seg), kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount,
                                                                  shift, nbits, hist, totals, nb, out_offset,
                                                                  seg_stride);
@@ -423,29 +444,10 @@ __global__ void k_finalize_regions(const unsigned long long* region_off, int til
     }
 }
 
-// Largest value of the log2-domain exponent p2(d) = qa dx^2 + qb dx dy + qc dy^2
-// (negative definite) over the rectangle [X0, X1] x [Y0, Y1] of offsets d = p - mu:
-// 0 if the rectangle holds mu, else the best of the four edges (each a 1-D
-// concave quadratic maximised at a clamped stationary point).
-__device__ inline double max_p2_rect(double qa, double qb, double qc, double X0, double X1, double Y0, double Y1) {
-    if (X0 <= 0.0 && 0.0 <= X1 && Y0 <= 0.0 && 0.0 <= Y1) return 0.0;
-    double best = -INFINITY;
-    const double xs[2] = {X0, X1}, ys[2] = {Y0, Y1};
-    for (int e = 0; e < 2; ++e) {
-        const double X = xs[e];
-        const double t = fmin(fmax(-qb * X / (2.0 * qc), Y0), Y1);
-        best = fmax(best, qa * X * X + qb * X * t + qc * t * t);
-        const double Y = ys[e];
-        const double u = fmin(fmax(-qb * Y / (2.0 * qa), X0), X1);
-        best = fmax(best, qa * u * u + qb * u * Y + qc * Y * Y);
-    }
-    return best;
-}
-
 // Margin (log2 units) between the FP64 tile test and the FP32 per-pixel test:
 // the FP32 exponent of a pixel is within about 1e-5 of its exact value, so a
-// tile whose best exact exponent is this far below the threshold has no pixel
-// with alpha >= 1/255.
+// tile none of whose pixel centres reaches alpha = 1/255 * 2^-margin in exact
+// arithmetic has no pixel that the blending kernels would blend.
 constexpr double kCullMargin = 1e-3;
 
 // After the coarse sort: per coarse entry k (super-tile st, depth rank j) the
@@ -480,28 +482,42 @@ __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restric
             for (uint32_t ly = ly0; ly <= ly1; ++ly)
                 for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
         } else {
+            // alpha >= 1/255 needs -p2 = a dx^2 - b dx dy + c dy^2 <= t (an ellipse);
+            // per tile row the ellipse's x-extent over the row's slab of pixel-centre
+            // offsets is bounded by its rightmost / leftmost points clamped into the
+            // slab, and a tile is kept when its pixel-centre x-range meets it.
             const Rec rec = recs[(size_t)view * N + gid];
-            const double qa = rec.a.z, qb = rec.a.w, qc = rec.b.x, op = rec.b.y;
+            const double a = -(double)rec.a.z, b = rec.a.w, c = -(double)rec.b.x, op = rec.b.y;
             const double mu = (double)rec.c.y + (double)rec.a.x, mv = (double)rec.c.z + (double)rec.a.y;
             const int px0 = (int)(rec.d.x & 0xFFFFu), px1 = (int)(rec.d.x >> 16);
             const int py0 = (int)(rec.d.y & 0xFFFFu), py1 = (int)(rec.d.y >> 16);
-            // usable only for a negative definite form and a positive opacity;
-            // otherwise keep every overlapped tile
-            const bool ok = qa < 0.0 && qc < 0.0 && 4.0 * qa * qc - qb * qb > 0.0 && op > 0.0;
-            const double thr = ok ? -log2(255.0 * op) - kCullMargin : 0.0;
-            for (uint32_t ly = ly0; ly <= ly1; ++ly) {
-                const int ty = (int)(by + ly);
-                const int ya = max(ty * tile, py0), yb = min(ty * tile + tile - 1, py1);
-                for (uint32_t lx = lx0; lx <= lx1; ++lx) {
-                    const int tx = (int)(bx + lx);
-                    const int xa = max(tx * tile, px0), xb = min(tx * tile + tile - 1, px1);
-                    bool keep = true;
-                    if (ok) {
-                        const double m = max_p2_rect(qa, qb, qc, xa + 0.5 - mu, xb + 0.5 - mu, ya + 0.5 - mv,
-                                                     yb + 0.5 - mv);
-                        keep = m >= thr;
+            const double det4 = 4.0 * a * c - b * b;
+            const bool usable = a > 0.0 && c > 0.0 && det4 > 1e-12 * 4.0 * a * c && op > 0.0;
+            if (!usable) {  // not a proper ellipse: keep every overlapped tile
+                for (uint32_t ly = ly0; ly <= ly1; ++ly)
+                    for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
+            } else {
+                const double t = log2(255.0 * op) + kCullMargin;
+                if (t > 0.0) {  // otherwise no pixel reaches alpha = 1/255
+                    const double y_full = sqrt(4.0 * a * t / det4);  // half-height
+                    const double x_ext = sqrt(4.0 * c * t / det4);   // half-width
+                    const double y_ext = b * x_ext / (2.0 * c);      // height of the rightmost point
+                    const double inv2a = 0.5 / a;
+                    for (uint32_t ly = ly0; ly <= ly1; ++ly) {
+                        const int ty = (int)(by + ly);
+                        const double Y0 = max(ty * tile, py0) + 0.5 - mv;
+                        const double Y1 = min(ty * tile + tile - 1, py1) + 0.5 - mv;
+                        if (Y1 < -y_full || Y0 > y_full) continue;
+                        const double yr = fmin(fmax(y_ext, Y0), Y1), yl = fmin(fmax(-y_ext, Y0), Y1);
+                        const double xr = (b * yr + sqrt(fmax(0.0, 4.0 * a * t - yr * yr * det4))) * inv2a;
+                        const double xl = (b * yl - sqrt(fmax(0.0, 4.0 * a * t - yl * yl * det4))) * inv2a;
+                        for (uint32_t lx = lx0; lx <= lx1; ++lx) {
+                            const int tx = (int)(bx + lx);
+                            const double X0 = max(tx * tile, px0) + 0.5 - mu;
+                            const double X1 = min(tx * tile + tile - 1, px1) + 0.5 - mu;
+                            if (X1 >= xl && X0 <= xr) mask |= 1u << (ly * (uint32_t)S + lx);
+                        }
                     }
-                    if (keep) mask |= 1u << (ly * (uint32_t)S + lx);
                 }
             }
         }
