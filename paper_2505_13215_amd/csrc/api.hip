@@ -135,7 +135,7 @@ struct Layout {
     // scratch, forward use
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_eff2,
         sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges, sc_tsizes, sc_toff, sc_tpart,
-        fwd_bytes;
+        sc_shape, sc_runs, fwd_bytes;
     // scratch, backward use
     size_t sc_g2, bwd_bytes;
     size_t scratch_bytes;
@@ -221,6 +221,8 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_tsizes = f.take(4 * (size_t)max_tiles);
     L.sc_toff = f.take(8 * ((size_t)max_tiles + 1));
     L.sc_tpart = f.take(8 * ((size_t)scan_blocks(max_tiles) + 2));
+    L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
+    L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
     L.fwd_bytes = f.off;
     Carve b;
     L.sc_g2 = b.take(4 * 9 * n * V_);
@@ -353,15 +355,21 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         uint32_t* cnt = at<uint32_t>(scratch, L.sc_cnt);
         uint64_t* rect = at<uint64_t>(scratch, L.sc_rect);
         unsigned long long* offsets = at<unsigned long long>(scratch, L.sc_offsets);
-        // coarse entries: one per (depth-ordered Gaussian, 64-px super-tile)
-        launch_coarse_count(dv, n, N, recs, P.v0, tile, S, cnt, rect, st);
-        launch_scan_u32_u64(cnt, nullptr, n, offsets, at<unsigned long long>(scratch, L.sc_partials), st);
+        // coarse entries: one per (depth-ordered Gaussian, super-tile); the tile
+        // mask travels in the key's upper half when the pass's super-tile ids fit
+        // the lower one
+        const int mkey = P.supers <= (1 << 16) ? 1 : 0;
+        CullShape* shapes = (cull && mkey) ? at<CullShape>(scratch, L.sc_shape) : nullptr;
+        launch_coarse_count(dv, n, N, recs, P.v0, tile, S, cnt, rect, shapes, st);
+        uint32_t* runs = at<uint32_t>(scratch, L.sc_runs);
+        launch_scan_u32_u64(cnt, nullptr, n, offsets, at<unsigned long long>(scratch, L.sc_partials), st, runs,
+                            L.ccap / 256 + 1);
         launch_finalize_coarse(offsets, n, L.ccap, S, status, eff_c, st);
         uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
         uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
         uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
         uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
-        launch_coarse_emit(offsets, n, N, rect, vp, P.v0, S, eff_c, pk, pv, st);
+        launch_coarse_emit(offsets, runs, n, N, rect, shapes, vp, P.v0, tile, S, mkey, L.ccap, eff_c, pk, pv, st);
         // stable sort of the coarse entries by super-tile (depth order kept inside each)
         const int bits = bits_for(P.supers);
         const int passes = n_passes_for(bits, kMaxRadixBits);
@@ -379,7 +387,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         }
         int64_t* cranges = at<int64_t>(scratch, L.sc_cranges);
         launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
-        launch_ranges(kin, eff_c, nullptr, cranges, st);
+        launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, eff_c, nullptr, cranges, st);
         // per-tile regions sized by the super-tile list, then ordered compaction
         uint32_t* tsizes = at<uint32_t>(scratch, L.sc_tsizes);
         unsigned long long* toff = at<unsigned long long>(scratch, L.sc_toff);
@@ -389,7 +397,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         // the buffer pair the sort did not end in receives (id, tile mask) per coarse entry
         uint32_t* cgid = (kin == pk) ? pk2 : pk;
         uint32_t* cmask = (kin == pk) ? pv2 : pv;
-        launch_coarse_gather(kin, vin, rect, dv, N, recs, vp, P.v0, tile, S, cull, eff_c, cgid, cmask, st);
+        launch_coarse_gather(kin, vin, rect, dv, N, vp, P.v0, S, mkey, eff_c, cgid, cmask, st);
         launch_tile_write(cgid, cmask, cranges, toff, pair_base + P.v0, eff_r, P.tiles, vp, P.v0, P.v1, S, ids,
                           at<int64_t>(state, L.st_ranges), st);
     }

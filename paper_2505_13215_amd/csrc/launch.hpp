@@ -55,17 +55,36 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
                        int n_seg = 1, uint64_t seg_stride = 0);
 int scan_blocks(int n);
 // out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
+// With run_start, run_start[r] (r < run_cap) receives the index i whose range
+// [out[i], out[i + 1]) holds output 256 r.
 void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigned long long* out,
-                         unsigned long long* partials, hipStream_t st);
+                         unsigned long long* partials, hipStream_t st, uint32_t* run_start = nullptr,
+                         uint64_t run_cap = 0);
+// The alpha >= 1/255 region of one splat as the binning's tile test needs it:
+// -p2 = a dx^2 - b dx dy + c dy^2 <= t, with dx, dy offsets from the centre (set
+// up in FP64 per splat, tested in FP32 on widened intervals).
+struct CullShape {
+    float b, inv2a, four_at, det4;  // det4 = 4ac - b^2
+    float y_full, y_ext;            // half-height; height of the rightmost point
+    float pad_x, pad_y;
+    float ui, uf, vi, vf;           // centre, integer and fractional parts
+    int px0, px1, py0, py1;         // pixel square
+    int mode;                       // 0: keep every tile, 1: test, 2: no pixel can pass
+};
+
 // Two-level binning over the views [v0, v1) of one pass; j = r * N + rank
 // indexes the depth-ordered Gaussians of view v0 + r (n = (v1 - v0) * N).
 // Super-tile ids are relative to view v0, tile ids t to its first tile.
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
-                         uint32_t* cnt, uint64_t* rect_sorted, hipStream_t st);
+                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, hipStream_t st);
 void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
                             unsigned long long* eff_count, hipStream_t st);
-void launch_coarse_emit(const unsigned long long* offsets, int n, int N, const uint64_t* rect_sorted,
-                        const ViewParams* views, int v0, int S, const unsigned long long* eff_count, uint32_t* keys,
+// With mkey (super-tile ids of the pass below 2^16) the keys carry each entry's
+// tile mask in their upper 16 bits (cull: less the tiles no pixel of which can
+// reach alpha >= 1/255).
+void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, int N,
+                        const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
+                        int S, int mkey, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys,
                         uint32_t* vals, hipStream_t st);
 void launch_tile_sizes(const int64_t* cranges, int tiles, const ViewParams* views, int v0, int v1, int S,
                        const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st);
@@ -73,19 +92,19 @@ void launch_finalize_regions(const unsigned long long* region_off, int tiles, un
                              int v1, uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
                              unsigned long long* eff_regions, hipStream_t st);
 // Per coarse entry: the splat id and the 16-bit mask of the super-tile's tiles
-// (bit ly * S + lx) that its pixel square overlaps, less (cull = 1) the tiles in
-// which no pixel centre can reach alpha >= 1/255.
+// (bit ly * S + lx) it goes to: from the key's upper half (mkey) or the tiles
+// its pixel square overlaps.
 void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int N, const Rec* recs, const ViewParams* views, int v0,
-                          int tile, int S, int cull, const unsigned long long* eff_count, uint32_t* cgid,
-                          uint32_t* cmask, hipStream_t st);
+                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S, int mkey,
+                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* cmask, hipStream_t st);
 void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
                        const unsigned long long* region_off, const unsigned long long* base_ptr,
                        const unsigned long long* eff_regions, int tiles, const ViewParams* views, int v0, int v1,
                        int S, uint32_t* ids, int64_t* ranges, hipStream_t st);
-// ranges of sorted keys: ranges[2k], ranges[2k+1] = [first, last+1) + *base (base may be null)
-void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,
-                   int64_t* ranges, hipStream_t st);
+// ranges of sorted keys (compared under key_mask): ranges[2k], ranges[2k+1] =
+// [first, last+1) + *base (base may be null)
+void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
+                   const unsigned long long* base, int64_t* ranges, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 void launch_zero_status(Status* s, unsigned long long* pair_base, int n_views, hipStream_t st);

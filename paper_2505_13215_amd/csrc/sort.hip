@@ -53,23 +53,23 @@ __device__ inline T block_exclusive_scan_256(T v, T* s_buf, T& total) {
 // ---------------------------------------------------------------------------
 // Radix sort pass (up to 11 bits per pass)
 // ---------------------------------------------------------------------------
-constexpr int kDigitsPerThread = kMaxRadix / kSortThreads;  // 8
-
-// In-place exclusive scan of s[0 .. radix) (radix <= kMaxRadix) by the block's
-// 256 threads, each owning kDigitsPerThread consecutive digits; returns the total.
+// In-place exclusive scan of s[0 .. radix) (radix <= 2^MB) by the block's 256
+// threads, each owning 2^MB / 256 consecutive digits; returns the total.
+template <int MB>
 __device__ inline uint32_t block_scan_digits(uint32_t* s, int radix, uint32_t* s_buf) {
-    const int d0 = threadIdx.x * kDigitsPerThread;
-    uint32_t v[kDigitsPerThread];
+    constexpr int DPT = (1 << MB) / kSortThreads;
+    const int d0 = threadIdx.x * DPT;
+    uint32_t v[DPT];
     uint32_t sum = 0;
 #pragma unroll
-    for (int q = 0; q < kDigitsPerThread; ++q) {
+    for (int q = 0; q < DPT; ++q) {
         v[q] = d0 + q < radix ? s[d0 + q] : 0u;
         sum += v[q];
     }
     uint32_t total;
     uint32_t run = block_exclusive_scan_256<uint32_t>(sum, s_buf, total);
 #pragma unroll
-    for (int q = 0; q < kDigitsPerThread; ++q) {
+    for (int q = 0; q < DPT; ++q) {
         if (d0 + q < radix) s[d0 + q] = run;
         run += v[q];
     }
@@ -77,11 +77,13 @@ __device__ inline uint32_t block_scan_digits(uint32_t* s, int radix, uint32_t* s
     return total;
 }
 
+// MB: largest digit width the instantiation handles (LDS is sized for it).
+template <int MB>
 __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                                 const unsigned long long* dcount, uint64_t hcount,
                                                                 int shift, int nbits, uint32_t* __restrict__ hist,
                                                                 int nblocks, uint64_t seg_stride) {
-    __shared__ uint32_t s_hist[4][kMaxRadix];
+    __shared__ uint32_t s_hist[4][1 << MB];
     const int radix = 1 << nbits;
     keys += (size_t)blockIdx.y * seg_stride;
     hist += (size_t)blockIdx.y * radix * nblocks;
@@ -131,14 +133,15 @@ __global__ void __launch_bounds__(256) k_radix_digit_scan(uint32_t* __restrict__
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+template <int MB>
 __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const unsigned long long* dcount, uint64_t hcount, int shift, int nbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int nblocks,
     const unsigned long long* out_offset, uint64_t seg_stride) {
-    __shared__ uint32_t s_wcount[4][kMaxRadix];
-    __shared__ uint32_t s_dstart[kMaxRadix];
-    __shared__ uint32_t s_gbase[kMaxRadix];
+    __shared__ uint32_t s_wcount[4][1 << MB];
+    __shared__ uint32_t s_dstart[1 << MB];
+    __shared__ uint32_t s_gbase[1 << MB];
     __shared__ uint32_t s_buf[256];
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
@@ -160,7 +163,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     // global base of digit d = (exclusive scan of totals)[d] + this block's scanned count
     for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] = totals[d];
     __syncthreads();
-    block_scan_digits(s_gbase, radix, s_buf);
+    block_scan_digits<MB>(s_gbase, radix, s_buf);
     for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] += hist[(size_t)d * nblocks + blockIdx.x];
 
     // wave w owns items [begin + w*512, begin + (w+1)*512), 8 rounds of 64
@@ -197,7 +200,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         s_dstart[d] = run;
     }
     __syncthreads();
-    block_scan_digits(s_dstart, radix, s_buf);
+    block_scan_digits<MB>(s_dstart, radix, s_buf);
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t idx = begin + (uint64_t)w * (kSortItems * 64) + (uint64_t)r * 64 + lane;
         if (idx < n) {
@@ -230,12 +233,22 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
                        int n_seg, uint64_t seg_stride) {
     const int nb = radix_blocks(capacity);
     if (nb == 0 || n_seg == 0) return;
-    k_radix_upsweep<<<dim3(nb, n_seg), kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,
-                                                               seg_stride);
+    const dim3 grid(nb, n_seg);
+    if (nbits <= 8) {
+        k_radix_upsweep<8><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb, seg_stride);
+    } else {
+        k_radix_upsweep<kMaxRadixBits><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,
+                                                                      seg_stride);
+    }
     k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount);
-    k_radix_downsweep<<<dim3(nb, n_seg), kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount,
-                                                                 shift, nbits, hist, totals, nb, out_offset,
-                                                                 seg_stride);
+    if (nbits <= 8) {
+        k_radix_downsweep<8><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount, shift,
+                                                            nbits, hist, totals, nb, out_offset, seg_stride);
+    } else {
+        k_radix_downsweep<kMaxRadixBits><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount,
+                                                                        hcount, shift, nbits, hist, totals, nb,
+                                                                        out_offset, seg_stride);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -269,9 +282,12 @@ __global__ void __launch_bounds__(256) k_scan_top(unsigned long long* __restrict
     if (threadIdx.x == 0) partials[nparts] = carry;
 }
 
+// With run_start: for every run of 256 outputs, the index whose range
+// [out[i], out[i + 1]) holds the run's first output (runs below run_cap).
 __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx,
                                                    int n, const unsigned long long* __restrict__ partials, int nparts,
-                                                   unsigned long long* __restrict__ out) {
+                                                   unsigned long long* __restrict__ out,
+                                                   uint32_t* __restrict__ run_start, uint64_t run_cap) {
     __shared__ unsigned long long s_buf[256];
     const int begin = blockIdx.x * kScanTile + threadIdx.x * 8;
     uint32_t v[8];
@@ -285,7 +301,11 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* __restrict__ 
     unsigned long long run = block_exclusive_scan_256<unsigned long long>(s, s_buf, tot) + partials[blockIdx.x];
     for (int k = 0; k < 8; ++k) {
         const int i = begin + k;
-        if (i < n) out[i] = run;
+        if (i < n) {
+            out[i] = run;
+            if (run_start)
+                for (uint64_t r = (run + 255) / 256; r * 256 < run + v[k] && r < run_cap; ++r) run_start[r] = (uint32_t)i;
+        }
         run += v[k];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partials[nparts];
@@ -294,11 +314,11 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* __restrict__ 
 int scan_blocks(int n) { return (n + kScanTile - 1) / kScanTile; }
 
 void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigned long long* out,
-                         unsigned long long* partials, hipStream_t st) {
+                         unsigned long long* partials, hipStream_t st, uint32_t* run_start, uint64_t run_cap) {
     const int nb = std::max(1, scan_blocks(n));
     k_scan_reduce<<<nb, 256, 0, st>>>(in, idx, n, partials);
     k_scan_top<<<1, 256, 0, st>>>(partials, nb);
-    k_scan_down<<<nb, 256, 0, st>>>(in, idx, n, partials, nb, out);
+    k_scan_down<<<nb, 256, 0, st>>>(in, idx, n, partials, nb, out, run_start, run_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,15 +328,97 @@ __device__ __forceinline__ uint64_t pack_rect(uint32_t x0, uint32_t x1, uint32_t
     return (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) | ((uint64_t)y1 << 48);
 }
 
+// Margin (log2 units) between the FP64 tile test and the FP32 per-pixel test:
+// the FP32 exponent of a pixel is within about 1e-5 of its exact value, so a
+// tile none of whose pixel centres reaches alpha = 1/255 * 2^-margin in exact
+// arithmetic has no pixel that the blending kernels would blend.
+constexpr double kCullMargin = 1e-3;
+
+// The alpha >= 1/255 region of one splat as the tile test needs it:
+// -p2 = a dx^2 - b dx dy + c dy^2 <= t, with dx, dy offsets from the centre.
+// Set up in FP64 per splat; the per-row test runs in FP32 on intervals widened
+// by pad_x / pad_y: 2e-3 of the ellipse's half-extent plus 0.01 px, several
+// times the FP32 rounding of the extent (whose worst case, near the ellipse's
+// top and bottom, is about 5e-4 of the half-width).
+
+__device__ inline CullShape cull_shape(const Rec& rec) {
+    CullShape cs;
+    const double a = -(double)rec.a.z, b = rec.a.w, c = -(double)rec.b.x, op = rec.b.y;
+    cs.ui = rec.c.y; cs.uf = rec.a.x; cs.vi = rec.c.z; cs.vf = rec.a.y;
+    cs.px0 = (int)(rec.d.x & 0xFFFFu); cs.px1 = (int)(rec.d.x >> 16);
+    cs.py0 = (int)(rec.d.y & 0xFFFFu); cs.py1 = (int)(rec.d.y >> 16);
+    const double det4 = 4.0 * a * c - b * b;
+    cs.mode = 0;
+    cs.b = cs.inv2a = cs.four_at = cs.det4 = cs.y_full = cs.y_ext = cs.pad_x = cs.pad_y = 0.f;
+    // a proper ellipse only; otherwise keep every overlapped tile
+    if (a > 0.0 && c > 0.0 && det4 > 1e-12 * 4.0 * a * c && op > 0.0) {
+        const double t = log2(255.0 * op) + kCullMargin;
+        if (t <= 0.0) {
+            cs.mode = 2;
+        } else {
+            cs.mode = 1;
+            const double y_full = sqrt(4.0 * a * t / det4), x_ext = sqrt(4.0 * c * t / det4);
+            cs.b = (float)b;
+            cs.inv2a = (float)(0.5 / a);
+            cs.four_at = (float)(4.0 * a * t);
+            cs.det4 = (float)det4;
+            cs.y_full = (float)y_full;
+            cs.y_ext = (float)(b * x_ext / (2.0 * c));
+            cs.pad_y = (float)(2e-3 * y_full + 1e-2);
+            cs.pad_x = (float)(2e-3 * (x_ext + fabs(b) * y_full * 0.5 / a) + 1e-2);
+        }
+    }
+    return cs;
+}
+
+// Tiles (bit ly * S + lx) of the super-tile at tile origin (bx, by) that the
+// splat's tile rectangle [tx0, tx1] x [ty0, ty1] overlaps and, when shape.mode
+// is 1, in which the ellipse's x-extent over the tile row's slab of pixel-centre
+// offsets (from its extreme points clamped into the slab) meets the tile's
+// pixel-centre x-range.
+__device__ inline uint32_t tile_mask(const CullShape& cs, int cull, uint32_t tx0, uint32_t tx1, uint32_t ty0,
+                                     uint32_t ty1, uint32_t bx, uint32_t by, int S, int tile) {
+    const uint32_t lx0 = max(tx0, bx) - bx, lx1 = min(tx1, bx + (uint32_t)S - 1u) - bx;
+    const uint32_t ly0 = max(ty0, by) - by, ly1 = min(ty1, by + (uint32_t)S - 1u) - by;
+    uint32_t mask = 0u;
+    if (!cull || cs.mode == 0) {
+        for (uint32_t ly = ly0; ly <= ly1; ++ly)
+            for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
+        return mask;
+    }
+    if (cs.mode == 2) return 0u;
+    for (uint32_t ly = ly0; ly <= ly1; ++ly) {
+        const int ty = (int)(by + ly);
+        const float Y0 = ((float)max(ty * tile, cs.py0) + 0.5f - cs.vi) - cs.vf;
+        const float Y1 = ((float)min(ty * tile + tile - 1, cs.py1) + 0.5f - cs.vi) - cs.vf;
+        if (Y1 < -cs.y_full - cs.pad_y || Y0 > cs.y_full + cs.pad_y) continue;
+        const float yr = fminf(fmaxf(cs.y_ext, Y0), Y1), yl = fminf(fmaxf(-cs.y_ext, Y0), Y1);
+        const float xr = (cs.b * yr + __builtin_sqrtf(fmaxf(0.f, cs.four_at - yr * yr * cs.det4))) * cs.inv2a +
+                         cs.pad_x;
+        const float xl = (cs.b * yl - __builtin_sqrtf(fmaxf(0.f, cs.four_at - yl * yl * cs.det4))) * cs.inv2a -
+                         cs.pad_x;
+        for (uint32_t lx = lx0; lx <= lx1; ++lx) {
+            const int tx = (int)(bx + lx);
+            const float X0 = ((float)max(tx * tile, cs.px0) + 0.5f - cs.ui) - cs.uf;
+            const float X1 = ((float)min(tx * tile + tile - 1, cs.px1) + 0.5f - cs.ui) - cs.uf;
+            if (X1 >= xl && X0 <= xr) mask |= 1u << (ly * (uint32_t)S + lx);
+        }
+    }
+    return mask;
+}
+
 // Per depth-ordered Gaussian j of the view range (j = r * N + rank, view
-// v0 + r): its tile rectangle and its super-tile count.
+// v0 + r): its tile rectangle, its super-tile count and (shapes != null) the
+// shape of its alpha >= 1/255 region for the tile test.
 __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n, int N,
                                                       const Rec* __restrict__ recs, int v0, int tile, int S,
-                                                      uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted) {
+                                                      uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted,
+                                                      CullShape* __restrict__ shapes) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int view = v0 + j / N;
-    const uint4 d = recs[(size_t)view * N + sorted_gid[j]].d;
+    const Rec& rec = recs[(size_t)view * N + sorted_gid[j]];
+    const uint4 d = rec.d;
     if (d.w == 0u) {
         cnt[j] = 0u;
         rect_sorted[j] = 0ull;
@@ -326,6 +428,7 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
     const uint32_t tx0 = (d.x & 0xFFFFu) / t, tx1 = (d.x >> 16) / t, ty0 = (d.y & 0xFFFFu) / t, ty1 = (d.y >> 16) / t;
     rect_sorted[j] = pack_rect(tx0, tx1, ty0, ty1);
     cnt[j] = (tx1 / s - tx0 / s + 1u) * (ty1 / s - ty0 / s + 1u);
+    if (shapes) shapes[j] = cull_shape(rec);
 }
 
 __global__ void k_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
@@ -342,48 +445,73 @@ __global__ void k_finalize_coarse(const unsigned long long* offsets, int n, uint
 }
 
 // Coarse entries (super-tile id relative to the range's first view, depth
-// rank j), written in (view, depth) order.  One block per 256 depth-ordered
-// Gaussians; threads stride over the block's contiguous output range and find
-// their Gaussian by binary search in LDS.
-__global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* __restrict__ offsets, int n, int N,
+// rank j), written in (view, depth) order: one thread per entry, which finds
+// its Gaussian by binary search over the count offsets (entries, not
+// Gaussians, are spread evenly: the nearest splats are the largest and sit
+// together in depth order).  With mkey the key's upper 16 bits carry the
+// entry's tile mask (the super-tile sort reads only the low bits); shapes !=
+// null applies the alpha >= 1/255 tile test.
+__global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* __restrict__ offsets,
+                                                     const uint32_t* __restrict__ run_start, int n, int N,
                                                      const uint64_t* __restrict__ rect_sorted,
-                                                     const ViewParams* __restrict__ views, int v0, int S,
-                                                     const unsigned long long* eff_count, uint32_t* __restrict__ keys,
-                                                     uint32_t* __restrict__ vals) {
+                                                     const CullShape* __restrict__ shapes,
+                                                     const ViewParams* __restrict__ views, int v0, int tile, int S,
+                                                     int mkey, const unsigned long long* eff_count,
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     __shared__ unsigned long long s_off[257];
-    __shared__ uint32_t s_kb[256], s_sxv[256], s_sw[256];
-    if (*eff_count == 0ull) return;
+    const uint64_t C = *eff_count;
     const int tid = threadIdx.x;
-    const int j0 = blockIdx.x * 256;
-    const int j = j0 + tid;
-    if (j < n) {
-        const ViewParams& V = views[v0 + j / N];
-        const uint64_t r = rect_sorted[j];
-        const uint32_t s = (uint32_t)S;
-        const uint32_t sx0 = (uint32_t)(r & 0xFFFFu) / s, sx1 = (uint32_t)((r >> 16) & 0xFFFFu) / s;
-        const uint32_t sy0 = (uint32_t)((r >> 32) & 0xFFFFu) / s;
-        s_off[tid] = offsets[j];
-        s_sw[tid] = sx1 - sx0 + 1u;
-        s_sxv[tid] = (uint32_t)V.sx;
-        s_kb[tid] = (uint32_t)(V.super_base - views[v0].super_base) + sy0 * (uint32_t)V.sx + sx0;
-    } else {
-        s_off[tid] = offsets[n];
-        s_sw[tid] = 1; s_sxv[tid] = 0; s_kb[tid] = 0;
-    }
-    if (tid == 0) s_off[256] = offsets[min(j0 + 256, n)];
-    __syncthreads();
-    const unsigned long long start = s_off[0], end = s_off[256];
-    for (unsigned long long p = start + tid; p < end; p += 256) {
-        int lo = 0, hi = 256;  // last k with s_off[k] <= p
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= p) lo = mid; else hi = mid;
+    // blocks take runs of 256 consecutive entries (run_start names the Gaussian
+    // holding a run's first entry); within a view invisible
+    // Gaussians sort last (culled key), so the visible ones all own entries and
+    // a run usually spans at most 256 consecutive Gaussians (entries past the
+    // block's window, after another view's invisible tail, search globally)
+    for (uint64_t p0 = (uint64_t)blockIdx.x * 256; p0 < C; p0 += (uint64_t)gridDim.x * 256) {
+        const int j0 = (int)run_start[p0 / 256];  // Gaussian holding entry p0
+        s_off[tid] = offsets[min(j0 + tid, n)];
+        if (tid == 0) s_off[256] = offsets[min(j0 + 256, n)];
+        __syncthreads();
+        const uint64_t p = p0 + tid;
+        if (p < C) {
+            int j;
+            unsigned long long pj;  // offsets[j]
+            if (p < s_off[256]) {
+                int lo = 0, hi = 256;  // last k with s_off[k] <= p
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_off[mid] <= p) lo = mid; else hi = mid;
+                }
+                j = j0 + lo;
+                pj = s_off[lo];
+            } else {
+                int lo = min(j0 + 256, n - 1), hi = n;  // offsets[lo] <= p < offsets[n]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (offsets[mid] <= p) lo = mid; else hi = mid;
+                }
+                j = lo;
+                pj = offsets[lo];
+            }
+            const ViewParams& V = views[v0 + j / N];
+            const uint64_t r = rect_sorted[j];
+            const uint32_t s = (uint32_t)S;
+            const uint32_t tx0 = (uint32_t)(r & 0xFFFFu), tx1 = (uint32_t)((r >> 16) & 0xFFFFu);
+            const uint32_t ty0 = (uint32_t)((r >> 32) & 0xFFFFu), ty1 = (uint32_t)(r >> 48);
+            const uint32_t sx0 = tx0 / s, sw = tx1 / s - sx0 + 1u, sy0 = ty0 / s;
+            const uint32_t local = (uint32_t)(p - pj);
+            const uint32_t sy = local / sw, sx = local - sy * sw;
+            uint32_t key = (uint32_t)(V.super_base - views[v0].super_base) + (sy0 + sy) * (uint32_t)V.sx + sx0 + sx;
+            if (mkey) {
+                CullShape keep_all;
+                keep_all.mode = 0;
+                const uint32_t m = tile_mask(shapes ? shapes[j] : keep_all, shapes != nullptr, tx0, tx1, ty0, ty1,
+                                             (sx0 + sx) * s, (sy0 + sy) * s, S, tile);
+                key |= m << 16;
+            }
+            keys[p] = key;
+            vals[p] = (uint32_t)j;
         }
-        const uint32_t local = (uint32_t)(p - s_off[lo]);
-        const uint32_t sw = s_sw[lo];
-        const uint32_t sy = local / sw, sx = local - sy * sw;
-        keys[p] = s_kb[lo] + sy * s_sxv[lo] + sx;
-        vals[p] = (uint32_t)(j0 + lo);
+        __syncthreads();
     }
 }
 
@@ -444,84 +572,39 @@ __global__ void k_finalize_regions(const unsigned long long* region_off, int til
     }
 }
 
-// Margin (log2 units) between the FP64 tile test and the FP32 per-pixel test:
-// the FP32 exponent of a pixel is within about 1e-5 of its exact value, so a
-// tile none of whose pixel centres reaches alpha = 1/255 * 2^-margin in exact
-// arithmetic has no pixel that the blending kernels would blend.
-constexpr double kCullMargin = 1e-3;
-
 // After the coarse sort: per coarse entry k (super-tile st, depth rank j) the
-// splat id and the mask of the super-tile's tiles (bit ly * S + lx) its pixel
-// square overlaps; with cull, tiles whose pixel centres (inside the square) all
-// stay below alpha = 1/255 are cleared.  The per-tile pass then streams 8
-// bytes per entry.
+// splat id and its tile mask (bit ly * S + lx of the super-tile): taken from the
+// key's upper half (mkey), or the tiles its pixel square overlaps.  The
+// per-tile pass then streams 8 bytes per entry.
 __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ ckeys,
                                                        const uint32_t* __restrict__ cvals,
                                                        const uint64_t* __restrict__ rect_sorted,
                                                        const uint32_t* __restrict__ sorted_gid, int N,
-                                                       const Rec* __restrict__ recs,
-                                                       const ViewParams* __restrict__ views, int v0, int tile, int S,
-                                                       int cull, const unsigned long long* eff_count,
+                                                       const ViewParams* __restrict__ views, int v0, int S, int mkey,
+                                                       const unsigned long long* eff_count,
                                                        uint32_t* __restrict__ cgid, uint32_t* __restrict__ cmask) {
     const uint64_t n = *eff_count;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t j = cvals[k];
-        const int view = v0 + (int)(j / (uint32_t)N);
-        const ViewParams& V = views[view];
-        const uint32_t st = ckeys[k] - (uint32_t)(V.super_base - views[v0].super_base);
-        const uint64_t r = rect_sorted[j];
-        const uint32_t SX = (uint32_t)V.sx;
-        const uint32_t bx = (st % SX) * (uint32_t)S, by = (st / SX) * (uint32_t)S;
-        const uint32_t x0 = (uint32_t)(r & 0xFFFFu), x1 = (uint32_t)((r >> 16) & 0xFFFFu);
-        const uint32_t y0 = (uint32_t)((r >> 32) & 0xFFFFu), y1 = (uint32_t)(r >> 48);
-        const uint32_t lx0 = max(x0, bx) - bx, lx1 = min(x1, bx + (uint32_t)S - 1u) - bx;
-        const uint32_t ly0 = max(y0, by) - by, ly1 = min(y1, by + (uint32_t)S - 1u) - by;
-        const uint32_t gid = sorted_gid[j];
-        uint32_t mask = 0u;
-        if (!cull) {
+        const uint32_t key = ckeys[k];
+        uint32_t mask;
+        if (mkey) {
+            mask = key >> 16;
+        } else {
+            const ViewParams& V = views[v0 + (int)(j / (uint32_t)N)];
+            const uint32_t st = key - (uint32_t)(V.super_base - views[v0].super_base);
+            const uint64_t r = rect_sorted[j];
+            const uint32_t SX = (uint32_t)V.sx;
+            const uint32_t bx = (st % SX) * (uint32_t)S, by = (st / SX) * (uint32_t)S;
+            const uint32_t x0 = (uint32_t)(r & 0xFFFFu), x1 = (uint32_t)((r >> 16) & 0xFFFFu);
+            const uint32_t y0 = (uint32_t)((r >> 32) & 0xFFFFu), y1 = (uint32_t)(r >> 48);
+            const uint32_t lx0 = max(x0, bx) - bx, lx1 = min(x1, bx + (uint32_t)S - 1u) - bx;
+            const uint32_t ly0 = max(y0, by) - by, ly1 = min(y1, by + (uint32_t)S - 1u) - by;
+            mask = 0u;
             for (uint32_t ly = ly0; ly <= ly1; ++ly)
                 for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
-        } else {
-            // alpha >= 1/255 needs -p2 = a dx^2 - b dx dy + c dy^2 <= t (an ellipse);
-            // per tile row the ellipse's x-extent over the row's slab of pixel-centre
-            // offsets is bounded by its rightmost / leftmost points clamped into the
-            // slab, and a tile is kept when its pixel-centre x-range meets it.
-            const Rec rec = recs[(size_t)view * N + gid];
-            const double a = -(double)rec.a.z, b = rec.a.w, c = -(double)rec.b.x, op = rec.b.y;
-            const double mu = (double)rec.c.y + (double)rec.a.x, mv = (double)rec.c.z + (double)rec.a.y;
-            const int px0 = (int)(rec.d.x & 0xFFFFu), px1 = (int)(rec.d.x >> 16);
-            const int py0 = (int)(rec.d.y & 0xFFFFu), py1 = (int)(rec.d.y >> 16);
-            const double det4 = 4.0 * a * c - b * b;
-            const bool usable = a > 0.0 && c > 0.0 && det4 > 1e-12 * 4.0 * a * c && op > 0.0;
-            if (!usable) {  // not a proper ellipse: keep every overlapped tile
-                for (uint32_t ly = ly0; ly <= ly1; ++ly)
-                    for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
-            } else {
-                const double t = log2(255.0 * op) + kCullMargin;
-                if (t > 0.0) {  // otherwise no pixel reaches alpha = 1/255
-                    const double y_full = sqrt(4.0 * a * t / det4);  // half-height
-                    const double x_ext = sqrt(4.0 * c * t / det4);   // half-width
-                    const double y_ext = b * x_ext / (2.0 * c);      // height of the rightmost point
-                    const double inv2a = 0.5 / a;
-                    for (uint32_t ly = ly0; ly <= ly1; ++ly) {
-                        const int ty = (int)(by + ly);
-                        const double Y0 = max(ty * tile, py0) + 0.5 - mv;
-                        const double Y1 = min(ty * tile + tile - 1, py1) + 0.5 - mv;
-                        if (Y1 < -y_full || Y0 > y_full) continue;
-                        const double yr = fmin(fmax(y_ext, Y0), Y1), yl = fmin(fmax(-y_ext, Y0), Y1);
-                        const double xr = (b * yr + sqrt(fmax(0.0, 4.0 * a * t - yr * yr * det4))) * inv2a;
-                        const double xl = (b * yl - sqrt(fmax(0.0, 4.0 * a * t - yl * yl * det4))) * inv2a;
-                        for (uint32_t lx = lx0; lx <= lx1; ++lx) {
-                            const int tx = (int)(bx + lx);
-                            const double X0 = max(tx * tile, px0) + 0.5 - mu;
-                            const double X1 = min(tx * tile + tile - 1, px1) + 0.5 - mu;
-                            if (X1 >= xl && X0 <= xr) mask |= 1u << (ly * (uint32_t)S + lx);
-                        }
-                    }
-                }
-            }
         }
-        cgid[k] = gid;
+        cgid[k] = sorted_gid[j];
         cmask[k] = mask;
     }
 }
@@ -585,14 +668,15 @@ __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__
     }
 }
 
-__global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ keys, const unsigned long long* eff_count,
+__global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ keys, uint32_t key_mask,
+                                                const unsigned long long* eff_count,
                                                 const unsigned long long* base_ptr, int64_t* __restrict__ ranges) {
     const uint64_t n = *eff_count;
     const int64_t base = base_ptr ? (int64_t)*base_ptr : 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t t = keys[i];
-        if (i == 0 || keys[i - 1] != t) ranges[2 * (size_t)t] = base + (int64_t)i;
-        if (i + 1 == n || keys[i + 1] != t) ranges[2 * (size_t)t + 1] = base + (int64_t)i + 1;
+        const uint32_t t = keys[i] & key_mask;
+        if (i == 0 || (keys[i - 1] & key_mask) != t) ranges[2 * (size_t)t] = base + (int64_t)i;
+        if (i + 1 == n || (keys[i + 1] & key_mask) != t) ranges[2 * (size_t)t + 1] = base + (int64_t)i + 1;
     }
 }
 
@@ -609,19 +693,22 @@ __global__ void k_zero_status(Status* s, unsigned long long* pair_base, int n_vi
 }
 
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
-                         uint32_t* cnt, uint64_t* rect_sorted, hipStream_t st) {
+                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, hipStream_t st) {
     if (n == 0) return;
-    k_coarse_count<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, n, N, recs, v0, tile, S, cnt, rect_sorted);
+    k_coarse_count<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, n, N, recs, v0, tile, S, cnt, rect_sorted, shapes);
 }
 void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
                             unsigned long long* eff_count, hipStream_t st) {
     k_finalize_coarse<<<1, 1, 0, st>>>(offsets, n, capacity, S, status, eff_count);
 }
-void launch_coarse_emit(const unsigned long long* offsets, int n, int N, const uint64_t* rect_sorted,
-                        const ViewParams* views, int v0, int S, const unsigned long long* eff_count, uint32_t* keys,
+void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, int N,
+                        const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
+                        int S, int mkey, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys,
                         uint32_t* vals, hipStream_t st) {
-    if (n == 0) return;
-    k_coarse_emit<<<ceil_div(n, 256), 256, 0, st>>>(offsets, n, N, rect_sorted, views, v0, S, eff_count, keys, vals);
+    if (n == 0 || capacity == 0) return;
+    const int nb = (int)std::min<uint64_t>(8192, (capacity + 255) / 256);
+    k_coarse_emit<<<nb, 256, 0, st>>>(offsets, run_start, n, N, rect_sorted, shapes, views, v0, tile, S, mkey,
+                                      eff_count, keys, vals);
 }
 void launch_tile_sizes(const int64_t* cranges, int tiles, const ViewParams* views, int v0, int v1, int S,
                        const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st) {
@@ -635,11 +722,10 @@ void launch_finalize_regions(const unsigned long long* region_off, int tiles, un
                                         eff_regions);
 }
 void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int N, const Rec* recs, const ViewParams* views, int v0,
-                          int tile, int S, int cull, const unsigned long long* eff_count, uint32_t* cgid,
-                          uint32_t* cmask, hipStream_t st) {
-    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, N, recs, views, v0, tile, S, cull,
-                                          eff_count, cgid, cmask);
+                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S, int mkey,
+                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* cmask, hipStream_t st) {
+    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, N, views, v0, S, mkey, eff_count,
+                                          cgid, cmask);
 }
 void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
                        const unsigned long long* region_off, const unsigned long long* base_ptr,
@@ -649,9 +735,9 @@ void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_
     k_tile_write<<<tiles, 256, 0, st>>>(cgid, cmask, cranges, region_off, base_ptr, eff_regions, views, v0, v1, S, ids,
                                         ranges);
 }
-void launch_ranges(const uint32_t* keys, const unsigned long long* eff_count, const unsigned long long* base,
-                   int64_t* ranges, hipStream_t st) {
-    k_ranges<<<2048, 256, 0, st>>>(keys, eff_count, base, ranges);
+void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
+                   const unsigned long long* base, int64_t* ranges, hipStream_t st) {
+    k_ranges<<<2048, 256, 0, st>>>(keys, key_mask, eff_count, base, ranges);
 }
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st) {
     if (n == 0) return;
