@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--gaussians", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=8)
+    ap.add_argument("--cpu-views", type=int, default=16)
     ap.add_argument("--stats-views", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs single-view leg")
     ap.add_argument("--batched-steps", type=int, default=3)
