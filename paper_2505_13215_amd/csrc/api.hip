@@ -225,7 +225,7 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
     L.fwd_bytes = f.off;
     Carve b;
-    L.sc_g2 = b.take(4 * 9 * n * V_);
+    L.sc_g2 = b.take(4 * (size_t)kG2Stride * n * V_);
     L.bwd_bytes = b.off;
     L.scratch_bytes = std::max(L.fwd_bytes, L.bwd_bytes);
     return L;
@@ -513,7 +513,7 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     void* stt = const_cast<void*>(state);
     float* g2 = at<float>(scratch, L.sc_g2);
-    launch_fill_f32(g2, (size_t)9 * N * n_views, 0.f, st);
+    launch_fill_f32(g2, (size_t)kG2Stride * N * n_views, 0.f, st);
     const ViewParams* vp = at<ViewParams>(stt, L.st_views);
     {
         StageScope sc(ctx, st, H4D_STAGE_BLEND_BWD);

@@ -51,6 +51,12 @@ __device__ __forceinline__ int find_view_of_tile(const ViewParams* views, int v0
     return v;
 }
 
+// Screen-space gradients of one (view, Gaussian) from the blending adjoint:
+// du dv dQ00 dQ01 dQ11 dop dr dg db (conic entries unscaled, Q01 counted once),
+// padded to one 64-byte record so that a splat's nine atomic additions touch a
+// single cache line.  Layout [view][N][kG2Stride].
+constexpr int kG2Stride = 16;
+
 // Per-view device pointers passed by value to the batched kernels.
 struct PtrTable {
     float* p[kMaxViews];

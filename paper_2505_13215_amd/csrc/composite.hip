@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const ViewParams& V = views[view];
     const int tile = gt - V.tile_base;
     recs += (size_t)view * N;
-    g2 += (size_t)view * 9 * N;
+    g2 += (size_t)view * N * kG2Stride;
     const float* __restrict__ dl = dls.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
     const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
@@ -289,9 +289,9 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const int comp0 = ((row & 1) << 1) | (row >> 1);
     const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
     const float fac1 = comp0 == 0 ? -0.5f : 1.0f;
-    float* const g2c0 = g2 + (size_t)comp0 * N;
-    float* const g2c1 = g2 + (size_t)(4 + comp0) * N;
-    float* const g2c8 = g2 + (size_t)8 * N;
+    float* const g2c0 = g2 + comp0;
+    float* const g2c1 = g2 + 4 + comp0;
+    float* const g2c8 = g2 + 8;
     for (int64_t base = start; base < end; base += CHUNK) {
         const int cnt = (int)min((int64_t)CHUNK, end - base);
         __syncthreads();  // the previous chunk's LDS is no longer read
@@ -356,10 +356,10 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 // results here, before the lane-divergent atomics below
                 asm volatile("" ::"v"(h0), "v"(h1), "v"(h2));
                 if (lead) {
-                    const uint32_t gid = s_sp[j].gid;
-                    atomicAdd(&g2c0[gid], h0 * fac0);
-                    atomicAdd(&g2c1[gid], h1 * fac1);
-                    if (row == 0) atomicAdd(&g2c8[gid], h2);
+                    const size_t o = (size_t)s_sp[j].gid * kG2Stride;
+                    atomicAdd(&g2c0[o], h0 * fac0);
+                    atomicAdd(&g2c1[o], h1 * fac1);
+                    if (row == 0) atomicAdd(&g2c8[o], h2);
                 }
             }
         }

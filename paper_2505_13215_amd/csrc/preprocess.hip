@@ -318,8 +318,8 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
 // Backward kernel: one thread per Gaussian, looping over the views of the call
 // (no atomics: every view's contribution to a Gaussian lands in one lane).
 // g2: per (view, Gaussian) screen-space gradients from the blending adjoint,
-// layout [view][9][N]: du dv dQ00 dQ01 dQ11 dop dr dg db (w.r.t. the unscaled
-// conic entries, Q01 counted once).
+// layout [view][N][kG2Stride]: du dv dQ00 dQ01 dQ11 dop dr dg db (w.r.t. the
+// unscaled conic entries, Q01 counted once).
 //
 // Per view the projection adjoint gives mu_c-bar, Sigma_c-bar and op-bar; the
 // slicing adjoint maps them to the spatial/temporal means and to the symmetric
@@ -448,7 +448,7 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
         ProjF p;
         project(V, w, p);
         double gmc[3], Sb[3][3], gop;
-        proj_bwd(V, w, p, g4.sh, g4.n, i, g2 + (size_t)v * 9 * N + i, (size_t)N, gmc, Sb, gop, gsh);
+        proj_bwd(V, w, p, g4.sh, g4.n, i, g2 + ((size_t)v * N + i) * kG2Stride, 1, gmc, Sb, gop, gsh);
         // effective opacity sigma * p(t); p(t) = exp(-delta^2 / (2 c))
         gsig += gop * pt;
         const double gpt = gop * sig;
@@ -534,7 +534,7 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
         ProjF p;
         project(V, w, p);
         double gmc[3], Sb[3][3], gop;
-        proj_bwd(V, w, p, g3.sh, g3.n, i, g2 + (size_t)v * 9 * N + gidx, (size_t)N, gmc, Sb, gop, gsh);
+        proj_bwd(V, w, p, g3.sh, g3.n, i, g2 + ((size_t)v * N + gidx) * kG2Stride, 1, gmc, Sb, gop, gsh);
         gsig += gop;
         for (int r = 0; r < 3; ++r) {
             gmu[r] += gmc[r];
