@@ -133,8 +133,8 @@ struct Layout {
     // state
     size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_T, st_nc, st_C, state_bytes;
     // scratch, forward use
-    size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_eff2,
-        sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges, sc_tsizes, sc_toff, sc_tpart,
+    size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff,
+        sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges,
         sc_shape, sc_runs, fwd_bytes;
     // scratch, backward use
     size_t sc_g2, bwd_bytes;
@@ -179,12 +179,8 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.total_tiles = tb;
     L.total_supers = sb;
     L.total_pix = pb;
-    int max_tiles = 0, max_super = 0;
-    for (int k = 0; k < L.n_passes(); ++k) {
-        const Pass p = L.pass(k);
-        max_tiles = std::max(max_tiles, p.tiles);
-        max_super = std::max(max_super, p.supers);
-    }
+    int max_super = 0;
+    for (int k = 0; k < L.n_passes(); ++k) max_super = std::max(max_super, L.pass(k).supers);
     const size_t n = (size_t)N, V_ = (size_t)V;
     const size_t np = n * (size_t)L.per_pass;  // Gaussians x views of one pass
     Carve s;
@@ -208,7 +204,6 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_offsets = f.take(8 * (np + 1));
     L.sc_partials = f.take(8 * ((size_t)scan_blocks((int)std::min<size_t>(np, 0x7FFFFFFF)) + 2));
     L.sc_eff = f.take(8);
-    L.sc_eff2 = f.take(8);
     L.sc_pkeys = f.take(4 * (size_t)L.ccap);
     L.sc_pvals = f.take(4 * (size_t)L.ccap);
     L.sc_pkeys2 = f.take(4 * (size_t)L.ccap);
@@ -218,9 +213,6 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
                                     radix_hist_words(n, L.per_pass, kDepthDigitBits)));
     L.sc_totals = f.take(4 * (size_t)kMaxRadix * (size_t)L.per_pass);
     L.sc_cranges = f.take(16 * (size_t)max_super);
-    L.sc_tsizes = f.take(4 * (size_t)max_tiles);
-    L.sc_toff = f.take(8 * ((size_t)max_tiles + 1));
-    L.sc_tpart = f.take(8 * ((size_t)scan_blocks(max_tiles) + 2));
     L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
     L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
     L.fwd_bytes = f.off;
@@ -351,7 +343,6 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     {
         StageScope sc(c, st, H4D_STAGE_BINNING);
         unsigned long long* eff_c = at<unsigned long long>(scratch, L.sc_eff);
-        unsigned long long* eff_r = at<unsigned long long>(scratch, L.sc_eff2);
         uint32_t* cnt = at<uint32_t>(scratch, L.sc_cnt);
         uint64_t* rect = at<uint64_t>(scratch, L.sc_rect);
         unsigned long long* offsets = at<unsigned long long>(scratch, L.sc_offsets);
@@ -364,15 +355,18 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         uint32_t* runs = at<uint32_t>(scratch, L.sc_runs);
         launch_scan_u32_u64(cnt, nullptr, n, offsets, at<unsigned long long>(scratch, L.sc_partials), st, runs,
                             L.ccap / 256 + 1);
-        launch_finalize_coarse(offsets, n, L.ccap, S, status, eff_c, st);
+        launch_finalize_coarse(offsets, n, L.ccap, L.cap, S, pair_base, P.v0, P.v1, status, eff_c, st);
         uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
         uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
         uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
         uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
         launch_coarse_emit(offsets, runs, n, N, rect, shapes, vp, P.v0, tile, S, mkey, L.ccap, eff_c, pk, pv, st);
         // stable sort of the coarse entries by super-tile (depth order kept inside each)
+        // (a single pass over the whole super-tile id also yields each super-tile's
+        // list range; otherwise the ranges come from the sorted keys)
         const int bits = bits_for(P.supers);
         const int passes = n_passes_for(bits, kMaxRadixBits);
+        int64_t* cranges = at<int64_t>(scratch, L.sc_cranges);
         uint32_t* kin = pk;
         uint32_t* vin = pv;
         int shift = 0;
@@ -380,25 +374,21 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
             const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
             uint32_t* kout = (kin == pk) ? pk2 : pk;
             uint32_t* vout = (vin == pv) ? pv2 : pv;
-            launch_radix_pass(kin, vin, kout, vout, eff_c, 0, L.ccap, shift, nb, hist, totals, nullptr, st);
+            launch_radix_pass(kin, vin, kout, vout, eff_c, 0, L.ccap, shift, nb, hist, totals, nullptr, st, 1, 0,
+                              passes == 1 ? cranges : nullptr, P.supers);
             kin = kout;
             vin = vout;
             shift += nb;
         }
-        int64_t* cranges = at<int64_t>(scratch, L.sc_cranges);
-        launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
-        launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, eff_c, nullptr, cranges, st);
-        // per-tile regions sized by the super-tile list, then ordered compaction
-        uint32_t* tsizes = at<uint32_t>(scratch, L.sc_tsizes);
-        unsigned long long* toff = at<unsigned long long>(scratch, L.sc_toff);
-        launch_tile_sizes(cranges, P.tiles, vp, P.v0, P.v1, S, eff_c, tsizes, st);
-        launch_scan_u32_u64(tsizes, nullptr, P.tiles, toff, at<unsigned long long>(scratch, L.sc_tpart), st);
-        launch_finalize_regions(toff, P.tiles, pair_base, P.v0, P.v1, L.cap, status, eff_c, eff_r, st);
+        if (passes > 1) {
+            launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
+            launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, eff_c, nullptr, cranges, st);
+        }
         // the buffer pair the sort did not end in receives (id, tile mask) per coarse entry
         uint32_t* cgid = (kin == pk) ? pk2 : pk;
         uint32_t* cmask = (kin == pk) ? pv2 : pv;
         launch_coarse_gather(kin, vin, rect, dv, N, vp, P.v0, S, mkey, eff_c, cgid, cmask, st);
-        launch_tile_write(cgid, cmask, cranges, toff, pair_base + P.v0, eff_r, P.tiles, vp, P.v0, P.v1, S, ids,
+        launch_tile_write(cgid, cmask, cranges, pair_base + P.v0, eff_c, P.tiles, vp, P.v0, P.v1, S, ids,
                           at<int64_t>(state, L.st_ranges), st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
@@ -466,9 +456,9 @@ h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     const G3Ptr p3 = to_ptr(g3);
     const G4Ptr p4 = to_ptr(g4);
     ViewParams* vp = at<ViewParams>(state, L.st_views);
-    launch_write_views(view_table(views, n_views, cfg->tile), vp, st);
-    launch_zero_status(at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base), n_views, st);
-    launch_fill_u64(at<unsigned long long>(state, L.st_ranges), 2 * (size_t)L.total_tiles, 0ull, st);
+    launch_init_state(view_table(views, n_views, cfg->tile), vp, at<Status>(state, L.st_status),
+                      at<unsigned long long>(state, L.st_pair_base), at<unsigned long long>(state, L.st_ranges),
+                      2 * (size_t)L.total_tiles, st);
     PtrTable tab;
     std::memset(&tab, 0, sizeof(tab));
     for (int v = 0; v < n_views; ++v) tab.p[v] = images[v];
@@ -577,9 +567,9 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     if (!state || state_bytes < L.state_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "state too small");
     if (!scratch || scratch_bytes < L.fwd_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    launch_write_views(view_table(&view, 1, cfg->tile), at<ViewParams>(state, L.st_views), st);
-    launch_zero_status(at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base), 1, st);
-    launch_fill_u64(at<unsigned long long>(state, L.st_ranges), 2 * (size_t)L.total_tiles, 0ull, st);
+    launch_init_state(view_table(&view, 1, cfg->tile), at<ViewParams>(state, L.st_views),
+                      at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base),
+                      at<unsigned long long>(state, L.st_ranges), 2 * (size_t)L.total_tiles, st);
     Rec* recs = at<Rec>(state, L.st_recs);
     launch_splats_to_records(n, u, v, conic, opacity, rgb, radius, depth, visible, width, height, recs,
                              at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);

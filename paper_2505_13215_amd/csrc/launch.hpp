@@ -20,7 +20,9 @@ struct ViewTableIn {
 };
 
 // preprocess.hip
-void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st);
+// The view table, cleared status / list-slot bases and empty tile ranges.
+void launch_init_state(const ViewTableIn& in, ViewParams* views, Status* status, unsigned long long* pair_base,
+                       unsigned long long* ranges, size_t n_range_words, hipStream_t st);
 // Records of views [v0, v0 + nv) (recs: all views, [view][N]); depth keys and
 // ids of view v0 + r at dkeys/dvals + r * N.
 void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,
@@ -49,10 +51,13 @@ size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits);
 // the count.  vals_out index is offset by *out_offset when out_offset != null.
 // hist holds radix_hist_words(capacity, n_seg, nbits) words, totals
 // 2^nbits * n_seg.
+// digit_ranges (may be null): for a pass over whole keys, [start, end) of each
+// of the first n_digit_ranges digits in the output.
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
-                       int n_seg = 1, uint64_t seg_stride = 0);
+                       int n_seg = 1, uint64_t seg_stride = 0, int64_t* digit_ranges = nullptr,
+                       int n_digit_ranges = 0);
 int scan_blocks(int n);
 // out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
 // With run_start, run_start[r] (r < run_cap) receives the index i whose range
@@ -77,7 +82,10 @@ struct CullShape {
 // Super-tile ids are relative to view v0, tile ids t to its first tile.
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
                          uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, hipStream_t st);
-void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
+// Coarse capacity (ccap entries) and list-slot (cap) checks; regions of the
+// pass: S^2 C slots from pair_base[v0], end to pair_base[v1].
+void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t ccap, uint64_t cap, int S,
+                            unsigned long long* pair_base, int v0, int v1, Status* status,
                             unsigned long long* eff_count, hipStream_t st);
 // With mkey (super-tile ids of the pass below 2^16) the keys carry each entry's
 // tile mask in their upper 16 bits (cull: less the tiles no pixel of which can
@@ -86,11 +94,6 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
                         const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
                         int S, int mkey, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys,
                         uint32_t* vals, hipStream_t st);
-void launch_tile_sizes(const int64_t* cranges, int tiles, const ViewParams* views, int v0, int v1, int S,
-                       const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st);
-void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int v0,
-                             int v1, uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
-                             unsigned long long* eff_regions, hipStream_t st);
 // Per coarse entry: the splat id and the 16-bit mask of the super-tile's tiles
 // (bit ly * S + lx) it goes to: from the key's upper half (mkey) or the tiles
 // its pixel square overlaps.
@@ -98,16 +101,15 @@ void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const ui
                           const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S, int mkey,
                           const unsigned long long* eff_count, uint32_t* cgid, uint32_t* cmask, hipStream_t st);
 void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
-                       const unsigned long long* region_off, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_regions, int tiles, const ViewParams* views, int v0, int v1,
-                       int S, uint32_t* ids, int64_t* ranges, hipStream_t st);
+                       const unsigned long long* base_ptr, const unsigned long long* eff_count, int tiles,
+                       const ViewParams* views, int v0, int v1, int S, uint32_t* ids, int64_t* ranges,
+                       hipStream_t st);
 // ranges of sorted keys (compared under key_mask): ranges[2k], ranges[2k+1] =
 // [first, last+1) + *base (base may be null)
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
-void launch_zero_status(Status* s, unsigned long long* pair_base, int n_views, hipStream_t st);
 
 // composite.hip
 bool composite_supported(int tile, int chunk);

@@ -589,8 +589,7 @@ __global__ void __launch_bounds__(128) k_preprocess_bwd3(G3Ptr g3, int n4, int N
 // ---------------------------------------------------------------------------
 // Per-call view table: widened to FP64, camera centre -R^T t, tile bookkeeping.
 // ---------------------------------------------------------------------------
-__global__ void k_write_views(ViewTableIn in, ViewParams* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void write_views(const ViewTableIn& in, ViewParams* out) {
     int tile_base = 0, super_base = 0;
     long long pix_base = 0;
     const int S = super_factor(in.tile);
@@ -623,8 +622,25 @@ __global__ void k_write_views(ViewTableIn in, ViewParams* out) {
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
-void launch_write_views(const ViewTableIn& in, ViewParams* out, hipStream_t st) {
-    k_write_views<<<1, 1, 0, st>>>(in, out);
+// Start of a forward call: the view table, cleared status and list-slot bases,
+// and empty tile ranges, in one launch.
+__global__ void __launch_bounds__(256) k_init_state(ViewTableIn in, ViewParams* views, Status* status,
+                                                    unsigned long long* pair_base,
+                                                    unsigned long long* ranges, size_t n_range_words) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) write_views(in, views);
+        if (threadIdx.x < 8) (&status->flags)[threadIdx.x] = 0ull;
+        for (int v = threadIdx.x; v <= in.n; v += blockDim.x) pair_base[v] = 0ull;
+    }
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_range_words;
+         i += (size_t)gridDim.x * blockDim.x)
+        ranges[i] = 0ull;
+}
+
+void launch_init_state(const ViewTableIn& in, ViewParams* views, Status* status, unsigned long long* pair_base,
+                       unsigned long long* ranges, size_t n_range_words, hipStream_t st) {
+    const int nb = (int)std::max<size_t>(1, std::min<size_t>(1024, (n_range_words + 255) / 256));
+    k_init_state<<<nb, 256, 0, st>>>(in, views, status, pair_base, ranges, n_range_words);
 }
 
 void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,

@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const unsigned long long* dcount, uint64_t hcount, int shift, int nbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int nblocks,
-    const unsigned long long* out_offset, uint64_t seg_stride) {
+    const unsigned long long* out_offset, uint64_t seg_stride, int64_t* __restrict__ digit_ranges, int n_digit_ranges) {
     __shared__ uint32_t s_wcount[4][1 << MB];
     __shared__ uint32_t s_dstart[1 << MB];
     __shared__ uint32_t s_gbase[1 << MB];
@@ -164,6 +164,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] = totals[d];
     __syncthreads();
     block_scan_digits<MB>(s_gbase, radix, s_buf);
+    // a single-pass sort over whole keys: the digit runs are the key ranges
+    if (digit_ranges && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int d = tid; d < n_digit_ranges; d += kSortThreads) {
+            digit_ranges[2 * (size_t)d] = s_gbase[d];
+            digit_ranges[2 * (size_t)d + 1] = (int64_t)s_gbase[d] + totals[d];
+        }
     for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] += hist[(size_t)d * nblocks + blockIdx.x];
 
     // wave w owns items [begin + w*512, begin + (w+1)*512), 8 rounds of 64
@@ -230,7 +236,7 @@ size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits) {
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
-                       int n_seg, uint64_t seg_stride) {
+                       int n_seg, uint64_t seg_stride, int64_t* digit_ranges, int n_digit_ranges) {
     const int nb = radix_blocks(capacity);
     if (nb == 0 || n_seg == 0) return;
     const dim3 grid(nb, n_seg);
@@ -243,11 +249,13 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
     k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount);
     if (nbits <= 8) {
         k_radix_downsweep<8><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount, shift,
-                                                            nbits, hist, totals, nb, out_offset, seg_stride);
+                                                            nbits, hist, totals, nb, out_offset, seg_stride,
+                                                            digit_ranges, n_digit_ranges);
     } else {
         k_radix_downsweep<kMaxRadixBits><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount,
                                                                         hcount, shift, nbits, hist, totals, nb,
-                                                                        out_offset, seg_stride);
+                                                                        out_offset, seg_stride, digit_ranges,
+                                                                        n_digit_ranges);
     }
 }
 
@@ -431,16 +439,24 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
     if (shapes) shapes[j] = cull_shape(rec);
 }
 
-__global__ void k_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
+// Coarse capacity check and tile-list regions of the pass: the S^2 tiles of a
+// super-tile get regions as long as the super-tile's list, so the pass needs
+// S^2 C list slots from pair_base[v0]; their end goes to pair_base[v1].
+__global__ void k_finalize_coarse(const unsigned long long* offsets, int n, uint64_t ccap, uint64_t cap, int S,
+                                  unsigned long long* pair_base, int v0, int v1, Status* status,
                                   unsigned long long* eff_count) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const unsigned long long C = offsets[n];
-    if (C > capacity) {
+    const unsigned long long base = pair_base[v0];
+    const unsigned long long R = C * (unsigned long long)(S * S);
+    status->pairs_needed += R;
+    if (C > ccap || base + R > cap) {
         status->flags |= kFlagOverflow;
-        status->pairs_needed += C * (unsigned long long)(S * S);  // regions hold at most S*S copies
         *eff_count = 0ull;
+        pair_base[v1] = base;
     } else {
         *eff_count = C;
+        pair_base[v1] = base + R;
     }
 }
 
@@ -534,44 +550,6 @@ __device__ __forceinline__ TileLoc locate_tile(const ViewParams* views, int v0, 
     return L;
 }
 
-// Region size of every tile = length of its super-tile's list.
-__global__ void __launch_bounds__(256) k_tile_sizes(const int64_t* __restrict__ cranges, int tiles,
-                                                    const ViewParams* __restrict__ views, int v0, int v1, int S,
-                                                    const unsigned long long* eff_count,
-                                                    uint32_t* __restrict__ sizes) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= tiles) return;
-    if (*eff_count == 0ull) {
-        sizes[t] = 0u;
-        return;
-    }
-    const TileLoc L = locate_tile(views, v0, v1, t, S);
-    sizes[t] = (uint32_t)(cranges[2 * L.st + 1] - cranges[2 * L.st]);
-}
-
-// Regions of the range start at pair_base[v0]; their end goes to pair_base[v1].
-__global__ void k_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base,
-                                   int v0, int v1, uint64_t capacity, Status* status,
-                                   const unsigned long long* eff_coarse, unsigned long long* eff_regions) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long base = pair_base[v0];
-    if (*eff_coarse == 0ull && (status->flags & kFlagOverflow)) {
-        *eff_regions = 0ull;
-        pair_base[v1] = base;
-        return;
-    }
-    const unsigned long long R = region_off[tiles];
-    status->pairs_needed += R;
-    if (base + R > capacity) {
-        status->flags |= kFlagOverflow;
-        *eff_regions = 0ull;
-        pair_base[v1] = base;
-    } else {
-        *eff_regions = 1ull;
-        pair_base[v1] = base + R;
-    }
-}
-
 // After the coarse sort: per coarse entry k (super-tile st, depth rank j) the
 // splat id and its tile mask (bit ly * S + lx of the super-tile): taken from the
 // key's upper half (mkey), or the tiles its pixel square overlaps.  The
@@ -610,25 +588,25 @@ __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restric
 }
 
 // One workgroup per tile: compact, in order, the entries of its super-tile's
-// list whose tile rectangle contains the tile; write the tile's range.  Each
-// round streams 1024 entries (4 per thread, striped) and orders them with wave
-// ballots and one barrier.
+// list whose tile mask holds the tile, into the tile's region (local tile lt of
+// super-tile st: S^2 * start(st) + lt * length(st) past pair_base[v0]); write
+// the tile's range.  Each round streams 1024 entries (4 per thread, striped)
+// and orders them with wave ballots and one barrier.
 __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__ cgid,
                                                     const uint32_t* __restrict__ cmask,
                                                     const int64_t* __restrict__ cranges,
-                                                    const unsigned long long* __restrict__ region_off,
                                                     const unsigned long long* base_ptr,
-                                                    const unsigned long long* eff_regions,
+                                                    const unsigned long long* eff_count,
                                                     const ViewParams* __restrict__ views, int v0, int v1, int S,
                                                     uint32_t* __restrict__ ids, int64_t* __restrict__ ranges) {
     __shared__ uint32_t s_wc[2][4][4];  // [parity][round][wave]
-    if (*eff_regions == 0ull) return;
+    if (*eff_count == 0ull) return;
     const int t = blockIdx.x;
     const TileLoc loc = locate_tile(views, v0, v1, t, S);
     const int st = loc.st;
     const uint32_t bit = (loc.ty % (uint32_t)S) * (uint32_t)S + loc.tx % (uint32_t)S;
     const int64_t cs = cranges[2 * st], ce = cranges[2 * st + 1];
-    const uint64_t out = (uint64_t)*base_ptr + (uint64_t)region_off[t];
+    const uint64_t out = (uint64_t)*base_ptr + (uint64_t)(S * S) * (uint64_t)cs + (uint64_t)bit * (uint64_t)(ce - cs);
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned long long lt = lanemask_lt();
     uint64_t run = 0;
@@ -686,20 +664,16 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 __global__ void k_fill_f32(float* p, size_t n, float val) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = val;
 }
-__global__ void k_zero_status(Status* s, unsigned long long* pair_base, int n_views) {
-    const int t = threadIdx.x;
-    if (t < 8) (&s->flags)[t] = 0ull;
-    for (int v = t; v <= n_views; v += blockDim.x) pair_base[v] = 0ull;
-}
 
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
                          uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, hipStream_t st) {
     if (n == 0) return;
     k_coarse_count<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, n, N, recs, v0, tile, S, cnt, rect_sorted, shapes);
 }
-void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t capacity, int S, Status* status,
+void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t ccap, uint64_t cap, int S,
+                            unsigned long long* pair_base, int v0, int v1, Status* status,
                             unsigned long long* eff_count, hipStream_t st) {
-    k_finalize_coarse<<<1, 1, 0, st>>>(offsets, n, capacity, S, status, eff_count);
+    k_finalize_coarse<<<1, 1, 0, st>>>(offsets, n, ccap, cap, S, pair_base, v0, v1, status, eff_count);
 }
 void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, int N,
                         const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
@@ -710,17 +684,6 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
     k_coarse_emit<<<nb, 256, 0, st>>>(offsets, run_start, n, N, rect_sorted, shapes, views, v0, tile, S, mkey,
                                       eff_count, keys, vals);
 }
-void launch_tile_sizes(const int64_t* cranges, int tiles, const ViewParams* views, int v0, int v1, int S,
-                       const unsigned long long* eff_count, uint32_t* sizes, hipStream_t st) {
-    if (tiles == 0) return;
-    k_tile_sizes<<<ceil_div(tiles, 256), 256, 0, st>>>(cranges, tiles, views, v0, v1, S, eff_count, sizes);
-}
-void launch_finalize_regions(const unsigned long long* region_off, int tiles, unsigned long long* pair_base, int v0,
-                             int v1, uint64_t capacity, Status* status, const unsigned long long* eff_coarse,
-                             unsigned long long* eff_regions, hipStream_t st) {
-    k_finalize_regions<<<1, 1, 0, st>>>(region_off, tiles, pair_base, v0, v1, capacity, status, eff_coarse,
-                                        eff_regions);
-}
 void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
                           const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S, int mkey,
                           const unsigned long long* eff_count, uint32_t* cgid, uint32_t* cmask, hipStream_t st) {
@@ -728,12 +691,11 @@ void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const ui
                                           cgid, cmask);
 }
 void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
-                       const unsigned long long* region_off, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_regions, int tiles, const ViewParams* views, int v0, int v1,
-                       int S, uint32_t* ids, int64_t* ranges, hipStream_t st) {
+                       const unsigned long long* base_ptr, const unsigned long long* eff_count, int tiles,
+                       const ViewParams* views, int v0, int v1, int S, uint32_t* ids, int64_t* ranges,
+                       hipStream_t st) {
     if (tiles == 0) return;
-    k_tile_write<<<tiles, 256, 0, st>>>(cgid, cmask, cranges, region_off, base_ptr, eff_regions, views, v0, v1, S, ids,
-                                        ranges);
+    k_tile_write<<<tiles, 256, 0, st>>>(cgid, cmask, cranges, base_ptr, eff_count, views, v0, v1, S, ids, ranges);
 }
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {
@@ -748,9 +710,6 @@ void launch_fill_f32(float* p, size_t n, float val, hipStream_t st) {
     if (n == 0) return;
     const int nb = (int)std::min<size_t>(8192, (n + 255) / 256);
     k_fill_f32<<<nb, 256, 0, st>>>(p, n, val);
-}
-void launch_zero_status(Status* s, unsigned long long* pair_base, int n_views, hipStream_t st) {
-    k_zero_status<<<1, 64, 0, st>>>(s, pair_base, n_views);
 }
 
 }  // namespace h4d
