@@ -108,6 +108,111 @@ def convert_leg(h4d, torch, rast, g3, g4, reps: int = 5) -> dict:
             "n3_out": int(o3["opacity"].numel())}
 
 
+def _time_steps(torch, fn, steps: int, warmup: int) -> float:
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def hybrid_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
+    """The paper's central comparison (Sec. 4): 500k Gaussians generated all-4D
+    with a static fraction f of long temporal scales; fwd + L1 + bwd per view
+    (1352x1014, one view per step) on the all-4D scene, then after
+    convert_static(0.5) on the hybrid 3D/4D scene, same views."""
+    out = {"workload": "hybrid_ratio_500k_1352x1014"}
+    for f in (0.0, 0.5, 0.9):
+        scene = sg.hybrid_ratio_scene(f)
+        sched = [v[0] for v in sg.view_schedule(scene, steps + warmup, 1, seed=2)]
+        W, H = scene.views[0].width, scene.views[0].height
+        rast = h4d.Rasterizer()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1)
+        target = torch.rand((3, H, W), generator=gen, device="cuda")
+        dl = torch.empty_like(target)
+        row = {}
+        g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+        t0 = time.perf_counter()
+        o3, o4, _ = h4d.convert_static(rast, g3, g4, 0.5)
+        torch.cuda.synchronize()
+        row["convert_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+        for name, (a3, a4) in (("all4d", (g3, g4)), ("hybrid", (o3, o4))):
+            it = {"i": 0}
+            gr = ({k: torch.empty_like(v) for k, v in a3.items()}, {k: torch.empty_like(v) for k, v in a4.items()})
+            rast.check_mode = "eager"
+            rast.forward(a3, a4, [sched[0]])
+            torch.cuda.synchronize()
+            rast.capacity = int(rast.last_pairs * 1.5) + 4096
+            rast.check_mode = "deferred"
+
+            def step():
+                v = sched[it["i"] % len(sched)]
+                it["i"] += 1
+                h = rast.forward(a3, a4, [v])
+                h4d.l1_loss_grad(rast, h.images, [target], [v], [dl], None)
+                rast.backward(h, a3, a4, [dl], out=gr)
+
+            dt = _time_steps(torch, step, steps, warmup)
+            rast.verify()
+            row[name] = {"ms_per_step": round(dt * 1e3, 4), "mpix_s": round(W * H / dt / 1e6, 2),
+                         "n3": int(a3["opacity"].numel()), "n4": int(a4["opacity"].numel())}
+        row["speedup"] = round(row["all4d"]["ms_per_step"] / row["hybrid"]["ms_per_step"], 3)
+        out[f"static_fraction_{f}"] = row
+        del g3, g4, o3, o4, rast
+        torch.cuda.empty_cache()
+    return out
+
+
+def training_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
+    """2M Gaussians (85 % static), 2704x2028, 4 views per step drawn from 20
+    cameras x 300 frame times, all views in one launch per stage (batched):
+    fwd + L1 + bwd + Adam over all parameters."""
+    scene = sg.training_scene()
+    sched = sg.view_schedule(scene, steps + warmup, 4, seed=2)
+    W, H = scene.views[0].width, scene.views[0].height
+    g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+    n_gauss = scene.n3 + scene.n4
+    del scene
+    gr3 = {k: torch.empty_like(v) for k, v in g3.items()}
+    gr4 = {k: torch.empty_like(v) for k, v in g4.items()}
+    keys = [("3", k) for k in h4d.G3_KEYS] + [("4", k) for k in h4d.G4_KEYS]
+    params = [(g3 if w == "3" else g4)[k] for w, k in keys]
+    grads = [(gr3 if w == "3" else gr4)[k] for w, k in keys]
+    ms = [torch.zeros_like(p) for p in params]
+    vs = [torch.zeros_like(p) for p in params]
+    lrs = [(LR3 if w == "3" else LR4)[k] for w, k in keys]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    targets = [torch.rand((3, H, W), generator=gen, device="cuda") for _ in range(4)]
+    dls = [torch.empty_like(t) for t in targets]
+    rast = h4d.Rasterizer(batched=True)
+    rast.forward(g3, g4, sched[0])
+    torch.cuda.synchronize()
+    rast.capacity = int(rast.last_pairs * 1.3) + 4096
+    rast.check_mode = "deferred"
+    it = {"i": 0, "step": 0}
+
+    def step():
+        views = sched[it["i"] % len(sched)]
+        it["i"] += 1
+        h = rast.forward(g3, g4, views)
+        h4d.l1_loss_grad(rast, h.images, targets, views, dls, None)
+        rast.backward(h, g3, g4, dls, out=(gr3, gr4))
+        it["step"] += 1
+        h4d.adam_step(rast, params, grads, ms, vs, lrs, it["step"])
+
+    dt = _time_steps(torch, step, steps, warmup)
+    rast.verify()
+    mpix = 4 * W * H / 1e6
+    return {"workload": "training_2M_2704x2028_4_views", "gaussians": n_gauss, "ms_per_step": round(dt * 1e3, 3),
+            "mpix_s": round(mpix / dt, 2), "views_per_step": 4, "step": "fwd+L1+bwd+Adam, batched",
+            "pairs_per_step": rast.last_pairs}
+
+
 def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
     """fwd + L1 + bwd over 32 views per call (1M Gaussians, 80 % static; 8 arc
     cameras, four at 1352x1014 and four at 2704x2028, times 0.125 ... 0.875):
@@ -182,6 +287,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=16)
     ap.add_argument("--stats-views", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs single-view leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the hybrid-ratio and 2M training legs")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run one plain device copy of MIB MiB (a known-size reference for counters)")
@@ -313,6 +419,17 @@ def main():
         batched = batched_leg(h4d, torch, sg, args.batched_steps, 1)
         log(f"batched vs single-view: {batched}")
 
+    hybrid = training = None
+    if not args.no_extra:
+        log("hybrid-ratio leg: 500k all-4D vs converted, f = 0, 0.5, 0.9")
+        hybrid = hybrid_leg(h4d, torch, sg, 10, 3)
+        log(f"hybrid: {hybrid}")
+        torch.cuda.empty_cache()
+        log("training leg: 2M Gaussians, 2704x2028, 4 views per step")
+        training = training_leg(h4d, torch, sg, 5, 2)
+        log(f"training: {training}")
+        torch.cuda.empty_cache()
+
     if args.calibrate_copy > 0:
         nbytes = args.calibrate_copy << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -343,6 +460,8 @@ def main():
         "pairs_per_view_max": peak_pairs,
         "convert_static": conv,
         "batched_vs_single": batched,
+        "hybrid_ratio": hybrid,
+        "training_2m": training,
     }
     print(json.dumps(out), flush=True)
 
