@@ -384,12 +384,11 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
             launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
             launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, eff_c, nullptr, cranges, st);
         }
-        // the buffer pair the sort did not end in receives (id, tile mask) per coarse entry
+        // splat ids of the sorted entries into the buffer the sort did not end in
         uint32_t* cgid = (kin == pk) ? pk2 : pk;
-        uint32_t* cmask = (kin == pk) ? pv2 : pv;
-        launch_coarse_gather(kin, vin, rect, dv, N, vp, P.v0, S, mkey, eff_c, cgid, cmask, st);
-        launch_tile_write(cgid, cmask, cranges, pair_base + P.v0, eff_c, P.tiles, vp, P.v0, P.v1, S, ids,
-                          at<int64_t>(state, L.st_ranges), st);
+        launch_coarse_gather(vin, dv, eff_c, cgid, st);
+        launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, eff_c, P.tiles, vp, P.v0, P.v1, S,
+                          ids, at<int64_t>(state, L.st_ranges), st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
     launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles, images,

@@ -94,16 +94,16 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
                         const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
                         int S, int mkey, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys,
                         uint32_t* vals, hipStream_t st);
-// Per coarse entry: the splat id and the 16-bit mask of the super-tile's tiles
-// (bit ly * S + lx) it goes to: from the key's upper half (mkey) or the tiles
-// its pixel square overlaps.
-void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S, int mkey,
-                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* cmask, hipStream_t st);
-void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
-                       const unsigned long long* base_ptr, const unsigned long long* eff_count, int tiles,
-                       const ViewParams* views, int v0, int v1, int S, uint32_t* ids, int64_t* ranges,
-                       hipStream_t st);
+// cgid[k] = splat id of sorted coarse entry k (values = depth ranks).
+void launch_coarse_gather(const uint32_t* cvals, const uint32_t* sorted_gid, const unsigned long long* eff_count,
+                          uint32_t* cgid, hipStream_t st);
+// Per tile: the splats of its super-tile's sorted coarse list that go to it
+// (the mask in the keys' upper half with mkey, else the square overlap), in
+// order, into its region; writes ranges[tile].
+void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
+                       const uint32_t* cgid, int mkey, const int64_t* cranges, const unsigned long long* base_ptr,
+                       const unsigned long long* eff_count, int tiles, const ViewParams* views, int v0, int v1, int S,
+                       uint32_t* ids, int64_t* ranges, hipStream_t st);
 // ranges of sorted keys (compared under key_mask): ranges[2k], ranges[2k+1] =
 // [first, last+1) + *base (base may be null)
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,

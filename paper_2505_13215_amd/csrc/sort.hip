@@ -240,23 +240,21 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
     const int nb = radix_blocks(capacity);
     if (nb == 0 || n_seg == 0) return;
     const dim3 grid(nb, n_seg);
-    if (nbits <= 8) {
-        k_radix_upsweep<8><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb, seg_stride);
-    } else {
-        k_radix_upsweep<kMaxRadixBits><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,
-                                                                      seg_stride);
-    }
-    k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount);
-    if (nbits <= 8) {
-        k_radix_downsweep<8><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount, shift,
-                                                            nbits, hist, totals, nb, out_offset, seg_stride,
-                                                            digit_ranges, n_digit_ranges);
-    } else {
-        k_radix_downsweep<kMaxRadixBits><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount,
-                                                                        hcount, shift, nbits, hist, totals, nb,
-                                                                        out_offset, seg_stride, digit_ranges,
-                                                                        n_digit_ranges);
-    }
+    // the smallest instantiation that holds the digit (LDS is sized by it)
+#define H4D_RADIX_PASS(MB)                                                                                          \
+    do {                                                                                                             \
+        k_radix_upsweep<MB><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,         \
+                                                          seg_stride);                                             \
+        k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount);  \
+        k_radix_downsweep<MB><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount,  \
+                                                            shift, nbits, hist, totals, nb, out_offset, seg_stride, \
+                                                            digit_ranges, n_digit_ranges);                         \
+    } while (0)
+    if (nbits <= 8) H4D_RADIX_PASS(8);
+    else if (nbits == 9) H4D_RADIX_PASS(9);
+    else if (nbits == 10) H4D_RADIX_PASS(10);
+    else H4D_RADIX_PASS(kMaxRadixBits);
+#undef H4D_RADIX_PASS
 }
 
 // ---------------------------------------------------------------------------
@@ -550,50 +548,30 @@ __device__ __forceinline__ TileLoc locate_tile(const ViewParams* views, int v0, 
     return L;
 }
 
-// After the coarse sort: per coarse entry k (super-tile st, depth rank j) the
-// splat id and its tile mask (bit ly * S + lx of the super-tile): taken from the
-// key's upper half (mkey), or the tiles its pixel square overlaps.  The
-// per-tile pass then streams 8 bytes per entry.
-__global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ ckeys,
-                                                       const uint32_t* __restrict__ cvals,
-                                                       const uint64_t* __restrict__ rect_sorted,
-                                                       const uint32_t* __restrict__ sorted_gid, int N,
-                                                       const ViewParams* __restrict__ views, int v0, int S, int mkey,
+// After the coarse sort: the splat id of every coarse entry, so that the
+// per-tile pass (16 tiles read each entry) needs no further indirection.
+__global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ cvals,
+                                                       const uint32_t* __restrict__ sorted_gid,
                                                        const unsigned long long* eff_count,
-                                                       uint32_t* __restrict__ cgid, uint32_t* __restrict__ cmask) {
+                                                       uint32_t* __restrict__ cgid) {
     const uint64_t n = *eff_count;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t j = cvals[k];
-        const uint32_t key = ckeys[k];
-        uint32_t mask;
-        if (mkey) {
-            mask = key >> 16;
-        } else {
-            const ViewParams& V = views[v0 + (int)(j / (uint32_t)N)];
-            const uint32_t st = key - (uint32_t)(V.super_base - views[v0].super_base);
-            const uint64_t r = rect_sorted[j];
-            const uint32_t SX = (uint32_t)V.sx;
-            const uint32_t bx = (st % SX) * (uint32_t)S, by = (st / SX) * (uint32_t)S;
-            const uint32_t x0 = (uint32_t)(r & 0xFFFFu), x1 = (uint32_t)((r >> 16) & 0xFFFFu);
-            const uint32_t y0 = (uint32_t)((r >> 32) & 0xFFFFu), y1 = (uint32_t)(r >> 48);
-            const uint32_t lx0 = max(x0, bx) - bx, lx1 = min(x1, bx + (uint32_t)S - 1u) - bx;
-            const uint32_t ly0 = max(y0, by) - by, ly1 = min(y1, by + (uint32_t)S - 1u) - by;
-            mask = 0u;
-            for (uint32_t ly = ly0; ly <= ly1; ++ly)
-                for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
-        }
-        cgid[k] = sorted_gid[j];
-        cmask[k] = mask;
-    }
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+        cgid[k] = sorted_gid[cvals[k]];
 }
 
 // One workgroup per tile: compact, in order, the entries of its super-tile's
 // list whose tile mask holds the tile, into the tile's region (local tile lt of
 // super-tile st: S^2 * start(st) + lt * length(st) past pair_base[v0]); write
-// the tile's range.  Each round streams 1024 entries (4 per thread, striped)
-// and orders them with wave ballots and one barrier.
-__global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__ cgid,
-                                                    const uint32_t* __restrict__ cmask,
+// the tile's range.  A sorted coarse entry k holds the super-tile (and, with
+// mkey, the tile mask in the upper 16 bits) in ckeys[k], its depth rank j in
+// cvals[k] and its splat id in cgid[k]; without mkey the mask is the tiles the
+// splat's square overlaps.
+// Each round streams 1024 entries (4 per thread, striped) and orders them with
+// wave ballots and one barrier.
+__global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__ ckeys,
+                                                    const uint32_t* __restrict__ cvals,
+                                                    const uint64_t* __restrict__ rect_sorted,
+                                                    const uint32_t* __restrict__ cgid, int mkey,
                                                     const int64_t* __restrict__ cranges,
                                                     const unsigned long long* base_ptr,
                                                     const unsigned long long* eff_count,
@@ -604,7 +582,8 @@ __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__
     const int t = blockIdx.x;
     const TileLoc loc = locate_tile(views, v0, v1, t, S);
     const int st = loc.st;
-    const uint32_t bit = (loc.ty % (uint32_t)S) * (uint32_t)S + loc.tx % (uint32_t)S;
+    const uint32_t lx = loc.tx % (uint32_t)S, ly = loc.ty % (uint32_t)S;
+    const uint32_t bit = ly * (uint32_t)S + lx;
     const int64_t cs = cranges[2 * st], ce = cranges[2 * st + 1];
     const uint64_t out = (uint64_t)*base_ptr + (uint64_t)(S * S) * (uint64_t)cs + (uint64_t)bit * (uint64_t)(ce - cs);
     const int tid = threadIdx.x, w = tid >> 6;
@@ -620,7 +599,13 @@ __global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__
             ov[r] = false;
             gid[r] = 0;
             if (k < ce) {
-                ov[r] = (cmask[k] >> bit) & 1u;
+                if (mkey) {
+                    ov[r] = (ckeys[k] >> (16u + bit)) & 1u;
+                } else {  // square overlap: the splat's tile rectangle holds the tile
+                    const uint64_t rc = rect_sorted[cvals[k]];
+                    ov[r] = loc.tx >= (uint32_t)(rc & 0xFFFFu) && loc.tx <= (uint32_t)((rc >> 16) & 0xFFFFu) &&
+                            loc.ty >= (uint32_t)((rc >> 32) & 0xFFFFu) && loc.ty <= (uint32_t)(rc >> 48);
+                }
                 if (ov[r]) gid[r] = cgid[k];
             }
             bal[r] = __ballot(ov[r]);
@@ -684,18 +669,17 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
     k_coarse_emit<<<nb, 256, 0, st>>>(offsets, run_start, n, N, rect_sorted, shapes, views, v0, tile, S, mkey,
                                       eff_count, keys, vals);
 }
-void launch_coarse_gather(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                          const uint32_t* sorted_gid, int N, const ViewParams* views, int v0, int S, int mkey,
-                          const unsigned long long* eff_count, uint32_t* cgid, uint32_t* cmask, hipStream_t st) {
-    k_coarse_gather<<<2048, 256, 0, st>>>(ckeys, cvals, rect_sorted, sorted_gid, N, views, v0, S, mkey, eff_count,
-                                          cgid, cmask);
+void launch_coarse_gather(const uint32_t* cvals, const uint32_t* sorted_gid, const unsigned long long* eff_count,
+                          uint32_t* cgid, hipStream_t st) {
+    k_coarse_gather<<<2048, 256, 0, st>>>(cvals, sorted_gid, eff_count, cgid);
 }
-void launch_tile_write(const uint32_t* cgid, const uint32_t* cmask, const int64_t* cranges,
-                       const unsigned long long* base_ptr, const unsigned long long* eff_count, int tiles,
-                       const ViewParams* views, int v0, int v1, int S, uint32_t* ids, int64_t* ranges,
-                       hipStream_t st) {
+void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
+                       const uint32_t* cgid, int mkey, const int64_t* cranges, const unsigned long long* base_ptr,
+                       const unsigned long long* eff_count, int tiles, const ViewParams* views, int v0, int v1, int S,
+                       uint32_t* ids, int64_t* ranges, hipStream_t st) {
     if (tiles == 0) return;
-    k_tile_write<<<tiles, 256, 0, st>>>(cgid, cmask, cranges, base_ptr, eff_count, views, v0, v1, S, ids, ranges);
+    k_tile_write<<<tiles, 256, 0, st>>>(ckeys, cvals, rect_sorted, cgid, mkey, cranges, base_ptr, eff_count, views,
+                                        v0, v1, S, ids, ranges);
 }
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {
