@@ -114,6 +114,7 @@ int bits_for(int n) {
 // near-equal width.  The depth sort uses 8-bit digits (its blocks are few and a
 // wide digit's per-block cost dominates); the super-tile sort up to 11.
 constexpr int kDepthDigitBits = 8;
+constexpr int kDepthSortItems = 2;  // 512 keys per block: ~500 blocks for 250k Gaussians
 int n_passes_for(int bits, int width) { return (bits + width - 1) / width; }
 int pass_bits(int bits, int width) { return (bits + n_passes_for(bits, width) - 1) / n_passes_for(bits, width); }
 
@@ -209,8 +210,8 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_pkeys2 = f.take(4 * (size_t)L.ccap);
     L.sc_pvals2 = f.take(4 * (size_t)L.ccap);
     const int cbits = pass_bits(bits_for(max_super), kMaxRadixBits);
-    L.sc_hist = f.take(4 * std::max(radix_hist_words(L.ccap, 1, cbits),
-                                    radix_hist_words(n, L.per_pass, kDepthDigitBits)));
+    L.sc_hist = f.take(4 * std::max(radix_hist_words(L.ccap, 1, cbits, kSortItems),
+                                    radix_hist_words(n, L.per_pass, kDepthDigitBits, kDepthSortItems)));
     L.sc_totals = f.take(4 * (size_t)kMaxRadix * (size_t)L.per_pass);
     L.sc_cranges = f.take(16 * (size_t)max_super);
     L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
@@ -329,7 +330,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         for (int pass = 0; pass < passes; ++pass) {
             const int nb = (32 - shift + (passes - pass) - 1) / (passes - pass);
             launch_radix_pass(dk, dv, dk2, dv2, nullptr, (uint64_t)N, (uint64_t)N, shift, nb, hist, totals, nullptr,
-                              st, nv, (uint64_t)N);
+                              st, nv, (uint64_t)N, nullptr, 0, kDepthSortItems);
             std::swap(dk, dk2);
             std::swap(dv, dv2);
             shift += nb;

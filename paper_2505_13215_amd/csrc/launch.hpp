@@ -42,22 +42,24 @@ constexpr int kScanTile = 2048;
 constexpr int kMaxRadixBits = 11;
 constexpr int kMaxRadix = 1 << kMaxRadixBits;
 
-int radix_blocks(uint64_t capacity);
+// blocks of one pass over `capacity` keys with `items` keys per thread
+int radix_blocks(uint64_t capacity, int items);
 // words of `hist` for passes of up to max_bits bits
-size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits);
+size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits, int items);
 // One stable LSD pass over `nbits` (<= 11) bits at `shift`, independently on
 // n_seg segments that start seg_stride elements apart (all arrays).  Count
 // (per segment) from *dcount when dcount != null, else hcount; capacity bounds
 // the count.  vals_out index is offset by *out_offset when out_offset != null.
-// hist holds radix_hist_words(capacity, n_seg, nbits) words, totals
-// 2^nbits * n_seg.
+// hist holds radix_hist_words(capacity, n_seg, nbits, items) words, totals
+// 2^nbits * n_seg.  items: keys per thread, kSortItems or 2 (8-bit digits
+// only; for short key sets, more and smaller blocks).
 // digit_ranges (may be null): for a pass over whole keys, [start, end) of each
 // of the first n_digit_ranges digits in the output.
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
                        int n_seg = 1, uint64_t seg_stride = 0, int64_t* digit_ranges = nullptr,
-                       int n_digit_ranges = 0);
+                       int n_digit_ranges = 0, int items = kSortItems);
 int scan_blocks(int n);
 // out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
 // With run_start, run_start[r] (r < run_cap) receives the index i whose range

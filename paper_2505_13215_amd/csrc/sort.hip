@@ -78,7 +78,7 @@ __device__ inline uint32_t block_scan_digits(uint32_t* s, int radix, uint32_t* s
 }
 
 // MB: largest digit width the instantiation handles (LDS is sized for it).
-template <int MB>
+template <int MB, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                                 const unsigned long long* dcount, uint64_t hcount,
                                                                 int shift, int nbits, uint32_t* __restrict__ hist,
@@ -90,11 +90,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* 
     const uint32_t mask = (uint32_t)radix - 1u;
     const int tid = threadIdx.x, w = tid >> 6;
     const uint64_t n = read_count(dcount, hcount);
-    const uint64_t begin = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t begin = (uint64_t)blockIdx.x * (kSortThreads * ITEMS);
     if (begin >= n) return;  // blocks past the live count are never scanned (uniform)
     for (int d = tid; d < 4 * radix; d += kSortThreads) s_hist[d / radix][d % radix] = 0;
     __syncthreads();
-    for (int k = 0; k < kSortItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         const uint64_t idx = begin + (uint64_t)k * kSortThreads + tid;
         if (idx < n) atomicAdd(&s_hist[w][(keys[idx] >> shift) & mask], 1u);
     }
@@ -107,10 +107,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* 
 // counts over the blocks that hold live keys (4 counts per thread per round)
 __global__ void __launch_bounds__(256) k_radix_digit_scan(uint32_t* __restrict__ hist, int nblocks, int radix,
                                                           uint32_t* __restrict__ totals,
-                                                          const unsigned long long* dcount, uint64_t hcount) {
+                                                          const unsigned long long* dcount, uint64_t hcount,
+                                                          int tile) {
     __shared__ uint32_t s_buf[256];
     const uint64_t n = read_count(dcount, hcount);
-    const int live = (int)min((uint64_t)nblocks, (n + kSortTile - 1) / kSortTile);
+    const int live = (int)min((uint64_t)nblocks, (n + tile - 1) / tile);
     uint32_t* h = hist + (size_t)blockIdx.y * radix * nblocks + (size_t)blockIdx.x * nblocks;
     totals += (size_t)blockIdx.y * radix;
     uint32_t carry = 0;
@@ -133,7 +134,7 @@ __global__ void __launch_bounds__(256) k_radix_digit_scan(uint32_t* __restrict__
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-template <int MB>
+template <int MB, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const unsigned long long* dcount, uint64_t hcount, int shift, int nbits,
@@ -143,11 +144,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     __shared__ uint32_t s_dstart[1 << MB];
     __shared__ uint32_t s_gbase[1 << MB];
     __shared__ uint32_t s_buf[256];
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    constexpr int TILE = kSortThreads * ITEMS;
+    __shared__ uint32_t s_keys[TILE];
+    __shared__ uint32_t s_vals[TILE];
 
     const uint64_t n = read_count(dcount, hcount);
-    const uint64_t begin = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t begin = (uint64_t)blockIdx.x * TILE;
     if (begin >= n) return;  // uniform over the block
     const int radix = 1 << nbits;
     {
@@ -172,11 +174,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         }
     for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] += hist[(size_t)d * nblocks + blockIdx.x];
 
-    // wave w owns items [begin + w*512, begin + (w+1)*512), 8 rounds of 64
-    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    // wave w owns items [begin + w * 64 ITEMS, begin + (w + 1) * 64 ITEMS), ITEMS rounds of 64
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
     const unsigned long long lt = lanemask_lt();
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t idx = begin + (uint64_t)w * (kSortItems * 64) + (uint64_t)r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint64_t idx = begin + (uint64_t)w * (ITEMS * 64) + (uint64_t)r * 64 + lane;
         const bool valid = idx < n;
         key[r] = valid ? keys_in[idx] : 0u;
         val[r] = valid ? vals_in[idx] : 0u;
@@ -207,8 +209,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     }
     __syncthreads();
     block_scan_digits<MB>(s_dstart, radix, s_buf);
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t idx = begin + (uint64_t)w * (kSortItems * 64) + (uint64_t)r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint64_t idx = begin + (uint64_t)w * (ITEMS * 64) + (uint64_t)r * 64 + lane;
         if (idx < n) {
             const uint32_t d = (key[r] >> shift) & mask;
             const uint32_t pos = s_dstart[d] + s_wcount[w][d] + rank[r];
@@ -217,7 +219,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         }
     }
     __syncthreads();
-    const int cnt = (int)min((uint64_t)kSortTile, n - begin);
+    const int cnt = (int)min((uint64_t)TILE, n - begin);
     const unsigned long long off = out_offset ? *out_offset : 0ull;
     for (int p = tid; p < cnt; p += kSortThreads) {
         const uint32_t k = s_keys[p];
@@ -228,32 +230,40 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     }
 }
 
-int radix_blocks(uint64_t capacity) { return (int)((capacity + kSortTile - 1) / kSortTile); }
-size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits) {
-    return ((size_t)1 << max_bits) * (size_t)std::max(1, radix_blocks(capacity)) * (size_t)std::max(1, n_seg);
+int radix_blocks(uint64_t capacity, int items) {
+    const uint64_t tile = (uint64_t)kSortThreads * items;
+    return (int)((capacity + tile - 1) / tile);
+}
+size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits, int items) {
+    return ((size_t)1 << max_bits) * (size_t)std::max(1, radix_blocks(capacity, items)) * (size_t)std::max(1, n_seg);
 }
 
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
-                       int n_seg, uint64_t seg_stride, int64_t* digit_ranges, int n_digit_ranges) {
-    const int nb = radix_blocks(capacity);
+                       int n_seg, uint64_t seg_stride, int64_t* digit_ranges, int n_digit_ranges, int items) {
+    const int nb = radix_blocks(capacity, items);
     if (nb == 0 || n_seg == 0) return;
     const dim3 grid(nb, n_seg);
     // the smallest instantiation that holds the digit (LDS is sized by it)
-#define H4D_RADIX_PASS(MB)                                                                                          \
-    do {                                                                                                             \
-        k_radix_upsweep<MB><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,         \
-                                                          seg_stride);                                             \
-        k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount);  \
-        k_radix_downsweep<MB><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount, hcount,  \
-                                                            shift, nbits, hist, totals, nb, out_offset, seg_stride, \
-                                                            digit_ranges, n_digit_ranges);                         \
+#define H4D_RADIX_PASS(MB, IT)                                                                                       \
+    do {                                                                                                              \
+        k_radix_upsweep<MB, IT><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,       \
+                                                              seg_stride);                                           \
+        k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount,    \
+                                                                    kSortThreads * IT);                              \
+        k_radix_downsweep<MB, IT><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount,        \
+                                                                hcount, shift, nbits, hist, totals, nb, out_offset,   \
+                                                                seg_stride, digit_ranges, n_digit_ranges);            \
     } while (0)
-    if (nbits <= 8) H4D_RADIX_PASS(8);
-    else if (nbits == 9) H4D_RADIX_PASS(9);
-    else if (nbits == 10) H4D_RADIX_PASS(10);
-    else H4D_RADIX_PASS(kMaxRadixBits);
+    if (items == 2 && nbits <= 8) {
+        H4D_RADIX_PASS(8, 2);  // short key sets: more, smaller blocks
+    } else {  // (a grid sized for smaller blocks only adds blocks past the live count)
+        if (nbits <= 8) H4D_RADIX_PASS(8, kSortItems);
+        else if (nbits == 9) H4D_RADIX_PASS(9, kSortItems);
+        else if (nbits == 10) H4D_RADIX_PASS(10, kSortItems);
+        else H4D_RADIX_PASS(kMaxRadixBits, kSortItems);
+    }
 #undef H4D_RADIX_PASS
 }
 
