@@ -388,7 +388,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         // splat ids of the sorted entries into the buffer the sort did not end in
         uint32_t* cgid = (kin == pk) ? pk2 : pk;
         launch_coarse_gather(vin, dv, eff_c, cgid, st);
-        launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, eff_c, P.tiles, vp, P.v0, P.v1, S,
+        launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, eff_c, P.supers, vp, P.v0, P.v1, S,
                           ids, at<int64_t>(state, L.st_ranges), st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);

@@ -99,12 +99,13 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
 // cgid[k] = splat id of sorted coarse entry k (values = depth ranks).
 void launch_coarse_gather(const uint32_t* cvals, const uint32_t* sorted_gid, const unsigned long long* eff_count,
                           uint32_t* cgid, hipStream_t st);
-// Per tile: the splats of its super-tile's sorted coarse list that go to it
-// (the mask in the keys' upper half with mkey, else the square overlap), in
-// order, into its region; writes ranges[tile].
+// Per tile (one workgroup per super-tile of the pass): the splats of its
+// super-tile's sorted coarse list that go to it (the mask in the keys' upper
+// half with mkey, else the square overlap), in order, into its region; writes
+// ranges[tile].
 void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
                        const uint32_t* cgid, int mkey, const int64_t* cranges, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_count, int tiles, const ViewParams* views, int v0, int v1, int S,
+                       const unsigned long long* eff_count, int supers, const ViewParams* views, int v0, int v1, int S,
                        uint32_t* ids, int64_t* ranges, hipStream_t st);
 // ranges of sorted keys (compared under key_mask): ranges[2k], ranges[2k+1] =
 // [first, last+1) + *base (base may be null)

@@ -539,25 +539,6 @@ __global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* _
     }
 }
 
-// Global tile id of tile t (relative to the range) -> its view, local tile
-// coordinates and super-tile id relative to the range.
-struct TileLoc {
-    int view, gt;
-    uint32_t tx, ty;
-    int st;
-};
-__device__ __forceinline__ TileLoc locate_tile(const ViewParams* views, int v0, int v1, int t, int S) {
-    TileLoc L;
-    L.gt = views[v0].tile_base + t;
-    L.view = find_view_of_tile(views, v0, v1, L.gt);
-    const ViewParams& V = views[L.view];
-    const int lt = L.gt - V.tile_base;
-    L.tx = (uint32_t)(lt % V.tiles_x);
-    L.ty = (uint32_t)(lt / V.tiles_x);
-    L.st = (V.super_base - views[v0].super_base) + (int)(L.ty / (uint32_t)S) * V.sx + (int)(L.tx / (uint32_t)S);
-    return L;
-}
-
 // After the coarse sort: the splat id of every coarse entry, so that the
 // per-tile pass (16 tiles read each entry) needs no further indirection.
 __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ cvals,
@@ -569,75 +550,78 @@ __global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restric
         cgid[k] = sorted_gid[cvals[k]];
 }
 
-// One workgroup per tile: compact, in order, the entries of its super-tile's
-// list whose tile mask holds the tile, into the tile's region (local tile lt of
-// super-tile st: S^2 * start(st) + lt * length(st) past pair_base[v0]); write
-// the tile's range.  A sorted coarse entry k holds the super-tile (and, with
-// mkey, the tile mask in the upper 16 bits) in ckeys[k], its depth rank j in
-// cvals[k] and its splat id in cgid[k]; without mkey the mask is the tiles the
-// splat's square overlaps.
-// Each round streams 1024 entries (4 per thread, striped) and orders them with
-// wave ballots and one barrier.
-__global__ void __launch_bounds__(256) k_tile_write(const uint32_t* __restrict__ ckeys,
-                                                    const uint32_t* __restrict__ cvals,
-                                                    const uint64_t* __restrict__ rect_sorted,
-                                                    const uint32_t* __restrict__ cgid, int mkey,
-                                                    const int64_t* __restrict__ cranges,
-                                                    const unsigned long long* base_ptr,
-                                                    const unsigned long long* eff_count,
-                                                    const ViewParams* __restrict__ views, int v0, int v1, int S,
-                                                    uint32_t* __restrict__ ids, int64_t* __restrict__ ranges) {
-    __shared__ uint32_t s_wc[2][4][4];  // [parity][round][wave]
+// One workgroup per super-tile, one wave per tile of it (S^2 waves): every
+// round the block stages blockDim entries of the super-tile's sorted coarse
+// list (tile mask, splat id) in LDS, and each wave compacts, in order, the
+// entries whose mask holds its tile into the tile's region (local tile lt:
+// S^2 * start + lt * length past pair_base[v0]), then writes the tile's range.
+// With mkey the mask is in the keys' upper 16 bits; otherwise it is the tiles
+// the splat's square overlaps.
+__global__ void __launch_bounds__(1024) k_tile_write(const uint32_t* __restrict__ ckeys,
+                                                     const uint32_t* __restrict__ cvals,
+                                                     const uint64_t* __restrict__ rect_sorted,
+                                                     const uint32_t* __restrict__ cgid, int mkey,
+                                                     const int64_t* __restrict__ cranges,
+                                                     const unsigned long long* base_ptr,
+                                                     const unsigned long long* eff_count,
+                                                     const ViewParams* __restrict__ views, int v0, int v1, int S,
+                                                     uint32_t* __restrict__ ids, int64_t* __restrict__ ranges) {
+    __shared__ uint32_t s_mask[1024];
+    __shared__ uint32_t s_gid[1024];
     if (*eff_count == 0ull) return;
-    const int t = blockIdx.x;
-    const TileLoc loc = locate_tile(views, v0, v1, t, S);
-    const int st = loc.st;
-    const uint32_t lx = loc.tx % (uint32_t)S, ly = loc.ty % (uint32_t)S;
-    const uint32_t bit = ly * (uint32_t)S + lx;
+    const int st = blockIdx.x;  // super-tile, relative to view v0's first
+    // its view: the last view of the pass whose first super-tile is <= st
+    int view = v0;
+    while (view + 1 < v1 && views[view + 1].super_base - views[v0].super_base <= st) ++view;
+    const ViewParams& V = views[view];
+    const int stl = st - (V.super_base - views[v0].super_base);
+    const uint32_t SX = (uint32_t)V.sx;
+    const uint32_t bx = (uint32_t)(stl % (int)SX) * (uint32_t)S, by = (uint32_t)(stl / (int)SX) * (uint32_t)S;
+    const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
+    const uint32_t lx = (uint32_t)w % (uint32_t)S, ly = (uint32_t)w / (uint32_t)S;
+    const uint32_t tx = bx + lx, ty = by + ly;
+    const bool exists = tx < (uint32_t)V.tiles_x && ty < (uint32_t)V.tiles_y;  // edge super-tiles are partial
     const int64_t cs = cranges[2 * st], ce = cranges[2 * st + 1];
-    const uint64_t out = (uint64_t)*base_ptr + (uint64_t)(S * S) * (uint64_t)cs + (uint64_t)bit * (uint64_t)(ce - cs);
-    const int tid = threadIdx.x, w = tid >> 6;
+    const uint64_t out = (uint64_t)*base_ptr + (uint64_t)(S * S) * (uint64_t)cs + (uint64_t)w * (uint64_t)(ce - cs);
     const unsigned long long lt = lanemask_lt();
+    const int round = blockDim.x;
     uint64_t run = 0;
-    int parity = 0;
-    for (int64_t k0 = cs; k0 < ce; k0 += 1024, parity ^= 1) {
-        uint32_t gid[4];
-        unsigned long long bal[4];
-        bool ov[4];
-        for (int r = 0; r < 4; ++r) {
-            const int64_t k = k0 + r * 256 + tid;
-            ov[r] = false;
-            gid[r] = 0;
-            if (k < ce) {
-                if (mkey) {
-                    ov[r] = (ckeys[k] >> (16u + bit)) & 1u;
-                } else {  // square overlap: the splat's tile rectangle holds the tile
-                    const uint64_t rc = rect_sorted[cvals[k]];
-                    ov[r] = loc.tx >= (uint32_t)(rc & 0xFFFFu) && loc.tx <= (uint32_t)((rc >> 16) & 0xFFFFu) &&
-                            loc.ty >= (uint32_t)((rc >> 32) & 0xFFFFu) && loc.ty <= (uint32_t)(rc >> 48);
-                }
-                if (ov[r]) gid[r] = cgid[k];
+    for (int64_t k0 = cs; k0 < ce; k0 += round) {
+        const int64_t k = k0 + tid;
+        uint32_t m = 0u, g = 0u;
+        if (k < ce) {
+            const uint32_t key = ckeys[k];
+            if (mkey) {
+                m = key >> 16;
+            } else {  // square overlap: the tiles of the splat's tile rectangle inside this super-tile
+                const uint64_t rc = rect_sorted[cvals[k]];
+                const uint32_t x0 = (uint32_t)(rc & 0xFFFFu), x1 = (uint32_t)((rc >> 16) & 0xFFFFu);
+                const uint32_t y0 = (uint32_t)((rc >> 32) & 0xFFFFu), y1 = (uint32_t)(rc >> 48);
+                for (uint32_t yy = max(y0, by); yy <= min(y1, by + (uint32_t)S - 1u); ++yy)
+                    for (uint32_t xx = max(x0, bx); xx <= min(x1, bx + (uint32_t)S - 1u); ++xx)
+                        m |= 1u << ((yy - by) * (uint32_t)S + (xx - bx));
             }
-            bal[r] = __ballot(ov[r]);
-            if ((tid & 63) == 0) s_wc[parity][r][w] = (uint32_t)__popcll(bal[r]);
+            g = cgid[k];
+        }
+        s_mask[tid] = m;
+        s_gid[tid] = g;
+        __syncthreads();
+        if (exists) {
+            const int cnt = (int)min((int64_t)round, ce - k0);
+            for (int c0 = 0; c0 < cnt; c0 += 64) {
+                const int c = c0 + lane;
+                const bool keep = c < cnt && ((s_mask[c] >> w) & 1u);
+                const unsigned long long bal = __ballot(keep);
+                if (keep) ids[out + run + (uint64_t)__popcll(bal & lt)] = s_gid[c];
+                run += (uint64_t)__popcll(bal);
+            }
         }
         __syncthreads();
-        uint32_t base_r = 0;
-        for (int r = 0; r < 4; ++r) {
-            uint32_t woff = 0, tot = 0;
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t c = s_wc[parity][r][q];
-                woff += q < w ? c : 0u;
-                tot += c;
-            }
-            if (ov[r]) ids[out + run + base_r + woff + (uint32_t)__popcll(bal[r] & lt)] = gid[r];
-            base_r += tot;
-        }
-        run += base_r;
     }
-    if (tid == 0) {
-        ranges[2 * (size_t)loc.gt] = (int64_t)out;
-        ranges[2 * (size_t)loc.gt + 1] = (int64_t)(out + run);
+    if (exists && lane == 0) {
+        const size_t gt = (size_t)V.tile_base + ty * (uint32_t)V.tiles_x + tx;
+        ranges[2 * gt] = (int64_t)out;
+        ranges[2 * gt + 1] = (int64_t)(out + run);
     }
 }
 
@@ -685,11 +669,11 @@ void launch_coarse_gather(const uint32_t* cvals, const uint32_t* sorted_gid, con
 }
 void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
                        const uint32_t* cgid, int mkey, const int64_t* cranges, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_count, int tiles, const ViewParams* views, int v0, int v1, int S,
+                       const unsigned long long* eff_count, int supers, const ViewParams* views, int v0, int v1, int S,
                        uint32_t* ids, int64_t* ranges, hipStream_t st) {
-    if (tiles == 0) return;
-    k_tile_write<<<tiles, 256, 0, st>>>(ckeys, cvals, rect_sorted, cgid, mkey, cranges, base_ptr, eff_count, views,
-                                        v0, v1, S, ids, ranges);
+    if (supers == 0) return;
+    k_tile_write<<<supers, 64 * S * S, 0, st>>>(ckeys, cvals, rect_sorted, cgid, mkey, cranges, base_ptr, eff_count,
+                                                views, v0, v1, S, ids, ranges);
 }
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {
