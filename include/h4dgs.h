@@ -212,8 +212,15 @@ typedef enum {
     H4D_STAGE_COUNT = 8
 } h4d_stage;
 
-/* enable != 0: every later call brackets each stage's kernels with HIP events
- * recorded on the call's stream (events are host objects; no device memory). */
+/* Timing of later calls with HIP events (host objects; no device memory):
+ * enable 0: off.
+ * enable 1: each stage's kernels are bracketed by two events recorded on the
+ *           call's stream; every stage reports, at the price of the idle time
+ *           such event commands add between stages.
+ * enable 2: only the blending kernels (H4D_STAGE_BLEND_FWD / _BWD) report,
+ *           timed from their own dispatch (start and end of the kernel itself);
+ *           nothing is added to the stream.
+ * Any other value: H4D_ERR_INVALID_ARG. */
 h4d_status h4dgs_profile(h4d_ctx *ctx, int32_t enable);
 /* Waits for the recorded events and writes, per stage, the summed milliseconds
  * and the number of bracketed launches since the previous read (arrays of

@@ -14,7 +14,7 @@
 
 struct h4d_ctx {
     std::string err;
-    bool profile = false;
+    int profile = 0;  // 0 off, 1 stages bracketed by events, 2 blend kernels by their own timestamps
     bool stats = false;
     struct Mark {
         hipEvent_t a, b;
@@ -61,13 +61,13 @@ struct StageScope {
     int stage;
     hipEvent_t a = nullptr;
     StageScope(h4d_ctx* c_, hipStream_t st_, int stage_) : c(c_), st(st_), stage(stage_) {
-        if (c && c->profile) {
+        if (c && c->profile == 1) {
             a = c->event();
             if (a) (void)hipEventRecord(a, st);
         }
     }
     ~StageScope() {
-        if (c && c->profile && a) {
+        if (c && a) {
             hipEvent_t b = c->event();
             if (b) {
                 (void)hipEventRecord(b, st);
@@ -76,6 +76,26 @@ struct StageScope {
                 c->pool.push_back(a);
             }
         }
+    }
+};
+
+// Events for one blend launch timed from its own dispatch (profile level 2);
+// both null otherwise.  The launch must happen (non-empty grid).
+struct KernelMark {
+    h4d_ctx* c;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelMark(h4d_ctx* c_, int stage_, bool launches) : c(c_), stage(stage_) {
+        if (!c || c->profile != 2 || !launches) return;
+        a = c->event();
+        b = a ? c->event() : nullptr;
+        if (!b && a) {
+            c->pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    ~KernelMark() {
+        if (a && b) c->marks.push_back(h4d_ctx::Mark{a, b, stage});
     }
 };
 
@@ -392,9 +412,10 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
                           ids, at<int64_t>(state, L.st_ranges), st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
+    KernelMark km(c, H4D_STAGE_BLEND_FWD, P.tiles > 0);
     launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles, images,
                          at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc), at<float>(state, L.st_C),
-                         stat_counters(c, state, L), st);
+                         stat_counters(c, state, L), st, km.a, km.b);
 }
 
 }  // namespace
@@ -512,10 +533,11 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
         for (int v = 0; v < n_views; ++v) tab.p[v] = dl_dimages[v];
         for (int k = 0; k < L.n_passes(); ++k) {
             const Pass P = L.pass(k);
+            KernelMark km(ctx, H4D_STAGE_BLEND_BWD, P.tiles > 0);
             launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs), N, at<uint32_t>(stt, L.st_ids),
                                  at<int64_t>(stt, L.st_ranges), vp, P.v0, P.v1, P.tiles, tab, at<float>(stt, L.st_T),
                                  at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), g2, stat_counters(ctx, stt, L),
-                                 st);
+                                 st, km.a, km.b);
         }
     }
     const G3Grad r3{grad3->n, grad3->mean, grad3->log_scale, grad3->quat, grad3->opacity, grad3->sh};
@@ -696,7 +718,8 @@ h4d_status h4dgs_l1_loss_grad(h4d_ctx* ctx, int32_t n_views, const float* const*
 
 h4d_status h4dgs_profile(h4d_ctx* ctx, int32_t enable) {
     if (!ctx) return H4D_ERR_INVALID_ARG;
-    ctx->profile = enable != 0;
+    if (enable < 0 || enable > 2) return fail(ctx, H4D_ERR_INVALID_ARG, "profile level %d not in {0, 1, 2}", enable);
+    ctx->profile = enable;
     return H4D_OK;
 }
 

@@ -17,6 +17,7 @@
 // (splat, component, wave).  Constant factors of the conic and centre
 // gradients are applied once per splat after the reduction.  Each wave stops
 // at its own last contributor.
+#include <hip/hip_ext.h>
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -377,29 +378,39 @@ bool composite_supported(int tile, int chunk) {
     return (tile == 8 || tile == 16 || tile == 32) && (chunk == 64 || chunk == 128 || chunk == 256 || chunk == 512);
 }
 
+template <class T>
+struct same_type {
+    using type = T;
+};
+// Launches k on st; with events, through the dispatch-timestamp launch so that
+// e0 / e1 take the kernel's own start and end (no extra commands on the stream).
+template <typename... P>
+static void launch_timed(void (*k)(P...), int grid, int block, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                         typename same_type<P>::type... args) {
+    if (!e0 && !e1) {
+        k<<<grid, block, 0, st>>>(args...);
+        return;
+    }
+    void* a[] = {(void*)&args...};
+    (void)hipExtLaunchKernel((const void*)k, dim3(grid), dim3(block), a, 0, st, e0, e1, 0);
+}
+
 template <int B, int C>
 static void fwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
                   int v1, int n_tiles, const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout,
-                  unsigned long long* counters, hipStream_t st) {
+                  unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
-    if (counters)
-        k_composite_fwd<B, C, true><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, images, Tfin,
-                                                            ncontrib, Cout, counters);
-    else
-        k_composite_fwd<B, C, false><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, images, Tfin,
-                                                             ncontrib, Cout, nullptr);
+    launch_timed(counters ? k_composite_fwd<B, C, true> : k_composite_fwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
+                 N, ids, ranges, views, v0, v1, images, Tfin, ncontrib, Cout, counters);
 }
 template <int B, int C>
 static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
                   int v1, int n_tiles, const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib,
-                  const float* Cout, float* g2, unsigned long long* counters, hipStream_t st) {
+                  const float* Cout, float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0,
+                  hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
-    if (counters)
-        k_composite_bwd<B, C, true><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, dls, Tfin, ncontrib,
-                                                            Cout, g2, counters);
-    else
-        k_composite_bwd<B, C, false><<<n_tiles, NT, 0, st>>>(recs, N, ids, ranges, views, v0, v1, dls, Tfin,
-                                                             ncontrib, Cout, g2, nullptr);
+    launch_timed(counters ? k_composite_bwd<B, C, true> : k_composite_bwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
+                 N, ids, ranges, views, v0, v1, dls, Tfin, ncontrib, Cout, g2, counters);
 }
 
 #define H4D_DISPATCH(FN, ...)                                                   \
@@ -420,17 +431,20 @@ static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ra
 
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int v0, int v1, int n_tiles, const PtrTable& images, float* Tfin,
-                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st) {
+                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(fwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, images, Tfin, ncontrib, Cout, counters, st);
+    H4D_DISPATCH(fwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, images, Tfin, ncontrib, Cout, counters, st, e0,
+                 e1);
 }
 
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int v0, int v1, int n_tiles, const CPtrTable& dls,
                           const float* Tfin, const uint32_t* ncontrib, const float* Cout, float* g2,
-                          unsigned long long* counters, hipStream_t st) {
+                          unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(bwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, dls, Tfin, ncontrib, Cout, g2, counters, st);
+    H4D_DISPATCH(bwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, dls, Tfin, ncontrib, Cout, g2, counters, st, e0,
+                 e1);
 }
 
 }  // namespace h4d

@@ -118,14 +118,17 @@ void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 bool composite_supported(int tile, int chunk);
 // One launch over the tiles of views [v0, v1) (n_tiles = their total): recs
 // holds every view's records ([view][N]), images/dls are indexed by view and
-// g2 is laid out [view][9][N].
+// g2 holds kG2Stride floats per (view, Gaussian).  Non-null e0 / e1 receive the
+// kernel's own start / end time.
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int v0, int v1, int n_tiles, const PtrTable& images, float* Tfin,
-                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st);
+                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int v0, int v1, int n_tiles, const CPtrTable& dls,
                           const float* Tfin, const uint32_t* ncontrib, const float* Cout, float* g2,
-                          unsigned long long* counters, hipStream_t st);
+                          unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
 // L1 loss gradient (loss.hip)
 void launch_l1_loss_grad(const float* img, const float* target, float* dl, size_t n, float scale, float* loss,
                          hipStream_t st);

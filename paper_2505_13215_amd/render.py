@@ -177,8 +177,11 @@ class Rasterizer:
 
 
     # -- instrumentation -----------------------------------------------------------
-    def profile(self, enable: bool = True):
-        self.ctx.check(self.ctx.L.h4dgs_profile(self.ctx.h, int(bool(enable))))
+    def profile(self, enable=True):
+        """Event timing of later calls: False / 0 off, True / 1 every stage
+        (event pairs between stages), 2 the blending kernels only, from their
+        own dispatch timestamps (no added stream commands)."""
+        self.ctx.check(self.ctx.L.h4dgs_profile(self.ctx.h, int(enable)))
 
     def profile_read(self) -> dict:
         """{stage: (total_ms, launches)} since the previous read (synchronises)."""

@@ -222,3 +222,16 @@ def test_null_context(L):
     st, sc = C.c_size_t(), C.c_size_t()
     assert lib.h4dgs_workspace_size(None, 1, 1, None, 1, None, C.byref(st), C.byref(sc)) == 1
     assert lib.h4dgs_last_error(None) == b"null context"
+
+
+def test_profile_levels(L):
+    c = _ctx(L)
+    for level in (0, 1, 2, 0):
+        assert c.L.h4dgs_profile(c.h, level) == 0
+    for level in (-1, 3):
+        assert c.L.h4dgs_profile(c.h, level) == 1
+        assert b"profile level" in c.L.h4dgs_last_error(c.h)
+    ms = (C.c_double * 8)()
+    n = (C.c_int64 * 8)()
+    assert c.L.h4dgs_profile_read(c.h, ms, n) == 0
+    assert list(n) == [0] * 8
