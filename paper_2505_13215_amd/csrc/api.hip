@@ -152,13 +152,13 @@ struct Layout {
     uint64_t ccap = 0;   // coarse (Gaussian, super-tile) entries: cap / S^2 suffices
     ViewGeom vg[kMaxViews];
     // state
-    size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_T, st_nc, st_C, state_bytes;
+    size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_T, st_nc, st_C, st_tcost, state_bytes;
     // scratch, forward use
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff,
         sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges,
-        sc_shape, sc_runs, fwd_bytes;
+        sc_shape, sc_runs, sc_order, fwd_bytes;
     // scratch, backward use
-    size_t sc_g2, bwd_bytes;
+    size_t sc_g2, sc_border, bwd_bytes;
     size_t scratch_bytes;
 
     int n_passes() const { return V / per_pass; }
@@ -214,6 +214,7 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.st_T = s.take(4 * (size_t)pb);
     L.st_nc = s.take(4 * (size_t)pb);
     L.st_C = s.take(12 * (size_t)pb);
+    L.st_tcost = s.take(4 * (size_t)tb);
     L.state_bytes = s.off;
     Carve f;
     L.sc_dkeys = f.take(4 * np);
@@ -236,9 +237,13 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_cranges = f.take(16 * (size_t)max_super);
     L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
     L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
+    int max_tiles = 0;
+    for (int k = 0; k < L.n_passes(); ++k) max_tiles = std::max(max_tiles, L.pass(k).tiles);
+    L.sc_order = f.take(4 * (size_t)max_tiles);
     L.fwd_bytes = f.off;
     Carve b;
     L.sc_g2 = b.take(4 * (size_t)kG2Stride * n * V_);
+    L.sc_border = b.take(4 * (size_t)tb);
     L.bwd_bytes = b.off;
     L.scratch_bytes = std::max(L.fwd_bytes, L.bwd_bytes);
     return L;
@@ -361,6 +366,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     unsigned long long* pair_base = at<unsigned long long>(state, L.st_pair_base);
     uint32_t* ids = at<uint32_t>(state, L.st_ids);
     const int S = super_factor(tile);
+    uint32_t* order = at<uint32_t>(scratch, L.sc_order);
     {
         StageScope sc(c, st, H4D_STAGE_BINNING);
         unsigned long long* eff_c = at<unsigned long long>(scratch, L.sc_eff);
@@ -410,12 +416,14 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         launch_coarse_gather(vin, dv, eff_c, cgid, st);
         launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, eff_c, P.supers, vp, P.v0, P.v1, S,
                           ids, at<int64_t>(state, L.st_ranges), st);
+        // dispatch order of the blending launch
+        launch_order_tiles(at<int64_t>(state, L.st_ranges), L.vg[P.v0].tile_base, P.tiles, order, st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
     KernelMark km(c, H4D_STAGE_BLEND_FWD, P.tiles > 0);
-    launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles, images,
-                         at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc), at<float>(state, L.st_C),
-                         stat_counters(c, state, L), st, km.a, km.b);
+    launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles, order,
+                         images, at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc), at<float>(state, L.st_C),
+                         at<uint32_t>(state, L.st_tcost), stat_counters(c, state, L), st, km.a, km.b);
 }
 
 }  // namespace
@@ -524,7 +532,12 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     void* stt = const_cast<void*>(state);
     float* g2 = at<float>(scratch, L.sc_g2);
-    launch_fill_f32(g2, (size_t)kG2Stride * N * n_views, 0.f, st);
+    uint32_t* border = at<uint32_t>(scratch, L.sc_border);
+    PassTiles pt;
+    pt.n = L.n_passes();
+    for (int k = 0; k < pt.n; ++k) pt.tile0[k] = L.vg[L.pass(k).v0].tile_base;
+    pt.tile0[pt.n] = L.total_tiles;
+    launch_bwd_prologue(g2, (size_t)kG2Stride * N * n_views, at<uint32_t>(stt, L.st_tcost), pt, border, st);
     const ViewParams* vp = at<ViewParams>(stt, L.st_views);
     {
         StageScope sc(ctx, st, H4D_STAGE_BLEND_BWD);
@@ -535,7 +548,8 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
             const Pass P = L.pass(k);
             KernelMark km(ctx, H4D_STAGE_BLEND_BWD, P.tiles > 0);
             launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs), N, at<uint32_t>(stt, L.st_ids),
-                                 at<int64_t>(stt, L.st_ranges), vp, P.v0, P.v1, P.tiles, tab, at<float>(stt, L.st_T),
+                                 at<int64_t>(stt, L.st_ranges), vp, P.v0, P.v1, P.tiles, border + pt.tile0[k], tab,
+                                 at<float>(stt, L.st_T),
                                  at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), g2, stat_counters(ctx, stt, L),
                                  st, km.a, km.b);
         }

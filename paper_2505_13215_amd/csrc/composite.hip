@@ -74,16 +74,35 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Largest value over the wave.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    return v;
+}
+
+// Tile (relative to the launch's first) of this workgroup: order[blockIdx.x],
+// the launch's tiles by decreasing cost, so that the expensive tiles start
+// first and every SIMD receives a mix of costs (an entry out of range, which a
+// permutation never has, falls back to blockIdx.x).
+__device__ __forceinline__ int dispatch_tile(const uint32_t* __restrict__ order) {
+    const uint32_t b = blockIdx.x;
+    const uint32_t t = order[b];
+    return (int)(t < gridDim.x ? t : b);
+}
+
 // STATS = true is a measurement-only instantiation that also counts (pixel,
-// splat) evaluations and blends into counters[0..1].
+// splat) evaluations and blends into counters[0..1].  tcost[tile] receives
+// the tile's last contributor (the adjoint's work on it).
 template <int B, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
-    const ViewParams* __restrict__ views, int v0, int v1, PtrTable images, float* __restrict__ Tfin,
-    uint32_t* __restrict__ ncontrib, float* __restrict__ Cout, unsigned long long* counters) {
+    const ViewParams* __restrict__ views, int v0, int v1, const uint32_t* __restrict__ order, PtrTable images,
+    float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib, float* __restrict__ Cout,
+    uint32_t* __restrict__ tcost, unsigned long long* counters) {
     constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
-    const int gt = views[v0].tile_base + (int)blockIdx.x;
+    __shared__ uint32_t s_cost;
+    const int gt = views[v0].tile_base + dispatch_tile(order);
     const int view = find_view_of_tile(views, v0, v1, gt);
     const ViewParams& V = views[view];
     const int tile = gt - V.tile_base;
@@ -172,6 +191,20 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
             Cout[3 * (size_t)V.pix_base + 2 * HW + p] = o2;
         }
     }
+    // the tile's cost for the adjoint: its last contributor over all pixels
+    uint32_t lane_last = 0u;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) lane_last = max(lane_last, last[k]);
+    const uint32_t wave_last = wave_max_u32(lane_last);
+    if (NT == 64) {
+        if (threadIdx.x == 0) tcost[gt] = wave_last;
+    } else {
+        if (threadIdx.x == 0) s_cost = 0u;
+        __syncthreads();
+        if (__lane_id() == 0) atomicMax(&s_cost, wave_last);
+        __syncthreads();
+        if (threadIdx.x == 0) tcost[gt] = s_cost;
+    }
     if (STATS) {
         const unsigned long long e = wave_sum_u64(n_eval), b = wave_sum_u64(n_blend);
         if (__lane_id() == 0) {
@@ -217,26 +250,19 @@ __device__ __forceinline__ void wave_sum9(float e0, float e1, float e2, float e3
     h2 = row_sum(g2);
 }
 
-// Largest value over the wave.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
-    return v;
-}
-
-// Per-splat gradient sums of the current group of 64 splats live in the
-// register file: the wave sum of splat j is written into lane j % 64 of nine
-// accumulator registers; every 64 splats (and at the end of a chunk) all lanes
-// flush their sums with parallel global atomics.
+// Per splat of the tile's list (up to its last contributor), the wave's nine
+// gradient sums (wave_sum9) are added into the splat's g2 record with global
+// atomics by four lanes.
 template <int B, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
-    const ViewParams* __restrict__ views, int v0, int v1, CPtrTable dls, const float* __restrict__ Tfin,
-    const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout, float* __restrict__ g2,
-    unsigned long long* counters) {
+    const ViewParams* __restrict__ views, int v0, int v1, const uint32_t* __restrict__ order, CPtrTable dls,
+    const float* __restrict__ Tfin, const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout,
+    float* __restrict__ g2, unsigned long long* counters) {
     constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
     __shared__ uint32_t s_max;
-    const int gt = views[v0].tile_base + (int)blockIdx.x;
+    const int gt = views[v0].tile_base + dispatch_tile(order);
     const int view = find_view_of_tile(views, v0, v1, gt);
     const ViewParams& V = views[view];
     const int tile = gt - V.tile_base;
@@ -397,20 +423,21 @@ static void launch_timed(void (*k)(P...), int grid, int block, hipStream_t st, h
 
 template <int B, int C>
 static void fwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
-                  int v1, int n_tiles, const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout,
-                  unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                  int v1, int n_tiles, const uint32_t* order, const PtrTable& images, float* Tfin,
+                  uint32_t* ncontrib, float* Cout, uint32_t* tcost, unsigned long long* counters, hipStream_t st,
+                  hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
     launch_timed(counters ? k_composite_fwd<B, C, true> : k_composite_fwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
-                 N, ids, ranges, views, v0, v1, images, Tfin, ncontrib, Cout, counters);
+                 N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout, tcost, counters);
 }
 template <int B, int C>
 static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
-                  int v1, int n_tiles, const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib,
-                  const float* Cout, float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0,
-                  hipEvent_t e1) {
+                  int v1, int n_tiles, const uint32_t* order, const CPtrTable& dls, const float* Tfin,
+                  const uint32_t* ncontrib, const float* Cout, float* g2, unsigned long long* counters, hipStream_t st,
+                  hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
     launch_timed(counters ? k_composite_bwd<B, C, true> : k_composite_bwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
-                 N, ids, ranges, views, v0, v1, dls, Tfin, ncontrib, Cout, g2, counters);
+                 N, ids, ranges, views, v0, v1, order, dls, Tfin, ncontrib, Cout, g2, counters);
 }
 
 #define H4D_DISPATCH(FN, ...)                                                   \
@@ -430,21 +457,21 @@ static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ra
     } while (0)
 
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int v0, int v1, int n_tiles, const PtrTable& images, float* Tfin,
-                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st,
-                          hipEvent_t e0, hipEvent_t e1) {
+                          const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
+                          const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
+                          unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(fwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, images, Tfin, ncontrib, Cout, counters, st, e0,
-                 e1);
+    H4D_DISPATCH(fwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, order, images, Tfin, ncontrib, Cout, tcost,
+                 counters, st, e0, e1);
 }
 
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int v0, int v1, int n_tiles, const CPtrTable& dls,
-                          const float* Tfin, const uint32_t* ncontrib, const float* Cout, float* g2,
-                          unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                          const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
+                          const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
+                          float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(bwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, dls, Tfin, ncontrib, Cout, g2, counters, st, e0,
-                 e1);
+    H4D_DISPATCH(bwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, order, dls, Tfin, ncontrib, Cout, g2, counters,
+                 st, e0, e1);
 }
 
 }  // namespace h4d

@@ -111,6 +111,19 @@ void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint6
 // [first, last+1) + *base (base may be null)
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st);
+// Dispatch order of the blending launches: the tiles of each pass, relative to
+// the pass's first, by decreasing cost (a permutation; ties in any order).
+// Forward: one pass [tile0, tile0 + n) with cost = list length (ranges).
+void launch_order_tiles(const int64_t* ranges, int tile0, int n, uint32_t* order, hipStream_t st);
+// Backward prologue: zeroes g2[0, n_g2) and orders the tiles of every pass by
+// tcost (pass k: global tiles [tile0[k], tile0[k + 1]), its order at the same
+// offsets).
+struct PassTiles {
+    int32_t n;                     // passes
+    int32_t tile0[kMaxViews + 1];
+};
+void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const PassTiles& passes, uint32_t* order,
+                         hipStream_t st);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 
@@ -118,16 +131,20 @@ void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 bool composite_supported(int tile, int chunk);
 // One launch over the tiles of views [v0, v1) (n_tiles = their total): recs
 // holds every view's records ([view][N]), images/dls are indexed by view and
-// g2 holds kG2Stride floats per (view, Gaussian).  Non-null e0 / e1 receive the
-// kernel's own start / end time.
+// g2 holds kG2Stride floats per (view, Gaussian).  order: the n_tiles tiles
+// (relative to the launch's first) in dispatch order, a permutation
+// (launch_order_tiles).  The forward writes, per tile, its last contributor
+// into tcost[global tile].  Non-null e0 / e1 receive the kernel's own start /
+// end time.
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int v0, int v1, int n_tiles, const PtrTable& images, float* Tfin,
-                          uint32_t* ncontrib, float* Cout, unsigned long long* counters, hipStream_t st,
-                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
-                          const ViewParams* views, int v0, int v1, int n_tiles, const CPtrTable& dls,
-                          const float* Tfin, const uint32_t* ncontrib, const float* Cout, float* g2,
+                          const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
+                          const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
                           unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+                          const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
+                          const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
+                          float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);
 // L1 loss gradient (loss.hip)
 void launch_l1_loss_grad(const float* img, const float* target, float* dl, size_t n, float scale, float* loss,

@@ -640,6 +640,75 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ key
 __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long val) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = val;
 }
+// Counting sort of n tile costs by one workgroup (blockDim a multiple of 64)
+// into order[0, n): decreasing cost in 1024 buckets linear in cost / max cost,
+// ties in any order.  A permutation of [0, n) whatever the costs.
+template <class Cost>
+__device__ void order_by_cost(int n, Cost cost, uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_hist[1024];
+    __shared__ uint32_t s_max;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int b = tid; b < 1024; b += nt) s_hist[b] = 0u;
+    if (tid == 0) s_max = 0u;
+    __syncthreads();
+    uint32_t mx = 0u;
+    for (int t = tid; t < n; t += nt) mx = max(mx, cost(t));
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+    if (__lane_id() == 0) atomicMax(&s_max, mx);
+    __syncthreads();
+    const uint64_t m = max(s_max, 1u);
+    auto bucket = [m](uint32_t c) { return 1023u - (uint32_t)((uint64_t)min((uint64_t)c, m) * 1023u / m); };
+    for (int t = tid; t < n; t += nt) atomicAdd(&s_hist[bucket(cost(t))], 1u);
+    __syncthreads();
+    if (tid < 64) {  // exclusive scan of the 1024 counts: 16 per lane
+        uint32_t v[16], sum = 0u;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            v[i] = s_hist[16 * tid + i];
+            sum += v[i];
+        }
+        uint32_t incl = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+            if (tid >= off) incl += y;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            s_hist[16 * tid + i] = run;
+            run += v[i];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < n; t += nt) {
+        const uint32_t pos = atomicAdd(&s_hist[bucket(cost(t))], 1u);
+        order[pos] = (uint32_t)t;
+    }
+}
+
+// Forward: cost of a tile = its list length.
+__global__ void __launch_bounds__(1024) k_order_tiles(const int64_t* __restrict__ ranges, int tile0, int n,
+                                                      uint32_t* __restrict__ order) {
+    const int64_t* r = ranges + 2 * (size_t)tile0;
+    order_by_cost(
+        n, [r](int t) { return (uint32_t)min(r[2 * t + 1] - r[2 * t], (int64_t)0xFFFFFFFFll); }, order);
+}
+
+// Backward: workgroup k < passes.n orders pass k by tcost, the others zero g2.
+__global__ void __launch_bounds__(1024) k_bwd_prologue(float* __restrict__ g2, size_t n_g2,
+                                                       const uint32_t* __restrict__ tcost, PassTiles passes,
+                                                       uint32_t* __restrict__ order) {
+    const int k = (int)blockIdx.x;
+    if (k < passes.n) {
+        const int t0 = passes.tile0[k];
+        const uint32_t* c = tcost + t0;
+        order_by_cost(passes.tile0[k + 1] - t0, [c](int t) { return c[t]; }, order + t0);
+        return;
+    }
+    const size_t nb = (size_t)(gridDim.x - passes.n);
+    for (size_t i = (size_t)(k - passes.n) * blockDim.x + threadIdx.x; i < n_g2; i += nb * blockDim.x) g2[i] = 0.0f;
+}
+
 __global__ void k_fill_f32(float* p, size_t n, float val) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = val;
 }
@@ -679,6 +748,17 @@ void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long 
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {
     k_ranges<<<2048, 256, 0, st>>>(keys, key_mask, eff_count, base, ranges);
 }
+void launch_order_tiles(const int64_t* ranges, int tile0, int n, uint32_t* order, hipStream_t st) {
+    if (n == 0) return;
+    k_order_tiles<<<1, 1024, 0, st>>>(ranges, tile0, n, order);
+}
+
+void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const PassTiles& passes, uint32_t* order,
+                         hipStream_t st) {
+    const int fill = (int)std::max<size_t>(1, std::min<size_t>(1024, (n_g2 + 4095) / 4096));
+    k_bwd_prologue<<<passes.n + fill, 1024, 0, st>>>(g2, n_g2, tcost, passes, order);
+}
+
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st) {
     if (n == 0) return;
     const int nb = (int)std::min<size_t>(4096, (n + 255) / 256);
