@@ -153,7 +153,7 @@ __device__ __forceinline__ bool eval_pix(const Splat& s, const ColTerm& c, int p
     G = __builtin_amdgcn_exp2f(p2);
     const float ap = s.op * G;
     clamped = ap > kMaxAlpha;
-    alpha = clamped ? kMaxAlpha : ap;
+    alpha = __builtin_fminf(ap, kMaxAlpha);  // ap is never NaN
     return in && !(p2 > 0.0f) && alpha >= kMinAlpha;
 }
 

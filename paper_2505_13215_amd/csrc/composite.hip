@@ -113,33 +113,37 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     const int px = tx * B + (int)threadIdx.x % B;
     const float pxc = (float)px + 0.5f;
     int py[PPL];
+    // T > 0: the pixel is live; a finished pixel keeps its final transmittance
+    // as -T (pixels outside the image start finished)
     float pyc[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
     uint32_t last[PPL];
-    bool done[PPL];
     bool lane_done = true;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int p = (int)threadIdx.x + k * NT;
         py[k] = ty * B + p / B;
         pyc[k] = (float)py[k] + 0.5f;
-        T[k] = 1.0f;
+        const bool inside = px < V.W && py[k] < V.H;
+        T[k] = inside ? 1.0f : -1.0f;
         cr[k] = cg[k] = cb[k] = 0.f;
         last[k] = 0u;
-        done[k] = !(px < V.W && py[k] < V.H);
-        lane_done = lane_done && done[k];
+        lane_done = lane_done && !inside;
     }
     const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
     const int64_t end = ranges[2 * (size_t)(V.tile_base + tile) + 1];
     unsigned long long n_eval = 0, n_blend = 0;
+    // wave-uniform: the splat loop runs for the whole wave (finished pixels are
+    // masked), so that its per-pixel flags stay lane masks
+    bool wave_done = __ballot(!lane_done) == 0ull;
     for (int64_t base = start; base < end; base += CHUNK) {
-        if (__syncthreads_count(lane_done) == NT) break;
+        if (__syncthreads_count(wave_done) == NT) break;
         const int cnt = (int)min((int64_t)CHUNK, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) {
             const uint32_t gid = ids[base + k];
             stage_splat(recs[gid], gid, s_sp[k]);
         }
         __syncthreads();
-        if (!lane_done) {
+        if (!wave_done) {
             const uint32_t rel0 = (uint32_t)(base - start);
             for (int j = 0; j < cnt; ++j) {
                 const Splat s = to_splat(s_sp[j]);
@@ -149,7 +153,8 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
                 for (int k = 0; k < PPL; ++k) {
                     float dy, G, alpha;
                     bool clamped;
-                    const bool ok = eval_pix(s, c, py[k], pyc[k], dy, G, alpha, clamped) && !done[k];
+                    const bool live = T[k] > 0.0f;
+                    const bool ok = eval_pix(s, c, py[k], pyc[k], dy, G, alpha, clamped) && live;
                     const float Tn = next_T(T[k], alpha);
                     const bool stop = ok && Tn < kMinT;
                     const bool bl = ok && !stop;
@@ -157,17 +162,16 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
                     cr[k] = __builtin_fmaf(s.cr, w, cr[k]);
                     cg[k] = __builtin_fmaf(s.cg, w, cg[k]);
                     cb[k] = __builtin_fmaf(s.cb, w, cb[k]);
-                    T[k] = bl ? Tn : T[k];
+                    T[k] = bl ? Tn : (stop ? -T[k] : T[k]);
                     last[k] = bl ? rel0 + (uint32_t)j + 1u : last[k];
                     if (STATS) {
-                        n_eval += (!done[k] && in_square(s, px, py[k])) ? 1u : 0u;
+                        n_eval += (live && in_square(s, px, py[k])) ? 1u : 0u;
                         n_blend += bl ? 1u : 0u;
                     }
-                    done[k] = done[k] || stop;
-                    all = all && done[k];
+                    all = all && !(live && !stop);
                 }
-                if (all) {
-                    lane_done = true;
+                if (__ballot(!all) == 0ull) {
+                    wave_done = true;
                     break;
                 }
             }
@@ -178,13 +182,14 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     for (int k = 0; k < PPL; ++k) {
         if (px < V.W && py[k] < V.H) {
             const size_t p = (size_t)py[k] * V.W + px;
-            const float o0 = __builtin_fmaf(T[k], V.bg[0], cr[k]), o1 = __builtin_fmaf(T[k], V.bg[1], cg[k]),
-                        o2 = __builtin_fmaf(T[k], V.bg[2], cb[k]);
+            const float Tk = __builtin_fabsf(T[k]);
+            const float o0 = __builtin_fmaf(Tk, V.bg[0], cr[k]), o1 = __builtin_fmaf(Tk, V.bg[1], cg[k]),
+                        o2 = __builtin_fmaf(Tk, V.bg[2], cb[k]);
             image[p] = o0;
             image[HW + p] = o1;
             image[2 * HW + p] = o2;
             const size_t q = (size_t)V.pix_base + p;
-            Tfin[q] = T[k];
+            Tfin[q] = Tk;
             ncontrib[q] = last[k];
             Cout[3 * (size_t)V.pix_base + p] = o0;
             Cout[3 * (size_t)V.pix_base + HW + p] = o1;
