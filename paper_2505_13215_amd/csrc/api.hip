@@ -397,12 +397,15 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         uint32_t* kin = pk;
         uint32_t* vin = pv;
         int shift = 0;
+        // with the tile mask in the keys the per-tile pass needs only splat ids:
+        // the last pass writes those in place of the depth ranks
         for (int p = 0; p < passes; ++p) {
             const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
             uint32_t* kout = (kin == pk) ? pk2 : pk;
             uint32_t* vout = (vin == pv) ? pv2 : pv;
             launch_radix_pass(kin, vin, kout, vout, eff_c, 0, L.ccap, shift, nb, hist, totals, nullptr, st, 1, 0,
-                              passes == 1 ? cranges : nullptr, P.supers);
+                              passes == 1 ? cranges : nullptr, P.supers, kSortItems,
+                              (mkey && p == passes - 1) ? dv : nullptr);
             kin = kout;
             vin = vout;
             shift += nb;
@@ -411,9 +414,13 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
             launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
             launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, eff_c, nullptr, cranges, st);
         }
-        // splat ids of the sorted entries into the buffer the sort did not end in
-        uint32_t* cgid = (kin == pk) ? pk2 : pk;
-        launch_coarse_gather(vin, dv, eff_c, cgid, st);
+        // splat ids of the sorted entries (otherwise gathered into the buffer
+        // the sort did not end in)
+        uint32_t* cgid = vin;
+        if (!mkey) {
+            cgid = (kin == pk) ? pk2 : pk;
+            launch_coarse_gather(vin, dv, eff_c, cgid, st);
+        }
         launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, eff_c, P.supers, vp, P.v0, P.v1, S,
                           ids, at<int64_t>(state, L.st_ranges), st);
         // dispatch order of the blending launch

@@ -139,7 +139,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const unsigned long long* dcount, uint64_t hcount, int shift, int nbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int nblocks,
-    const unsigned long long* out_offset, uint64_t seg_stride, int64_t* __restrict__ digit_ranges, int n_digit_ranges) {
+    const unsigned long long* out_offset, uint64_t seg_stride, int64_t* __restrict__ digit_ranges, int n_digit_ranges,
+    const uint32_t* __restrict__ val_map) {
     __shared__ uint32_t s_wcount[4][1 << MB];
     __shared__ uint32_t s_dstart[1 << MB];
     __shared__ uint32_t s_gbase[1 << MB];
@@ -226,7 +227,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         const uint32_t d = (k >> shift) & mask;
         const uint64_t dst = (uint64_t)s_gbase[d] + (uint64_t)(p - (int)s_dstart[d]);
         keys_out[dst] = k;
-        vals_out[dst + off] = s_vals[p];
+        vals_out[dst + off] = val_map ? val_map[s_vals[p]] : s_vals[p];
     }
 }
 
@@ -241,7 +242,8 @@ size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits, int items) {
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
-                       int n_seg, uint64_t seg_stride, int64_t* digit_ranges, int n_digit_ranges, int items) {
+                       int n_seg, uint64_t seg_stride, int64_t* digit_ranges, int n_digit_ranges, int items,
+                       const uint32_t* val_map) {
     const int nb = radix_blocks(capacity, items);
     if (nb == 0 || n_seg == 0) return;
     const dim3 grid(nb, n_seg);
@@ -254,7 +256,7 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
                                                                     kSortThreads * IT);                              \
         k_radix_downsweep<MB, IT><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount,        \
                                                                 hcount, shift, nbits, hist, totals, nb, out_offset,   \
-                                                                seg_stride, digit_ranges, n_digit_ranges);            \
+                                                                seg_stride, digit_ranges, n_digit_ranges, val_map);   \
     } while (0)
     if (items == 2 && nbits <= 8) {
         H4D_RADIX_PASS(8, 2);  // short key sets: more, smaller blocks
