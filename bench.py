@@ -343,12 +343,28 @@ def main():
         step(i)
         peak_pairs = max(peak_pairs, rast.last_pairs)
     torch.cuda.synchronize()
+
+    # stage breakdown over the views of the timed steps (untimed: event pairs
+    # between stages add idle time); it also sizes the pair buffer for them
+    rast.profile(1)
+    rast.profile_read()
+    for i in range(args.warmup, args.warmup + args.steps):
+        step(i)
+        peak_pairs = max(peak_pairs, rast.last_pairs)
+    torch.cuda.synchronize()
+    sprof = rast.profile_read()
+    rast.profile(0)
+    stages = {k: (v[0] / max(v[1], 1)) for k, v in sprof.items() if v[1] > 0}
+    log("stage ms per launch: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+    dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages.get(k, 0.0))
+
     rast.capacity = int(max(peak_pairs, 1) * 1.5) + 4096
     rast.check_mode = "deferred"
     log(f"timing {args.steps} steps (pairs per view up to {peak_pairs})")
     for attempt in range(2):
-        # blending kernels timed from their own dispatch: nothing added to the stream
-        rast.profile(2)
+        # the dominant blending kernel timed from its own dispatch: nothing is
+        # added to the stream
+        rast.profile(3 if dom == "blend_fwd" else 4)
         rast.profile_read()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -376,18 +392,6 @@ def main():
     log("blend kernels, ms per launch in the timed region: " +
         ", ".join(f"{k} {v:.4f}" for k, v in kernel_ms.items()))
 
-    # stage breakdown (outside the timed region: event pairs between stages add idle time)
-    rast.profile(1)
-    rast.profile_read()
-    for i in range(args.warmup, args.warmup + args.steps):
-        step(i)
-    torch.cuda.synchronize()
-    sprof = rast.profile_read()
-    rast.profile(0)
-    rast.verify()
-    stages = {k: (v[0] / max(v[1], 1)) for k, v in sprof.items() if v[1] > 0}
-    log("stage ms per launch: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
-
     # evaluation counts of the blending kernels (counting instantiation, outside the timed region)
     log(f"counting blend evaluations on {args.stats_views} views")
     rast.stats(True)
@@ -407,7 +411,6 @@ def main():
         cnt[k] /= nst
     flops_fwd = FLOPS_EVAL * cnt["fwd_eval"] + FLOPS_BLEND_FWD * cnt["fwd_blend"]
     flops_bwd = FLOPS_EVAL * cnt["bwd_eval"] + FLOPS_BLEND_BWD * cnt["bwd_blend"]
-    dom = max(("blend_fwd", "blend_bwd"), key=lambda k: kernel_ms.get(k, 0.0))
     dom_ms = kernel_ms[dom]
     dom_flops = flops_bwd if dom == "blend_bwd" else flops_fwd
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12

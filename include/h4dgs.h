@@ -220,6 +220,7 @@ typedef enum {
  * enable 2: only the blending kernels (H4D_STAGE_BLEND_FWD / _BWD) report,
  *           timed from their own dispatch (start and end of the kernel itself);
  *           nothing is added to the stream.
+ * enable 3 / 4: as 2, the forward / the backward blending kernel only.
  * Any other value: H4D_ERR_INVALID_ARG. */
 h4d_status h4dgs_profile(h4d_ctx *ctx, int32_t enable);
 /* Waits for the recorded events and writes, per stage, the summed milliseconds

@@ -14,7 +14,9 @@
 
 struct h4d_ctx {
     std::string err;
-    int profile = 0;  // 0 off, 1 stages bracketed by events, 2 blend kernels by their own timestamps
+    // 0 off, 1 stages bracketed by events, 2 both blending kernels by their own
+    // timestamps, 3 the forward one only, 4 the backward one only
+    int profile = 0;
     bool stats = false;
     struct Mark {
         hipEvent_t a, b;
@@ -79,14 +81,17 @@ struct StageScope {
     }
 };
 
-// Events for one blend launch timed from its own dispatch (profile level 2);
+// Events for one blend launch timed from its own dispatch (profile levels 2-4);
 // both null otherwise.  The launch must happen (non-empty grid).
 struct KernelMark {
     h4d_ctx* c;
     int stage;
     hipEvent_t a = nullptr, b = nullptr;
     KernelMark(h4d_ctx* c_, int stage_, bool launches) : c(c_), stage(stage_) {
-        if (!c || c->profile != 2 || !launches) return;
+        if (!c || !launches) return;
+        const bool on = c->profile == 2 || (c->profile == 3 && stage == H4D_STAGE_BLEND_FWD) ||
+                        (c->profile == 4 && stage == H4D_STAGE_BLEND_BWD);
+        if (!on) return;
         a = c->event();
         b = a ? c->event() : nullptr;
         if (!b && a) {
@@ -739,7 +744,7 @@ h4d_status h4dgs_l1_loss_grad(h4d_ctx* ctx, int32_t n_views, const float* const*
 
 h4d_status h4dgs_profile(h4d_ctx* ctx, int32_t enable) {
     if (!ctx) return H4D_ERR_INVALID_ARG;
-    if (enable < 0 || enable > 2) return fail(ctx, H4D_ERR_INVALID_ARG, "profile level %d not in {0, 1, 2}", enable);
+    if (enable < 0 || enable > 4) return fail(ctx, H4D_ERR_INVALID_ARG, "profile level %d not in [0, 4]", enable);
     ctx->profile = enable;
     return H4D_OK;
 }

@@ -180,7 +180,8 @@ class Rasterizer:
     def profile(self, enable=True):
         """Event timing of later calls: False / 0 off, True / 1 every stage
         (event pairs between stages), 2 the blending kernels only, from their
-        own dispatch timestamps (no added stream commands)."""
+        own dispatch timestamps (no added stream commands), 3 / 4 the forward /
+        backward blending kernel only."""
         self.ctx.check(self.ctx.L.h4dgs_profile(self.ctx.h, int(enable)))
 
     def profile_read(self) -> dict:

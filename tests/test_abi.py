@@ -226,9 +226,9 @@ def test_null_context(L):
 
 def test_profile_levels(L):
     c = _ctx(L)
-    for level in (0, 1, 2, 0):
+    for level in (0, 1, 2, 3, 4, 0):
         assert c.L.h4dgs_profile(c.h, level) == 0
-    for level in (-1, 3):
+    for level in (-1, 5):
         assert c.L.h4dgs_profile(c.h, level) == 1
         assert b"profile level" in c.L.h4dgs_last_error(c.h)
     ms = (C.c_double * 8)()

@@ -39,6 +39,9 @@ def test_profile_levels_report_the_right_stages(h4d, batched):
     rast.profile(2)
     got2 = _step(h4d, rast, g3, g4, views)
     p2 = rast.profile_read()
+    rast.profile(4)
+    _step(h4d, rast, g3, g4, views)
+    p4 = rast.profile_read()
     rast.profile(1)
     got1 = _step(h4d, rast, g3, g4, views)
     p1 = rast.profile_read()
@@ -50,6 +53,11 @@ def test_profile_levels_report_the_right_stages(h4d, batched):
         assert torch.equal(a, b) and torch.equal(a, c)
     for k, (ms, n) in p2.items():
         if k in ("blend_fwd", "blend_bwd"):
+            assert n == n_blend and ms > 0.0, (k, ms, n)
+        else:
+            assert n == 0 and ms == 0.0, (k, ms, n)
+    for k, (ms, n) in p4.items():
+        if k == "blend_bwd":
             assert n == n_blend and ms > 0.0, (k, ms, n)
         else:
             assert n == 0 and ms == 0.0, (k, ms, n)
