@@ -157,11 +157,12 @@ struct Layout {
     uint64_t ccap = 0;   // coarse (Gaussian, super-tile) entries: cap / S^2 suffices
     ViewGeom vg[kMaxViews];
     // state
-    size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_T, st_nc, st_C, st_tcost, state_bytes;
+    size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_thist, st_T, st_nc, st_C, st_tcost,
+        state_bytes;
     // scratch, forward use
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff,
         sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges,
-        sc_shape, sc_runs, sc_order, fwd_bytes;
+        sc_shape, sc_runs, fwd_bytes;
     // scratch, backward use
     size_t sc_g2, sc_border, bwd_bytes;
     size_t scratch_bytes;
@@ -216,6 +217,7 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.st_recs = s.take(sizeof(Rec) * n * V_);
     L.st_ids = s.take(4 * (size_t)L.cap);
     L.st_ranges = s.take(16 * (size_t)tb);
+    L.st_thist = s.take(4 * (size_t)kCostBuckets * V_);  // one per pass (at most V); cleared with the ranges
     L.st_T = s.take(4 * (size_t)pb);
     L.st_nc = s.take(4 * (size_t)pb);
     L.st_C = s.take(12 * (size_t)pb);
@@ -229,7 +231,7 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_cnt = f.take(4 * np);
     L.sc_rect = f.take(8 * np);
     L.sc_offsets = f.take(8 * (np + 1));
-    L.sc_partials = f.take(8 * ((size_t)scan_blocks((int)std::min<size_t>(np, 0x7FFFFFFF)) + 2));
+    L.sc_partials = f.take(8 * ((size_t)coarse_count_blocks((int)std::min<size_t>(np, 0x7FFFFFFF)) + 2));
     L.sc_eff = f.take(8);
     L.sc_pkeys = f.take(4 * (size_t)L.ccap);
     L.sc_pvals = f.take(4 * (size_t)L.ccap);
@@ -242,9 +244,6 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_cranges = f.take(16 * (size_t)max_super);
     L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
     L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
-    int max_tiles = 0;
-    for (int k = 0; k < L.n_passes(); ++k) max_tiles = std::max(max_tiles, L.pass(k).tiles);
-    L.sc_order = f.take(4 * (size_t)max_tiles);
     L.fwd_bytes = f.off;
     Carve b;
     L.sc_g2 = b.take(4 * (size_t)kG2Stride * n * V_);
@@ -252,6 +251,12 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.bwd_bytes = b.off;
     L.scratch_bytes = std::max(L.fwd_bytes, L.bwd_bytes);
     return L;
+}
+
+// 64-bit words the forward's init clears from st_ranges on: the tile ranges
+// and the blending cost histograms behind them
+size_t range_words(const Layout& L) {
+    return (L.st_thist + 4 * (size_t)kCostBuckets * (size_t)L.V - L.st_ranges + 7) / 8;
 }
 
 template <typename T>
@@ -371,7 +376,6 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     unsigned long long* pair_base = at<unsigned long long>(state, L.st_pair_base);
     uint32_t* ids = at<uint32_t>(state, L.st_ids);
     const int S = super_factor(tile);
-    uint32_t* order = at<uint32_t>(scratch, L.sc_order);
     {
         StageScope sc(c, st, H4D_STAGE_BINNING);
         unsigned long long* eff_c = at<unsigned long long>(scratch, L.sc_eff);
@@ -383,11 +387,11 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         // the lower one
         const int mkey = P.supers <= (1 << 16) ? 1 : 0;
         CullShape* shapes = (cull && mkey) ? at<CullShape>(scratch, L.sc_shape) : nullptr;
-        launch_coarse_count(dv, n, N, recs, P.v0, tile, S, cnt, rect, shapes, st);
+        unsigned long long* partials = at<unsigned long long>(scratch, L.sc_partials);
+        launch_coarse_count(dv, n, N, recs, P.v0, tile, S, cnt, rect, shapes, partials, st);
         uint32_t* runs = at<uint32_t>(scratch, L.sc_runs);
-        launch_scan_u32_u64(cnt, nullptr, n, offsets, at<unsigned long long>(scratch, L.sc_partials), st, runs,
-                            L.ccap / 256 + 1);
-        launch_finalize_coarse(offsets, n, L.ccap, L.cap, S, pair_base, P.v0, P.v1, status, eff_c, st);
+        launch_coarse_offsets(cnt, n, partials, L.ccap, L.cap, S, pair_base, P.v0, P.v1, status, eff_c, offsets, runs,
+                              L.ccap / 256 + 1, st);
         uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
         uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
         uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
@@ -428,14 +432,14 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         }
         launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, eff_c, P.supers, vp, P.v0, P.v1, S,
                           ids, at<int64_t>(state, L.st_ranges), st);
-        // dispatch order of the blending launch
-        launch_order_tiles(at<int64_t>(state, L.st_ranges), L.vg[P.v0].tile_base, P.tiles, order, st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
     KernelMark km(c, H4D_STAGE_BLEND_FWD, P.tiles > 0);
-    launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles, order,
-                         images, at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc), at<float>(state, L.st_C),
-                         at<uint32_t>(state, L.st_tcost), stat_counters(c, state, L), st, km.a, km.b);
+    launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles,
+                         nullptr, images, at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc),
+                         at<float>(state, L.st_C), at<uint32_t>(state, L.st_tcost),
+                         at<uint32_t>(state, L.st_thist) + (size_t)kCostBuckets * (P.v0 / L.per_pass),
+                         stat_counters(c, state, L), st, km.a, km.b);
 }
 
 }  // namespace
@@ -499,7 +503,7 @@ h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     ViewParams* vp = at<ViewParams>(state, L.st_views);
     launch_init_state(view_table(views, n_views, cfg->tile), vp, at<Status>(state, L.st_status),
                       at<unsigned long long>(state, L.st_pair_base), at<unsigned long long>(state, L.st_ranges),
-                      2 * (size_t)L.total_tiles, st);
+                      range_words(L), st);
     PtrTable tab;
     std::memset(&tab, 0, sizeof(tab));
     for (int v = 0; v < n_views; ++v) tab.p[v] = images[v];
@@ -549,7 +553,8 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     pt.n = L.n_passes();
     for (int k = 0; k < pt.n; ++k) pt.tile0[k] = L.vg[L.pass(k).v0].tile_base;
     pt.tile0[pt.n] = L.total_tiles;
-    launch_bwd_prologue(g2, (size_t)kG2Stride * N * n_views, at<uint32_t>(stt, L.st_tcost), pt, border, st);
+    launch_bwd_prologue(g2, (size_t)kG2Stride * N * n_views, at<uint32_t>(stt, L.st_tcost),
+                        at<uint32_t>(stt, L.st_thist), pt, border, st);
     const ViewParams* vp = at<ViewParams>(stt, L.st_views);
     {
         StageScope sc(ctx, st, H4D_STAGE_BLEND_BWD);
@@ -617,7 +622,7 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     hipStream_t st = static_cast<hipStream_t>(stream);
     launch_init_state(view_table(&view, 1, cfg->tile), at<ViewParams>(state, L.st_views),
                       at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base),
-                      at<unsigned long long>(state, L.st_ranges), 2 * (size_t)L.total_tiles, st);
+                      at<unsigned long long>(state, L.st_ranges), range_words(L), st);
     Rec* recs = at<Rec>(state, L.st_recs);
     launch_splats_to_records(n, u, v, conic, opacity, rgb, radius, depth, visible, width, height, recs,
                              at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);

@@ -107,6 +107,13 @@ struct G4Grad {
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Dispatch-order bucket of a tile whose adjoint walks `cost` list entries:
+// 0 for the most expensive (costs of 1023 and more share bucket 0).
+constexpr int kCostBuckets = 1024;
+__device__ __forceinline__ uint32_t cost_bucket(uint32_t cost) {
+    return (uint32_t)(kCostBuckets - 1) - min(cost, (uint32_t)(kCostBuckets - 1));
+}
+
 // One front-to-back blending step, shared bit-for-bit by the forward and the
 // backward kernels (the backward recomputes transmittance instead of storing it,
 // so both must take every decision identically).  Inputs are the LDS copy of a

@@ -80,25 +80,27 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-// Tile (relative to the launch's first) of this workgroup: order[blockIdx.x],
-// the launch's tiles by decreasing cost, so that the expensive tiles start
-// first and every SIMD receives a mix of costs (an entry out of range, which a
-// permutation never has, falls back to blockIdx.x).
+// Tile (relative to the launch's first) of this workgroup: order[blockIdx.x]
+// when an order is given (the launch's tiles by decreasing cost, so that the
+// expensive tiles start first and every SIMD receives a mix of costs; an entry
+// out of range, which a permutation never has, falls back to blockIdx.x).
 __device__ __forceinline__ int dispatch_tile(const uint32_t* __restrict__ order) {
     const uint32_t b = blockIdx.x;
+    if (!order) return (int)b;
     const uint32_t t = order[b];
     return (int)(t < gridDim.x ? t : b);
 }
 
 // STATS = true is a measurement-only instantiation that also counts (pixel,
 // splat) evaluations and blends into counters[0..1].  tcost[tile] receives
-// the tile's last contributor (the adjoint's work on it).
+// the tile's last contributor (the adjoint's work on it), thist[cost_bucket]
+// counts the launch's tiles per bucket.
 template <int B, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
     const ViewParams* __restrict__ views, int v0, int v1, const uint32_t* __restrict__ order, PtrTable images,
     float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib, float* __restrict__ Cout,
-    uint32_t* __restrict__ tcost, unsigned long long* counters) {
+    uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist, unsigned long long* counters) {
     constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
     __shared__ uint32_t s_cost;
@@ -202,13 +204,19 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     for (int k = 0; k < PPL; ++k) lane_last = max(lane_last, last[k]);
     const uint32_t wave_last = wave_max_u32(lane_last);
     if (NT == 64) {
-        if (threadIdx.x == 0) tcost[gt] = wave_last;
+        if (threadIdx.x == 0) {
+            tcost[gt] = wave_last;
+            atomicAdd(&thist[cost_bucket(wave_last)], 1u);
+        }
     } else {
         if (threadIdx.x == 0) s_cost = 0u;
         __syncthreads();
         if (__lane_id() == 0) atomicMax(&s_cost, wave_last);
         __syncthreads();
-        if (threadIdx.x == 0) tcost[gt] = s_cost;
+        if (threadIdx.x == 0) {
+            tcost[gt] = s_cost;
+            atomicAdd(&thist[cost_bucket(s_cost)], 1u);
+        }
     }
     if (STATS) {
         const unsigned long long e = wave_sum_u64(n_eval), b = wave_sum_u64(n_blend);
@@ -429,11 +437,11 @@ static void launch_timed(void (*k)(P...), int grid, int block, hipStream_t st, h
 template <int B, int C>
 static void fwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
                   int v1, int n_tiles, const uint32_t* order, const PtrTable& images, float* Tfin,
-                  uint32_t* ncontrib, float* Cout, uint32_t* tcost, unsigned long long* counters, hipStream_t st,
-                  hipEvent_t e0, hipEvent_t e1) {
+                  uint32_t* ncontrib, float* Cout, uint32_t* tcost, uint32_t* thist, unsigned long long* counters,
+                  hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
     launch_timed(counters ? k_composite_fwd<B, C, true> : k_composite_fwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
-                 N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout, tcost, counters);
+                 N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout, tcost, thist, counters);
 }
 template <int B, int C>
 static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
@@ -464,10 +472,11 @@ static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ra
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
-                          unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                          uint32_t* thist, unsigned long long* counters, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
     if (n_tiles == 0) return;
     H4D_DISPATCH(fwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, order, images, Tfin, ncontrib, Cout, tcost,
-                 counters, st, e0, e1);
+                 thist, counters, st, e0, e1);
 }
 
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,

@@ -83,13 +83,19 @@ struct CullShape {
 // Two-level binning over the views [v0, v1) of one pass; j = r * N + rank
 // indexes the depth-ordered Gaussians of view v0 + r (n = (v1 - v0) * N).
 // Super-tile ids are relative to view v0, tile ids t to its first tile.
+// partials: coarse_count_blocks(n) + 1 words, each count workgroup's sum.
+int coarse_count_blocks(int n);
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
-                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, hipStream_t st);
-// Coarse capacity (ccap entries) and list-slot (cap) checks; regions of the
-// pass: S^2 C slots from pair_base[v0], end to pair_base[v1].
-void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t ccap, uint64_t cap, int S,
-                            unsigned long long* pair_base, int v0, int v1, Status* status,
-                            unsigned long long* eff_count, hipStream_t st);
+                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, unsigned long long* partials,
+                         hipStream_t st);
+// offsets[j] = sum of cnt before j (offsets[n] = C) with run_start as in
+// launch_scan_u32_u64; coarse capacity (ccap entries) and list-slot (cap)
+// checks; regions of the pass: S^2 C slots from pair_base[v0], end to
+// pair_base[v1]; *eff_count = C, or 0 on overflow.
+void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* partials, uint64_t ccap, uint64_t cap,
+                           int S, unsigned long long* pair_base, int v0, int v1, Status* status,
+                           unsigned long long* eff_count, unsigned long long* offsets, uint32_t* run_start,
+                           uint64_t run_cap, hipStream_t st);
 // With mkey (super-tile ids of the pass below 2^16) the keys carry each entry's
 // tile mask in their upper 16 bits (cull: less the tiles no pixel of which can
 // reach alpha >= 1/255).
@@ -112,19 +118,17 @@ void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint6
 // [first, last+1) + *base (base may be null)
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st);
-// Dispatch order of the blending launches: the tiles of each pass, relative to
-// the pass's first, by decreasing cost (a permutation; ties in any order).
-// Forward: one pass [tile0, tile0 + n) with cost = list length (ranges).
-void launch_order_tiles(const int64_t* ranges, int tile0, int n, uint32_t* order, hipStream_t st);
 // Backward prologue: zeroes g2[0, n_g2) and orders the tiles of every pass by
-// tcost (pass k: global tiles [tile0[k], tile0[k + 1]), its order at the same
-// offsets).
+// decreasing tcost (pass k: global tiles [tile0[k], tile0[k + 1]), its order
+// at the same offsets, relative to tile0[k]; thist + k kCostBuckets: the
+// forward's per-bucket tile counts of pass k).  A permutation whatever the
+// counts hold: buckets that overflow fall back to identity order.
 struct PassTiles {
     int32_t n;                     // passes
     int32_t tile0[kMaxViews + 1];
 };
-void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const PassTiles& passes, uint32_t* order,
-                         hipStream_t st);
+void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const uint32_t* thist,
+                         const PassTiles& passes, uint32_t* order, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 
@@ -132,15 +136,16 @@ void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 bool composite_supported(int tile, int chunk);
 // One launch over the tiles of views [v0, v1) (n_tiles = their total): recs
 // holds every view's records ([view][N]), images/dls are indexed by view and
-// g2 holds kG2Stride floats per (view, Gaussian).  order: the n_tiles tiles
-// (relative to the launch's first) in dispatch order, a permutation
-// (launch_order_tiles).  The forward writes, per tile, its last contributor
-// into tcost[global tile].  Non-null e0 / e1 receive the kernel's own start /
-// end time.
+// g2 holds kG2Stride floats per (view, Gaussian).  order (may be null: tile
+// b = workgroup b): the n_tiles tiles (relative to the launch's first) in
+// dispatch order, a permutation.  The forward writes, per tile, its last
+// contributor into tcost[global tile] and counts the launch's tiles per
+// cost_bucket into thist[kCostBuckets] (zero on entry).  Non-null e0 / e1
+// receive the kernel's own start / end time.
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
-                          unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
+                          uint32_t* thist, unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,

@@ -35,19 +35,20 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 // inclusive-to-exclusive block scan of one value per thread (256 threads)
 template <typename T>
 __device__ inline T block_exclusive_scan_256(T v, T* s_buf, T& total) {
-    const int tid = threadIdx.x;
-    s_buf[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        T add = tid >= off ? s_buf[tid - off] : (T)0;
-        __syncthreads();
-        s_buf[tid] += add;
-        __syncthreads();
+    // wave scans, then the four wave totals (s_buf[0..3])
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    T incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const T y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
     }
-    total = s_buf[255];
-    const T incl = s_buf[tid];
+    if (lane == 63) s_buf[w] = incl;
     __syncthreads();
-    return incl - v;
+    T base = (T)0;
+    for (int k = 0; k < w; ++k) base += s_buf[k];
+    total = s_buf[0] + s_buf[1] + s_buf[2] + s_buf[3];
+    __syncthreads();  // s_buf is free again for the caller
+    return base + incl - v;
 }
 
 // ---------------------------------------------------------------------------
@@ -428,35 +429,81 @@ __device__ inline uint32_t tile_mask(const CullShape& cs, int cull, uint32_t tx0
 // Per depth-ordered Gaussian j of the view range (j = r * N + rank, view
 // v0 + r): its tile rectangle, its super-tile count and (shapes != null) the
 // shape of its alpha >= 1/255 region for the tile test.
+// One Gaussian per thread; each workgroup also leaves its sum of counts for
+// the offsets' scan (partials[blockIdx.x]).
 __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n, int N,
                                                       const Rec* __restrict__ recs, int v0, int tile, int S,
                                                       uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted,
-                                                      CullShape* __restrict__ shapes) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int view = v0 + j / N;
-    const Rec& rec = recs[(size_t)view * N + sorted_gid[j]];
-    const uint4 d = rec.d;
-    if (d.w == 0u) {
-        cnt[j] = 0u;
-        rect_sorted[j] = 0ull;
-        return;
-    }
+                                                      CullShape* __restrict__ shapes,
+                                                      unsigned long long* __restrict__ partials) {
+    __shared__ unsigned long long s_buf[256];
     const uint32_t t = (uint32_t)tile, s = (uint32_t)S;
-    const uint32_t tx0 = (d.x & 0xFFFFu) / t, tx1 = (d.x >> 16) / t, ty0 = (d.y & 0xFFFFu) / t, ty1 = (d.y >> 16) / t;
-    rect_sorted[j] = pack_rect(tx0, tx1, ty0, ty1);
-    cnt[j] = (tx1 / s - tx0 / s + 1u) * (ty1 / s - ty0 / s + 1u);
-    if (shapes) shapes[j] = cull_shape(rec);
+    const int j = blockIdx.x * 256 + (int)threadIdx.x;
+    uint32_t c = 0u;
+    if (j < n) {
+        const int view = v0 + j / N;
+        const Rec& rec = recs[(size_t)view * N + sorted_gid[j]];
+        const uint4 d = rec.d;
+        uint64_t rect = 0ull;
+        if (d.w != 0u) {
+            const uint32_t tx0 = (d.x & 0xFFFFu) / t, tx1 = (d.x >> 16) / t, ty0 = (d.y & 0xFFFFu) / t,
+                           ty1 = (d.y >> 16) / t;
+            rect = pack_rect(tx0, tx1, ty0, ty1);
+            c = (tx1 / s - tx0 / s + 1u) * (ty1 / s - ty0 / s + 1u);
+            if (shapes) shapes[j] = cull_shape(rec);
+        }
+        rect_sorted[j] = rect;
+        cnt[j] = c;
+    }
+    unsigned long long tot;
+    block_exclusive_scan_256<unsigned long long>((unsigned long long)c, s_buf, tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Coarse capacity check and tile-list regions of the pass: the S^2 tiles of a
-// super-tile get regions as long as the super-tile's list, so the pass needs
-// S^2 C list slots from pair_base[v0]; their end goes to pair_base[v1].
-__global__ void k_finalize_coarse(const unsigned long long* offsets, int n, uint64_t ccap, uint64_t cap, int S,
-                                  unsigned long long* pair_base, int v0, int v1, Status* status,
-                                  unsigned long long* eff_count) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long C = offsets[n];
+// offsets[j] = partials[j / 256] (scanned) + this workgroup's exclusive scan;
+// run_start as in k_scan_down.
+__global__ void __launch_bounds__(256) k_coarse_down(const uint32_t* __restrict__ cnt, int n,
+                                                     const unsigned long long* __restrict__ partials, int nparts,
+                                                     unsigned long long* __restrict__ offsets,
+                                                     uint32_t* __restrict__ run_start, uint64_t run_cap) {
+    __shared__ unsigned long long s_buf[256];
+    const int j = blockIdx.x * 256 + (int)threadIdx.x;
+    const uint32_t c = j < n ? cnt[j] : 0u;
+    unsigned long long tot;
+    const unsigned long long run =
+        block_exclusive_scan_256<unsigned long long>((unsigned long long)c, s_buf, tot) + partials[blockIdx.x];
+    if (j < n) {
+        offsets[j] = run;
+        for (uint64_t r = (run + 255) / 256; r * 256 < run + c && r < run_cap; ++r) run_start[r] = (uint32_t)j;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = partials[nparts];
+}
+
+// Exclusive scan of the count workgroups' sums (partials[nparts] = total C),
+// then the coarse capacity check and the tile-list regions of the pass: the
+// S^2 tiles of a super-tile get regions as long as the super-tile's list, so
+// the pass needs S^2 C list slots from pair_base[v0]; their end goes to
+// pair_base[v1].
+__global__ void __launch_bounds__(256) k_coarse_top(unsigned long long* __restrict__ partials, int nparts,
+                                                    uint64_t ccap, uint64_t cap, int S,
+                                                    unsigned long long* pair_base, int v0, int v1, Status* status,
+                                                    unsigned long long* eff_count) {
+    __shared__ unsigned long long s_buf[256];
+    // thread t scans the contiguous chunk [t q, (t + 1) q) of the partials
+    const int q = (nparts + 255) / 256;
+    const int i0 = min(nparts, (int)threadIdx.x * q), i1 = min(nparts, i0 + q);
+    unsigned long long sum = 0;
+    for (int i = i0; i < i1; ++i) sum += partials[i];
+    unsigned long long carry;
+    unsigned long long run = block_exclusive_scan_256<unsigned long long>(sum, s_buf, carry);
+    for (int i = i0; i < i1; ++i) {
+        const unsigned long long v = partials[i];
+        partials[i] = run;
+        run += v;
+    }
+    if (threadIdx.x != 0) return;
+    partials[nparts] = carry;
+    const unsigned long long C = carry;
     const unsigned long long base = pair_base[v0];
     const unsigned long long R = C * (unsigned long long)(S * S);
     status->pairs_needed += R;
@@ -642,69 +689,55 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ key
 __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long val) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = val;
 }
-// Counting sort of n tile costs by one workgroup (blockDim a multiple of 64)
-// into order[0, n): decreasing cost in 1024 buckets linear in cost / max cost,
-// ties in any order.  A permutation of [0, n) whatever the costs.
-template <class Cost>
-__device__ void order_by_cost(int n, Cost cost, uint32_t* __restrict__ order) {
-    __shared__ uint32_t s_hist[1024];
-    __shared__ uint32_t s_max;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int b = tid; b < 1024; b += nt) s_hist[b] = 0u;
-    if (tid == 0) s_max = 0u;
-    __syncthreads();
-    uint32_t mx = 0u;
-    for (int t = tid; t < n; t += nt) mx = max(mx, cost(t));
-    for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
-    if (__lane_id() == 0) atomicMax(&s_max, mx);
-    __syncthreads();
-    const uint64_t m = max(s_max, 1u);
-    auto bucket = [m](uint32_t c) { return 1023u - (uint32_t)((uint64_t)min((uint64_t)c, m) * 1023u / m); };
-    for (int t = tid; t < n; t += nt) atomicAdd(&s_hist[bucket(cost(t))], 1u);
-    __syncthreads();
-    if (tid < 64) {  // exclusive scan of the 1024 counts: 16 per lane
-        uint32_t v[16], sum = 0u;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            v[i] = s_hist[16 * tid + i];
-            sum += v[i];
-        }
-        uint32_t incl = sum;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
-            if (tid >= off) incl += y;
-        }
-        uint32_t run = incl - sum;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            s_hist[16 * tid + i] = run;
-            run += v[i];
-        }
-    }
-    __syncthreads();
-    for (int t = tid; t < n; t += nt) {
-        const uint32_t pos = atomicAdd(&s_hist[bucket(cost(t))], 1u);
-        order[pos] = (uint32_t)t;
-    }
-}
-
-// Forward: cost of a tile = its list length.
-__global__ void __launch_bounds__(1024) k_order_tiles(const int64_t* __restrict__ ranges, int tile0, int n,
-                                                      uint32_t* __restrict__ order) {
-    const int64_t* r = ranges + 2 * (size_t)tile0;
-    order_by_cost(
-        n, [r](int t) { return (uint32_t)min(r[2 * t + 1] - r[2 * t], (int64_t)0xFFFFFFFFll); }, order);
-}
-
-// Backward: workgroup k < passes.n orders pass k by tcost, the others zero g2.
+// Backward: workgroup k < passes.n orders pass k from the forward's per-bucket
+// tile counts (an exclusive scan, then one scatter pass over the tiles; ties
+// in any order), the other workgroups zero g2.  Counts that do not add up to
+// the pass's tiles give the identity order.
 __global__ void __launch_bounds__(1024) k_bwd_prologue(float* __restrict__ g2, size_t n_g2,
-                                                       const uint32_t* __restrict__ tcost, PassTiles passes,
+                                                       const uint32_t* __restrict__ tcost,
+                                                       const uint32_t* __restrict__ thist, PassTiles passes,
                                                        uint32_t* __restrict__ order) {
     const int k = (int)blockIdx.x;
     if (k < passes.n) {
-        const int t0 = passes.tile0[k];
-        const uint32_t* c = tcost + t0;
-        order_by_cost(passes.tile0[k + 1] - t0, [c](int t) { return c[t]; }, order + t0);
+        __shared__ uint32_t s_pos[kCostBuckets];
+        __shared__ uint32_t s_total, s_bad;
+        static_assert(kCostBuckets == 16 * 64, "one wave scans the buckets");
+        const int tid = threadIdx.x, nt = blockDim.x;
+        const int t0 = passes.tile0[k], n = passes.tile0[k + 1] - t0;
+        const uint32_t* h = thist + (size_t)k * kCostBuckets;
+        order += t0;
+        if (tid < 64) {
+            uint32_t v[16], sum = 0u;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                v[i] = h[16 * tid + i];
+                sum += v[i];
+            }
+            uint32_t incl = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+                if (tid >= off) incl += y;
+            }
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                s_pos[16 * tid + i] = run;
+                run += v[i];
+            }
+            if (tid == 63) s_total = run;
+        }
+        if (tid == 0) s_bad = 0u;
+        __syncthreads();
+        if (s_total == (uint32_t)n) {
+            for (int t = tid; t < n; t += nt) {
+                const uint32_t pos = atomicAdd(&s_pos[cost_bucket(tcost[t0 + t])], 1u);
+                if (pos < (uint32_t)n) order[pos] = (uint32_t)t;
+                else s_bad = 1u;
+            }
+        }
+        __syncthreads();
+        if (s_total != (uint32_t)n || s_bad)
+            for (int t = tid; t < n; t += nt) order[t] = (uint32_t)t;
         return;
     }
     const size_t nb = (size_t)(gridDim.x - passes.n);
@@ -715,15 +748,21 @@ __global__ void k_fill_f32(float* p, size_t n, float val) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = val;
 }
 
+int coarse_count_blocks(int n) { return ceil_div(n, 256); }
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
-                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, hipStream_t st) {
+                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, unsigned long long* partials,
+                         hipStream_t st) {
     if (n == 0) return;
-    k_coarse_count<<<ceil_div(n, 256), 256, 0, st>>>(sorted_gid, n, N, recs, v0, tile, S, cnt, rect_sorted, shapes);
+    k_coarse_count<<<coarse_count_blocks(n), 256, 0, st>>>(sorted_gid, n, N, recs, v0, tile, S, cnt, rect_sorted,
+                                                           shapes, partials);
 }
-void launch_finalize_coarse(const unsigned long long* offsets, int n, uint64_t ccap, uint64_t cap, int S,
-                            unsigned long long* pair_base, int v0, int v1, Status* status,
-                            unsigned long long* eff_count, hipStream_t st) {
-    k_finalize_coarse<<<1, 1, 0, st>>>(offsets, n, ccap, cap, S, pair_base, v0, v1, status, eff_count);
+void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* partials, uint64_t ccap, uint64_t cap,
+                           int S, unsigned long long* pair_base, int v0, int v1, Status* status,
+                           unsigned long long* eff_count, unsigned long long* offsets, uint32_t* run_start,
+                           uint64_t run_cap, hipStream_t st) {
+    const int nb = coarse_count_blocks(n);
+    k_coarse_top<<<1, 256, 0, st>>>(partials, nb, ccap, cap, S, pair_base, v0, v1, status, eff_count);
+    if (n > 0) k_coarse_down<<<nb, 256, 0, st>>>(cnt, n, partials, nb, offsets, run_start, run_cap);
 }
 void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, int N,
                         const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
@@ -750,15 +789,10 @@ void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long 
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {
     k_ranges<<<2048, 256, 0, st>>>(keys, key_mask, eff_count, base, ranges);
 }
-void launch_order_tiles(const int64_t* ranges, int tile0, int n, uint32_t* order, hipStream_t st) {
-    if (n == 0) return;
-    k_order_tiles<<<1, 1024, 0, st>>>(ranges, tile0, n, order);
-}
-
-void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const PassTiles& passes, uint32_t* order,
-                         hipStream_t st) {
+void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const uint32_t* thist,
+                         const PassTiles& passes, uint32_t* order, hipStream_t st) {
     const int fill = (int)std::max<size_t>(1, std::min<size_t>(1024, (n_g2 + 4095) / 4096));
-    k_bwd_prologue<<<passes.n + fill, 1024, 0, st>>>(g2, n_g2, tcost, passes, order);
+    k_bwd_prologue<<<passes.n + fill, 1024, 0, st>>>(g2, n_g2, tcost, thist, passes, order);
 }
 
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st) {
