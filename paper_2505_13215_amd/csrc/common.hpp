@@ -164,10 +164,7 @@ __device__ __forceinline__ bool eval_pix(const Splat& s, const ColTerm& c, int p
     return in && !(p2 > 0.0f) && alpha >= kMinAlpha;
 }
 
-__device__ __forceinline__ float next_T(float T, float alpha) {
-#pragma clang fp contract(off)
-    const float oma = 1.0f - alpha;
-    return T * oma;
-}
+// T (1 - alpha) as T - alpha T in one fused operation (exact T for alpha = 0).
+__device__ __forceinline__ float next_T(float T, float alpha) { return __builtin_fmaf(-alpha, T, T); }
 
 }  // namespace h4d

@@ -364,7 +364,8 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                     n_blend += ok ? 1u : 0u;
                 }
                 any = any || ok;
-                const float w = ok ? alpha * T[k] : 0.0f;
+                const float a = ok ? alpha : 0.0f;
+                const float w = a * T[k];
                 const float gc = G0[k] * s.cr + G1[k] * s.cg + G2[k] * s.cb;
                 P[k] = __builtin_fmaf(w, gc, P[k]);
                 // dL/dalpha = T dot(dL/dC, c) - dot(dL/dC, colour behind) / (1 - alpha),
@@ -381,7 +382,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 sd += dpn;
                 sdy += dpy;
                 syy = __builtin_fmaf(dpy, dy, syy);
-                T[k] = ok ? next_T(T[k], alpha) : T[k];
+                T[k] = next_T(T[k], a);  // unchanged where a = 0
             }
             // conic and centre terms without their constant factors (applied after
             // the reduction): sum d (2 qa dx + qb dy), sum d (qb dx + 2 qc dy),
