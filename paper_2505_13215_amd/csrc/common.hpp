@@ -134,8 +134,11 @@ struct Splat {
 
 // Column part: pixel-centre x minus splat-centre x, its conic term and the
 // x half of the square test.
+// Column part of the quadratic form p2 = qa dx^2 + qb dx dy + qc dy^2 (shared
+// by a lane's pixels): qa dx^2 and qb dx, so that each pixel adds
+// dy (qc dy + qb dx) with two fused multiply-adds.
 struct ColTerm {
-    float dx, qadx;
+    float dx, qadx, a2, bx;  // dx, qa dx, qa dx^2, qb dx
     bool inx;
 };
 
@@ -145,6 +148,8 @@ __device__ __forceinline__ ColTerm eval_col(const Splat& s, int px, float pxc) {
     c.inx = px >= s.x0 && px <= s.x1;
     c.dx = (pxc - s.ui) - s.uf;
     c.qadx = s.qa * c.dx;
+    c.a2 = c.qadx * c.dx;
+    c.bx = s.qb * c.dx;
     return c;
 }
 
@@ -155,8 +160,8 @@ __device__ __forceinline__ bool eval_pix(const Splat& s, const ColTerm& c, int p
 #pragma clang fp contract(off)
     const bool in = c.inx && py >= s.y0 && py <= s.y1;
     dy = (pyc - s.vi) - s.vf;
-    const float t = __builtin_fmaf(s.qb, dy, c.qadx);
-    const float p2 = __builtin_fmaf(s.qc * dy, dy, c.dx * t);
+    const float u = __builtin_fmaf(s.qc, dy, c.bx);
+    const float p2 = __builtin_fmaf(dy, u, c.a2);
     G = __builtin_amdgcn_exp2f(p2);
     const float ap = s.op * G;
     clamped = ap > kMaxAlpha;

@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         for (int j = 0; j < jend; ++j) {
             const Splat s = to_splat(s_sp[j]);
             const ColTerm c = eval_col(s, px, pxc);
-            const float twoqadx = 2.0f * c.qadx, qbdx = s.qb * c.dx, dx2 = c.dx * c.dx, twoqc = 2.0f * s.qc;
+            const float twoqadx = 2.0f * c.qadx, qbdx = c.bx, dx2 = c.dx * c.dx, twoqc = 2.0f * s.qc;
             // per-splat sums of this lane's pixels: dL/dopacity, dL/drgb, and the
             // moments sum d, sum d dy, sum d dy^2 of d = dL/dpower (the lane's pixels
             // share dx, so the centre and conic terms follow from them below)
