@@ -294,7 +294,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not part of it",
+        print("bench.py measures one GPU only (--gpus 1); multi-GPU runs are not part of it",
               file=sys.stderr)
         sys.exit(2)
 
@@ -392,6 +392,25 @@ def main():
     log("blend kernels, ms per launch in the timed region: " +
         ", ".join(f"{k} {v:.4f}" for k, v in kernel_ms.items()))
 
+    # the same steps without the optimiser (render_fwd + loss gradient +
+    # render_bwd, the fwd+bwd step as the survey defines Mpix/s), reported beside
+    def step_fb(i):
+        v = sched[i][0]
+        h = rast.forward(g3, g4, [v])
+        h4d.l1_loss_grad(rast, h.images, [targets[i % len(targets)]], [v], [dl], loss)
+        rast.backward(h, g3, g4, [dl], out=(gr3, gr4))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        step_fb(i)
+    torch.cuda.synchronize()
+    dt_fb = time.perf_counter() - t0
+    rast.verify()
+    fwd_bwd = {"step": "fwd+L1+bwd (no optimiser)", "ms_per_step": round(dt_fb * 1e3 / args.steps, 4),
+               "mpix_s": round(args.steps * W * H / dt_fb / 1e6, 2)}
+    log(f"without the optimiser: {fwd_bwd}")
+
     # evaluation counts of the blending kernels (counting instantiation, outside the timed region)
     log(f"counting blend evaluations on {args.stats_views} views")
     rast.stats(True)
@@ -472,6 +491,7 @@ def main():
                    "parallelism": "single_gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fwd_bwd_only": fwd_bwd,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "blend_evals_per_view": {k: int(v) for k, v in cnt.items()},
         "pairs_per_view_max": peak_pairs,

@@ -160,7 +160,7 @@ struct Layout {
     size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_thist, st_T, st_nc, st_C, st_tcost,
         state_bytes;
     // scratch, forward use
-    size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff,
+    size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_ceff,
         sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges,
         sc_shape, sc_runs, fwd_bytes;
     // scratch, backward use
@@ -233,6 +233,7 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_offsets = f.take(8 * (np + 1));
     L.sc_partials = f.take(8 * ((size_t)coarse_count_blocks((int)std::min<size_t>(np, 0x7FFFFFFF)) + 2));
     L.sc_eff = f.take(8);
+    L.sc_ceff = f.take(8);
     L.sc_pkeys = f.take(4 * (size_t)L.ccap);
     L.sc_pvals = f.take(4 * (size_t)L.ccap);
     L.sc_pkeys2 = f.take(4 * (size_t)L.ccap);
@@ -406,22 +407,28 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         uint32_t* kin = pk;
         uint32_t* vin = pv;
         int shift = 0;
-        // with the tile mask in the keys the per-tile pass needs only splat ids:
-        // the last pass writes those in place of the depth ranks
+        // with the tile mask in the keys, the first pass also drops the entries
+        // whose mask is empty (after culling, about 40 % of them), and the
+        // per-tile pass needs only splat ids: the last pass writes those in place
+        // of the depth ranks
+        // (the first pass writes the kept count whenever it runs, i.e. ccap > 0)
+        const bool drop = mkey && L.ccap > 0;
+        unsigned long long* ceff = drop ? at<unsigned long long>(scratch, L.sc_ceff) : eff_c;  // entries kept
         for (int p = 0; p < passes; ++p) {
             const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
             uint32_t* kout = (kin == pk) ? pk2 : pk;
             uint32_t* vout = (vin == pv) ? pv2 : pv;
-            launch_radix_pass(kin, vin, kout, vout, eff_c, 0, L.ccap, shift, nb, hist, totals, nullptr, st, 1, 0,
-                              passes == 1 ? cranges : nullptr, P.supers, kSortItems,
-                              (mkey && p == passes - 1) ? dv : nullptr);
+            launch_radix_pass(kin, vin, kout, vout, p == 0 ? eff_c : ceff, 0, L.ccap, shift, nb, hist, totals, nullptr,
+                              st, 1, 0, passes == 1 ? cranges : nullptr, P.supers, kSortItems,
+                              (mkey && p == passes - 1) ? dv : nullptr, (drop && p == 0) ? 1 : 0,
+                              (drop && p == 0) ? ceff : nullptr);
             kin = kout;
             vin = vout;
             shift += nb;
         }
         if (passes > 1) {
             launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
-            launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, eff_c, nullptr, cranges, st);
+            launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, ceff, nullptr, cranges, st);
         }
         // splat ids of the sorted entries (otherwise gathered into the buffer
         // the sort did not end in)
@@ -430,7 +437,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
             cgid = (kin == pk) ? pk2 : pk;
             launch_coarse_gather(vin, dv, eff_c, cgid, st);
         }
-        launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, eff_c, P.supers, vp, P.v0, P.v1, S,
+        launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, ceff, P.supers, vp, P.v0, P.v1, S,
                           ids, at<int64_t>(state, L.st_ranges), st);
     }
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);

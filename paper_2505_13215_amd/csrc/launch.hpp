@@ -55,12 +55,15 @@ size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits, int items);
 // only; for short key sets, more and smaller blocks).
 // digit_ranges (may be null): for a pass over whole keys, [start, end) of each
 // of the first n_digit_ranges digits in the output.  val_map (may be null):
-// the values written out are val_map[value].
+// the values written out are val_map[value].  skip_empty: keys whose upper 16
+// bits are zero are dropped (the output holds the others, in order, from
+// position 0); out_count (may be null) receives the number of keys written.
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
                        int n_seg = 1, uint64_t seg_stride = 0, int64_t* digit_ranges = nullptr,
-                       int n_digit_ranges = 0, int items = kSortItems, const uint32_t* val_map = nullptr);
+                       int n_digit_ranges = 0, int items = kSortItems, const uint32_t* val_map = nullptr,
+                       int skip_empty = 0, unsigned long long* out_count = nullptr);
 int scan_blocks(int n);
 // out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
 // With run_start, run_start[r] (r < run_cap) receives the index i whose range

@@ -79,11 +79,13 @@ __device__ inline uint32_t block_scan_digits(uint32_t* s, int radix, uint32_t* s
 }
 
 // MB: largest digit width the instantiation handles (LDS is sized for it).
+// skip_empty: keys whose upper 16 bits are zero (coarse entries with an empty
+// tile mask) are left out of the counts (and, in the downsweep, of the output).
 template <int MB, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                                 const unsigned long long* dcount, uint64_t hcount,
                                                                 int shift, int nbits, uint32_t* __restrict__ hist,
-                                                                int nblocks, uint64_t seg_stride) {
+                                                                int nblocks, uint64_t seg_stride, int skip_empty) {
     __shared__ uint32_t s_hist[4][1 << MB];
     const int radix = 1 << nbits;
     keys += (size_t)blockIdx.y * seg_stride;
@@ -97,7 +99,10 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(const uint32_t* 
     __syncthreads();
     for (int k = 0; k < ITEMS; ++k) {
         const uint64_t idx = begin + (uint64_t)k * kSortThreads + tid;
-        if (idx < n) atomicAdd(&s_hist[w][(keys[idx] >> shift) & mask], 1u);
+        if (idx < n) {
+            const uint32_t key = keys[idx];
+            if (!skip_empty || (key >> 16) != 0u) atomicAdd(&s_hist[w][(key >> shift) & mask], 1u);
+        }
     }
     __syncthreads();
     for (int d = tid; d < radix; d += kSortThreads)
@@ -141,7 +146,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     uint32_t* __restrict__ vals_out, const unsigned long long* dcount, uint64_t hcount, int shift, int nbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int nblocks,
     const unsigned long long* out_offset, uint64_t seg_stride, int64_t* __restrict__ digit_ranges, int n_digit_ranges,
-    const uint32_t* __restrict__ val_map) {
+    const uint32_t* __restrict__ val_map, int skip_empty, unsigned long long* out_count) {
     __shared__ uint32_t s_wcount[4][1 << MB];
     __shared__ uint32_t s_dstart[1 << MB];
     __shared__ uint32_t s_gbase[1 << MB];
@@ -152,7 +157,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
 
     const uint64_t n = read_count(dcount, hcount);
     const uint64_t begin = (uint64_t)blockIdx.x * TILE;
-    if (begin >= n) return;  // uniform over the block
+    if (begin >= n) {  // uniform over the block
+        // no keys at all: the kept count is still written (block 0 holds keys otherwise)
+        if (out_count && n == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *out_count = 0ull;
+        return;
+    }
     const int radix = 1 << nbits;
     {
         const size_t so = (size_t)blockIdx.y * seg_stride;
@@ -167,7 +176,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     // global base of digit d = (exclusive scan of totals)[d] + this block's scanned count
     for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] = totals[d];
     __syncthreads();
-    block_scan_digits<MB>(s_gbase, radix, s_buf);
+    const uint32_t n_out = block_scan_digits<MB>(s_gbase, radix, s_buf);
+    if (out_count && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *out_count = n_out;
     // a single-pass sort over whole keys: the digit runs are the key ranges
     if (digit_ranges && blockIdx.x == 0 && blockIdx.y == 0)
         for (int d = tid; d < n_digit_ranges; d += kSortThreads) {
@@ -181,8 +191,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     const unsigned long long lt = lanemask_lt();
     for (int r = 0; r < ITEMS; ++r) {
         const uint64_t idx = begin + (uint64_t)w * (ITEMS * 64) + (uint64_t)r * 64 + lane;
-        const bool valid = idx < n;
-        key[r] = valid ? keys_in[idx] : 0u;
+        key[r] = idx < n ? keys_in[idx] : 0u;
+        const bool valid = idx < n && (!skip_empty || (key[r] >> 16) != 0u);
         val[r] = valid ? vals_in[idx] : 0u;
         const uint32_t d = (key[r] >> shift) & mask;
         unsigned long long peers = __ballot(valid);
@@ -210,10 +220,10 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         s_dstart[d] = run;
     }
     __syncthreads();
-    block_scan_digits<MB>(s_dstart, radix, s_buf);
+    const int cnt = (int)block_scan_digits<MB>(s_dstart, radix, s_buf);  // keys this block places
     for (int r = 0; r < ITEMS; ++r) {
         const uint64_t idx = begin + (uint64_t)w * (ITEMS * 64) + (uint64_t)r * 64 + lane;
-        if (idx < n) {
+        if (idx < n && (!skip_empty || (key[r] >> 16) != 0u)) {
             const uint32_t d = (key[r] >> shift) & mask;
             const uint32_t pos = s_dstart[d] + s_wcount[w][d] + rank[r];
             s_keys[pos] = key[r];
@@ -221,7 +231,6 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         }
     }
     __syncthreads();
-    const int cnt = (int)min((uint64_t)TILE, n - begin);
     const unsigned long long off = out_offset ? *out_offset : 0ull;
     for (int p = tid; p < cnt; p += kSortThreads) {
         const uint32_t k = s_keys[p];
@@ -244,7 +253,7 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
                        uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
                        int n_seg, uint64_t seg_stride, int64_t* digit_ranges, int n_digit_ranges, int items,
-                       const uint32_t* val_map) {
+                       const uint32_t* val_map, int skip_empty, unsigned long long* out_count) {
     const int nb = radix_blocks(capacity, items);
     if (nb == 0 || n_seg == 0) return;
     const dim3 grid(nb, n_seg);
@@ -252,12 +261,13 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
 #define H4D_RADIX_PASS(MB, IT)                                                                                       \
     do {                                                                                                              \
         k_radix_upsweep<MB, IT><<<grid, kSortThreads, 0, st>>>(keys_in, dcount, hcount, shift, nbits, hist, nb,       \
-                                                              seg_stride);                                           \
+                                                              seg_stride, skip_empty);                               \
         k_radix_digit_scan<<<dim3(1 << nbits, n_seg), 256, 0, st>>>(hist, nb, 1 << nbits, totals, dcount, hcount,    \
                                                                     kSortThreads * IT);                              \
         k_radix_downsweep<MB, IT><<<grid, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out, dcount,        \
                                                                 hcount, shift, nbits, hist, totals, nb, out_offset,   \
-                                                                seg_stride, digit_ranges, n_digit_ranges, val_map);   \
+                                                                seg_stride, digit_ranges, n_digit_ranges, val_map,    \
+                                                                skip_empty, out_count);                               \
     } while (0)
     if (items == 2 && nbits <= 8) {
         H4D_RADIX_PASS(8, 2);  // short key sets: more, smaller blocks
