@@ -409,14 +409,34 @@ __device__ inline uint32_t tile_mask(const CullShape& cs, int cull, uint32_t tx0
                                      uint32_t ty1, uint32_t bx, uint32_t by, int S, int tile) {
     const uint32_t lx0 = max(tx0, bx) - bx, lx1 = min(tx1, bx + (uint32_t)S - 1u) - bx;
     const uint32_t ly0 = max(ty0, by) - by, ly1 = min(ty1, by + (uint32_t)S - 1u) - by;
-    uint32_t mask = 0u;
+    // S <= 4: fixed, unrolled loops over the super-tile's rows and columns (tiles
+    // outside [l0, l1] are masked), so that the lanes of a wave do not diverge
+    uint32_t cols = 0u, rows = 0u;  // bit l: column / row l overlaps the rectangle
+#pragma unroll
+    for (uint32_t l = 0; l < 4u; ++l) {
+        cols |= (l >= lx0 && l <= lx1) ? 1u << l : 0u;
+        rows |= (l >= ly0 && l <= ly1) ? 1u << l : 0u;
+    }
     if (!cull || cs.mode == 0) {
-        for (uint32_t ly = ly0; ly <= ly1; ++ly)
-            for (uint32_t lx = lx0; lx <= lx1; ++lx) mask |= 1u << (ly * (uint32_t)S + lx);
-        return mask;
+        uint32_t mask = 0u;
+#pragma unroll
+        for (uint32_t ly = 0; ly < 4u; ++ly)
+            if ((rows >> ly) & 1u) mask |= cols << (ly * (uint32_t)S);
+        return mask & ((S == 4) ? 0xFFFFu : 0xFu);
     }
     if (cs.mode == 2) return 0u;
-    for (uint32_t ly = ly0; ly <= ly1; ++ly) {
+    // the columns' pixel-centre offset intervals do not depend on the row
+    float X0[4], X1[4];
+#pragma unroll
+    for (uint32_t lx = 0; lx < 4u; ++lx) {
+        const int tx = (int)(bx + lx);
+        X0[lx] = ((float)max(tx * tile, cs.px0) + 0.5f - cs.ui) - cs.uf;
+        X1[lx] = ((float)min(tx * tile + tile - 1, cs.px1) + 0.5f - cs.ui) - cs.uf;
+    }
+    uint32_t mask = 0u;
+#pragma unroll
+    for (uint32_t ly = 0; ly < 4u; ++ly) {
+        if (!((rows >> ly) & 1u)) continue;
         const int ty = (int)(by + ly);
         const float Y0 = ((float)max(ty * tile, cs.py0) + 0.5f - cs.vi) - cs.vf;
         const float Y1 = ((float)min(ty * tile + tile - 1, cs.py1) + 0.5f - cs.vi) - cs.vf;
@@ -426,12 +446,9 @@ __device__ inline uint32_t tile_mask(const CullShape& cs, int cull, uint32_t tx0
                          cs.pad_x;
         const float xl = (cs.b * yl - __builtin_sqrtf(fmaxf(0.f, cs.four_at - yl * yl * cs.det4))) * cs.inv2a -
                          cs.pad_x;
-        for (uint32_t lx = lx0; lx <= lx1; ++lx) {
-            const int tx = (int)(bx + lx);
-            const float X0 = ((float)max(tx * tile, cs.px0) + 0.5f - cs.ui) - cs.uf;
-            const float X1 = ((float)min(tx * tile + tile - 1, cs.px1) + 0.5f - cs.ui) - cs.uf;
-            if (X1 >= xl && X0 <= xr) mask |= 1u << (ly * (uint32_t)S + lx);
-        }
+#pragma unroll
+        for (uint32_t lx = 0; lx < 4u; ++lx)
+            if (((cols >> lx) & 1u) && X1[lx] >= xl && X0[lx] <= xr) mask |= 1u << (ly * (uint32_t)S + lx);
     }
     return mask;
 }
