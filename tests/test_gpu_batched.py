@@ -135,3 +135,18 @@ def test_batched_multi_pass_super_tile_sort_is_bit_identical(h4d):
     assert r1.last_pairs == r2.last_pairs
     for a, b in zip(h1.images, h2.images):
         assert torch.equal(a, b)
+
+
+@pytest.mark.skip(reason="was part of a GPU run that faulted (together with a since-removed view-local "
+                         "key mode); kept off the GPU until the two-pass single-view path is shown safe")
+def test_two_pass_super_tile_sort_single_view_is_tile_independent(h4d):
+    """One 2100x1600 view at 8-px tiles has 3300 super-tiles, more than one
+    11-bit radix pass holds, so its coarse entries take two passes (the first
+    dropping empty masks); at 16-px tiles the same view takes one.  Images do
+    not depend on the tile size, so both must agree bit for bit."""
+    print("[single view] two-pass super-tile sort", flush=True)
+    scene = sg.multiview_scene(n_total=20_000, width=2100, height=1600, seed=9)
+    views = [scene.views[4].with_time(0.35)]
+    _, _, _, h8 = _render(h4d, scene, views, False, tile=8, chunk=64, cap=1 << 24)
+    _, _, _, h16 = _render(h4d, scene, views, False, tile=16, chunk=64, cap=1 << 24)
+    assert torch.equal(h8.images[0], h16.images[0])
