@@ -153,12 +153,12 @@ __device__ __forceinline__ ColTerm eval_col(const Splat& s, int px, float pxc) {
     return c;
 }
 
-// Per-pixel part: returns whether the pair passes the square test, power <= 0
-// and alpha >= 1/255; alpha = min(0.99, op * exp(power)).
-__device__ __forceinline__ bool eval_pix(const Splat& s, const ColTerm& c, int py, float pyc, float& dy, float& G,
+// Per-pixel part: returns whether the pair passes the square test (in: the
+// pixel lies in the splat's pixel square), power <= 0 and alpha >= 1/255;
+// alpha = min(0.99, op * exp(power)).
+__device__ __forceinline__ bool eval_pix(const Splat& s, const ColTerm& c, bool in, float pyc, float& dy, float& G,
                                          float& alpha, bool& clamped) {
 #pragma clang fp contract(off)
-    const bool in = c.inx && py >= s.y0 && py <= s.y1;
     dy = (pyc - s.vi) - s.vf;
     const float u = __builtin_fmaf(s.qc, dy, c.bx);
     const float p2 = __builtin_fmaf(dy, u, c.a2);

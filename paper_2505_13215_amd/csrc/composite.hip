@@ -18,6 +18,7 @@
 // gradients are applied once per splat after the reduction.  Each wave stops
 // at its own last contributor.
 #include <hip/hip_ext.h>
+#include <type_traits>
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -25,9 +26,12 @@ namespace h4d {
 
 // LDS copy of one record (64 bytes, 16-byte aligned so that a lane reads it
 // with four 128-bit LDS loads): packed pixel square, centre split into integer
-// and fractional parts, scaled conic, opacity, colour.
+// and fractional parts, scaled conic, opacity, colour.  Bit 31 of ry (image
+// rows stay below 2^15) is set when the square holds every pixel row of the
+// tile: the blending loops then skip the per-pixel row test, and y0, y1 are
+// not read.
 struct __align__(16) LSplat {
-    uint32_t rx, ry;              // x0 | x1 << 16, y0 | y1 << 16
+    uint32_t rx, ry;              // x0 | x1 << 16, y0 | y1 << 16 (| rows-in flag << 31)
     float ui, uf, vi, vf;
     float qa, qb, qc, op;
     float cr, cg, cb;
@@ -35,15 +39,20 @@ struct __align__(16) LSplat {
     uint32_t pad[2];
 };
 static_assert(sizeof(LSplat) == 64, "LDS splat is 64 bytes");
+constexpr uint32_t kRowsIn = 0x80000000u;
 
-__device__ __forceinline__ void stage_splat(const Rec& r, uint32_t gid, LSplat& s) {
+// row0, row1: the tile's first and last pixel rows
+__device__ __forceinline__ void stage_splat(const Rec& r, uint32_t gid, int row0, int row1, LSplat& s) {
     s.gid = gid;
-    s.rx = r.d.x; s.ry = r.d.y;
+    s.rx = r.d.x;
+    const uint32_t y0 = r.d.y & 0xFFFFu, y1 = r.d.y >> 16;
+    s.ry = r.d.y | ((y0 <= (uint32_t)row0 && y1 >= (uint32_t)row1) ? kRowsIn : 0u);
     s.ui = r.c.y; s.uf = r.a.x; s.vi = r.c.z; s.vf = r.a.y;
     s.qa = r.a.z; s.qb = r.a.w; s.qc = r.b.x; s.op = r.b.y;
     s.cr = r.b.z; s.cg = r.b.w; s.cb = r.c.x;
 }
 
+// (y0, y1 as stored: only meaningful when the rows-in flag is clear)
 __device__ __forceinline__ Splat to_splat(const LSplat& l) {
     Splat s;
     s.x0 = (int)(l.rx & 0xFFFFu); s.x1 = (int)(l.rx >> 16); s.y0 = (int)(l.ry & 0xFFFFu); s.y1 = (int)(l.ry >> 16);
@@ -53,8 +62,34 @@ __device__ __forceinline__ Splat to_splat(const LSplat& l) {
     return s;
 }
 
-__device__ __forceinline__ bool in_square(const Splat& s, int px, int py) {
-    return px >= s.x0 && px <= s.x1 && py >= s.y0 && py <= s.y1;
+// Rows-in flags of the staged splats [g0, g0 + n), n <= 64, as a wave-uniform
+// bit mask (bit i: splat g0 + i).
+__device__ __forceinline__ unsigned long long rows_in_mask(const LSplat* sp, int g0, int n) {
+    const int lane = __lane_id();
+    return __ballot(lane < n && (sp[g0 + lane].ry & kRowsIn) != 0u);
+}
+
+// Calls step(j, tag) for j = 0 .. n-1 in order, tag = std::true_type where bit j
+// of rin is set, else std::false_type; stops early (returning true) when step
+// returns true.  Runs of equal flags go through their own loop, so that the
+// loop-carried pixel state stays in place across each run.
+template <class F>
+__device__ __forceinline__ bool walk_runs(unsigned long long rin, int n, F&& step) {
+    int j = 0;
+    while (j < n) {
+        for (; j < n && ((rin >> j) & 1ull); ++j)
+            if (step(j, std::true_type{})) return true;
+        for (; j < n && !((rin >> j) & 1ull); ++j)
+            if (step(j, std::false_type{})) return true;
+    }
+    return false;
+}
+
+// Square test of one pixel: its column (c.inx) and, unless the square holds
+// every row of the tile (ROWS_IN), its row.
+template <bool ROWS_IN>
+__device__ __forceinline__ bool square_test(const Splat& s, const ColTerm& c, int py) {
+    return ROWS_IN ? c.inx : (c.inx && py >= s.y0 && py <= s.y1);
 }
 
 // Lane layout: a 16 x 16 tile is one wave, every lane holding four pixels
@@ -142,12 +177,15 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
         const int cnt = (int)min((int64_t)CHUNK, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) {
             const uint32_t gid = ids[base + k];
-            stage_splat(recs[gid], gid, s_sp[k]);
+            stage_splat(recs[gid], gid, ty * B, ty * B + B - 1, s_sp[k]);
         }
         __syncthreads();
         if (!wave_done) {
             const uint32_t rel0 = (uint32_t)(base - start);
-            for (int j = 0; j < cnt; ++j) {
+            // one blending step of the lane's pixels with splat j; true once every
+            // pixel of the wave is finished
+            auto step = [&](int j, auto rows_tag) {
+                constexpr bool RI = decltype(rows_tag)::value;
                 const Splat s = to_splat(s_sp[j]);
                 const ColTerm c = eval_col(s, px, pxc);
                 bool all = true;
@@ -156,7 +194,8 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
                     float dy, G, alpha;
                     bool clamped;
                     const bool live = T[k] > 0.0f;
-                    const bool ok = eval_pix(s, c, py[k], pyc[k], dy, G, alpha, clamped) && live;
+                    const bool in = square_test<RI>(s, c, py[k]);
+                    const bool ok = eval_pix(s, c, in, pyc[k], dy, G, alpha, clamped) && live;
                     const float Tn = next_T(T[k], alpha);
                     const bool stop = ok && Tn < kMinT;
                     const bool bl = ok && !stop;
@@ -167,15 +206,19 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
                     T[k] = bl ? Tn : (stop ? -T[k] : T[k]);
                     last[k] = bl ? rel0 + (uint32_t)j + 1u : last[k];
                     if (STATS) {
-                        n_eval += (live && in_square(s, px, py[k])) ? 1u : 0u;
+                        n_eval += (live && in) ? 1u : 0u;
                         n_blend += bl ? 1u : 0u;
                     }
                     all = all && !(live && !stop);
                 }
-                if (__ballot(!all) == 0ull) {
-                    wave_done = true;
-                    break;
-                }
+                return __ballot(!all) == 0ull;
+            };
+            // splats whose square holds all of the tile's rows take the step
+            // without the row test
+            for (int g0 = 0; g0 < cnt && !wave_done; g0 += 64) {
+                const int gn = min(64, cnt - g0);
+                wave_done = walk_runs(rows_in_mask(s_sp, g0, gn), gn,
+                                      [&](int i, auto tag) { return step(g0 + i, tag); });
             }
         }
     }
@@ -337,13 +380,15 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         __syncthreads();  // the previous chunk's LDS is no longer read
         for (int k = threadIdx.x; k < cnt; k += NT) {
             const uint32_t gid = ids[base + k];
-            stage_splat(recs[gid], gid, s_sp[k]);
+            stage_splat(recs[gid], gid, ty * B, ty * B + B - 1, s_sp[k]);
         }
         __syncthreads();
         const uint32_t rel0 = (uint32_t)(base - start);
         // entries past this wave's last contributor need no work
         const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
-        for (int j = 0; j < jend; ++j) {
+        // the adjoint of one blending step with splat j
+        auto step = [&](int j, auto rows_tag) {
+            constexpr bool RI = decltype(rows_tag)::value;
             const Splat s = to_splat(s_sp[j]);
             const ColTerm c = eval_col(s, px, pxc);
             const float twoqadx = 2.0f * c.qadx, qbdx = c.bx, dx2 = c.dx * c.dx, twoqc = 2.0f * s.qc;
@@ -357,10 +402,11 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 float dy, Gk, alpha;
                 bool clamped;
                 const bool live = rel0 + (uint32_t)j < nc[k];
-                const bool pass = eval_pix(s, c, py[k], pyc[k], dy, Gk, alpha, clamped);
+                const bool in = square_test<RI>(s, c, py[k]);
+                const bool pass = eval_pix(s, c, in, pyc[k], dy, Gk, alpha, clamped);
                 const bool ok = pass && live;
                 if (STATS) {
-                    n_eval += (live && in_square(s, px, py[k])) ? 1u : 0u;
+                    n_eval += (live && in) ? 1u : 0u;
                     n_blend += ok ? 1u : 0u;
                 }
                 any = any || ok;
@@ -403,6 +449,15 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                     if (row == 0) atomicAdd(&g2c8[o], h2);
                 }
             }
+        };
+        // splats whose square holds all of the tile's rows take the step without
+        // the row test
+        for (int g0 = 0; g0 < jend; g0 += 64) {
+            const int gn = min(64, jend - g0);
+            walk_runs(rows_in_mask(s_sp, g0, gn), gn, [&](int i, auto tag) {
+                step(g0 + i, tag);
+                return false;
+            });
         }
     }
     if (STATS) {
