@@ -568,22 +568,21 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
     for (int k = 0; k < 48; ++k) gr.sh[k * n + i] = gsh[k];
 }
 
-// Two kernels so that the lighter 3D path is not compiled for the 4D path's
-// register footprint.
-__global__ void __launch_bounds__(128) k_preprocess_bwd4(G4Ptr g4, int N, const ViewParams* __restrict__ views,
-                                                         int n_views, const Rec* __restrict__ recs,
-                                                         const float* __restrict__ g2, G4Grad gr4) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= g4.n) return;
-    bwd_4d(g4, g, views, n_views, N, recs, g2, gr4);
-}
-
-__global__ void __launch_bounds__(128) k_preprocess_bwd3(G3Ptr g3, int n4, int N, const ViewParams* __restrict__ views,
-                                                         int n_views, const Rec* __restrict__ recs,
-                                                         const float* __restrict__ g2, G3Grad gr3) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g3.n) return;
-    bwd_3d(g3, i, n4 + i, views, n_views, N, recs, g2, gr3);
+// One launch for both sets: workgroups [0, nb4) take the 4D Gaussians (the
+// longer threads, started first), the rest the 3D ones.  Both paths hold one
+// wave per SIMD (FP64 state of 400+ registers), so sharing the launch costs no
+// occupancy and lets the two sets fill the machine together.
+__global__ void __launch_bounds__(128) k_preprocess_bwd(G3Ptr g3, G4Ptr g4, int nb4, const ViewParams* __restrict__ views,
+                                                        int n_views, const Rec* __restrict__ recs,
+                                                        const float* __restrict__ g2, G3Grad gr3, G4Grad gr4) {
+    const int N = g3.n + g4.n;
+    if ((int)blockIdx.x < nb4) {
+        const int g = blockIdx.x * blockDim.x + threadIdx.x;
+        if (g < g4.n) bwd_4d(g4, g, views, n_views, N, recs, g2, gr4);
+    } else {
+        const int i = (blockIdx.x - nb4) * blockDim.x + threadIdx.x;
+        if (i < g3.n) bwd_3d(g3, i, g4.n + i, views, n_views, N, recs, g2, gr3);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -654,9 +653,8 @@ void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* v
                            const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st) {
     const int N = g3.n + g4.n;
     if (N == 0) return;
-    if (g4.n > 0) k_preprocess_bwd4<<<ceil_div(g4.n, 128), 128, 0, st>>>(g4, N, views, n_views, recs, g2, gr4);
-    if (g3.n > 0)
-        k_preprocess_bwd3<<<ceil_div(g3.n, 128), 128, 0, st>>>(g3, g4.n, N, views, n_views, recs, g2, gr3);
+    const int nb4 = ceil_div(g4.n, 128), nb3 = ceil_div(g3.n, 128);
+    k_preprocess_bwd<<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4);
 }
 
 }  // namespace h4d
