@@ -1,6 +1,9 @@
 // Bias-corrected Adam over several float32 segments in one launch.
 // HBM-bound: 16 B read + 12 B written per scalar; float4 vectorised when a
-// segment is 16-byte aligned and a multiple of 4 long, scalar otherwise.
+// segment is 16-byte aligned and a multiple of 4 long, scalar otherwise.  The
+// vector path reads and writes with non-temporal hints: parameters and moments
+// are touched once per step, and streaming them past the caches leaves the
+// step's other working set (records, tile lists, sort buffers) cached.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -21,19 +24,26 @@ __global__ void __launch_bounds__(256) k_adam(AdamTable t) {
                      (s.n & 3) == 0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     if (vec) {
-        float4* P = reinterpret_cast<float4*>(s.p);
-        const float4* G = reinterpret_cast<const float4*>(s.g);
-        float4* M = reinterpret_cast<float4*>(s.m);
-        float4* Vv = reinterpret_cast<float4*>(s.v);
         const size_t n4 = (size_t)s.n / 4;
+        typedef float nf4 __attribute__((ext_vector_type(4)));
+        nf4* P4 = reinterpret_cast<nf4*>(s.p);
+        const nf4* G4 = reinterpret_cast<const nf4*>(s.g);
+        nf4* M4 = reinterpret_cast<nf4*>(s.m);
+        nf4* V4 = reinterpret_cast<nf4*>(s.v);
         for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-            float4 p = P[i], m = M[i], v = Vv[i];
-            const float4 g = G[i];
-            adam_one(p.x, g.x, m.x, v.x, s.lr, t);
-            adam_one(p.y, g.y, m.y, v.y, s.lr, t);
-            adam_one(p.z, g.z, m.z, v.z, s.lr, t);
-            adam_one(p.w, g.w, m.w, v.w, s.lr, t);
-            P[i] = p; M[i] = m; Vv[i] = v;
+            const nf4 pp = __builtin_nontemporal_load(&P4[i]), mm = __builtin_nontemporal_load(&M4[i]),
+                      vv = __builtin_nontemporal_load(&V4[i]);
+            const nf4 g = __builtin_nontemporal_load(&G4[i]);
+            float pa[4] = {pp.x, pp.y, pp.z, pp.w}, ma[4] = {mm.x, mm.y, mm.z, mm.w};
+            float va[4] = {vv.x, vv.y, vv.z, vv.w};
+            const float ga[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) adam_one(pa[q], ga[q], ma[q], va[q], s.lr, t);
+            const nf4 p = {pa[0], pa[1], pa[2], pa[3]}, m = {ma[0], ma[1], ma[2], ma[3]};
+            const nf4 v = {va[0], va[1], va[2], va[3]};
+            __builtin_nontemporal_store(p, &P4[i]);
+            __builtin_nontemporal_store(m, &M4[i]);
+            __builtin_nontemporal_store(v, &V4[i]);
         }
     } else {
         for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)s.n; i += stride) {

@@ -10,7 +10,7 @@
 // The backward recomputes transmittance front to back with the very same
 // blending test as the forward (eval_col / eval_pix, next_T).  The colour behind
 // a splat enters dL/dalpha only through its dot product with dL/dC, kept per
-// pixel as dot(dL/dC, C_out) minus a running dot(dL/dC, prefix).  Each lane sums
+// pixel as R = dot(dL/dC, C_out), less each blended splat's share in turn.  Each lane sums
 // its pixels in registers; the nine per-splat gradients are reduced across the
 // wave by reduce-scatter (lane-half and row swaps, then DPP row sums; skipped
 // when no lane blended the splat) and added to HBM with one global atomic per
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const int px = tx * B + (int)threadIdx.x % B;
     const float pxc = (float)px + 0.5f;
     int py[PPL];
-    float pyc[PPL], G0[PPL], G1[PPL], G2[PPL], D[PPL], P[PPL], T[PPL];
+    float pyc[PPL], G0[PPL], G1[PPL], G2[PPL], R[PPL], T[PPL];
     uint32_t nc[PPL];
     uint32_t lane_nc = 0;
 #pragma unroll
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         const int p = (int)threadIdx.x + k * NT;
         py[k] = ty * B + p / B;
         pyc[k] = (float)py[k] + 0.5f;
-        G0[k] = G1[k] = G2[k] = D[k] = 0.f;
+        G0[k] = G1[k] = G2[k] = R[k] = 0.f;
         nc[k] = 0u;
         if (px < V.W && py[k] < V.H) {
             const size_t q = (size_t)py[k] * V.W + px;
@@ -349,11 +349,10 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
             const float c0 = Cout[3 * (size_t)V.pix_base + q];
             const float c1 = Cout[3 * (size_t)V.pix_base + HW + q];
             const float c2 = Cout[3 * (size_t)V.pix_base + 2 * HW + q];
-            D[k] = G0[k] * c0 + G1[k] * c1 + G2[k] * c2;  // dot(dL/dC, C_out)
+            R[k] = G0[k] * c0 + G1[k] * c1 + G2[k] * c2;  // dot(dL/dC, C_out)
             nc[k] = ncontrib[(size_t)V.pix_base + q];
         }
         T[k] = 1.0f;
-        P[k] = 0.f;  // dot(dL/dC, colour blended so far)
         lane_nc = max(lane_nc, nc[k]);
     }
     if (threadIdx.x == 0) s_max = 0u;
@@ -413,11 +412,12 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 const float a = ok ? alpha : 0.0f;
                 const float w = a * T[k];
                 const float gc = G0[k] * s.cr + G1[k] * s.cg + G2[k] * s.cb;
-                P[k] = __builtin_fmaf(w, gc, P[k]);
+                R[k] = __builtin_fmaf(-w, gc, R[k]);  // less the colour blended so far
                 // dL/dalpha = T dot(dL/dC, c) - dot(dL/dC, colour behind) / (1 - alpha),
-                // colour behind = C_out - prefix (includes T_final * bg)
+                // colour behind = C_out - prefix, whose dot product R now holds
+                // (it includes T_final * bg)
                 const float ioma = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float da = __builtin_fmaf(T[k], gc, -((D[k] - P[k]) * ioma));
+                const float da = __builtin_fmaf(T[k], gc, -(R[k] * ioma));
                 e6 = __builtin_fmaf(G0[k], w, e6);
                 e7 = __builtin_fmaf(G1[k], w, e7);
                 e8 = __builtin_fmaf(G2[k], w, e8);
