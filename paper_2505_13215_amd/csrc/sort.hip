@@ -506,6 +506,58 @@ __global__ void __launch_bounds__(256) k_coarse_down(const uint32_t* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = partials[nparts];
 }
 
+// The capacity check and tile-list regions of a pass whose coarse entries
+// total C (one thread): see k_coarse_top.
+__device__ inline void coarse_finalize(unsigned long long C, uint64_t ccap, uint64_t cap, int S,
+                                       unsigned long long* pair_base, int v0, int v1, Status* status,
+                                       unsigned long long* eff_count) {
+    const unsigned long long base = pair_base[v0];
+    const unsigned long long R = C * (unsigned long long)(S * S);
+    status->pairs_needed += R;
+    if (C > ccap || base + R > cap) {
+        status->flags |= kFlagOverflow;
+        *eff_count = 0ull;
+        pair_base[v1] = base;
+    } else {
+        *eff_count = C;
+        pair_base[v1] = base + R;
+    }
+}
+
+// Few count workgroups (nparts <= kDirectParts): k_coarse_top and k_coarse_down
+// in one launch.  Each workgroup sums the partials of the workgroups before it
+// (workgroup 0 sums them all, finalizes the pass and writes offsets[n]), then
+// scans its own counts as k_coarse_down does.
+constexpr int kDirectParts = 2048;
+__global__ void __launch_bounds__(256) k_coarse_down_direct(const uint32_t* __restrict__ cnt, int n,
+                                                            const unsigned long long* __restrict__ partials,
+                                                            int nparts, uint64_t ccap, uint64_t cap, int S,
+                                                            unsigned long long* pair_base, int v0, int v1,
+                                                            Status* status, unsigned long long* eff_count,
+                                                            unsigned long long* __restrict__ offsets,
+                                                            uint32_t* __restrict__ run_start, uint64_t run_cap) {
+    __shared__ unsigned long long s_buf[256];
+    const int b = (int)blockIdx.x;
+    const int upto = b == 0 ? nparts : b;
+    unsigned long long acc = 0;
+    for (int i = (int)threadIdx.x; i < upto; i += 256) acc += partials[i];
+    unsigned long long sum;
+    block_exclusive_scan_256<unsigned long long>(acc, s_buf, sum);
+    const unsigned long long before = b == 0 ? 0ull : sum;
+    if (b == 0 && threadIdx.x == 0) {
+        coarse_finalize(sum, ccap, cap, S, pair_base, v0, v1, status, eff_count);
+        offsets[n] = sum;
+    }
+    const int j = b * 256 + (int)threadIdx.x;
+    const uint32_t c = j < n ? cnt[j] : 0u;
+    unsigned long long tot;
+    const unsigned long long run = block_exclusive_scan_256<unsigned long long>((unsigned long long)c, s_buf, tot) + before;
+    if (j < n) {
+        offsets[j] = run;
+        for (uint64_t r = (run + 255) / 256; r * 256 < run + c && r < run_cap; ++r) run_start[r] = (uint32_t)j;
+    }
+}
+
 // Exclusive scan of the count workgroups' sums (partials[nparts] = total C),
 // then the coarse capacity check and the tile-list regions of the pass: the
 // S^2 tiles of a super-tile get regions as long as the super-tile's list, so
@@ -530,18 +582,7 @@ __global__ void __launch_bounds__(256) k_coarse_top(unsigned long long* __restri
     }
     if (threadIdx.x != 0) return;
     partials[nparts] = carry;
-    const unsigned long long C = carry;
-    const unsigned long long base = pair_base[v0];
-    const unsigned long long R = C * (unsigned long long)(S * S);
-    status->pairs_needed += R;
-    if (C > ccap || base + R > cap) {
-        status->flags |= kFlagOverflow;
-        *eff_count = 0ull;
-        pair_base[v1] = base;
-    } else {
-        *eff_count = C;
-        pair_base[v1] = base + R;
-    }
+    coarse_finalize(carry, ccap, cap, S, pair_base, v0, v1, status, eff_count);
 }
 
 // Coarse entries (super-tile id relative to the range's first view, depth
@@ -788,6 +829,11 @@ void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* parti
                            unsigned long long* eff_count, unsigned long long* offsets, uint32_t* run_start,
                            uint64_t run_cap, hipStream_t st) {
     const int nb = coarse_count_blocks(n);
+    if (n > 0 && nb <= kDirectParts) {
+        k_coarse_down_direct<<<nb, 256, 0, st>>>(cnt, n, partials, nb, ccap, cap, S, pair_base, v0, v1, status,
+                                                 eff_count, offsets, run_start, run_cap);
+        return;
+    }
     k_coarse_top<<<1, 256, 0, st>>>(partials, nb, ccap, cap, S, pair_base, v0, v1, status, eff_count);
     if (n > 0) k_coarse_down<<<nb, 256, 0, st>>>(cnt, n, partials, nb, offsets, run_start, run_cap);
 }
