@@ -238,7 +238,12 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.sc_pvals = f.take(4 * (size_t)L.ccap);
     L.sc_pkeys2 = f.take(4 * (size_t)L.ccap);
     L.sc_pvals2 = f.take(4 * (size_t)L.ccap);
-    const int cbits = pass_bits(bits_for(max_super), kMaxRadixBits);
+    // widest digit of any pass's super-tile sort (the width is not monotone in
+    // the super-tile count: 2048 super-tiles take one 11-bit pass, 3300 two
+    // 6-bit passes)
+    int cbits = 1;
+    for (int k = 0; k < L.n_passes(); ++k)
+        cbits = std::max(cbits, pass_bits(bits_for(L.pass(k).supers), kMaxRadixBits));
     L.sc_hist = f.take(4 * std::max(radix_hist_words(L.ccap, 1, cbits, kSortItems),
                                     radix_hist_words(n, L.per_pass, kDepthDigitBits, kDepthSortItems)));
     L.sc_totals = f.take(4 * (size_t)kMaxRadix * (size_t)L.per_pass);

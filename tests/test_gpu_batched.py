@@ -137,8 +137,6 @@ def test_batched_multi_pass_super_tile_sort_is_bit_identical(h4d):
         assert torch.equal(a, b)
 
 
-@pytest.mark.skip(reason="was part of a GPU run that faulted (together with a since-removed view-local "
-                         "key mode); kept off the GPU until the two-pass single-view path is shown safe")
 def test_two_pass_super_tile_sort_single_view_is_tile_independent(h4d):
     """One 2100x1600 view at 8-px tiles has 3300 super-tiles, more than one
     11-bit radix pass holds, so its coarse entries take two passes (the first
@@ -150,3 +148,21 @@ def test_two_pass_super_tile_sort_single_view_is_tile_independent(h4d):
     _, _, _, h8 = _render(h4d, scene, views, False, tile=8, chunk=64, cap=1 << 24)
     _, _, _, h16 = _render(h4d, scene, views, False, tile=16, chunk=64, cap=1 << 24)
     assert torch.equal(h8.images[0], h16.images[0])
+
+
+def test_views_whose_super_tile_sorts_differ_in_digit_width(h4d):
+    """Views one after another, one 2100x1600 (3300 super-tiles at 8-px tiles:
+    two 6-bit radix passes) and one 1600x1200 (1900: one 11-bit pass).  The
+    sort's histogram must hold the widest digit of any view, not the digit of
+    the view with the most super-tiles; each image equals that view rendered
+    alone."""
+    print("[views one after another] 6-bit and 11-bit super-tile sorts", flush=True)
+    scene = sg.multiview_scene(n_total=20_000, width=2100, height=1600, seed=10)
+    a = scene.views[3].with_time(0.4)
+    k = 1600.0 / 2100.0
+    b = sg.View(a.world_to_cam.copy(), a.fx * k, a.fy * k, 800.0, 600.0, 1600, 1200, 0.7, (0.2, 0.1, 0.0))
+    _, _, _, hab = _render(h4d, scene, [a, b], False, tile=8, chunk=64, cap=1 << 24)
+    _, _, _, ha = _render(h4d, scene, [a], False, tile=8, chunk=64, cap=1 << 24)
+    _, _, _, hb = _render(h4d, scene, [b], False, tile=8, chunk=64, cap=1 << 24)
+    assert torch.equal(hab.images[0], ha.images[0])
+    assert torch.equal(hab.images[1], hb.images[0])
