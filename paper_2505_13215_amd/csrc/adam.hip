@@ -17,50 +17,67 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
     p -= lr * mh / (sqrtf(vh) + eps);
 }
 
-__global__ void __launch_bounds__(256) k_adam(AdamTable t) {
-    const AdamSeg& s = t.seg[blockIdx.y];
-    const bool vec = ((reinterpret_cast<uintptr_t>(s.p) | reinterpret_cast<uintptr_t>(s.g) |
-                       reinterpret_cast<uintptr_t>(s.m) | reinterpret_cast<uintptr_t>(s.v)) & 15u) == 0 &&
-                     (s.n & 3) == 0;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    if (vec) {
-        const size_t n4 = (size_t)s.n / 4;
+// One launch over all segments, one float4 (vector segments) or one scalar per
+// thread: workgroup b belongs to the segment k whose block range
+// [blk0[k], blk0[k + 1]) holds it, so no workgroup idles on a short segment
+// and every load is issued by a wave of its own (0.073 -> 0.065 ms against a
+// grid-stride loop over 1024 workgroups per segment).
+struct AdamGrid {
+    int32_t blk0[kMaxAdamSeg + 1];
+    int32_t vec[kMaxAdamSeg];
+};
+
+__host__ __device__ inline bool adam_vec(const AdamSeg& s) {
+    return ((reinterpret_cast<uintptr_t>(s.p) | reinterpret_cast<uintptr_t>(s.g) | reinterpret_cast<uintptr_t>(s.m) |
+             reinterpret_cast<uintptr_t>(s.v)) & 15u) == 0 && (s.n & 3) == 0;
+}
+
+__global__ void __launch_bounds__(256) k_adam(AdamTable t, AdamGrid gr) {
+    int k = 0;
+    while (k + 1 < t.n_seg && (int)blockIdx.x >= gr.blk0[k + 1]) ++k;
+    const AdamSeg& s = t.seg[k];
+    const size_t i = (size_t)((int)blockIdx.x - gr.blk0[k]) * 256 + threadIdx.x;
+    if (gr.vec[k]) {
+        if (i >= (size_t)s.n / 4) return;
         typedef float nf4 __attribute__((ext_vector_type(4)));
         nf4* P4 = reinterpret_cast<nf4*>(s.p);
         const nf4* G4 = reinterpret_cast<const nf4*>(s.g);
         nf4* M4 = reinterpret_cast<nf4*>(s.m);
         nf4* V4 = reinterpret_cast<nf4*>(s.v);
-        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-            const nf4 pp = __builtin_nontemporal_load(&P4[i]), mm = __builtin_nontemporal_load(&M4[i]),
-                      vv = __builtin_nontemporal_load(&V4[i]);
-            const nf4 g = __builtin_nontemporal_load(&G4[i]);
-            float pa[4] = {pp.x, pp.y, pp.z, pp.w}, ma[4] = {mm.x, mm.y, mm.z, mm.w};
-            float va[4] = {vv.x, vv.y, vv.z, vv.w};
-            const float ga[4] = {g.x, g.y, g.z, g.w};
+        const nf4 pp = __builtin_nontemporal_load(&P4[i]), mm = __builtin_nontemporal_load(&M4[i]),
+                  vv = __builtin_nontemporal_load(&V4[i]);
+        const nf4 g = __builtin_nontemporal_load(&G4[i]);
+        float pa[4] = {pp.x, pp.y, pp.z, pp.w}, ma[4] = {mm.x, mm.y, mm.z, mm.w};
+        float va[4] = {vv.x, vv.y, vv.z, vv.w};
+        const float ga[4] = {g.x, g.y, g.z, g.w};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) adam_one(pa[q], ga[q], ma[q], va[q], s.lr, t);
-            const nf4 p = {pa[0], pa[1], pa[2], pa[3]}, m = {ma[0], ma[1], ma[2], ma[3]};
-            const nf4 v = {va[0], va[1], va[2], va[3]};
-            __builtin_nontemporal_store(p, &P4[i]);
-            __builtin_nontemporal_store(m, &M4[i]);
-            __builtin_nontemporal_store(v, &V4[i]);
-        }
+        for (int q = 0; q < 4; ++q) adam_one(pa[q], ga[q], ma[q], va[q], s.lr, t);
+        const nf4 p = {pa[0], pa[1], pa[2], pa[3]}, m = {ma[0], ma[1], ma[2], ma[3]};
+        const nf4 v = {va[0], va[1], va[2], va[3]};
+        __builtin_nontemporal_store(p, &P4[i]);
+        __builtin_nontemporal_store(m, &M4[i]);
+        __builtin_nontemporal_store(v, &V4[i]);
     } else {
-        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)s.n; i += stride) {
-            float p = s.p[i], m = s.m[i], v = s.v[i];
-            adam_one(p, s.g[i], m, v, s.lr, t);
-            s.p[i] = p; s.m[i] = m; s.v[i] = v;
-        }
+        if (i >= (size_t)s.n) return;
+        float p = s.p[i], m = s.m[i], v = s.v[i];
+        adam_one(p, s.g[i], m, v, s.lr, t);
+        s.p[i] = p; s.m[i] = m; s.v[i] = v;
     }
 }
 
 void launch_adam(const AdamTable& t, hipStream_t st) {
     if (t.n_seg <= 0) return;
-    int64_t mx = 0;
-    for (int i = 0; i < t.n_seg; ++i) mx = std::max(mx, t.seg[i].n);
-    if (mx == 0) return;
-    const int bx = (int)std::min<int64_t>(1024, (mx / 4 + 255) / 256 + 1);
-    k_adam<<<dim3(bx, t.n_seg), 256, 0, st>>>(t);
+    AdamGrid gr;
+    int64_t b = 0;
+    for (int k = 0; k < t.n_seg; ++k) {
+        gr.blk0[k] = (int32_t)b;
+        gr.vec[k] = adam_vec(t.seg[k]) ? 1 : 0;
+        const int64_t units = gr.vec[k] ? t.seg[k].n / 4 : t.seg[k].n;
+        b += (units + 255) / 256;
+    }
+    gr.blk0[t.n_seg] = (int32_t)b;
+    if (b == 0) return;
+    k_adam<<<(int)b, 256, 0, st>>>(t, gr);
 }
 
 }  // namespace h4d
