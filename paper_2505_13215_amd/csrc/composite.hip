@@ -172,13 +172,18 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_fwd(
     // wave-uniform: the splat loop runs for the whole wave (finished pixels are
     // masked), so that its per-pixel flags stay lane masks
     bool wave_done = __ballot(!lane_done) == 0ull;
+    const int tid = (int)threadIdx.x;
+    // this thread's first list slot of the next chunk, loaded a chunk ahead so
+    // that staging waits for the record gather only
+    uint32_t nid = (tid < CHUNK && start + tid < end) ? ids[start + tid] : 0u;
     for (int64_t base = start; base < end; base += CHUNK) {
         if (__syncthreads_count(wave_done) == NT) break;
         const int cnt = (int)min((int64_t)CHUNK, end - base);
-        for (int k = threadIdx.x; k < cnt; k += NT) {
-            const uint32_t gid = ids[base + k];
+        for (int k = tid; k < cnt; k += NT) {
+            const uint32_t gid = k == tid ? nid : ids[base + k];
             stage_splat(recs[gid], gid, ty * B, ty * B + B - 1, s_sp[k]);
         }
+        nid = (tid < CHUNK && base + CHUNK + tid < end) ? ids[base + CHUNK + tid] : 0u;
         __syncthreads();
         if (!wave_done) {
             const uint32_t rel0 = (uint32_t)(base - start);
@@ -374,13 +379,18 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     float* const g2c0 = g2 + comp0;
     float* const g2c1 = g2 + 4 + comp0;
     float* const g2c8 = g2 + 8;
+    const int tid = (int)threadIdx.x;
+    // this thread's first list slot of the next chunk, loaded a chunk ahead so
+    // that staging waits for the record gather only
+    uint32_t nid = (tid < CHUNK && start + tid < end) ? ids[start + tid] : 0u;
     for (int64_t base = start; base < end; base += CHUNK) {
         const int cnt = (int)min((int64_t)CHUNK, end - base);
         __syncthreads();  // the previous chunk's LDS is no longer read
-        for (int k = threadIdx.x; k < cnt; k += NT) {
-            const uint32_t gid = ids[base + k];
+        for (int k = tid; k < cnt; k += NT) {
+            const uint32_t gid = k == tid ? nid : ids[base + k];
             stage_splat(recs[gid], gid, ty * B, ty * B + B - 1, s_sp[k]);
         }
+        nid = (tid < CHUNK && base + CHUNK + tid < end) ? ids[base + CHUNK + tid] : 0u;
         __syncthreads();
         const uint32_t rel0 = (uint32_t)(base - start);
         // entries past this wave's last contributor need no work

@@ -702,10 +702,10 @@ __global__ void __launch_bounds__(1024) k_tile_write(const uint32_t* __restrict_
     const uint64_t out = (uint64_t)*base_ptr + (uint64_t)(S * S) * (uint64_t)cs + (uint64_t)w * (uint64_t)(ce - cs);
     const unsigned long long lt = lanemask_lt();
     const int round = blockDim.x;
-    uint64_t run = 0;
-    for (int64_t k0 = cs; k0 < ce; k0 += round) {
-        const int64_t k = k0 + tid;
-        uint32_t m = 0u, g = 0u;
+    // entry k's tile mask within this super-tile and splat id (zeros past ce)
+    auto fetch = [&](int64_t k, uint32_t& m, uint32_t& g) {
+        m = 0u;
+        g = 0u;
         if (k < ce) {
             const uint32_t key = ckeys[k];
             if (mkey) {
@@ -720,9 +720,16 @@ __global__ void __launch_bounds__(1024) k_tile_write(const uint32_t* __restrict_
             }
             g = cgid[k];
         }
+    };
+    uint64_t run = 0;
+    uint32_t m, g;
+    fetch(cs + tid, m, g);
+    for (int64_t k0 = cs; k0 < ce; k0 += round) {
         s_mask[tid] = m;
         s_gid[tid] = g;
         __syncthreads();
+        // the next round's entries are loaded while this round is compacted
+        fetch(k0 + round + tid, m, g);
         if (exists) {
             const int cnt = (int)min((int64_t)round, ce - k0);
             for (int c0 = 0; c0 < cnt; c0 += 64) {
