@@ -1,10 +1,13 @@
 """Build of the gfx950 HIP library ``libh4dgs.so`` (in-tree, next to this file)."""
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
+import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -15,7 +18,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-munsafe-fp-atomics",  # hardware float atomics (global_atomic_add_f32) instead of CAS loops
     # no wave-level rewriting of atomics with uniform addresses (the blending
     # adjoint issues them from single lanes after its own reduction)
@@ -25,23 +27,49 @@ HIPCC_FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
+# Per-source additions.  The blending kernels are VALU-bound loops whose
+# transcendental and LDS latencies the instruction-level-parallelism scheduler
+# hides better (forward 0.137 -> 0.129 ms, backward 0.224 -> 0.219 ms); the
+# FP64 per-Gaussian kernels run slower with it, so it stays per file.
+SOURCE_FLAGS = {
+    "composite.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
 
 def sources() -> list:
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into one shared library (always recompiles)."""
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *sources(), "-o", tmp]
+def _run(cmd: list, verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed to build libh4dgs.so")
-    os.replace(tmp, LIB)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link them into one shared library (always
+    recompiles)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    inc = ["-I", os.path.join(ROOT, "include")]
+    objdir = tempfile.mkdtemp(prefix="h4dgs_build_")
+    try:
+        objs, cmds = [], []
+        for src in sources():
+            obj = os.path.join(objdir, os.path.basename(src) + ".o")
+            extra = SOURCE_FLAGS.get(os.path.basename(src), [])
+            cmds.append([hipcc, *HIPCC_FLAGS, *extra, *inc, "-c", src, "-o", obj])
+            objs.append(obj)
+        workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = LIB + ".tmp"
+        _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(objdir, ignore_errors=True)
     return LIB
 
 
