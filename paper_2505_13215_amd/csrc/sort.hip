@@ -816,7 +816,13 @@ __global__ void __launch_bounds__(1024) k_bwd_prologue(float* __restrict__ g2, s
         return;
     }
     const size_t nb = (size_t)(gridDim.x - passes.n);
-    for (size_t i = (size_t)(k - passes.n) * blockDim.x + threadIdx.x; i < n_g2; i += nb * blockDim.x) g2[i] = 0.0f;
+    const size_t i0 = (size_t)(k - passes.n) * blockDim.x + threadIdx.x, step = nb * blockDim.x;
+    if ((reinterpret_cast<uintptr_t>(g2) & 15u) == 0 && (n_g2 & 3) == 0) {  // 16-byte stores
+        float4* g4 = reinterpret_cast<float4*>(g2);
+        for (size_t i = i0; i < n_g2 / 4; i += step) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        for (size_t i = i0; i < n_g2; i += step) g2[i] = 0.0f;
+    }
 }
 
 __global__ void k_fill_f32(float* p, size_t n, float val) {
