@@ -1,7 +1,8 @@
 // Front-to-back blending on gfx950 (Eq. 3; Alg. 1 BlendInOrder) and its adjoint.
 //
-// One workgroup per B x B tile (B = 8 and 16: one wave64; 32: four waves), one or
-// four pixels per lane, all of a lane's pixels in one column.  The tile's
+// One workgroup per B x B tile (B = 8: one wave64; 16: one wave in the adjoint,
+// two in the forward; 32: four waves), one to four pixels per lane, all of a
+// lane's pixels in one column.  The tile's
 // depth-ordered list is walked in chunks: each chunk of records is gathered
 // once from HBM into LDS and broadcast to every lane.  A pixel's contributors
 // are exactly the splats whose pixel square contains it, so the image does not
@@ -92,15 +93,26 @@ __device__ __forceinline__ bool square_test(const Splat& s, const ColTerm& c, in
     return ROWS_IN ? c.inx : (c.inx && py >= s.y0 && py <= s.y1);
 }
 
-// Lane layout: a 16 x 16 tile is one wave, every lane holding four pixels
-// (rows r, r + 4, r + 8, r + 12 of its column); 8 x 8 is one wave with one pixel
-// per lane; 32 x 32 is four waves with four pixels per lane.  The per-splat LDS
-// reads, loop control and (backward) cross-lane reductions are shared by all of
-// a lane's pixels.
+// Lane layout (adjoint): a 16 x 16 tile is one wave, every lane holding four
+// pixels (rows r, r + 4, r + 8, r + 12 of its column); 8 x 8 is one wave with one
+// pixel per lane; 32 x 32 is four waves with four pixels per lane.  The per-splat
+// LDS reads, loop control and cross-lane reductions are shared by all of a
+// lane's pixels.
 template <int B>
 struct Shape {
     static constexpr int NT = (B == 32) ? 256 : 64;  // threads per tile
     static constexpr int PPL = B * B / NT;           // pixels per lane
+};
+// The forward splits a 16 x 16 tile over two waves (two pixels per lane, rows
+// r and r + 8 of a column): every tile's work starts at once, so the launch
+// ends with its longest tile, and halving the longest unit of work outweighs
+// sharing the column terms over two pixels instead of four (0.128 -> 0.122 ms;
+// one pixel per lane: 0.155 ms).  The adjoint keeps one wave per tile: its
+// tiles are dispatched longest first, and two waves would double its atomics.
+template <int B>
+struct ShapeF {
+    static constexpr int NT = (B == 32) ? 256 : (B == 16 ? 128 : 64);
+    static constexpr int PPL = B * B / NT;
 };
 
 // Sum over the wave (measurement counters only).
@@ -133,12 +145,12 @@ __device__ __forceinline__ int dispatch_tile(const uint32_t* __restrict__ order)
 // (at most 64 registers: 8 waves per SIMD, about 1 % faster than the 7 the
 // compiler would otherwise settle for)
 template <int B, int CHUNK, bool STATS>
-__global__ void __launch_bounds__(Shape<B>::NT, 8) k_composite_fwd(
+__global__ void __launch_bounds__(ShapeF<B>::NT, 8) k_composite_fwd(
     const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
     const ViewParams* __restrict__ views, int v0, int v1, const uint32_t* __restrict__ order, PtrTable images,
     float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib, float* __restrict__ Cout,
     uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist, unsigned long long* counters) {
-    constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
+    constexpr int NT = ShapeF<B>::NT, PPL = ShapeF<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
     __shared__ uint32_t s_cost;
     const int gt = views[v0].tile_base + dispatch_tile(order);
@@ -507,7 +519,7 @@ static void fwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ra
                   int v1, int n_tiles, const uint32_t* order, const PtrTable& images, float* Tfin,
                   uint32_t* ncontrib, float* Cout, uint32_t* tcost, uint32_t* thist, unsigned long long* counters,
                   hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    constexpr int NT = Shape<B>::NT;
+    constexpr int NT = ShapeF<B>::NT;
     launch_timed(counters ? k_composite_fwd<B, C, true> : k_composite_fwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
                  N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout, tcost, thist, counters);
 }
