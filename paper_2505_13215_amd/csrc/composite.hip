@@ -103,17 +103,23 @@ struct Shape {
     static constexpr int NT = (B == 32) ? 256 : 64;  // threads per tile
     static constexpr int PPL = B * B / NT;           // pixels per lane
 };
-// The forward splits a 16 x 16 tile over two waves (two pixels per lane, rows
-// r and r + 8 of a column): every tile's work starts at once, so the launch
-// ends with its longest tile, and halving the longest unit of work outweighs
-// sharing the column terms over two pixels instead of four (0.128 -> 0.122 ms;
-// one pixel per lane: 0.155 ms).  The adjoint keeps one wave per tile: its
-// tiles are dispatched longest first, and two waves would double its atomics.
-template <int B>
+// SPLIT: the forward spreads a 16 x 16 tile over two waves (two pixels per
+// lane, rows r and r + 8 of a column).  When all of a launch's tiles are
+// resident at once, the launch ends with its longest tile, and halving the
+// longest unit of work outweighs sharing the column terms over two pixels
+// instead of four (one view: 0.128 -> 0.122 ms; one pixel per lane: 0.155 ms).
+// Launches of many more tiles than wave slots balance themselves and only pay
+// the extra instructions (32 views: 5.0 -> 5.8 ms), so they keep one wave per
+// tile.  The adjoint keeps one wave per tile: its tiles are dispatched longest
+// first, and two waves would double its atomics.
+template <int B, bool SPLIT>
 struct ShapeF {
-    static constexpr int NT = (B == 32) ? 256 : (B == 16 ? 128 : 64);
+    static constexpr int NT = (B == 16 && SPLIT) ? 128 : Shape<B>::NT;
     static constexpr int PPL = B * B / NT;
 };
+// at most this many tiles in a launch take the split forward (about one wave
+// slot per tile at the forward's 8 waves per SIMD)
+constexpr int kSplitTiles = 8192;
 
 // Sum over the wave (measurement counters only).
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -144,13 +150,13 @@ __device__ __forceinline__ int dispatch_tile(const uint32_t* __restrict__ order)
 // counts the launch's tiles per bucket.
 // (at most 64 registers: 8 waves per SIMD, about 1 % faster than the 7 the
 // compiler would otherwise settle for)
-template <int B, int CHUNK, bool STATS>
-__global__ void __launch_bounds__(ShapeF<B>::NT, 8) k_composite_fwd(
+template <int B, int CHUNK, bool STATS, bool SPLIT>
+__global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
     const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
     const ViewParams* __restrict__ views, int v0, int v1, const uint32_t* __restrict__ order, PtrTable images,
     float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib, float* __restrict__ Cout,
     uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist, unsigned long long* counters) {
-    constexpr int NT = ShapeF<B>::NT, PPL = ShapeF<B>::PPL;
+    constexpr int NT = ShapeF<B, SPLIT>::NT, PPL = ShapeF<B, SPLIT>::PPL;
     __shared__ LSplat s_sp[CHUNK];
     __shared__ uint32_t s_cost;
     const int gt = views[v0].tile_base + dispatch_tile(order);
@@ -519,9 +525,19 @@ static void fwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ra
                   int v1, int n_tiles, const uint32_t* order, const PtrTable& images, float* Tfin,
                   uint32_t* ncontrib, float* Cout, uint32_t* tcost, uint32_t* thist, unsigned long long* counters,
                   hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    constexpr int NT = ShapeF<B>::NT;
-    launch_timed(counters ? k_composite_fwd<B, C, true> : k_composite_fwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
-                 N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout, tcost, thist, counters);
+    if constexpr (B == 16) {
+        if (n_tiles <= kSplitTiles) {
+            constexpr int NT = ShapeF<B, true>::NT;
+            launch_timed(counters ? k_composite_fwd<B, C, true, true> : k_composite_fwd<B, C, false, true>, n_tiles,
+                         NT, st, e0, e1, recs, N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout,
+                         tcost, thist, counters);
+            return;
+        }
+    }
+    constexpr int NT = ShapeF<B, false>::NT;
+    launch_timed(counters ? k_composite_fwd<B, C, true, false> : k_composite_fwd<B, C, false, false>, n_tiles, NT, st,
+                 e0, e1, recs, N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout, tcost, thist,
+                 counters);
 }
 template <int B, int C>
 static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,

@@ -563,24 +563,57 @@ __global__ void __launch_bounds__(256) k_coarse_down_direct(const uint32_t* __re
 // S^2 tiles of a super-tile get regions as long as the super-tile's list, so
 // the pass needs S^2 C list slots from pair_base[v0]; their end goes to
 // pair_base[v1].
-__global__ void __launch_bounds__(256) k_coarse_top(unsigned long long* __restrict__ partials, int nparts,
-                                                    uint64_t ccap, uint64_t cap, int S,
-                                                    unsigned long long* pair_base, int v0, int v1, Status* status,
-                                                    unsigned long long* eff_count) {
-    __shared__ unsigned long long s_buf[256];
+// (1024 threads, each scanning a contiguous chunk of the partials four loads
+// at a time: with many count workgroups, e.g. 32 views of 1M Gaussians, this
+// single workgroup's walk over the partials is the launch)
+__global__ void __launch_bounds__(1024) k_coarse_top(unsigned long long* __restrict__ partials, int nparts,
+                                                     uint64_t ccap, uint64_t cap, int S,
+                                                     unsigned long long* pair_base, int v0, int v1, Status* status,
+                                                     unsigned long long* eff_count) {
+    __shared__ unsigned long long s_w[16];
+    const int tid = (int)threadIdx.x, lane = tid & 63, w = tid >> 6;
     // thread t scans the contiguous chunk [t q, (t + 1) q) of the partials
-    const int q = (nparts + 255) / 256;
-    const int i0 = min(nparts, (int)threadIdx.x * q), i1 = min(nparts, i0 + q);
-    unsigned long long sum = 0;
-    for (int i = i0; i < i1; ++i) sum += partials[i];
-    unsigned long long carry;
-    unsigned long long run = block_exclusive_scan_256<unsigned long long>(sum, s_buf, carry);
-    for (int i = i0; i < i1; ++i) {
+    const int q = (nparts + 1023) / 1024;
+    const int i0 = min(nparts, tid * q), i1 = min(nparts, i0 + q);
+    unsigned long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int i = i0;
+    for (; i + 3 < i1; i += 4) {
+        a0 += partials[i];
+        a1 += partials[i + 1];
+        a2 += partials[i + 2];
+        a3 += partials[i + 3];
+    }
+    for (; i < i1; ++i) a0 += partials[i];
+    const unsigned long long sum = (a0 + a1) + (a2 + a3);
+    // exclusive scan of the chunk sums over the workgroup (wave scans, then the
+    // 16 wave totals)
+    unsigned long long incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    unsigned long long run = incl - sum, carry = 0;
+    for (int k = 0; k < 16; ++k) {
+        const unsigned long long t = s_w[k];
+        if (k < w) run += t;
+        carry += t;
+    }
+    for (i = i0; i + 3 < i1; i += 4) {
+        const unsigned long long v0_ = partials[i], v1_ = partials[i + 1], v2_ = partials[i + 2], v3_ = partials[i + 3];
+        partials[i] = run;
+        partials[i + 1] = run + v0_;
+        partials[i + 2] = run + v0_ + v1_;
+        partials[i + 3] = run + v0_ + v1_ + v2_;
+        run += v0_ + v1_ + v2_ + v3_;
+    }
+    for (; i < i1; ++i) {
         const unsigned long long v = partials[i];
         partials[i] = run;
         run += v;
     }
-    if (threadIdx.x != 0) return;
+    if (tid != 0) return;
     partials[nparts] = carry;
     coarse_finalize(carry, ccap, cap, S, pair_base, v0, v1, status, eff_count);
 }
@@ -847,7 +880,7 @@ void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* parti
                                                  eff_count, offsets, run_start, run_cap);
         return;
     }
-    k_coarse_top<<<1, 256, 0, st>>>(partials, nb, ccap, cap, S, pair_base, v0, v1, status, eff_count);
+    k_coarse_top<<<1, 1024, 0, st>>>(partials, nb, ccap, cap, S, pair_base, v0, v1, status, eff_count);
     if (n > 0) k_coarse_down<<<nb, 256, 0, st>>>(cnt, n, partials, nb, offsets, run_start, run_cap);
 }
 void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, int N,
@@ -877,7 +910,8 @@ void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long 
 }
 void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const uint32_t* thist,
                          const PassTiles& passes, uint32_t* order, hipStream_t st) {
-    const int fill = (int)std::max<size_t>(1, std::min<size_t>(1024, (n_g2 + 4095) / 4096));
+    // one 16-byte store per thread (no grid-stride loop)
+    const int fill = (int)std::max<size_t>(1, std::min<size_t>(1u << 20, (n_g2 + 4095) / 4096));
     k_bwd_prologue<<<passes.n + fill, 1024, 0, st>>>(g2, n_g2, tcost, thist, passes, order);
 }
 

@@ -166,3 +166,18 @@ def test_views_whose_super_tile_sorts_differ_in_digit_width(h4d):
     _, _, _, hb = _render(h4d, scene, [b], False, tile=8, chunk=64, cap=1 << 24)
     assert torch.equal(hab.images[0], ha.images[0])
     assert torch.equal(hab.images[1], hb.images[0])
+
+
+def test_batched_pass_with_many_count_workgroups(h4d):
+    """Two views of 300k Gaussians in one batched pass: 600k depth-ordered
+    Gaussians, more than 2048 count workgroups, so the coarse offsets take the
+    separate top-level scan; each image equals that view rendered alone (whose
+    300k Gaussians take the in-kernel scan)."""
+    print("[batched forward] many count workgroups", flush=True)
+    scene = sg.multiview_scene(n_total=300_000, width=320, height=240, seed=11)
+    views = [scene.views[1].with_time(0.3), scene.views[12].with_time(0.6)]
+    r1, _, _, h1 = _render(h4d, scene, views, False, tile=16, chunk=64, cap=1 << 24)
+    r2, _, _, h2 = _render(h4d, scene, views, True, tile=16, chunk=64, cap=1 << 24)
+    assert r1.last_pairs == r2.last_pairs
+    for a, b in zip(h1.images, h2.images):
+        assert torch.equal(a, b)
