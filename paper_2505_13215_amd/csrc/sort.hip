@@ -888,7 +888,8 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
                         int S, int mkey, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys,
                         uint32_t* vals, hipStream_t st) {
     if (n == 0 || capacity == 0) return;
-    const int nb = (int)std::min<uint64_t>(8192, (capacity + 255) / 256);
+    // (32 views of 1M Gaussians in one pass: about 25 runs of 256 entries per workgroup)
+    const int nb = (int)std::min<uint64_t>(65536, (capacity + 255) / 256);
     k_coarse_emit<<<nb, 256, 0, st>>>(offsets, run_start, n, N, rect_sorted, shapes, views, v0, tile, S, mkey,
                                       eff_count, keys, vals);
 }
