@@ -5,7 +5,9 @@ in (default tile and chunk), through the C ABI.
 Three independent checks per view: the whole image against the oracle's tile
 pipeline, sampled pixels (corners, the ragged last tile row and column, random
 ones) against the oracle's per-pixel brute force over all Gaussians, and the
-full backward to every raw parameter.
+full backward to every raw parameter.  At the 2M-Gaussian training workload
+(4 views at 2704x2028): sampled pixels against the brute force, and the
+4-view adjoint against the sum of one-view adjoints.
 """
 import numpy as np
 import pytest
@@ -107,3 +109,63 @@ def test_full_size_repeated_steps_are_stable(h4d, big, gpu_params):
         img = rast.forward(g3, g4, [v]).images[0]
         rast.verify()
         assert torch.equal(img, r)
+
+
+# -- the 2M-Gaussian training workload ---------------------------------------
+
+@pytest.fixture(scope="module")
+def train2m(h4d):
+    """2M Gaussians (85 % static 3D), 2704x2028 images, a batch of 4 views."""
+    scene = sg.training_scene()
+    views = sg.view_schedule(scene, 1, 4, seed=3)[0]
+    return scene, views, h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+
+
+def test_training_workload_sampled_pixels(h4d, train2m):
+    """The 4-view call at the training workload's size: sampled pixels of every
+    view (corners, the ragged last tile row and column, random ones) against
+    the oracle's per-pixel brute force over all 2M Gaussians."""
+    scene, views, g3, g4 = train2m
+    print("[2M training workload] forward, 4 views at 2704x2028", flush=True)
+    rast = h4d.Rasterizer()
+    h = rast.forward(g3, g4, views)
+    torch.cuda.synchronize()
+    assert rast.last_pairs > 0
+    for k, v in enumerate(views):
+        img = h.images[k].cpu().numpy()
+        xs, ys = _sample_pixels(v.width, v.height, 200, seed=10 + k)
+        rgb, T, amb = oracle.pixels(scene, v, xs, ys)
+        ok = ~amb
+        assert ok.mean() > 0.9
+        got = img[:, ys, xs].T
+        assert np.abs(got - rgb)[ok].max() <= IMG_TOL, k
+
+
+def test_training_workload_gradients_are_view_sums(h4d, train2m):
+    """The 4-view backward equals the sum of the four one-view backwards (the
+    adjoint is linear in dL/dC and the views share no state), compared
+    normwise per parameter array since the float32 atomic sums run in another
+    order."""
+    scene, views, g3, g4 = train2m
+    print("[2M training workload] backward, 4 views vs one at a time", flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    dls = [torch.randn((3, v.height, v.width), generator=gen, device="cuda") * 1e-4 for v in views]
+    rast = h4d.Rasterizer()
+    h = rast.forward(g3, g4, views)
+    a3, a4 = rast.backward(h, g3, g4, dls)
+    s3 = {k: torch.zeros_like(x) for k, x in a3.items()}
+    s4 = {k: torch.zeros_like(x) for k, x in a4.items()}
+    for v, d in zip(views, dls):
+        h1 = rast.forward(g3, g4, [v])
+        b3, b4 = rast.backward(h1, g3, g4, [d])
+        for k in s3:
+            s3[k] += b3[k]
+        for k in s4:
+            s4[k] += b4[k]
+    torch.cuda.synchronize()
+    assert float(a3["opacity"].norm()) > 0 and float(a4["opacity"].norm()) > 0
+    for k in a3:
+        assert float((a3[k] - s3[k]).norm()) <= 1e-5 * float(a3[k].norm()) + 1e-30, k
+    for k in a4:
+        assert float((a4[k] - s4[k]).norm()) <= 1e-5 * float(a4[k].norm()) + 1e-30, k
