@@ -217,3 +217,38 @@ def test_batched_full_size_matches_single_view(h4d):
         assert float((a3[k] - b3[k]).norm()) <= 1e-5 * float(a3[k].norm()) + 1e-30, k
     for k in a4:
         assert float((a4[k] - b4[k]).norm()) <= 1e-5 * float(a4[k].norm()) + 1e-30, k
+
+
+def test_batched_pass_beyond_masked_key_range(h4d):
+    """Five 4096x4096 views at 8-pixel tiles: 16384 super-tiles each, 81920 in
+    the batched pass, more than the 65536 whose ids leave the key's upper half
+    to the tile mask.  That pass keys the coarse entries by super-tile id alone
+    (no tile mask, no culling, splat ids gathered after the sort); its images
+    must equal the views rendered one after another (16384 super-tiles each,
+    masked keys) bit for bit, its gradients normwise up to the order of the
+    atomic sums."""
+    print("[batched unmasked keys] 5 views 4096x4096, tile 8", flush=True)
+    scene = sg.tiny_scene(seed=31)
+    views = [sg.look_at((0.3 * k - 0.6, 0.1 * k, -3.0), (0.0, 0.0, 0.0), 4096, 4096, t=0.15 + 0.17 * k)
+             for k in range(5)]
+    g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
+    dls = [torch.randn((3, v.height, v.width), generator=gen, device="cuda") * 1e-6 for v in views]
+    out = []
+    for batched in (False, True):
+        rast = h4d.Rasterizer(tile=8, chunk=64, batched=batched)
+        h = rast.forward(g3, g4, views)
+        gr3, gr4 = rast.backward(h, g3, g4, dls)
+        torch.cuda.synchronize()
+        out.append(([im.clone() for im in h.images], gr3, gr4))
+        del h, rast
+        torch.cuda.empty_cache()
+    (im1, a3, a4), (im2, b3, b4) = out
+    for v, (a, b) in enumerate(zip(im1, im2)):
+        assert torch.equal(a, b), v
+    assert float(a3["opacity"].norm()) > 0 and float(a4["opacity"].norm()) > 0
+    for k in a3:
+        assert float((a3[k] - b3[k]).norm()) <= 1e-5 * float(a3[k].norm()) + 1e-30, k
+    for k in a4:
+        assert float((a4[k] - b4[k]).norm()) <= 1e-5 * float(a4[k].norm()) + 1e-30, k
