@@ -134,6 +134,17 @@ h4d_status h4dgs_render_fwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, 
                             int32_t n_views, const h4d_config *cfg, float *const *images, void *state,
                             size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
 
+/* Inference render: the forward of render_fwd (same arguments, same images,
+ * bit for bit) without the state only the backward reads (per-pixel final
+ * transmittance, last contributor and output colour; per-tile adjoint cost),
+ * for rendering without training.  `state` still holds the records, lists
+ * and status (h4dgs_check applies as after render_fwd).  render_bwd must not
+ * follow it: the adjoint would read the state of an earlier render_fwd, or
+ * none. */
+h4d_status h4dgs_render_infer(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
+                              int32_t n_views, const h4d_config *cfg, float *const *images, void *state,
+                              size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
+
 /* Backward: the exact adjoint of render_fwd.  dl_dimages: host array of
  * n_views device pointers to float[3][H][W] (dL/dC, loss weighting included).
  * The gradients of every raw parameter are OVERWRITTEN with

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "CAPACITY", 3: "HIP", 4: "NONFINIT
 
 EXPORTS = (
     "h4dgs_create", "h4dgs_destroy", "h4dgs_last_error", "h4dgs_version", "h4dgs_workspace_size",
-    "h4dgs_render_fwd", "h4dgs_render_bwd", "h4dgs_check", "h4dgs_rasterize_splats",
+    "h4dgs_render_fwd", "h4dgs_render_infer", "h4dgs_render_bwd", "h4dgs_check", "h4dgs_rasterize_splats",
     "h4dgs_convert_scratch_bytes", "h4dgs_convert_static", "h4dgs_adam", "h4dgs_l1_loss_grad",
     "h4dgs_profile", "h4dgs_profile_read", "h4dgs_stats", "h4dgs_stats_read",
 )
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
     L.h4dgs_version.restype = C.c_char_p
     L.h4dgs_workspace_size.argtypes = [vp, i32, i32, vp, i32, vp, P(sz), P(sz)]
     L.h4dgs_render_fwd.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp, sz, vp]
+    L.h4dgs_render_infer.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp, sz, vp]
     L.h4dgs_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp, sz, vp, vp, vp]
     L.h4dgs_check.argtypes = [vp, vp, sz, P(i64), vp]
     L.h4dgs_rasterize_splats.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp,

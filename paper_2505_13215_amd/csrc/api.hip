@@ -349,8 +349,10 @@ unsigned long long* stat_counters(h4d_ctx* c, void* state, const Layout& L) {
     return c->stats ? reinterpret_cast<unsigned long long*>(&at<Status>(state, L.st_status)->pad[0]) : nullptr;
 }
 
+// keep: write the adjoint's per-pixel and per-tile state (false for an
+// inference render)
 void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chunk, int cull, void* state,
-                   void* scratch, const PtrTable& images, hipStream_t st) {
+                   void* scratch, const PtrTable& images, hipStream_t st, bool keep = true) {
     const int N = L.N;
     const int nv = P.v1 - P.v0;
     const int n = nv * N;  // depth-ordered Gaussians of the pass, view-major
@@ -448,10 +450,11 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
     KernelMark km(c, H4D_STAGE_BLEND_FWD, P.tiles > 0);
     launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles,
-                         nullptr, images, at<float>(state, L.st_T), at<uint32_t>(state, L.st_nc),
-                         at<float>(state, L.st_C), at<uint32_t>(state, L.st_tcost),
-                         at<uint32_t>(state, L.st_thist) + (size_t)kCostBuckets * (P.v0 / L.per_pass),
-                         stat_counters(c, state, L), st, km.a, km.b);
+                         nullptr, images, keep ? at<float>(state, L.st_T) : nullptr,
+                         keep ? at<uint32_t>(state, L.st_nc) : nullptr, keep ? at<float>(state, L.st_C) : nullptr,
+                         keep ? at<uint32_t>(state, L.st_tcost) : nullptr,
+                         keep ? at<uint32_t>(state, L.st_thist) + (size_t)kCostBuckets * (P.v0 / L.per_pass) : nullptr,
+                         keep ? stat_counters(c, state, L) : nullptr, st, km.a, km.b);
 }
 
 }  // namespace
@@ -491,9 +494,9 @@ h4d_status h4dgs_workspace_size(h4d_ctx* ctx, int32_t n3, int32_t n4, const h4d_
     return H4D_OK;
 }
 
-h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
-                            int32_t n_views, const h4d_config* cfg, float* const* images, void* state,
-                            size_t state_bytes, void* scratch, size_t scratch_bytes, void* stream) {
+static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
+                                 int32_t n_views, const h4d_config* cfg, float* const* images, void* state,
+                                 size_t state_bytes, void* scratch, size_t scratch_bytes, void* stream, bool keep) {
     if (!ctx) return H4D_ERR_INVALID_ARG;
     h4d_status s;
     if ((s = check_sets(ctx, g3, g4)) != H4D_OK) return s;
@@ -526,9 +529,23 @@ h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
             launch_preprocess(p3, p4, vp, P.v0, P.v1 - P.v0, at<Rec>(state, L.st_recs),
                               at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
         }
-        bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st);
+        bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st, keep);
     }
-    return hip_check(ctx, "render_fwd");
+    return hip_check(ctx, keep ? "render_fwd" : "render_infer");
+}
+
+h4d_status h4dgs_render_fwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
+                            int32_t n_views, const h4d_config* cfg, float* const* images, void* state,
+                            size_t state_bytes, void* scratch, size_t scratch_bytes, void* stream) {
+    return render_forward(ctx, g3, g4, views, n_views, cfg, images, state, state_bytes, scratch, scratch_bytes,
+                          stream, true);
+}
+
+h4d_status h4dgs_render_infer(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
+                              int32_t n_views, const h4d_config* cfg, float* const* images, void* state,
+                              size_t state_bytes, void* scratch, size_t scratch_bytes, void* stream) {
+    return render_forward(ctx, g3, g4, views, n_views, cfg, images, state, state_bytes, scratch, scratch_bytes,
+                          stream, false);
 }
 
 h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,

@@ -258,15 +258,19 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
             image[p] = o0;
             image[HW + p] = o1;
             image[2 * HW + p] = o2;
-            const size_t q = (size_t)V.pix_base + p;
-            Tfin[q] = Tk;
-            ncontrib[q] = last[k];
-            Cout[3 * (size_t)V.pix_base + p] = o0;
-            Cout[3 * (size_t)V.pix_base + HW + p] = o1;
-            Cout[3 * (size_t)V.pix_base + 2 * HW + p] = o2;
+            if (Tfin) {  // the adjoint's per-pixel state (not kept by an inference render)
+                const size_t q = (size_t)V.pix_base + p;
+                Tfin[q] = Tk;
+                ncontrib[q] = last[k];
+                Cout[3 * (size_t)V.pix_base + p] = o0;
+                Cout[3 * (size_t)V.pix_base + HW + p] = o1;
+                Cout[3 * (size_t)V.pix_base + 2 * HW + p] = o2;
+            }
         }
     }
     // the tile's cost for the adjoint: its last contributor over all pixels
+    // (tcost is the same for the whole launch, so the barriers below stay uniform)
+    if (tcost) {
     uint32_t lane_last = 0u;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) lane_last = max(lane_last, last[k]);
@@ -285,6 +289,7 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
             tcost[gt] = s_cost;
             atomicAdd(&thist[cost_bucket(s_cost)], 1u);
         }
+    }
     }
     if (STATS) {
         const unsigned long long e = wave_sum_u64(n_eval), b = wave_sum_u64(n_blend);

@@ -58,6 +58,7 @@ class FwdHandle:
     n4: int
     state: torch.Tensor
     images: list
+    differentiable: bool = True  # False after an inference render
 
 
 # Launch configuration of the training step (tile edge in pixels, splats staged
@@ -111,7 +112,12 @@ class Rasterizer:
             self._scratch = torch.empty(max(sc, 256), dtype=torch.uint8, device="cuda")
 
     # -- forward / backward -----------------------------------------------------
-    def forward(self, g3: dict, g4: dict, views) -> FwdHandle:
+    def infer(self, g3: dict, g4: dict, views) -> FwdHandle:
+        """Inference render: the same images as ``forward`` without the state
+        the adjoint reads (its handle cannot be passed to ``backward``)."""
+        return self.forward(g3, g4, views, _keep=False)
+
+    def forward(self, g3: dict, g4: dict, views, _keep: bool = True) -> FwdHandle:
         if self._pending is not None and self.check_mode == "eager":
             self._pending = None
         s3, s4 = g3_struct(g3), g4_struct(g4)
@@ -122,11 +128,12 @@ class Rasterizer:
             self._ensure(s3.n, s4.n, va, n_views)
             cfg = self.config()
             imgs = L.ptr_array([im.data_ptr() for im in images])
-            self.ctx.check(self.ctx.L.h4dgs_render_fwd(
+            entry = self.ctx.L.h4dgs_render_fwd if _keep else self.ctx.L.h4dgs_render_infer
+            self.ctx.check(entry(
                 self.ctx.h, C.byref(s3), C.byref(s4), va, n_views, C.byref(cfg), imgs, _ptr(self._state),
                 self._state.numel(), _ptr(self._scratch), self._scratch.numel(), _stream()))
             self._gen += 1
-            h = FwdHandle(self._gen, va, n_views, cfg, s3.n, s4.n, self._state, images)
+            h = FwdHandle(self._gen, va, n_views, cfg, s3.n, s4.n, self._state, images, bool(_keep))
             if self.check_mode != "eager":
                 self._pending = h
                 return h
@@ -156,6 +163,8 @@ class Rasterizer:
         """Gradients of every raw parameter; ``out`` = (gr3, gr4) dicts to fill in place."""
         if h.generation != self._gen:
             raise RuntimeError("backward must follow its own forward (the workspace was reused)")
+        if not h.differentiable:
+            raise RuntimeError("an inference render keeps no state for the backward")
         s3, s4 = g3_struct(g3), g4_struct(g4)
         if out is None:
             gr3 = {k: torch.empty_like(g3[k]) for k in G3_KEYS}
