@@ -413,6 +413,18 @@ def main():
                "mpix_s": round(args.steps * W * H / dt_fb / 1e6, 2)}
     log(f"without the optimiser: {fwd_bwd}")
 
+    # inference render (no adjoint state) over the same views, beside
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        rast.infer(g3, g4, [sched[i][0]])
+    torch.cuda.synchronize()
+    dt_inf = time.perf_counter() - t0
+    rast.verify()
+    inference = {"render": "render_infer, one view per frame", "ms_per_frame": round(dt_inf * 1e3 / args.steps, 4),
+                 "frames_per_s": round(args.steps / dt_inf, 1)}
+    log(f"inference: {inference}")
+
     # evaluation counts of the blending kernels (counting instantiation, outside the timed region)
     log(f"counting blend evaluations on {args.stats_views} views")
     rast.stats(True)
@@ -494,6 +506,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fwd_bwd_only": fwd_bwd,
+        "inference": inference,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "blend_evals_per_view": {k: int(v) for k, v in cnt.items()},
         "pairs_per_view_max": peak_pairs,
