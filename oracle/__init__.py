@@ -78,6 +78,13 @@ def lib():
         L.orc_convert_static.argtypes = [vp, f32, vp, vp, vp, vp]
         L.orc_adam.argtypes = [C.c_int64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i32, vp, vp, vp]
         L.orc_num_threads.restype = i32
+        L.orc_local_new.argtypes = [vp, i32, vp, i32, i32, vp]
+        L.orc_local_new.restype = vp
+        L.orc_local_free.argtypes = [vp]
+        L.orc_local_amb.argtypes = [vp, i32, vp]
+        L.orc_local_grad.argtypes = [vp, vp, vp]
+        L.orc_local_fd.argtypes = [vp, vp, i32, vp, dbl, vp, vp]
+        L.orc_blended_at.argtypes = [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -317,3 +324,90 @@ def adam(p, g, m, v, lr, b1, b2, eps, step):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def blended_at(scene, view, px, py, cap: int = 512, tile: int = 16):
+    """The Gaussians blended at the given pixels, front to back: a list per
+    pixel of (merged id, blend weight alpha T) pairs."""
+    L = lib()
+    sr = _SceneRef(scene.g3, scene.g4)
+    V = _view(view)
+    px, py = _c(px, np.int32), _c(py, np.int32)
+    n = px.shape[0]
+    ids = np.zeros((n, cap), np.int32)
+    w = np.zeros((n, cap), np.float64)
+    cnt = np.zeros(n, np.int32)
+    assert L.orc_blended_at(sr.ref, C.byref(V), tile, n, _p(px), _p(py), cap, _p(ids), _p(w), _p(cnt)) == 0
+    assert cnt.max(initial=0) <= cap, "raise cap"
+    return [list(zip(ids[k, :cnt[k]].tolist(), w[k, :cnt[k]].tolist())) for k in range(n)]
+
+
+# Parameter order of one Gaussian's row in Local.grad / Local.fd (the ABI field order).
+ROW4 = [("mean", c) for c in range(3)] + [("mean_t", None)] + [("log_scale", c) for c in range(4)] + \
+    [("quat_l", c) for c in range(4)] + [("quat_r", c) for c in range(4)] + [("opacity", None)] + \
+    [("sh", c) for c in range(48)]
+ROW3 = [("mean", c) for c in range(3)] + [("log_scale", c) for c in range(3)] + [("quat", c) for c in range(4)] + \
+    [("opacity", None)] + [("sh", c) for c in range(48)]
+
+
+class Local:
+    """Oracle evaluation restricted to the pixel squares of a few selected
+    Gaussians (merged ids: 4D rows first, then 3D rows) in the given views, for
+    scenes too large to composite whole.  The candidate lists are those of the
+    whole-view path for the tiles the squares touch.
+
+    amb(v): uint8 [H, W], bit 0 = inside a selected square, bit 1 = guard-band
+    flag (the same flags ``render`` sets there).
+    grad(dls): float64 [n_sel, 65], the selected Gaussians' gradients of
+    sum_v <dls[v], C_v> with dls zeroed at flagged pixels (rows in ROW4 / ROW3
+    order; a 3D row fills its first 59 entries).
+    fd(dls, entries, hrel): central differences of the same loss for
+    (selection index, row index) entries, float64, and an ok flag (False where a
+    move changes a discrete decision)."""
+
+    def __init__(self, scene, views, sel, tile: int = 16):
+        L = lib()
+        self._sr = _SceneRef(scene.g3, scene.g4)
+        self._views = (_OView * len(views))(*[_view(v) for v in views])
+        self.views = list(views)
+        self.sel = _c(sel, np.int32)
+        self.n4 = scene.n4
+        self.h = L.orc_local_new(self._sr.ref, len(views), self._views, tile, int(self.sel.size), _p(self.sel))
+        if not self.h:
+            raise ValueError("orc_local_new rejected its arguments")
+
+    def _dls(self, dls):
+        keep = [_c(d, np.float32) for d in dls]
+        arr = (C.c_void_p * len(keep))(*[a.ctypes.data for a in keep])
+        return keep, arr
+
+    def amb(self, v: int) -> np.ndarray:
+        view = self.views[v]
+        out = np.zeros((view.height, view.width), np.uint8)
+        assert lib().orc_local_amb(self.h, v, _p(out)) == 0
+        return out
+
+    def grad(self, dls) -> np.ndarray:
+        keep, arr = self._dls(dls)
+        rows = np.zeros((self.sel.size, 65), np.float64)
+        assert lib().orc_local_grad(self.h, arr, _p(rows)) == 0
+        return rows
+
+    def fd(self, dls, entries, hrel: float = 1e-6):
+        keep, arr = self._dls(dls)
+        ent = _c(entries, np.int32).reshape(-1, 2)
+        fd = np.zeros(ent.shape[0], np.float64)
+        ok = np.zeros(ent.shape[0], np.int32)
+        assert lib().orc_local_fd(self.h, arr, ent.shape[0], _p(ent), float(hrel), _p(fd), _p(ok)) == 0
+        return fd, ok.astype(bool)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().orc_local_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -307,6 +307,7 @@ template <class S> struct Rec {
     int r = 0;              // integer screen radius
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;  // pixel square, inclusive
     float key = 0.f;        // FP32 depth key used for ordering (reading: kernel precision)
+    int kinks = 0;          // which clamps are active: bit c = colour channel c at 0, bit 3/4 = x/y Jacobian
     double margin = 1.0;    // min relative margin of this Gaussian's FP64 discrete decisions
     bool key_shaky = false; // depth lies within kGlobalTol of a float32 rounding boundary
 };
@@ -341,6 +342,7 @@ template <class S> void project(const OView& V, const Param<S>& P, const Geo<S>&
     const double limx = kClampFov * (0.5 * V.W / V.fx), limy = kClampFov * (0.5 * V.H / V.fy);
     const S xt = val(x) > limx ? S(limx) : (val(x) < -limx ? S(-limx) : x);
     const S yt = val(y) > limy ? S(limy) : (val(y) < -limy ? S(-limy) : y);
+    const int jkinks = (std::fabs(val(x)) > limx ? 8 : 0) | (std::fabs(val(y)) > limy ? 16 : 0);
     // EWA: J = d(pixel)/d(camera point) with the clamped ratios
     S J[2][3] = {{S(V.fx) / z, S(0.0), -S(V.fx) * xt / z}, {S(0.0), S(V.fy) / z, -S(V.fy) * yt / z}};
     S M[2][3];
@@ -394,7 +396,9 @@ template <class S> void project(const OView& V, const Param<S>& P, const Geo<S>&
         S acc = S(kShOffset);
         for (int k = 0; k < 16; ++k) acc += P.sh[k * 3 + ch] * Y[k];
         r.rgb[ch] = val(acc) > 0.0 ? acc : S(0.0);
+        if (!(val(acc) > 0.0)) r.kinks |= 1 << ch;
     }
+    r.kinks |= jkinks;
     r.margin = margin;
     r.culled = cull;
     r.visible = !cull && (r.x0 <= r.x1) && (r.y0 <= r.y1);
@@ -460,8 +464,8 @@ struct Blended {  // one blended entry, kept for the adjoint
 
 constexpr double kEps32 = 5.9604644775390625e-08;  // 2^-24
 
-template <class S>
-void blend_pixel(int i, int j, const int32_t* list, int64_t len, const std::vector<Rec<S>>& recs, const OView& V,
+template <class S, class Recs = std::vector<Rec<S>>>
+void blend_pixel(int i, int j, const int32_t* list, int64_t len, const Recs& recs, const OView& V,
                  S C[3], S& Tout, int& nblend, bool& amb, std::vector<Blended>* keep) {
     const double x = i + 0.5, y = j + 0.5;
     S T = S(1.0);
@@ -838,30 +842,35 @@ void gaussian_bwd(const OScene& sc, int g, const OView& V, const G2& gs, double*
 }
 
 // Composite adjoint of one pixel (upstream gbar = dL/dC, 3 channels).
-inline void blend_pixel_bwd(const std::vector<Blended>& bl, const std::vector<Rec<double>>& recs, const double Tfin,
-                            const double bg[3], const double gbar[3], std::vector<G2>& acc) {
+// acc(g) returns the accumulator of Gaussian g, or null to drop its terms.
+template <class Recs, class Acc>
+inline void blend_pixel_bwd(const std::vector<Blended>& bl, const Recs& recs, const double Tfin,
+                            const double bg[3], const double gbar[3], Acc&& acc) {
     const size_t n = bl.size();
     // S_k = sum_{j>k} rgb_j alpha_j T_j + T_final * bg, built back to front
     double Ssuf[3] = {Tfin * bg[0], Tfin * bg[1], Tfin * bg[2]};
     for (size_t kk = n; kk-- > 0;) {
         const Blended& e = bl[kk];
         const Rec<double>& r = recs[e.g];
-        G2& a = acc[e.g];
+        G2* ap = acc(e.g);
         const double w = e.alpha * e.T;
-        double galpha = 0;
-        for (int c = 0; c < 3; ++c) {
-            a.rgb[c] += gbar[c] * w;
-            galpha += gbar[c] * (r.rgb[c] * e.T - Ssuf[c] / (1.0 - e.alpha));
-        }
-        if (!e.clamped) {
-            a.op += galpha * e.G;
-            const double gpow = galpha * e.alpha;
-            // power = -1/2 (Qa dx^2 + 2 Qb dx dy + Qc dy^2), dx = x - u, dy = y - v
-            a.u += gpow * (r.Q[0] * e.dx + r.Q[1] * e.dy);
-            a.v += gpow * (r.Q[1] * e.dx + r.Q[2] * e.dy);
-            a.Q[0] += gpow * (-0.5 * e.dx * e.dx);
-            a.Q[1] += gpow * (-e.dx * e.dy);
-            a.Q[2] += gpow * (-0.5 * e.dy * e.dy);
+        if (ap) {
+            G2& a = *ap;
+            double galpha = 0;
+            for (int c = 0; c < 3; ++c) {
+                a.rgb[c] += gbar[c] * w;
+                galpha += gbar[c] * (r.rgb[c] * e.T - Ssuf[c] / (1.0 - e.alpha));
+            }
+            if (!e.clamped) {
+                a.op += galpha * e.G;
+                const double gpow = galpha * e.alpha;
+                // power = -1/2 (Qa dx^2 + 2 Qb dx dy + Qc dy^2), dx = x - u, dy = y - v
+                a.u += gpow * (r.Q[0] * e.dx + r.Q[1] * e.dy);
+                a.v += gpow * (r.Q[1] * e.dx + r.Q[2] * e.dy);
+                a.Q[0] += gpow * (-0.5 * e.dx * e.dx);
+                a.Q[1] += gpow * (-e.dx * e.dy);
+                a.Q[2] += gpow * (-0.5 * e.dy * e.dy);
+            }
         }
         for (int c = 0; c < 3; ++c) Ssuf[c] += r.rgb[c] * w;
     }
@@ -904,7 +913,7 @@ void render_view_bwd(const OScene& sc, const OView& V, int B, const float* dimg,
                     blend_pixel<double>(i, j, list, len, recs, V, C, Tp, nb, a, &bl);
                     const size_t p = (size_t)j * V.W + i;
                     const double gb[3] = {dimg[p], dimg[(size_t)HW + p], dimg[2 * (size_t)HW + p]};
-                    blend_pixel_bwd(bl, recs, Tp, V.bg, gb, my);
+                    blend_pixel_bwd(bl, recs, Tp, V.bg, gb, [&](int g) { return &my[g]; });
                 }
         }
     }
@@ -950,6 +959,178 @@ void render_view_bwd(const OScene& sc, const OView& V, int B, const float* dimg,
             for (int k = 0; k < 48; ++k) grad.sh3[k * n + i] += gsh[k];
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Local evaluation around a few selected Gaussians of a large scene.
+// A Gaussian's parameters change the image only inside its pixel square, so
+// its gradient, and central differences of a loss that is linear in the image,
+// need only the pixels of that square.  They are composited from the same
+// depth-ordered candidate lists as the whole-view path, built here for the
+// tiles the selected squares touch only, from every Gaussian's record.
+// ---------------------------------------------------------------------------
+constexpr int kRow = 65;  // one Gaussian's raw parameters in ABI field order (a 3D row uses the first 59)
+
+// Parameter k of a Gaussian's row: 4D mean(3) mean_t log_scale(4) quat_l(4)
+// quat_r(4) opacity sh(48); 3D mean(3) log_scale(3) quat(4) opacity sh(48).
+inline double* param_slot(Param<double>& P, int k) {
+    if (P.is4d) {
+        if (k < 3) return &P.mu[k];
+        if (k == 3) return &P.mt;
+        if (k < 8) return &P.ls[k - 4];
+        if (k < 12) return &P.q[k - 8];
+        if (k < 16) return &P.q2[k - 12];
+        if (k == 16) return &P.op;
+        if (k < 65) return &P.sh[k - 17];
+    } else {
+        if (k < 3) return &P.mu[k];
+        if (k < 6) return &P.ls[k - 3];
+        if (k < 10) return &P.q[k - 6];
+        if (k == 10) return &P.op;
+        if (k < 59) return &P.sh[k - 11];
+    }
+    return nullptr;
+}
+
+// Record of Gaussian g in view V with parameter k moved by delta (k < 0: none).
+inline Rec<double> record_of(const OScene& sc, const OView& V, int g, int k, double delta, double* theta = nullptr) {
+    Param<double> P;
+    load_param<double>(sc, nullptr, g, P);
+    if (k >= 0) {
+        double* x = param_slot(P, k);
+        *x += delta;
+        if (theta) *theta = *x;
+    }
+    Geo<double> G;
+    world(P, V.time, G);
+    Rec<double> r;
+    project(V, P, G, r);
+    return r;
+}
+
+// Records with one Gaussian's record replaced.
+struct Overlay {
+    const std::vector<Rec<double>>* base;
+    int g;
+    const Rec<double>* alt;
+    const Rec<double>& operator[](size_t i) const { return (int)i == g ? *alt : (*base)[i]; }
+};
+
+inline bool has_square(const Rec<double>& r) { return r.r > 0 && r.x0 <= r.x1 && r.y0 <= r.y1; }
+
+struct LocalView {
+    OView V;
+    int B = 16, tx = 0, ty = 0;
+    std::vector<Rec<double>> recs;
+    std::vector<int32_t> slot;                // tile -> index into lists, -1 when untouched
+    std::vector<std::vector<int32_t>> lists;  // candidate lists of the touched tiles, (key, id) order
+    std::vector<int32_t> region;              // pixels inside a selected square
+    std::vector<uint8_t> amb;                 // per pixel of the view: guard-band flag (region pixels only)
+    const int32_t* list_of(int i, int j, int64_t& len) const {
+        const std::vector<int32_t>& l = lists[slot[(j / B) * tx + i / B]];
+        len = (int64_t)l.size();
+        return l.data();
+    }
+};
+
+struct Local {
+    OScene sc;
+    std::vector<int32_t> sel;
+    std::vector<int32_t> selidx;  // merged id -> selection index, -1 otherwise
+    std::vector<LocalView> views;
+};
+
+// Records of every Gaussian, candidate lists of the tiles holding a pixel of
+// `in_region` (one byte per pixel), and the guard-band flags of those pixels.
+void local_build(const OScene& sc, const OView& V, int B, const std::vector<uint8_t>& in_region, LocalView& lv) {
+    lv.V = V;
+    lv.B = B;
+    lv.tx = (V.W + B - 1) / B;
+    lv.ty = (V.H + B - 1) / B;
+    if (lv.recs.empty()) preprocess_all<double>(sc, nullptr, V, lv.recs);
+    const int N = (int)lv.recs.size();
+    const int T = lv.tx * lv.ty;
+    lv.slot.assign(T, -1);
+    int nl = 0;
+    lv.region.clear();
+    for (size_t p = 0; p < in_region.size(); ++p)
+        if (in_region[p]) {
+            lv.region.push_back((int32_t)p);
+            const int t = (int)((p / V.W) / B) * lv.tx + (int)((p % V.W) / B);
+            if (lv.slot[t] < 0) lv.slot[t] = nl++;
+        }
+    lv.lists.assign(nl, {});
+    // per tile row, prefix counts of touched tiles: a Gaussian whose tile range
+    // touches none is skipped without visiting its tiles
+    std::vector<int32_t> pre((size_t)lv.ty * (lv.tx + 1), 0);
+    for (int t2 = 0; t2 < lv.ty; ++t2)
+        for (int t1 = 0; t1 < lv.tx; ++t1)
+            pre[(size_t)t2 * (lv.tx + 1) + t1 + 1] = pre[(size_t)t2 * (lv.tx + 1) + t1] + (lv.slot[t2 * lv.tx + t1] >= 0);
+    // the same candidates as the whole-view path: every Gaussian that is not
+    // culled, over its square widened by one pixel, taken in (depth key, id)
+    // order so that every list comes out sorted
+    std::vector<int32_t> order;
+    order.reserve((size_t)N);
+    for (int g = 0; g < N; ++g)
+        if (!lv.recs[g].culled) order.push_back(g);
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        if (lv.recs[a].key != lv.recs[b].key) return lv.recs[a].key < lv.recs[b].key;
+        return a < b;
+    });
+    for (int g : order) {
+        const Rec<double>& r = lv.recs[g];
+        const int x0 = std::max(0, r.x0 - 1), x1 = std::min(V.W - 1, r.x1 + 1);
+        const int y0 = std::max(0, r.y0 - 1), y1 = std::min(V.H - 1, r.y1 + 1);
+        if (x0 > x1 || y0 > y1) continue;
+        for (int t2 = y0 / B; t2 <= y1 / B; ++t2) {
+            const int32_t* row = pre.data() + (size_t)t2 * (lv.tx + 1);
+            if (row[x1 / B + 1] == row[x0 / B]) continue;
+            for (int t1 = x0 / B; t1 <= x1 / B; ++t1) {
+                const int s = lv.slot[t2 * lv.tx + t1];
+                if (s >= 0) lv.lists[s].push_back(g);
+            }
+        }
+    }
+    // guard-band flags of the region pixels, as the whole-view path sets them
+    lv.amb.assign((size_t)V.W * V.H, 0);
+    for (int g = 0; g < N; ++g) {
+        const Rec<double>& r = lv.recs[g];
+        if (r.margin >= kGlobalTol || r.r == 0) continue;
+        const int xa = std::max(0, r.x0 - 1), xb = std::min(V.W - 1, r.x1 + 1);
+        const int ya = std::max(0, r.y0 - 1), yb = std::min(V.H - 1, r.y1 + 1);
+        for (int j = ya; j <= yb; ++j)
+            for (int i = xa; i <= xb; ++i) lv.amb[(size_t)j * V.W + i] = 1;
+    }
+    const int64_t nr = (int64_t)lv.region.size();
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < nr; ++k) {
+        const int p = lv.region[k], i = p % V.W, j = p / V.W;
+        int64_t len;
+        const int32_t* list = lv.list_of(i, j, len);
+        double C[3], Tp;
+        int nb;
+        bool a;
+        blend_pixel<double>(i, j, list, len, lv.recs, V, C, Tp, nb, a, nullptr);
+        if (a) lv.amb[p] = 1;
+    }
+}
+
+// The region of the selected Gaussians: the pixels of their squares.
+void local_setup(const OScene& sc, const OView& V, int B, const std::vector<int32_t>& sel, LocalView& lv) {
+    preprocess_all<double>(sc, nullptr, V, lv.recs);
+    std::vector<uint8_t> in_region((size_t)V.W * V.H, 0);
+    for (int g : sel) {
+        const Rec<double>& r = lv.recs[g];
+        if (!has_square(r)) continue;
+        for (int j = r.y0; j <= r.y1; ++j)
+            for (int i = r.x0; i <= r.x1; ++i) in_region[(size_t)j * V.W + i] = 1;
+    }
+    local_build(sc, V, B, in_region, lv);
+}
+
+// Upstream gradient of a pixel channel, zero at guard-band pixels.
+inline double upstream(const LocalView& lv, const float* dimg, int p, int c) {
+    return lv.amb[p] ? 0.0 : (double)dimg[(size_t)c * lv.V.W * lv.V.H + p];
 }
 
 // ---------------------------------------------------------------------------
@@ -1104,6 +1285,241 @@ int orc_mat2quat(const double* R, double* q) {
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) M[i][j] = R[3 * i + j];
     mat2quat(M, q);
+    return 0;
+}
+
+// ---- local evaluation around selected Gaussians -----------------------------
+// The scene arrays must stay alive until orc_local_free.  sel: merged ids
+// (4D rows first), distinct.
+void* orc_local_new(const OScene* sc, int n_views, const OView* views, int B, int n_sel, const int32_t* sel) {
+    if (!sc || !views || n_views < 1 || B <= 0 || n_sel < 0) return nullptr;
+    const int N = sc->n3 + sc->n4;
+    Local* L = new Local();
+    L->sc = *sc;
+    L->sel.assign(sel, sel + n_sel);
+    L->selidx.assign((size_t)N, -1);
+    for (int s = 0; s < n_sel; ++s) {
+        if (sel[s] < 0 || sel[s] >= N || L->selidx[sel[s]] >= 0) { delete L; return nullptr; }
+        L->selidx[sel[s]] = s;
+    }
+    L->views.resize(n_views);
+    for (int v = 0; v < n_views; ++v) local_setup(*sc, views[v], B, L->sel, L->views[v]);
+    return L;
+}
+
+void orc_local_free(void* h) { delete static_cast<Local*>(h); }
+
+// The Gaussians blended at given pixels of one view, front to back, with their
+// blend weights alpha T: ids / weights [npx][cap], counts[npx] (the full count,
+// of which the first min(count, cap) are written).
+int orc_blended_at(const OScene* sc, const OView* V, int B, int npx, const int32_t* px, const int32_t* py, int cap,
+                   int32_t* ids, double* weights, int32_t* counts) {
+    if (!sc || !V || B <= 0 || npx < 0 || cap < 0 || !px || !py || !counts) return 1;
+    std::vector<uint8_t> in_region((size_t)V->W * V->H, 0);
+    for (int k = 0; k < npx; ++k) {
+        if (px[k] < 0 || px[k] >= V->W || py[k] < 0 || py[k] >= V->H) return 1;
+        in_region[(size_t)py[k] * V->W + px[k]] = 1;
+    }
+    LocalView lv;
+    local_build(*sc, *V, B, in_region, lv);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int k = 0; k < npx; ++k) {
+        int64_t len;
+        const int32_t* list = lv.list_of(px[k], py[k], len);
+        std::vector<Blended> bl;
+        double C[3], Tp;
+        int nb;
+        bool a;
+        blend_pixel<double>(px[k], py[k], list, len, lv.recs, *V, C, Tp, nb, a, &bl);
+        counts[k] = (int32_t)bl.size();
+        for (int e = 0; e < std::min<int>(cap, (int)bl.size()); ++e) {
+            ids[(size_t)k * cap + e] = bl[e].g;
+            weights[(size_t)k * cap + e] = bl[e].alpha * bl[e].T;
+        }
+    }
+    return 0;
+}
+
+// Per pixel of view v: bit 0 = inside a selected square, bit 1 = guard-band flag.
+int orc_local_amb(void* h, int v, uint8_t* out) {
+    const Local* L = static_cast<const Local*>(h);
+    if (!L || v < 0 || v >= (int)L->views.size() || !out) return 1;
+    const LocalView& lv = L->views[v];
+    std::memset(out, 0, (size_t)lv.V.W * lv.V.H);
+    for (int p : lv.region) out[p] = (uint8_t)(1 | (lv.amb[p] ? 2 : 0));
+    return 0;
+}
+
+// Gradients of the selected Gaussians, summed over the views, of
+// L = sum_v <dimgs[v], C_v> with dimgs zeroed at guard-band pixels:
+// rows[n_sel][65] in the ABI field order (a 3D row fills its first 59).
+int orc_local_grad(void* h, const float* const* dimgs, double* rows) {
+    const Local* L = static_cast<const Local*>(h);
+    if (!L || !dimgs || !rows) return 1;
+    const int ns = (int)L->sel.size();
+    std::fill(rows, rows + (size_t)ns * kRow, 0.0);
+    const int nth = omp_get_max_threads();
+    for (size_t v = 0; v < L->views.size(); ++v) {
+        const LocalView& lv = L->views[v];
+        const float* dimg = dimgs[v];
+        std::vector<std::vector<G2>> acc(nth, std::vector<G2>((size_t)ns, G2{0, 0, {0, 0, 0}, 0, {0, 0, 0}}));
+        const int64_t nr = (int64_t)lv.region.size();
+#pragma omp parallel
+        {
+            std::vector<Blended> bl;
+            std::vector<G2>& my = acc[omp_get_thread_num()];
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t k = 0; k < nr; ++k) {
+                const int p = lv.region[k], i = p % lv.V.W, j = p / lv.V.W;
+                int64_t len;
+                const int32_t* list = lv.list_of(i, j, len);
+                bl.clear();
+                double C[3], Tp;
+                int nb;
+                bool a;
+                blend_pixel<double>(i, j, list, len, lv.recs, lv.V, C, Tp, nb, a, &bl);
+                const double gb[3] = {upstream(lv, dimg, p, 0), upstream(lv, dimg, p, 1), upstream(lv, dimg, p, 2)};
+                blend_pixel_bwd(bl, lv.recs, Tp, lv.V.bg, gb, [&](int g) -> G2* {
+                    const int s = L->selidx[g];
+                    return s >= 0 ? &my[s] : nullptr;
+                });
+            }
+        }
+        for (int s = 0; s < ns; ++s) {
+            const int g = L->sel[s];
+            if (!lv.recs[g].visible) continue;
+            G2 gs{0, 0, {0, 0, 0}, 0, {0, 0, 0}};
+            for (int th = 0; th < nth; ++th) {
+                const G2& a = acc[th][s];
+                gs.u += a.u; gs.v += a.v; gs.op += a.op;
+                for (int k = 0; k < 3; ++k) { gs.Q[k] += a.Q[k]; gs.rgb[k] += a.rgb[k]; }
+            }
+            double gmu[3] = {0, 0, 0}, gmt = 0, gls[4] = {0, 0, 0, 0}, gq[4] = {0, 0, 0, 0}, gq2[4] = {0, 0, 0, 0},
+                   gop = 0, gsh[48];
+            std::memset(gsh, 0, sizeof(gsh));
+            gaussian_bwd(L->sc, g, lv.V, gs, gmu, &gmt, gls, gq, gq2, &gop, gsh);
+            double* o = rows + (size_t)s * kRow;
+            if (g < L->sc.n4) {
+                for (int k = 0; k < 3; ++k) o[k] += gmu[k];
+                o[3] += gmt;
+                for (int k = 0; k < 4; ++k) { o[4 + k] += gls[k]; o[8 + k] += gq[k]; o[12 + k] += gq2[k]; }
+                o[16] += gop;
+                for (int k = 0; k < 48; ++k) o[17 + k] += gsh[k];
+            } else {
+                for (int k = 0; k < 3; ++k) { o[k] += gmu[k]; o[3 + k] += gls[k]; }
+                for (int k = 0; k < 4; ++k) o[6 + k] += gq[k];
+                o[10] += gop;
+                for (int k = 0; k < 48; ++k) o[11 + k] += gsh[k];
+            }
+        }
+    }
+    return 0;
+}
+
+// Central differences of the same loss: entry e moves parameter ent[2e + 1]
+// of selected Gaussian ent[2e] by +-hrel max(1, |theta|) (in float64) and
+// re-composites that Gaussian's square in every view.  ok[e] = 0 when either
+// move changes a discrete decision: the Gaussian's cull, square, clamps or
+// list position, or any pixel's blend count or clamped count (the loss is
+// discontinuous or kinked there).  fd[e] = (L+ - L-) / (theta+ - theta-).
+int orc_local_fd(void* h, const float* const* dimgs, int n_ent, const int32_t* ent, double hrel, double* fd,
+                 int32_t* ok) {
+    const Local* L = static_cast<const Local*>(h);
+    if (!L || !dimgs || n_ent < 0 || !ent || !fd || !ok) return 1;
+    auto nclamp = [](const std::vector<Blended>& b) {
+        int c = 0;
+        for (const Blended& x : b) c += x.clamped;
+        return c;
+    };
+    // per (selected Gaussian, view): blend and clamp counts of the pixels of its
+    // square at the unmoved parameters, computed on first use
+    std::vector<std::vector<std::vector<int32_t>>> base(L->sel.size(), std::vector<std::vector<int32_t>>(L->views.size()));
+    for (int e = 0; e < n_ent; ++e) {
+        const int s = ent[2 * e], k = ent[2 * e + 1];
+        fd[e] = 0.0;
+        ok[e] = 0;
+        if (s < 0 || s >= (int)L->sel.size()) return 1;
+        const int g = L->sel[s];
+        if (k < 0 || k >= (g < L->sc.n4 ? 65 : 59)) return 1;
+        Param<double> P;
+        load_param<double>(L->sc, nullptr, g, P);
+        const double theta = *param_slot(P, k);
+        const double step = hrel * std::max(1.0, std::fabs(theta));
+        double tp = 0, tm = 0, dL = 0;
+        bool same = true;
+        for (size_t v = 0; v < L->views.size() && same; ++v) {
+            const LocalView& lv = L->views[v];
+            const Rec<double>& r0 = lv.recs[g];
+            const Rec<double> rp = record_of(L->sc, lv.V, g, k, step, &tp);
+            const Rec<double> rm = record_of(L->sc, lv.V, g, k, -step, &tm);
+            for (const Rec<double>* r : {&rp, &rm})
+                same = same && r->culled == r0.culled && r->visible == r0.visible && r->r == r0.r &&
+                       r->x0 == r0.x0 && r->x1 == r0.x1 && r->y0 == r0.y0 && r->y1 == r0.y1 && r->kinks == r0.kinks;
+            if (!same || !has_square(r0)) continue;
+            // the depth order must keep g where it was in the lists of its tiles
+            for (int t2 = r0.y0 / lv.B; t2 <= r0.y1 / lv.B && same; ++t2)
+                for (int t1 = r0.x0 / lv.B; t1 <= r0.x1 / lv.B && same; ++t1) {
+                    const std::vector<int32_t>& l = lv.lists[lv.slot[t2 * lv.tx + t1]];
+                    const auto it = std::find(l.begin(), l.end(), g);
+                    if (it == l.end()) continue;
+                    for (const Rec<double>* r : {&rp, &rm}) {
+                        if (it != l.begin()) {
+                            const Rec<double>& q = lv.recs[*(it - 1)];
+                            if (!(q.key < r->key || (q.key == r->key && *(it - 1) < g))) same = false;
+                        }
+                        if (it + 1 != l.end()) {
+                            const Rec<double>& q = lv.recs[*(it + 1)];
+                            if (!(r->key < q.key || (r->key == q.key && g < *(it + 1)))) same = false;
+                        }
+                    }
+                }
+            if (!same) break;
+            const Overlay op{&lv.recs, g, &rp}, om{&lv.recs, g, &rm};
+            const float* dimg = dimgs[v];
+            const int W = lv.V.W, sw = r0.x1 - r0.x0 + 1;
+            const int npx = sw * (r0.y1 - r0.y0 + 1);
+            std::vector<int32_t>& b0 = base[s][v];
+            if (b0.empty()) {
+                b0.resize(2 * (size_t)npx);
+#pragma omp parallel for schedule(dynamic, 64)
+                for (int q = 0; q < npx; ++q) {
+                    const int i = r0.x0 + q % sw, j = r0.y0 + q / sw;
+                    int64_t len;
+                    const int32_t* list = lv.list_of(i, j, len);
+                    std::vector<Blended> b;
+                    double C[3], T;
+                    int n;
+                    bool a;
+                    blend_pixel<double>(i, j, list, len, lv.recs, lv.V, C, T, n, a, &b);
+                    b0[2 * q] = n;
+                    b0[2 * q + 1] = nclamp(b);
+                }
+            }
+            double acc = 0.0;
+            int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : acc, bad)
+            for (int q = 0; q < npx; ++q) {
+                const int i = r0.x0 + q % sw, j = r0.y0 + q / sw;
+                const int p = j * W + i;
+                int64_t len;
+                const int32_t* list = lv.list_of(i, j, len);
+                std::vector<Blended> b1, b2;
+                double C1[3], C2[3], T1, T2;
+                int n1, n2;
+                bool a;
+                blend_pixel<double, Overlay>(i, j, list, len, op, lv.V, C1, T1, n1, a, &b1);
+                blend_pixel<double, Overlay>(i, j, list, len, om, lv.V, C2, T2, n2, a, &b2);
+                if (n1 != b0[2 * q] || n2 != b0[2 * q] || nclamp(b1) != b0[2 * q + 1] || nclamp(b2) != b0[2 * q + 1])
+                    ++bad;
+                for (int c = 0; c < 3; ++c)
+                    acc += upstream(lv, dimg, p, c) * ((C1[c] + T1 * lv.V.bg[c]) - (C2[c] + T2 * lv.V.bg[c]));
+            }
+            if (bad) same = false;
+            dL += acc;
+        }
+        ok[e] = same ? 1 : 0;
+        fd[e] = same && tp != tm ? dL / (tp - tm) : 0.0;
+    }
     return 0;
 }
 

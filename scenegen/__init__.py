@@ -261,6 +261,23 @@ def param_tangents(scene: Scene, seed: int = 4) -> tuple:
     return t3, t4
 
 
+def raw_quaternion_norms(scene: Scene, seed: int = 6, lo: float = 0.5, hi: float = 2.0) -> Scene:
+    """The same scene with every quaternion column (q of the 3D set, q_l and
+    q_r of the 4D set) multiplied by its own factor drawn from U[lo, hi].  The
+    rasterizer takes raw quaternions and normalises them itself, so the
+    rendered scene is the same up to rounding, while the normalisation and its
+    adjoint (the 1/|q| factor) are exercised; training moves quaternions off the
+    unit sphere after the first optimiser step."""
+    rng = np.random.default_rng(seed)
+    g3 = dict(scene.g3)
+    g4 = dict(scene.g4)
+    for d, keys in ((g4, ("quat_l", "quat_r")), (g3, ("quat",))):
+        for k in keys:
+            q = d[k].astype(np.float64)
+            d[k] = _f32(q * rng.uniform(lo, hi, size=(1, q.shape[1])))
+    return Scene(g3, g4, list(scene.views), name=scene.name + "_raw_quats")
+
+
 def subset(scene: Scene, idx3, idx4) -> Scene:
     g3 = {k: np.ascontiguousarray(v[..., idx3]) for k, v in scene.g3.items()}
     g4 = {k: np.ascontiguousarray(v[..., idx4]) for k, v in scene.g4.items()}

@@ -282,6 +282,135 @@ def test_point_lands_where_the_pinhole_model_says():
     assert abs(i + 0.5 - uv[0]) <= 0.5 and abs(j + 0.5 - uv[1]) <= 0.5
 
 
+def _single_3d(X, log_s, sh=None, quat=(1.0, 0.0, 0.0, 0.0), op_logit=2.0):
+    return dict(mean=np.asarray(X, np.float64)[:, None].astype(np.float32),
+                log_scale=np.asarray(log_s, np.float64)[:, None].astype(np.float32),
+                quat=np.asarray(quat, np.float64)[:, None].astype(np.float32),
+                opacity=np.array([op_logit], np.float32),
+                sh=np.zeros((48, 1), np.float32) if sh is None else sh)
+
+
+@pytest.mark.parametrize("side", [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1)])
+def test_jacobian_clamp_beyond_the_field_of_view(side):
+    """A Gaussian whose camera-space ratio x/z (or y/z) lies beyond 1.3 times the
+    half field of view: its 2D covariance minus the dilation equals J S J^T
+    with J the central-difference Jacobian of the pinhole map taken at the
+    clamped point (the point of the same depth on the ray at 1.3 times the
+    half field of view), and differs from the unclamped one.  (3DGS-lineage
+    clamp, reading of the constants the paper inherits, Sec. 4.3.)"""
+    v = sg.View(np.eye(3, 4, dtype=np.float32), 100.0, 90.0, 64.0, 48.0, 128, 96, 0.5)
+    z = 3.0
+    limx, limy = 1.3 * 64.0 / 100.0, 1.3 * 48.0 / 90.0
+    tx = (limx * 1.4 if side[0] > 0 else -limx * 1.25) if side[0] else 0.1
+    ty = (limy * 1.3 if side[1] > 0 else -limy * 1.6) if side[1] else -0.05
+    X = np.array([tx * z, ty * z, z])
+    ls = np.log([0.05, 0.12, 0.08])
+    q = np.array([0.9, 0.2, -0.3, 0.25])
+    q /= np.linalg.norm(q)
+    sc = sg.Scene(_single_3d(X, ls, quat=q), sg.empty_4d(), [v])
+    pr = oracle.project(sc, v)
+    assert pr["culled"][0] == 0
+    Q = np.array([[pr["q00"][0], pr["q01"][0]], [pr["q01"][0], pr["q11"][0]]])
+    S2 = np.linalg.inv(Q) - 0.3 * np.eye(2)
+    mu, Sg, _ = oracle.world(sc, 0, v.t)
+    def jac_at(P):
+        J = np.zeros((2, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = 1e-6
+            J[:, k] = (_pixel_of(v, P + e) - _pixel_of(v, P - e)) / 2e-6
+        return J
+    xc = np.clip(mu[0] / mu[2], -limx, limx)
+    yc = np.clip(mu[1] / mu[2], -limy, limy)
+    Jc = jac_at(np.array([xc * mu[2], yc * mu[2], mu[2]]))
+    assert np.allclose(S2, Jc @ Sg @ Jc.T, rtol=1e-7, atol=1e-9)
+    Ju = jac_at(mu)
+    assert not np.allclose(S2, Ju @ Sg @ Ju.T, rtol=1e-3, atol=1e-6)
+
+
+def test_sh_view_direction_points_from_the_camera_to_the_gaussian():
+    """A Gaussian carrying only degree-1 coefficients, seen by cameras on
+    opposite sides: its colour is 0.5 + c Y_1m(d) with d the unit vector from
+    the camera centre to the Gaussian (Y_1-1 = -k y, Y_10 = k z, Y_11 = -k x,
+    k = sqrt(3 / (4 pi)), Condon-Shortley phase).  Reversing d flips each
+    degree-1 term, so the colours of opposite cameras would swap."""
+    k1 = math.sqrt(3.0 / (4.0 * math.pi))
+    X = np.array([0.1, -0.2, 0.3])
+    sh = np.zeros((48, 1), np.float32)
+    coef = {1: (0.3, -0.1, 0.2), 2: (-0.4, 0.25, 0.1), 3: (0.15, 0.35, -0.3)}  # index l^2 + l + m -> RGB
+    for idx, rgb in coef.items():
+        sh[3 * idx:3 * idx + 3, 0] = rgb
+    checked = 0
+    for eye in [(0.1, -0.2, -2.7), (0.1, -0.2, 3.3), (-2.9, -0.2, 0.3), (3.1, -0.2, 0.3), (0.1, 2.8, 0.3),
+                (0.1, -3.2, 0.3), (1.7, 1.1, -2.0)]:
+        up_ok = abs(eye[1] - X[1]) < 2.0
+        v = sg.look_at(eye, tuple(X), 64, 48) if up_ok else _look_at_z_up(eye, X)
+        sc = sg.Scene(_single_3d(X, np.log([0.05] * 3), sh=sh), sg.empty_4d(), [v])
+        pr = oracle.project(sc, v)
+        Xf = X.astype(np.float32).astype(np.float64)
+        M = v.world_to_cam.astype(np.float64)
+        C = -M[:, :3].T @ M[:, 3]
+        d = (Xf - C) / np.linalg.norm(Xf - C)
+        Y = {1: -k1 * d[1], 2: k1 * d[2], 3: -k1 * d[0]}
+        expect = 0.5 + sum(sh[3 * i:3 * i + 3, 0].astype(np.float64) * Y[i] for i in (1, 2, 3))
+        got = np.array([pr["r"][0], pr["g"][0], pr["b"][0]])
+        assert np.allclose(got, np.maximum(expect, 0.0), atol=1e-12), (eye, got, expect)
+        rev = 0.5 - (expect - 0.5)
+        assert not np.allclose(got, np.maximum(rev, 0.0), atol=1e-3)
+        checked += 1
+    assert checked == 7
+
+
+def _look_at_z_up(eye, target):
+    """Camera at eye looking at target with world up = +z (for views along y)."""
+    eye = np.asarray(eye, np.float64)
+    f = np.asarray(target, np.float64) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.array([0.0, 0.0, 1.0]))
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])
+    M = np.concatenate([R, (-R @ eye)[:, None]], axis=1).astype(np.float32)
+    return sg.View(M, 55.4, 55.4, 32.0, 24.0, 64, 48, 0.5)
+
+
+def test_raw_quaternion_norm_leaves_image_and_scales_gradient():
+    """Quaternions are normalised before use: scaling a quaternion column by
+    lambda leaves the image unchanged and divides its gradient by lambda (the
+    gradient is orthogonal to the quaternion), for q, q_l and q_r."""
+    base = sg.tiny_scene(n3=200, n4=200, width=64, height=48, seed=9)
+    raw = sg.raw_quaternion_norms(base, seed=4)
+    v = base.views[0]
+    a = oracle.render(base, v)["img"]
+    b = oracle.render(raw, v)["img"]
+    # the float32 rounding of the scaled quaternion moves the image by ~1e-7
+    assert np.abs(a - b).max() < 1e-5
+    dl = sg.upstream_grads([v], seed=5)
+    ga3, ga4 = oracle.render_bwd(base, [v], dl)
+    gb3, gb4 = oracle.render_bwd(raw, [v], dl)
+    # compare on the raw scene itself: its gradient times |q| against the
+    # gradient of the same scene with each column normalised in float64
+    unit = sg.Scene({k: x.copy() for k, x in raw.g3.items()}, {k: x.copy() for k, x in raw.g4.items()}, raw.views)
+    for d, gr_raw, gr_unit_src, keys in ((raw.g3, gb3, "3", ("quat",)), (raw.g4, gb4, "4", ("quat_l", "quat_r"))):
+        for k in keys:
+            q = d[k].astype(np.float64)
+            nrm = np.linalg.norm(q, axis=0)
+            assert nrm.min() < 0.6 and nrm.max() > 1.8
+            radial = (gr_raw[k] * q).sum(0)
+            assert np.abs(radial).max() <= 1e-10 * np.abs(gr_raw[k]).max() * nrm.max()
+    # the gradient of the normalised scene (float64 division, rounded) times 1/|q|
+    for (d, k, which) in ((raw.g3, "quat", 3), (raw.g4, "quat_l", 4), (raw.g4, "quat_r", 4)):
+        q = d[k].astype(np.float64)
+        (unit.g3 if which == 3 else unit.g4)[k] = (q / np.linalg.norm(q, axis=0)).astype(np.float32)
+    gu3, gu4 = oracle.render_bwd(unit, [v], dl)
+    for d, gr_raw, gr_unit, keys in ((raw.g3, gb3, gu3, ("quat",)), (raw.g4, gb4, gu4, ("quat_l", "quat_r"))):
+        for k in keys:
+            nrm = np.linalg.norm(d[k].astype(np.float64), axis=0)
+            got = gr_raw[k] * nrm
+            want = gr_unit[k]
+            assert np.linalg.norm(got - want) <= 1e-4 * np.linalg.norm(want), k
+
+
 # --- Eq. 8: the static limit ----------------------------------------------------
 
 def _static_pair(n=60, seed=7, tilt=False):

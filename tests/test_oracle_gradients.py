@@ -1,5 +1,7 @@
 """Pins of the oracle's hand-written adjoint: forward-mode AD (dual numbers)
 dot-product test and central finite differences (no GPU)."""
+import zlib
+
 import numpy as np
 import pytest
 
@@ -22,7 +24,7 @@ def _dot(g, t):
 @pytest.mark.parametrize("group", [("3", k) for k in GROUPS3] + [("4", k) for k in GROUPS4])
 def test_vjp_equals_dual_jvp_per_group(small, group):
     v = small.views[0]
-    rng = np.random.default_rng(hash(group) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(repr(group).encode()))
     ubar = rng.normal(size=(3, v.height, v.width)).astype(np.float32)
     t3, t4 = sg.param_tangents(small, seed=9)
     keep3 = {k: t3[k] for k in t3 if group == ("3", k)}
