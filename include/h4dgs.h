@@ -134,22 +134,32 @@ h4d_status h4dgs_render_fwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, 
                             int32_t n_views, const h4d_config *cfg, float *const *images, void *state,
                             size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
 
-/* Inference render: the forward of render_fwd (same arguments, same images,
- * bit for bit) without the state only the backward reads (per-pixel final
- * transmittance, last contributor and output colour; per-tile adjoint cost),
- * for rendering without training.  `state` still holds the records, lists
- * and status (h4dgs_check applies as after render_fwd).  render_bwd must not
- * follow it: the adjoint would read the state of an earlier render_fwd, or
- * none. */
+/* Inference render (the paper's rendering speed claims, Tables 1-2): the
+ * forward of render_fwd (same arguments, same images, bit for bit) without the
+ * state only the backward reads (per-pixel final transmittance, last
+ * contributor and output colour; per-tile adjoint cost), for rendering without
+ * training.  `state` still holds the records, lists and status (h4dgs_check
+ * applies as after render_fwd).  render_bwd must not follow it: it would
+ * combine this call's records and tile lists with the per-pixel state of an
+ * earlier render_fwd (or uninitialised memory), so its gradients are
+ * meaningless; its reads stay inside each tile's list and the records. */
 h4d_status h4dgs_render_infer(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
                               int32_t n_views, const h4d_config *cfg, float *const *images, void *state,
                               size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
 
-/* Backward: the exact adjoint of render_fwd.  dl_dimages: host array of
- * n_views device pointers to float[3][H][W] (dL/dC, loss weighting included).
- * The gradients of every raw parameter are OVERWRITTEN with
+/* Backward (the training step's fast adjoint, which Sec. 5.2 adopts from
+ * prior work without describing it): the exact adjoint of render_fwd
+ * through blending (Eq. 3), projection, slicing (Eq. 5-6), covariance (Eq. 2
+ * and its 4D analogue), rotation (Eq. 4) and the activations; per-pixel
+ * transmittance is recomputed front to back, not stored.  dl_dimages: host
+ * array of n_views device pointers to float[3][H][W] (dL/dC, loss weighting
+ * included).  The gradients of every raw parameter (grad3/grad4: device
+ * arrays laid out as the parameters) are OVERWRITTEN with
  * sum_v J_v^T dl_dimages_v.  Same g3, g4, views and cfg as the forward; state
- * as the forward left it. */
+ * as the forward left it (unchanged in between); scratch as sized by
+ * h4dgs_workspace_size.  Argument errors: H4D_ERR_INVALID_ARG before anything
+ * is enqueued.  After a forward whose pairs overflowed, the blending kernels
+ * find empty tile lists and the gradients hold only what no pair needs. */
 h4d_status h4dgs_render_bwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
                             int32_t n_views, const h4d_config *cfg, const float *const *dl_dimages,
                             const void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
@@ -209,6 +219,21 @@ h4d_status h4dgs_adam(h4d_ctx *ctx, int32_t n_seg, float *const *params, const f
 h4d_status h4dgs_l1_loss_grad(h4d_ctx *ctx, int32_t n_views, const float *const *images,
                               const float *const *targets, const h4d_view *views, float *const *dl_dimages,
                               float *loss, void *stream);
+
+/* ---- workspace self-check (host arithmetic only, no device work) ---------
+ * Every radix sort pass of the binning writes 2^nbits counts per sort block
+ * and segment into a histogram buffer of the scratch workspace.  The forward
+ * checks each pass against the buffer sizes of its workspace layout on the
+ * host before launching anything (and the launcher again per pass); these two
+ * calls expose that arithmetic so that it can be tested without a GPU.
+ * h4dgs_radix_hist_words: histogram words one pass over `capacity` keys in
+ * n_seg segments with nbits-bit digits and `items` keys per thread (8 or 2)
+ * needs.  h4dgs_radix_pass_check: H4D_OK if such a pass fits histogram /
+ * digit-total buffers of hist_words / totals_words 32-bit words, else
+ * H4D_ERR_INVALID_ARG (also for nbits outside [1, 11] or other items). */
+size_t h4dgs_radix_hist_words(uint64_t capacity, int32_t n_seg, int32_t nbits, int32_t items);
+h4d_status h4dgs_radix_pass_check(uint64_t capacity, int32_t n_seg, int32_t nbits, int32_t items,
+                                  size_t hist_words, size_t totals_words);
 
 /* ---- instrumentation ---------------------------------------------------- */
 typedef enum {

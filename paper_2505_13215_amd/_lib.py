@@ -27,7 +27,8 @@ EXPORTS = (
     "h4dgs_create", "h4dgs_destroy", "h4dgs_last_error", "h4dgs_version", "h4dgs_workspace_size",
     "h4dgs_render_fwd", "h4dgs_render_infer", "h4dgs_render_bwd", "h4dgs_check", "h4dgs_rasterize_splats",
     "h4dgs_convert_scratch_bytes", "h4dgs_convert_static", "h4dgs_adam", "h4dgs_l1_loss_grad",
-    "h4dgs_profile", "h4dgs_profile_read", "h4dgs_stats", "h4dgs_stats_read",
+    "h4dgs_profile", "h4dgs_profile_read", "h4dgs_stats", "h4dgs_stats_read", "h4dgs_radix_hist_words",
+    "h4dgs_radix_pass_check",
 )
 
 STAGES = ("preprocess", "depth_sort", "binning", "blend_fwd", "blend_bwd", "preprocess_bwd", "adam", "loss")
@@ -94,8 +95,11 @@ def load(path: str = LIB_PATH):
     L.h4dgs_profile_read.argtypes = [vp, vp, vp]
     L.h4dgs_stats.argtypes = [vp, i32]
     L.h4dgs_stats_read.argtypes = [vp, vp, sz, vp, vp]
+    L.h4dgs_radix_hist_words.argtypes = [C.c_uint64, i32, i32, i32]
+    L.h4dgs_radix_hist_words.restype = sz
+    L.h4dgs_radix_pass_check.argtypes = [C.c_uint64, i32, i32, i32, sz, sz]
     for name in EXPORTS:
-        if name not in ("h4dgs_last_error", "h4dgs_version", "h4dgs_convert_scratch_bytes"):
+        if name not in ("h4dgs_last_error", "h4dgs_version", "h4dgs_convert_scratch_bytes", "h4dgs_radix_hist_words"):
             getattr(L, name).restype = i32
     _lib = L
     return L

@@ -163,6 +163,7 @@ struct Layout {
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_ceff,
         sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges,
         sc_shape, sc_runs, fwd_bytes;
+    size_t hist_words = 0, totals_words = 0;  // 32-bit words of the radix histogram / digit totals
     // scratch, backward use
     size_t sc_g2, sc_border, bwd_bytes;
     size_t scratch_bytes;
@@ -244,9 +245,11 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     int cbits = 1;
     for (int k = 0; k < L.n_passes(); ++k)
         cbits = std::max(cbits, pass_bits(bits_for(L.pass(k).supers), kMaxRadixBits));
-    L.sc_hist = f.take(4 * std::max(radix_hist_words(L.ccap, 1, cbits, kSortItems),
-                                    radix_hist_words(n, L.per_pass, kDepthDigitBits, kDepthSortItems)));
-    L.sc_totals = f.take(4 * (size_t)kMaxRadix * (size_t)L.per_pass);
+    L.hist_words = std::max(radix_hist_words(L.ccap, 1, cbits, kSortItems),
+                            radix_hist_words(n, L.per_pass, kDepthDigitBits, kDepthSortItems));
+    L.totals_words = (size_t)kMaxRadix * (size_t)L.per_pass;
+    L.sc_hist = f.take(4 * L.hist_words);
+    L.sc_totals = f.take(4 * L.totals_words);
     L.sc_cranges = f.take(16 * (size_t)max_super);
     L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
     L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
@@ -257,6 +260,30 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     L.bwd_bytes = b.off;
     L.scratch_bytes = std::max(L.fwd_bytes, L.bwd_bytes);
     return L;
+}
+
+// Every radix pass the forward will launch fits the layout's histogram and
+// digit-total buffers (checked on the host before anything is enqueued; the
+// launcher checks each pass again).
+bool plan_fits(const Layout& L) {
+    for (int k = 0; k < L.n_passes(); ++k) {
+        const Pass P = L.pass(k);
+        const int passes = n_passes_for(32, kDepthDigitBits);
+        for (int p = 0, shift = 0; p < passes; ++p) {
+            const int nb = (32 - shift + (passes - p) - 1) / (passes - p);
+            if (!radix_pass_fits((uint64_t)L.N, P.v1 - P.v0, nb, kDepthSortItems, L.hist_words, L.totals_words))
+                return false;
+            shift += nb;
+        }
+        const int bits = bits_for(P.supers);
+        const int cp = n_passes_for(bits, kMaxRadixBits);
+        for (int p = 0, shift = 0; p < cp; ++p) {
+            const int nb = (bits - shift + (cp - p) - 1) / (cp - p);
+            if (!radix_pass_fits(L.ccap, 1, nb, kSortItems, L.hist_words, L.totals_words)) return false;
+            shift += nb;
+        }
+    }
+    return true;
 }
 
 // 64-bit words the forward's init clears from st_ranges on: the tile ranges
@@ -351,7 +378,9 @@ unsigned long long* stat_counters(h4d_ctx* c, void* state, const Layout& L) {
 
 // keep: write the adjoint's per-pixel and per-tile state (false for an
 // inference render)
-void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chunk, int cull, void* state,
+// Returns false (after launching only part of the pass) when a radix pass did
+// not fit its buffers, which plan_fits rules out beforehand.
+bool bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chunk, int cull, void* state,
                    void* scratch, const PtrTable& images, hipStream_t st, bool keep = true) {
     const int N = L.N;
     const int nv = P.v1 - P.v0;
@@ -372,8 +401,9 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         int shift = 0;
         for (int pass = 0; pass < passes; ++pass) {
             const int nb = (32 - shift + (passes - pass) - 1) / (passes - pass);
-            launch_radix_pass(dk, dv, dk2, dv2, nullptr, (uint64_t)N, (uint64_t)N, shift, nb, hist, totals, nullptr,
-                              st, nv, (uint64_t)N, nullptr, 0, kDepthSortItems);
+            if (!launch_radix_pass(dk, dv, dk2, dv2, nullptr, (uint64_t)N, (uint64_t)N, shift, nb, hist, L.hist_words,
+                                   totals, L.totals_words, nullptr, st, nv, (uint64_t)N, nullptr, 0, kDepthSortItems))
+                return false;
             std::swap(dk, dk2);
             std::swap(dv, dv2);
             shift += nb;
@@ -425,10 +455,12 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
             const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
             uint32_t* kout = (kin == pk) ? pk2 : pk;
             uint32_t* vout = (vin == pv) ? pv2 : pv;
-            launch_radix_pass(kin, vin, kout, vout, p == 0 ? eff_c : ceff, 0, L.ccap, shift, nb, hist, totals, nullptr,
-                              st, 1, 0, passes == 1 ? cranges : nullptr, P.supers, kSortItems,
-                              (mkey && p == passes - 1) ? dv : nullptr, (drop && p == 0) ? 1 : 0,
-                              (drop && p == 0) ? ceff : nullptr);
+            if (!launch_radix_pass(kin, vin, kout, vout, p == 0 ? eff_c : ceff, 0, L.ccap, shift, nb, hist,
+                                   L.hist_words, totals, L.totals_words, nullptr, st, 1, 0,
+                                   passes == 1 ? cranges : nullptr, P.supers, kSortItems,
+                                   (mkey && p == passes - 1) ? dv : nullptr, (drop && p == 0) ? 1 : 0,
+                                   (drop && p == 0) ? ceff : nullptr))
+                return false;
             kin = kout;
             vin = vout;
             shift += nb;
@@ -455,6 +487,7 @@ void bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
                          keep ? at<uint32_t>(state, L.st_tcost) : nullptr,
                          keep ? at<uint32_t>(state, L.st_thist) + (size_t)kCostBuckets * (P.v0 / L.per_pass) : nullptr,
                          keep ? stat_counters(c, state, L) : nullptr, st, km.a, km.b);
+    return true;
 }
 
 }  // namespace
@@ -512,6 +545,7 @@ static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d*
         return fail(ctx, H4D_ERR_INVALID_ARG, "state too small (%zu < %zu)", state_bytes, L.state_bytes);
     if (!scratch || scratch_bytes < L.fwd_bytes)
         return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small (%zu < %zu)", scratch_bytes, L.fwd_bytes);
+    if (!plan_fits(L)) return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: radix buffers of the layout too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const G3Ptr p3 = to_ptr(g3);
     const G4Ptr p4 = to_ptr(g4);
@@ -529,7 +563,8 @@ static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d*
             launch_preprocess(p3, p4, vp, P.v0, P.v1 - P.v0, at<Rec>(state, L.st_recs),
                               at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
         }
-        bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st, keep);
+        if (!bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st, keep))
+            return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: a radix pass did not fit its buffers");
     }
     return hip_check(ctx, keep ? "render_fwd" : "render_infer");
 }
@@ -648,6 +683,7 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     const Layout L = make_layout(n, &view, 1, cfg);
     if (!state || state_bytes < L.state_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "state too small");
     if (!scratch || scratch_bytes < L.fwd_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small");
+    if (!plan_fits(L)) return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: radix buffers of the layout too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
     launch_init_state(view_table(&view, 1, cfg->tile), at<ViewParams>(state, L.st_views),
                       at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base),
@@ -658,7 +694,8 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     PtrTable tab;
     std::memset(&tab, 0, sizeof(tab));
     tab.p[0] = image;
-    bin_and_blend(ctx, L, L.pass(0), cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st);
+    if (!bin_and_blend(ctx, L, L.pass(0), cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st))
+        return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: a radix pass did not fit its buffers");
     const size_t hw = (size_t)width * height;
     if (T_final) (void)hipMemcpyAsync(T_final, at<float>(state, L.st_T), 4 * hw, hipMemcpyDeviceToDevice, st);
     if (sorted_ids && L.cap > 0)
@@ -667,6 +704,15 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
         (void)hipMemcpyAsync(ranges, at<int64_t>(state, L.st_ranges), 16 * (size_t)L.total_tiles,
                              hipMemcpyDeviceToDevice, st);
     return hip_check(ctx, "rasterize_splats");
+}
+
+h4d_status h4dgs_radix_pass_check(uint64_t capacity, int32_t n_seg, int32_t nbits, int32_t items,
+                                  size_t hist_words, size_t totals_words) {
+    return radix_pass_fits(capacity, n_seg, nbits, items, hist_words, totals_words) ? H4D_OK : H4D_ERR_INVALID_ARG;
+}
+
+size_t h4dgs_radix_hist_words(uint64_t capacity, int32_t n_seg, int32_t nbits, int32_t items) {
+    return radix_hist_words(capacity, n_seg, nbits, items);
 }
 
 size_t h4dgs_convert_scratch_bytes(int32_t n4) {

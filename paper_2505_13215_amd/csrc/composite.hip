@@ -357,6 +357,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const float* __restrict__ dl = dls.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
     const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
+    const int64_t list_end = ranges[2 * (size_t)(V.tile_base + tile) + 1];
     const size_t HW = (size_t)V.W * V.H;
     const int lane = __lane_id();
     // all pixels of a lane share one column (NT is a multiple of B)
@@ -389,7 +390,9 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     __syncthreads();
     if (lane_nc) atomicMax(&s_max, lane_nc);
     __syncthreads();
-    const int64_t end = start + (int64_t)s_max;
+    // the forward's last contributor; never past the tile's list (a state whose
+    // per-pixel part comes from another forward reads no foreign entries)
+    const int64_t end = min(start + (int64_t)s_max, list_end);
     const uint32_t wave_nc = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_nc));
     const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;

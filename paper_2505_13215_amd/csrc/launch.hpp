@@ -46,24 +46,31 @@ constexpr int kMaxRadix = 1 << kMaxRadixBits;
 int radix_blocks(uint64_t capacity, int items);
 // words of `hist` for passes of up to max_bits bits
 size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits, int items);
+// Whether a pass fits histogram / digit-total buffers of the given sizes (in
+// 32-bit words): hist needs radix_hist_words(capacity, n_seg, nbits, items),
+// totals 2^nbits * n_seg; nbits in [1, 11], items kSortItems or 2 (8-bit
+// digits only).
+bool radix_pass_fits(uint64_t capacity, int n_seg, int nbits, int items, size_t hist_words, size_t totals_words);
 // One stable LSD pass over `nbits` (<= 11) bits at `shift`, independently on
 // n_seg segments that start seg_stride elements apart (all arrays).  Count
 // (per segment) from *dcount when dcount != null, else hcount; capacity bounds
 // the count.  vals_out index is offset by *out_offset when out_offset != null.
-// hist holds radix_hist_words(capacity, n_seg, nbits, items) words, totals
-// 2^nbits * n_seg.  items: keys per thread, kSortItems or 2 (8-bit digits
-// only; for short key sets, more and smaller blocks).
+// hist / totals hold hist_words / totals_words words; a pass that does not fit
+// them (radix_pass_fits) launches nothing and returns false.  items: keys per
+// thread, kSortItems or 2 (8-bit digits only; for short key sets, more and
+// smaller blocks).
 // digit_ranges (may be null): for a pass over whole keys, [start, end) of each
 // of the first n_digit_ranges digits in the output.  val_map (may be null):
 // the values written out are val_map[value].  skip_empty: keys whose upper 16
 // bits are zero are dropped (the output holds the others, in order, from
 // position 0); out_count (may be null) receives the number of keys written.
-void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+bool launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
-                       uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
-                       int n_seg = 1, uint64_t seg_stride = 0, int64_t* digit_ranges = nullptr,
-                       int n_digit_ranges = 0, int items = kSortItems, const uint32_t* val_map = nullptr,
-                       int skip_empty = 0, unsigned long long* out_count = nullptr);
+                       uint32_t* hist, size_t hist_words, uint32_t* totals, size_t totals_words,
+                       const unsigned long long* out_offset, hipStream_t st, int n_seg = 1, uint64_t seg_stride = 0,
+                       int64_t* digit_ranges = nullptr, int n_digit_ranges = 0, int items = kSortItems,
+                       const uint32_t* val_map = nullptr, int skip_empty = 0,
+                       unsigned long long* out_count = nullptr);
 int scan_blocks(int n);
 // out[j] = sum_{i<j} in[idx[i]] (idx may be null), out[n] = total; 64-bit.
 // With run_start, run_start[r] (r < run_cap) receives the index i whose range

@@ -249,13 +249,24 @@ size_t radix_hist_words(uint64_t capacity, int n_seg, int max_bits, int items) {
     return ((size_t)1 << max_bits) * (size_t)std::max(1, radix_blocks(capacity, items)) * (size_t)std::max(1, n_seg);
 }
 
-void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+bool radix_pass_fits(uint64_t capacity, int n_seg, int nbits, int items, size_t hist_words, size_t totals_words) {
+    if (nbits < 1 || nbits > kMaxRadixBits || n_seg < 0 || (items != 2 && items != kSortItems)) return false;
+    if (items == 2 && nbits > 8) return false;
+    return radix_hist_words(capacity, n_seg, nbits, items) <= hist_words &&
+           ((size_t)1 << nbits) * (size_t)std::max(1, n_seg) <= totals_words;
+}
+
+bool launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                        const unsigned long long* dcount, uint64_t hcount, uint64_t capacity, int shift, int nbits,
-                       uint32_t* hist, uint32_t* totals, const unsigned long long* out_offset, hipStream_t st,
-                       int n_seg, uint64_t seg_stride, int64_t* digit_ranges, int n_digit_ranges, int items,
-                       const uint32_t* val_map, int skip_empty, unsigned long long* out_count) {
+                       uint32_t* hist, size_t hist_words, uint32_t* totals, size_t totals_words,
+                       const unsigned long long* out_offset, hipStream_t st, int n_seg, uint64_t seg_stride,
+                       int64_t* digit_ranges, int n_digit_ranges, int items, const uint32_t* val_map, int skip_empty,
+                       unsigned long long* out_count) {
+    // every block writes 2^nbits counts per segment: refuse a pass whose
+    // histogram or digit totals would not fit the buffers it was given
+    if (!radix_pass_fits(capacity, n_seg, nbits, items, hist_words, totals_words)) return false;
     const int nb = radix_blocks(capacity, items);
-    if (nb == 0 || n_seg == 0) return;
+    if (nb == 0 || n_seg == 0) return true;
     const dim3 grid(nb, n_seg);
     // the smallest instantiation that holds the digit (LDS is sized by it)
 #define H4D_RADIX_PASS(MB, IT)                                                                                       \
@@ -278,6 +289,7 @@ void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
         else H4D_RADIX_PASS(kMaxRadixBits, kSortItems);
     }
 #undef H4D_RADIX_PASS
+    return true;
 }
 
 // ---------------------------------------------------------------------------

@@ -235,3 +235,25 @@ def test_profile_levels(L):
     n = (C.c_int64 * 8)()
     assert c.L.h4dgs_profile_read(c.h, ms, n) == 0
     assert list(n) == [0] * 8
+
+
+def test_radix_pass_buffer_check_on_the_host(L):
+    """The host-side check every radix pass of the binning goes through before
+    launch: exactly sized buffers pass, one word less of histogram or digit
+    totals fails (the launcher then enqueues nothing), and so do digit widths
+    outside [1, 11] or more than 8 bits with 2 keys per thread."""
+    lib = L.load()
+    for cap, nseg, bits, items in [(250_000, 1, 8, 2), (250_000, 32, 8, 2), (26_000_000, 1, 11, 8),
+                                   (5_000, 1, 6, 8), (0, 1, 9, 8), (1, 3, 1, 8)]:
+        need = lib.h4dgs_radix_hist_words(cap, nseg, bits, items)
+        tot = (1 << bits) * max(1, nseg)
+        assert need >= (1 << bits) * max(1, nseg)
+        assert lib.h4dgs_radix_pass_check(cap, nseg, bits, items, need, tot) == L.H4D_OK
+        assert lib.h4dgs_radix_pass_check(cap, nseg, bits, items, need - 1, tot) == L.H4D_ERR_INVALID_ARG
+        assert lib.h4dgs_radix_pass_check(cap, nseg, bits, items, need, tot - 1) == L.H4D_ERR_INVALID_ARG
+    # the failure that once happened: a histogram sized for 6-bit digits, used
+    # by an 11-bit pass over the same keys
+    small = lib.h4dgs_radix_hist_words(3_000_000, 1, 6, 8)
+    assert lib.h4dgs_radix_pass_check(3_000_000, 1, 11, 8, small, 1 << 11) == L.H4D_ERR_INVALID_ARG
+    for bits, items in [(0, 8), (12, 8), (9, 2), (8, 4)]:
+        assert lib.h4dgs_radix_pass_check(1000, 1, bits, items, 1 << 40, 1 << 40) == L.H4D_ERR_INVALID_ARG
