@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import scenegen as sg
-from parity_util import check_image
+from parity_util import check_image, check_pixels, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -135,6 +135,9 @@ def test_batched_multi_pass_super_tile_sort_is_bit_identical(h4d):
     assert r1.last_pairs == r2.last_pairs
     for a, b in zip(h1.images, h2.images):
         assert torch.equal(a, b)
+    for v, img in zip(views, h2.images):
+        ref = oracle.render(scene, v)
+        check_image(img.cpu().numpy(), ref["img"], ref["amb"])
 
 
 def test_two_pass_super_tile_sort_single_view_is_tile_independent(h4d):
@@ -148,6 +151,8 @@ def test_two_pass_super_tile_sort_single_view_is_tile_independent(h4d):
     _, _, _, h8 = _render(h4d, scene, views, False, tile=8, chunk=64, cap=1 << 24)
     _, _, _, h16 = _render(h4d, scene, views, False, tile=16, chunk=64, cap=1 << 24)
     assert torch.equal(h8.images[0], h16.images[0])
+    ref = oracle.render(scene, views[0])
+    check_image(h8.images[0].cpu().numpy(), ref["img"], ref["amb"])
 
 
 def test_views_whose_super_tile_sorts_differ_in_digit_width(h4d):
@@ -181,6 +186,9 @@ def test_batched_pass_with_many_count_workgroups(h4d):
     assert r1.last_pairs == r2.last_pairs
     for a, b in zip(h1.images, h2.images):
         assert torch.equal(a, b)
+    for v, img in zip(views, h2.images):
+        ref = oracle.render(scene, v)
+        check_image(img.cpu().numpy(), ref["img"], ref["amb"])
 
 
 def test_batched_full_size_matches_single_view(h4d):
@@ -217,6 +225,13 @@ def test_batched_full_size_matches_single_view(h4d):
         assert float((a3[k] - b3[k]).norm()) <= 1e-5 * float(a3[k].norm()) + 1e-30, k
     for k in a4:
         assert float((a4[k] - b4[k]).norm()) <= 1e-5 * float(a4[k].norm()) + 1e-30, k
+    # every one of the 32 batched views against the oracle's per-pixel brute
+    # force over all 1M Gaussians: corners, ragged last tile row and column,
+    # random pixels
+    print("[batched full size] sampled pixels of the 32 views against the oracle", flush=True)
+    for k, (v, img) in enumerate(zip(views, im2)):
+        xs, ys = sample_pixels(v.width, v.height, 40, seed=100 + k)
+        check_pixels(scene, v, img.cpu().numpy(), xs, ys)
 
 
 def test_batched_pass_beyond_masked_key_range(h4d):
@@ -247,6 +262,9 @@ def test_batched_pass_beyond_masked_key_range(h4d):
     (im1, a3, a4), (im2, b3, b4) = out
     for v, (a, b) in enumerate(zip(im1, im2)):
         assert torch.equal(a, b), v
+    for k, (v, img) in enumerate(zip(views, im2)):
+        xs, ys = sample_pixels(v.width, v.height, 1500, seed=200 + k, tile=8)
+        check_pixels(scene, v, img.cpu().numpy(), xs, ys)
     assert float(a3["opacity"].norm()) > 0 and float(a4["opacity"].norm()) > 0
     for k in a3:
         assert float((a3[k] - b3[k]).norm()) <= 1e-5 * float(a3[k].norm()) + 1e-30, k

@@ -1,9 +1,12 @@
-"""The inference render (render_infer): the training forward's images bit for
-bit, with or without batching, at the small views and at the training-step
-workload, and no backward from its handle."""
+"""The inference render (render_infer): against the oracle, and the training
+forward's images bit for bit, with or without batching, at the small views and
+at the training-step workload (whose whole image is compared with the oracle in
+the full-size tests), and no backward from its handle."""
 import pytest
 
+import oracle
 import scenegen as sg
+from parity_util import check_image
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -31,6 +34,9 @@ def test_infer_images_equal_forward(h4d, batched):
     h = rast.infer(g3, g4, views)
     for a, b in zip(ref, h.images):
         assert torch.equal(a, b)
+    for v, img in zip(views, h.images):
+        o = oracle.render(scene, v)
+        check_image(img.cpu().numpy(), o["img"], o["amb"])
     with pytest.raises(RuntimeError):
         rast.backward(h, g3, g4, [torch.zeros_like(im) for im in h.images])
 

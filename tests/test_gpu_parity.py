@@ -397,3 +397,36 @@ def test_l1_loss_gradient(h4d, sizes):
         assert np.array_equal(d.cpu().numpy(), expect)
         ref_loss += np.abs(a.astype(np.float64) - b).mean() / V
     assert abs(float(loss) - ref_loss) <= 1e-5 * ref_loss
+
+
+# ---------------------------------------------------------------------------
+# raw (non-unit) quaternions: the normalisation and its 1/|q| adjoint
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_raw_quaternions_forward_and_backward(h4d, seed):
+    """Quaternion columns (q, q_l, q_r) scaled by seeded factors in [0.3, 3]
+    as training leaves them after an optimiser step: the image against the
+    oracle, and every gradient (upstream zeroed at flagged pixels) against the
+    oracle's adjoint of the same raw arrays, which carries the 1/|q| factor
+    and the projection onto the tangent of the unit sphere."""
+    print(f"[raw quaternions] tiny seed {seed}", flush=True)
+    scene = sg.raw_quaternion_norms(sg.tiny_scene(seed=seed), seed=30 + seed, lo=0.3, hi=3.0)
+    for k in ("quat_l", "quat_r"):
+        nrm = np.linalg.norm(scene.g4[k].astype(np.float64), axis=0)
+        assert nrm.min() < 0.5 and nrm.max() > 2.0
+    v = scene.views[0]
+    ref = oracle.render(scene, v)
+    _, _, _, h = _render(h4d, scene, [v])
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+    dl = [mask_flagged(sg.upstream_grads([v], seed=40 + seed)[0], ref["amb"])]
+    gr3, gr4 = _grads_gpu(h4d, scene, [v], dl)
+    r3, r4 = oracle.render_bwd(scene, [v], dl)
+    _check_grads(scene, gr3, gr4, r3, r4, np.zeros(scene.n3 + scene.n4, bool))
+    # the quaternion gradients are tangent to the sphere at q: <q, dL/dq> = 0
+    for gr, keys in ((gr4, ("quat_l", "quat_r")), (gr3, ("quat",))):
+        for k in keys:
+            g = gr[k].cpu().numpy().astype(np.float64)
+            q = (scene.g4 if gr is gr4 else scene.g3)[k].astype(np.float64)
+            dot = np.abs((g * q).sum(0))
+            assert dot.max() <= 1e-5 * np.abs(g).max() * np.abs(q).max(), k
