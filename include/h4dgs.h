@@ -13,10 +13,12 @@
  *  - All parameter, image and gradient arrays are DEVICE pointers to float32,
  *    structure-of-arrays, component-major: component c of Gaussian i is at
  *    a[c * n + i].  Arrays marked "host" are host memory.
- *  - The caller owns every buffer.  The library never allocates device memory:
- *    it reports the sizes it needs (h4dgs_workspace_size) and works inside the
- *    caller's `state` and `scratch` buffers.  Device buffers must be 256-byte
- *    aligned (any hipMalloc / PyTorch allocation is).
+ *  - The caller owns every buffer.  No call allocates device memory: each
+ *    reports the sizes it needs (h4dgs_workspace_size) and works inside the
+ *    caller's `state` and `scratch` buffers, except h4dgs_render_infer_noalloc,
+ *    which works inside a fixed workspace of the library's device code (a
+ *    static array loaded with it).  Device buffers must be 256-byte aligned
+ *    (any hipMalloc / PyTorch allocation is).
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
  *    and returns before it completes, except where a call says it synchronises.
  *  - Errors are return codes; nothing is thrown across the ABI.
@@ -146,6 +148,30 @@ h4d_status h4dgs_render_fwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, 
 h4d_status h4dgs_render_infer(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
                               int32_t n_views, const h4d_config *cfg, float *const *images, void *state,
                               size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Allocation-free inference render, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and images as h4dgs_render_infer, but the
+ * call's state and scratch live in a fixed workspace of H4DGS_NOALLOC_BYTES
+ * inside the library: one copy per GPU, allocated when the library's device
+ * code is loaded on that GPU and held until the process ends.  The call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * status_out (device, may be NULL): receives two uint64 words, the status
+ * flags (bit 0 = the (Gaussian, tile) pairs exceeded cfg->pair_capacity; the
+ * images are then incomplete) and the number of pairs the call needed;
+ * written on `stream` after the render.
+ * Errors: H4D_ERR_CAPACITY (on the host, before anything is enqueued) when
+ * the call's workspace (h4dgs_workspace_size: state rounded up to 256 bytes
+ * plus the forward's part of scratch) exceeds H4DGS_NOALLOC_BYTES; the
+ * arguments are checked as for h4dgs_render_infer.
+ * Every call on one GPU shares that GPU's workspace and leaves its contents
+ * behind (each call clears what it needs cleared): calls that overlap on one
+ * GPU (other streams, other host threads) race and give undefined images;
+ * serialise them.  No backward can follow (there is no state handle). */
+#define H4DGS_NOALLOC_BYTES ((size_t)256 << 20)
+h4d_status h4dgs_render_infer_noalloc(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
+                                      int32_t n_views, const h4d_config *cfg, float *const *images,
+                                      uint64_t *status_out, void *stream);
 
 /* Backward (the training step's fast adjoint, which Sec. 5.2 adopts from
  * prior work without describing it): the exact adjoint of render_fwd

@@ -28,8 +28,10 @@ EXPORTS = (
     "h4dgs_render_fwd", "h4dgs_render_infer", "h4dgs_render_bwd", "h4dgs_check", "h4dgs_rasterize_splats",
     "h4dgs_convert_scratch_bytes", "h4dgs_convert_static", "h4dgs_adam", "h4dgs_l1_loss_grad",
     "h4dgs_profile", "h4dgs_profile_read", "h4dgs_stats", "h4dgs_stats_read", "h4dgs_radix_hist_words",
-    "h4dgs_radix_pass_check",
+    "h4dgs_radix_pass_check", "h4dgs_render_infer_noalloc",
 )
+
+NOALLOC_BYTES = 256 << 20  # H4DGS_NOALLOC_BYTES
 
 STAGES = ("preprocess", "depth_sort", "binning", "blend_fwd", "blend_bwd", "preprocess_bwd", "adam", "loss")
 
@@ -82,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.h4dgs_workspace_size.argtypes = [vp, i32, i32, vp, i32, vp, P(sz), P(sz)]
     L.h4dgs_render_fwd.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp, sz, vp]
     L.h4dgs_render_infer.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp, sz, vp]
+    L.h4dgs_render_infer_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
     L.h4dgs_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp, sz, vp, vp, vp]
     L.h4dgs_check.argtypes = [vp, vp, sz, P(i64), vp]
     L.h4dgs_rasterize_splats.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp,

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,13 @@ struct h4d_ctx {
         for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
+
+// Workspace of h4dgs_render_infer_noalloc (state and scratch of one call), for
+// callers that cannot allocate.  Every GPU the library runs on holds its own
+// copy at its own address until the process ends.  Host code never uses this
+// name as an address: it asks hipGetSymbolAddress for the current device's
+// copy once and passes that pointer on.
+static __device__ __align__(256) unsigned char noalloc_workspace[H4DGS_NOALLOC_BYTES];
 
 namespace h4d {
 namespace {
@@ -490,6 +498,29 @@ bool bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     return true;
 }
 
+constexpr int kNoallocDevices = 64;
+std::mutex noalloc_mu;
+char* noalloc_base[kNoallocDevices] = {};
+
+// The current device's copy of noalloc_workspace, looked up on the first call
+// on that device (with it current) and kept.
+h4d_status noalloc_workspace_on_device(h4d_ctx* ctx, char** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_check(ctx, "render_infer_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kNoallocDevices)
+        return fail(ctx, H4D_ERR_UNSUPPORTED, "render_infer_noalloc: device %d beyond %d", dev, kNoallocDevices);
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_base[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_workspace));
+        if (e != hipSuccess || !p)
+            return fail(ctx, H4D_ERR_HIP, "render_infer_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        noalloc_base[dev] = static_cast<char*>(p);
+    }
+    *out = noalloc_base[dev];
+    return H4D_OK;
+}
+
 }  // namespace
 }  // namespace h4d
 
@@ -581,6 +612,37 @@ h4d_status h4dgs_render_infer(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4
                               size_t state_bytes, void* scratch, size_t scratch_bytes, void* stream) {
     return render_forward(ctx, g3, g4, views, n_views, cfg, images, state, state_bytes, scratch, scratch_bytes,
                           stream, false);
+}
+
+h4d_status h4dgs_render_infer_noalloc(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
+                                      int32_t n_views, const h4d_config* cfg, float* const* images,
+                                      uint64_t* status_out, void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    h4d_status s;
+    if ((s = check_sets(ctx, g3, g4)) != H4D_OK) return s;
+    if ((s = check_config(ctx, cfg)) != H4D_OK) return s;
+    if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
+    if ((s = check_pass_size(ctx, cfg, (int64_t)g3->n + g4->n, n_views)) != H4D_OK) return s;
+    const Layout L = make_layout(g3->n + g4->n, views, n_views, cfg);
+    const size_t state_room = align_up(L.state_bytes);
+    const size_t limit = (size_t)H4DGS_NOALLOC_BYTES;
+    if (state_room > limit || L.fwd_bytes > limit - state_room)
+        return fail(ctx, H4D_ERR_CAPACITY,
+                    "render_infer_noalloc: the call needs %zu bytes of workspace (state %zu + scratch %zu), "
+                    "the fixed workspace holds %zu",
+                    state_room + L.fwd_bytes, state_room, L.fwd_bytes, limit);
+    char* base = nullptr;
+    if ((s = noalloc_workspace_on_device(ctx, &base)) != H4D_OK) return s;
+    if ((s = render_forward(ctx, g3, g4, views, n_views, cfg, images, base, state_room, base + state_room,
+                            limit - state_room, stream, false)) != H4D_OK)
+        return s;
+    if (status_out) {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (hipMemcpyAsync(status_out, base + L.st_status, 2 * sizeof(uint64_t), hipMemcpyDeviceToDevice, st) !=
+            hipSuccess)
+            return hip_check(ctx, "render_infer_noalloc: status copy");
+    }
+    return H4D_OK;
 }
 
 h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,

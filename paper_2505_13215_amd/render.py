@@ -252,6 +252,31 @@ def render(rast: Rasterizer, g3: dict, g4: dict, views) -> tuple:
 
 # -- other entry points ------------------------------------------------------------
 
+def render_infer_noalloc(rast: Rasterizer, g3: dict, g4: dict, views, images=None, status=None):
+    """Inference render whose state and scratch live in the library's fixed
+    per-GPU workspace (``h4dgs_render_infer_noalloc``): the caller passes only
+    inputs and outputs.  ``images`` (one [3, H, W] float32 tensor per view)
+    and ``status`` (a 2-element int64 tensor receiving the status flags and the
+    pair count) are allocated here when not given.  Returns (images, status)."""
+    s3, s4 = g3_struct(g3), g4_struct(g4)
+    va = L.view_array(views)
+    if images is None:
+        images = [torch.empty((3, v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
+    for im, v in zip(images, views):
+        if tuple(im.shape) != (3, v.height, v.width):
+            raise ValueError(f"image shape {tuple(im.shape)} does not match the view's {(3, v.height, v.width)}")
+        _chk(im, "image")
+    if status is None:
+        status = torch.empty(2, dtype=torch.int64, device="cuda")
+    if status.dtype != torch.int64 or status.numel() < 2 or not status.is_cuda:
+        raise ValueError("status: expected at least 2 int64 CUDA elements")
+    cfg = rast.config()
+    imgs = L.ptr_array([im.data_ptr() for im in images])
+    rast.ctx.check(rast.ctx.L.h4dgs_render_infer_noalloc(rast.ctx.h, C.byref(s3), C.byref(s4), va, len(views),
+                                                         C.byref(cfg), imgs, _ptr(status), _stream()))
+    return images, status
+
+
 def rasterize_splats(rast: Rasterizer, sp: dict, width: int, height: int, bg=(0.0, 0.0, 0.0)):
     """Binning, sorting and blending of given screen-space splats.  Returns
     (image[3,H,W], T[H,W], ids, ranges[tiles, 2]); tile t's depth-ordered list
