@@ -73,24 +73,99 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, views, adam_scalars: int) -> dict:
-    """The FP64 oracle, as it stands, on a bounded sample: forward + backward of
-    the given views and one Adam step over the same number of scalars."""
+def cpu_baseline(scene, views, adam_scalars: int, reps: int = 3) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the timed step:
+    ``reps`` runs over the given views, each timing the forward and the
+    backward of every view and one Adam step over the step's scalars; the
+    medians over the runs give the per-step rate (one view, its forward, its
+    backward and one Adam step per step)."""
     import oracle
     oracle.build()
-    t0 = time.perf_counter()
-    for v in views:
-        ref = oracle.render(scene, v)
-        dl = np.sign(ref["img"] - 0.5).astype(np.float32) / (3 * v.width * v.height)
-        oracle.render_bwd(scene, [v], [dl])
-    n = adam_scalars
-    z = np.zeros(n, np.float32)
-    oracle.adam(z, z, z, z, 1e-3, 0.9, 0.999, 1e-8, 1)
-    dt = time.perf_counter() - t0
+    fwd, bwd, adam = [], [], []
+    z = np.zeros(adam_scalars, np.float32)
+    for _ in range(reps):
+        tf = tb = 0.0
+        for v in views:
+            t0 = time.perf_counter()
+            ref = oracle.render(scene, v)
+            t1 = time.perf_counter()
+            dl = np.sign(ref["img"] - 0.5).astype(np.float32) / (3 * v.width * v.height)
+            t2 = time.perf_counter()
+            oracle.render_bwd(scene, [v], [dl])
+            t3 = time.perf_counter()
+            tf += t1 - t0
+            tb += t3 - t2
+        t0 = time.perf_counter()
+        oracle.adam(z, z, z, z, 1e-3, 0.9, 0.999, 1e-8, 1)
+        adam.append(time.perf_counter() - t0)
+        fwd.append(tf)
+        bwd.append(tb)
+    f, b, a = float(np.median(fwd)), float(np.median(bwd)), float(np.median(adam))
+    nv = len(views)
     pix = sum(v.width * v.height for v in views)
-    return {"value": pix / dt / 1e6, "unit": "Mpix/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{len(views)} view(s) of 1352x1014 of the 250k-Gaussian scene: FP64 forward + backward "
-                      f"+ one Adam step over {n} scalars, {dt:.1f} s"}
+    step = f + b + nv * a
+    return {"value": pix / step / 1e6, "unit": "Mpix/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "fwd_s_per_view": round(f / nv, 3), "bwd_s_per_view": round(b / nv, 3), "adam_s": round(a, 3),
+            "fwd_mpix_s": round(pix / f / 1e6, 4), "bwd_mpix_s": round(pix / b / 1e6, 4),
+            "sample": f"{nv} view(s) of 1352x1014 of the 250k-Gaussian scene, median of {reps} runs: FP64 "
+                      f"forward, backward and one Adam step over {adam_scalars} scalars per view"}
+
+
+# Algorithmic HBM bytes of a step (the fixed yardstick: what the method must
+# move, not what this implementation moves).
+B_PARAM3, B_PARAM4 = 236, 260  # parameter row of a 3D / 4D Gaussian
+B_ONSCREEN = 48 + 48 + 36 + 36  # screen record written + read back, 2D gradient accumulator written + read
+B_PAIR = 16                     # list entry: emission write (depth + id) and one ordering read
+B_TRAVERSED = 40 + 40 + 36      # entry read by the forward, by the adjoint, gradient written
+B_PIXEL = 64                    # colour, T, n_contrib written; target, dL/dC, adjoint state read
+B_ADAM = 28                     # per scalar: p, g, m, v read; p, m, v written
+
+
+def alg_bytes(n3: int, n4: int, param_passes: int, cnt: dict, pixels: int) -> dict:
+    """param_passes: times the parameter rows are read for the rendering of
+    one step (once per view when views are rendered one after another, once
+    per step when batched); each step then reads them again in the adjoint and
+    writes an equal gradient."""
+    params = (B_PARAM3 * n3 + B_PARAM4 * n4) * (param_passes + 2)
+    parts = {"params": params, "onscreen": B_ONSCREEN * cnt["onscreen"], "pairs": B_PAIR * cnt["list_entries"],
+             "traversed": B_TRAVERSED * cnt["traversed"], "pixels": B_PIXEL * pixels}
+    parts["total"] = sum(parts.values())
+    return parts
+
+
+def hbm_entry(bytes_alg: float, seconds: float) -> dict:
+    gbs = bytes_alg / seconds / 1e9
+    return {"bytes_alg": int(bytes_alg), "achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
+def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
+    """GB/s (read + write) of a plain device copy on this GPU, median of reps."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    del src, dst
+    return round(2 * (mib << 20) / float(np.median(ts)) / 1e9, 1)
+
+
+def count_step(rast, fn) -> dict:
+    """Workload counts of one call of fn (counting variants of the kernels,
+    outside any timed region)."""
+    rast.stats(True)
+    mode = rast.check_mode
+    rast.check_mode = "eager"
+    fn()
+    c = rast.stats_read()
+    rast.stats(False)
+    rast.check_mode = mode
+    return c
 
 
 def convert_leg(h4d, torch, rast, g3, g4, reps: int = 5) -> dict:
@@ -210,9 +285,21 @@ def training_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
     dt = _time_steps(torch, step, steps, warmup)
     rast.verify()
     mpix = 4 * W * H / 1e6
+
+    def counted():
+        views = sched[0]
+        h = rast.forward(g3, g4, views)
+        h4d.l1_loss_grad(rast, h.images, targets, views, dls, None)
+        rast.backward(h, g3, g4, dls, out=(gr3, gr4))
+
+    cnt = count_step(rast, counted)
+    n3, n4 = int(g3["opacity"].numel()), int(g4["opacity"].numel())
+    n_scalars = sum(p.numel() for p in params)
+    alg = alg_bytes(n3, n4, 1, cnt, 4 * W * H)
     return {"workload": "training_2M_2704x2028_4_views", "gaussians": n_gauss, "ms_per_step": round(dt * 1e3, 3),
             "mpix_s": round(mpix / dt, 2), "views_per_step": 4, "step": "fwd+L1+bwd+Adam, batched",
-            "pairs_per_step": rast.last_pairs}
+            "pairs_per_step": rast.last_pairs, "counts": {k: int(v) for k, v in cnt.items()},
+            "hbm": hbm_entry(alg["total"] + B_ADAM * n_scalars, dt)}
 
 
 def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
@@ -274,6 +361,27 @@ def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
     step.verify()
     out["batched_graph"] = {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
     out["speedup"] = round(out["single_view"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3)
+    del step
+    torch.cuda.empty_cache()
+    # workload counts of the call (the same lists either way) and the share of
+    # the HBM roofline of each form: the batched form reads the parameters once
+    # per call, the views one after another once per view
+    crast = h4d.Rasterizer(batched=True)
+    dls = [torch.empty_like(t) for t in targets]
+
+    def counted():
+        h = crast.forward(g3, g4, views)
+        h4d.l1_loss_grad(crast, h.images, targets, views, dls, None)
+        crast.backward(h, g3, g4, dls, out=(gr3, gr4))
+
+    cnt = count_step(crast, counted)
+    n3, n4 = int(g3["opacity"].numel()), int(g4["opacity"].numel())
+    pix = int(round(mpix * 1e6))
+    a_single = alg_bytes(n3, n4, len(views), cnt, pix)
+    a_batched = alg_bytes(n3, n4, 1, cnt, pix)
+    out["counts"] = {k: int(v) for k, v in cnt.items()}
+    out["hbm"] = {"single_view": hbm_entry(a_single["total"], out["single_view"]["ms_per_step"] * 1e-3),
+                  "batched_graph": hbm_entry(a_batched["total"], out["batched_graph"]["ms_per_step"] * 1e-3)}
     return out
 
 
@@ -286,7 +394,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--gaussians", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=16)
+    ap.add_argument("--cpu-views", type=int, default=4)
     ap.add_argument("--stats-views", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs single-view leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the hybrid-ratio and 2M training legs")
@@ -429,7 +537,7 @@ def main():
     log(f"counting blend evaluations on {args.stats_views} views")
     rast.stats(True)
     rast.check_mode = "eager"
-    cnt = dict(fwd_eval=0, fwd_blend=0, bwd_eval=0, bwd_blend=0)
+    cnt = dict(fwd_eval=0, fwd_blend=0, bwd_eval=0, bwd_blend=0, list_entries=0, traversed=0, onscreen=0)
     nst = max(1, min(args.stats_views, args.steps))
     for i in range(args.warmup, args.warmup + nst):
         v = sched[i][0]
@@ -451,6 +559,16 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": recorded_traffic(kname), "kernel": kname,
                 "kernel_ms": round(dom_ms, 4), "flops_per_launch": dom_flops}
+
+    # share of the HBM roofline: algorithmic bytes of a step (counted per view
+    # above) over its measured time, against the published 8 TB/s
+    alg = alg_bytes(scene.n3, scene.n4, 1, cnt, W * H)
+    copy_gbs = copy_bandwidth(torch)
+    hbm = {"yardstick_bytes_per_step": {k: int(v) for k, v in alg.items()},
+           "fwd_bwd_step": hbm_entry(alg["total"], dt_fb / args.steps),
+           "train_step_with_adam": hbm_entry(alg["total"] + B_ADAM * n_scalars, dt / args.steps),
+           "peak_gbs": PEAK_HBM_GBS, "copy_kernel_gbs": copy_gbs}
+    log(f"HBM: {hbm}")
 
     # static conversion (Sec. 4.1-4.2): on the workload's sets, and on 500k all-4D
     # Gaussians of which half are static
@@ -504,6 +622,7 @@ def main():
                    "tile": args.tile, "chunk": args.chunk, "step": "fwd+L1+bwd+Adam",
                    "parallelism": "single_gpu"},
         "roofline": roofline,
+        "hbm": hbm,
         "cpu_baseline": cpu,
         "fwd_bwd_only": fwd_bwd,
         "inference": inference,

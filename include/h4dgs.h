@@ -292,10 +292,15 @@ h4d_status h4dgs_profile_read(h4d_ctx *ctx, double *ms, int64_t *launches);
 
 /* enable != 0: later render calls use counting variants of the blending
  * kernels (slower; for measurement only).  h4dgs_stats_read synchronises
- * `stream` and reads, from the state the last forward/backward used:
+ * `stream` and reads, from the state the last forward/backward used, seven
+ * counts (out: host array of at least 7):
  * out[0] (pixel, splat) evaluations of the forward blend (pixel inside the
  * splat's square, before the pixel stopped), out[1] blended ones,
- * out[2] evaluations of the backward blend, out[3] blended ones. */
+ * out[2] evaluations of the backward blend, out[3] blended ones,
+ * out[4] entries of the forward's tile lists ((Gaussian, tile) pairs),
+ * out[5] list entries the blending traverses (each tile's list up to its last
+ * contributor, summed over tiles), out[6] (Gaussian, view) records whose pixel
+ * square meets the image.  out[4..6] are summed over the forward's views. */
 h4d_status h4dgs_stats(h4d_ctx *ctx, int32_t enable);
 h4d_status h4dgs_stats_read(h4d_ctx *ctx, const void *state, size_t state_bytes, int64_t *out, void *stream);
 

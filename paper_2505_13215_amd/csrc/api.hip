@@ -418,6 +418,8 @@ bool bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
         }
     }
     // dk / dv now hold the depth-ordered keys and ids
+    if (unsigned long long* sc = keep ? stat_counters(c, state, L) : nullptr)
+        launch_count_onscreen(recs + (size_t)P.v0 * N, (size_t)n, sc + 6, st);
     Status* status = at<Status>(state, L.st_status);
     unsigned long long* pair_base = at<unsigned long long>(state, L.st_pair_base);
     uint32_t* ids = at<uint32_t>(state, L.st_ids);
@@ -926,7 +928,7 @@ h4d_status h4dgs_stats_read(h4d_ctx* ctx, const void* state, size_t state_bytes,
     if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return hip_check(ctx, "stats_read");
     Status hs;
     if (hipMemcpy(&hs, state, sizeof(Status), hipMemcpyDeviceToHost) != hipSuccess) return hip_check(ctx, "stats_read");
-    for (int k = 0; k < 4; ++k) out[k] = (int64_t)hs.pad[k];
+    for (int k = 0; k < 7; ++k) out[k] = (int64_t)hs.pad[k];
     return H4D_OK;
 }
 

@@ -82,7 +82,10 @@ static_assert(sizeof(Rec) == 64, "record is 64 bytes");
 struct Status {
     unsigned long long flags;        // bit 0: pair capacity overflow
     unsigned long long pairs_needed; // sum over views of the pairs the call needed
-    unsigned long long pad[6];
+    // counters of the counting variants (h4dgs_stats): blend evaluations and
+    // blends of the forward and the adjoint, tile-list entries, traversed
+    // entries (each tile's last contributor) and on-screen records
+    unsigned long long pad[14];
 };
 
 constexpr unsigned long long kFlagOverflow = 1ull;

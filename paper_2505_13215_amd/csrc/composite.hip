@@ -275,6 +275,7 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
 #pragma unroll
     for (int k = 0; k < PPL; ++k) lane_last = max(lane_last, last[k]);
     const uint32_t wave_last = wave_max_u32(lane_last);
+    uint32_t tile_last = wave_last;
     if (NT == 64) {
         if (threadIdx.x == 0) {
             tcost[gt] = wave_last;
@@ -285,10 +286,15 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
         __syncthreads();
         if (__lane_id() == 0) atomicMax(&s_cost, wave_last);
         __syncthreads();
+        tile_last = s_cost;
         if (threadIdx.x == 0) {
             tcost[gt] = s_cost;
             atomicAdd(&thist[cost_bucket(s_cost)], 1u);
         }
+    }
+    if (STATS && threadIdx.x == 0) {
+        atomicAdd(&counters[4], (unsigned long long)(end - start));
+        atomicAdd(&counters[5], (unsigned long long)tile_last);
     }
     }
     if (STATS) {

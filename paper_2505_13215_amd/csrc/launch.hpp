@@ -25,6 +25,7 @@ void launch_init_state(const ViewTableIn& in, ViewParams* views, Status* status,
                        unsigned long long* ranges, size_t n_range_words, hipStream_t st);
 // Records of views [v0, v0 + nv) (recs: all views, [view][N]); depth keys and
 // ids of view v0 + r at dkeys/dvals + r * N.
+void launch_count_onscreen(const Rec* recs, size_t n, unsigned long long* counter, hipStream_t st);
 void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,
                        uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,

@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(256) k_init_state(ViewTableIn in, ViewParams* 
                                                     unsigned long long* ranges, size_t n_range_words) {
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) write_views(in, views);
-        if (threadIdx.x < 8) (&status->flags)[threadIdx.x] = 0ull;
+        if (threadIdx.x < sizeof(Status) / 8) (&status->flags)[threadIdx.x] = 0ull;
         for (int v = threadIdx.x; v <= in.n; v += blockDim.x) pair_base[v] = 0ull;
     }
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_range_words;

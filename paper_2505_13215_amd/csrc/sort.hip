@@ -499,6 +499,21 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// Counting variant only: records of the views [v0, v0 + nv) whose pixel square
+// meets the image (the on-screen (Gaussian, view) pairs), added to *counter.
+__global__ void __launch_bounds__(256) k_count_onscreen(const Rec* __restrict__ recs, size_t n,
+                                                        unsigned long long* counter) {
+    const size_t j = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const bool on = j < n && recs[j].d.w != 0u;
+    const unsigned long long c = (unsigned long long)__popcll(__ballot(on));
+    if (__lane_id() == 0 && c) atomicAdd(counter, c);
+}
+
+void launch_count_onscreen(const Rec* recs, size_t n, unsigned long long* counter, hipStream_t st) {
+    if (n == 0) return;
+    k_count_onscreen<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(recs, n, counter);
+}
+
 // offsets[j] = partials[j / 256] (scanned) + this workgroup's exclusive scan;
 // run_start as in k_scan_down.
 __global__ void __launch_bounds__(256) k_coarse_down(const uint32_t* __restrict__ cnt, int n,

@@ -205,10 +205,11 @@ class Rasterizer:
         self.ctx.check(self.ctx.L.h4dgs_stats(self.ctx.h, int(bool(enable))))
 
     def stats_read(self) -> dict:
-        out = (C.c_int64 * 4)()
+        out = (C.c_int64 * 7)()
         self.ctx.check(self.ctx.L.h4dgs_stats_read(self.ctx.h, _ptr(self._state), self._state.numel(), out,
                                                    _stream()))
-        return dict(fwd_eval=int(out[0]), fwd_blend=int(out[1]), bwd_eval=int(out[2]), bwd_blend=int(out[3]))
+        return dict(fwd_eval=int(out[0]), fwd_blend=int(out[1]), bwd_eval=int(out[2]), bwd_blend=int(out[3]),
+                    list_entries=int(out[4]), traversed=int(out[5]), onscreen=int(out[6]))
 
 
 def l1_loss_grad(rast: Rasterizer, images, targets, views, dl_out, loss: torch.Tensor = None):

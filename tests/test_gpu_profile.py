@@ -64,3 +64,48 @@ def test_profile_levels_report_the_right_stages(h4d, batched):
     for k in ("preprocess", "depth_sort", "binning", "blend_fwd", "blend_bwd", "preprocess_bwd"):
         assert p1[k][1] >= 1 and p1[k][0] > 0.0, (k, p1[k])
     assert all(n == 0 for _, n in p0.values())
+
+
+def test_counting_mode_counts_match_the_oracle(h4d):
+    """The counting variants' workload counts against the oracle's definition
+    on a scene with no guard-band pixel (every blend decision agrees): blends
+    (the sum of per-pixel blend counts, equal in the adjoint), on-screen
+    records (visible Gaussians whose pixel square meets the image), tile-list
+    entries (without culling: every (Gaussian, tile) pair whose square meets
+    the tile) and traversed entries (per tile, the list position of the last
+    splat any of its pixels blends)."""
+    import numpy as np
+    import oracle
+    scene = sg.tiny_scene(seed=18, width=150, height=100)
+    v = scene.views[0]
+    ref = oracle.render(scene, v)
+    assert not ref["amb"].any()
+    tile = 16
+    rast = h4d.Rasterizer(tile=tile, chunk=64, pair_capacity=1 << 20, cull=False)
+    g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+    rast.stats(True)
+    h = rast.forward(g3, g4, [v])
+    rast.backward(h, g3, g4, [torch.ones_like(h.images[0])])
+    c = rast.stats_read()
+    rast.stats(False)
+    pr = oracle.project(scene, v)
+    on = (pr["visible"] > 0) & (pr["x0"] <= pr["x1"]) & (pr["y0"] <= pr["y1"])
+    assert c["onscreen"] == int(on.sum())
+    assert c["fwd_blend"] == int(ref["nblend"].sum()) == c["bwd_blend"]
+    tiles_x, tiles_y = (v.width + tile - 1) // tile, (v.height + tile - 1) // tile
+    lists = [[] for _ in range(tiles_x * tiles_y)]
+    order = np.lexsort((np.arange(on.size), pr["key"]))  # by depth key, then id
+    for g in order[on[order]]:
+        for ty in range(int(pr["y0"][g]) // tile, int(pr["y1"][g]) // tile + 1):
+            for tx in range(int(pr["x0"][g]) // tile, int(pr["x1"][g]) // tile + 1):
+                lists[ty * tiles_x + tx].append(int(g))
+    assert c["list_entries"] == sum(len(lst) for lst in lists)
+    ys, xs = np.mgrid[0:v.height, 0:v.width]
+    xs, ys = xs.ravel().astype(np.int32), ys.ravel().astype(np.int32)
+    last = np.zeros(len(lists), np.int64)
+    pos = [{g: i for i, g in enumerate(lst)} for lst in lists]
+    for x, y, bl in zip(xs, ys, oracle.blended_at(scene, v, xs, ys, cap=1024)):
+        if bl:
+            t = (y // tile) * tiles_x + x // tile
+            last[t] = max(last[t], pos[t][bl[-1][0]] + 1)
+    assert c["traversed"] == int(last.sum())
