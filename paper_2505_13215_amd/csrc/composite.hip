@@ -404,15 +404,16 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     unsigned long long n_eval = 0, n_blend = 0;
     // after wave_sum9, lanes 0, 16, 32, 48 hold (in h0 and h1) the components
     // 0 2 1 3 and 4 6 5 7 of g2, lane 0 (in h2) component 8; their constant
-    // factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1
+    // factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1.  The
+    // centre and conic sums (h0, and h1 in row 0) also take the splat's
+    // opacity (their per-pixel terms are summed without it): h1's factor is
+    // m1 * opacity + c1.
     const int row = lane >> 4;
     const bool lead = (lane & 15) == 0;
     const int comp0 = ((row & 1) << 1) | (row >> 1);
     const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
-    const float fac1 = comp0 == 0 ? -0.5f : 1.0f;
-    float* const g2c0 = g2 + comp0;
-    float* const g2c1 = g2 + 4 + comp0;
-    float* const g2c8 = g2 + 8;
+    const float m1 = comp0 == 0 ? -0.5f : 0.0f, c1 = comp0 == 0 ? 0.0f : 1.0f;
+    const int off0 = comp0, off1 = 4 + comp0;
     const int tid = (int)threadIdx.x;
     // this thread's first list slot of the next chunk, loaded a chunk ahead so
     // that staging waits for the record gather only
@@ -429,16 +430,18 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         const uint32_t rel0 = (uint32_t)(base - start);
         // entries past this wave's last contributor need no work
         const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
-        // the adjoint of one blending step with splat j
-        auto step = [&](int j, auto rows_tag) {
+        // the adjoint of one blending step with splat j; gid: its splat id
+        auto step = [&](int j, uint32_t gid, auto rows_tag) {
             constexpr bool RI = decltype(rows_tag)::value;
             const Splat s = to_splat(s_sp[j]);
             const ColTerm c = eval_col(s, px, pxc);
             const float twoqadx = 2.0f * c.qadx, qbdx = c.bx, dx2 = c.dx * c.dx, twoqc = 2.0f * s.qc;
             // per-splat sums of this lane's pixels: dL/dopacity, dL/drgb, and the
-            // moments sum d, sum d dy, sum d dy^2 of d = dL/dpower (the lane's pixels
-            // share dx, so the centre and conic terms follow from them below)
-            float e5 = 0.f, e6 = 0.f, e7 = 0.f, e8 = 0.f, sd = 0.f, sdy = 0.f, syy = 0.f;
+            // moments sum q, sum q dy, sum q dy^2 of q = dL/dalpha * exp2(power),
+            // which is dL/dpower (natural log domain) divided by the splat's opacity
+            // (the lane's pixels share dx, so the centre and conic terms follow
+            // from them below)
+            float e5 = 0.f, e6 = 0.f, e7 = 0.f, e8 = 0.f, sdy = 0.f, syy = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
@@ -465,21 +468,21 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 e6 = __builtin_fmaf(G0[k], w, e6);
                 e7 = __builtin_fmaf(G1[k], w, e7);
                 e8 = __builtin_fmaf(G2[k], w, e8);
-                const float das = (ok && !clamped) ? da : 0.0f;  // no gradient through the 0.99 clamp
-                e5 = __builtin_fmaf(das, Gk, e5);
-                const float dpn = das * alpha;  // dL/dpower (natural log domain)
-                const float dpy = dpn * dy;
-                sd += dpn;
-                sdy += dpy;
-                syy = __builtin_fmaf(dpy, dy, syy);
+                // no gradient through the 0.99 clamp (da is finite: alpha <= 0.99)
+                const float gz = (ok && !clamped) ? Gk : 0.0f;
+                const float q = da * gz;  // dL/dopacity share; dL/dpower = opacity * q
+                const float qdy = q * dy;
+                e5 += q;
+                sdy += qdy;
+                syy = __builtin_fmaf(qdy, dy, syy);
                 T[k] = next_T(T[k], a);  // unchanged where a = 0
             }
-            // conic and centre terms without their constant factors (applied after
-            // the reduction): sum d (2 qa dx + qb dy), sum d (qb dx + 2 qc dy),
-            // sum d dx^2, sum d dx dy, sum d dy^2
-            const float e0 = __builtin_fmaf(sd, twoqadx, s.qb * sdy);
-            const float e1 = __builtin_fmaf(sd, qbdx, twoqc * sdy);
-            const float e2 = dx2 * sd, e3 = c.dx * sdy, e4 = syy;
+            // conic and centre terms without their constant factors and the
+            // opacity (applied after the reduction): sum q (2 qa dx + qb dy),
+            // sum q (qb dx + 2 qc dy), sum q dx^2, sum q dx dy, sum q dy^2
+            const float e0 = __builtin_fmaf(e5, twoqadx, s.qb * sdy);
+            const float e1 = __builtin_fmaf(e5, qbdx, twoqc * sdy);
+            const float e2 = dx2 * e5, e3 = c.dx * sdy, e4 = syy;
             if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
                 float h0, h1, h2;
                 wave_sum9(e0, e1, e2, e3, e4, e5, e6, e7, e8, h0, h1, h2);
@@ -487,19 +490,21 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 // results here, before the lane-divergent atomics below
                 asm volatile("" ::"v"(h0), "v"(h1), "v"(h2));
                 if (lead) {
-                    const size_t o = (size_t)s_sp[j].gid * kG2Stride;
-                    atomicAdd(&g2c0[o], h0 * fac0);
-                    atomicAdd(&g2c1[o], h1 * fac1);
-                    if (row == 0) atomicAdd(&g2c8[o], h2);
+                    float* const rec = g2 + (size_t)gid * kG2Stride;
+                    atomicAdd(rec + off0, h0 * (fac0 * s.op));
+                    atomicAdd(rec + off1, h1 * __builtin_fmaf(m1, s.op, c1));
+                    if (row == 0) atomicAdd(rec + 8, h2);
                 }
             }
         };
         // splats whose square holds all of the tile's rows take the step without
-        // the row test
+        // the row test; the group's splat ids sit one per lane and reach the
+        // step as wave-uniform values
         for (int g0 = 0; g0 < jend; g0 += 64) {
             const int gn = min(64, jend - g0);
+            const uint32_t gids = s_sp[g0 + min(lane, gn - 1)].gid;
             walk_runs(rows_in_mask(s_sp, g0, gn), gn, [&](int i, auto tag) {
-                step(g0 + i, tag);
+                step(g0 + i, (uint32_t)__builtin_amdgcn_readlane((int)gids, i), tag);
                 return false;
             });
         }
