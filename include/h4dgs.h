@@ -191,6 +191,32 @@ h4d_status h4dgs_render_bwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, 
                             const void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
                             h4d_g3d_mut *grad3, h4d_g4d_mut *grad4, void *stream);
 
+/* Per-Gaussian statistics of a backward call, for the optimiser's
+ * visibility mask and for densification (device arrays of one set's n rows;
+ * any pointer may be NULL):
+ *   grad_norm[n]  += sum, over the call's views in which the Gaussian's pixel
+ *                    square meets the image, of the norm of the loss gradient
+ *                    with respect to its projected centre in normalised device
+ *                    coordinates (the pixel-space gradient times half the
+ *                    image width and height), the statistic 3D Gaussian
+ *                    Splatting densifies by;
+ *   visible[n]    += the number of those views;
+ *   step_visible[n] = 1 if there is at least one such view, else 0. */
+typedef struct {
+    float *grad_norm;
+    float *visible;
+    uint8_t *step_visible;
+} h4d_set_stats;
+
+/* h4dgs_render_bwd (same arguments, same gradients) that also accumulates
+ * the statistics above for the 3D and the 4D set (Sec. 4.3: densification
+ * and pruning run on each set separately). */
+h4d_status h4dgs_render_bwd_stats(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
+                                  int32_t n_views, const h4d_config *cfg, const float *const *dl_dimages,
+                                  const void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
+                                  h4d_g3d_mut *grad3, h4d_g4d_mut *grad4, const h4d_set_stats *stats3,
+                                  const h4d_set_stats *stats4, void *stream);
+
 /* Synchronises `stream`, then reads the status the last render_fwd left in
  * `state`.  Returns H4D_OK or H4D_ERR_CAPACITY; *pairs_needed (host, may be
  * NULL) receives the number of pairs the call needed. */
@@ -228,6 +254,70 @@ h4d_status h4dgs_convert_static(h4d_ctx *ctx, const h4d_g4d *in4, const h4d_g3d 
                                 h4d_g4d_mut *out4, h4d_g3d_mut *out3, int32_t *perm, int32_t *n4_out,
                                 int32_t *n3_out, void *scratch, size_t scratch_bytes, void *stream);
 
+/* Adaptive densification and pruning, run on the 3D and the 4D set
+ * separately with limits of their own (Sec. 4.3 adopts the clone / split /
+ * prune scheme of 3D Gaussian Splatting and applies it to each set; the paper
+ * uses no opacity reset).  Per row i of a set, with g = stats->grad_norm[i],
+ * c = stats->visible[i] and L = the largest of its three spatial log-scales:
+ *   selected  iff c > 0 and (double)g >= (double)grad_threshold * (double)c;
+ *   cloned    iff selected and L <= log_dense_scale;
+ *   split     iff selected and L >  log_dense_scale;
+ *   a row is pruned iff (double)opacity_logit < opacity_logit_min or
+ *   L > log_max_scale (all compared in double, exactly).
+ * Output rows (out3 / out4, row stride = their n, the capacity, which must be
+ * at least max(2, split_n) times the input count): the rows that are not
+ * split and not pruned, in order; then the clones (exact copies) that are not
+ * pruned, in order; then for k = 0 .. split_n - 1 the k-th child of every split
+ * row, in order, unless pruned.  A child copies its parent except for its
+ * log-scales, fl32((double)ls - log_shrink) for every component (the prune
+ * test uses these), and its centre: the parent's plus the parent's rotation
+ * applied to exp(ls) * z, with z the row's k-th draw from noise (standard
+ * normal, caller-drawn): 3D: noise3[split_n][3][n3], rotation R(q) (Eq. 2),
+ * centre = mean; 4D: noise4[split_n][4][n4], rotation R_l R_r (Eq. 4) on
+ * (x, y, z, t), centre = (mean, mean_t), so children spread in space and
+ * time.  src3 / src4 (device int32, capacity rows): the source row of each
+ * output row, or -(1 + parent) for a new row (clone or child).  *n3_out and
+ * *n4_out (host) receive the row counts; the call synchronises `stream`.
+ * scratch: at least h4dgs_densify_scratch_bytes(n3, n4).  The statistics are
+ * not reset here (the caller zeroes them for the new rows). */
+typedef struct {
+    float grad_threshold;     /* 3DGS: 2e-4 */
+    int32_t split_n;          /* children per split row, 1 .. 8 (3DGS: 2) */
+    double log_dense_scale;   /* 3DGS: log(0.01 * scene extent) */
+    double opacity_logit_min; /* 3DGS: logit(0.005) */
+    double log_max_scale;     /* +inf: no size pruning */
+    double log_shrink;        /* 3DGS: log(0.8 * split_n) */
+} h4d_densify_params;
+size_t h4dgs_densify_scratch_bytes(int32_t n3, int32_t n4);
+h4d_status h4dgs_densify(h4d_ctx *ctx, const h4d_g3d *in3, const h4d_g4d *in4, const h4d_set_stats *stats3,
+                         const h4d_set_stats *stats4, const float *noise3, const float *noise4,
+                         const h4d_densify_params *p3, const h4d_densify_params *p4, h4d_g3d_mut *out3,
+                         h4d_g4d_mut *out4, int32_t *src3, int32_t *src4, int32_t *n3_out, int32_t *n4_out,
+                         void *scratch, size_t scratch_bytes, void *stream);
+
+/* Optimiser state across densification: out row r of a set takes row
+ * src[r] of the input arrays (laid out as the parameters) when src[r] >= 0,
+ * zeros otherwise (a new row's moments start at zero); rows3 / rows4 output
+ * rows (<= the outputs' n, which is their row stride); src as h4dgs_densify
+ * wrote it (a value outside [0, n) reads as zeros).  Enqueued on `stream`. */
+h4d_status h4dgs_gather_rows(h4d_ctx *ctx, const h4d_g3d *in3, const h4d_g4d *in4, const int32_t *src3,
+                             int32_t rows3, const int32_t *src4, int32_t rows4, h4d_g3d_mut *out3,
+                             h4d_g4d_mut *out4, void *stream);
+
+/* Optimiser state across the static conversion: moves one set of per-
+ * parameter arrays (an Adam moment, laid out exactly as the parameters) the
+ * way h4dgs_convert_static moved the parameters, following its perm (device,
+ * [in4->n], from a convert_static call on the same sets).  A kept 4D row takes
+ * all its entries; a converted row takes those of the fields the conversion
+ * copies (mean, the three spatial log-scales, opacity, SH) and gets zeros for
+ * its new quaternion (Eq. 9 makes a new parameter, whose moments start from
+ * zero); the 3D rows are copied.  in4/in3: the moment arrays of the old sets;
+ * out4/out3: capacities and row strides as for convert_static (out4->n >=
+ * in4->n, out3->n >= in3->n + in4->n), rows past the new counts are left
+ * unwritten.  Enqueued on `stream`; errors as for convert_static. */
+h4d_status h4dgs_convert_moments(h4d_ctx *ctx, const h4d_g4d *in4, const h4d_g3d *in3, const int32_t *perm,
+                                 h4d_g4d_mut *out4, h4d_g3d_mut *out3, void *stream);
+
 /* One bias-corrected Adam step (Kingma & Ba) over up to 16 float32 segments:
  * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2, p -= lr * m_hat / (sqrt(v_hat)
  * + eps), in place.  Host arrays of n_seg device pointers / sizes / learning
@@ -236,6 +326,19 @@ h4d_status h4dgs_convert_static(h4d_ctx *ctx, const h4d_g4d *in4, const h4d_g3d 
 h4d_status h4dgs_adam(h4d_ctx *ctx, int32_t n_seg, float *const *params, const float *const *grads,
                       float *const *m, float *const *v, const int64_t *sizes, const float *lrs, double beta1,
                       double beta2, double eps, int32_t step, void *stream);
+
+/* h4dgs_adam with a visibility mask per segment (the sparse update that
+ * leaves Gaussians outside the step's views untouched, so that a step costs
+ * what its visible Gaussians need): masks (host array of n_seg device
+ * pointers, each may be NULL = no mask) and rows (host, per segment): element
+ * e of a masked segment belongs to Gaussian e % rows (the component-major
+ * layout) and is updated only where mask[e % rows] != 0; elsewhere the
+ * parameter and both moments keep their values.  size must be a multiple of
+ * rows.  The bias correction uses the global step. */
+h4d_status h4dgs_adam_masked(h4d_ctx *ctx, int32_t n_seg, float *const *params, const float *const *grads,
+                             float *const *m, float *const *v, const int64_t *sizes, const float *lrs,
+                             const uint8_t *const *masks, const int64_t *rows, double beta1, double beta2,
+                             double eps, int32_t step, void *stream);
 
 /* L1 photometric loss of n_views images against targets (both float[3][H][W]
  * per view, host arrays of device pointers): dl_dimages_v = sign(C - target) /

@@ -28,7 +28,8 @@ EXPORTS = (
     "h4dgs_render_fwd", "h4dgs_render_infer", "h4dgs_render_bwd", "h4dgs_check", "h4dgs_rasterize_splats",
     "h4dgs_convert_scratch_bytes", "h4dgs_convert_static", "h4dgs_adam", "h4dgs_l1_loss_grad",
     "h4dgs_profile", "h4dgs_profile_read", "h4dgs_stats", "h4dgs_stats_read", "h4dgs_radix_hist_words",
-    "h4dgs_radix_pass_check", "h4dgs_render_infer_noalloc",
+    "h4dgs_radix_pass_check", "h4dgs_render_infer_noalloc", "h4dgs_convert_moments", "h4dgs_render_bwd_stats",
+    "h4dgs_densify_scratch_bytes", "h4dgs_densify", "h4dgs_gather_rows", "h4dgs_adam_masked",
 )
 
 NOALLOC_BYTES = 256 << 20  # H4DGS_NOALLOC_BYTES
@@ -55,6 +56,15 @@ class View(C.Structure):
     _fields_ = [("world_to_cam", C.c_float * 12), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
                 ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32), ("t", C.c_float),
                 ("bg", C.c_float * 3)]
+
+
+class SetStats(C.Structure):
+    _fields_ = [("grad_norm", C.c_void_p), ("visible", C.c_void_p), ("step_visible", C.c_void_p)]
+
+
+class DensifyParams(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("split_n", C.c_int32), ("log_dense_scale", C.c_double),
+                ("opacity_logit_min", C.c_double), ("log_max_scale", C.c_double), ("log_shrink", C.c_double)]
 
 
 class Config(C.Structure):
@@ -92,6 +102,14 @@ def load(path: str = LIB_PATH):
     L.h4dgs_convert_scratch_bytes.argtypes = [i32]
     L.h4dgs_convert_scratch_bytes.restype = sz
     L.h4dgs_convert_static.argtypes = [vp, vp, vp, f32, vp, vp, vp, P(i32), P(i32), vp, sz, vp]
+    L.h4dgs_convert_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.h4dgs_render_bwd_stats.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp, sz, vp, vp, vp, vp, vp]
+    L.h4dgs_densify_scratch_bytes.argtypes = [i32, i32]
+    L.h4dgs_densify_scratch_bytes.restype = sz
+    L.h4dgs_densify.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32), vp, sz, vp]
+    L.h4dgs_gather_rows.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp]
+    L.h4dgs_adam_masked.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
+                                    i32, vp]
     L.h4dgs_adam.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, i32, vp]
     L.h4dgs_l1_loss_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.h4dgs_profile.argtypes = [vp, i32]
@@ -102,7 +120,8 @@ def load(path: str = LIB_PATH):
     L.h4dgs_radix_hist_words.restype = sz
     L.h4dgs_radix_pass_check.argtypes = [C.c_uint64, i32, i32, i32, sz, sz]
     for name in EXPORTS:
-        if name not in ("h4dgs_last_error", "h4dgs_version", "h4dgs_convert_scratch_bytes", "h4dgs_radix_hist_words"):
+        if name not in ("h4dgs_last_error", "h4dgs_version", "h4dgs_convert_scratch_bytes", "h4dgs_radix_hist_words",
+                        "h4dgs_densify_scratch_bytes"):
             getattr(L, name).restype = i32
     _lib = L
     return L

@@ -50,8 +50,19 @@ __global__ void __launch_bounds__(256) k_adam(AdamTable t, AdamGrid gr) {
         float pa[4] = {pp.x, pp.y, pp.z, pp.w}, ma[4] = {mm.x, mm.y, mm.z, mm.w};
         float va[4] = {vv.x, vv.y, vv.z, vv.w};
         const float ga[4] = {g.x, g.y, g.z, g.w};
+        if (s.mask) {
+            // rows of the four elements (consecutive indices, each wrapping
+            // at `rows`); masked-off rows keep parameter and moments
+            int64_t row = (int64_t)((4 * i) % (size_t)s.rows);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) adam_one(pa[q], ga[q], ma[q], va[q], s.lr, t);
+            for (int q = 0; q < 4; ++q) {
+                if (s.mask[row]) adam_one(pa[q], ga[q], ma[q], va[q], s.lr, t);
+                row = row + 1 == s.rows ? 0 : row + 1;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) adam_one(pa[q], ga[q], ma[q], va[q], s.lr, t);
+        }
         const nf4 p = {pa[0], pa[1], pa[2], pa[3]}, m = {ma[0], ma[1], ma[2], ma[3]};
         const nf4 v = {va[0], va[1], va[2], va[3]};
         __builtin_nontemporal_store(p, &P4[i]);
@@ -59,6 +70,7 @@ __global__ void __launch_bounds__(256) k_adam(AdamTable t, AdamGrid gr) {
         __builtin_nontemporal_store(v, &V4[i]);
     } else {
         if (i >= (size_t)s.n) return;
+        if (s.mask && !s.mask[i % (size_t)s.rows]) return;
         float p = s.p[i], m = s.m[i], v = s.v[i];
         adam_one(p, s.g[i], m, v, s.lr, t);
         s.p[i] = p; s.m[i] = m; s.v[i] = v;

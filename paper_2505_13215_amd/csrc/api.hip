@@ -647,10 +647,11 @@ h4d_status h4dgs_render_infer_noalloc(h4d_ctx* ctx, const h4d_g3d* g3, const h4d
     return H4D_OK;
 }
 
-h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
-                            int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages, const void* state,
-                            size_t state_bytes, void* scratch, size_t scratch_bytes, h4d_g3d_mut* grad3,
-                            h4d_g4d_mut* grad4, void* stream) {
+static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
+                                  int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages,
+                                  const void* state, size_t state_bytes, void* scratch, size_t scratch_bytes,
+                                  h4d_g3d_mut* grad3, h4d_g4d_mut* grad4, const h4d_set_stats* stats3,
+                                  const h4d_set_stats* stats4, void* stream) {
     if (!ctx) return H4D_ERR_INVALID_ARG;
     h4d_status s;
     if ((s = check_sets(ctx, g3, g4)) != H4D_OK) return s;
@@ -702,11 +703,34 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
     const G3Grad r3{grad3->n, grad3->mean, grad3->log_scale, grad3->quat, grad3->opacity, grad3->sh};
     const G4Grad r4{grad4->n, grad4->mean, grad4->mean_t, grad4->log_scale, grad4->quat_l, grad4->quat_r,
                     grad4->opacity, grad4->sh};
+    const SetStats s3 = stats3 ? SetStats{stats3->grad_norm, stats3->visible, stats3->step_visible}
+                               : SetStats{nullptr, nullptr, nullptr};
+    const SetStats s4 = stats4 ? SetStats{stats4->grad_norm, stats4->visible, stats4->step_visible}
+                               : SetStats{nullptr, nullptr, nullptr};
     {
         StageScope sc(ctx, st, H4D_STAGE_PREPROCESS_BWD);
-        launch_preprocess_bwd(to_ptr(g3), to_ptr(g4), vp, n_views, at<Rec>(stt, L.st_recs), g2, r3, r4, st);
+        launch_preprocess_bwd(to_ptr(g3), to_ptr(g4), vp, n_views, at<Rec>(stt, L.st_recs), g2, r3, r4, s3, s4, st);
     }
     return hip_check(ctx, "render_bwd");
+}
+
+h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
+                            int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages, const void* state,
+                            size_t state_bytes, void* scratch, size_t scratch_bytes, h4d_g3d_mut* grad3,
+                            h4d_g4d_mut* grad4, void* stream) {
+    return render_backward(ctx, g3, g4, views, n_views, cfg, dl_dimages, state, state_bytes, scratch, scratch_bytes,
+                           grad3, grad4, nullptr, nullptr, stream);
+}
+
+h4d_status h4dgs_render_bwd_stats(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
+                                  int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages,
+                                  const void* state, size_t state_bytes, void* scratch, size_t scratch_bytes,
+                                  h4d_g3d_mut* grad3, h4d_g4d_mut* grad4, const h4d_set_stats* stats3,
+                                  const h4d_set_stats* stats4, void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    if (!stats3 || !stats4) return fail(ctx, H4D_ERR_INVALID_ARG, "null statistics descriptor");
+    return render_backward(ctx, g3, g4, views, n_views, cfg, dl_dimages, state, state_bytes, scratch, scratch_bytes,
+                           grad3, grad4, stats3, stats4, stream);
 }
 
 h4d_status h4dgs_check(h4d_ctx* ctx, const void* state, size_t state_bytes, int64_t* pairs_needed, void* stream) {
@@ -832,6 +856,132 @@ h4d_status h4dgs_convert_static(h4d_ctx* ctx, const h4d_g4d* in4, const h4d_g3d*
     return H4D_OK;
 }
 
+size_t h4dgs_densify_scratch_bytes(int32_t n3, int32_t n4) {
+    const size_t n = (size_t)std::max(0, std::max(n3, n4));
+    const size_t nb = (size_t)std::max(1, scan_blocks((int)n));
+    return align_up(3 * 4 * n) + align_up(3 * 8 * (n + 1)) + align_up(3 * 8 * (nb + 1)) + align_up(16);
+}
+
+namespace {
+h4d_status check_densify_params(h4d_ctx* ctx, const h4d_densify_params* p, const char* which) {
+    if (!p) return fail(ctx, H4D_ERR_INVALID_ARG, "%s: null densify parameters", which);
+    if (p->split_n < 1 || p->split_n > 8) return fail(ctx, H4D_ERR_INVALID_ARG, "%s: split_n not in [1, 8]", which);
+    if (!(p->grad_threshold >= 0.f) || !std::isfinite(p->grad_threshold))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "%s: grad_threshold must be finite and >= 0", which);
+    if (std::isnan(p->log_dense_scale) || std::isnan(p->opacity_logit_min) || std::isnan(p->log_max_scale) ||
+        !std::isfinite(p->log_shrink))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "%s: NaN limit or non-finite log_shrink", which);
+    return H4D_OK;
+}
+DensifyP to_densify(const h4d_densify_params& p) {
+    return DensifyP{p.grad_threshold, p.split_n, p.log_dense_scale, p.opacity_logit_min, p.log_max_scale,
+                    p.log_shrink};
+}
+}  // namespace
+
+h4d_status h4dgs_densify(h4d_ctx* ctx, const h4d_g3d* in3, const h4d_g4d* in4, const h4d_set_stats* st3,
+                         const h4d_set_stats* st4, const float* noise3, const float* noise4,
+                         const h4d_densify_params* p3, const h4d_densify_params* p4, h4d_g3d_mut* out3,
+                         h4d_g4d_mut* out4, int32_t* src3, int32_t* src4, int32_t* n3_out, int32_t* n4_out,
+                         void* scratch, size_t scratch_bytes, void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    h4d_status s;
+    if ((s = check_sets(ctx, in3, in4)) != H4D_OK) return s;
+    if ((s = check_densify_params(ctx, p3, "3D")) != H4D_OK) return s;
+    if ((s = check_densify_params(ctx, p4, "4D")) != H4D_OK) return s;
+    if (!out3 || !out4 || !n3_out || !n4_out || !st3 || !st4) return fail(ctx, H4D_ERR_INVALID_ARG, "null output");
+    const int64_t cap3 = (int64_t)in3->n * std::max(2, p3->split_n), cap4 = (int64_t)in4->n * std::max(2, p4->split_n);
+    if (cap3 > 0x7FFFFFFF || cap4 > 0x7FFFFFFF) return fail(ctx, H4D_ERR_INVALID_ARG, "too many output rows");
+    if (out3->n < cap3) return fail(ctx, H4D_ERR_CAPACITY, "out3 capacity %d < %lld", out3->n, (long long)cap3);
+    if (out4->n < cap4) return fail(ctx, H4D_ERR_CAPACITY, "out4 capacity %d < %lld", out4->n, (long long)cap4);
+    if (in3->n > 0 && (!st3->grad_norm || !st3->visible || !noise3 || !src3 || !out3->mean || !out3->log_scale ||
+                       !out3->quat || !out3->opacity || !out3->sh))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "3D set: null statistics, noise, src or output array");
+    if (in4->n > 0 && (!st4->grad_norm || !st4->visible || !noise4 || !src4 || !out4->mean || !out4->mean_t ||
+                       !out4->log_scale || !out4->quat_l || !out4->quat_r || !out4->opacity || !out4->sh))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "4D set: null statistics, noise, src or output array");
+    if ((in3->n > 0 && (const void*)out3->mean == (const void*)in3->mean) ||
+        (in4->n > 0 && (const void*)out4->mean == (const void*)in4->mean))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "outputs must not alias inputs");
+    const size_t need = h4dgs_densify_scratch_bytes(in3->n, in4->n);
+    if (!scratch || scratch_bytes < need)
+        return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small (%zu < %zu)", scratch_bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t n = (size_t)std::max(in3->n, in4->n);
+    const size_t nb = (size_t)std::max(1, scan_blocks((int)n));
+    Carve c;
+    const size_t o_flags = c.take(3 * 4 * n), o_scan = c.take(3 * 8 * (n + 1)), o_part = c.take(3 * 8 * (nb + 1)),
+                 o_cnt = c.take(16);
+    int32_t* dcount = at<int32_t>(scratch, o_cnt);
+    const G3Grad o3{out3->n, out3->mean, out3->log_scale, out3->quat, out3->opacity, out3->sh};
+    const G4Grad o4{out4->n, out4->mean, out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r, out4->opacity,
+                    out4->sh};
+    int32_t hc[2] = {0, 0};
+    // the sets one after another in the same scratch (each ends in a count read back)
+    launch_densify3(to_ptr(in3), st3->grad_norm, st3->visible, noise3, to_densify(*p3), o3, src3,
+                    at<uint32_t>(scratch, o_flags), at<unsigned long long>(scratch, o_scan),
+                    at<unsigned long long>(scratch, o_part), dcount, st);
+    if ((s = hip_check(ctx, "densify (3D)")) != H4D_OK) return s;
+    if (hipMemcpyAsync(&hc[0], dcount, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_check(ctx, "densify: count readback");
+    launch_densify4(to_ptr(in4), st4->grad_norm, st4->visible, noise4, to_densify(*p4), o4, src4,
+                    at<uint32_t>(scratch, o_flags), at<unsigned long long>(scratch, o_scan),
+                    at<unsigned long long>(scratch, o_part), dcount, st);
+    if ((s = hip_check(ctx, "densify (4D)")) != H4D_OK) return s;
+    if (hipMemcpyAsync(&hc[1], dcount, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_check(ctx, "densify: count readback");
+    *n3_out = hc[0];
+    *n4_out = hc[1];
+    return H4D_OK;
+}
+
+h4d_status h4dgs_gather_rows(h4d_ctx* ctx, const h4d_g3d* in3, const h4d_g4d* in4, const int32_t* src3,
+                             int32_t rows3, const int32_t* src4, int32_t rows4, h4d_g3d_mut* out3, h4d_g4d_mut* out4,
+                             void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    h4d_status s;
+    if ((s = check_sets(ctx, in3, in4)) != H4D_OK) return s;
+    if (!out3 || !out4) return fail(ctx, H4D_ERR_INVALID_ARG, "null output");
+    if (rows3 < 0 || rows4 < 0 || out3->n < rows3 || out4->n < rows4)
+        return fail(ctx, H4D_ERR_INVALID_ARG, "row counts must be in [0, output capacity]");
+    if (rows3 > 0 && (!src3 || !out3->mean || !out3->log_scale || !out3->quat || !out3->opacity || !out3->sh))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "3D: null src or output array");
+    if (rows4 > 0 && (!src4 || !out4->mean || !out4->mean_t || !out4->log_scale || !out4->quat_l || !out4->quat_r ||
+                      !out4->opacity || !out4->sh))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "4D: null src or output array");
+    const G3Grad o3{out3->n, out3->mean, out3->log_scale, out3->quat, out3->opacity, out3->sh};
+    const G4Grad o4{out4->n, out4->mean, out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r, out4->opacity,
+                    out4->sh};
+    launch_gather_rows(to_ptr(in3), src3, rows3, o3, to_ptr(in4), src4, rows4, o4, static_cast<hipStream_t>(stream));
+    return hip_check(ctx, "gather_rows");
+}
+
+h4d_status h4dgs_convert_moments(h4d_ctx* ctx, const h4d_g4d* in4, const h4d_g3d* in3, const int32_t* perm,
+                                 h4d_g4d_mut* out4, h4d_g3d_mut* out3, void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    h4d_status s;
+    if ((s = check_sets(ctx, in3, in4)) != H4D_OK) return s;
+    if (!out4 || !out3) return fail(ctx, H4D_ERR_INVALID_ARG, "null output");
+    if (out4->n < in4->n) return fail(ctx, H4D_ERR_CAPACITY, "out4 capacity %d < %d", out4->n, in4->n);
+    if ((int64_t)out3->n < (int64_t)in3->n + in4->n)
+        return fail(ctx, H4D_ERR_CAPACITY, "out3 capacity %d < %d", out3->n, in3->n + in4->n);
+    if (in4->n > 0 && (!perm || !out4->mean || !out4->mean_t || !out4->log_scale || !out4->quat_l || !out4->quat_r ||
+                       !out4->opacity || !out4->sh))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "null 4D output array or perm");
+    if (out3->n > 0 && (!out3->mean || !out3->log_scale || !out3->quat || !out3->opacity || !out3->sh))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "null 3D output array");
+    if ((in3->n > 0 && (const void*)out3->mean == (const void*)in3->mean) ||
+        (in4->n > 0 && (const void*)out4->mean == (const void*)in4->mean))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "outputs must not alias inputs");
+    const G4Grad o4{out4->n, out4->mean, out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r, out4->opacity,
+                    out4->sh};
+    const G3Grad o3{out3->n, out3->mean, out3->log_scale, out3->quat, out3->opacity, out3->sh};
+    launch_convert_moments(to_ptr(in4), to_ptr(in3), perm, o4, o3, static_cast<hipStream_t>(stream));
+    return hip_check(ctx, "convert_moments");
+}
+
 h4d_status h4dgs_adam(h4d_ctx* ctx, int32_t n_seg, float* const* params, const float* const* grads, float* const* m,
                       float* const* v, const int64_t* sizes, const float* lrs, double beta1, double beta2,
                       double eps, int32_t step, void* stream) {
@@ -855,13 +1005,49 @@ h4d_status h4dgs_adam(h4d_ctx* ctx, int32_t n_seg, float* const* params, const f
         if (sizes[i] < 0) return fail(ctx, H4D_ERR_INVALID_ARG, "segment %d: negative size", i);
         if (sizes[i] > 0 && (!params[i] || !grads[i] || !m[i] || !v[i]))
             return fail(ctx, H4D_ERR_INVALID_ARG, "segment %d: null pointer", i);
-        t.seg[i] = AdamSeg{params[i], grads[i], m[i], v[i], sizes[i], lrs[i]};
+        t.seg[i] = AdamSeg{params[i], grads[i], m[i], v[i], sizes[i], lrs[i], nullptr, 0};
     }
     {
         StageScope sc(ctx, static_cast<hipStream_t>(stream), H4D_STAGE_ADAM);
         launch_adam(t, static_cast<hipStream_t>(stream));
     }
     return hip_check(ctx, "adam");
+}
+
+h4d_status h4dgs_adam_masked(h4d_ctx* ctx, int32_t n_seg, float* const* params, const float* const* grads,
+                             float* const* m, float* const* v, const int64_t* sizes, const float* lrs,
+                             const uint8_t* const* masks, const int64_t* rows, double beta1, double beta2, double eps,
+                             int32_t step, void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    if (n_seg < 0 || n_seg > kMaxAdamSeg)
+        return fail(ctx, H4D_ERR_INVALID_ARG, "n_seg must be in [0, %d]", kMaxAdamSeg);
+    if (n_seg > 0 && (!params || !grads || !m || !v || !sizes || !lrs || !masks || !rows))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "null segment table");
+    if (step < 1) return fail(ctx, H4D_ERR_INVALID_ARG, "step must be >= 1");
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0))
+        return fail(ctx, H4D_ERR_INVALID_ARG, "bad Adam constants");
+    AdamTable t;
+    std::memset(&t, 0, sizeof(t));
+    t.n_seg = n_seg;
+    t.b1 = (float)beta1; t.b2 = (float)beta2; t.eps = (float)eps;
+    t.omb1 = (float)(1.0 - beta1);
+    t.omb2 = (float)(1.0 - beta2);
+    t.c1 = (float)(1.0 - std::pow(beta1, step));
+    t.c2 = (float)(1.0 - std::pow(beta2, step));
+    for (int i = 0; i < n_seg; ++i) {
+        if (sizes[i] < 0) return fail(ctx, H4D_ERR_INVALID_ARG, "segment %d: negative size", i);
+        if (sizes[i] > 0 && (!params[i] || !grads[i] || !m[i] || !v[i]))
+            return fail(ctx, H4D_ERR_INVALID_ARG, "segment %d: null pointer", i);
+        if (masks[i] && (rows[i] <= 0 || sizes[i] % rows[i] != 0))
+            return fail(ctx, H4D_ERR_INVALID_ARG, "segment %d: size %lld is not a multiple of rows %lld", i,
+                        (long long)sizes[i], (long long)rows[i]);
+        t.seg[i] = AdamSeg{params[i], grads[i], m[i], v[i], sizes[i], lrs[i], masks[i], masks[i] ? rows[i] : 0};
+    }
+    {
+        StageScope sc(ctx, static_cast<hipStream_t>(stream), H4D_STAGE_ADAM);
+        launch_adam(t, static_cast<hipStream_t>(stream));
+    }
+    return hip_check(ctx, "adam_masked");
 }
 
 h4d_status h4dgs_l1_loss_grad(h4d_ctx* ctx, int32_t n_views, const float* const* images, const float* const* targets,

@@ -108,6 +108,29 @@ struct G4Grad {
     float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
 };
 
+// Optional per-Gaussian statistics of one backward call (any pointer may be
+// null): grad += sum over the views in which the Gaussian covers a pixel of
+// |dL/d(centre)| in normalised device coordinates, vis += the number of those
+// views, step_vis = 1 if there is one, else 0.
+struct SetStats {
+    float* grad;
+    float* vis;
+    uint8_t* step_vis;
+};
+
+// One view's share: the image-plane gradient (pixels) of the centre, e0 and e1,
+// scaled to normalised device coordinates (half the image size per unit).
+__device__ inline double ndc_grad_norm(float e0, float e1, int W, int H) {
+    const double gx = (double)e0 * (0.5 * (double)W), gy = (double)e1 * (0.5 * (double)H);
+    return sqrt(gx * gx + gy * gy);
+}
+
+__device__ inline void write_stats(const SetStats& st, int i, double gsum, int nvis) {
+    if (st.grad) st.grad[i] += (float)gsum;
+    if (st.vis) st.vis[i] += (float)nvis;
+    if (st.step_vis) st.step_vis[i] = nvis > 0 ? 1 : 0;
+}
+
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Dispatch-order bucket of a tile whose adjoint walks `cost` list entries:

@@ -37,7 +37,7 @@ struct __align__(16) LSplat {
     float qa, qb, qc, op;
     float cr, cg, cb;
     uint32_t gid;                 // splat id (used by the backward)
-    uint32_t pad[2];
+    float qa2, qc2;               // 2 qa, 2 qc (used by the backward)
 };
 static_assert(sizeof(LSplat) == 64, "LDS splat is 64 bytes");
 constexpr uint32_t kRowsIn = 0x80000000u;
@@ -51,6 +51,7 @@ __device__ __forceinline__ void stage_splat(const Rec& r, uint32_t gid, int row0
     s.ui = r.c.y; s.uf = r.a.x; s.vi = r.c.z; s.vf = r.a.y;
     s.qa = r.a.z; s.qb = r.a.w; s.qc = r.b.x; s.op = r.b.y;
     s.cr = r.b.z; s.cg = r.b.w; s.cb = r.c.x;
+    s.qa2 = 2.0f * r.a.z; s.qc2 = 2.0f * r.b.x;
 }
 
 // (y0, y1 as stored: only meaningful when the rows-in flag is clear)
@@ -60,6 +61,22 @@ __device__ __forceinline__ Splat to_splat(const LSplat& l) {
     s.ui = l.ui; s.uf = l.uf; s.vi = l.vi; s.vf = l.vf;
     s.qa = l.qa; s.qb = l.qb; s.qc = l.qc; s.op = l.op;
     s.cr = l.cr; s.cg = l.cg; s.cb = l.cb;
+    return s;
+}
+
+// The same record read as four 128-bit LDS loads from one address, with the
+// adjoint's extra fields (2 qa, 2 qc).
+__device__ __forceinline__ Splat to_splat_wide(const LSplat& l, float& qa2, float& qc2) {
+    const uint4* p = reinterpret_cast<const uint4*>(&l);
+    const uint4 w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3];
+    Splat s;
+    s.x0 = (int)(w0.x & 0xFFFFu); s.x1 = (int)(w0.x >> 16); s.y0 = (int)(w0.y & 0xFFFFu); s.y1 = (int)(w0.y >> 16);
+    s.ui = __uint_as_float(w0.z); s.uf = __uint_as_float(w0.w);
+    s.vi = __uint_as_float(w1.x); s.vf = __uint_as_float(w1.y);
+    s.qa = __uint_as_float(w1.z); s.qb = __uint_as_float(w1.w);
+    s.qc = __uint_as_float(w2.x); s.op = __uint_as_float(w2.y);
+    s.cr = __uint_as_float(w2.z); s.cg = __uint_as_float(w2.w); s.cb = __uint_as_float(w3.x);
+    qa2 = __uint_as_float(w3.z); qc2 = __uint_as_float(w3.w);
     return s;
 }
 
@@ -433,9 +450,9 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         // the adjoint of one blending step with splat j; gid: its splat id
         auto step = [&](int j, uint32_t gid, auto rows_tag) {
             constexpr bool RI = decltype(rows_tag)::value;
-            const Splat s = to_splat(s_sp[j]);
+            float qa2, qc2;
+            const Splat s = to_splat_wide(s_sp[j], qa2, qc2);
             const ColTerm c = eval_col(s, px, pxc);
-            const float twoqadx = 2.0f * c.qadx, qbdx = c.bx, dx2 = c.dx * c.dx, twoqc = 2.0f * s.qc;
             // per-splat sums of this lane's pixels: dL/dopacity, dL/drgb, and the
             // moments sum q, sum q dy, sum q dy^2 of q = dL/dalpha * exp2(power),
             // which is dL/dpower (natural log domain) divided by the splat's opacity
@@ -479,10 +496,12 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
             }
             // conic and centre terms without their constant factors and the
             // opacity (applied after the reduction): sum q (2 qa dx + qb dy),
-            // sum q (qb dx + 2 qc dy), sum q dx^2, sum q dx dy, sum q dy^2
-            const float e0 = __builtin_fmaf(e5, twoqadx, s.qb * sdy);
-            const float e1 = __builtin_fmaf(e5, qbdx, twoqc * sdy);
-            const float e2 = dx2 * e5, e3 = c.dx * sdy, e4 = syy;
+            // sum q (qb dx + 2 qc dy), sum q dx^2, sum q dx dy, sum q dy^2,
+            // from A = dx sum q
+            const float A = c.dx * e5;
+            const float e0 = __builtin_fmaf(qa2, A, s.qb * sdy);
+            const float e1 = __builtin_fmaf(s.qb, A, qc2 * sdy);
+            const float e2 = c.dx * A, e3 = c.dx * sdy, e4 = syy;
             if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
                 float h0, h1, h2;
                 wave_sum9(e0, e1, e2, e3, e4, e5, e6, e7, e8, h0, h1, h2);

@@ -119,6 +119,42 @@ __global__ void k_convert_counts(const unsigned long long* keep_off, const unsig
     }
 }
 
+// Optimiser state across the conversion: the moment arrays (laid out as the
+// parameters) follow the rows the conversion moved (perm from
+// k_convert_scatter).  A kept 4D row takes all its moments; a converted row
+// takes those of the fields it copies (mean, spatial log-scales, opacity, SH)
+// and starts its new quaternion's at zero.
+__global__ void k_convert_moments(G4Ptr in4, const int32_t* __restrict__ perm, G4Grad out4, G3Grad out3) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n4 = in4.n;
+    if (i >= n4) return;
+    const size_t ni = (size_t)n4;
+    const int32_t p = perm[i];
+    if (p >= 0) {
+        const size_t r = (size_t)p, no = (size_t)out4.n;
+        for (int k = 0; k < 3; ++k) out4.mean[k * no + r] = in4.mean[k * ni + i];
+        out4.mean_t[r] = in4.mean_t[i];
+        for (int k = 0; k < 4; ++k) out4.log_scale[k * no + r] = in4.log_scale[k * ni + i];
+        for (int k = 0; k < 4; ++k) out4.quat_l[k * no + r] = in4.quat_l[k * ni + i];
+        for (int k = 0; k < 4; ++k) out4.quat_r[k * no + r] = in4.quat_r[k * ni + i];
+        out4.opacity[r] = in4.opacity[i];
+        for (int k = 0; k < 48; ++k) out4.sh[k * no + r] = in4.sh[k * ni + i];
+    } else {
+        const size_t r = (size_t)(-1 - (int64_t)p), no = (size_t)out3.n;
+        for (int k = 0; k < 3; ++k) out3.mean[k * no + r] = in4.mean[k * ni + i];
+        for (int k = 0; k < 3; ++k) out3.log_scale[k * no + r] = in4.log_scale[k * ni + i];
+        for (int k = 0; k < 4; ++k) out3.quat[k * no + r] = 0.0f;
+        out3.opacity[r] = in4.opacity[i];
+        for (int k = 0; k < 48; ++k) out3.sh[k * no + r] = in4.sh[k * ni + i];
+    }
+}
+
+void launch_convert_moments(const G4Ptr& in4, const G3Ptr& in3, const int32_t* perm, const G4Grad& out4,
+                            const G3Grad& out3, hipStream_t st) {
+    if (in3.n > 0) k_copy_rows<<<ceil_div(in3.n, 256), 256, 0, st>>>(in3, out3);
+    if (in4.n > 0) k_convert_moments<<<ceil_div(in4.n, 256), 256, 0, st>>>(in4, perm, out4, out3);
+}
+
 // flags: [2][n4] uint32; scan: [2][n4 + 1] u64; partials: [2][scan_blocks + 1]
 void launch_convert_static(const G4Ptr& in4, const G3Ptr& in3, double log_tau, const G4Grad& out4,
                            const G3Grad& out3, int32_t* perm, uint32_t* flags, unsigned long long* scan,

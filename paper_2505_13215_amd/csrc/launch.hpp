@@ -29,7 +29,8 @@ void launch_count_onscreen(const Rec* recs, size_t n, unsigned long long* counte
 void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,
                        uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
-                           const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st);
+                           const float* g2, const G3Grad& gr3, const G4Grad& gr4, const SetStats& st3,
+                           const SetStats& st4, hipStream_t st);
 void launch_splats_to_records(int n, const float* u, const float* v, const float* conic, const float* opacity,
                               const float* rgb, const int32_t* radius, const float* depth, const uint8_t* visible,
                               int W, int H, Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
@@ -168,6 +169,22 @@ void launch_l1_loss_grad(const float* img, const float* target, float* dl, size_
                          hipStream_t st);
 
 // convert.hip
+// Densification limits as the kernels take them (see h4d_densify_params).
+struct DensifyP {
+    float thr;
+    int split_n;
+    double log_dense, logit_min, log_max_scale, log_shrink;
+};
+void launch_densify3(const G3Ptr& g, const float* grad, const float* vis, const float* noise, const DensifyP& p,
+                     const G3Grad& o, int32_t* src, uint32_t* flags, unsigned long long* scan,
+                     unsigned long long* partials, int32_t* count, hipStream_t st);
+void launch_densify4(const G4Ptr& g, const float* grad, const float* vis, const float* noise, const DensifyP& p,
+                     const G4Grad& o, int32_t* src, uint32_t* flags, unsigned long long* scan,
+                     unsigned long long* partials, int32_t* count, hipStream_t st);
+void launch_gather_rows(const G3Ptr& g3, const int32_t* src3, int rows3, const G3Grad& o3, const G4Ptr& g4,
+                        const int32_t* src4, int rows4, const G4Grad& o4, hipStream_t st);
+void launch_convert_moments(const G4Ptr& in4, const G3Ptr& in3, const int32_t* perm, const G4Grad& out4,
+                            const G3Grad& out3, hipStream_t st);
 void launch_convert_static(const G4Ptr& in4, const G3Ptr& in3, double log_tau, const G4Grad& out4,
                            const G3Grad& out3, int32_t* perm, uint32_t* flags, unsigned long long* scan,
                            unsigned long long* partials, int32_t* counts, hipStream_t st);
@@ -180,6 +197,10 @@ struct AdamSeg {
     float* v;
     int64_t n;
     float lr;
+    // optional row mask: element e belongs to row e % rows and is updated only
+    // where mask[row] != 0 (parameter, moments unchanged elsewhere)
+    const uint8_t* mask;
+    int64_t rows;
 };
 constexpr int kMaxAdamSeg = 16;
 struct AdamTable {

@@ -9,6 +9,7 @@
 // key) lands exactly where the FP64 definition puts it.
 #include "common.hpp"
 #include "launch.hpp"
+#include "rotation.hpp"
 
 namespace h4d {
 
@@ -89,37 +90,6 @@ struct WorldF {
 struct Rot4 {
     double L[4][4], Rr[4][4], R[4][4];
 };
-
-__device__ inline void rot_left(const double q[4], double M[4][4]) {
-    const double a = q[0], b = q[1], c = q[2], d = q[3];
-    M[0][0] = a; M[0][1] = -b; M[0][2] = -c; M[0][3] = -d;
-    M[1][0] = b; M[1][1] = a;  M[1][2] = -d; M[1][3] = c;
-    M[2][0] = c; M[2][1] = d;  M[2][2] = a;  M[2][3] = -b;
-    M[3][0] = d; M[3][1] = -c; M[3][2] = b;  M[3][3] = a;
-}
-__device__ inline void rot_right(const double q[4], double M[4][4]) {
-    const double p = q[0], qq = q[1], r = q[2], s = q[3];
-    M[0][0] = p;  M[0][1] = -qq; M[0][2] = -r;  M[0][3] = -s;
-    M[1][0] = qq; M[1][1] = p;   M[1][2] = s;   M[1][3] = -r;
-    M[2][0] = r;  M[2][1] = -s;  M[2][2] = p;   M[2][3] = qq;
-    M[3][0] = s;  M[3][1] = r;   M[3][2] = -qq; M[3][3] = p;
-}
-
-__device__ inline double load_unit4(const float* q, int n, int i, double out[4]) {
-    double a[4];
-    for (int k = 0; k < 4; ++k) a[k] = (double)q[(size_t)k * n + i];
-    const double nrm = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
-    const double inv = 1.0 / nrm;
-    for (int k = 0; k < 4; ++k) out[k] = a[k] * inv;
-    return nrm;
-}
-
-__device__ inline void quat_rot3(const double q[4], double R[3][3]) {
-    const double w = q[0], x = q[1], y = q[2], z = q[3];
-    R[0][0] = 1.0 - 2.0 * (y * y + z * z); R[0][1] = 2.0 * (x * y - w * z); R[0][2] = 2.0 * (x * z + w * y);
-    R[1][0] = 2.0 * (x * y + w * z); R[1][1] = 1.0 - 2.0 * (x * x + z * z); R[1][2] = 2.0 * (y * z - w * x);
-    R[2][0] = 2.0 * (x * z - w * y); R[2][1] = 2.0 * (y * z + w * x); R[2][2] = 1.0 - 2.0 * (x * x + y * y);
-}
 
 __device__ inline double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
@@ -401,7 +371,8 @@ __device__ inline void unit_bwd(const double qh[4], double nrm, const double gqh
 }
 
 __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restrict__ views, int n_views, int N,
-                              const Rec* __restrict__ recs, const float* __restrict__ g2, const G4Grad& gr) {
+                              const Rec* __restrict__ recs, const float* __restrict__ g2, const G4Grad& gr,
+                              const SetStats& st) {
     const size_t n = (size_t)g4.n;
     double s[4], ql[4], qr[4];
     for (int k = 0; k < 4; ++k) s[k] = exp((double)g4.log_scale[k * n + i]);
@@ -435,9 +406,16 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
         for (int k = 0; k < 4; ++k) Ss[r][k] = 0.0;
     float gsh[48];
     for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    double stat_g = 0.0;
+    int stat_n = 0;
     for (int v = 0; v < n_views; ++v) {
         if (recs[(size_t)v * N + i].d.w == 0u) continue;  // covers no pixel in this view
         const ViewParams& V = views[v];
+        if (st.grad || st.vis || st.step_vis) {
+            const float* e = g2 + ((size_t)v * N + i) * kG2Stride;
+            stat_g += ndc_grad_norm(e[0], e[1], V.W, V.H);
+            ++stat_n;
+        }
         const double delta = V.time - mt;
         const double pt = exp(-(delta * delta) * 0.5 * ic);
         WorldF w;
@@ -515,11 +493,13 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
     for (int k = 0; k < 3; ++k) gr.mean[k * n + i] = (float)gmu[k];
     gr.mean_t[i] = (float)gmt;
     gr.opacity[i] = (float)(gsig * sig * (1.0 - sig));
+    write_stats(st, i, stat_g, stat_n);
     for (int k = 0; k < 48; ++k) gr.sh[k * n + i] = gsh[k];
 }
 
 __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams* __restrict__ views, int n_views,
-                              int N, const Rec* __restrict__ recs, const float* __restrict__ g2, const G3Grad& gr) {
+                              int N, const Rec* __restrict__ recs, const float* __restrict__ g2, const G3Grad& gr,
+                              const SetStats& st) {
     const size_t n = (size_t)g3.n;
     WorldF w;
     Cov3 z;
@@ -528,9 +508,16 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
     double Ss[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     float gsh[48];
     for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    double stat_g = 0.0;
+    int stat_n = 0;
     for (int v = 0; v < n_views; ++v) {
         if (recs[(size_t)v * N + gidx].d.w == 0u) continue;
         const ViewParams& V = views[v];
+        if (st.grad || st.vis || st.step_vis) {
+            const float* e = g2 + ((size_t)v * N + gidx) * kG2Stride;
+            stat_g += ndc_grad_norm(e[0], e[1], V.W, V.H);
+            ++stat_n;
+        }
         ProjF p;
         project(V, w, p);
         double gmc[3], Sb[3][3], gop;
@@ -565,6 +552,7 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
     unit_bwd(z.q, z.nq, gq, gr.quat + i, n);
     for (int k = 0; k < 3; ++k) gr.mean[k * n + i] = (float)gmu[k];
     gr.opacity[i] = (float)(gsig * z.sig * (1.0 - z.sig));
+    write_stats(st, i, stat_g, stat_n);
     for (int k = 0; k < 48; ++k) gr.sh[k * n + i] = gsh[k];
 }
 
@@ -574,14 +562,15 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
 // occupancy and lets the two sets fill the machine together.
 __global__ void __launch_bounds__(128) k_preprocess_bwd(G3Ptr g3, G4Ptr g4, int nb4, const ViewParams* __restrict__ views,
                                                         int n_views, const Rec* __restrict__ recs,
-                                                        const float* __restrict__ g2, G3Grad gr3, G4Grad gr4) {
+                                                        const float* __restrict__ g2, G3Grad gr3, G4Grad gr4,
+                                                        SetStats st3, SetStats st4) {
     const int N = g3.n + g4.n;
     if ((int)blockIdx.x < nb4) {
         const int g = blockIdx.x * blockDim.x + threadIdx.x;
-        if (g < g4.n) bwd_4d(g4, g, views, n_views, N, recs, g2, gr4);
+        if (g < g4.n) bwd_4d(g4, g, views, n_views, N, recs, g2, gr4, st4);
     } else {
         const int i = (blockIdx.x - nb4) * blockDim.x + threadIdx.x;
-        if (i < g3.n) bwd_3d(g3, i, g4.n + i, views, n_views, N, recs, g2, gr3);
+        if (i < g3.n) bwd_3d(g3, i, g4.n + i, views, n_views, N, recs, g2, gr3, st3);
     }
 }
 
@@ -650,11 +639,12 @@ void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views
 }
 
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
-                           const float* g2, const G3Grad& gr3, const G4Grad& gr4, hipStream_t st) {
+                           const float* g2, const G3Grad& gr3, const G4Grad& gr4, const SetStats& st3,
+                           const SetStats& st4, hipStream_t st) {
     const int N = g3.n + g4.n;
     if (N == 0) return;
     const int nb4 = ceil_div(g4.n, 128), nb3 = ceil_div(g3.n, 128);
-    k_preprocess_bwd<<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4);
+    k_preprocess_bwd<<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4);
 }
 
 }  // namespace h4d

@@ -44,6 +44,24 @@ def g4_struct(g4: dict):
     return L.G4D(n, *[_ptr(g4[k]) for k in G4_KEYS])
 
 
+def _stats_struct(d: dict, n: int) -> L.SetStats:
+    def get(key, dtype):
+        t = d.get(key)
+        if t is None:
+            return C.c_void_p(0)
+        if t.device.type != "cuda" or t.dtype != dtype or t.numel() != n or not t.is_contiguous():
+            raise ValueError(f"stats {key}: expected {n} contiguous {dtype} CUDA elements")
+        return _ptr(t)
+    return L.SetStats(get("grad_norm", torch.float32), get("visible", torch.float32),
+                      get("step_visible", torch.uint8))
+
+
+def new_stats(n3: int, n4: int, device="cuda") -> tuple:
+    """Zeroed per-Gaussian statistics (grad_norm, visible, step_visible) of both sets."""
+    return tuple({"grad_norm": torch.zeros(n, device=device), "visible": torch.zeros(n, device=device),
+                  "step_visible": torch.zeros(n, dtype=torch.uint8, device=device)} for n in (n3, n4))
+
+
 def to_device(d: dict, device="cuda") -> dict:
     return {k: torch.as_tensor(v, dtype=torch.float32, device=device).contiguous() for k, v in d.items()}
 
@@ -159,8 +177,11 @@ class Rasterizer:
         self.ctx.check(rc)
         return self.last_pairs
 
-    def backward(self, h: FwdHandle, g3: dict, g4: dict, dl_images, out=None) -> tuple:
-        """Gradients of every raw parameter; ``out`` = (gr3, gr4) dicts to fill in place."""
+    def backward(self, h: FwdHandle, g3: dict, g4: dict, dl_images, out=None, stats=None) -> tuple:
+        """Gradients of every raw parameter; ``out`` = (gr3, gr4) dicts to fill in
+        place; ``stats`` = (st3, st4) dicts of per-Gaussian statistics to
+        accumulate (keys grad_norm, visible: float32 [n]; step_visible: uint8
+        [n]; any may be missing)."""
         if h.generation != self._gen:
             raise RuntimeError("backward must follow its own forward (the workspace was reused)")
         if not h.differentiable:
@@ -179,9 +200,16 @@ class Rasterizer:
         m4 = L.G4D(s4.n, *[_ptr(gr4[k]) for k in G4_KEYS])
         dl = [_chk(d, "dl_dimage") for d in dl_images]
         arr = L.ptr_array([d.data_ptr() for d in dl])
-        self.ctx.check(self.ctx.L.h4dgs_render_bwd(
-            self.ctx.h, C.byref(s3), C.byref(s4), h.views, h.n_views, C.byref(h.cfg), arr, _ptr(h.state),
-            h.state.numel(), _ptr(self._scratch), self._scratch.numel(), C.byref(m3), C.byref(m4), _stream()))
+        if stats is None:
+            self.ctx.check(self.ctx.L.h4dgs_render_bwd(
+                self.ctx.h, C.byref(s3), C.byref(s4), h.views, h.n_views, C.byref(h.cfg), arr, _ptr(h.state),
+                h.state.numel(), _ptr(self._scratch), self._scratch.numel(), C.byref(m3), C.byref(m4), _stream()))
+        else:
+            st = [_stats_struct(d, n) for d, n in zip(stats, (s3.n, s4.n))]
+            self.ctx.check(self.ctx.L.h4dgs_render_bwd_stats(
+                self.ctx.h, C.byref(s3), C.byref(s4), h.views, h.n_views, C.byref(h.cfg), arr, _ptr(h.state),
+                h.state.numel(), _ptr(self._scratch), self._scratch.numel(), C.byref(m3), C.byref(m4),
+                C.byref(st[0]), C.byref(st[1]), _stream()))
         return gr3, gr4
 
 
@@ -315,19 +343,31 @@ def rasterize_splats(rast: Rasterizer, sp: dict, width: int, height: int, bg=(0.
     raise L.H4DError(L.H4D_ERR_CAPACITY, "pair capacity kept overflowing")
 
 
-def convert_static(rast: Rasterizer, g3: dict, g4: dict, tau: float):
-    """Static identification + 4D->3D conversion.  Returns (g3', g4', perm)."""
-    s3, s4 = g3_struct(g3), g4_struct(g4)
-    n3, n4 = s3.n, s4.n
-    dev = "cuda"
-    cap3 = n3 + n4
-    o3 = {"mean": torch.empty((3, cap3), device=dev), "log_scale": torch.empty((3, cap3), device=dev),
-          "quat": torch.empty((4, cap3), device=dev), "opacity": torch.empty(cap3, device=dev),
-          "sh": torch.empty((48, cap3), device=dev)}
+def _set_buffers(n3: int, n4: int, dev="cuda"):
+    """Uninitialised parameter-shaped arrays for n3 3D and n4 4D rows."""
+    o3 = {"mean": torch.empty((3, n3), device=dev), "log_scale": torch.empty((3, n3), device=dev),
+          "quat": torch.empty((4, n3), device=dev), "opacity": torch.empty(n3, device=dev),
+          "sh": torch.empty((48, n3), device=dev)}
     o4 = {"mean": torch.empty((3, n4), device=dev), "mean_t": torch.empty(n4, device=dev),
           "log_scale": torch.empty((4, n4), device=dev), "quat_l": torch.empty((4, n4), device=dev),
           "quat_r": torch.empty((4, n4), device=dev), "opacity": torch.empty(n4, device=dev),
           "sh": torch.empty((48, n4), device=dev)}
+    return o3, o4
+
+
+def _first_rows(d: dict, k: int) -> dict:
+    return {name: (v[..., :k] if v.dim() == 2 else v[:k]).contiguous() for name, v in d.items()}
+
+
+def convert_static(rast: Rasterizer, g3: dict, g4: dict, tau: float, moments=()):
+    """Static identification + 4D->3D conversion.  Returns (g3', g4', perm);
+    with ``moments`` (pairs (m3, m4) of parameter-shaped arrays, e.g. Adam's
+    first and second moments) also the list of the moved pairs."""
+    s3, s4 = g3_struct(g3), g4_struct(g4)
+    n3, n4 = s3.n, s4.n
+    dev = "cuda"
+    cap3 = n3 + n4
+    o3, o4 = _set_buffers(cap3, n4, dev)
     m3 = L.G3D(cap3, *[_ptr(o3[k]) for k in G3_KEYS])
     m4 = L.G4D(n4, *[_ptr(o4[k]) for k in G4_KEYS])
     perm = torch.empty(max(1, n4), dtype=torch.int32, device=dev)
@@ -338,9 +378,57 @@ def convert_static(rast: Rasterizer, g3: dict, g4: dict, tau: float):
         rast.ctx.h, C.byref(s4), C.byref(s3), C.c_float(tau), C.byref(m4), C.byref(m3), _ptr(perm), C.byref(n4o),
         C.byref(n3o), _ptr(scratch), scratch.numel(), _stream()))
     k3, k4 = n3o.value, n4o.value
-    g3n = {k: (v[..., :k3] if v.dim() == 2 else v[:k3]).contiguous() for k, v in o3.items()}
-    g4n = {k: (v[..., :k4] if v.dim() == 2 else v[:k4]).contiguous() for k, v in o4.items()}
-    return g3n, g4n, perm[:n4]
+    g3n, g4n = _first_rows(o3, k3), _first_rows(o4, k4)
+    if not moments:
+        return g3n, g4n, perm[:n4]
+    moved = []
+    for a3, a4 in moments:
+        b3, b4 = _set_buffers(cap3, n4, dev)
+        rast.ctx.check(rast.ctx.L.h4dgs_convert_moments(
+            rast.ctx.h, C.byref(g4_struct(a4)), C.byref(g3_struct(a3)), _ptr(perm),
+            C.byref(L.G4D(n4, *[_ptr(b4[k]) for k in G4_KEYS])), C.byref(L.G3D(cap3, *[_ptr(b3[k]) for k in G3_KEYS])),
+            _stream()))
+        moved.append((_first_rows(b3, k3), _first_rows(b4, k4)))
+    return g3n, g4n, perm[:n4], moved
+
+
+def densify(rast: Rasterizer, g3: dict, g4: dict, stats3: dict, stats4: dict, noise3: torch.Tensor,
+            noise4: torch.Tensor, p3: L.DensifyParams, p4: L.DensifyParams, moments=()):
+    """Clone / split / prune of each set (h4dgs_densify).  noise3: float32
+    [split_n, 3, n3], noise4: [split_n, 4, n4] standard normal draws.  Returns
+    (g3', g4', src3, src4[, moved]) where moved lists the moment pairs
+    (m3, m4) gathered to the new rows (zeros for new rows)."""
+    s3, s4 = g3_struct(g3), g4_struct(g4)
+    n3, n4 = s3.n, s4.n
+    cap3, cap4 = n3 * max(2, p3.split_n), n4 * max(2, p4.split_n)
+    o3, o4 = _set_buffers(cap3, cap4)
+    src3 = torch.empty(max(1, cap3), dtype=torch.int32, device="cuda")
+    src4 = torch.empty(max(1, cap4), dtype=torch.int32, device="cuda")
+    nsc = int(rast.ctx.L.h4dgs_densify_scratch_bytes(n3, n4))
+    scratch = torch.empty(max(256, nsc), dtype=torch.uint8, device="cuda")
+    st3, st4 = _stats_struct(stats3, n3), _stats_struct(stats4, n4)
+    n3o, n4o = C.c_int32(), C.c_int32()
+    for t, shape in ((noise3, (p3.split_n, 3, n3)), (noise4, (p4.split_n, 4, n4))):
+        if tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"noise: expected a contiguous float32 CUDA tensor of shape {shape}")
+    rast.ctx.check(rast.ctx.L.h4dgs_densify(
+        rast.ctx.h, C.byref(s3), C.byref(s4), C.byref(st3), C.byref(st4), _ptr(noise3), _ptr(noise4),
+        C.byref(p3), C.byref(p4), C.byref(L.G3D(cap3, *[_ptr(o3[k]) for k in G3_KEYS])),
+        C.byref(L.G4D(cap4, *[_ptr(o4[k]) for k in G4_KEYS])), _ptr(src3), _ptr(src4), C.byref(n3o), C.byref(n4o),
+        _ptr(scratch), scratch.numel(), _stream()))
+    k3, k4 = n3o.value, n4o.value
+    out = [_first_rows(o3, k3), _first_rows(o4, k4), src3[:k3].clone(), src4[:k4].clone()]
+    if not moments:
+        return tuple(out)
+    moved = []
+    for a3, a4 in moments:
+        b3, b4 = _set_buffers(k3, k4)
+        rast.ctx.check(rast.ctx.L.h4dgs_gather_rows(
+            rast.ctx.h, C.byref(g3_struct(a3)), C.byref(g4_struct(a4)), _ptr(src3), k3, _ptr(src4), k4,
+            C.byref(L.G3D(k3, *[_ptr(b3[k]) for k in G3_KEYS])), C.byref(L.G4D(k4, *[_ptr(b4[k]) for k in G4_KEYS])),
+            _stream()))
+        moved.append((b3, b4))
+    return tuple(out) + (moved,)
 
 
 class CapturedStep:
@@ -384,9 +472,26 @@ class CapturedStep:
         return self.rast.verify()
 
 
-def adam_step(rast: Rasterizer, params, grads, ms, vs, lrs, step: int, betas=(0.9, 0.999), eps=1e-8):
-    """One Adam step over lists of float32 CUDA tensors (in place on params, ms, vs)."""
+def adam_step(rast: Rasterizer, params, grads, ms, vs, lrs, step: int, betas=(0.9, 0.999), eps=1e-8,
+              masks=None):
+    """One Adam step over lists of float32 CUDA tensors (in place on params,
+    ms, vs).  masks: optional list of (uint8 [rows] CUDA tensor or None) per
+    parameter: only the rows (Gaussians) whose mask is set are updated."""
     n = len(params)
+    if masks is not None:
+        for i in range(0, n, 16):
+            sl = slice(i, min(n, i + 16))
+            P, G, M, V, K = params[sl], grads[sl], ms[sl], vs[sl], masks[sl]
+            k = len(P)
+            sizes = (C.c_int64 * k)(*[int(p.numel()) for p in P])
+            rows = (C.c_int64 * k)(*[int(mk.numel()) if mk is not None else 0 for mk in K])
+            lr = (C.c_float * k)(*[float(x) for x in lrs[sl]])
+            mp = L.ptr_array([mk.data_ptr() if mk is not None and mk.numel() else 0 for mk in K])
+            rast.ctx.check(rast.ctx.L.h4dgs_adam_masked(
+                rast.ctx.h, k, L.ptr_array([p.data_ptr() for p in P]), L.ptr_array([g.data_ptr() for g in G]),
+                L.ptr_array([m.data_ptr() for m in M]), L.ptr_array([v.data_ptr() for v in V]), sizes, lr, mp, rows,
+                C.c_double(betas[0]), C.c_double(betas[1]), C.c_double(eps), int(step), _stream()))
+        return
     for i in range(0, n, 16):
         sl = slice(i, min(n, i + 16))
         P, G, M, V = params[sl], grads[sl], ms[sl], vs[sl]

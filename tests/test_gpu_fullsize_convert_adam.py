@@ -103,3 +103,46 @@ def test_adam_full_size_sampled(h4d):
             assert (np.abs(P[i][idx[i]].cpu().numpy() - po) <= ptol + 1e-12).all(), (step, i)
     del P, M, V, G
     torch.cuda.empty_cache()
+
+
+def _moved_moments(m3, m4, perm):
+    """The moment arrays after the conversion, gathered on the host with the
+    oracle's permutation: kept 4D rows in order; old 3D rows, then converted
+    rows with the moments of their copied fields and zeros for the quaternion."""
+    keep = np.nonzero(perm >= 0)[0]
+    keep = keep[np.argsort(perm[keep])]
+    conv = np.nonzero(perm < 0)[0]
+    conv = conv[np.argsort(-1 - perm[conv])]
+    o4 = {k: v[..., keep] for k, v in m4.items()}
+    add = dict(mean=m4["mean"][:, conv], log_scale=m4["log_scale"][:3, conv],
+               quat=np.zeros((4, conv.size), np.float32), opacity=m4["opacity"][conv], sh=m4["sh"][:, conv])
+    o3 = {k: np.concatenate([m3[k], add[k]], axis=-1) for k in m3}
+    return o3, o4
+
+
+@pytest.mark.parametrize("frac", [0.5, 0.9])
+def test_convert_moments_full_size(h4d, frac):
+    """Adam's moments follow the conversion (500k 4D Gaussians plus 100k 3D
+    ones): bit-exact against a host gather driven by the oracle's permutation,
+    with zeros for the converted rows' new quaternions."""
+    print(f"[convert moments] 500k, static fraction {frac}", flush=True)
+    scene = sg.hybrid_ratio_scene(frac)
+    rng = np.random.default_rng(int(10 * frac))
+    scene.g3 = sg.draw_3d(rng, 100_000, 2.0)
+    moms = []
+    for _ in range(2):
+        m3 = {k: rng.normal(size=v.shape).astype(np.float32) for k, v in scene.g3.items()}
+        m4 = {k: rng.normal(size=v.shape).astype(np.float32) for k, v in scene.g4.items()}
+        moms.append((m3, m4))
+    rperm, rn4, rn3, _ = oracle.convert_static(scene, 0.5)
+    rast = h4d.Rasterizer()
+    o3, o4, perm, moved = h4d.convert_static(rast, h4d.to_device(scene.g3), h4d.to_device(scene.g4), 0.5,
+                                             moments=[(h4d.to_device(a), h4d.to_device(b)) for a, b in moms])
+    assert np.array_equal(perm.cpu().numpy(), rperm)
+    for (m3, m4), (g3m, g4m) in zip(moms, moved):
+        w3, w4 = _moved_moments(m3, m4, rperm)
+        for k in w4:
+            assert np.array_equal(g4m[k].cpu().numpy(), w4[k]), k
+        for k in w3:
+            assert np.array_equal(g3m[k].cpu().numpy(), w3[k]), k
+        assert g3m["opacity"].shape[0] == rn3 and g4m["opacity"].shape[0] == rn4

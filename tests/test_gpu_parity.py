@@ -325,6 +325,31 @@ def test_convert_static_bit_exact(h4d, frac):
         assert np.abs(qn - rn).max() <= 1e-6
 
 
+def test_convert_moments_follow_the_rows(h4d):
+    """Two moment sets (Adam's m and v) moved with the conversion of a small
+    mixed scene: bit-exact against a host gather driven by the oracle's
+    permutation (converted rows keep the moments of their copied fields and
+    start their quaternion's at zero)."""
+    from test_gpu_fullsize_convert_adam import _moved_moments
+    rng = np.random.default_rng(17)
+    g4 = sg.draw_4d(rng, 2000, 2.0, static_fraction=0.4, tau=0.5)
+    g3 = sg.draw_3d(rng, 700, 2.0)
+    scene = sg.Scene(g3, g4)
+    moms = [({k: rng.normal(size=v.shape).astype(np.float32) for k, v in g3.items()},
+             {k: rng.normal(size=v.shape).astype(np.float32) for k, v in g4.items()}) for _ in range(2)]
+    rperm, rn4, rn3, _ = oracle.convert_static(scene, 0.5)
+    rast = h4d.Rasterizer()
+    _, _, perm, moved = h4d.convert_static(rast, h4d.to_device(g3), h4d.to_device(g4), 0.5,
+                                           moments=[(h4d.to_device(a), h4d.to_device(b)) for a, b in moms])
+    assert np.array_equal(perm.cpu().numpy(), rperm) and (rperm < 0).sum() > 100
+    for (m3, m4), (g3m, g4m) in zip(moms, moved):
+        w3, w4 = _moved_moments(m3, m4, rperm)
+        for k in w4:
+            assert np.array_equal(g4m[k].cpu().numpy(), w4[k]), k
+        for k in w3:
+            assert np.array_equal(g3m[k].cpu().numpy(), w3[k]), k
+
+
 def test_convert_static_empty_sets(h4d):
     rast = h4d.Rasterizer()
     g3 = sg.draw_3d(np.random.default_rng(0), 10, 1.0)
