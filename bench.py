@@ -296,10 +296,28 @@ def training_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
     n3, n4 = int(g3["opacity"].numel()), int(g4["opacity"].numel())
     n_scalars = sum(p.numel() for p in params)
     alg = alg_bytes(n3, n4, 1, cnt, 4 * W * H)
+    # the static identification every 500 steps: convert_static(0.5) with the
+    # Adam moments moved along, timed on the step's sets and spread over 500 steps
+    m3 = {k: ms[i] for i, (w, k) in enumerate(keys) if w == "3"}
+    m4 = {k: ms[i] for i, (w, k) in enumerate(keys) if w == "4"}
+    v3 = {k: vs[i] for i, (w, k) in enumerate(keys) if w == "3"}
+    v4 = {k: vs[i] for i, (w, k) in enumerate(keys) if w == "4"}
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o3, o4, _, moved = h4d.convert_static(rast, g3, g4, 0.5, moments=[(m3, m4), (v3, v4)])
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        del o3, o4, moved
+    conv_ms = 1e3 * float(np.median(ts))
+    per = dt * 1e3 + conv_ms / 500.0
     return {"workload": "training_2M_2704x2028_4_views", "gaussians": n_gauss, "ms_per_step": round(dt * 1e3, 3),
             "mpix_s": round(mpix / dt, 2), "views_per_step": 4, "step": "fwd+L1+bwd+Adam, batched",
             "pairs_per_step": rast.last_pairs, "counts": {k: int(v) for k, v in cnt.items()},
-            "hbm": hbm_entry(alg["total"] + B_ADAM * n_scalars, dt)}
+            "hbm": hbm_entry(alg["total"] + B_ADAM * n_scalars, dt),
+            "convert_every_500": {"convert_with_moments_ms": round(conv_ms, 3),
+                                  "ms_per_step_amortized": round(per, 4), "mpix_s_amortized": round(mpix / per * 1e3, 2)}}
 
 
 def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
