@@ -34,10 +34,11 @@ def build(force: bool = False) -> str:
 
 class _OScene(C.Structure):
     _fields_ = [("n3", C.c_int32)] + [(k, C.c_void_p) for k in ("mean3", "ls3", "q3", "op3", "sh3")] + \
-               [("n4", C.c_int32)] + [(k, C.c_void_p) for k in ("mean4", "mt4", "ls4", "ql4", "qr4", "op4", "sh4")]
+               [("n4", C.c_int32)] + [(k, C.c_void_p) for k in ("mean4", "mt4", "ls4", "ql4", "qr4", "op4", "sh4")] + \
+               [("sht_deg", C.c_int32), ("sht_period", C.c_double), ("sht4", C.c_void_p)]
 
 
-_GRAD_FIELDS = ("mean3", "ls3", "q3", "op3", "sh3", "mean4", "mt4", "ls4", "ql4", "qr4", "op4", "sh4")
+_GRAD_FIELDS = ("mean3", "ls3", "q3", "op3", "sh3", "mean4", "mt4", "ls4", "ql4", "qr4", "op4", "sh4", "sht4")
 
 
 class _OTangent(C.Structure):
@@ -97,10 +98,16 @@ def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
-class _SceneRef:
-    """Keeps the contiguous float32 arrays alive while the C struct points at them."""
+def _period(scene) -> float:
+    return float(getattr(scene, "time_period", 1.0))
 
-    def __init__(self, g3: dict, g4: dict):
+
+class _SceneRef:
+    """Keeps the contiguous float32 arrays alive while the C struct points at them.
+    A 4D set may carry time coefficients of its colour, g4["sh_t"] = [48 D][n4]
+    (D = 1 or 2), with period `period`."""
+
+    def __init__(self, g3: dict, g4: dict, period: float = 1.0):
         self.keep = []
 
         def f(a):
@@ -110,9 +117,13 @@ class _SceneRef:
 
         self.n3 = int(np.asarray(g3["opacity"]).shape[0])
         self.n4 = int(np.asarray(g4["opacity"]).shape[0])
+        sht = g4.get("sh_t")
+        deg = 0 if sht is None else int(np.asarray(sht).shape[0]) // 48
+        assert sht is None or (np.asarray(sht).shape[0] == 48 * deg and 1 <= deg <= 2 and period > 0)
         self.s = _OScene(self.n3, f(g3["mean"]), f(g3["log_scale"]), f(g3["quat"]), f(g3["opacity"]), f(g3["sh"]),
                          self.n4, f(g4["mean"]), f(g4["mean_t"]), f(g4["log_scale"]), f(g4["quat_l"]),
-                         f(g4["quat_r"]), f(g4["opacity"]), f(g4["sh"]))
+                         f(g4["quat_r"]), f(g4["opacity"]), f(g4["sh"]), deg, float(period),
+                         f(sht) if sht is not None else None)
 
     @property
     def ref(self):
@@ -138,7 +149,7 @@ def render(scene, view, tile: int = 16):
     """FP64 forward of one view.  Returns dict(img[3,H,W], T[H,W], nblend[H,W],
     amb[H,W]); ``amb`` flags pixels touched by a decision within the FP32 guard band."""
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     V = _view(view)
     H, W = view.height, view.width
     img = np.zeros((3, H, W), np.float64)
@@ -152,7 +163,7 @@ def render(scene, view, tile: int = 16):
 
 def render_jvp(scene, tangent3: dict, tangent4: dict, view, tile: int = 16):
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     keep = []
 
     def d(a):
@@ -165,7 +176,8 @@ def render_jvp(scene, tangent3: dict, tangent4: dict, view, tile: int = 16):
     t = _OTangent(d(tangent3.get("mean")), d(tangent3.get("log_scale")), d(tangent3.get("quat")),
                   d(tangent3.get("opacity")), d(tangent3.get("sh")), d(tangent4.get("mean")),
                   d(tangent4.get("mean_t")), d(tangent4.get("log_scale")), d(tangent4.get("quat_l")),
-                  d(tangent4.get("quat_r")), d(tangent4.get("opacity")), d(tangent4.get("sh")))
+                  d(tangent4.get("quat_r")), d(tangent4.get("opacity")), d(tangent4.get("sh")),
+                  d(tangent4.get("sh_t")))
     V = _view(view)
     img = np.zeros((3, view.height, view.width), np.float64)
     dimg = np.zeros_like(img)
@@ -183,11 +195,11 @@ def render_bwd(scene, views, dl_dimgs, tile: int = 16, want_g2: bool = False):
     """FP64 adjoint.  Gradients are summed over ``views``.  Returns (g3, g4[, g2])
     with float64 arrays shaped like the parameters; g2 is [n_views][N][9]."""
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     g3, g4 = zeros_like_params(scene)
     G = _OGrad(_p(g3["mean"]), _p(g3["log_scale"]), _p(g3["quat"]), _p(g3["opacity"]), _p(g3["sh"]),
                _p(g4["mean"]), _p(g4["mean_t"]), _p(g4["log_scale"]), _p(g4["quat_l"]), _p(g4["quat_r"]),
-               _p(g4["opacity"]), _p(g4["sh"]))
+               _p(g4["opacity"]), _p(g4["sh"]), _p(g4.get("sh_t")))
     N = scene.n3 + scene.n4
     g2s = []
     for v, dl in zip(views, dl_dimgs):
@@ -203,7 +215,7 @@ def render_bwd(scene, views, dl_dimgs, tile: int = 16, want_g2: bool = False):
 
 def project(scene, view) -> dict:
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     V = _view(view)
     N = scene.n3 + scene.n4
     out = np.zeros((N, 20), np.float64)
@@ -215,7 +227,7 @@ def project(scene, view) -> dict:
 
 def world(scene, g: int, t: float):
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     mu = np.zeros(3)
     Sg = np.zeros(9)
     op = np.zeros(3)
@@ -259,7 +271,7 @@ def sh_basis(d):
 def pixels(scene, view, px, py):
     """Brute-force colour of selected pixels (no tiles).  Returns (rgb[n,3], T[n], amb[n])."""
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     V = _view(view)
     px = _c(px, np.int32)
     py = _c(py, np.int32)
@@ -303,7 +315,7 @@ def composite_records(rec: dict, W: int, H: int, tile: int = 16, bg=(0.0, 0.0, 0
 def convert_static(scene, tau: float):
     """Returns (perm[n4], n4_out, n3_out, q3d[4, n_conv])."""
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     n4 = scene.n4
     perm = np.zeros(n4, np.int32)
     n4o = np.zeros(1, np.int32)
@@ -330,7 +342,7 @@ def blended_at(scene, view, px, py, cap: int = 512, tile: int = 16):
     """The Gaussians blended at the given pixels, front to back: a list per
     pixel of (merged id, blend weight alpha T) pairs."""
     L = lib()
-    sr = _SceneRef(scene.g3, scene.g4)
+    sr = _SceneRef(scene.g3, scene.g4, _period(scene))
     V = _view(view)
     px, py = _c(px, np.int32), _c(py, np.int32)
     n = px.shape[0]
@@ -367,7 +379,7 @@ class Local:
 
     def __init__(self, scene, views, sel, tile: int = 16):
         L = lib()
-        self._sr = _SceneRef(scene.g3, scene.g4)
+        self._sr = _SceneRef(scene.g3, scene.g4, _period(scene))
         self._views = (_OView * len(views))(*[_view(v) for v in views])
         self.views = list(views)
         self.sel = _c(sel, np.int32)

@@ -98,14 +98,19 @@ struct OScene {
     const float *mean3, *ls3, *q3, *op3, *sh3;              // [3][n3] [3][n3] [4][n3] [n3] [48][n3]
     int32_t n4;
     const float *mean4, *mt4, *ls4, *ql4, *qr4, *op4, *sh4; // [3] [1] [4] [4] [4] [1] [48] x n4
+    int32_t sht_deg;     // time degree D of the 4D colour (0: plain SH)
+    double sht_period;   // period T of its cosine terms
+    const float *sht4;   // [48 D] x n4: coefficients of cos(2 pi n (t - mu_t) / T), n = 1 .. D
 };
 struct OTangent {  // same layout as OScene, float64, any pointer may be null (= zero tangent)
     const double *mean3, *ls3, *q3, *op3, *sh3;
     const double *mean4, *mt4, *ls4, *ql4, *qr4, *op4, *sh4;
+    const double *sht4;
 };
-struct OGrad {     // float64 outputs, same layout as OScene
+struct OGrad {     // float64 outputs, same layout as OScene (sht4 may be null when D = 0)
     double *mean3, *ls3, *q3, *op3, *sh3;
     double *mean4, *mt4, *ls4, *ql4, *qr4, *op4, *sh4;
+    double *sht4;
 };
 struct OView {
     double R[9], T[3];   // world -> camera, row-major
@@ -121,9 +126,13 @@ struct OView {
 // g >= n4 is the 3D row g - n4 (Alg. 1 projects the 4D set first, then appends
 // the 3D set to the same screen-space array M').
 // ---------------------------------------------------------------------------
+constexpr int kMaxTimeDeg = 2;
 template <class S> struct Param {
     bool is4d;
     S mu[3], mt, ls[4], q[4], q2[4], op, sh[48];
+    int sht_deg;       // time degree of the colour (4D only)
+    double period;
+    S sht[48 * kMaxTimeDeg];
 };
 
 template <class S> inline S mk(float x, const double* tan, size_t idx) {
@@ -143,6 +152,10 @@ template <class S> void load_param(const OScene& sc, const OTangent* tg, int g, 
         for (int k = 0; k < 4; ++k) P.q2[k] = mk<S>(sc.qr4[k * n + i], tg ? tg->qr4 : nullptr, k * n + i);
         P.op = mk<S>(sc.op4[i], tg ? tg->op4 : nullptr, i);
         for (int k = 0; k < 48; ++k) P.sh[k] = mk<S>(sc.sh4[k * n + i], tg ? tg->sh4 : nullptr, k * n + i);
+        P.sht_deg = sc.sht_deg;
+        P.period = sc.sht_period;
+        for (int k = 0; k < 48 * sc.sht_deg; ++k)
+            P.sht[k] = mk<S>(sc.sht4[k * n + i], tg ? tg->sht4 : nullptr, k * n + i);
     } else {
         const size_t n = (size_t)sc.n3, i = (size_t)(g - n4);
         P.is4d = false;
@@ -154,6 +167,21 @@ template <class S> void load_param(const OScene& sc, const OTangent* tg, int g, 
         for (int k = 0; k < 4; ++k) P.q2[k] = S(0.0);
         P.op = mk<S>(sc.op3[i], tg ? tg->op3 : nullptr, i);
         for (int k = 0; k < 48; ++k) P.sh[k] = mk<S>(sc.sh3[k * n + i], tg ? tg->sh3 : nullptr, k * n + i);
+        P.sht_deg = 0;
+        P.period = 1.0;
+    }
+}
+
+// Colour coefficients of a Gaussian at time t (4D spherindrical harmonics, the
+// colour model 4D Gaussian splatting uses): for a 4D Gaussian of time degree
+// D, c_j = sh_j + sum_{n=1..D} cos(2 pi n (t - mu_t) / T) sht_{n,j}; otherwise
+// c_j = sh_j.
+template <class S> void sh_at(const Param<S>& P, double time, S c[48]) {
+    for (int j = 0; j < 48; ++j) c[j] = P.sh[j];
+    if (!P.is4d) return;
+    for (int n = 1; n <= P.sht_deg; ++n) {
+        const S w = cos(S(2.0 * M_PI * n / P.period) * (S(time) - P.mt));
+        for (int j = 0; j < 48; ++j) c[j] += w * P.sht[(n - 1) * 48 + j];
     }
 }
 
@@ -390,11 +418,12 @@ template <class S> void project(const OView& V, const Param<S>& P, const Geo<S>&
     S e[3] = {G.mu[0] - S(C[0]), G.mu[1] - S(C[1]), G.mu[2] - S(C[2])};
     const S en = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
     S dir[3] = {e[0] / en, e[1] / en, e[2] / en};
-    S Y[16];
+    S Y[16], cf[48];
     sh_basis(dir, Y);
+    sh_at(P, V.time, cf);
     for (int ch = 0; ch < 3; ++ch) {
         S acc = S(kShOffset);
-        for (int k = 0; k < 16; ++k) acc += P.sh[k * 3 + ch] * Y[k];
+        for (int k = 0; k < 16; ++k) acc += cf[k * 3 + ch] * Y[k];
         r.rgb[ch] = val(acc) > 0.0 ? acc : S(0.0);
         if (!(val(acc) > 0.0)) r.kinks |= 1 << ch;
     }
@@ -605,8 +634,10 @@ inline void sh_basis_grad(const double dir[3], double dY[16][3]) {
 }
 
 // per-Gaussian chain rule for one view; accumulates into grad arrays of Gaussian g
+// gsh receives the gradient of this view's colour coefficients (sh_at);
+// gsht (may be null) the accumulated gradient of the time coefficients.
 void gaussian_bwd(const OScene& sc, int g, const OView& V, const G2& gs, double* gmu, double* gmt, double* gls,
-                  double* gq, double* gq2, double* gop, double* gsh) {
+                  double* gq, double* gq2, double* gop, double* gsh, double* gsht) {
     Param<double> P;
     load_param<double>(sc, nullptr, g, P);
     // ---- forward recomputation
@@ -672,18 +703,33 @@ void gaussian_bwd(const OScene& sc, int g, const OView& V, const G2& gs, double*
     // ---- colour adjoint (clamp at zero passes the gradient only where raw > 0)
     double gmu_c[3] = {0, 0, 0};
     double gdir[3] = {0, 0, 0};
-    double dY[16][3];
+    double dY[16][3], cf[48], gcf[48];
     sh_basis_grad(dir, dY);
+    sh_at(P, V.time, cf);
+    for (int j = 0; j < 48; ++j) gcf[j] = 0.0;
     for (int ch = 0; ch < 3; ++ch) {
         double raw = kShOffset;
-        for (int k = 0; k < 16; ++k) raw += P.sh[k * 3 + ch] * Y[k];
+        for (int k = 0; k < 16; ++k) raw += cf[k * 3 + ch] * Y[k];
         const double gc = raw > 0.0 ? gs.rgb[ch] : 0.0;
         if (gc == 0.0) continue;
         for (int k = 0; k < 16; ++k) {
-            gsh[k * 3 + ch] += gc * Y[k];
-            for (int a3 = 0; a3 < 3; ++a3) gdir[a3] += gc * P.sh[k * 3 + ch] * dY[k][a3];
+            gcf[k * 3 + ch] += gc * Y[k];
+            for (int a3 = 0; a3 < 3; ++a3) gdir[a3] += gc * cf[k * 3 + ch] * dY[k][a3];
         }
     }
+    for (int j = 0; j < 48; ++j) gsh[j] += gcf[j];
+    // time coefficients: dc_j/dsht_{n,j} = cos(phase_n); dc_j/dmu_t =
+    // sum_n (2 pi n / T) sin(phase_n) sht_{n,j}, phase_n = 2 pi n (t - mu_t) / T
+    if (P.is4d)
+        for (int n = 1; n <= P.sht_deg; ++n) {
+            const double k2 = 2.0 * M_PI * n / P.period, ph = k2 * (V.time - P.mt);
+            double acc = 0.0;
+            for (int j = 0; j < 48; ++j) {
+                if (gsht) gsht[(n - 1) * 48 + j] += std::cos(ph) * gcf[j];
+                acc += gcf[j] * P.sht[(n - 1) * 48 + j];
+            }
+            *gmt += k2 * std::sin(ph) * acc;
+        }
     {
         const double dd = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
         for (int i = 0; i < 3; ++i) gmu_c[i] += (gdir[i] - dir[i] * dd) / en;
@@ -938,11 +984,14 @@ void render_view_bwd(const OScene& sc, const OView& V, int B, const float* dimg,
     for (int g = 0; g < N; ++g) {
         if (!recs[g].visible) continue;
         double gmu[3] = {0, 0, 0}, gmt = 0, gls[4] = {0, 0, 0, 0}, gq[4] = {0, 0, 0, 0}, gq2[4] = {0, 0, 0, 0}, gop = 0,
-               gsh[48];
+               gsh[48], gsht[48 * kMaxTimeDeg];
         std::memset(gsh, 0, sizeof(gsh));
-        gaussian_bwd(sc, g, V, g2[g], gmu, &gmt, gls, gq, gq2, &gop, gsh);
+        std::memset(gsht, 0, sizeof(gsht));
+        gaussian_bwd(sc, g, V, g2[g], gmu, &gmt, gls, gq, gq2, &gop, gsh, gsht);
         if (g < n4) {
             const size_t n = n4, i = g;
+            if (grad.sht4)
+                for (int k = 0; k < 48 * sc.sht_deg; ++k) grad.sht4[k * n + i] += gsht[k];
             for (int k = 0; k < 3; ++k) grad.mean4[k * n + i] += gmu[k];
             grad.mt4[i] += gmt;
             for (int k = 0; k < 4; ++k) grad.ls4[k * n + i] += gls[k];
@@ -1293,6 +1342,7 @@ int orc_mat2quat(const double* R, double* q) {
 // (4D rows first), distinct.
 void* orc_local_new(const OScene* sc, int n_views, const OView* views, int B, int n_sel, const int32_t* sel) {
     if (!sc || !views || n_views < 1 || B <= 0 || n_sel < 0) return nullptr;
+    if (sc->sht_deg != 0) return nullptr;  // local rows hold no time coefficients
     const int N = sc->n3 + sc->n4;
     Local* L = new Local();
     L->sc = *sc;
@@ -1397,7 +1447,7 @@ int orc_local_grad(void* h, const float* const* dimgs, double* rows) {
             double gmu[3] = {0, 0, 0}, gmt = 0, gls[4] = {0, 0, 0, 0}, gq[4] = {0, 0, 0, 0}, gq2[4] = {0, 0, 0, 0},
                    gop = 0, gsh[48];
             std::memset(gsh, 0, sizeof(gsh));
-            gaussian_bwd(L->sc, g, lv.V, gs, gmu, &gmt, gls, gq, gq2, &gop, gsh);
+            gaussian_bwd(L->sc, g, lv.V, gs, gmu, &gmt, gls, gq, gq2, &gop, gsh, nullptr);
             double* o = rows + (size_t)s * kRow;
             if (g < L->sc.n4) {
                 for (int k = 0; k < 3; ++k) o[k] += gmu[k];

@@ -152,6 +152,7 @@ class Scene:
     g4: dict
     views: list = field(default_factory=list)
     name: str = ""
+    time_period: float = 1.0  # period of the 4D colour's cosine terms (g4["sh_t"], when present)
 
     @property
     def n3(self) -> int:
@@ -275,13 +276,25 @@ def raw_quaternion_norms(scene: Scene, seed: int = 6, lo: float = 0.5, hi: float
         for k in keys:
             q = d[k].astype(np.float64)
             d[k] = _f32(q * rng.uniform(lo, hi, size=(1, q.shape[1])))
-    return Scene(g3, g4, list(scene.views), name=scene.name + "_raw_quats")
+    return Scene(g3, g4, list(scene.views), name=scene.name + "_raw_quats", time_period=scene.time_period)
+
+
+def with_time_colour(scene: Scene, degree: int = 1, seed: int = 7, sigma: float = 0.3,
+                     period: float = 1.0) -> Scene:
+    """The same scene whose 4D Gaussians also carry time coefficients of
+    their colour, g4["sh_t"] = [48 degree][n4] ~ N(0, sigma) (the cosine terms
+    of 4D Gaussian splatting's colour model), with the given period."""
+    rng = np.random.default_rng(seed)
+    g4 = dict(scene.g4)
+    g4["sh_t"] = _f32(rng.normal(0.0, sigma, size=(48 * degree, scene.n4)))
+    return Scene(dict(scene.g3), g4, list(scene.views), name=scene.name + f"_time_colour{degree}",
+                 time_period=float(period))
 
 
 def subset(scene: Scene, idx3, idx4) -> Scene:
     g3 = {k: np.ascontiguousarray(v[..., idx3]) for k, v in scene.g3.items()}
     g4 = {k: np.ascontiguousarray(v[..., idx4]) for k, v in scene.g4.items()}
-    return Scene(g3, g4, list(scene.views), name=scene.name + "_subset")
+    return Scene(g3, g4, list(scene.views), name=scene.name + "_subset", time_period=scene.time_period)
 
 
 def synthetic_records(n: int, width: int, height: int, seed: int = 5, max_radius: int = 60) -> dict:
