@@ -62,14 +62,24 @@ typedef struct {
 /* Dynamic 4D Gaussians (Sec. 3.2, Eq. 4-7): spatial mean[3][n], temporal
  * mean mean_t[n], log_scale[4][n] (x, y, z, t), quat_l[4][n] = (a,b,c,d) and
  * quat_r[4][n] = (p,q,r,s) of the left/right isoclinic rotations, opacity[n]
- * (logit), sh[48][n]. */
+ * (logit), sh[48][n].
+ * Optional time-varying colour (the cosine terms of 4D Gaussian splatting's
+ * colour model, which the paper's 4D Gaussians inherit, end of Sec. 3.2):
+ * with sh_t_degree D in {1, 2}, sh_t[48 D][n] and a period T = sh_t_period,
+ * the SH coefficients at view time t are sh + sum_{k=1..D} cos(2 pi k (t -
+ * mean_t) / T) sh_t[k - 1]; D = 0 (sh_t ignored) is plain SH. */
 typedef struct {
     int32_t n;
     const float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+    int32_t sh_t_degree;
+    float sh_t_period;
+    const float *sh_t;
 } h4d_g4d;
 
 /* Writable mirrors: gradients (overwritten by h4dgs_render_bwd) and the
- * outputs of h4dgs_convert_static.  Field meaning and layout as above. */
+ * outputs of h4dgs_convert_static.  Field meaning and layout as above; for a
+ * 4D input with time coefficients the mirror's sh_t must be given (its
+ * degree and period fields are not read). */
 typedef struct {
     int32_t n;
     float *mean, *log_scale, *quat, *opacity, *sh;
@@ -77,6 +87,9 @@ typedef struct {
 typedef struct {
     int32_t n;
     float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+    int32_t sh_t_degree;
+    float sh_t_period;
+    float *sh_t;
 } h4d_g4d_mut;
 
 /* One rendered view (host struct): pinhole camera, world -> camera [R | t]

@@ -49,7 +49,8 @@ class G3D(C.Structure):
 
 class G4D(C.Structure):
     _fields_ = [("n", C.c_int32)] + [(k, C.c_void_p) for k in
-                                     ("mean", "mean_t", "log_scale", "quat_l", "quat_r", "opacity", "sh")]
+                                     ("mean", "mean_t", "log_scale", "quat_l", "quat_r", "opacity", "sh")] + \
+               [("sh_t_degree", C.c_int32), ("sh_t_period", C.c_float), ("sh_t", C.c_void_p)]
 
 
 class View(C.Structure):

@@ -354,12 +354,25 @@ h4d_status check_sets(h4d_ctx* c, const h4d_g3d* g3, const h4d_g4d* g4) {
     if (g4->n > 0 && (!g4->mean || !g4->mean_t || !g4->log_scale || !g4->quat_l || !g4->quat_r || !g4->opacity ||
                       !g4->sh))
         return fail(c, H4D_ERR_INVALID_ARG, "4D set: null array with n = %d", g4->n);
+    if (g4->sh_t_degree < 0 || g4->sh_t_degree > kMaxTimeDeg)
+        return fail(c, H4D_ERR_INVALID_ARG, "4D set: sh_t_degree %d not in [0, %d]", g4->sh_t_degree, kMaxTimeDeg);
+    if (g4->sh_t_degree > 0 && (!(g4->sh_t_period > 0.f) || !std::isfinite(g4->sh_t_period) ||
+                                (g4->n > 0 && !g4->sh_t)))
+        return fail(c, H4D_ERR_INVALID_ARG, "4D set: time coefficients need sh_t and a finite period > 0");
+    return H4D_OK;
+}
+
+// An output mirror of a 4D set with time coefficients must have room for them.
+h4d_status check_time_out(h4d_ctx* c, const h4d_g4d* in4, const h4d_g4d_mut* out4, int32_t rows, const char* what) {
+    if (in4->sh_t_degree > 0 && rows > 0 && !out4->sh_t)
+        return fail(c, H4D_ERR_INVALID_ARG, "%s: the 4D set has time coefficients, the output has no sh_t", what);
     return H4D_OK;
 }
 
 G3Ptr to_ptr(const h4d_g3d* g) { return G3Ptr{g->n, g->mean, g->log_scale, g->quat, g->opacity, g->sh}; }
 G4Ptr to_ptr(const h4d_g4d* g) {
-    return G4Ptr{g->n, g->mean, g->mean_t, g->log_scale, g->quat_l, g->quat_r, g->opacity, g->sh};
+    return G4Ptr{g->n,      g->mean,        g->mean_t,          g->log_scale, g->quat_l, g->quat_r,
+                 g->opacity, g->sh, g->sh_t_degree, g->sh_t_period, g->sh_t};
 }
 
 ViewTableIn view_table(const h4d_view* views, int V, int tile) {
@@ -668,6 +681,7 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
     if (g4->n > 0 && (!grad4->mean || !grad4->mean_t || !grad4->log_scale || !grad4->quat_l || !grad4->quat_r ||
                       !grad4->opacity || !grad4->sh))
         return fail(ctx, H4D_ERR_INVALID_ARG, "4D gradient: null array");
+    if ((s = check_time_out(ctx, g4, grad4, g4->n, "render_bwd")) != H4D_OK) return s;
     const int N = g3->n + g4->n;
     const Layout L = make_layout(N, views, n_views, cfg);
     if (!state || state_bytes < L.state_bytes)
@@ -701,8 +715,8 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
         }
     }
     const G3Grad r3{grad3->n, grad3->mean, grad3->log_scale, grad3->quat, grad3->opacity, grad3->sh};
-    const G4Grad r4{grad4->n, grad4->mean, grad4->mean_t, grad4->log_scale, grad4->quat_l, grad4->quat_r,
-                    grad4->opacity, grad4->sh};
+    const G4Grad r4{grad4->n,       grad4->mean, grad4->mean_t, grad4->log_scale, grad4->quat_l, grad4->quat_r,
+                    grad4->opacity, grad4->sh,   grad4->sh_t};
     const SetStats s3 = stats3 ? SetStats{stats3->grad_norm, stats3->visible, stats3->step_visible}
                                : SetStats{nullptr, nullptr, nullptr};
     const SetStats s4 = stats4 ? SetStats{stats4->grad_norm, stats4->visible, stats4->step_visible}
@@ -828,6 +842,7 @@ h4d_status h4dgs_convert_static(h4d_ctx* ctx, const h4d_g4d* in4, const h4d_g3d*
     if ((in3->n > 0 && (const void*)out3->mean == (const void*)in3->mean) ||
         (in4->n > 0 && (const void*)out4->mean == (const void*)in4->mean))
         return fail(ctx, H4D_ERR_INVALID_ARG, "outputs must not alias inputs");
+    if ((s = check_time_out(ctx, in4, out4, in4->n, "convert_static")) != H4D_OK) return s;
     const int n4 = in4->n;
     const size_t need = h4dgs_convert_scratch_bytes(n4);
     if (!scratch || scratch_bytes < need) return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small (%zu < %zu)",
@@ -838,8 +853,8 @@ h4d_status h4dgs_convert_static(h4d_ctx* ctx, const h4d_g4d* in4, const h4d_g3d*
     Carve c;
     const size_t o_flags = c.take(8 * n), o_scan = c.take(16 * (n + 1)), o_part = c.take(16 * (nb + 1)),
                  o_cnt = c.take(16);
-    const G4Grad o4{out4->n, out4->mean, out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r, out4->opacity,
-                    out4->sh};
+    const G4Grad o4{out4->n,  out4->mean,    out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r,
+                    out4->opacity, out4->sh, out4->sh_t};
     const G3Grad o3{out3->n, out3->mean, out3->log_scale, out3->quat, out3->opacity, out3->sh};
     const double log_tau = std::log((double)tau);
     int32_t* dcounts = at<int32_t>(scratch, o_cnt);
@@ -903,6 +918,7 @@ h4d_status h4dgs_densify(h4d_ctx* ctx, const h4d_g3d* in3, const h4d_g4d* in4, c
     if ((in3->n > 0 && (const void*)out3->mean == (const void*)in3->mean) ||
         (in4->n > 0 && (const void*)out4->mean == (const void*)in4->mean))
         return fail(ctx, H4D_ERR_INVALID_ARG, "outputs must not alias inputs");
+    if ((s = check_time_out(ctx, in4, out4, in4->n, "densify")) != H4D_OK) return s;
     const size_t need = h4dgs_densify_scratch_bytes(in3->n, in4->n);
     if (!scratch || scratch_bytes < need)
         return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small (%zu < %zu)", scratch_bytes, need);
@@ -914,8 +930,8 @@ h4d_status h4dgs_densify(h4d_ctx* ctx, const h4d_g3d* in3, const h4d_g4d* in4, c
                  o_cnt = c.take(16);
     int32_t* dcount = at<int32_t>(scratch, o_cnt);
     const G3Grad o3{out3->n, out3->mean, out3->log_scale, out3->quat, out3->opacity, out3->sh};
-    const G4Grad o4{out4->n, out4->mean, out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r, out4->opacity,
-                    out4->sh};
+    const G4Grad o4{out4->n,  out4->mean,    out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r,
+                    out4->opacity, out4->sh, out4->sh_t};
     int32_t hc[2] = {0, 0};
     // the sets one after another in the same scratch (each ends in a count read back)
     launch_densify3(to_ptr(in3), st3->grad_norm, st3->visible, noise3, to_densify(*p3), o3, src3,
@@ -951,9 +967,10 @@ h4d_status h4dgs_gather_rows(h4d_ctx* ctx, const h4d_g3d* in3, const h4d_g4d* in
     if (rows4 > 0 && (!src4 || !out4->mean || !out4->mean_t || !out4->log_scale || !out4->quat_l || !out4->quat_r ||
                       !out4->opacity || !out4->sh))
         return fail(ctx, H4D_ERR_INVALID_ARG, "4D: null src or output array");
+    if ((s = check_time_out(ctx, in4, out4, rows4, "gather_rows")) != H4D_OK) return s;
     const G3Grad o3{out3->n, out3->mean, out3->log_scale, out3->quat, out3->opacity, out3->sh};
-    const G4Grad o4{out4->n, out4->mean, out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r, out4->opacity,
-                    out4->sh};
+    const G4Grad o4{out4->n,  out4->mean,    out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r,
+                    out4->opacity, out4->sh, out4->sh_t};
     launch_gather_rows(to_ptr(in3), src3, rows3, o3, to_ptr(in4), src4, rows4, o4, static_cast<hipStream_t>(stream));
     return hip_check(ctx, "gather_rows");
 }
@@ -975,8 +992,9 @@ h4d_status h4dgs_convert_moments(h4d_ctx* ctx, const h4d_g4d* in4, const h4d_g3d
     if ((in3->n > 0 && (const void*)out3->mean == (const void*)in3->mean) ||
         (in4->n > 0 && (const void*)out4->mean == (const void*)in4->mean))
         return fail(ctx, H4D_ERR_INVALID_ARG, "outputs must not alias inputs");
-    const G4Grad o4{out4->n, out4->mean, out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r, out4->opacity,
-                    out4->sh};
+    if ((s = check_time_out(ctx, in4, out4, in4->n, "convert_moments")) != H4D_OK) return s;
+    const G4Grad o4{out4->n,  out4->mean,    out4->mean_t, out4->log_scale, out4->quat_l, out4->quat_r,
+                    out4->opacity, out4->sh, out4->sh_t};
     const G3Grad o3{out3->n, out3->mean, out3->log_scale, out3->quat, out3->opacity, out3->sh};
     launch_convert_moments(to_ptr(in4), to_ptr(in3), perm, o4, o3, static_cast<hipStream_t>(stream));
     return hip_check(ctx, "convert_moments");

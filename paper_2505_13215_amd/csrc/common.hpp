@@ -98,6 +98,11 @@ struct G3Ptr {
 struct G4Ptr {
     int32_t n;
     const float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+    // time coefficients of the colour: sh_t[48 sh_t_deg][n], terms cos(2 pi k
+    // (t - mean_t) / sh_t_period), k = 1 .. sh_t_deg (0: plain SH)
+    int32_t sh_t_deg;
+    float sh_t_period;
+    const float* sh_t;
 };
 struct G3Grad {
     int32_t n;
@@ -106,7 +111,9 @@ struct G3Grad {
 struct G4Grad {
     int32_t n;
     float *mean, *mean_t, *log_scale, *quat_l, *quat_r, *opacity, *sh;
+    float* sh_t;  // [48 sh_t_deg][n] of the matching input set, when it has any
 };
+constexpr int kMaxTimeDeg = 2;
 
 // Optional per-Gaussian statistics of one backward call (any pointer may be
 // null): grad += sum over the views in which the Gaussian covers a pixel of

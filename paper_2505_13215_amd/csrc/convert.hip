@@ -1,6 +1,8 @@
 // Static identification and 4D -> 3D conversion on gfx950 (Sec. 4.1-4.2,
 // Eq. 7-9): mask, stable compaction of the 4D set, append of the converted rows
-// to the 3D set with the Eq. 9 quaternion of the spatial rotation block.
+// to the 3D set with the Eq. 9 quaternion of the spatial rotation block.  A
+// converted row keeps its time-independent SH coefficients; its time
+// coefficients (if any) are dropped with the time axis.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -69,6 +71,8 @@ __global__ void k_convert_scatter(G4Ptr in4, const uint32_t* __restrict__ conv,
         for (int k = 0; k < 4; ++k) out4.quat_r[k * no + r] = in4.quat_r[k * ni + i];
         out4.opacity[r] = in4.opacity[i];
         for (int k = 0; k < 48; ++k) out4.sh[k * no + r] = in4.sh[k * ni + i];
+        if (in4.sh_t)
+            for (int k = 0; k < 48 * in4.sh_t_deg; ++k) out4.sh_t[k * no + r] = in4.sh_t[k * ni + i];
         perm[i] = (int32_t)r;
     } else {
         const size_t r = (size_t)n3 + (size_t)conv_off[i];
@@ -139,6 +143,8 @@ __global__ void k_convert_moments(G4Ptr in4, const int32_t* __restrict__ perm, G
         for (int k = 0; k < 4; ++k) out4.quat_r[k * no + r] = in4.quat_r[k * ni + i];
         out4.opacity[r] = in4.opacity[i];
         for (int k = 0; k < 48; ++k) out4.sh[k * no + r] = in4.sh[k * ni + i];
+        if (in4.sh_t)
+            for (int k = 0; k < 48 * in4.sh_t_deg; ++k) out4.sh_t[k * no + r] = in4.sh_t[k * ni + i];
     } else {
         const size_t r = (size_t)(-1 - (int64_t)p), no = (size_t)out3.n;
         for (int k = 0; k < 3; ++k) out3.mean[k * no + r] = in4.mean[k * ni + i];

@@ -87,6 +87,8 @@ __device__ inline void copy_row4(const G4Ptr& g, size_t i, const G4Grad& o, size
     for (int k = 0; k < 4; ++k) o.quat_r[k * no + r] = g.quat_r[k * n + i];
     o.opacity[r] = g.opacity[i];
     for (int k = 0; k < 48; ++k) o.sh[k * no + r] = g.sh[k * n + i];
+    if (g.sh_t)
+        for (int k = 0; k < 48 * g.sh_t_deg; ++k) o.sh_t[k * no + r] = g.sh_t[k * n + i];
 }
 
 // noise: [split_n][3][n] standard normal draws
@@ -206,6 +208,8 @@ __global__ void k_gather_rows4(G4Ptr g, const int32_t* __restrict__ src, int row
     for (int k = 0; k < 4; ++k) o.quat_r[k * no + r] = get(g.quat_r, k);
     o.opacity[r] = get(g.opacity, 0);
     for (int k = 0; k < 48; ++k) o.sh[k * no + r] = get(g.sh, k);
+    if (g.sh_t)
+        for (int k = 0; k < 48 * g.sh_t_deg; ++k) o.sh_t[k * no + r] = get(g.sh_t, k);
 }
 
 namespace {

@@ -226,6 +226,36 @@ __device__ inline void colour(const float* shp, int n, int i, const double Y[16]
     }
 }
 
+// Time weights of a 4D Gaussian's colour at view time t: w[k] = cos(2 pi (k +
+// 1) (t - mean_t) / T) and their derivatives dw[k] with respect to mean_t.
+__device__ inline void time_weights(const G4Ptr& g, int i, double time, double w[kMaxTimeDeg],
+                                    double dw[kMaxTimeDeg]) {
+    const double d = time - (double)g.mean_t[i];
+    for (int k = 0; k < g.sh_t_deg; ++k) {
+        const double om = 2.0 * M_PI * (double)(k + 1) / (double)g.sh_t_period;
+        w[k] = cos(om * d);
+        dw[k] = om * sin(om * d);
+    }
+}
+
+// SH coefficient j of 4D Gaussian i at the time of the weights w.
+__device__ inline double coef_at(const G4Ptr& g, int i, int j, const double w[kMaxTimeDeg]) {
+    const size_t n = (size_t)g.n;
+    double c = (double)g.sh[(size_t)j * n + i];
+    for (int k = 0; k < g.sh_t_deg; ++k) c += w[k] * (double)g.sh_t[((size_t)k * 48 + j) * n + i];
+    return c;
+}
+
+// Time coefficients of a 4D Gaussian's colour in the adjoint (null: none):
+// weights and their mean_t derivatives at the view's time, the set, and the
+// gradient rows (accumulated) of sh_t.
+struct TimeColour {
+    const G4Ptr* g;
+    int i;
+    double w[kMaxTimeDeg], dw[kMaxTimeDeg];
+    float* gsht;
+};
+
 // ---------------------------------------------------------------------------
 // Forward kernel: one thread per Gaussian of the merged list [4D | 3D].
 // ---------------------------------------------------------------------------
@@ -264,7 +294,17 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
         const double s = -0.5 * 1.4426950408889634;  // -log2(e)/2
         double Y[16], raw[3];
         sh_eval(p.dir[0], p.dir[1], p.dir[2], Y);
-        colour(shp, shn, shi, Y, raw);
+        if (g < g4.n && g4.sh_t_deg > 0) {
+            double tw[kMaxTimeDeg], tdw[kMaxTimeDeg];
+            time_weights(g4, g, V.time, tw, tdw);
+            for (int ch = 0; ch < 3; ++ch) {
+                double acc = kShOffset;
+                for (int k = 0; k < 16; ++k) acc += coef_at(g4, g, k * 3 + ch, tw) * Y[k];
+                raw[ch] = acc;
+            }
+        } else {
+            colour(shp, shn, shi, Y, raw);
+        }
         const double fu = floor(p.u), fv = floor(p.v);
         rec.a = make_float4((float)(p.u - fu), (float)(p.v - fv), (float)(Qa * s), (float)(Qb * 2.0 * s));
         rec.b = make_float4((float)(Qc * s), (float)w.op, (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0));
@@ -296,9 +336,13 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
 // part of Sigma4-bar, which is summed over views so that the covariance and
 // rotation adjoints run once per Gaussian.
 // ---------------------------------------------------------------------------
+// TIME: tc holds the Gaussian's time coefficients; their gradient rows are
+// accumulated and gmt receives mean_t's share through the time weights (a
+// separate instantiation, so that sets without them compile as plain SH).
+template <bool TIME>
 __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const ProjF& p, const float* shp, int shn,
                                 int shi, const float* g2, size_t gstride, double gmu[3], double Sb[3][3],
-                                double& gop, float* gsh) {
+                                double& gop, float* gsh, const TimeColour* tc = nullptr, double* gmt = nullptr) {
     const double gu = g2[0], gv = g2[gstride], gQa = g2[2 * gstride], gQb = g2[3 * gstride],
                  gQc = g2[4 * gstride];
     gop = g2[5 * gstride];
@@ -306,7 +350,15 @@ __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const Proj
     // colour
     double Y[16], raw[3];
     sh_eval(p.dir[0], p.dir[1], p.dir[2], Y);
-    colour(shp, shn, shi, Y, raw);
+    auto cf = [&](int j) {
+        if constexpr (TIME) return coef_at(*tc->g, tc->i, j, tc->w);
+        else return (double)shp[(size_t)j * shn + shi];
+    };
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = kShOffset;
+        for (int k = 0; k < 16; ++k) acc += cf(k * 3 + ch) * Y[k];
+        raw[ch] = acc;
+    }
     double gc[3];
     for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] > 0.0 ? grgb[ch] : 0.0;
     double wY[16];
@@ -314,9 +366,22 @@ __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const Proj
         double acc = 0.0;
         for (int ch = 0; ch < 3; ++ch) {
             gsh[k * 3 + ch] += (float)(gc[ch] * Y[k]);
-            acc += gc[ch] * (double)shp[(size_t)(k * 3 + ch) * shn + shi];
+            acc += gc[ch] * cf(k * 3 + ch);
         }
         wY[k] = acc;
+    }
+    if constexpr (TIME) {
+        // dc_j / dsh_t[k][j] = w[k], dc_j / dmean_t = sum_k dw[k] sh_t[k][j]
+        const size_t n = (size_t)tc->g->n;
+        double gm = 0.0;
+        for (int kk = 0; kk < tc->g->sh_t_deg; ++kk)
+            for (int j = 0; j < 48; ++j) {
+                const double gj = gc[j % 3] * Y[j / 3];
+                const size_t o = ((size_t)kk * 48 + j) * n + tc->i;
+                tc->gsht[o] += (float)(tc->w[kk] * gj);
+                gm += gj * tc->dw[kk] * (double)tc->g->sh_t[o];
+            }
+        *gmt += gm;
     }
     double gd[3];
     sh_grad_dot(p.dir[0], p.dir[1], p.dir[2], wY, gd);
@@ -370,6 +435,7 @@ __device__ inline void unit_bwd(const double qh[4], double nrm, const double gqh
     for (int k = 0; k < 4; ++k) out[k * stride] = (float)((gqh[k] - qh[k] * dq) * in);
 }
 
+template <bool TIME>
 __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restrict__ views, int n_views, int N,
                               const Rec* __restrict__ recs, const float* __restrict__ g2, const G4Grad& gr,
                               const SetStats& st) {
@@ -406,6 +472,8 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
         for (int k = 0; k < 4; ++k) Ss[r][k] = 0.0;
     float gsh[48];
     for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    if constexpr (TIME)
+        for (int k = 0; k < 48 * g4.sh_t_deg; ++k) gr.sh_t[(size_t)k * n + i] = 0.f;  // accumulated per view below
     double stat_g = 0.0;
     int stat_n = 0;
     for (int v = 0; v < n_views; ++v) {
@@ -426,7 +494,17 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
         ProjF p;
         project(V, w, p);
         double gmc[3], Sb[3][3], gop;
-        proj_bwd(V, w, p, g4.sh, g4.n, i, g2 + ((size_t)v * N + i) * kG2Stride, 1, gmc, Sb, gop, gsh);
+        if constexpr (TIME) {
+            TimeColour tc;
+            tc.g = &g4;
+            tc.i = i;
+            tc.gsht = gr.sh_t;
+            time_weights(g4, i, V.time, tc.w, tc.dw);
+            proj_bwd<true>(V, w, p, g4.sh, g4.n, i, g2 + ((size_t)v * N + i) * kG2Stride, 1, gmc, Sb, gop, gsh, &tc,
+                           &gmt);
+        } else {
+            proj_bwd<false>(V, w, p, g4.sh, g4.n, i, g2 + ((size_t)v * N + i) * kG2Stride, 1, gmc, Sb, gop, gsh);
+        }
         // effective opacity sigma * p(t); p(t) = exp(-delta^2 / (2 c))
         gsig += gop * pt;
         const double gpt = gop * sig;
@@ -521,7 +599,7 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
         ProjF p;
         project(V, w, p);
         double gmc[3], Sb[3][3], gop;
-        proj_bwd(V, w, p, g3.sh, g3.n, i, g2 + ((size_t)v * N + gidx) * kG2Stride, 1, gmc, Sb, gop, gsh);
+        proj_bwd<false>(V, w, p, g3.sh, g3.n, i, g2 + ((size_t)v * N + gidx) * kG2Stride, 1, gmc, Sb, gop, gsh);
         gsig += gop;
         for (int r = 0; r < 3; ++r) {
             gmu[r] += gmc[r];
@@ -560,6 +638,8 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
 // longer threads, started first), the rest the 3D ones.  Both paths hold one
 // wave per SIMD (FP64 state of 400+ registers), so sharing the launch costs no
 // occupancy and lets the two sets fill the machine together.
+// TIME: the 4D set carries time coefficients of its colour.
+template <bool TIME>
 __global__ void __launch_bounds__(128) k_preprocess_bwd(G3Ptr g3, G4Ptr g4, int nb4, const ViewParams* __restrict__ views,
                                                         int n_views, const Rec* __restrict__ recs,
                                                         const float* __restrict__ g2, G3Grad gr3, G4Grad gr4,
@@ -567,7 +647,7 @@ __global__ void __launch_bounds__(128) k_preprocess_bwd(G3Ptr g3, G4Ptr g4, int 
     const int N = g3.n + g4.n;
     if ((int)blockIdx.x < nb4) {
         const int g = blockIdx.x * blockDim.x + threadIdx.x;
-        if (g < g4.n) bwd_4d(g4, g, views, n_views, N, recs, g2, gr4, st4);
+        if (g < g4.n) bwd_4d<TIME>(g4, g, views, n_views, N, recs, g2, gr4, st4);
     } else {
         const int i = (blockIdx.x - nb4) * blockDim.x + threadIdx.x;
         if (i < g3.n) bwd_3d(g3, i, g4.n + i, views, n_views, N, recs, g2, gr3, st3);
@@ -644,7 +724,10 @@ void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* v
     const int N = g3.n + g4.n;
     if (N == 0) return;
     const int nb4 = ceil_div(g4.n, 128), nb3 = ceil_div(g3.n, 128);
-    k_preprocess_bwd<<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4);
+    if (g4.sh_t_deg > 0)
+        k_preprocess_bwd<true><<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4);
+    else
+        k_preprocess_bwd<false><<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4);
 }
 
 }  // namespace h4d

@@ -37,11 +37,29 @@ def g3_struct(g3: dict, mut=False):
     return L.G3D(n, *[_ptr(g3[k]) for k in G3_KEYS])
 
 
-def g4_struct(g4: dict):
-    n = int(g4["opacity"].shape[0])
-    for k in G4_KEYS:
+def g4_keys(g4: dict) -> tuple:
+    """The 4D set's arrays: G4_KEYS, and "sh_t" (time coefficients of the
+    colour, [48 D][n]) when the set has them."""
+    return G4_KEYS + (("sh_t",) if "sh_t" in g4 else ())
+
+
+def time_degree(g4: dict) -> int:
+    t = g4.get("sh_t")
+    if t is None:
+        return 0
+    if t.dim() != 2 or t.shape[0] % 48 or t.shape[1] != g4["opacity"].shape[0]:
+        raise ValueError("g4.sh_t: expected [48 D, n4]")
+    return int(t.shape[0]) // 48
+
+
+def g4_struct(g4: dict, period: float = 1.0, n: int = None):
+    """Descriptor of a 4D set (or of a parameter-shaped mirror of one, e.g.
+    gradients or moments, whose row stride is n)."""
+    n = int(g4["opacity"].shape[0]) if n is None else int(n)
+    for k in g4_keys(g4):
         _chk(g4[k], "g4." + k)
-    return L.G4D(n, *[_ptr(g4[k]) for k in G4_KEYS])
+    deg = time_degree(g4)
+    return L.G4D(n, *[_ptr(g4[k]) for k in G4_KEYS], deg, float(period), _ptr(g4["sh_t"]) if deg else None)
 
 
 def _stats_struct(d: dict, n: int) -> L.SetStats:
@@ -97,8 +115,10 @@ class Rasterizer:
     in which no pixel can reach alpha >= 1/255 (images unchanged)."""
 
     def __init__(self, tile: int = DEFAULT_TILE, chunk: int = DEFAULT_CHUNK, pair_capacity: int = 1 << 22,
-                 growth: float = 1.3, check: str = "eager", batched: bool = False, cull: bool = True):
+                 growth: float = 1.3, check: str = "eager", batched: bool = False, cull: bool = True,
+                 time_period: float = 1.0):
         self.ctx = L.Context()
+        self.time_period = float(time_period)  # period of the 4D colour's time terms
         self.tile, self.chunk = int(tile), int(chunk)
         self.batched = bool(batched)
         self.cull = bool(cull)
@@ -138,7 +158,7 @@ class Rasterizer:
     def forward(self, g3: dict, g4: dict, views, _keep: bool = True) -> FwdHandle:
         if self._pending is not None and self.check_mode == "eager":
             self._pending = None
-        s3, s4 = g3_struct(g3), g4_struct(g4)
+        s3, s4 = g3_struct(g3), g4_struct(g4, self.time_period)
         n_views = len(views)
         va = L.view_array(views)
         images = [torch.empty((3, v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
@@ -186,18 +206,16 @@ class Rasterizer:
             raise RuntimeError("backward must follow its own forward (the workspace was reused)")
         if not h.differentiable:
             raise RuntimeError("an inference render keeps no state for the backward")
-        s3, s4 = g3_struct(g3), g4_struct(g4)
+        s3, s4 = g3_struct(g3), g4_struct(g4, self.time_period)
         if out is None:
             gr3 = {k: torch.empty_like(g3[k]) for k in G3_KEYS}
-            gr4 = {k: torch.empty_like(g4[k]) for k in G4_KEYS}
+            gr4 = {k: torch.empty_like(g4[k]) for k in g4_keys(g4)}
         else:
             gr3, gr4 = out
             for k in G3_KEYS:
                 _chk(gr3[k], "grad3." + k)
-            for k in G4_KEYS:
-                _chk(gr4[k], "grad4." + k)
         m3 = L.G3D(s3.n, *[_ptr(gr3[k]) for k in G3_KEYS])
-        m4 = L.G4D(s4.n, *[_ptr(gr4[k]) for k in G4_KEYS])
+        m4 = g4_struct(gr4, self.time_period, n=s4.n)
         dl = [_chk(d, "dl_dimage") for d in dl_images]
         arr = L.ptr_array([d.data_ptr() for d in dl])
         if stats is None:
@@ -258,7 +276,7 @@ class H4DGSRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rast: Rasterizer, views, *params):
         g3 = dict(zip(G3_KEYS, params[:5]))
-        g4 = dict(zip(G4_KEYS, params[5:]))
+        g4 = dict(zip(G4_KEYS + ("sh_t",), params[5:]))
         h = rast.forward(g3, g4, views)
         ctx.rast, ctx.h = rast, h
         ctx.save_for_backward(*params)
@@ -268,15 +286,15 @@ class H4DGSRender(torch.autograd.Function):
     def backward(ctx, *dl):
         params = ctx.saved_tensors
         g3 = dict(zip(G3_KEYS, params[:5]))
-        g4 = dict(zip(G4_KEYS, params[5:]))
+        g4 = dict(zip(G4_KEYS + ("sh_t",), params[5:]))
         dls = [d.contiguous() if d is not None else torch.zeros_like(im) for d, im in zip(dl, ctx.h.images)]
         gr3, gr4 = ctx.rast.backward(ctx.h, g3, g4, dls)
-        return (None, None, *[gr3[k] for k in G3_KEYS], *[gr4[k] for k in G4_KEYS])
+        return (None, None, *[gr3[k] for k in G3_KEYS], *[gr4[k] for k in g4_keys(g4)])
 
 
 def render(rast: Rasterizer, g3: dict, g4: dict, views) -> tuple:
     """Differentiable render of ``views``; returns one [3, H, W] image per view."""
-    return H4DGSRender.apply(rast, list(views), *[g3[k] for k in G3_KEYS], *[g4[k] for k in G4_KEYS])
+    return H4DGSRender.apply(rast, list(views), *[g3[k] for k in G3_KEYS], *[g4[k] for k in g4_keys(g4)])
 
 
 # -- other entry points ------------------------------------------------------------
@@ -287,7 +305,7 @@ def render_infer_noalloc(rast: Rasterizer, g3: dict, g4: dict, views, images=Non
     inputs and outputs.  ``images`` (one [3, H, W] float32 tensor per view)
     and ``status`` (a 2-element int64 tensor receiving the status flags and the
     pair count) are allocated here when not given.  Returns (images, status)."""
-    s3, s4 = g3_struct(g3), g4_struct(g4)
+    s3, s4 = g3_struct(g3), g4_struct(g4, rast.time_period)
     va = L.view_array(views)
     if images is None:
         images = [torch.empty((3, v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
@@ -343,8 +361,9 @@ def rasterize_splats(rast: Rasterizer, sp: dict, width: int, height: int, bg=(0.
     raise L.H4DError(L.H4D_ERR_CAPACITY, "pair capacity kept overflowing")
 
 
-def _set_buffers(n3: int, n4: int, dev="cuda"):
-    """Uninitialised parameter-shaped arrays for n3 3D and n4 4D rows."""
+def _set_buffers(n3: int, n4: int, dev="cuda", deg4: int = 0):
+    """Uninitialised parameter-shaped arrays for n3 3D and n4 4D rows (with
+    time coefficients of degree deg4 for the 4D set)."""
     o3 = {"mean": torch.empty((3, n3), device=dev), "log_scale": torch.empty((3, n3), device=dev),
           "quat": torch.empty((4, n3), device=dev), "opacity": torch.empty(n3, device=dev),
           "sh": torch.empty((48, n3), device=dev)}
@@ -352,6 +371,8 @@ def _set_buffers(n3: int, n4: int, dev="cuda"):
           "log_scale": torch.empty((4, n4), device=dev), "quat_l": torch.empty((4, n4), device=dev),
           "quat_r": torch.empty((4, n4), device=dev), "opacity": torch.empty(n4, device=dev),
           "sh": torch.empty((48, n4), device=dev)}
+    if deg4:
+        o4["sh_t"] = torch.empty((48 * deg4, n4), device=dev)
     return o3, o4
 
 
@@ -363,13 +384,14 @@ def convert_static(rast: Rasterizer, g3: dict, g4: dict, tau: float, moments=())
     """Static identification + 4D->3D conversion.  Returns (g3', g4', perm);
     with ``moments`` (pairs (m3, m4) of parameter-shaped arrays, e.g. Adam's
     first and second moments) also the list of the moved pairs."""
-    s3, s4 = g3_struct(g3), g4_struct(g4)
+    s3, s4 = g3_struct(g3), g4_struct(g4, rast.time_period)
     n3, n4 = s3.n, s4.n
     dev = "cuda"
     cap3 = n3 + n4
-    o3, o4 = _set_buffers(cap3, n4, dev)
+    deg = time_degree(g4)
+    o3, o4 = _set_buffers(cap3, n4, dev, deg)
     m3 = L.G3D(cap3, *[_ptr(o3[k]) for k in G3_KEYS])
-    m4 = L.G4D(n4, *[_ptr(o4[k]) for k in G4_KEYS])
+    m4 = g4_struct(o4, rast.time_period, n=n4)
     perm = torch.empty(max(1, n4), dtype=torch.int32, device=dev)
     nsc = int(rast.ctx.L.h4dgs_convert_scratch_bytes(n4))
     scratch = torch.empty(max(256, nsc), dtype=torch.uint8, device=dev)
@@ -383,10 +405,10 @@ def convert_static(rast: Rasterizer, g3: dict, g4: dict, tau: float, moments=())
         return g3n, g4n, perm[:n4]
     moved = []
     for a3, a4 in moments:
-        b3, b4 = _set_buffers(cap3, n4, dev)
+        b3, b4 = _set_buffers(cap3, n4, dev, time_degree(a4))
         rast.ctx.check(rast.ctx.L.h4dgs_convert_moments(
-            rast.ctx.h, C.byref(g4_struct(a4)), C.byref(g3_struct(a3)), _ptr(perm),
-            C.byref(L.G4D(n4, *[_ptr(b4[k]) for k in G4_KEYS])), C.byref(L.G3D(cap3, *[_ptr(b3[k]) for k in G3_KEYS])),
+            rast.ctx.h, C.byref(g4_struct(a4, rast.time_period)), C.byref(g3_struct(a3)), _ptr(perm),
+            C.byref(g4_struct(b4, rast.time_period, n=n4)), C.byref(L.G3D(cap3, *[_ptr(b3[k]) for k in G3_KEYS])),
             _stream()))
         moved.append((_first_rows(b3, k3), _first_rows(b4, k4)))
     return g3n, g4n, perm[:n4], moved
@@ -398,10 +420,10 @@ def densify(rast: Rasterizer, g3: dict, g4: dict, stats3: dict, stats4: dict, no
     [split_n, 3, n3], noise4: [split_n, 4, n4] standard normal draws.  Returns
     (g3', g4', src3, src4[, moved]) where moved lists the moment pairs
     (m3, m4) gathered to the new rows (zeros for new rows)."""
-    s3, s4 = g3_struct(g3), g4_struct(g4)
+    s3, s4 = g3_struct(g3), g4_struct(g4, rast.time_period)
     n3, n4 = s3.n, s4.n
     cap3, cap4 = n3 * max(2, p3.split_n), n4 * max(2, p4.split_n)
-    o3, o4 = _set_buffers(cap3, cap4)
+    o3, o4 = _set_buffers(cap3, cap4, deg4=time_degree(g4))
     src3 = torch.empty(max(1, cap3), dtype=torch.int32, device="cuda")
     src4 = torch.empty(max(1, cap4), dtype=torch.int32, device="cuda")
     nsc = int(rast.ctx.L.h4dgs_densify_scratch_bytes(n3, n4))
@@ -414,7 +436,7 @@ def densify(rast: Rasterizer, g3: dict, g4: dict, stats3: dict, stats4: dict, no
     rast.ctx.check(rast.ctx.L.h4dgs_densify(
         rast.ctx.h, C.byref(s3), C.byref(s4), C.byref(st3), C.byref(st4), _ptr(noise3), _ptr(noise4),
         C.byref(p3), C.byref(p4), C.byref(L.G3D(cap3, *[_ptr(o3[k]) for k in G3_KEYS])),
-        C.byref(L.G4D(cap4, *[_ptr(o4[k]) for k in G4_KEYS])), _ptr(src3), _ptr(src4), C.byref(n3o), C.byref(n4o),
+        C.byref(g4_struct(o4, rast.time_period, n=cap4)), _ptr(src3), _ptr(src4), C.byref(n3o), C.byref(n4o),
         _ptr(scratch), scratch.numel(), _stream()))
     k3, k4 = n3o.value, n4o.value
     out = [_first_rows(o3, k3), _first_rows(o4, k4), src3[:k3].clone(), src4[:k4].clone()]
@@ -422,10 +444,10 @@ def densify(rast: Rasterizer, g3: dict, g4: dict, stats3: dict, stats4: dict, no
         return tuple(out)
     moved = []
     for a3, a4 in moments:
-        b3, b4 = _set_buffers(k3, k4)
+        b3, b4 = _set_buffers(k3, k4, deg4=time_degree(a4))
         rast.ctx.check(rast.ctx.L.h4dgs_gather_rows(
-            rast.ctx.h, C.byref(g3_struct(a3)), C.byref(g4_struct(a4)), _ptr(src3), k3, _ptr(src4), k4,
-            C.byref(L.G3D(k3, *[_ptr(b3[k]) for k in G3_KEYS])), C.byref(L.G4D(k4, *[_ptr(b4[k]) for k in G4_KEYS])),
+            rast.ctx.h, C.byref(g3_struct(a3)), C.byref(g4_struct(a4, rast.time_period)), _ptr(src3), k3, _ptr(src4),
+            k4, C.byref(L.G3D(k3, *[_ptr(b3[k]) for k in G3_KEYS])), C.byref(g4_struct(b4, rast.time_period, n=k4)),
             _stream()))
         moved.append((b3, b4))
     return tuple(out) + (moved,)

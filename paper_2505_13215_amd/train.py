@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _lib as L
-from .render import G3_KEYS, G4_KEYS, Rasterizer, adam_step, convert_static, densify, l1_loss_grad, new_stats
+from .render import G3_KEYS, Rasterizer, adam_step, convert_static, densify, g4_keys, l1_loss_grad, new_stats
 
 # Learning rates per parameter array (the paper does not list its own; these
 # are the magnitudes of the 3D Gaussian Splatting lineage it builds on).
@@ -79,7 +79,7 @@ class Trainer:
                  lr4: dict = None, limits3: DensifyLimits = None, limits4: DensifyLimits = None, seed: int = 0,
                  rast: Rasterizer = None, masked: bool = True):
         self.g3 = {k: g3[k].contiguous() for k in G3_KEYS}
-        self.g4 = {k: g4[k].contiguous() for k in G4_KEYS}
+        self.g4 = {k: g4[k].contiguous() for k in g4_keys(g4)}
         self.extent = float(extent)
         self.schedule = schedule or Schedule()
         self.lr3, self.lr4 = dict(lr3 or LR3), dict(lr4 or LR4)
@@ -118,7 +118,9 @@ class Trainer:
                                     (self.g4, self.gr4, self.m4, self.v4, self.lr4, self.st4)):
             for k in g:
                 if g[k].numel():
-                    out.append((g[k], gr[k], m[k], v[k], lr[k], st["step_visible"] if self.masked else None))
+                    # the colour's time coefficients train at the SH rate
+                    rate = lr.get(k, lr["sh"])
+                    out.append((g[k], gr[k], m[k], v[k], rate, st["step_visible"] if self.masked else None))
         return out
 
     # -- one iteration ---------------------------------------------------------------
