@@ -320,7 +320,7 @@ def training_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
                                   "ms_per_step_amortized": round(per, 4), "mpix_s_amortized": round(mpix / per * 1e3, 2)}}
 
 
-def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
+def batched_leg(h4d, torch, sg, steps: int, warmup: int, forms: str = "both") -> dict:
     """fwd + L1 + bwd over 32 views per call (1M Gaussians, 80 % static; 8 arc
     cameras, four at 1352x1014 and four at 2704x2028, times 0.125 ... 0.875):
     views one after another (eager launches), against all views in one launch
@@ -338,7 +338,37 @@ def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
     out = {"workload": "batched_1M_32views", "views": len(views), "mpix_per_step": round(mpix, 3),
            "gaussians": int(g3["opacity"].numel() + g4["opacity"].numel())}
 
-    # views one after another, eager
+    if forms != "batched":
+        out["single_view"] = _single_view_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup, out)
+    if forms != "single":
+        out["batched_graph"] = _batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup)
+    if forms != "both":
+        return out
+    out["speedup"] = round(out["single_view"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3)
+    # workload counts of the call (the same lists either way) and the share of
+    # the HBM roofline of each form: the batched form reads the parameters once
+    # per call, the views one after another once per view
+    crast = h4d.Rasterizer(batched=True)
+    dls = [torch.empty_like(t) for t in targets]
+
+    def counted():
+        h = crast.forward(g3, g4, views)
+        h4d.l1_loss_grad(crast, h.images, targets, views, dls, None)
+        crast.backward(h, g3, g4, dls, out=(gr3, gr4))
+
+    cnt = count_step(crast, counted)
+    n3, n4 = int(g3["opacity"].numel()), int(g4["opacity"].numel())
+    pix = int(round(mpix * 1e6))
+    a_single = alg_bytes(n3, n4, len(views), cnt, pix)
+    a_batched = alg_bytes(n3, n4, 1, cnt, pix)
+    out["counts"] = {k: int(v) for k, v in cnt.items()}
+    out["hbm"] = {"single_view": hbm_entry(a_single["total"], out["single_view"]["ms_per_step"] * 1e-3),
+                  "batched_graph": hbm_entry(a_batched["total"], out["batched_graph"]["ms_per_step"] * 1e-3)}
+    return out
+
+
+def _single_view_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup, out) -> dict:
+    """The views one after another, eager launches."""
     rast = h4d.Rasterizer()
     dls = [torch.empty_like(t) for t in targets]
     loss = torch.zeros(1, device="cuda")
@@ -362,11 +392,13 @@ def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     rast.verify()
-    out["single_view"] = {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
     del rast, dls
     torch.cuda.empty_cache()
+    return {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
 
-    # batched, captured once, replayed
+
+def _batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup) -> dict:
+    """All views in one launch per stage, captured once and replayed."""
     step = h4d.CapturedStep(h4d.Rasterizer(batched=True), g3, g4, views, targets, (gr3, gr4))
     for _ in range(warmup):
         step.replay()
@@ -377,30 +409,9 @@ def batched_leg(h4d, torch, sg, steps: int, warmup: int) -> dict:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     step.verify()
-    out["batched_graph"] = {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
-    out["speedup"] = round(out["single_view"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3)
     del step
     torch.cuda.empty_cache()
-    # workload counts of the call (the same lists either way) and the share of
-    # the HBM roofline of each form: the batched form reads the parameters once
-    # per call, the views one after another once per view
-    crast = h4d.Rasterizer(batched=True)
-    dls = [torch.empty_like(t) for t in targets]
-
-    def counted():
-        h = crast.forward(g3, g4, views)
-        h4d.l1_loss_grad(crast, h.images, targets, views, dls, None)
-        crast.backward(h, g3, g4, dls, out=(gr3, gr4))
-
-    cnt = count_step(crast, counted)
-    n3, n4 = int(g3["opacity"].numel()), int(g4["opacity"].numel())
-    pix = int(round(mpix * 1e6))
-    a_single = alg_bytes(n3, n4, len(views), cnt, pix)
-    a_batched = alg_bytes(n3, n4, 1, cnt, pix)
-    out["counts"] = {k: int(v) for k, v in cnt.items()}
-    out["hbm"] = {"single_view": hbm_entry(a_single["total"], out["single_view"]["ms_per_step"] * 1e-3),
-                  "batched_graph": hbm_entry(a_batched["total"], out["batched_graph"]["ms_per_step"] * 1e-3)}
-    return out
+    return {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
 
 
 def main():
@@ -417,6 +428,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs single-view leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the hybrid-ratio and 2M training legs")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--batched-only", choices=("both", "single", "batched"),
+                    help="profiling aid: run only the batched-call leg (one or both forms) and print its result")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run one plain device copy of MIB MiB (a known-size reference for counters)")
     args = ap.parse_args()
@@ -434,6 +447,10 @@ def main():
     args.tile = args.tile or h4d.DEFAULT_TILE
     args.chunk = args.chunk or h4d.DEFAULT_CHUNK
     torch.cuda.set_device(0)
+    if args.batched_only:
+        res = batched_leg(h4d, torch, sg, args.batched_steps, 1, forms=args.batched_only)
+        print(json.dumps({"batched_vs_single": res}), flush=True)
+        return
     log("building the synthetic scene")
     scene = sg.multiview_scene(n_total=args.gaussians)
     sched = sg.view_schedule(scene, args.warmup + args.steps, 1, seed=2)
