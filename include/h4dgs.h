@@ -107,17 +107,25 @@ typedef struct {
 /* Launch configuration.  tile: tile edge in pixels (8, 16 or 32); chunk:
  * list entries staged in LDS per round of the blending kernels (64, 128, 256
  * or 512); batched: 0 = views processed one after another,
- * 1 = all views of a call in one pass per stage; cull: 0 = a tile's list holds
+ * 1 = the views of a call in one pass per stage (several passes only when
+ * their super-tiles exceed 65536); in a batched call whose views repeat a
+ * camera (same pose, intrinsics and size) at several times, the 3D Gaussians
+ * are projected, sorted and binned once per camera and each view's tiles merge
+ * that list with the view's own 4D list (the 3D Gaussians do not depend on
+ * t); cull: 0 = a tile's list holds
  * every splat whose pixel square overlaps the tile (Alg. 1), 1 = in addition a
  * splat is left out of tiles in which no pixel centre can reach
  * alpha >= 1/255 (tested in FP64 with a margin far above the FP32 evaluation
- * error, so no pixel's blending changes); pair_capacity: number of tile-list
- * slots the workspace holds, summed over the call's views (a tile's slots
- * number the splats touching its super-tile of 4 x 4 tiles (2 x 2 for
- * 32-pixel tiles), so this exceeds the number of (Gaussian, tile) pairs).
- * Images do not depend on tile, chunk or cull (a pixel's contributors are
- * fixed by its own square and alpha tests), so these are pure performance
- * knobs. */
+ * error, so no pixel's blending changes); pair_capacity: capacity of the
+ * call's binning in (Gaussian, tile) slots, summed over its views: the
+ * workspace holds pair_capacity / S^2 (Gaussian, super-tile) entries, a
+ * super-tile being S x S tiles (S = 4; 2 for 32-pixel tiles) and each entry
+ * standing for its S^2 tiles, so this exceeds the number of (Gaussian, tile)
+ * pairs.  A view may span at most 65536 super-tiles (16384 x 16384 pixels at
+ * 16- and 32-pixel tiles, 8192 x 8192 at 8; H4D_ERR_UNSUPPORTED otherwise).
+ * Images do not depend on tile, chunk, batched or cull (a pixel's
+ * contributors are fixed by its own square and alpha tests), so these are
+ * pure performance knobs. */
 typedef struct {
     int32_t tile;
     int32_t chunk;
@@ -239,11 +247,12 @@ h4d_status h4dgs_check(h4d_ctx *ctx, const void *state, size_t state_bytes, int6
  * u[n], v[n], conic[3][n] (inverse 2D covariance entries 00, 01, 11), effective
  * opacity[n], rgb[3][n], integer radius[n], depth key[n] and visible[n] (uint8).
  * Splat i covers pixel (x, y) iff |x + 0.5 - u| <= r and |y + 0.5 - v| <= r.
- * Writes image[3][H][W], T_final[H][W] (may be NULL) and, if sorted_ids is not
- * NULL, the per-tile depth-ordered splat ids (sorted_ids[pair_capacity]) with
- * tile ranges (ranges[2 * tiles]: start, end): tile t's list is
- * sorted_ids[ranges[2t] .. ranges[2t+1]); lists of different tiles need not be
- * adjacent.  Uses the same kernels as render_fwd.
+ * Writes image[3][H][W], T_final[H][W] (may be NULL) and, if sorted_ids and
+ * ranges are not NULL, the per-tile depth-ordered splat ids
+ * (sorted_ids[pair_capacity]) with tile ranges (ranges[2 * tiles]: start,
+ * end): tile t's list is sorted_ids[ranges[2t] .. ranges[2t+1]), the lists
+ * one after another in tile order, as h4dgs_tile_lists writes them.  Uses the
+ * same kernels as render_fwd.
  * Workspace: h4dgs_workspace_size(n3 = n, n4 = 0, one view of W x H). */
 h4d_status h4dgs_rasterize_splats(h4d_ctx *ctx, int32_t n, const float *u, const float *v, const float *conic,
                                   const float *opacity, const float *rgb, const int32_t *radius,
@@ -251,6 +260,23 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx *ctx, int32_t n, const float *u, const
                                   const float *bg /* host, 3 */, const h4d_config *cfg, float *image,
                                   float *T_final, uint32_t *sorted_ids, int64_t *ranges, void *state,
                                   size_t state_bytes, void *scratch, size_t scratch_bytes, void *stream);
+
+/* The tile lists (Alg. 1: the depth-ordered splats of every tile, the lists
+ * BlendInOrder traverses) of the last render_fwd / render_infer on `state`,
+ * written out for inspection: the blending kernels never store them, they
+ * compact each tile's entries from its super-tile's sorted list as they go;
+ * this call walks every list the same way.  Same n3, n4, views and cfg as
+ * that call; scratch as sized by h4dgs_workspace_size (overwritten).
+ * ids (device, ids_capacity words): the splat ids (indices into the merged
+ * set [4D | 3D]) of every tile, one list after another in global tile order
+ * (views in order), entries from position ids_capacity on left unwritten;
+ * ranges (device, int64[2 * total tiles]): start and end of each tile's
+ * list (the last end is the number of entries; a shared static list counts
+ * once per view that uses it).  Enqueued on `stream`. */
+h4d_status h4dgs_tile_lists(h4d_ctx *ctx, int32_t n3, int32_t n4, const h4d_view *views, int32_t n_views,
+                            const h4d_config *cfg, const void *state, size_t state_bytes, void *scratch,
+                            size_t scratch_bytes, uint32_t *ids, uint64_t ids_capacity, int64_t *ranges,
+                            void *stream);
 
 /* Static identification and 4D -> 3D conversion (Sec. 4.1-4.2, Eq. 7-9).
  * Row i of in4 is static iff (double)log_scale_t[i] > log((double)tau).  out4

@@ -29,7 +29,7 @@ EXPORTS = (
     "h4dgs_convert_scratch_bytes", "h4dgs_convert_static", "h4dgs_adam", "h4dgs_l1_loss_grad",
     "h4dgs_profile", "h4dgs_profile_read", "h4dgs_stats", "h4dgs_stats_read", "h4dgs_radix_hist_words",
     "h4dgs_radix_pass_check", "h4dgs_render_infer_noalloc", "h4dgs_convert_moments", "h4dgs_render_bwd_stats",
-    "h4dgs_densify_scratch_bytes", "h4dgs_densify", "h4dgs_gather_rows", "h4dgs_adam_masked",
+    "h4dgs_densify_scratch_bytes", "h4dgs_densify", "h4dgs_gather_rows", "h4dgs_adam_masked", "h4dgs_tile_lists",
 )
 
 NOALLOC_BYTES = 256 << 20  # H4DGS_NOALLOC_BYTES

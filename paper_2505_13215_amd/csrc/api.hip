@@ -152,53 +152,71 @@ int n_passes_for(int bits, int width) { return (bits + width - 1) / width; }
 int pass_bits(int bits, int width) { return (bits + n_passes_for(bits, width) - 1) / n_passes_for(bits, width); }
 
 // One pass of binning + blending covers the views [v0, v1): every view alone
-// (views processed one after another), or all views of the call (batched).
+// (views processed one after another), or as many of the call's views as the
+// pass's super-tile ids allow (batched).  supers counts the pass's super-tiles
+// including its static groups' grids.
 struct Pass {
     int v0, v1, tiles, supers;
 };
 
 struct Layout {
     int N = 0, V = 0, total_tiles = 0, total_supers = 0;
-    int per_pass = 1;  // views per pass
+    int n3 = 0, n4 = 0;
     int64_t total_pix = 0;
-    uint64_t cap = 0;    // tile-list slots
-    uint64_t ccap = 0;   // coarse (Gaussian, super-tile) entries: cap / S^2 suffices
+    uint64_t cap = 0;    // capacity in (Gaussian, tile) slots, S^2 per coarse entry
+    uint64_t ccap = 0;   // coarse (Gaussian, super-tile) entries of the call: cap / S^2
     ViewGeom vg[kMaxViews];
+    int n_pass = 0;
+    Pass passes[kMaxViews];
+    bool fits = true;    // every view's super-tiles fit one pass's key range
+    // shared static binning (one pass holding every view): static groups of
+    // views with the same camera, their leader views and grids
+    bool shared = false;
+    int n_groups = 0;
+    ViewShare share[kMaxViews];
     // state
-    size_t st_status, st_pair_base, st_views, st_recs, st_ids, st_ranges, st_thist, st_T, st_nc, st_C, st_tcost,
-        state_bytes;
+    size_t st_status, st_pair_base, st_views, st_recs, st_ckeys, st_cvals, st_cranges, st_thist, st_T, st_nc, st_C,
+        st_tcost, state_bytes;
     // scratch, forward use
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_ceff,
-        sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_cranges,
-        sc_shape, sc_runs, fwd_bytes;
+        sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_shape, sc_runs, sc_wcnt, sc_woff, sc_wpart,
+        fwd_bytes;
     size_t hist_words = 0, totals_words = 0;  // 32-bit words of the radix histogram / digit totals
     // scratch, backward use
     size_t sc_g2, sc_border, bwd_bytes;
     size_t scratch_bytes;
 
-    int n_passes() const { return V / per_pass; }
-    Pass pass(int k) const {
-        Pass p;
-        p.v0 = k * per_pass;
-        p.v1 = p.v0 + per_pass;
-        const int tb_end = p.v1 < V ? vg[p.v1].tile_base : total_tiles;
-        const int sb_end = p.v1 < V ? vg[p.v1].super_base : total_supers;
-        p.tiles = tb_end - vg[p.v0].tile_base;
-        p.supers = sb_end - vg[p.v0].super_base;
-        return p;
+    int n_passes() const { return n_pass; }
+    Pass pass(int k) const { return passes[k]; }
+    // depth-ordered entries of a pass and their segment layout
+    SegLayout segs(const Pass& P) const {
+        const int nv = P.v1 - P.v0;
+        return shared ? SegLayout{nv, n4, n3} : SegLayout{nv, N, 0};
+    }
+    int64_t entries(const Pass& P) const {
+        const int nv = P.v1 - P.v0;
+        return shared ? (int64_t)nv * n4 + (int64_t)n_groups * n3 : (int64_t)nv * N;
     }
 };
 
-Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
+// Views with the same camera (pose, intrinsics, image size): a batched call
+// that repeats a camera at several times bins the 3D Gaussians once per camera.
+bool same_camera(const h4d_view& a, const h4d_view& b) {
+    return std::memcmp(a.world_to_cam, b.world_to_cam, sizeof(a.world_to_cam)) == 0 && a.fx == b.fx &&
+           a.fy == b.fy && a.cx == b.cx && a.cy == b.cy && a.width == b.width && a.height == b.height;
+}
+
+Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config* cfg) {
     Layout L;
     L.N = N;
     L.V = V;
-    L.per_pass = cfg->batched ? V : 1;
+    L.n3 = n3;
+    L.n4 = N - n3;
     L.cap = (uint64_t)std::max<int64_t>(0, cfg->pair_capacity);
     int tb = 0, sb = 0;
     int64_t pb = 0;
     const int S = super_factor(cfg->tile);
-    L.ccap = (L.cap + (uint64_t)(S * S) - 1) / (uint64_t)(S * S);
+    L.ccap = L.cap / (uint64_t)(S * S);
     for (int v = 0; v < V; ++v) {
         ViewGeom& g = L.vg[v];
         g.tiles_x = ceil_div(views[v].width, cfg->tile);
@@ -211,21 +229,79 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
         tb += g.tiles_x * g.tiles_y;
         sb += g.sx * g.sy;
         pb += (int64_t)views[v].width * views[v].height;
+        if (g.sx * g.sy > kMaxPassSupers) L.fits = false;
     }
     L.total_tiles = tb;
-    L.total_supers = sb;
     L.total_pix = pb;
-    int max_super = 0;
-    for (int k = 0; k < L.n_passes(); ++k) max_super = std::max(max_super, L.pass(k).supers);
+    // static groups: each view's first view with the same camera leads its group
+    for (int v = 0; v < V; ++v) {
+        int lead = v;
+        for (int u = 0; u < v; ++u)
+            if (same_camera(views[u], views[v])) {
+                lead = u;
+                break;
+            }
+        L.share[v].static_view = lead;
+        L.share[v].group_leader = -1;
+    }
+    int n_groups = 0, group_supers = 0;
+    bool repeats = false;
+    for (int v = 0; v < V; ++v) {
+        if (L.share[v].static_view == v) {
+            L.share[n_groups].group_leader = v;
+            ++n_groups;
+            group_supers += L.vg[v].sx * L.vg[v].sy;
+        } else {
+            repeats = true;
+        }
+    }
+    L.shared = cfg->batched && repeats && n3 > 0 && L.fits && (int64_t)sb + group_supers <= kMaxPassSupers;
+    if (L.shared) {
+        L.n_groups = n_groups;
+        int gs = sb;
+        for (int g = 0; g < n_groups; ++g) {
+            const int lead = L.share[g].group_leader;
+            for (int v = 0; v < V; ++v)
+                if (L.share[v].static_view == lead) {
+                    L.share[v].static_group = g;
+                    L.share[v].static_super_base = gs;
+                }
+            gs += L.vg[lead].sx * L.vg[lead].sy;
+        }
+        L.total_supers = gs;
+        L.n_pass = 1;
+        L.passes[0] = Pass{0, V, tb, gs};
+    } else {
+        for (int v = 0; v < V; ++v) {
+            L.share[v].static_view = v;
+            L.share[v].static_group = -1;
+            L.share[v].static_super_base = L.vg[v].super_base;
+            L.share[v].group_leader = -1;
+        }
+        L.total_supers = sb;
+        // views one after another, or batched passes of consecutive views whose
+        // super-tiles fit the key range
+        for (int v = 0; v < V;) {
+            int e = v + 1, supers = L.vg[v].sx * L.vg[v].sy;
+            while (cfg->batched && e < V && supers + L.vg[e].sx * L.vg[e].sy <= kMaxPassSupers)
+                supers += L.vg[e].sx * L.vg[e].sy, ++e;
+            const int tiles = (e < V ? L.vg[e].tile_base : tb) - L.vg[v].tile_base;
+            L.passes[L.n_pass++] = Pass{v, e, tiles, supers};
+            v = e;
+        }
+    }
+    int max_views = 1;
+    for (int k = 0; k < L.n_pass; ++k) max_views = std::max(max_views, L.passes[k].v1 - L.passes[k].v0);
     const size_t n = (size_t)N, V_ = (size_t)V;
-    const size_t np = n * (size_t)L.per_pass;  // Gaussians x views of one pass
+    const size_t np = n * (size_t)max_views;  // depth-ordered entries of the largest pass (bound)
     Carve s;
     L.st_status = s.take(sizeof(Status));
     L.st_pair_base = s.take(8 * (V_ + 1));
     L.st_views = s.take(sizeof(ViewParams) * V_);
     L.st_recs = s.take(sizeof(Rec) * n * V_);
-    L.st_ids = s.take(4 * (size_t)L.cap);
-    L.st_ranges = s.take(16 * (size_t)tb);
+    L.st_ckeys = s.take(4 * (size_t)L.ccap);
+    L.st_cvals = s.take(4 * (size_t)L.ccap);
+    L.st_cranges = s.take(16 * (size_t)L.total_supers);
     L.st_thist = s.take(4 * (size_t)kCostBuckets * V_);  // one per pass (at most V); cleared with the ranges
     L.st_T = s.take(4 * (size_t)pb);
     L.st_nc = s.take(4 * (size_t)pb);
@@ -253,14 +329,23 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
     int cbits = 1;
     for (int k = 0; k < L.n_passes(); ++k)
         cbits = std::max(cbits, pass_bits(bits_for(L.pass(k).supers), kMaxRadixBits));
-    L.hist_words = std::max(radix_hist_words(L.ccap, 1, cbits, kSortItems),
-                            radix_hist_words(n, L.per_pass, kDepthDigitBits, kDepthSortItems));
-    L.totals_words = (size_t)kMaxRadix * (size_t)L.per_pass;
+    // the depth sort's segments: a pass's views (all Gaussians, or the 4D ones
+    // when shared) and the static groups (3D ones)
+    size_t dwords = radix_hist_words(n, max_views, kDepthDigitBits, kDepthSortItems);
+    if (L.shared)
+        dwords = std::max(radix_hist_words((uint64_t)L.n4, V, kDepthDigitBits, kDepthSortItems),
+                          radix_hist_words((uint64_t)L.n3, L.n_groups, kDepthDigitBits, kDepthSortItems));
+    L.hist_words = std::max(radix_hist_words(L.ccap, 1, cbits, kSortItems), dwords);
+    L.totals_words = (size_t)kMaxRadix * (size_t)max_views;
     L.sc_hist = f.take(4 * L.hist_words);
     L.sc_totals = f.take(4 * L.totals_words);
-    L.sc_cranges = f.take(16 * (size_t)max_super);
     L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
     L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
+    // tile lists written out on request (h4dgs_tile_lists): per-tile counts,
+    // their offsets and the scan's partial sums
+    L.sc_wcnt = f.take(4 * (size_t)tb);
+    L.sc_woff = f.take(8 * ((size_t)tb + 1));
+    L.sc_wpart = f.take(8 * ((size_t)scan_blocks(tb) + 2));
     L.fwd_bytes = f.off;
     Carve b;
     L.sc_g2 = b.take(4 * (size_t)kG2Stride * n * V_);
@@ -273,16 +358,40 @@ Layout make_layout(int N, const h4d_view* views, int V, const h4d_config* cfg) {
 // Every radix pass the forward will launch fits the layout's histogram and
 // digit-total buffers (checked on the host before anything is enqueued; the
 // launcher checks each pass again).
+// Depth sorts of a pass: segments of equal length starting at `offset` in the
+// key arrays (the pass's views; with shared static binning, the views' 4D
+// Gaussians and the static groups' 3D Gaussians).
+struct DepthJob {
+    size_t offset;
+    int n_seg;
+    int len;
+};
+int depth_jobs(const Layout& L, const Pass& P, DepthJob* jobs) {
+    const int nv = P.v1 - P.v0;
+    int n = 0;
+    if (!L.shared) {
+        jobs[n++] = DepthJob{0, nv, L.N};
+        return n;
+    }
+    if (L.n4 > 0) jobs[n++] = DepthJob{0, nv, L.n4};
+    if (L.n3 > 0) jobs[n++] = DepthJob{(size_t)nv * L.n4, L.n_groups, L.n3};
+    return n;
+}
+
 bool plan_fits(const Layout& L) {
     for (int k = 0; k < L.n_passes(); ++k) {
         const Pass P = L.pass(k);
+        DepthJob jobs[2];
+        const int nj = depth_jobs(L, P, jobs);
         const int passes = n_passes_for(32, kDepthDigitBits);
-        for (int p = 0, shift = 0; p < passes; ++p) {
-            const int nb = (32 - shift + (passes - p) - 1) / (passes - p);
-            if (!radix_pass_fits((uint64_t)L.N, P.v1 - P.v0, nb, kDepthSortItems, L.hist_words, L.totals_words))
-                return false;
-            shift += nb;
-        }
+        for (int q = 0; q < nj; ++q)
+            for (int p = 0, shift = 0; p < passes; ++p) {
+                const int nb = (32 - shift + (passes - p) - 1) / (passes - p);
+                if (!radix_pass_fits((uint64_t)jobs[q].len, jobs[q].n_seg, nb, kDepthSortItems, L.hist_words,
+                                     L.totals_words))
+                    return false;
+                shift += nb;
+            }
         const int bits = bits_for(P.supers);
         const int cp = n_passes_for(bits, kMaxRadixBits);
         for (int p = 0, shift = 0; p < cp; ++p) {
@@ -294,10 +403,10 @@ bool plan_fits(const Layout& L) {
     return true;
 }
 
-// 64-bit words the forward's init clears from st_ranges on: the tile ranges
-// and the blending cost histograms behind them
+// 64-bit words the forward's init clears from st_cranges on: the super-tile
+// list ranges and the blending cost histograms behind them
 size_t range_words(const Layout& L) {
-    return (L.st_thist + 4 * (size_t)kCostBuckets * (size_t)L.V - L.st_ranges + 7) / 8;
+    return (L.st_thist + 4 * (size_t)kCostBuckets * (size_t)L.V - L.st_cranges + 7) / 8;
 }
 
 template <typename T>
@@ -325,6 +434,14 @@ h4d_status check_pass_size(h4d_ctx* c, const h4d_config* cfg, int64_t N, int n_v
         return fail(c, H4D_ERR_INVALID_ARG, "batched pass too large: %lld Gaussians x %lld views >= 2^31",
                     (long long)N, (long long)per);
     return H4D_OK;
+}
+
+// Every view's super-tiles fit one binning pass's key range (16 bits): images
+// up to 16384 pixels square at 16- and 32-pixel tiles, 8192 at 8-pixel tiles.
+h4d_status check_layout(h4d_ctx* c, const Layout& L, const h4d_config* cfg) {
+    if (L.fits) return H4D_OK;
+    return fail(c, H4D_ERR_UNSUPPORTED, "a view has more than %d super-tiles of %d x %d pixels", kMaxPassSupers,
+                cfg->tile * super_factor(cfg->tile), cfg->tile * super_factor(cfg->tile));
 }
 
 h4d_status check_views(h4d_ctx* c, const h4d_view* views, int n_views) {
@@ -375,11 +492,12 @@ G4Ptr to_ptr(const h4d_g4d* g) {
                  g->opacity, g->sh, g->sh_t_degree, g->sh_t_period, g->sh_t};
 }
 
-ViewTableIn view_table(const h4d_view* views, int V, int tile) {
+ViewTableIn view_table(const h4d_view* views, int V, int tile, const Layout& L) {
     ViewTableIn t;
     std::memset(&t, 0, sizeof(t));
     t.n = V;
     t.tile = tile;
+    for (int v = 0; v < V; ++v) t.share[v] = L.share[v];
     for (int v = 0; v < V; ++v) {
         ViewIn& o = t.v[v];
         std::memcpy(o.M, views[v].world_to_cam, sizeof(o.M));
@@ -391,21 +509,27 @@ ViewTableIn view_table(const h4d_view* views, int V, int tile) {
 }
 
 
-// Binning, sorting and blending of one view whose records are in place
-// (recs_v, ntiles, dkeys, dvals filled): Alg. 1 from CreateTiles to BlendInOrder.
 unsigned long long* stat_counters(h4d_ctx* c, void* state, const Layout& L) {
     return c->stats ? reinterpret_cast<unsigned long long*>(&at<Status>(state, L.st_status)->pad[0]) : nullptr;
 }
 
-// keep: write the adjoint's per-pixel and per-tile state (false for an
-// inference render)
+// The call's sorted coarse lists in its state.
+CoarseLists coarse_lists(const Layout& L, const void* state) {
+    void* s = const_cast<void*>(state);
+    return CoarseLists{at<uint32_t>(s, L.st_ckeys), at<uint32_t>(s, L.st_cvals), at<int64_t>(s, L.st_cranges)};
+}
+
+// Binning and sorting of one pass whose records and depth keys are in place
+// (Alg. 1 from DuplicateWithKeys to IdentifyTileRanges): its coarse lists go to
+// the state's coarse arrays from cbase[P.v0] on, their ranges to st_cranges.
 // Returns false (after launching only part of the pass) when a radix pass did
 // not fit its buffers, which plan_fits rules out beforehand.
-bool bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chunk, int cull, void* state,
-                   void* scratch, const PtrTable& images, hipStream_t st, bool keep = true) {
+bool bin_pass(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int cull, void* state, void* scratch,
+              hipStream_t st, bool keep) {
     const int N = L.N;
     const int nv = P.v1 - P.v0;
-    const int n = nv * N;  // depth-ordered Gaussians of the pass, view-major
+    const int n = (int)L.entries(P);  // depth-ordered entries of the pass (segment layout)
+    const SegLayout sg = L.segs(P);
     const Rec* recs = at<Rec>(state, L.st_recs);
     const ViewParams* vp = at<ViewParams>(state, L.st_views);
     uint32_t* dk = at<uint32_t>(scratch, L.sc_dkeys);
@@ -415,16 +539,22 @@ bool bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     uint32_t* hist = at<uint32_t>(scratch, L.sc_hist);
     uint32_t* totals = at<uint32_t>(scratch, L.sc_totals);
     {
-        // depth order per view: stable LSD passes over the float32 depth bits,
-        // each view of the pass a segment of its own
+        // depth order per segment: stable LSD passes over the float32 depth bits
         StageScope sc(c, st, H4D_STAGE_DEPTH_SORT);
+        DepthJob jobs[2];
+        const int nj = depth_jobs(L, P, jobs);
         const int passes = n_passes_for(32, kDepthDigitBits);
         int shift = 0;
         for (int pass = 0; pass < passes; ++pass) {
             const int nb = (32 - shift + (passes - pass) - 1) / (passes - pass);
-            if (!launch_radix_pass(dk, dv, dk2, dv2, nullptr, (uint64_t)N, (uint64_t)N, shift, nb, hist, L.hist_words,
-                                   totals, L.totals_words, nullptr, st, nv, (uint64_t)N, nullptr, 0, kDepthSortItems))
-                return false;
+            for (int q = 0; q < nj; ++q) {
+                const size_t o = jobs[q].offset;
+                if (!launch_radix_pass(dk + o, dv + o, dk2 + o, dv2 + o, nullptr, (uint64_t)jobs[q].len,
+                                       (uint64_t)jobs[q].len, shift, nb, hist, L.hist_words, totals, L.totals_words,
+                                       nullptr, st, jobs[q].n_seg, (uint64_t)jobs[q].len, nullptr, 0,
+                                       kDepthSortItems))
+                    return false;
+            }
             std::swap(dk, dk2);
             std::swap(dv, dv2);
             shift += nb;
@@ -432,85 +562,90 @@ bool bin_and_blend(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int chu
     }
     // dk / dv now hold the depth-ordered keys and ids
     if (unsigned long long* sc = keep ? stat_counters(c, state, L) : nullptr)
-        launch_count_onscreen(recs + (size_t)P.v0 * N, (size_t)n, sc + 6, st);
+        launch_count_onscreen(recs, N, L.n4, vp, P.v0, nv, sc + 6, st);
     Status* status = at<Status>(state, L.st_status);
-    unsigned long long* pair_base = at<unsigned long long>(state, L.st_pair_base);
-    uint32_t* ids = at<uint32_t>(state, L.st_ids);
+    unsigned long long* cbase = at<unsigned long long>(state, L.st_pair_base);
     const int S = super_factor(tile);
-    {
-        StageScope sc(c, st, H4D_STAGE_BINNING);
-        unsigned long long* eff_c = at<unsigned long long>(scratch, L.sc_eff);
-        uint32_t* cnt = at<uint32_t>(scratch, L.sc_cnt);
-        uint64_t* rect = at<uint64_t>(scratch, L.sc_rect);
-        unsigned long long* offsets = at<unsigned long long>(scratch, L.sc_offsets);
-        // coarse entries: one per (depth-ordered Gaussian, super-tile); the tile
-        // mask travels in the key's upper half when the pass's super-tile ids fit
-        // the lower one
-        const int mkey = P.supers <= (1 << 16) ? 1 : 0;
-        CullShape* shapes = (cull && mkey) ? at<CullShape>(scratch, L.sc_shape) : nullptr;
-        unsigned long long* partials = at<unsigned long long>(scratch, L.sc_partials);
-        launch_coarse_count(dv, n, N, recs, P.v0, tile, S, cnt, rect, shapes, partials, st);
-        uint32_t* runs = at<uint32_t>(scratch, L.sc_runs);
-        launch_coarse_offsets(cnt, n, partials, L.ccap, L.cap, S, pair_base, P.v0, P.v1, status, eff_c, offsets, runs,
-                              L.ccap / 256 + 1, st);
-        uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
-        uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
-        uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
-        uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
-        launch_coarse_emit(offsets, runs, n, N, rect, shapes, vp, P.v0, tile, S, mkey, L.ccap, eff_c, pk, pv, st);
-        // stable sort of the coarse entries by super-tile (depth order kept inside each)
-        // (a single pass over the whole super-tile id also yields each super-tile's
-        // list range; otherwise the ranges come from the sorted keys)
-        const int bits = bits_for(P.supers);
-        const int passes = n_passes_for(bits, kMaxRadixBits);
-        int64_t* cranges = at<int64_t>(scratch, L.sc_cranges);
-        uint32_t* kin = pk;
-        uint32_t* vin = pv;
-        int shift = 0;
-        // with the tile mask in the keys, the first pass also drops the entries
-        // whose mask is empty (after culling, about 40 % of them), and the
-        // per-tile pass needs only splat ids: the last pass writes those in place
-        // of the depth ranks
-        // (the first pass writes the kept count whenever it runs, i.e. ccap > 0)
-        const bool drop = mkey && L.ccap > 0;
-        unsigned long long* ceff = drop ? at<unsigned long long>(scratch, L.sc_ceff) : eff_c;  // entries kept
-        for (int p = 0; p < passes; ++p) {
-            const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
-            uint32_t* kout = (kin == pk) ? pk2 : pk;
-            uint32_t* vout = (vin == pv) ? pv2 : pv;
-            if (!launch_radix_pass(kin, vin, kout, vout, p == 0 ? eff_c : ceff, 0, L.ccap, shift, nb, hist,
-                                   L.hist_words, totals, L.totals_words, nullptr, st, 1, 0,
-                                   passes == 1 ? cranges : nullptr, P.supers, kSortItems,
-                                   (mkey && p == passes - 1) ? dv : nullptr, (drop && p == 0) ? 1 : 0,
-                                   (drop && p == 0) ? ceff : nullptr))
-                return false;
-            kin = kout;
-            vin = vout;
-            shift += nb;
-        }
-        if (passes > 1) {
-            launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
-            launch_ranges(kin, mkey ? 0xFFFFu : 0xFFFFFFFFu, ceff, nullptr, cranges, st);
-        }
-        // splat ids of the sorted entries (otherwise gathered into the buffer
-        // the sort did not end in)
-        uint32_t* cgid = vin;
-        if (!mkey) {
-            cgid = (kin == pk) ? pk2 : pk;
-            launch_coarse_gather(vin, dv, eff_c, cgid, st);
-        }
-        launch_tile_write(kin, vin, rect, cgid, mkey, cranges, pair_base + P.v0, ceff, P.supers, vp, P.v0, P.v1, S,
-                          ids, at<int64_t>(state, L.st_ranges), st);
+    StageScope sc(c, st, H4D_STAGE_BINNING);
+    unsigned long long* eff_c = at<unsigned long long>(scratch, L.sc_eff);
+    uint32_t* cnt = at<uint32_t>(scratch, L.sc_cnt);
+    uint64_t* rect = at<uint64_t>(scratch, L.sc_rect);
+    unsigned long long* offsets = at<unsigned long long>(scratch, L.sc_offsets);
+    // coarse entries: one per (depth-ordered Gaussian, super-tile), the tile
+    // mask in the key's upper half
+    CullShape* shapes = cull ? at<CullShape>(scratch, L.sc_shape) : nullptr;
+    unsigned long long* partials = at<unsigned long long>(scratch, L.sc_partials);
+    launch_coarse_count(dv, n, N, sg, recs, vp, P.v0, tile, S, cnt, rect, shapes, partials, st);
+    uint32_t* runs = at<uint32_t>(scratch, L.sc_runs);
+    launch_coarse_offsets(cnt, n, partials, L.ccap, S, cbase, P.v0, P.v1, status, eff_c, offsets, runs,
+                          L.ccap / 256 + 1, st);
+    uint32_t* pk = at<uint32_t>(scratch, L.sc_pkeys);
+    uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
+    uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
+    uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
+    launch_coarse_emit(offsets, runs, n, sg, rect, shapes, vp, P.v0, tile, S, L.ccap, eff_c, pk, pv, st);
+    // stable sort of the coarse entries by super-tile (depth order kept inside
+    // each); the last pass writes the state's coarse arrays from cbase[P.v0]
+    // on, with splat ids in place of the depth ranks.  The first pass also
+    // drops the entries whose tile mask is empty (after culling, about 40 % of
+    // them).  A single pass over the whole super-tile id also yields each
+    // super-tile's list range; otherwise the ranges come from the sorted keys.
+    const int bits = bits_for(P.supers);
+    const int passes = n_passes_for(bits, kMaxRadixBits);
+    int64_t* cranges = at<int64_t>(state, L.st_cranges) + 2 * (size_t)L.vg[P.v0].super_base;
+    uint32_t* ckeys = at<uint32_t>(state, L.st_ckeys);
+    uint32_t* cvals = at<uint32_t>(state, L.st_cvals);
+    const unsigned long long* out0 = cbase + P.v0;
+    uint32_t* kin = pk;
+    uint32_t* vin = pv;
+    int shift = 0;
+    const bool drop = L.ccap > 0;  // (the first pass writes the kept count whenever it runs)
+    unsigned long long* ceff = drop ? at<unsigned long long>(scratch, L.sc_ceff) : eff_c;  // entries kept
+    for (int p = 0; p < passes; ++p) {
+        const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
+        const bool last = p == passes - 1;
+        uint32_t* kout = last ? ckeys : (kin == pk ? pk2 : pk);
+        uint32_t* vout = last ? cvals : (vin == pv ? pv2 : pv);
+        if (!launch_radix_pass(kin, vin, kout, vout, p == 0 ? eff_c : ceff, 0, L.ccap, shift, nb, hist,
+                               L.hist_words, totals, L.totals_words, last ? out0 : nullptr, st, 1, 0,
+                               passes == 1 ? cranges : nullptr, P.supers, kSortItems, last ? dv : nullptr,
+                               (drop && p == 0) ? 1 : 0, (drop && p == 0) ? ceff : nullptr))
+            return false;
+        kin = kout;
+        vin = vout;
+        shift += nb;
     }
+    if (passes > 1) {
+        launch_fill_u64(reinterpret_cast<unsigned long long*>(cranges), 2 * (size_t)P.supers, 0ull, st);
+        launch_ranges(ckeys, 0xFFFFu, ceff, out0, cranges, st);
+    }
+    return true;
+}
+
+// Every tile list of the call written out (ids: pair-capacity words; ranges:
+// [start, end) per global tile).
+void write_tile_lists(const Layout& L, int tile, void* state, void* scratch, uint32_t* ids, uint64_t ids_cap,
+                      int64_t* ranges, hipStream_t st) {
+    launch_walk_lists(tile, at<Rec>(state, L.st_recs), L.N, coarse_lists(L, state), L.shared,
+                      at<ViewParams>(state, L.st_views), 0, L.V, L.total_tiles, at<uint32_t>(scratch, L.sc_wcnt),
+                      at<unsigned long long>(scratch, L.sc_woff), at<unsigned long long>(scratch, L.sc_wpart), ids,
+                      ids_cap, ranges, st);
+}
+
+// Blending of one pass whose coarse lists are in place.
+// keep: write the adjoint's per-pixel and per-tile state (false for an
+// inference render)
+void blend_pass(h4d_ctx* c, const Layout& L, int k, int tile, int chunk, void* state, const PtrTable& images,
+                hipStream_t st, bool keep) {
+    const Pass P = L.pass(k);
     StageScope sc(c, st, H4D_STAGE_BLEND_FWD);
     KernelMark km(c, H4D_STAGE_BLEND_FWD, P.tiles > 0);
-    launch_composite_fwd(tile, chunk, recs, N, ids, at<int64_t>(state, L.st_ranges), vp, P.v0, P.v1, P.tiles,
-                         nullptr, images, keep ? at<float>(state, L.st_T) : nullptr,
-                         keep ? at<uint32_t>(state, L.st_nc) : nullptr, keep ? at<float>(state, L.st_C) : nullptr,
-                         keep ? at<uint32_t>(state, L.st_tcost) : nullptr,
-                         keep ? at<uint32_t>(state, L.st_thist) + (size_t)kCostBuckets * (P.v0 / L.per_pass) : nullptr,
+    launch_composite_fwd(tile, chunk, at<Rec>(state, L.st_recs), L.N, coarse_lists(L, state), L.shared,
+                         at<ViewParams>(state, L.st_views), P.v0, P.v1, P.tiles, nullptr, images,
+                         keep ? at<float>(state, L.st_T) : nullptr, keep ? at<uint32_t>(state, L.st_nc) : nullptr,
+                         keep ? at<float>(state, L.st_C) : nullptr, keep ? at<uint32_t>(state, L.st_tcost) : nullptr,
+                         keep ? at<uint32_t>(state, L.st_thist) + (size_t)kCostBuckets * k : nullptr,
                          keep ? stat_counters(c, state, L) : nullptr, st, km.a, km.b);
-    return true;
 }
 
 constexpr int kNoallocDevices = 64;
@@ -567,7 +702,8 @@ h4d_status h4dgs_workspace_size(h4d_ctx* ctx, int32_t n3, int32_t n4, const h4d_
     if (n3 < 0 || n4 < 0 || (int64_t)n3 + n4 > 0x7FFFFFFF) return fail(ctx, H4D_ERR_INVALID_ARG, "bad Gaussian counts");
     if ((s = check_pass_size(ctx, cfg, (int64_t)n3 + n4, n_views)) != H4D_OK) return s;
     if (!state_bytes || !scratch_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "null size output");
-    const Layout L = make_layout(n3 + n4, views, n_views, cfg);
+    const Layout L = make_layout(n3 + n4, n3, views, n_views, cfg);
+    if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
     *state_bytes = L.state_bytes;
     *scratch_bytes = L.scratch_bytes;
     return H4D_OK;
@@ -586,7 +722,8 @@ static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d*
     for (int v = 0; v < n_views; ++v)
         if (!images[v]) return fail(ctx, H4D_ERR_INVALID_ARG, "image %d is null", v);
     const int N = g3->n + g4->n;
-    const Layout L = make_layout(N, views, n_views, cfg);
+    const Layout L = make_layout(N, g3->n, views, n_views, cfg);
+    if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
     if (!state || state_bytes < L.state_bytes)
         return fail(ctx, H4D_ERR_INVALID_ARG, "state too small (%zu < %zu)", state_bytes, L.state_bytes);
     if (!scratch || scratch_bytes < L.fwd_bytes)
@@ -596,8 +733,8 @@ static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d*
     const G3Ptr p3 = to_ptr(g3);
     const G4Ptr p4 = to_ptr(g4);
     ViewParams* vp = at<ViewParams>(state, L.st_views);
-    launch_init_state(view_table(views, n_views, cfg->tile), vp, at<Status>(state, L.st_status),
-                      at<unsigned long long>(state, L.st_pair_base), at<unsigned long long>(state, L.st_ranges),
+    launch_init_state(view_table(views, n_views, cfg->tile, L), vp, at<Status>(state, L.st_status),
+                      at<unsigned long long>(state, L.st_pair_base), at<unsigned long long>(state, L.st_cranges),
                       range_words(L), st);
     PtrTable tab;
     std::memset(&tab, 0, sizeof(tab));
@@ -606,11 +743,12 @@ static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d*
         const Pass P = L.pass(k);
         {
             StageScope sc(ctx, st, H4D_STAGE_PREPROCESS);
-            launch_preprocess(p3, p4, vp, P.v0, P.v1 - P.v0, at<Rec>(state, L.st_recs),
+            launch_preprocess(p3, p4, vp, P.v0, P.v1 - P.v0, L.shared ? 1 : 0, at<Rec>(state, L.st_recs),
                               at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
         }
-        if (!bin_and_blend(ctx, L, P, cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st, keep))
+        if (!bin_pass(ctx, L, P, cfg->tile, cfg->cull, state, scratch, st, keep))
             return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: a radix pass did not fit its buffers");
+        blend_pass(ctx, L, k, cfg->tile, cfg->chunk, state, tab, st, keep);
     }
     return hip_check(ctx, keep ? "render_fwd" : "render_infer");
 }
@@ -638,7 +776,8 @@ h4d_status h4dgs_render_infer_noalloc(h4d_ctx* ctx, const h4d_g3d* g3, const h4d
     if ((s = check_config(ctx, cfg)) != H4D_OK) return s;
     if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
     if ((s = check_pass_size(ctx, cfg, (int64_t)g3->n + g4->n, n_views)) != H4D_OK) return s;
-    const Layout L = make_layout(g3->n + g4->n, views, n_views, cfg);
+    const Layout L = make_layout(g3->n + g4->n, g3->n, views, n_views, cfg);
+    if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
     const size_t state_room = align_up(L.state_bytes);
     const size_t limit = (size_t)H4DGS_NOALLOC_BYTES;
     if (state_room > limit || L.fwd_bytes > limit - state_room)
@@ -683,7 +822,8 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
         return fail(ctx, H4D_ERR_INVALID_ARG, "4D gradient: null array");
     if ((s = check_time_out(ctx, g4, grad4, g4->n, "render_bwd")) != H4D_OK) return s;
     const int N = g3->n + g4->n;
-    const Layout L = make_layout(N, views, n_views, cfg);
+    const Layout L = make_layout(N, g3->n, views, n_views, cfg);
+    if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
     if (!state || state_bytes < L.state_bytes)
         return fail(ctx, H4D_ERR_INVALID_ARG, "state too small (%zu < %zu)", state_bytes, L.state_bytes);
     if (!scratch || scratch_bytes < L.bwd_bytes)
@@ -707,8 +847,8 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
         for (int k = 0; k < L.n_passes(); ++k) {
             const Pass P = L.pass(k);
             KernelMark km(ctx, H4D_STAGE_BLEND_BWD, P.tiles > 0);
-            launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs), N, at<uint32_t>(stt, L.st_ids),
-                                 at<int64_t>(stt, L.st_ranges), vp, P.v0, P.v1, P.tiles, border + pt.tile0[k], tab,
+            launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs), N, coarse_lists(L, stt),
+                                 L.shared, vp, P.v0, P.v1, P.tiles, border + pt.tile0[k], tab,
                                  at<float>(stt, L.st_T),
                                  at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), g2, stat_counters(ctx, stt, L),
                                  st, km.a, km.b);
@@ -782,30 +922,49 @@ h4d_status h4dgs_rasterize_splats(h4d_ctx* ctx, int32_t n, const float* u, const
     view.height = height;
     for (int k = 0; k < 3; ++k) view.bg[k] = bg[k];
     if ((s = check_views(ctx, &view, 1)) != H4D_OK) return s;
-    const Layout L = make_layout(n, &view, 1, cfg);
+    const Layout L = make_layout(n, 0, &view, 1, cfg);
+    if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
     if (!state || state_bytes < L.state_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "state too small");
     if (!scratch || scratch_bytes < L.fwd_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small");
     if (!plan_fits(L)) return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: radix buffers of the layout too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    launch_init_state(view_table(&view, 1, cfg->tile), at<ViewParams>(state, L.st_views),
+    launch_init_state(view_table(&view, 1, cfg->tile, L), at<ViewParams>(state, L.st_views),
                       at<Status>(state, L.st_status), at<unsigned long long>(state, L.st_pair_base),
-                      at<unsigned long long>(state, L.st_ranges), range_words(L), st);
+                      at<unsigned long long>(state, L.st_cranges), range_words(L), st);
     Rec* recs = at<Rec>(state, L.st_recs);
     launch_splats_to_records(n, u, v, conic, opacity, rgb, radius, depth, visible, width, height, recs,
                              at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
     PtrTable tab;
     std::memset(&tab, 0, sizeof(tab));
     tab.p[0] = image;
-    if (!bin_and_blend(ctx, L, L.pass(0), cfg->tile, cfg->chunk, cfg->cull, state, scratch, tab, st))
+    if (!bin_pass(ctx, L, L.pass(0), cfg->tile, cfg->cull, state, scratch, st, true))
         return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: a radix pass did not fit its buffers");
+    blend_pass(ctx, L, 0, cfg->tile, cfg->chunk, state, tab, st, true);
     const size_t hw = (size_t)width * height;
     if (T_final) (void)hipMemcpyAsync(T_final, at<float>(state, L.st_T), 4 * hw, hipMemcpyDeviceToDevice, st);
-    if (sorted_ids && L.cap > 0)
-        (void)hipMemcpyAsync(sorted_ids, at<uint32_t>(state, L.st_ids), 4 * (size_t)L.cap, hipMemcpyDeviceToDevice, st);
-    if (ranges)
-        (void)hipMemcpyAsync(ranges, at<int64_t>(state, L.st_ranges), 16 * (size_t)L.total_tiles,
-                             hipMemcpyDeviceToDevice, st);
+    if (sorted_ids && ranges)
+        write_tile_lists(L, cfg->tile, state, scratch, sorted_ids, L.cap, ranges, st);
     return hip_check(ctx, "rasterize_splats");
+}
+
+h4d_status h4dgs_tile_lists(h4d_ctx* ctx, int32_t n3, int32_t n4, const h4d_view* views, int32_t n_views,
+                            const h4d_config* cfg, const void* state, size_t state_bytes, void* scratch,
+                            size_t scratch_bytes, uint32_t* ids, uint64_t ids_capacity, int64_t* ranges,
+                            void* stream) {
+    if (!ctx) return H4D_ERR_INVALID_ARG;
+    h4d_status s;
+    if ((s = check_config(ctx, cfg)) != H4D_OK) return s;
+    if ((s = check_views(ctx, views, n_views)) != H4D_OK) return s;
+    if (n3 < 0 || n4 < 0 || (int64_t)n3 + n4 > 0x7FFFFFFF) return fail(ctx, H4D_ERR_INVALID_ARG, "bad Gaussian counts");
+    if ((s = check_pass_size(ctx, cfg, (int64_t)n3 + n4, n_views)) != H4D_OK) return s;
+    const Layout L = make_layout(n3 + n4, n3, views, n_views, cfg);
+    if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
+    if (!state || state_bytes < L.state_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "state too small");
+    if (!scratch || scratch_bytes < L.fwd_bytes) return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small");
+    if (!ids || !ranges) return fail(ctx, H4D_ERR_INVALID_ARG, "ids / ranges is null");
+    write_tile_lists(L, cfg->tile, const_cast<void*>(state), scratch, ids, ids_capacity, ranges,
+                     static_cast<hipStream_t>(stream));
+    return hip_check(ctx, "tile_lists");
 }
 
 h4d_status h4dgs_radix_pass_check(uint64_t capacity, int32_t n_seg, int32_t nbits, int32_t items,

@@ -34,15 +34,29 @@ struct ViewParams {
     int32_t tiles_x, tiles_y;
     int32_t tile_base;   // first global tile id of this view
     int64_t pix_base;    // first pixel of this view in the concatenated pixel arrays
-    int32_t sx, sy;      // 64-pixel super-tile grid
+    int32_t sx, sy;      // super-tile grid (S x S tiles each)
     int32_t super_base;  // first global super-tile id of this view
-    int32_t pad;
+    // Static binning shared by the views of one camera (a batched call whose
+    // views repeat a camera at several times): the 3D Gaussians of this view
+    // are projected, sorted and binned once, in the records of view
+    // static_view, onto the super-tile grid of static group static_group, whose
+    // first global super-tile id is static_super_base.  Unshared: static_view
+    // is the view itself, static_group -1, static_super_base = super_base.
+    int32_t static_view;
+    int32_t static_group;
+    int32_t static_super_base;
+    // entry k of the table: the view whose records hold static group k (-1
+    // past the last group)
+    int32_t group_leader;
 };
 
 // Tiles per super-tile edge: binning groups tiles into S x S blocks (S = 4 for
 // 8- and 16-pixel tiles, 2 for 32-pixel tiles), so that a super-tile holds at
 // most 16 tiles and a splat's tiles within it fit a 16-bit mask.
 __host__ __device__ constexpr int super_factor(int tile) { return tile == 32 ? 2 : 4; }
+// Super-tiles of one binning pass: their ids fill the low 16 bits of the coarse
+// sort keys, the tile masks the high 16.
+constexpr int kMaxPassSupers = 1 << 16;
 
 // The view of global tile `gt` among views [v0, v1) (tile ids ascend with the view).
 __device__ __forceinline__ int find_view_of_tile(const ViewParams* views, int v0, int v1, int gt) {
@@ -50,6 +64,22 @@ __device__ __forceinline__ int find_view_of_tile(const ViewParams* views, int v0
     while (v + 1 < v1 && views[v + 1].tile_base <= gt) ++v;
     return v;
 }
+
+// Sorted coarse lists of a call (binning's output, read by the blending
+// kernels): per super-tile, its (Gaussian, super-tile) entries in depth order.
+struct CoarseLists {
+    const uint32_t* keys;   // super-tile id (pass-relative) | tile mask << 16
+    const uint32_t* vals;   // splat id (relative to the record's view)
+    const int64_t* ranges;  // [start, end) per global super-tile id
+};
+
+// Layout of a pass's depth-ordered entries: na segments of la entries (the
+// views v0 .. v0 + na - 1, all their Gaussians, or only the 4D ones when the
+// static binning is shared), then segments of lb entries, one per static group
+// (the 3D Gaussians of the group's camera).
+struct SegLayout {
+    int na, la, lb;
+};
 
 // Screen-space gradients of one (view, Gaussian) from the blending adjoint:
 // du dv dQ00 dQ01 dQ11 dop dr dg db (conic entries unscaled, Q01 counted once),

@@ -3,10 +3,11 @@
 // One workgroup per B x B tile (B = 8: one wave64; 16: one wave in the adjoint,
 // two in the forward; 32: four waves), one to four pixels per lane, all of a
 // lane's pixels in one column.  The tile's
-// depth-ordered list is walked in chunks: each chunk of records is gathered
-// once from HBM into LDS and broadcast to every lane.  A pixel's contributors
-// are exactly the splats whose pixel square contains it, so the image does not
-// depend on B or on the chunk size.
+// depth-ordered list is walked in chunks: the first wave pulls the chunk's
+// entries from the sorted coarse lists (TileWalk), then each chunk of records
+// is gathered once from HBM into LDS and broadcast to every lane.  A pixel's
+// contributors are exactly the splats whose pixel square contains it, so the
+// image does not depend on B or on the chunk size.
 //
 // The backward recomputes transmittance front to back with the very same
 // blending test as the forward (eval_col / eval_pix, next_T).  The colour behind
@@ -22,6 +23,7 @@
 #include <type_traits>
 #include "common.hpp"
 #include "launch.hpp"
+#include "walk.hpp"
 
 namespace h4d {
 
@@ -167,22 +169,45 @@ __device__ __forceinline__ int dispatch_tile(const uint32_t* __restrict__ order)
 // counts the launch's tiles per bucket.
 // (at most 64 registers: 8 waves per SIMD, about 1 % faster than the 7 the
 // compiler would otherwise settle for)
-template <int B, int CHUNK, bool STATS, bool SPLIT>
+// Pulls the next chunk of the tile's list (up to `need` entries) into s_ids and
+// its length into *s_cnt; called by the first wave only.
+template <bool MERGE, int CHUNK>
+__device__ __forceinline__ void walk_chunk(TileWalk<MERGE>& walk, WalkQueues& q, uint32_t* s_ids, int* s_cnt,
+                                           int need) {
+    const int lane = __lane_id();
+    int cnt = 0;
+    for (int c0 = 0; c0 < need; c0 += 64) {
+        uint32_t id;
+        const int got = walk.next(min(64, need - c0), q, id);
+        if (lane < got) s_ids[c0 + lane] = id;
+        cnt += got;
+        if (got < min(64, need - c0)) break;  // the list ended (wave-uniform)
+    }
+    if (lane == 0) *s_cnt = cnt;
+}
+
+// MERGE: the tile's list merges the static group's 3D list with the view's 4D
+// list (shared static binning); otherwise it is one list.
+template <int B, int CHUNK, bool STATS, bool SPLIT, bool MERGE>
 __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
-    const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
-    const ViewParams* __restrict__ views, int v0, int v1, const uint32_t* __restrict__ order, PtrTable images,
-    float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib, float* __restrict__ Cout,
-    uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist, unsigned long long* counters) {
+    const Rec* __restrict__ recs, int N, CoarseLists lists, const ViewParams* __restrict__ views, int v0, int v1,
+    const uint32_t* __restrict__ order, PtrTable images, float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib,
+    float* __restrict__ Cout, uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist,
+    unsigned long long* counters) {
     constexpr int NT = ShapeF<B, SPLIT>::NT, PPL = ShapeF<B, SPLIT>::PPL;
     __shared__ LSplat s_sp[CHUNK];
+    __shared__ uint32_t s_ids[CHUNK];
+    __shared__ WalkQueues s_q;
+    __shared__ int s_cnt;
     __shared__ uint32_t s_cost;
     const int gt = views[v0].tile_base + dispatch_tile(order);
     const int view = find_view_of_tile(views, v0, v1, gt);
     const ViewParams& V = views[view];
     const int tile = gt - V.tile_base;
-    recs += (size_t)view * N;
     float* __restrict__ image = images.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
+    TileWalk<MERGE> walk;
+    walk.init(lists, V, view, recs, N, super_factor(B), tx, ty);
     // all pixels of a lane share one column (NT is a multiple of B)
     const int px = tx * B + (int)threadIdx.x % B;
     const float pxc = (float)px + 0.5f;
@@ -203,27 +228,24 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
         last[k] = 0u;
         lane_done = lane_done && !inside;
     }
-    const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
-    const int64_t end = ranges[2 * (size_t)(V.tile_base + tile) + 1];
     unsigned long long n_eval = 0, n_blend = 0;
     // wave-uniform: the splat loop runs for the whole wave (finished pixels are
     // masked), so that its per-pixel flags stay lane masks
     bool wave_done = __ballot(!lane_done) == 0ull;
     const int tid = (int)threadIdx.x;
-    // this thread's first list slot of the next chunk, loaded a chunk ahead so
-    // that staging waits for the record gather only
-    uint32_t nid = (tid < CHUNK && start + tid < end) ? ids[start + tid] : 0u;
-    for (int64_t base = start; base < end; base += CHUNK) {
+    uint32_t rel0 = 0;  // list position of the chunk's first entry
+    for (;;) {
         if (__syncthreads_count(wave_done) == NT) break;
-        const int cnt = (int)min((int64_t)CHUNK, end - base);
+        if (tid < 64) walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids, &s_cnt, CHUNK);
+        __syncthreads();
+        const int cnt = s_cnt;
+        if (cnt == 0) break;  // uniform: the list is exhausted
         for (int k = tid; k < cnt; k += NT) {
-            const uint32_t gid = k == tid ? nid : ids[base + k];
-            stage_splat(recs[gid], gid, ty * B, ty * B + B - 1, s_sp[k]);
+            const uint32_t raw = s_ids[k];
+            stage_splat(walk.record(raw), raw & ~kFromStatic, ty * B, ty * B + B - 1, s_sp[k]);
         }
-        nid = (tid < CHUNK && base + CHUNK + tid < end) ? ids[base + CHUNK + tid] : 0u;
         __syncthreads();
         if (!wave_done) {
-            const uint32_t rel0 = (uint32_t)(base - start);
             // one blending step of the lane's pixels with splat j; true once every
             // pixel of the wave is finished
             auto step = [&](int j, auto rows_tag) {
@@ -263,6 +285,7 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
                                       [&](int i, auto tag) { return step(g0 + i, tag); });
             }
         }
+        rel0 += (uint32_t)cnt;
     }
     const size_t HW = (size_t)V.W * V.H;
 #pragma unroll
@@ -309,9 +332,13 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
             atomicAdd(&thist[cost_bucket(s_cost)], 1u);
         }
     }
-    if (STATS && threadIdx.x == 0) {
-        atomicAdd(&counters[4], (unsigned long long)(end - start));
-        atomicAdd(&counters[5], (unsigned long long)tile_last);
+    if (STATS && threadIdx.x < 64) {
+        // the tile's list length: the entries walked and those left
+        const unsigned long long len = (unsigned long long)rel0 + walk.remaining();
+        if (threadIdx.x == 0) {
+            atomicAdd(&counters[4], len);
+            atomicAdd(&counters[5], (unsigned long long)tile_last);
+        }
     }
     }
     if (STATS) {
@@ -362,25 +389,27 @@ __device__ __forceinline__ void wave_sum9(float e0, float e1, float e2, float e3
 // Per splat of the tile's list (up to its last contributor), the wave's nine
 // gradient sums (wave_sum9) are added into the splat's g2 record with global
 // atomics by four lanes.
-template <int B, int CHUNK, bool STATS>
+template <int B, int CHUNK, bool STATS, bool MERGE>
 __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
-    const Rec* __restrict__ recs, int N, const uint32_t* __restrict__ ids, const int64_t* __restrict__ ranges,
-    const ViewParams* __restrict__ views, int v0, int v1, const uint32_t* __restrict__ order, CPtrTable dls,
-    const float* __restrict__ Tfin, const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout,
-    float* __restrict__ g2, unsigned long long* counters) {
+    const Rec* __restrict__ recs, int N, CoarseLists lists, const ViewParams* __restrict__ views, int v0, int v1,
+    const uint32_t* __restrict__ order, CPtrTable dls, const float* __restrict__ Tfin,
+    const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout, float* __restrict__ g2,
+    unsigned long long* counters) {
     constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
+    __shared__ uint32_t s_ids[CHUNK];
+    __shared__ WalkQueues s_q;
+    __shared__ int s_cnt;
     __shared__ uint32_t s_max;
     const int gt = views[v0].tile_base + dispatch_tile(order);
     const int view = find_view_of_tile(views, v0, v1, gt);
     const ViewParams& V = views[view];
     const int tile = gt - V.tile_base;
-    recs += (size_t)view * N;
-    g2 += (size_t)view * N * kG2Stride;
+    g2 += (size_t)view * N * kG2Stride;  // indexed by splat id: the view's own gradient records
     const float* __restrict__ dl = dls.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
-    const int64_t start = ranges[2 * (size_t)(V.tile_base + tile)];
-    const int64_t list_end = ranges[2 * (size_t)(V.tile_base + tile) + 1];
+    TileWalk<MERGE> walk;
+    walk.init(lists, V, view, recs, N, super_factor(B), tx, ty);
     const size_t HW = (size_t)V.W * V.H;
     const int lane = __lane_id();
     // all pixels of a lane share one column (NT is a multiple of B)
@@ -413,9 +442,10 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     __syncthreads();
     if (lane_nc) atomicMax(&s_max, lane_nc);
     __syncthreads();
-    // the forward's last contributor; never past the tile's list (a state whose
-    // per-pixel part comes from another forward reads no foreign entries)
-    const int64_t end = min(start + (int64_t)s_max, list_end);
+    // the forward's last contributor (the walk ends with the tile's list, so a
+    // state whose per-pixel part comes from another forward reads no foreign
+    // entries)
+    const uint32_t total = s_max;
     const uint32_t wave_nc = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_nc));
     const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;
@@ -432,19 +462,17 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const float m1 = comp0 == 0 ? -0.5f : 0.0f, c1 = comp0 == 0 ? 0.0f : 1.0f;
     const int off0 = comp0, off1 = 4 + comp0;
     const int tid = (int)threadIdx.x;
-    // this thread's first list slot of the next chunk, loaded a chunk ahead so
-    // that staging waits for the record gather only
-    uint32_t nid = (tid < CHUNK && start + tid < end) ? ids[start + tid] : 0u;
-    for (int64_t base = start; base < end; base += CHUNK) {
-        const int cnt = (int)min((int64_t)CHUNK, end - base);
+    for (uint32_t rel0 = 0; rel0 < total;) {
         __syncthreads();  // the previous chunk's LDS is no longer read
-        for (int k = tid; k < cnt; k += NT) {
-            const uint32_t gid = k == tid ? nid : ids[base + k];
-            stage_splat(recs[gid], gid, ty * B, ty * B + B - 1, s_sp[k]);
-        }
-        nid = (tid < CHUNK && base + CHUNK + tid < end) ? ids[base + CHUNK + tid] : 0u;
+        if (tid < 64) walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids, &s_cnt, (int)min((uint32_t)CHUNK, total - rel0));
         __syncthreads();
-        const uint32_t rel0 = (uint32_t)(base - start);
+        const int cnt = s_cnt;
+        if (cnt == 0) break;  // uniform: the list is exhausted
+        for (int k = tid; k < cnt; k += NT) {
+            const uint32_t raw = s_ids[k];
+            stage_splat(walk.record(raw), raw & ~kFromStatic, ty * B, ty * B + B - 1, s_sp[k]);
+        }
+        __syncthreads();
         // entries past this wave's last contributor need no work
         const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
         // the adjoint of one blending step with splat j; gid: its splat id
@@ -527,6 +555,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 return false;
             });
         }
+        rel0 += (uint32_t)cnt;
     }
     if (STATS) {
         const unsigned long long e = wave_sum_u64(n_eval), b = wave_sum_u64(n_blend);
@@ -559,32 +588,105 @@ static void launch_timed(void (*k)(P...), int grid, int block, hipStream_t st, h
 }
 
 template <int B, int C>
-static void fwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
+static void fwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, const ViewParams* views, int v0,
                   int v1, int n_tiles, const uint32_t* order, const PtrTable& images, float* Tfin,
                   uint32_t* ncontrib, float* Cout, uint32_t* tcost, uint32_t* thist, unsigned long long* counters,
                   hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const bool stats = counters != nullptr;
+#define H4D_FWD(SPLIT)                                                                                            \
+    launch_timed(merge ? (stats ? k_composite_fwd<B, C, true, SPLIT, true> : k_composite_fwd<B, C, false, SPLIT, true>) \
+                       : (stats ? k_composite_fwd<B, C, true, SPLIT, false>                                         \
+                                : k_composite_fwd<B, C, false, SPLIT, false>),                                      \
+                 n_tiles, ShapeF<B, SPLIT>::NT, st, e0, e1, recs, N, lists, views, v0, v1, order, images, Tfin,    \
+                 ncontrib, Cout, tcost, thist, counters)
     if constexpr (B == 16) {
         if (n_tiles <= kSplitTiles) {
-            constexpr int NT = ShapeF<B, true>::NT;
-            launch_timed(counters ? k_composite_fwd<B, C, true, true> : k_composite_fwd<B, C, false, true>, n_tiles,
-                         NT, st, e0, e1, recs, N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout,
-                         tcost, thist, counters);
+            H4D_FWD(true);
             return;
         }
     }
-    constexpr int NT = ShapeF<B, false>::NT;
-    launch_timed(counters ? k_composite_fwd<B, C, true, false> : k_composite_fwd<B, C, false, false>, n_tiles, NT, st,
-                 e0, e1, recs, N, ids, ranges, views, v0, v1, order, images, Tfin, ncontrib, Cout, tcost, thist,
-                 counters);
+    H4D_FWD(false);
+#undef H4D_FWD
 }
 template <int B, int C>
-static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges, const ViewParams* views, int v0,
+static void bwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, const ViewParams* views, int v0,
                   int v1, int n_tiles, const uint32_t* order, const CPtrTable& dls, const float* Tfin,
                   const uint32_t* ncontrib, const float* Cout, float* g2, unsigned long long* counters, hipStream_t st,
                   hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
-    launch_timed(counters ? k_composite_bwd<B, C, true> : k_composite_bwd<B, C, false>, n_tiles, NT, st, e0, e1, recs,
-                 N, ids, ranges, views, v0, v1, order, dls, Tfin, ncontrib, Cout, g2, counters);
+    const bool stats = counters != nullptr;
+    launch_timed(merge ? (stats ? k_composite_bwd<B, C, true, true> : k_composite_bwd<B, C, false, true>)
+                       : (stats ? k_composite_bwd<B, C, true, false> : k_composite_bwd<B, C, false, false>),
+                 n_tiles, NT, st, e0, e1, recs, N, lists, views, v0, v1, order, dls, Tfin, ncontrib, Cout, g2,
+                 counters);
+}
+
+// Tile lists written out (for inspection): one wave per tile walks the list as
+// the blending kernels do.  k_walk_count: cnt[tile] = list length;
+// k_walk_dump: the splat ids of tile t (indices into the merged set [4D | 3D])
+// at out[offsets[t] ..), and ranges[t] = [offsets[t], offsets[t] + cnt[t]).
+template <int S, bool MERGE>
+__global__ void __launch_bounds__(64) k_walk_count(const Rec* __restrict__ recs, int N, CoarseLists lists,
+                                                   const ViewParams* __restrict__ views, int v0, int v1,
+                                                   uint32_t* __restrict__ cnt) {
+    __shared__ WalkQueues s_q;
+    const int gt = views[v0].tile_base + (int)blockIdx.x;
+    const int view = find_view_of_tile(views, v0, v1, gt);
+    const ViewParams& V = views[view];
+    const int tile = gt - V.tile_base;
+    TileWalk<MERGE> walk;
+    walk.init(lists, V, view, recs, N, S, tile % V.tiles_x, tile / V.tiles_x);
+    const uint64_t n = walk.remaining();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = (uint32_t)n;
+}
+
+template <int S, bool MERGE>
+__global__ void __launch_bounds__(64) k_walk_dump(const Rec* __restrict__ recs, int N, CoarseLists lists,
+                                                  const ViewParams* __restrict__ views, int v0, int v1,
+                                                  const unsigned long long* __restrict__ offsets,
+                                                  uint32_t* __restrict__ out, uint64_t out_cap,
+                                                  int64_t* __restrict__ ranges) {
+    __shared__ WalkQueues s_q;
+    const int gt = views[v0].tile_base + (int)blockIdx.x;
+    const int view = find_view_of_tile(views, v0, v1, gt);
+    const ViewParams& V = views[view];
+    const int tile = gt - V.tile_base;
+    TileWalk<MERGE> walk;
+    walk.init(lists, V, view, recs, N, S, tile % V.tiles_x, tile / V.tiles_x);
+    const unsigned long long o0 = offsets[blockIdx.x], o1 = offsets[blockIdx.x + 1];
+    unsigned long long o = o0;
+    for (;;) {
+        uint32_t id;
+        const int got = walk.next(64, s_q, id);
+        const unsigned long long w = o + (unsigned)__lane_id();
+        if (__lane_id() < got && w < o1 && w < out_cap) out[w] = id & ~kFromStatic;
+        o += (unsigned)got;
+        if (got < 64) break;
+    }
+    if (threadIdx.x == 0) {
+        ranges[2 * (size_t)gt] = (int64_t)o0;
+        ranges[2 * (size_t)gt + 1] = (int64_t)o1;
+    }
+}
+
+void launch_walk_lists(int tile, const Rec* recs, int N, const CoarseLists& lists, bool merge,
+                       const ViewParams* views, int v0, int v1, int n_tiles, uint32_t* cnt,
+                       unsigned long long* offsets, unsigned long long* partials, uint32_t* out, uint64_t out_cap,
+                       int64_t* ranges, hipStream_t st) {
+    if (n_tiles == 0) return;
+#define H4D_WALK(S, M)                                                                                       \
+    do {                                                                                                     \
+        k_walk_count<S, M><<<n_tiles, 64, 0, st>>>(recs, N, lists, views, v0, v1, cnt);                      \
+        launch_scan_u32_u64(cnt, nullptr, n_tiles, offsets, partials, st);                                   \
+        k_walk_dump<S, M><<<n_tiles, 64, 0, st>>>(recs, N, lists, views, v0, v1, offsets, out, out_cap,      \
+                                                  ranges);                                                 \
+    } while (0)
+    if (super_factor(tile) == 2) {
+        if (merge) H4D_WALK(2, true); else H4D_WALK(2, false);
+    } else {
+        if (merge) H4D_WALK(4, true); else H4D_WALK(4, false);
+    }
+#undef H4D_WALK
 }
 
 #define H4D_DISPATCH(FN, ...)                                                   \
@@ -603,23 +705,23 @@ static void bwd_t(const Rec* recs, int N, const uint32_t* ids, const int64_t* ra
         else if (tile == 32 && chunk == 512) FN<32, 512>(__VA_ARGS__);          \
     } while (0)
 
-void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
                           uint32_t* thist, unsigned long long* counters, hipStream_t st, hipEvent_t e0,
                           hipEvent_t e1) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(fwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, order, images, Tfin, ncontrib, Cout, tcost,
+    H4D_DISPATCH(fwd_t, recs, N, lists, merge, views, v0, v1, n_tiles, order, images, Tfin, ncontrib, Cout, tcost,
                  thist, counters, st, e0, e1);
 }
 
-void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
                           float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(bwd_t, recs, N, ids, ranges, views, v0, v1, n_tiles, order, dls, Tfin, ncontrib, Cout, g2, counters,
-                 st, e0, e1);
+    H4D_DISPATCH(bwd_t, recs, N, lists, merge, views, v0, v1, n_tiles, order, dls, Tfin, ncontrib, Cout, g2,
+                 counters, st, e0, e1);
 }
 
 }  // namespace h4d

@@ -13,21 +13,32 @@ struct ViewIn {
     float t;
     float bg[3];
 };
+// Per view: the shared static binning (ViewParams' static_* fields, filled by
+// the host) and, at index k, the leader view of static group k (or -1).
+struct ViewShare {
+    int32_t static_view, static_group, static_super_base, group_leader;
+};
 struct ViewTableIn {
     int32_t n;
     int32_t tile;
     ViewIn v[kMaxViews];
+    ViewShare share[kMaxViews];
 };
 
 // preprocess.hip
 // The view table, cleared status / list-slot bases and empty tile ranges.
 void launch_init_state(const ViewTableIn& in, ViewParams* views, Status* status, unsigned long long* pair_base,
                        unsigned long long* ranges, size_t n_range_words, hipStream_t st);
-// Records of views [v0, v0 + nv) (recs: all views, [view][N]); depth keys and
-// ids of view v0 + r at dkeys/dvals + r * N.
-void launch_count_onscreen(const Rec* recs, size_t n, unsigned long long* counter, hipStream_t st);
-void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,
-                       uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
+// Counting variant: the on-screen (view, Gaussian) records of views [v0, v0 +
+// nv) (3D Gaussians read from each view's static_view), added to *counter.
+void launch_count_onscreen(const Rec* recs, int N, int n4, const ViewParams* views, int v0, int nv,
+                           unsigned long long* counter, hipStream_t st);
+// Records of views [v0, v0 + nv) (recs: all views, [view][N]), depth keys and
+// ids in the pass's segment layout: unshared (shared = 0), view v0 + r's at
+// r * N; shared, view v0 + r's 4D Gaussians at r * n4 and the 3D Gaussians of
+// static group g (computed for its leader view only) at nv * n4 + g * n3.
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, int shared,
+                       Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
                            const float* g2, const G3Grad& gr3, const G4Grad& gr4, const SetStats& st3,
                            const SetStats& st4, hipStream_t st);
@@ -56,7 +67,8 @@ bool radix_pass_fits(uint64_t capacity, int n_seg, int nbits, int items, size_t 
 // One stable LSD pass over `nbits` (<= 11) bits at `shift`, independently on
 // n_seg segments that start seg_stride elements apart (all arrays).  Count
 // (per segment) from *dcount when dcount != null, else hcount; capacity bounds
-// the count.  vals_out index is offset by *out_offset when out_offset != null.
+// the count.  Output positions (keys, values, digit ranges) are offset by
+// *out_offset when out_offset != null.
 // hist / totals hold hist_words / totals_words words; a pass that does not fit
 // them (radix_pass_fits) launches nothing and returns false.  items: keys per
 // thread, kSortItems or 2 (8-bit digits only; for short key sets, more and
@@ -92,42 +104,31 @@ struct CullShape {
     int mode;                       // 0: keep every tile, 1: test, 2: no pixel can pass
 };
 
-// Two-level binning over the views [v0, v1) of one pass; j = r * N + rank
-// indexes the depth-ordered Gaussians of view v0 + r (n = (v1 - v0) * N).
-// Super-tile ids are relative to view v0, tile ids t to its first tile.
+// Two-level binning over the views [v0, v1) of one pass; j indexes the pass's
+// depth-ordered entries in the segment layout sg (n entries; sorted_gid[j]:
+// the splat id, relative to its record's view).  Super-tile ids are relative to
+// view v0's first (a pass holds at most kMaxPassSupers of them).
 // partials: coarse_count_blocks(n) + 1 words, each count workgroup's sum.
 int coarse_count_blocks(int n);
-void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
-                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, unsigned long long* partials,
-                         hipStream_t st);
+void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, SegLayout sg, const Rec* recs,
+                         const ViewParams* views, int v0, int tile, int S, uint32_t* cnt, uint64_t* rect_sorted,
+                         CullShape* shapes, unsigned long long* partials, hipStream_t st);
 // offsets[j] = sum of cnt before j (offsets[n] = C) with run_start as in
-// launch_scan_u32_u64; coarse capacity (ccap entries) and list-slot (cap)
-// checks; regions of the pass: S^2 C slots from pair_base[v0], end to
-// pair_base[v1]; *eff_count = C, or 0 on overflow.
-void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* partials, uint64_t ccap, uint64_t cap,
-                           int S, unsigned long long* pair_base, int v0, int v1, Status* status,
-                           unsigned long long* eff_count, unsigned long long* offsets, uint32_t* run_start,
-                           uint64_t run_cap, hipStream_t st);
-// With mkey (super-tile ids of the pass below 2^16) the keys carry each entry's
-// tile mask in their upper 16 bits (cull: less the tiles no pixel of which can
-// reach alpha >= 1/255).
-void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, int N,
+// launch_scan_u32_u64; capacity check: the pass's C coarse entries go to
+// [cbase[v0], cbase[v0] + C) of the call's ccap; cbase[v1] receives the end
+// and status->pairs_needed grows by S^2 C; *eff_count = C, or 0 on overflow.
+void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* partials, uint64_t ccap, int S,
+                           unsigned long long* cbase, int v0, int v1, Status* status, unsigned long long* eff_count,
+                           unsigned long long* offsets, uint32_t* run_start, uint64_t run_cap, hipStream_t st);
+// Keys carry each entry's tile mask in their upper 16 bits (cull: less the
+// tiles no pixel of which can reach alpha >= 1/255).
+void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, SegLayout sg,
                         const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
-                        int S, int mkey, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys,
-                        uint32_t* vals, hipStream_t st);
-// cgid[k] = splat id of sorted coarse entry k (values = depth ranks).
-void launch_coarse_gather(const uint32_t* cvals, const uint32_t* sorted_gid, const unsigned long long* eff_count,
-                          uint32_t* cgid, hipStream_t st);
-// Per tile (one workgroup per super-tile of the pass): the splats of its
-// super-tile's sorted coarse list that go to it (the mask in the keys' upper
-// half with mkey, else the square overlap), in order, into its region; writes
-// ranges[tile].
-void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                       const uint32_t* cgid, int mkey, const int64_t* cranges, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_count, int supers, const ViewParams* views, int v0, int v1, int S,
-                       uint32_t* ids, int64_t* ranges, hipStream_t st);
-// ranges of sorted keys (compared under key_mask): ranges[2k], ranges[2k+1] =
-// [first, last+1) + *base (base may be null)
+                        int S, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals,
+                        hipStream_t st);
+// ranges of the sorted keys keys[*base ..) (compared under key_mask):
+// ranges[2k], ranges[2k+1] = [first, last+1), counted from keys (base may be
+// null: 0)
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st);
 // Backward prologue: zeroes g2[0, n_g2) and orders the tiles of every pass by
@@ -147,23 +148,34 @@ void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 // composite.hip
 bool composite_supported(int tile, int chunk);
 // One launch over the tiles of views [v0, v1) (n_tiles = their total): recs
-// holds every view's records ([view][N]), images/dls are indexed by view and
-// g2 holds kG2Stride floats per (view, Gaussian).  order (may be null: tile
+// holds every view's records ([view][N]), lists the call's sorted coarse lists
+// (merge: each tile merges its static group's 3D list with its own 4D list),
+// images/dls are indexed by view and g2 holds kG2Stride floats per (view,
+// Gaussian).  order (may be null: tile
 // b = workgroup b): the n_tiles tiles (relative to the launch's first) in
 // dispatch order, a permutation.  The forward writes, per tile, its last
 // contributor into tcost[global tile] and counts the launch's tiles per
 // cost_bucket into thist[kCostBuckets] (zero on entry).  Non-null e0 / e1
 // receive the kernel's own start / end time.
-void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
                           uint32_t* thist, unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);
-void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const uint32_t* ids, const int64_t* ranges,
+void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
                           float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);
+// The tile lists of the views [v0, v1) written out: ids (indices into the
+// merged set [4D | 3D]) of tile t (relative to view v0's first tile) at
+// out[offsets[t] ..) (positions from out_cap on are not written),
+// ranges[global tile] = [offsets[t], offsets[t + 1]); cnt holds n_tiles
+// words, offsets n_tiles + 1, partials scan_blocks(n_tiles) + 1.
+void launch_walk_lists(int tile, const Rec* recs, int N, const CoarseLists& lists, bool merge,
+                       const ViewParams* views, int v0, int v1, int n_tiles, uint32_t* cnt,
+                       unsigned long long* offsets, unsigned long long* partials, uint32_t* out, uint64_t out_cap,
+                       int64_t* ranges, hipStream_t st);
 // L1 loss gradient (loss.hip)
 void launch_l1_loss_grad(const float* img, const float* target, float* dl, size_t n, float scale, float* loss,
                          hipStream_t st);

@@ -260,18 +260,31 @@ struct TimeColour {
 // Forward kernel: one thread per Gaussian of the merged list [4D | 3D].
 // ---------------------------------------------------------------------------
 // grid.y runs over the views [v0, v0 + gridDim.y): records go to recs[view][N]
-// (absolute), depth keys and ids to dkeys/dvals[view - v0][N].
+// (absolute), depth keys and ids to the pass's segment layout: unshared,
+// dkeys/dvals[view - v0][N]; shared (static binning per camera), the view's 4D
+// Gaussians at (view - v0) n4 + g and, for a static group's leader view only,
+// the 3D Gaussians at nv n4 + group n3 + (g - n4) (the other views of the group
+// use the leader's 3D records and compute none).
 __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const ViewParams* __restrict__ views,
-                                                    int v0, Rec* __restrict__ recs,
+                                                    int v0, int shared, Rec* __restrict__ recs,
                                                     uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
     const int N = g3.n + g4.n;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
     const int view = v0 + (int)blockIdx.y;
     const ViewParams& V = views[view];
+    size_t slot;
+    if (!shared) {
+        slot = (size_t)blockIdx.y * N + g;
+    } else if (g < g4.n) {
+        slot = (size_t)blockIdx.y * g4.n + g;
+    } else {
+        if (V.static_view != view) return;  // the group's leader holds this 3D record
+        slot = (size_t)gridDim.y * g4.n + (size_t)V.static_group * g3.n + (g - g4.n);
+    }
     recs += (size_t)view * N;
-    dkeys += (size_t)blockIdx.y * N;
-    dvals += (size_t)blockIdx.y * N;
+    dkeys += slot - g;
+    dvals += slot - g;
     WorldF w;
     const float* shp;
     int shn, shi;
@@ -589,8 +602,8 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
     double stat_g = 0.0;
     int stat_n = 0;
     for (int v = 0; v < n_views; ++v) {
-        if (recs[(size_t)v * N + gidx].d.w == 0u) continue;
         const ViewParams& V = views[v];
+        if (recs[(size_t)V.static_view * N + gidx].d.w == 0u) continue;  // covers no pixel in this view
         if (st.grad || st.vis || st.step_vis) {
             const float* e = g2 + ((size_t)v * N + gidx) * kG2Stride;
             stat_g += ndc_grad_norm(e[0], e[1], V.W, V.H);
@@ -679,7 +692,10 @@ __device__ void write_views(const ViewTableIn& in, ViewParams* out) {
         p.sx = ceil_div(p.tiles_x, S);
         p.sy = ceil_div(p.tiles_y, S);
         p.super_base = super_base;
-        p.pad = 0;
+        p.static_view = in.share[v].static_view;
+        p.static_group = in.share[v].static_group;
+        p.static_super_base = in.share[v].static_super_base;
+        p.group_leader = in.share[v].group_leader;
         super_base += p.sx * p.sy;
         tile_base += p.tiles_x * p.tiles_y;
         pix_base += (long long)s.W * s.H;
@@ -711,11 +727,11 @@ void launch_init_state(const ViewTableIn& in, ViewParams* views, Status* status,
     k_init_state<<<nb, 256, 0, st>>>(in, views, status, pair_base, ranges, n_range_words);
 }
 
-void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, Rec* recs,
-                       uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
+void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, int shared,
+                       Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
     const int N = g3.n + g4.n;
     if (N == 0 || nv == 0) return;
-    k_preprocess<<<dim3(ceil_div(N, 256), nv), 256, 0, st>>>(g3, g4, views, v0, recs, dkeys, dvals);
+    k_preprocess<<<dim3(ceil_div(N, 256), nv), 256, 0, st>>>(g3, g4, views, v0, shared, recs, dkeys, dvals);
 }
 
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,

@@ -4,15 +4,19 @@
 // Design: the per-view depth order is established once over the N Gaussians
 // (LSD radix sort of the float32 depth bits, stable, so equal depths keep
 // ascending id).  Binning is then two-level: every depth-ordered Gaussian emits
-// one coarse entry per 64-pixel super-tile its square touches; a stable sort of
-// the coarse entries by super-tile keeps depth order inside each super-tile's
-// list; finally one workgroup per tile walks its super-tile's list and compacts
-// (64-lane ballot + prefix) the entries whose tile rectangle contains the tile
-// into that tile's region.  Every tile list is therefore exactly its (depth
-// bits, id)-ordered set of overlapping splats - the order a global
-// (tile, depth, id) sort gives - without sorting (Gaussian, tile) pairs at all.
-// Tile regions are sized by their super-tile's list length, so lists are not
-// contiguous across tiles; ranges give each list's [start, end).
+// one coarse entry per super-tile (S x S tiles) its square touches, keyed by
+// the super-tile and carrying the mask of the super-tile's tiles it reaches; a
+// stable sort of the coarse entries by super-tile keeps depth order inside each
+// super-tile's list.  A tile's list is the sub-sequence of its super-tile's
+// list whose mask holds the tile, which the blending kernels compact on the fly
+// (64-lane ballot + prefix, walk.hpp): exactly the tile's (depth bits,
+// id)-ordered set of overlapping splats - the order a global (tile, depth, id)
+// sort gives - without sorting or storing (Gaussian, tile) pairs at all.
+//
+// When a batched call repeats a camera at several times, the 3D Gaussians are
+// sorted and binned once per camera (a static group) onto a super-tile grid of
+// the group's own, and each view bins only its 4D Gaussians; the blending
+// kernels merge the two lists by depth.
 //
 // Every LSD pass is: per-block digit histogram -> per-digit scan across blocks
 // -> stable scatter.  The stable scatter ranks keys inside a wave with ballots
@@ -178,11 +182,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
     __syncthreads();
     const uint32_t n_out = block_scan_digits<MB>(s_gbase, radix, s_buf);
     if (out_count && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *out_count = n_out;
+    const unsigned long long off = out_offset ? *out_offset : 0ull;
     // a single-pass sort over whole keys: the digit runs are the key ranges
     if (digit_ranges && blockIdx.x == 0 && blockIdx.y == 0)
         for (int d = tid; d < n_digit_ranges; d += kSortThreads) {
-            digit_ranges[2 * (size_t)d] = s_gbase[d];
-            digit_ranges[2 * (size_t)d + 1] = (int64_t)s_gbase[d] + totals[d];
+            digit_ranges[2 * (size_t)d] = (int64_t)off + s_gbase[d];
+            digit_ranges[2 * (size_t)d + 1] = (int64_t)off + s_gbase[d] + totals[d];
         }
     for (int d = tid; d < radix; d += kSortThreads) s_gbase[d] += hist[(size_t)d * nblocks + blockIdx.x];
 
@@ -231,13 +236,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_downsweep(
         }
     }
     __syncthreads();
-    const unsigned long long off = out_offset ? *out_offset : 0ull;
     for (int p = tid; p < cnt; p += kSortThreads) {
         const uint32_t k = s_keys[p];
         const uint32_t d = (k >> shift) & mask;
-        const uint64_t dst = (uint64_t)s_gbase[d] + (uint64_t)(p - (int)s_dstart[d]);
+        const uint64_t dst = off + (uint64_t)s_gbase[d] + (uint64_t)(p - (int)s_dstart[d]);
         keys_out[dst] = k;
-        vals_out[dst + off] = val_map ? val_map[s_vals[p]] : s_vals[p];
+        vals_out[dst] = val_map ? val_map[s_vals[p]] : s_vals[p];
     }
 }
 
@@ -465,13 +469,31 @@ __device__ inline uint32_t tile_mask(const CullShape& cs, int cull, uint32_t tx0
     return mask;
 }
 
-// Per depth-ordered Gaussian j of the view range (j = r * N + rank, view
-// v0 + r): its tile rectangle, its super-tile count and (shapes != null) the
-// shape of its alpha >= 1/255 region for the tile test.
-// One Gaussian per thread; each workgroup also leaves its sum of counts for
+// Where depth-ordered entry j of a pass (segment layout sg) belongs: the view
+// whose records hold it and, for its super-tile keys, that view's grid and the
+// grid's first super-tile id relative to the pass (a static group's grid for
+// the group segments).
+struct SegPos {
+    int view, super0;
+};
+__device__ __forceinline__ SegPos seg_of(int j, const SegLayout& sg, const ViewParams* __restrict__ views, int v0) {
+    const int split = sg.na * sg.la;
+    if (j < split) {
+        const int v = v0 + j / sg.la;
+        return SegPos{v, views[v].super_base - views[v0].super_base};
+    }
+    const int leader = views[(j - split) / sg.lb].group_leader;
+    return SegPos{leader, views[leader].static_super_base - views[v0].super_base};
+}
+
+// Per depth-ordered entry j of the pass: its tile rectangle, its super-tile
+// count and (shapes != null) the shape of its alpha >= 1/255 region for the
+// tile test.
+// One entry per thread; each workgroup also leaves its sum of counts for
 // the offsets' scan (partials[blockIdx.x]).
 __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n, int N,
-                                                      const Rec* __restrict__ recs, int v0, int tile, int S,
+                                                      SegLayout sg, const Rec* __restrict__ recs,
+                                                      const ViewParams* __restrict__ views, int v0, int tile, int S,
                                                       uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted,
                                                       CullShape* __restrict__ shapes,
                                                       unsigned long long* __restrict__ partials) {
@@ -480,8 +502,8 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
     const int j = blockIdx.x * 256 + (int)threadIdx.x;
     uint32_t c = 0u;
     if (j < n) {
-        const int view = v0 + j / N;
-        const Rec& rec = recs[(size_t)view * N + sorted_gid[j]];
+        const SegPos sp = seg_of(j, sg, views, v0);
+        const Rec& rec = recs[(size_t)sp.view * N + sorted_gid[j]];
         const uint4 d = rec.d;
         uint64_t rect = 0ull;
         if (d.w != 0u) {
@@ -499,19 +521,24 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Counting variant only: records of the views [v0, v0 + nv) whose pixel square
-// meets the image (the on-screen (Gaussian, view) pairs), added to *counter.
-__global__ void __launch_bounds__(256) k_count_onscreen(const Rec* __restrict__ recs, size_t n,
+// Counting variant only: (view, Gaussian) pairs of the views [v0, v0 + nv)
+// whose pixel square meets the image (the on-screen pairs; a 3D Gaussian's
+// record is its view's static_view's), added to *counter.  grid.y: the view.
+__global__ void __launch_bounds__(256) k_count_onscreen(const Rec* __restrict__ recs, int N, int n4,
+                                                        const ViewParams* __restrict__ views, int v0,
                                                         unsigned long long* counter) {
-    const size_t j = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const bool on = j < n && recs[j].d.w != 0u;
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    const int v = v0 + (int)blockIdx.y;
+    const int rv = i < n4 ? v : views[v].static_view;
+    const bool on = i < N && recs[(size_t)rv * N + i].d.w != 0u;
     const unsigned long long c = (unsigned long long)__popcll(__ballot(on));
     if (__lane_id() == 0 && c) atomicAdd(counter, c);
 }
 
-void launch_count_onscreen(const Rec* recs, size_t n, unsigned long long* counter, hipStream_t st) {
-    if (n == 0) return;
-    k_count_onscreen<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(recs, n, counter);
+void launch_count_onscreen(const Rec* recs, int N, int n4, const ViewParams* views, int v0, int nv,
+                           unsigned long long* counter, hipStream_t st) {
+    if (N == 0 || nv == 0) return;
+    k_count_onscreen<<<dim3((unsigned)((N + 255) / 256), nv), 256, 0, st>>>(recs, N, n4, views, v0, counter);
 }
 
 // offsets[j] = partials[j / 256] (scanned) + this workgroup's exclusive scan;
@@ -533,21 +560,20 @@ __global__ void __launch_bounds__(256) k_coarse_down(const uint32_t* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = partials[nparts];
 }
 
-// The capacity check and tile-list regions of a pass whose coarse entries
-// total C (one thread): see k_coarse_top.
-__device__ inline void coarse_finalize(unsigned long long C, uint64_t ccap, uint64_t cap, int S,
-                                       unsigned long long* pair_base, int v0, int v1, Status* status,
-                                       unsigned long long* eff_count) {
-    const unsigned long long base = pair_base[v0];
-    const unsigned long long R = C * (unsigned long long)(S * S);
-    status->pairs_needed += R;
-    if (C > ccap || base + R > cap) {
+// The capacity check of a pass whose coarse entries total C (one thread): its
+// entries take [cbase[v0], cbase[v0] + C) of the call's ccap; the need is
+// counted in (Gaussian, tile) slots, S^2 per coarse entry.
+__device__ inline void coarse_finalize(unsigned long long C, uint64_t ccap, int S, unsigned long long* cbase, int v0,
+                                       int v1, Status* status, unsigned long long* eff_count) {
+    const unsigned long long base = cbase[v0];
+    status->pairs_needed += C * (unsigned long long)(S * S);
+    if (base + C > ccap) {
         status->flags |= kFlagOverflow;
         *eff_count = 0ull;
-        pair_base[v1] = base;
+        cbase[v1] = base;
     } else {
         *eff_count = C;
-        pair_base[v1] = base + R;
+        cbase[v1] = base + C;
     }
 }
 
@@ -558,8 +584,8 @@ __device__ inline void coarse_finalize(unsigned long long C, uint64_t ccap, uint
 constexpr int kDirectParts = 2048;
 __global__ void __launch_bounds__(256) k_coarse_down_direct(const uint32_t* __restrict__ cnt, int n,
                                                             const unsigned long long* __restrict__ partials,
-                                                            int nparts, uint64_t ccap, uint64_t cap, int S,
-                                                            unsigned long long* pair_base, int v0, int v1,
+                                                            int nparts, uint64_t ccap, int S,
+                                                            unsigned long long* cbase, int v0, int v1,
                                                             Status* status, unsigned long long* eff_count,
                                                             unsigned long long* __restrict__ offsets,
                                                             uint32_t* __restrict__ run_start, uint64_t run_cap) {
@@ -572,7 +598,7 @@ __global__ void __launch_bounds__(256) k_coarse_down_direct(const uint32_t* __re
     block_exclusive_scan_256<unsigned long long>(acc, s_buf, sum);
     const unsigned long long before = b == 0 ? 0ull : sum;
     if (b == 0 && threadIdx.x == 0) {
-        coarse_finalize(sum, ccap, cap, S, pair_base, v0, v1, status, eff_count);
+        coarse_finalize(sum, ccap, S, cbase, v0, v1, status, eff_count);
         offsets[n] = sum;
     }
     const int j = b * 256 + (int)threadIdx.x;
@@ -586,17 +612,13 @@ __global__ void __launch_bounds__(256) k_coarse_down_direct(const uint32_t* __re
 }
 
 // Exclusive scan of the count workgroups' sums (partials[nparts] = total C),
-// then the coarse capacity check and the tile-list regions of the pass: the
-// S^2 tiles of a super-tile get regions as long as the super-tile's list, so
-// the pass needs S^2 C list slots from pair_base[v0]; their end goes to
-// pair_base[v1].
+// then the coarse capacity check of the pass (coarse_finalize).
 // (1024 threads, each scanning a contiguous chunk of the partials four loads
 // at a time: with many count workgroups, e.g. 32 views of 1M Gaussians, this
 // single workgroup's walk over the partials is the launch)
 __global__ void __launch_bounds__(1024) k_coarse_top(unsigned long long* __restrict__ partials, int nparts,
-                                                     uint64_t ccap, uint64_t cap, int S,
-                                                     unsigned long long* pair_base, int v0, int v1, Status* status,
-                                                     unsigned long long* eff_count) {
+                                                     uint64_t ccap, int S, unsigned long long* cbase, int v0,
+                                                     int v1, Status* status, unsigned long long* eff_count) {
     __shared__ unsigned long long s_w[16];
     const int tid = (int)threadIdx.x, lane = tid & 63, w = tid >> 6;
     // thread t scans the contiguous chunk [t q, (t + 1) q) of the partials
@@ -642,31 +664,31 @@ __global__ void __launch_bounds__(1024) k_coarse_top(unsigned long long* __restr
     }
     if (tid != 0) return;
     partials[nparts] = carry;
-    coarse_finalize(carry, ccap, cap, S, pair_base, v0, v1, status, eff_count);
+    coarse_finalize(carry, ccap, S, cbase, v0, v1, status, eff_count);
 }
 
-// Coarse entries (super-tile id relative to the range's first view, depth
-// rank j), written in (view, depth) order: one thread per entry, which finds
-// its Gaussian by binary search over the count offsets (entries, not
-// Gaussians, are spread evenly: the nearest splats are the largest and sit
-// together in depth order).  With mkey the key's upper 16 bits carry the
-// entry's tile mask (the super-tile sort reads only the low bits); shapes !=
-// null applies the alpha >= 1/255 tile test.
+// Coarse entries (super-tile id relative to the pass's first, depth rank j),
+// written in (segment, depth) order: one thread per entry, which finds its
+// Gaussian by binary search over the count offsets (entries, not Gaussians,
+// are spread evenly: the nearest splats are the largest and sit together in
+// depth order).  The key's upper 16 bits carry the entry's tile mask (the
+// super-tile sort reads only the low bits); shapes != null applies the alpha
+// >= 1/255 tile test.
 __global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* __restrict__ offsets,
-                                                     const uint32_t* __restrict__ run_start, int n, int N,
+                                                     const uint32_t* __restrict__ run_start, int n, SegLayout sg,
                                                      const uint64_t* __restrict__ rect_sorted,
                                                      const CullShape* __restrict__ shapes,
                                                      const ViewParams* __restrict__ views, int v0, int tile, int S,
-                                                     int mkey, const unsigned long long* eff_count,
+                                                     const unsigned long long* eff_count,
                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     __shared__ unsigned long long s_off[257];
     const uint64_t C = *eff_count;
     const int tid = threadIdx.x;
     // blocks take runs of 256 consecutive entries (run_start names the Gaussian
-    // holding a run's first entry); within a view invisible
+    // holding a run's first entry); within a segment invisible
     // Gaussians sort last (culled key), so the visible ones all own entries and
     // a run usually spans at most 256 consecutive Gaussians (entries past the
-    // block's window, after another view's invisible tail, search globally)
+    // block's window, after another segment's invisible tail, search globally)
     for (uint64_t p0 = (uint64_t)blockIdx.x * 256; p0 < C; p0 += (uint64_t)gridDim.x * 256) {
         const int j0 = (int)run_start[p0 / 256];  // Gaussian holding entry p0
         s_off[tid] = offsets[min(j0 + tid, n)];
@@ -693,7 +715,8 @@ __global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* _
                 j = lo;
                 pj = offsets[lo];
             }
-            const ViewParams& V = views[v0 + j / N];
+            const SegPos sp = seg_of(j, sg, views, v0);
+            const ViewParams& V = views[sp.view];
             const uint64_t r = rect_sorted[j];
             const uint32_t s = (uint32_t)S;
             const uint32_t tx0 = (uint32_t)(r & 0xFFFFu), tx1 = (uint32_t)((r >> 16) & 0xFFFFu);
@@ -701,111 +724,16 @@ __global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* _
             const uint32_t sx0 = tx0 / s, sw = tx1 / s - sx0 + 1u, sy0 = ty0 / s;
             const uint32_t local = (uint32_t)(p - pj);
             const uint32_t sy = local / sw, sx = local - sy * sw;
-            uint32_t key = (uint32_t)(V.super_base - views[v0].super_base) + (sy0 + sy) * (uint32_t)V.sx + sx0 + sx;
-            if (mkey) {
-                CullShape keep_all;
-                keep_all.mode = 0;
-                const uint32_t m = tile_mask(shapes ? shapes[j] : keep_all, shapes != nullptr, tx0, tx1, ty0, ty1,
-                                             (sx0 + sx) * s, (sy0 + sy) * s, S, tile);
-                key |= m << 16;
-            }
+            uint32_t key = (uint32_t)sp.super0 + (sy0 + sy) * (uint32_t)V.sx + sx0 + sx;
+            CullShape keep_all;
+            keep_all.mode = 0;
+            const uint32_t m = tile_mask(shapes ? shapes[j] : keep_all, shapes != nullptr, tx0, tx1, ty0, ty1,
+                                         (sx0 + sx) * s, (sy0 + sy) * s, S, tile);
+            key |= m << 16;
             keys[p] = key;
             vals[p] = (uint32_t)j;
         }
         __syncthreads();
-    }
-}
-
-// After the coarse sort: the splat id of every coarse entry, so that the
-// per-tile pass (16 tiles read each entry) needs no further indirection.
-__global__ void __launch_bounds__(256) k_coarse_gather(const uint32_t* __restrict__ cvals,
-                                                       const uint32_t* __restrict__ sorted_gid,
-                                                       const unsigned long long* eff_count,
-                                                       uint32_t* __restrict__ cgid) {
-    const uint64_t n = *eff_count;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
-        cgid[k] = sorted_gid[cvals[k]];
-}
-
-// One workgroup per super-tile, one wave per tile of it (S^2 waves): every
-// round the block stages blockDim entries of the super-tile's sorted coarse
-// list (tile mask, splat id) in LDS, and each wave compacts, in order, the
-// entries whose mask holds its tile into the tile's region (local tile lt:
-// S^2 * start + lt * length past pair_base[v0]), then writes the tile's range.
-// With mkey the mask is in the keys' upper 16 bits; otherwise it is the tiles
-// the splat's square overlaps.
-__global__ void __launch_bounds__(1024) k_tile_write(const uint32_t* __restrict__ ckeys,
-                                                     const uint32_t* __restrict__ cvals,
-                                                     const uint64_t* __restrict__ rect_sorted,
-                                                     const uint32_t* __restrict__ cgid, int mkey,
-                                                     const int64_t* __restrict__ cranges,
-                                                     const unsigned long long* base_ptr,
-                                                     const unsigned long long* eff_count,
-                                                     const ViewParams* __restrict__ views, int v0, int v1, int S,
-                                                     uint32_t* __restrict__ ids, int64_t* __restrict__ ranges) {
-    __shared__ uint32_t s_mask[1024];
-    __shared__ uint32_t s_gid[1024];
-    if (*eff_count == 0ull) return;
-    const int st = blockIdx.x;  // super-tile, relative to view v0's first
-    // its view: the last view of the pass whose first super-tile is <= st
-    int view = v0;
-    while (view + 1 < v1 && views[view + 1].super_base - views[v0].super_base <= st) ++view;
-    const ViewParams& V = views[view];
-    const int stl = st - (V.super_base - views[v0].super_base);
-    const uint32_t SX = (uint32_t)V.sx;
-    const uint32_t bx = (uint32_t)(stl % (int)SX) * (uint32_t)S, by = (uint32_t)(stl / (int)SX) * (uint32_t)S;
-    const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
-    const uint32_t lx = (uint32_t)w % (uint32_t)S, ly = (uint32_t)w / (uint32_t)S;
-    const uint32_t tx = bx + lx, ty = by + ly;
-    const bool exists = tx < (uint32_t)V.tiles_x && ty < (uint32_t)V.tiles_y;  // edge super-tiles are partial
-    const int64_t cs = cranges[2 * st], ce = cranges[2 * st + 1];
-    const uint64_t out = (uint64_t)*base_ptr + (uint64_t)(S * S) * (uint64_t)cs + (uint64_t)w * (uint64_t)(ce - cs);
-    const unsigned long long lt = lanemask_lt();
-    const int round = blockDim.x;
-    // entry k's tile mask within this super-tile and splat id (zeros past ce)
-    auto fetch = [&](int64_t k, uint32_t& m, uint32_t& g) {
-        m = 0u;
-        g = 0u;
-        if (k < ce) {
-            const uint32_t key = ckeys[k];
-            if (mkey) {
-                m = key >> 16;
-            } else {  // square overlap: the tiles of the splat's tile rectangle inside this super-tile
-                const uint64_t rc = rect_sorted[cvals[k]];
-                const uint32_t x0 = (uint32_t)(rc & 0xFFFFu), x1 = (uint32_t)((rc >> 16) & 0xFFFFu);
-                const uint32_t y0 = (uint32_t)((rc >> 32) & 0xFFFFu), y1 = (uint32_t)(rc >> 48);
-                for (uint32_t yy = max(y0, by); yy <= min(y1, by + (uint32_t)S - 1u); ++yy)
-                    for (uint32_t xx = max(x0, bx); xx <= min(x1, bx + (uint32_t)S - 1u); ++xx)
-                        m |= 1u << ((yy - by) * (uint32_t)S + (xx - bx));
-            }
-            g = cgid[k];
-        }
-    };
-    uint64_t run = 0;
-    uint32_t m, g;
-    fetch(cs + tid, m, g);
-    for (int64_t k0 = cs; k0 < ce; k0 += round) {
-        s_mask[tid] = m;
-        s_gid[tid] = g;
-        __syncthreads();
-        // the next round's entries are loaded while this round is compacted
-        fetch(k0 + round + tid, m, g);
-        if (exists) {
-            const int cnt = (int)min((int64_t)round, ce - k0);
-            for (int c0 = 0; c0 < cnt; c0 += 64) {
-                const int c = c0 + lane;
-                const bool keep = c < cnt && ((s_mask[c] >> w) & 1u);
-                const unsigned long long bal = __ballot(keep);
-                if (keep) ids[out + run + (uint64_t)__popcll(bal & lt)] = s_gid[c];
-                run += (uint64_t)__popcll(bal);
-            }
-        }
-        __syncthreads();
-    }
-    if (exists && lane == 0) {
-        const size_t gt = (size_t)V.tile_base + ty * (uint32_t)V.tiles_x + tx;
-        ranges[2 * gt] = (int64_t)out;
-        ranges[2 * gt + 1] = (int64_t)(out + run);
     }
 }
 
@@ -814,6 +742,7 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ key
                                                 const unsigned long long* base_ptr, int64_t* __restrict__ ranges) {
     const uint64_t n = *eff_count;
     const int64_t base = base_ptr ? (int64_t)*base_ptr : 0;
+    keys += base;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t t = keys[i] & key_mask;
         if (i == 0 || (keys[i - 1] & key_mask) != t) ranges[2 * (size_t)t] = base + (int64_t)i;
@@ -890,47 +819,34 @@ __global__ void k_fill_f32(float* p, size_t n, float val) {
 }
 
 int coarse_count_blocks(int n) { return ceil_div(n, 256); }
-void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, const Rec* recs, int v0, int tile, int S,
-                         uint32_t* cnt, uint64_t* rect_sorted, CullShape* shapes, unsigned long long* partials,
-                         hipStream_t st) {
+void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, SegLayout sg, const Rec* recs,
+                         const ViewParams* views, int v0, int tile, int S, uint32_t* cnt, uint64_t* rect_sorted,
+                         CullShape* shapes, unsigned long long* partials, hipStream_t st) {
     if (n == 0) return;
-    k_coarse_count<<<coarse_count_blocks(n), 256, 0, st>>>(sorted_gid, n, N, recs, v0, tile, S, cnt, rect_sorted,
-                                                           shapes, partials);
+    k_coarse_count<<<coarse_count_blocks(n), 256, 0, st>>>(sorted_gid, n, N, sg, recs, views, v0, tile, S, cnt,
+                                                           rect_sorted, shapes, partials);
 }
-void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* partials, uint64_t ccap, uint64_t cap,
-                           int S, unsigned long long* pair_base, int v0, int v1, Status* status,
-                           unsigned long long* eff_count, unsigned long long* offsets, uint32_t* run_start,
-                           uint64_t run_cap, hipStream_t st) {
+void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* partials, uint64_t ccap, int S,
+                           unsigned long long* cbase, int v0, int v1, Status* status, unsigned long long* eff_count,
+                           unsigned long long* offsets, uint32_t* run_start, uint64_t run_cap, hipStream_t st) {
     const int nb = coarse_count_blocks(n);
     if (n > 0 && nb <= kDirectParts) {
-        k_coarse_down_direct<<<nb, 256, 0, st>>>(cnt, n, partials, nb, ccap, cap, S, pair_base, v0, v1, status,
-                                                 eff_count, offsets, run_start, run_cap);
+        k_coarse_down_direct<<<nb, 256, 0, st>>>(cnt, n, partials, nb, ccap, S, cbase, v0, v1, status, eff_count,
+                                                 offsets, run_start, run_cap);
         return;
     }
-    k_coarse_top<<<1, 1024, 0, st>>>(partials, nb, ccap, cap, S, pair_base, v0, v1, status, eff_count);
+    k_coarse_top<<<1, 1024, 0, st>>>(partials, nb, ccap, S, cbase, v0, v1, status, eff_count);
     if (n > 0) k_coarse_down<<<nb, 256, 0, st>>>(cnt, n, partials, nb, offsets, run_start, run_cap);
 }
-void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, int N,
+void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, SegLayout sg,
                         const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
-                        int S, int mkey, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys,
-                        uint32_t* vals, hipStream_t st) {
+                        int S, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals,
+                        hipStream_t st) {
     if (n == 0 || capacity == 0) return;
     // (32 views of 1M Gaussians in one pass: about 25 runs of 256 entries per workgroup)
     const int nb = (int)std::min<uint64_t>(65536, (capacity + 255) / 256);
-    k_coarse_emit<<<nb, 256, 0, st>>>(offsets, run_start, n, N, rect_sorted, shapes, views, v0, tile, S, mkey,
-                                      eff_count, keys, vals);
-}
-void launch_coarse_gather(const uint32_t* cvals, const uint32_t* sorted_gid, const unsigned long long* eff_count,
-                          uint32_t* cgid, hipStream_t st) {
-    k_coarse_gather<<<2048, 256, 0, st>>>(cvals, sorted_gid, eff_count, cgid);
-}
-void launch_tile_write(const uint32_t* ckeys, const uint32_t* cvals, const uint64_t* rect_sorted,
-                       const uint32_t* cgid, int mkey, const int64_t* cranges, const unsigned long long* base_ptr,
-                       const unsigned long long* eff_count, int supers, const ViewParams* views, int v0, int v1, int S,
-                       uint32_t* ids, int64_t* ranges, hipStream_t st) {
-    if (supers == 0) return;
-    k_tile_write<<<supers, 64 * S * S, 0, st>>>(ckeys, cvals, rect_sorted, cgid, mkey, cranges, base_ptr, eff_count,
-                                                views, v0, v1, S, ids, ranges);
+    k_coarse_emit<<<nb, 256, 0, st>>>(offsets, run_start, n, sg, rect_sorted, shapes, views, v0, tile, S, eff_count,
+                                      keys, vals);
 }
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {

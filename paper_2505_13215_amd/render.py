@@ -231,6 +231,28 @@ class Rasterizer:
         return gr3, gr4
 
 
+    def tile_lists(self, h: FwdHandle) -> tuple:
+        """The tile lists of forward `h` (the last one on this rasterizer):
+        (ids, ranges[total tiles, 2]); tile t's depth-ordered splat ids (into the
+        merged set [4D | 3D]) are ids[ranges[t, 0]:ranges[t, 1]], tiles of the
+        views one after another."""
+        if h.generation != self._gen:
+            raise RuntimeError("tile_lists must follow its own forward (the workspace was reused)")
+        t = h.cfg.tile
+        tiles = sum(((h.views[k].width + t - 1) // t) * ((h.views[k].height + t - 1) // t) for k in range(h.n_views))
+        cap = max(1, h.cfg.pair_capacity)
+        ranges = torch.empty((tiles, 2), dtype=torch.int64, device="cuda")
+        for _ in range(2):
+            ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+            self.ctx.check(self.ctx.L.h4dgs_tile_lists(
+                self.ctx.h, h.n3, h.n4, h.views, h.n_views, C.byref(h.cfg), _ptr(h.state), h.state.numel(),
+                _ptr(self._scratch), self._scratch.numel(), _ptr(ids), C.c_uint64(cap), _ptr(ranges), _stream()))
+            total = int(ranges[-1, 1]) if tiles else 0
+            if total <= cap:
+                return ids, ranges
+            cap = total  # a shared static list counts once per view: make room and write again
+        raise RuntimeError("tile lists kept growing")
+
     # -- instrumentation -----------------------------------------------------------
     def profile(self, enable=True):
         """Event timing of later calls: False / 0 off, True / 1 every stage

@@ -76,12 +76,22 @@ def test_workspace_size_grows_with_inputs(L):
     assert st.value >= s1 + 2000 * 64 + 128 * 96 * 20
 
 
+def _distinct_views(L, n=4, W=128, H=96):
+    v = sg.tiny_scene(n3=1, n4=1, width=W, height=H).views[0]
+    out = []
+    for k in range(n):
+        M = v.world_to_cam.copy()
+        M[0, 3] += 0.01 * k
+        out.append(sg.View(M, v.fx, v.fy, v.cx, v.cy, W, H, 0.5, v.bg))
+    return L.view_array(out)
+
+
 def test_batched_workspace(L):
     """Batched mode keeps the same state (kept from forward to backward) and
     needs per-pass scratch for every view of the call at once."""
     c = _ctx(L)
     st, sc = C.c_size_t(), C.c_size_t()
-    va = _views(L, 4)
+    va = _distinct_views(L, 4)
     assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, va, 4, C.byref(_cfg(L)), C.byref(st), C.byref(sc)) == 0
     s_single, k_single = st.value, sc.value
     assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, va, 4, C.byref(_cfg(L, batched=1)), C.byref(st),
@@ -90,6 +100,44 @@ def test_batched_workspace(L):
     assert sc.value >= k_single
     # depth keys, ids and their sort buffers for all four views
     assert sc.value >= 4 * 4000 * 16
+
+
+def test_shared_static_binning_workspace(L):
+    """Four views of one camera in a batched call bin the 3D Gaussians once,
+    on a super-tile grid of their own: the state grows by that grid's list
+    ranges (16 bytes per super-tile: 128 x 96 pixels at 16-pixel tiles is 2 x 2
+    super-tiles of 64 pixels, rounded up to the workspace's 256-byte alignment),
+    the scratch does not grow (its depth sorts are over fewer keys)."""
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, _distinct_views(L, 4), 4, C.byref(_cfg(L, batched=1)),
+                                    C.byref(st), C.byref(sc)) == 0
+    s_distinct, k_distinct = st.value, sc.value
+    assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, _views(L, 4), 4, C.byref(_cfg(L, batched=1)), C.byref(st),
+                                    C.byref(sc)) == 0
+    assert 0 < st.value - s_distinct <= 256 and sc.value <= k_distinct
+    # no 3D Gaussians: nothing to share
+    assert c.L.h4dgs_workspace_size(c.h, 0, 4000, _views(L, 4), 4, C.byref(_cfg(L, batched=1)), C.byref(st),
+                                    C.byref(sc)) == 0
+    s0 = st.value
+    assert c.L.h4dgs_workspace_size(c.h, 0, 4000, _distinct_views(L, 4), 4, C.byref(_cfg(L, batched=1)),
+                                    C.byref(st), C.byref(sc)) == 0
+    assert st.value == s0
+
+
+def test_views_beyond_one_pass_of_super_tiles_are_refused(L):
+    """A view's super-tiles must fit one pass's 16-bit key range: 8200 x 8200
+    pixels at 8-pixel tiles (257 x 257 super-tiles of 32 pixels) is refused
+    before anything is enqueued, 8192 x 8192 is accepted."""
+    c = _ctx(L)
+    st, sc = C.c_size_t(), C.c_size_t()
+    ok = c.L.h4dgs_workspace_size(c.h, 10, 10, _views(L, 1, 8192, 8192), 1, C.byref(_cfg(L, tile=8)), C.byref(st),
+                                  C.byref(sc))
+    assert ok == L.H4D_OK
+    bad = c.L.h4dgs_workspace_size(c.h, 10, 10, _views(L, 1, 8200, 8200), 1, C.byref(_cfg(L, tile=8)),
+                                   C.byref(st), C.byref(sc))
+    assert bad == L.H4D_ERR_UNSUPPORTED
+    assert "super-tiles" in c.L.h4dgs_last_error(c.h).decode()
 
 
 def test_batched_pass_size_limit(L):

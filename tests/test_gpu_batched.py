@@ -194,7 +194,8 @@ def test_batched_pass_with_many_count_workgroups(h4d):
 def test_batched_full_size_matches_single_view(h4d):
     """The batched workload at full size: 1M Gaussians (80 % static), 8 cameras
     (four at 1352x1014, four at 2704x2028) x 4 times = 32 views, 109.7 Mpix,
-    in one pass.  Images bit-identical to the views rendered one after another
+    in one pass, the 3D Gaussians binned once per camera.  Images
+    bit-identical to the views rendered one after another
     at the default tile and chunk; gradients equal up to the order of the
     floating-point atomic sums, compared normwise per parameter array (a
     reordered sum of float32 terms differs by a few units of rounding of the
@@ -217,7 +218,8 @@ def test_batched_full_size_matches_single_view(h4d):
         del h, rast
         torch.cuda.empty_cache()
     (p1, im1, a3, a4), (p2, im2, b3, b4) = out
-    assert p1 == p2 and p1 > 0
+    # the batched call bins the 3D Gaussians once per camera (8, not 32 times)
+    assert p1 > 0 and 0 < p2 < p1
     assert float(a3["opacity"].norm()) > 0 and float(a4["opacity"].norm()) > 0
     for v, (a, b) in enumerate(zip(im1, im2)):
         assert torch.equal(a, b), v
@@ -234,15 +236,13 @@ def test_batched_full_size_matches_single_view(h4d):
         check_pixels(scene, v, img.cpu().numpy(), xs, ys)
 
 
-def test_batched_pass_beyond_masked_key_range(h4d):
+def test_batched_call_beyond_one_pass_of_super_tiles(h4d):
     """Five 4096x4096 views at 8-pixel tiles: 16384 super-tiles each, 81920 in
-    the batched pass, more than the 65536 whose ids leave the key's upper half
-    to the tile mask.  That pass keys the coarse entries by super-tile id alone
-    (no tile mask, no culling, splat ids gathered after the sort); its images
-    must equal the views rendered one after another (16384 super-tiles each,
-    masked keys) bit for bit, its gradients normwise up to the order of the
-    atomic sums."""
-    print("[batched unmasked keys] 5 views 4096x4096, tile 8", flush=True)
+    the call, more than the 65536 one pass's keys can number (their upper half
+    carries the tile mask).  The batched call splits into passes of four views
+    and one; its images must equal the views rendered one after another bit for
+    bit, its gradients normwise up to the order of the atomic sums."""
+    print("[batched call in two passes] 5 views 4096x4096, tile 8", flush=True)
     scene = sg.tiny_scene(seed=31)
     views = [sg.look_at((0.3 * k - 0.6, 0.1 * k, -3.0), (0.0, 0.0, 0.0), 4096, 4096, t=0.15 + 0.17 * k)
              for k in range(5)]

@@ -72,7 +72,8 @@ def test_noalloc_rejects_calls_beyond_its_workspace(h4d):
     scene = sg.tiny_scene(n3=10, n4=10, seed=54)
     g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
     v = sg.look_at((0.0, 0.0, -3.0), (0.0, 0.0, 0.0), 64, 48)
-    rast = h4d.Rasterizer(pair_capacity=h4d._lib.NOALLOC_BYTES // 4 + 1)
+    # 8 bytes of state per coarse entry, one entry per 16 pair slots
+    rast = h4d.Rasterizer(pair_capacity=2 * h4d._lib.NOALLOC_BYTES + 4096)
     st, sc = rast.sizes(10, 10, h4d._lib.view_array([v]), 1)
     assert st > h4d._lib.NOALLOC_BYTES
     with pytest.raises(h4d.H4DError) as e:
