@@ -140,9 +140,12 @@ const char *h4dgs_last_error(const h4d_ctx *ctx);
 /* Build identification string (static storage). */
 const char *h4dgs_version(void);
 
-/* Bytes of `state` (kept unchanged from render_fwd to render_bwd) and of
- * `scratch` (free between calls) for n3 + n4 Gaussians, the given host array of
- * n_views views and the configuration.  Pure host arithmetic. */
+/* Bytes of `state` (kept from render_fwd to render_bwd: the caller leaves it
+ * unchanged in between; the backward accumulates into its gradient records)
+ * and of `scratch` (free between calls) for n3 + n4 Gaussians, the given host
+ * array of n_views views and the configuration.  Pure host arithmetic.  An
+ * inference render needs only a leading part of the state (no gradient
+ * records: N x n_views x 64 bytes less). */
 h4d_status h4dgs_workspace_size(h4d_ctx *ctx, int32_t n3, int32_t n4, const h4d_view *views, int32_t n_views,
                                 const h4d_config *cfg, size_t *state_bytes, size_t *scratch_bytes);
 
@@ -203,13 +206,15 @@ h4d_status h4dgs_render_infer_noalloc(h4d_ctx *ctx, const h4d_g3d *g3, const h4d
  * included).  The gradients of every raw parameter (grad3/grad4: device
  * arrays laid out as the parameters) are OVERWRITTEN with
  * sum_v J_v^T dl_dimages_v.  Same g3, g4, views and cfg as the forward; state
- * as the forward left it (unchanged in between); scratch as sized by
- * h4dgs_workspace_size.  Argument errors: H4D_ERR_INVALID_ARG before anything
- * is enqueued.  After a forward whose pairs overflowed, the blending kernels
+ * as the forward left it (unchanged in between by the caller; the backward
+ * accumulates screen-space gradients in it, and a further backward on the
+ * same state clears them first, so it gives the same gradients); scratch as
+ * sized by h4dgs_workspace_size.  Argument errors: H4D_ERR_INVALID_ARG before
+ * anything is enqueued.  After a forward whose pairs overflowed, the blending kernels
  * find empty tile lists and the gradients hold only what no pair needs. */
 h4d_status h4dgs_render_bwd(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
                             int32_t n_views, const h4d_config *cfg, const float *const *dl_dimages,
-                            const void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
+                            void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
                             h4d_g3d_mut *grad3, h4d_g4d_mut *grad4, void *stream);
 
 /* Per-Gaussian statistics of a backward call, for the optimiser's
@@ -234,7 +239,7 @@ typedef struct {
  * and pruning run on each set separately). */
 h4d_status h4dgs_render_bwd_stats(h4d_ctx *ctx, const h4d_g3d *g3, const h4d_g4d *g4, const h4d_view *views,
                                   int32_t n_views, const h4d_config *cfg, const float *const *dl_dimages,
-                                  const void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
+                                  void *state, size_t state_bytes, void *scratch, size_t scratch_bytes,
                                   h4d_g3d_mut *grad3, h4d_g4d_mut *grad4, const h4d_set_stats *stats3,
                                   const h4d_set_stats *stats4, void *stream);
 

@@ -175,15 +175,17 @@ struct Layout {
     int n_groups = 0;
     ViewShare share[kMaxViews];
     // state
+    // (the gradient records st_g2 come last: an inference render needs only
+    // infer_bytes of the state)
     size_t st_status, st_pair_base, st_views, st_recs, st_ckeys, st_cvals, st_cranges, st_thist, st_T, st_nc, st_C,
-        st_tcost, state_bytes;
+        st_tcost, infer_bytes, st_g2, state_bytes;
     // scratch, forward use
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_ceff,
         sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_shape, sc_runs, sc_wcnt, sc_woff, sc_wpart,
         fwd_bytes;
     size_t hist_words = 0, totals_words = 0;  // 32-bit words of the radix histogram / digit totals
     // scratch, backward use
-    size_t sc_g2, sc_border, bwd_bytes;
+    size_t sc_border, bwd_bytes;
     size_t scratch_bytes;
 
     int n_passes() const { return n_pass; }
@@ -242,6 +244,7 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
                 break;
             }
         L.share[v].static_view = lead;
+        L.share[v].static_next = -1;
         L.share[v].group_leader = -1;
     }
     int n_groups = 0, group_supers = 0;
@@ -261,10 +264,13 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
         int gs = sb;
         for (int g = 0; g < n_groups; ++g) {
             const int lead = L.share[g].group_leader;
+            int prev = -1;
             for (int v = 0; v < V; ++v)
                 if (L.share[v].static_view == lead) {
                     L.share[v].static_group = g;
                     L.share[v].static_super_base = gs;
+                    if (prev >= 0) L.share[prev].static_next = v;
+                    prev = v;
                 }
             gs += L.vg[lead].sx * L.vg[lead].sy;
         }
@@ -276,6 +282,7 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
             L.share[v].static_view = v;
             L.share[v].static_group = -1;
             L.share[v].static_super_base = L.vg[v].super_base;
+            L.share[v].static_next = -1;
             L.share[v].group_leader = -1;
         }
         L.total_supers = sb;
@@ -307,6 +314,8 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
     L.st_nc = s.take(4 * (size_t)pb);
     L.st_C = s.take(12 * (size_t)pb);
     L.st_tcost = s.take(4 * (size_t)tb);
+    L.infer_bytes = s.off;
+    L.st_g2 = s.take(4 * (size_t)kG2Stride * n * V_);
     L.state_bytes = s.off;
     Carve f;
     L.sc_dkeys = f.take(4 * np);
@@ -348,7 +357,6 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
     L.sc_wpart = f.take(8 * ((size_t)scan_blocks(tb) + 2));
     L.fwd_bytes = f.off;
     Carve b;
-    L.sc_g2 = b.take(4 * (size_t)kG2Stride * n * V_);
     L.sc_border = b.take(4 * (size_t)tb);
     L.bwd_bytes = b.off;
     L.scratch_bytes = std::max(L.fwd_bytes, L.bwd_bytes);
@@ -724,8 +732,9 @@ static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d*
     const int N = g3->n + g4->n;
     const Layout L = make_layout(N, g3->n, views, n_views, cfg);
     if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
-    if (!state || state_bytes < L.state_bytes)
-        return fail(ctx, H4D_ERR_INVALID_ARG, "state too small (%zu < %zu)", state_bytes, L.state_bytes);
+    const size_t need = keep ? L.state_bytes : L.infer_bytes;
+    if (!state || state_bytes < need)
+        return fail(ctx, H4D_ERR_INVALID_ARG, "state too small (%zu < %zu)", state_bytes, need);
     if (!scratch || scratch_bytes < L.fwd_bytes)
         return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small (%zu < %zu)", scratch_bytes, L.fwd_bytes);
     if (!plan_fits(L)) return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: radix buffers of the layout too small");
@@ -744,7 +753,8 @@ static h4d_status render_forward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d*
         {
             StageScope sc(ctx, st, H4D_STAGE_PREPROCESS);
             launch_preprocess(p3, p4, vp, P.v0, P.v1 - P.v0, L.shared ? 1 : 0, at<Rec>(state, L.st_recs),
-                              at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals), st);
+                              at<uint32_t>(scratch, L.sc_dkeys), at<uint32_t>(scratch, L.sc_dvals),
+                              keep ? at<float>(state, L.st_g2) : nullptr, st);
         }
         if (!bin_pass(ctx, L, P, cfg->tile, cfg->cull, state, scratch, st, keep))
             return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: a radix pass did not fit its buffers");
@@ -778,7 +788,7 @@ h4d_status h4dgs_render_infer_noalloc(h4d_ctx* ctx, const h4d_g3d* g3, const h4d
     if ((s = check_pass_size(ctx, cfg, (int64_t)g3->n + g4->n, n_views)) != H4D_OK) return s;
     const Layout L = make_layout(g3->n + g4->n, g3->n, views, n_views, cfg);
     if ((s = check_layout(ctx, L, cfg)) != H4D_OK) return s;
-    const size_t state_room = align_up(L.state_bytes);
+    const size_t state_room = align_up(L.infer_bytes);
     const size_t limit = (size_t)H4DGS_NOALLOC_BYTES;
     if (state_room > limit || L.fwd_bytes > limit - state_room)
         return fail(ctx, H4D_ERR_CAPACITY,
@@ -801,7 +811,7 @@ h4d_status h4dgs_render_infer_noalloc(h4d_ctx* ctx, const h4d_g3d* g3, const h4d
 
 static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
                                   int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages,
-                                  const void* state, size_t state_bytes, void* scratch, size_t scratch_bytes,
+                                  void* state, size_t state_bytes, void* scratch, size_t scratch_bytes,
                                   h4d_g3d_mut* grad3, h4d_g4d_mut* grad4, const h4d_set_stats* stats3,
                                   const h4d_set_stats* stats4, void* stream) {
     if (!ctx) return H4D_ERR_INVALID_ARG;
@@ -829,15 +839,22 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
     if (!scratch || scratch_bytes < L.bwd_bytes)
         return fail(ctx, H4D_ERR_INVALID_ARG, "scratch too small (%zu < %zu)", scratch_bytes, L.bwd_bytes);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    void* stt = const_cast<void*>(state);
-    float* g2 = at<float>(scratch, L.sc_g2);
+    void* stt = state;
+    float* g2 = at<float>(stt, L.st_g2);
+    Status* status = at<Status>(stt, L.st_status);
     uint32_t* border = at<uint32_t>(scratch, L.sc_border);
+    // the forward zeroed the gradient records its on-screen pairs use; with
+    // shared static binning the statistics need every view's own 3D records,
+    // which it did not zero, and otherwise the 3D gradients of a static group
+    // go to its view's records
+    const bool want_stats = stats3 || stats4;
+    const int static_rows = (L.shared && !want_stats) ? 1 : 0;
     PassTiles pt;
     pt.n = L.n_passes();
     for (int k = 0; k < pt.n; ++k) pt.tile0[k] = L.vg[L.pass(k).v0].tile_base;
     pt.tile0[pt.n] = L.total_tiles;
-    launch_bwd_prologue(g2, (size_t)kG2Stride * N * n_views, at<uint32_t>(stt, L.st_tcost),
-                        at<uint32_t>(stt, L.st_thist), pt, border, st);
+    launch_bwd_prologue(g2, (size_t)kG2Stride * N * n_views, &status->g2_dirty, (L.shared && want_stats) ? 1 : 0,
+                        at<uint32_t>(stt, L.st_tcost), at<uint32_t>(stt, L.st_thist), pt, border, st);
     const ViewParams* vp = at<ViewParams>(stt, L.st_views);
     {
         StageScope sc(ctx, st, H4D_STAGE_BLEND_BWD);
@@ -848,7 +865,7 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
             const Pass P = L.pass(k);
             KernelMark km(ctx, H4D_STAGE_BLEND_BWD, P.tiles > 0);
             launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs), N, coarse_lists(L, stt),
-                                 L.shared, vp, P.v0, P.v1, P.tiles, border + pt.tile0[k], tab,
+                                 L.shared, static_rows, vp, P.v0, P.v1, P.tiles, border + pt.tile0[k], tab,
                                  at<float>(stt, L.st_T),
                                  at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), g2, stat_counters(ctx, stt, L),
                                  st, km.a, km.b);
@@ -863,13 +880,14 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
                                : SetStats{nullptr, nullptr, nullptr};
     {
         StageScope sc(ctx, st, H4D_STAGE_PREPROCESS_BWD);
-        launch_preprocess_bwd(to_ptr(g3), to_ptr(g4), vp, n_views, at<Rec>(stt, L.st_recs), g2, r3, r4, s3, s4, st);
+        launch_preprocess_bwd(to_ptr(g3), to_ptr(g4), vp, n_views, at<Rec>(stt, L.st_recs), g2, r3, r4, s3, s4,
+                              static_rows, status, st);
     }
     return hip_check(ctx, "render_bwd");
 }
 
 h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
-                            int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages, const void* state,
+                            int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages, void* state,
                             size_t state_bytes, void* scratch, size_t scratch_bytes, h4d_g3d_mut* grad3,
                             h4d_g4d_mut* grad4, void* stream) {
     return render_backward(ctx, g3, g4, views, n_views, cfg, dl_dimages, state, state_bytes, scratch, scratch_bytes,
@@ -878,7 +896,7 @@ h4d_status h4dgs_render_bwd(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, 
 
 h4d_status h4dgs_render_bwd_stats(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d* g4, const h4d_view* views,
                                   int32_t n_views, const h4d_config* cfg, const float* const* dl_dimages,
-                                  const void* state, size_t state_bytes, void* scratch, size_t scratch_bytes,
+                                  void* state, size_t state_bytes, void* scratch, size_t scratch_bytes,
                                   h4d_g3d_mut* grad3, h4d_g4d_mut* grad4, const h4d_set_stats* stats3,
                                   const h4d_set_stats* stats4, void* stream) {
     if (!ctx) return H4D_ERR_INVALID_ARG;

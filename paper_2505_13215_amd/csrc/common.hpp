@@ -45,9 +45,11 @@ struct ViewParams {
     int32_t static_view;
     int32_t static_group;
     int32_t static_super_base;
+    int32_t static_next;  // the next view of the same static group (-1: none)
     // entry k of the table: the view whose records hold static group k (-1
     // past the last group)
     int32_t group_leader;
+    int32_t pad;
 };
 
 // Tiles per super-tile edge: binning groups tiles into S x S blocks (S = 4 for
@@ -84,7 +86,10 @@ struct SegLayout {
 // Screen-space gradients of one (view, Gaussian) from the blending adjoint:
 // du dv dQ00 dQ01 dQ11 dop dr dg db (conic entries unscaled, Q01 counted once),
 // padded to one 64-byte record so that a splat's nine atomic additions touch a
-// single cache line.  Layout [view][N][kG2Stride].
+// single cache line.  Layout [view][N][kG2Stride].  The forward zeroes the
+// records of its on-screen (view, Gaussian) pairs; with shared static
+// binning and no statistics wanted, the views of a static group add their 3D
+// gradients into the records of the group's view.
 constexpr int kG2Stride = 16;
 
 // Per-view device pointers passed by value to the batched kernels.
@@ -115,7 +120,10 @@ struct Status {
     // counters of the counting variants (h4dgs_stats): blend evaluations and
     // blends of the forward and the adjoint, tile-list entries, traversed
     // entries (each tile's last contributor) and on-screen records
-    unsigned long long pad[14];
+    unsigned long long pad[13];
+    // nonzero once a backward has accumulated into the screen-space gradient
+    // records (which the forward leaves zeroed): a further backward clears them
+    unsigned long long g2_dirty;
 };
 
 constexpr unsigned long long kFlagOverflow = 1ull;

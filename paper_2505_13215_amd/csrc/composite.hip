@@ -389,10 +389,12 @@ __device__ __forceinline__ void wave_sum9(float e0, float e1, float e2, float e3
 // Per splat of the tile's list (up to its last contributor), the wave's nine
 // gradient sums (wave_sum9) are added into the splat's g2 record with global
 // atomics by four lanes.
+// static_rows (MERGE): the gradients of the static list's entries go to the
+// records of the static group's view.
 template <int B, int CHUNK, bool STATS, bool MERGE>
 __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
-    const Rec* __restrict__ recs, int N, CoarseLists lists, const ViewParams* __restrict__ views, int v0, int v1,
-    const uint32_t* __restrict__ order, CPtrTable dls, const float* __restrict__ Tfin,
+    const Rec* __restrict__ recs, int N, CoarseLists lists, int static_rows, const ViewParams* __restrict__ views,
+    int v0, int v1, const uint32_t* __restrict__ order, CPtrTable dls, const float* __restrict__ Tfin,
     const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout, float* __restrict__ g2,
     unsigned long long* counters) {
     constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
@@ -405,7 +407,10 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const int view = find_view_of_tile(views, v0, v1, gt);
     const ViewParams& V = views[view];
     const int tile = gt - V.tile_base;
-    g2 += (size_t)view * N * kG2Stride;  // indexed by splat id: the view's own gradient records
+    // indexed by splat id: the view's own gradient records, and those its
+    // static list's entries go to
+    float* __restrict__ g2s = g2 + (size_t)(MERGE && static_rows ? V.static_view : view) * N * kG2Stride;
+    g2 += (size_t)view * N * kG2Stride;
     const float* __restrict__ dl = dls.p[view];
     const int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
     TileWalk<MERGE> walk;
@@ -470,7 +475,7 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
         if (cnt == 0) break;  // uniform: the list is exhausted
         for (int k = tid; k < cnt; k += NT) {
             const uint32_t raw = s_ids[k];
-            stage_splat(walk.record(raw), raw & ~kFromStatic, ty * B, ty * B + B - 1, s_sp[k]);
+            stage_splat(walk.record(raw), raw, ty * B, ty * B + B - 1, s_sp[k]);  // (gid keeps the static flag)
         }
         __syncthreads();
         // entries past this wave's last contributor need no work
@@ -537,7 +542,8 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
                 // results here, before the lane-divergent atomics below
                 asm volatile("" ::"v"(h0), "v"(h1), "v"(h2));
                 if (lead) {
-                    float* const rec = g2 + (size_t)gid * kG2Stride;
+                    float* const rec = ((MERGE && (gid & kFromStatic)) ? g2s : g2) +
+                                       (size_t)(gid & ~kFromStatic) * kG2Stride;
                     atomicAdd(rec + off0, h0 * (fac0 * s.op));
                     atomicAdd(rec + off1, h1 * __builtin_fmaf(m1, s.op, c1));
                     if (row == 0) atomicAdd(rec + 8, h2);
@@ -609,16 +615,16 @@ static void fwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, 
 #undef H4D_FWD
 }
 template <int B, int C>
-static void bwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, const ViewParams* views, int v0,
-                  int v1, int n_tiles, const uint32_t* order, const CPtrTable& dls, const float* Tfin,
+static void bwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, int static_rows,
+                  const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order, const CPtrTable& dls, const float* Tfin,
                   const uint32_t* ncontrib, const float* Cout, float* g2, unsigned long long* counters, hipStream_t st,
                   hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
     const bool stats = counters != nullptr;
     launch_timed(merge ? (stats ? k_composite_bwd<B, C, true, true> : k_composite_bwd<B, C, false, true>)
                        : (stats ? k_composite_bwd<B, C, true, false> : k_composite_bwd<B, C, false, false>),
-                 n_tiles, NT, st, e0, e1, recs, N, lists, views, v0, v1, order, dls, Tfin, ncontrib, Cout, g2,
-                 counters);
+                 n_tiles, NT, st, e0, e1, recs, N, lists, static_rows, views, v0, v1, order, dls, Tfin, ncontrib,
+                 Cout, g2, counters);
 }
 
 // Tile lists written out (for inspection): one wave per tile walks the list as
@@ -716,12 +722,13 @@ void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const Coa
 }
 
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
-                          const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
-                          const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
-                          float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                          int static_rows, const ViewParams* views, int v0, int v1, int n_tiles,
+                          const uint32_t* order, const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib,
+                          const float* Cout, float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
     if (n_tiles == 0) return;
-    H4D_DISPATCH(bwd_t, recs, N, lists, merge, views, v0, v1, n_tiles, order, dls, Tfin, ncontrib, Cout, g2,
-                 counters, st, e0, e1);
+    H4D_DISPATCH(bwd_t, recs, N, lists, merge, static_rows, views, v0, v1, n_tiles, order, dls, Tfin, ncontrib,
+                 Cout, g2, counters, st, e0, e1);
 }
 
 }  // namespace h4d

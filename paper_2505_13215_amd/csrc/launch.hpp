@@ -16,7 +16,7 @@ struct ViewIn {
 // Per view: the shared static binning (ViewParams' static_* fields, filled by
 // the host) and, at index k, the leader view of static group k (or -1).
 struct ViewShare {
-    int32_t static_view, static_group, static_super_base, group_leader;
+    int32_t static_view, static_group, static_super_base, static_next, group_leader;
 };
 struct ViewTableIn {
     int32_t n;
@@ -37,11 +37,15 @@ void launch_count_onscreen(const Rec* recs, int N, int n4, const ViewParams* vie
 // ids in the pass's segment layout: unshared (shared = 0), view v0 + r's at
 // r * N; shared, view v0 + r's 4D Gaussians at r * n4 and the 3D Gaussians of
 // static group g (computed for its leader view only) at nv * n4 + g * n3.
+// g2 (may be null): zeroed for every record that covers a pixel.
 void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, int shared,
-                       Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
+                       Rec* recs, uint32_t* dkeys, uint32_t* dvals, float* g2, hipStream_t st);
+// static_rows: the adjoint added each static group's 3D gradients into the
+// records of the group's view (no statistics then).  Marks g2 used
+// (status->g2_dirty).
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
                            const float* g2, const G3Grad& gr3, const G4Grad& gr4, const SetStats& st3,
-                           const SetStats& st4, hipStream_t st);
+                           const SetStats& st4, int static_rows, Status* status, hipStream_t st);
 void launch_splats_to_records(int n, const float* u, const float* v, const float* conic, const float* opacity,
                               const float* rgb, const int32_t* radius, const float* depth, const uint8_t* visible,
                               int W, int H, Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st);
@@ -131,8 +135,8 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
 // null: 0)
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st);
-// Backward prologue: zeroes g2[0, n_g2) and orders the tiles of every pass by
-// decreasing tcost (pass k: global tiles [tile0[k], tile0[k + 1]), its order
+// Backward prologue: zeroes g2[0, n_g2) if *dirty != 0 or force, and orders the
+// tiles of every pass by decreasing tcost (pass k: global tiles [tile0[k], tile0[k + 1]), its order
 // at the same offsets, relative to tile0[k]; thist + k kCostBuckets: the
 // forward's per-bucket tile counts of pass k).  A permutation whatever the
 // counts hold: buckets that overflow fall back to identity order.
@@ -140,8 +144,8 @@ struct PassTiles {
     int32_t n;                     // passes
     int32_t tile0[kMaxViews + 1];
 };
-void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const uint32_t* thist,
-                         const PassTiles& passes, uint32_t* order, hipStream_t st);
+void launch_bwd_prologue(float* g2, size_t n_g2, const unsigned long long* dirty, int force, const uint32_t* tcost,
+                         const uint32_t* thist, const PassTiles& passes, uint32_t* order, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 
@@ -162,11 +166,13 @@ void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const Coa
                           const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
                           uint32_t* thist, unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);
+// static_rows (merge only): the 3D entries' gradients go to the records of
+// their static group's view instead of the tile's own view.
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
-                          const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
-                          const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib, const float* Cout,
-                          float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
-                          hipEvent_t e1 = nullptr);
+                          int static_rows, const ViewParams* views, int v0, int v1, int n_tiles,
+                          const uint32_t* order, const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib,
+                          const float* Cout, float* g2, unsigned long long* counters, hipStream_t st,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // The tile lists of the views [v0, v1) written out: ids (indices into the
 // merged set [4D | 3D]) of tile t (relative to view v0's first tile) at
 // out[offsets[t] ..) (positions from out_cap on are not written),

@@ -265,9 +265,12 @@ struct TimeColour {
 // Gaussians at (view - v0) n4 + g and, for a static group's leader view only,
 // the 3D Gaussians at nv n4 + group n3 + (g - n4) (the other views of the group
 // use the leader's 3D records and compute none).
+// g2 (may be null): the screen-space gradient records, zeroed for the records
+// that cover a pixel.
 __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const ViewParams* __restrict__ views,
                                                     int v0, int shared, Rec* __restrict__ recs,
-                                                    uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
+                                                    uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals,
+                                                    float* __restrict__ g2) {
     const int N = g3.n + g4.n;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
@@ -326,6 +329,14 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
         rec.d = make_uint4((uint32_t)p.x0 | ((uint32_t)p.x1 << 16), (uint32_t)p.y0 | ((uint32_t)p.y1 << 16),
                            (uint32_t)p.r, 1u);
         key = __float_as_uint(depth);
+        if (g2) {
+            float4* row = reinterpret_cast<float4*>(g2 + ((size_t)view * N + g) * kG2Stride);
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            row[0] = z;
+            row[1] = z;
+            row[2] = z;
+            row[3] = z;
+        }
     } else {
         rec.a = make_float4(0.f, 0.f, 0.f, 0.f);
         rec.b = rec.a;
@@ -590,7 +601,7 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
 
 __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams* __restrict__ views, int n_views,
                               int N, const Rec* __restrict__ recs, const float* __restrict__ g2, const G3Grad& gr,
-                              const SetStats& st) {
+                              const SetStats& st, int static_rows) {
     const size_t n = (size_t)g3.n;
     WorldF w;
     Cov3 z;
@@ -601,18 +612,37 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
     for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
     double stat_g = 0.0;
     int stat_n = 0;
+    // the views of a static group share one camera and one record: their
+    // screen-space gradients are summed (by the adjoint itself when
+    // static_rows) and taken through the projection once
     for (int v = 0; v < n_views; ++v) {
         const ViewParams& V = views[v];
-        if (recs[(size_t)V.static_view * N + gidx].d.w == 0u) continue;  // covers no pixel in this view
-        if (st.grad || st.vis || st.step_vis) {
-            const float* e = g2 + ((size_t)v * N + gidx) * kG2Stride;
-            stat_g += ndc_grad_norm(e[0], e[1], V.W, V.H);
-            ++stat_n;
+        if (V.static_view != v) continue;                  // summed into its group's leader below
+        if (recs[(size_t)v * N + gidx].d.w == 0u) continue;  // covers no pixel in this camera
+        // (a view alone, or the group's sum already in its record: that record
+        // as it is; otherwise the members' records summed here)
+        float e[9];
+        for (int k = 0; k < 9; ++k) e[k] = 0.f;
+        const float* direct = nullptr;
+        if (static_rows || V.static_next < 0) {
+            direct = g2 + ((size_t)v * N + gidx) * kG2Stride;
+            if (st.grad || st.vis || st.step_vis) {
+                stat_g += ndc_grad_norm(direct[0], direct[1], V.W, V.H);
+                ++stat_n;
+            }
+        }
+        for (int u = direct ? -1 : v; u >= 0; u = views[u].static_next) {
+            const float* g = g2 + ((size_t)u * N + gidx) * kG2Stride;
+            if (st.grad || st.vis || st.step_vis) {
+                stat_g += ndc_grad_norm(g[0], g[1], views[u].W, views[u].H);
+                ++stat_n;
+            }
+            for (int k = 0; k < 9; ++k) e[k] += g[k];
         }
         ProjF p;
         project(V, w, p);
         double gmc[3], Sb[3][3], gop;
-        proj_bwd<false>(V, w, p, g3.sh, g3.n, i, g2 + ((size_t)v * N + gidx) * kG2Stride, 1, gmc, Sb, gop, gsh);
+        proj_bwd<false>(V, w, p, g3.sh, g3.n, i, direct ? direct : e, 1, gmc, Sb, gop, gsh);
         gsig += gop;
         for (int r = 0; r < 3; ++r) {
             gmu[r] += gmc[r];
@@ -656,14 +686,16 @@ template <bool TIME>
 __global__ void __launch_bounds__(128) k_preprocess_bwd(G3Ptr g3, G4Ptr g4, int nb4, const ViewParams* __restrict__ views,
                                                         int n_views, const Rec* __restrict__ recs,
                                                         const float* __restrict__ g2, G3Grad gr3, G4Grad gr4,
-                                                        SetStats st3, SetStats st4) {
+                                                        SetStats st3, SetStats st4, int static_rows,
+                                                        Status* status) {
     const int N = g3.n + g4.n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) status->g2_dirty = 1ull;  // (read by the next backward's prologue)
     if ((int)blockIdx.x < nb4) {
         const int g = blockIdx.x * blockDim.x + threadIdx.x;
         if (g < g4.n) bwd_4d<TIME>(g4, g, views, n_views, N, recs, g2, gr4, st4);
     } else {
         const int i = (blockIdx.x - nb4) * blockDim.x + threadIdx.x;
-        if (i < g3.n) bwd_3d(g3, i, g4.n + i, views, n_views, N, recs, g2, gr3, st3);
+        if (i < g3.n) bwd_3d(g3, i, g4.n + i, views, n_views, N, recs, g2, gr3, st3, static_rows);
     }
 }
 
@@ -695,7 +727,9 @@ __device__ void write_views(const ViewTableIn& in, ViewParams* out) {
         p.static_view = in.share[v].static_view;
         p.static_group = in.share[v].static_group;
         p.static_super_base = in.share[v].static_super_base;
+        p.static_next = in.share[v].static_next;
         p.group_leader = in.share[v].group_leader;
+        p.pad = 0;
         super_base += p.sx * p.sy;
         tile_base += p.tiles_x * p.tiles_y;
         pix_base += (long long)s.W * s.H;
@@ -728,22 +762,24 @@ void launch_init_state(const ViewTableIn& in, ViewParams* views, Status* status,
 }
 
 void launch_preprocess(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int v0, int nv, int shared,
-                       Rec* recs, uint32_t* dkeys, uint32_t* dvals, hipStream_t st) {
+                       Rec* recs, uint32_t* dkeys, uint32_t* dvals, float* g2, hipStream_t st) {
     const int N = g3.n + g4.n;
     if (N == 0 || nv == 0) return;
-    k_preprocess<<<dim3(ceil_div(N, 256), nv), 256, 0, st>>>(g3, g4, views, v0, shared, recs, dkeys, dvals);
+    k_preprocess<<<dim3(ceil_div(N, 256), nv), 256, 0, st>>>(g3, g4, views, v0, shared, recs, dkeys, dvals, g2);
 }
 
 void launch_preprocess_bwd(const G3Ptr& g3, const G4Ptr& g4, const ViewParams* views, int n_views, const Rec* recs,
                            const float* g2, const G3Grad& gr3, const G4Grad& gr4, const SetStats& st3,
-                           const SetStats& st4, hipStream_t st) {
+                           const SetStats& st4, int static_rows, Status* status, hipStream_t st) {
     const int N = g3.n + g4.n;
-    if (N == 0) return;
     const int nb4 = ceil_div(g4.n, 128), nb3 = ceil_div(g3.n, 128);
-    if (g4.sh_t_deg > 0)
-        k_preprocess_bwd<true><<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4);
+    const int nb = std::max(1, nb4 + nb3);  // (one workgroup at least: it marks the records used)
+    if (g4.sh_t_deg > 0 && N > 0)
+        k_preprocess_bwd<true><<<nb, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4,
+                                                   static_rows, status);
     else
-        k_preprocess_bwd<false><<<nb4 + nb3, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4);
+        k_preprocess_bwd<false><<<nb, 128, 0, st>>>(g3, g4, nb4, views, n_views, recs, g2, gr3, gr4, st3, st4,
+                                                    static_rows, status);
 }
 
 }  // namespace h4d

@@ -755,9 +755,11 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 }
 // Backward: workgroup k < passes.n orders pass k from the forward's per-bucket
 // tile counts (an exclusive scan, then one scatter pass over the tiles; ties
-// in any order), the other workgroups zero g2.  Counts that do not add up to
+// in any order), the other workgroups zero g2 when a backward has used it
+// since the forward (*dirty) or when force is set.  Counts that do not add up to
 // the pass's tiles give the identity order.
 __global__ void __launch_bounds__(1024) k_bwd_prologue(float* __restrict__ g2, size_t n_g2,
+                                                       const unsigned long long* __restrict__ dirty, int force,
                                                        const uint32_t* __restrict__ tcost,
                                                        const uint32_t* __restrict__ thist, PassTiles passes,
                                                        uint32_t* __restrict__ order) {
@@ -804,6 +806,7 @@ __global__ void __launch_bounds__(1024) k_bwd_prologue(float* __restrict__ g2, s
             for (int t = tid; t < n; t += nt) order[t] = (uint32_t)t;
         return;
     }
+    if (!force && *dirty == 0ull) return;  // the records are as the forward left them (uniform)
     const size_t nb = (size_t)(gridDim.x - passes.n);
     const size_t i0 = (size_t)(k - passes.n) * blockDim.x + threadIdx.x, step = nb * blockDim.x;
     if ((reinterpret_cast<uintptr_t>(g2) & 15u) == 0 && (n_g2 & 3) == 0) {  // 16-byte stores
@@ -852,11 +855,11 @@ void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long 
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {
     k_ranges<<<2048, 256, 0, st>>>(keys, key_mask, eff_count, base, ranges);
 }
-void launch_bwd_prologue(float* g2, size_t n_g2, const uint32_t* tcost, const uint32_t* thist,
-                         const PassTiles& passes, uint32_t* order, hipStream_t st) {
+void launch_bwd_prologue(float* g2, size_t n_g2, const unsigned long long* dirty, int force, const uint32_t* tcost,
+                         const uint32_t* thist, const PassTiles& passes, uint32_t* order, hipStream_t st) {
     // one 16-byte store per thread (no grid-stride loop)
     const int fill = (int)std::max<size_t>(1, std::min<size_t>(1u << 20, (n_g2 + 4095) / 4096));
-    k_bwd_prologue<<<passes.n + fill, 1024, 0, st>>>(g2, n_g2, tcost, thist, passes, order);
+    k_bwd_prologue<<<passes.n + fill, 1024, 0, st>>>(g2, n_g2, dirty, force, tcost, thist, passes, order);
 }
 
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st) {

@@ -13,10 +13,11 @@
 // Shared static binning (MERGE): the 3D Gaussians of views that repeat a
 // camera are binned once per camera, so a tile's list is the depth-order merge
 // of two lists - the static group's 3D entries and the view's own 4D entries.
-// Each side is compacted into a queue of up to 64 entries (with their depth
-// bits); the next up to 64 entries of the merge are then picked by a merge-path
-// search per lane.  Equal depth bits put the 4D entry first, which is the
-// order of the merged index [4D | 3D] that a single sort over both sets gives.
+// Each side is compacted into a queue of up to 64 entries (with their records'
+// depth keys); the next up to 64
+// entries of the merge come from a bitonic merge of the two queues across the
+// wave.  Equal depth bits put the 4D entry first, which is the order of the
+// merged index [4D | 3D] that a single sort over both sets gives.
 //
 // One wave walks; the state lives in its registers (positions, queue counts)
 // and in its own LDS queues.
@@ -45,9 +46,10 @@ __device__ __forceinline__ unsigned long long walk_lanemask_lt() {
 }
 
 // Appends to q[n ..) the ids of the entries of r whose key holds bit `bit`, in
-// order (and, with DEPTH, their records' depth bits to qd), until n == need or
-// r is exhausted; r.pos ends just past the last entry taken (or at r.end).
-// Four windows of 64 entries are loaded at once.
+// order (and, with DEPTH, their records' depth keys to qd), until n == need or r is
+// exhausted; r.pos ends just past the last entry taken (or at r.end).
+// Windows of 64 entries are loaded up to four at a time, as many as the
+// entries still wanted suggest (about one entry in four is kept).
 template <bool DEPTH>
 __device__ inline int walk_fill(const CoarseLists& L, uint32_t bit, WalkRun& r, uint32_t* q, uint32_t* qd, int n,
                                 int need, const Rec* __restrict__ recs) {
@@ -55,34 +57,33 @@ __device__ inline int walk_fill(const CoarseLists& L, uint32_t bit, WalkRun& r, 
     const unsigned long long lt = walk_lanemask_lt();
     while (n < need && r.pos < r.end) {
         const int64_t p0 = r.pos;
+        const int nw = min(4, (need - n + 15) >> 4);
         uint32_t kk[4], vv[4], dd[4];
-        bool keep[4];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const int64_t k = p0 + w * 64 + lane;
-            const bool in = k < r.end;
-            kk[w] = in ? L.keys[k] : 0u;
+            const bool in = w < nw && k < r.end;
+            kk[w] = in ? L.keys[k] : 0u;  // (a key of 0 has no tile bit)
             vv[w] = in ? L.vals[k] : 0u;
         }
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            keep[w] = ((kk[w] >> bit) & 1u) != 0u;  // keys past r.end are 0
-            if (DEPTH) dd[w] = keep[w] ? __float_as_uint(recs[vv[w]].c.w) : 0u;
-        }
+        for (int w = 0; w < 4; ++w)
+            if (DEPTH) dd[w] = ((kk[w] >> bit) & 1u) != 0u ? __float_as_uint(recs[vv[w]].c.w) : 0u;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            if (n >= need || r.pos >= r.end) break;  // wave-uniform
-            const unsigned long long m = __ballot(keep[w]);
+            if (w >= nw || n >= need || r.pos >= r.end) break;  // wave-uniform
+            const bool keep = ((kk[w] >> bit) & 1u) != 0u;
+            const unsigned long long m = __ballot(keep);
             const int cnt = __popcll(m);
             const int take = min(cnt, need - n);
             const int rank = __popcll(m & lt);
-            if (keep[w] && rank < take) {
+            if (keep && rank < take) {
                 q[n + rank] = vv[w];
                 if (DEPTH) qd[n + rank] = dd[w];
             }
             if (take < cnt) {
                 // stop just past the lane that holds the last entry taken
-                const unsigned long long last = __ballot(keep[w] && rank == take - 1);
+                const unsigned long long last = __ballot(keep && rank == take - 1);
                 r.pos = p0 + w * 64 + __builtin_ctzll(last) + 1;
             } else {
                 r.pos = min(p0 + (int64_t)(w + 1) * 64, r.end);
@@ -91,6 +92,12 @@ __device__ inline int walk_fill(const CoarseLists& L, uint32_t bit, WalkRun& r, 
         }
     }
     return n;
+}
+
+// 64-bit lane exchange with lane ^ s.
+__device__ __forceinline__ unsigned long long walk_xor(unsigned long long v, int s) {
+    const int lo = __shfl_xor((int)(uint32_t)v, s), hi = __shfl_xor((int)(uint32_t)(v >> 32), s);
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
 // Number of entries of r whose key holds `bit` (the rest of a list, for the
@@ -152,19 +159,26 @@ struct TileWalk {
         na = walk_fill<true>(L, bit, a, s.a, s.ad, na, 64, recs_a);
         nb = walk_fill<true>(L, bit, b, s.b, s.bd, nb, 64, recs_b);
         const int k = min(need, na + nb);
-        // merge path: x = entries of a among the first `lane` outputs
-        const int i = lane;
-        int lo = max(0, i - nb), hi = min(i, na);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s.ad[mid] < s.bd[i - 1 - mid]) lo = mid + 1;
-            else hi = mid;
+        // The 64 smallest of the two queues (each its list's next entries, in
+        // order) by a bitonic merge across the wave: keys (depth bits, static
+        // flag, id) are distinct and order entries as the merged index does
+        // (equal depth bits: 4D first).  Queue a ascending against queue b
+        // descending, lane-wise minimum (the lower half, a bitonic sequence),
+        // then six half-cleaner stages sort it.
+        const unsigned long long inf = ~0ull;
+        const int j = 63 - lane;
+        const unsigned long long ka =
+            lane < na ? ((unsigned long long)s.ad[lane] << 32) | kFromStatic | s.a[lane] : inf;
+        const unsigned long long kb = j < nb ? ((unsigned long long)s.bd[j] << 32) | s.b[j] : inf;
+        unsigned long long m = ka < kb ? ka : kb;
+#pragma unroll
+        for (int st = 32; st > 0; st >>= 1) {
+            const unsigned long long o = walk_xor(m, st);
+            m = (lane & st) ? (m > o ? m : o) : (m < o ? m : o);
         }
-        const int x = min(lo, 63), y = min(max(i - lo, 0), 63);
-        const bool from_a = lo < na && (i - lo >= nb || s.ad[x] < s.bd[y]);
-        const bool act = i < k;
-        id = act ? (from_a ? (s.a[x] | kFromStatic) : s.b[y]) : 0u;
-        const int xa = __popcll(__ballot(act && from_a)), xb = k - xa;
+        const bool act = lane < k;
+        id = act ? (uint32_t)m : 0u;
+        const int xa = __popcll(__ballot(act && ((uint32_t)m & kFromStatic))), xb = k - xa;
         // drop the consumed heads (every lane reads before any lane writes)
         const uint32_t ta = lane + xa < 64 ? s.a[min(lane + xa, 63)] : 0u;
         const uint32_t tad = lane + xa < 64 ? s.ad[min(lane + xa, 63)] : 0u;

@@ -106,8 +106,9 @@ def test_shared_static_binning_workspace(L):
     """Four views of one camera in a batched call bin the 3D Gaussians once,
     on a super-tile grid of their own: the state grows by that grid's list
     ranges (16 bytes per super-tile: 128 x 96 pixels at 16-pixel tiles is 2 x 2
-    super-tiles of 64 pixels, rounded up to the workspace's 256-byte alignment),
-    the scratch does not grow (its depth sorts are over fewer keys)."""
+    super-tiles of 64 pixels, rounded up to the workspace's 256-byte
+    alignment); the scratch does not grow (its depth sorts are over fewer
+    keys)."""
     c = _ctx(L)
     st, sc = C.c_size_t(), C.c_size_t()
     assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, _distinct_views(L, 4), 4, C.byref(_cfg(L, batched=1)),

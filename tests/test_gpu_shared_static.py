@@ -175,3 +175,33 @@ def test_shared_static_captured_replays(h4d):
             scale = float(b.abs().max()) + 1e-30
             assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * scale), rep
         _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_repeated_backward_gives_the_same_gradients(h4d, batched):
+    """The forward zeroes the gradient records its pairs use and the backward
+    accumulates into them: a second backward on the same forward (with and
+    without statistics) clears them first and gives the same gradients, and
+    the shared static binning's summed 3D records (no statistics) stay within
+    the oracle's bar."""
+    print(f"[repeated backward] batched={batched}", flush=True)
+    scene = sg.tiny_scene(n3=1500, n4=1000, seed=77)
+    views = _views()
+    dls = []
+    for k, v in enumerate(views):
+        amb = oracle.render(scene, v)["amb"]
+        dls.append(mask_flagged(sg.upstream_grads([v], seed=90 + k)[0], amb))
+    td = [torch.as_tensor(d, device="cuda") for d in dls]
+    g3, g4 = h4d.to_device(scene.g3), h4d.to_device(scene.g4)
+    rast = h4d.Rasterizer(batched=batched)
+    h = rast.forward(g3, g4, views)
+    runs = [rast.backward(h, g3, g4, td), rast.backward(h, g3, g4, td, stats=h4d.new_stats(scene.n3, scene.n4)),
+            rast.backward(h, g3, g4, td)]
+    torch.cuda.synchronize()
+    a3, a4 = runs[0]
+    for b3, b4 in runs[1:]:
+        for a, b in [(a3[k], b3[k]) for k in a3] + [(a4[k], b4[k]) for k in a4]:
+            scale = float(a.abs().max()) + 1e-30
+            assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * scale)
+    r3, r4 = oracle.render_bwd(scene, views, dls)
+    check_grads(scene, a3, a4, r3, r4, np.zeros(scene.n3 + scene.n4, bool))
