@@ -178,7 +178,7 @@ struct Layout {
     // (the gradient records st_g2 come last: an inference render needs only
     // infer_bytes of the state)
     size_t st_status, st_pair_base, st_views, st_recs, st_ckeys, st_cvals, st_cranges, st_thist, st_T, st_nc, st_C,
-        st_tcost, infer_bytes, st_g2, state_bytes;
+        st_tcost, infer_bytes, st_g2, st_tids, state_bytes;
     // scratch, forward use
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_ceff,
         sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_shape, sc_runs, sc_wcnt, sc_woff, sc_wpart,
@@ -316,6 +316,7 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
     L.st_tcost = s.take(4 * (size_t)tb);
     L.infer_bytes = s.off;
     L.st_g2 = s.take(4 * (size_t)kG2Stride * n * V_);
+    L.st_tids = s.take(4 * (size_t)kTileIds * (size_t)tb);
     L.state_bytes = s.off;
     Carve f;
     L.sc_dkeys = f.take(4 * np);
@@ -653,7 +654,8 @@ void blend_pass(h4d_ctx* c, const Layout& L, int k, int tile, int chunk, void* s
                          keep ? at<float>(state, L.st_T) : nullptr, keep ? at<uint32_t>(state, L.st_nc) : nullptr,
                          keep ? at<float>(state, L.st_C) : nullptr, keep ? at<uint32_t>(state, L.st_tcost) : nullptr,
                          keep ? at<uint32_t>(state, L.st_thist) + (size_t)kCostBuckets * k : nullptr,
-                         keep ? stat_counters(c, state, L) : nullptr, st, km.a, km.b);
+                         keep ? at<uint32_t>(state, L.st_tids) : nullptr, keep ? stat_counters(c, state, L) : nullptr,
+                         st, km.a, km.b);
 }
 
 constexpr int kNoallocDevices = 64;
@@ -867,7 +869,8 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
             launch_composite_bwd(cfg->tile, cfg->chunk, at<Rec>(stt, L.st_recs), N, coarse_lists(L, stt),
                                  L.shared, static_rows, vp, P.v0, P.v1, P.tiles, border + pt.tile0[k], tab,
                                  at<float>(stt, L.st_T),
-                                 at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), g2, stat_counters(ctx, stt, L),
+                                 at<uint32_t>(stt, L.st_nc), at<float>(stt, L.st_C), at<uint32_t>(stt, L.st_tids), g2,
+                                 stat_counters(ctx, stt, L),
                                  st, km.a, km.b);
         }
     }

@@ -75,6 +75,11 @@ struct CoarseLists {
     const int64_t* ranges;  // [start, end) per global super-tile id
 };
 
+// Entries of each tile's list that the forward keeps (in walk order, with the
+// static flag) for the adjoint, which re-walks only tiles whose last
+// contributor lies beyond them.
+constexpr int kTileIds = 256;
+
 // Layout of a pass's depth-ordered entries: na segments of la entries (the
 // views v0 .. v0 + na - 1, all their Gaussians, or only the 4D ones when the
 // static binning is shared), then segments of lb entries, one per static group

@@ -192,7 +192,7 @@ template <int B, int CHUNK, bool STATS, bool SPLIT, bool MERGE>
 __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
     const Rec* __restrict__ recs, int N, CoarseLists lists, const ViewParams* __restrict__ views, int v0, int v1,
     const uint32_t* __restrict__ order, PtrTable images, float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib,
-    float* __restrict__ Cout, uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist,
+    float* __restrict__ Cout, uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist, uint32_t* __restrict__ tids,
     unsigned long long* counters) {
     constexpr int NT = ShapeF<B, SPLIT>::NT, PPL = ShapeF<B, SPLIT>::PPL;
     __shared__ LSplat s_sp[CHUNK];
@@ -243,6 +243,8 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
         for (int k = tid; k < cnt; k += NT) {
             const uint32_t raw = s_ids[k];
             stage_splat(walk.record(raw), raw & ~kFromStatic, ty * B, ty * B + B - 1, s_sp[k]);
+            // the list's head, kept for the adjoint
+            if (tids && rel0 + (uint32_t)k < (uint32_t)kTileIds) tids[(size_t)gt * kTileIds + rel0 + k] = raw;
         }
         __syncthreads();
         if (!wave_done) {
@@ -395,8 +397,8 @@ template <int B, int CHUNK, bool STATS, bool MERGE>
 __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const Rec* __restrict__ recs, int N, CoarseLists lists, int static_rows, const ViewParams* __restrict__ views,
     int v0, int v1, const uint32_t* __restrict__ order, CPtrTable dls, const float* __restrict__ Tfin,
-    const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout, float* __restrict__ g2,
-    unsigned long long* counters) {
+    const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout, const uint32_t* __restrict__ tids,
+    float* __restrict__ g2, unsigned long long* counters) {
     constexpr int NT = Shape<B>::NT, PPL = Shape<B>::PPL;
     __shared__ LSplat s_sp[CHUNK];
     __shared__ uint32_t s_ids[CHUNK];
@@ -467,14 +469,25 @@ __global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
     const float m1 = comp0 == 0 ? -0.5f : 0.0f, c1 = comp0 == 0 ? 0.0f : 1.0f;
     const int off0 = comp0, off1 = 4 + comp0;
     const int tid = (int)threadIdx.x;
+    // the forward kept the list's head: a tile whose contributors all lie in
+    // it reads them from there, any other walks its list again
+    const bool kept = total <= (uint32_t)kTileIds;
+    const uint32_t* __restrict__ head = tids + (size_t)gt * kTileIds;
     for (uint32_t rel0 = 0; rel0 < total;) {
         __syncthreads();  // the previous chunk's LDS is no longer read
-        if (tid < 64) walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids, &s_cnt, (int)min((uint32_t)CHUNK, total - rel0));
-        __syncthreads();
-        const int cnt = s_cnt;
-        if (cnt == 0) break;  // uniform: the list is exhausted
+        int cnt;
+        if (kept) {
+            cnt = (int)min((uint32_t)CHUNK, total - rel0);
+        } else {
+            if (tid < 64) walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids, &s_cnt, (int)min((uint32_t)CHUNK, total - rel0));
+            __syncthreads();
+            cnt = s_cnt;
+            if (cnt == 0) break;  // uniform: the list is exhausted
+        }
         for (int k = tid; k < cnt; k += NT) {
-            const uint32_t raw = s_ids[k];
+            uint32_t raw = kept ? head[rel0 + k] : s_ids[k];
+            // (a head written by another forward reads no record past the set)
+            if ((MERGE ? (raw & ~kFromStatic) : raw) >= (uint32_t)N) raw = 0u;
             stage_splat(walk.record(raw), raw, ty * B, ty * B + B - 1, s_sp[k]);  // (gid keeps the static flag)
         }
         __syncthreads();
@@ -596,15 +609,15 @@ static void launch_timed(void (*k)(P...), int grid, int block, hipStream_t st, h
 template <int B, int C>
 static void fwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, const ViewParams* views, int v0,
                   int v1, int n_tiles, const uint32_t* order, const PtrTable& images, float* Tfin,
-                  uint32_t* ncontrib, float* Cout, uint32_t* tcost, uint32_t* thist, unsigned long long* counters,
-                  hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                  uint32_t* ncontrib, float* Cout, uint32_t* tcost, uint32_t* thist, uint32_t* tids,
+                  unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const bool stats = counters != nullptr;
 #define H4D_FWD(SPLIT)                                                                                            \
     launch_timed(merge ? (stats ? k_composite_fwd<B, C, true, SPLIT, true> : k_composite_fwd<B, C, false, SPLIT, true>) \
                        : (stats ? k_composite_fwd<B, C, true, SPLIT, false>                                         \
                                 : k_composite_fwd<B, C, false, SPLIT, false>),                                      \
                  n_tiles, ShapeF<B, SPLIT>::NT, st, e0, e1, recs, N, lists, views, v0, v1, order, images, Tfin,    \
-                 ncontrib, Cout, tcost, thist, counters)
+                 ncontrib, Cout, tcost, thist, tids, counters)
     if constexpr (B == 16) {
         if (n_tiles <= kSplitTiles) {
             H4D_FWD(true);
@@ -616,15 +629,15 @@ static void fwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, 
 }
 template <int B, int C>
 static void bwd_t(const Rec* recs, int N, const CoarseLists& lists, bool merge, int static_rows,
-                  const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order, const CPtrTable& dls, const float* Tfin,
-                  const uint32_t* ncontrib, const float* Cout, float* g2, unsigned long long* counters, hipStream_t st,
-                  hipEvent_t e0, hipEvent_t e1) {
+                  const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order, const CPtrTable& dls,
+                  const float* Tfin, const uint32_t* ncontrib, const float* Cout, const uint32_t* tids, float* g2,
+                  unsigned long long* counters, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     constexpr int NT = Shape<B>::NT;
     const bool stats = counters != nullptr;
     launch_timed(merge ? (stats ? k_composite_bwd<B, C, true, true> : k_composite_bwd<B, C, false, true>)
                        : (stats ? k_composite_bwd<B, C, true, false> : k_composite_bwd<B, C, false, false>),
                  n_tiles, NT, st, e0, e1, recs, N, lists, static_rows, views, v0, v1, order, dls, Tfin, ncontrib,
-                 Cout, g2, counters);
+                 Cout, tids, g2, counters);
 }
 
 // Tile lists written out (for inspection): one wave per tile walks the list as
@@ -714,21 +727,21 @@ void launch_walk_lists(int tile, const Rec* recs, int N, const CoarseLists& list
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
-                          uint32_t* thist, unsigned long long* counters, hipStream_t st, hipEvent_t e0,
-                          hipEvent_t e1) {
+                          uint32_t* thist, uint32_t* tids, unsigned long long* counters, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1) {
     if (n_tiles == 0) return;
     H4D_DISPATCH(fwd_t, recs, N, lists, merge, views, v0, v1, n_tiles, order, images, Tfin, ncontrib, Cout, tcost,
-                 thist, counters, st, e0, e1);
+                 thist, tids, counters, st, e0, e1);
 }
 
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           int static_rows, const ViewParams* views, int v0, int v1, int n_tiles,
                           const uint32_t* order, const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib,
-                          const float* Cout, float* g2, unsigned long long* counters, hipStream_t st, hipEvent_t e0,
-                          hipEvent_t e1) {
+                          const float* Cout, const uint32_t* tids, float* g2, unsigned long long* counters,
+                          hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (n_tiles == 0) return;
     H4D_DISPATCH(bwd_t, recs, N, lists, merge, static_rows, views, v0, v1, n_tiles, order, dls, Tfin, ncontrib,
-                 Cout, g2, counters, st, e0, e1);
+                 Cout, tids, g2, counters, st, e0, e1);
 }
 
 }  // namespace h4d

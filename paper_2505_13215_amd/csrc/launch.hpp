@@ -159,20 +159,22 @@ bool composite_supported(int tile, int chunk);
 // b = workgroup b): the n_tiles tiles (relative to the launch's first) in
 // dispatch order, a permutation.  The forward writes, per tile, its last
 // contributor into tcost[global tile] and counts the launch's tiles per
-// cost_bucket into thist[kCostBuckets] (zero on entry).  Non-null e0 / e1
-// receive the kernel's own start / end time.
+// cost_bucket into thist[kCostBuckets] (zero on entry) and keeps the first
+// kTileIds entries of each tile's list in tids[global tile][kTileIds] (may be
+// null), which the adjoint reads for tiles whose contributors all lie there.
+// Non-null e0 / e1 receive the kernel's own start / end time.
 void launch_composite_fwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           const ViewParams* views, int v0, int v1, int n_tiles, const uint32_t* order,
                           const PtrTable& images, float* Tfin, uint32_t* ncontrib, float* Cout, uint32_t* tcost,
-                          uint32_t* thist, unsigned long long* counters, hipStream_t st, hipEvent_t e0 = nullptr,
-                          hipEvent_t e1 = nullptr);
+                          uint32_t* thist, uint32_t* tids, unsigned long long* counters, hipStream_t st,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // static_rows (merge only): the 3D entries' gradients go to the records of
 // their static group's view instead of the tile's own view.
 void launch_composite_bwd(int tile, int chunk, const Rec* recs, int N, const CoarseLists& lists, bool merge,
                           int static_rows, const ViewParams* views, int v0, int v1, int n_tiles,
                           const uint32_t* order, const CPtrTable& dls, const float* Tfin, const uint32_t* ncontrib,
-                          const float* Cout, float* g2, unsigned long long* counters, hipStream_t st,
-                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                          const float* Cout, const uint32_t* tids, float* g2, unsigned long long* counters,
+                          hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // The tile lists of the views [v0, v1) written out: ids (indices into the
 // merged set [4D | 3D]) of tile t (relative to view v0's first tile) at
 // out[offsets[t] ..) (positions from out_cap on are not written),
