@@ -167,8 +167,15 @@ __device__ __forceinline__ int dispatch_tile(const uint32_t* __restrict__ order)
 // splat) evaluations and blends into counters[0..1].  tcost[tile] receives
 // the tile's last contributor (the adjoint's work on it), thist[cost_bucket]
 // counts the launch's tiles per bucket.
-// (at most 64 registers: 8 waves per SIMD, about 1 % faster than the 7 the
-// compiler would otherwise settle for)
+// Waves per SIMD the forward asks registers for: with one or two pixels per
+// lane, 8 (at most 64 registers, about 1 % faster than the 7 the compiler
+// would otherwise settle for); with four, the blending state of four pixels
+// stays live across the list walk, and 6 (5 with the merging walk) avoids
+// spilling it (32 views: 6.5 -> 5.9 ms).
+template <int B, bool SPLIT, bool MERGE>
+struct FwdWaves {
+    static constexpr int value = ShapeF<B, SPLIT>::PPL == 4 ? (MERGE ? 5 : 6) : 8;
+};
 // Pulls the next chunk of the tile's list (up to `need` entries) into s_ids and
 // its length into *s_cnt; called by the first wave only.
 template <bool MERGE, int CHUNK>
@@ -189,7 +196,7 @@ __device__ __forceinline__ void walk_chunk(TileWalk<MERGE>& walk, WalkQueues& q,
 // MERGE: the tile's list merges the static group's 3D list with the view's 4D
 // list (shared static binning); otherwise it is one list.
 template <int B, int CHUNK, bool STATS, bool SPLIT, bool MERGE>
-__global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), 8) k_composite_fwd(
+__global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, MERGE>::value)) k_composite_fwd(
     const Rec* __restrict__ recs, int N, CoarseLists lists, const ViewParams* __restrict__ views, int v0, int v1,
     const uint32_t* __restrict__ order, PtrTable images, float* __restrict__ Tfin, uint32_t* __restrict__ ncontrib,
     float* __restrict__ Cout, uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist, uint32_t* __restrict__ tids,
@@ -393,8 +400,10 @@ __device__ __forceinline__ void wave_sum9(float e0, float e1, float e2, float e3
 // atomics by four lanes.
 // static_rows (MERGE): the gradients of the static list's entries go to the
 // records of the static group's view.
+// (registers for 5 waves per SIMD, what the plain adjoint uses anyway: the
+// merging walk would otherwise take the occupancy down to 4)
 template <int B, int CHUNK, bool STATS, bool MERGE>
-__global__ void __launch_bounds__(Shape<B>::NT) k_composite_bwd(
+__global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     const Rec* __restrict__ recs, int N, CoarseLists lists, int static_rows, const ViewParams* __restrict__ views,
     int v0, int v1, const uint32_t* __restrict__ order, CPtrTable dls, const float* __restrict__ Tfin,
     const uint32_t* __restrict__ ncontrib, const float* __restrict__ Cout, const uint32_t* __restrict__ tids,
