@@ -185,7 +185,7 @@ struct Layout {
         fwd_bytes;
     size_t hist_words = 0, totals_words = 0;  // 32-bit words of the radix histogram / digit totals
     // scratch, backward use
-    size_t sc_border, bwd_bytes;
+    size_t sc_border, sc_okeys, sc_ovals, sc_okeys2, sc_ovals2, sc_ohist, sc_ototals, ohist_words, bwd_bytes;
     size_t scratch_bytes;
 
     int n_passes() const { return n_pass; }
@@ -359,6 +359,14 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
     L.fwd_bytes = f.off;
     Carve b;
     L.sc_border = b.take(4 * (size_t)tb);
+    // the tile order's sort (used when a pass has many tiles)
+    L.sc_okeys = b.take(4 * (size_t)tb);
+    L.sc_ovals = b.take(4 * (size_t)tb);
+    L.sc_okeys2 = b.take(4 * (size_t)tb);
+    L.sc_ovals2 = b.take(4 * (size_t)tb);
+    L.ohist_words = radix_hist_words((uint64_t)tb, 1, kMaxRadixBits, kSortItems);
+    L.sc_ohist = b.take(4 * L.ohist_words);
+    L.sc_ototals = b.take(4 * (size_t)kMaxRadix);
     L.bwd_bytes = b.off;
     L.scratch_bytes = std::max(L.fwd_bytes, L.bwd_bytes);
     return L;
@@ -855,8 +863,14 @@ static h4d_status render_backward(h4d_ctx* ctx, const h4d_g3d* g3, const h4d_g4d
     pt.n = L.n_passes();
     for (int k = 0; k < pt.n; ++k) pt.tile0[k] = L.vg[L.pass(k).v0].tile_base;
     pt.tile0[pt.n] = L.total_tiles;
-    launch_bwd_prologue(g2, (size_t)kG2Stride * N * n_views, &status->g2_dirty, (L.shared && want_stats) ? 1 : 0,
-                        at<uint32_t>(stt, L.st_tcost), at<uint32_t>(stt, L.st_thist), pt, border, st);
+    const OrderSort osort{at<uint32_t>(scratch, L.sc_okeys),  at<uint32_t>(scratch, L.sc_ovals),
+                          at<uint32_t>(scratch, L.sc_okeys2), at<uint32_t>(scratch, L.sc_ovals2),
+                          at<uint32_t>(scratch, L.sc_ohist),  at<uint32_t>(scratch, L.sc_ototals),
+                          L.ohist_words,                      (size_t)kMaxRadix};
+    if (!launch_bwd_prologue(g2, (size_t)kG2Stride * N * n_views, &status->g2_dirty,
+                             (L.shared && want_stats) ? 1 : 0, at<uint32_t>(stt, L.st_tcost),
+                             at<uint32_t>(stt, L.st_thist), pt, osort, border, st))
+        return fail(ctx, H4D_ERR_UNSUPPORTED, "internal: the tile order's sort did not fit its buffers");
     const ViewParams* vp = at<ViewParams>(stt, L.st_views);
     {
         StageScope sc(ctx, st, H4D_STAGE_BLEND_BWD);

@@ -136,7 +136,11 @@ void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_s
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st);
 // Backward prologue: zeroes g2[0, n_g2) if *dirty != 0 or force, and orders the
-// tiles of every pass by decreasing tcost (pass k: global tiles [tile0[k], tile0[k + 1]), its order
+// tiles of every pass by decreasing tcost: one workgroup per pass from the
+// forward's bucket counts, or, when a pass has more than kOrderBlockTiles
+// tiles, by a radix sort over the buffers of `sort` (keys, vals, keys2, vals2:
+// one word per tile; hist / totals as the radix pass needs for that many keys
+// and 11-bit digits).  Returns false if a sort pass did not fit its buffers. (pass k: global tiles [tile0[k], tile0[k + 1]), its order
 // at the same offsets, relative to tile0[k]; thist + k kCostBuckets: the
 // forward's per-bucket tile counts of pass k).  A permutation whatever the
 // counts hold: buckets that overflow fall back to identity order.
@@ -144,8 +148,14 @@ struct PassTiles {
     int32_t n;                     // passes
     int32_t tile0[kMaxViews + 1];
 };
-void launch_bwd_prologue(float* g2, size_t n_g2, const unsigned long long* dirty, int force, const uint32_t* tcost,
-                         const uint32_t* thist, const PassTiles& passes, uint32_t* order, hipStream_t st);
+constexpr int kOrderBlockTiles = 32768;
+struct OrderSort {
+    uint32_t *keys, *vals, *keys2, *vals2, *hist, *totals;
+    size_t hist_words, totals_words;
+};
+bool launch_bwd_prologue(float* g2, size_t n_g2, const unsigned long long* dirty, int force, const uint32_t* tcost,
+                         const uint32_t* thist, const PassTiles& passes, const OrderSort& sort, uint32_t* order,
+                         hipStream_t st);
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st);
 void launch_fill_f32(float* p, size_t n, float val, hipStream_t st);
 

@@ -753,18 +753,19 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ key
 __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long val) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = val;
 }
-// Backward: workgroup k < passes.n orders pass k from the forward's per-bucket
-// tile counts (an exclusive scan, then one scatter pass over the tiles; ties
-// in any order), the other workgroups zero g2 when a backward has used it
-// since the forward (*dirty) or when force is set.  Counts that do not add up to
-// the pass's tiles give the identity order.
+// Backward: workgroup k < passes.n (order_blocks = passes.n) orders pass k
+// from the forward's per-bucket tile counts (an exclusive scan, then one
+// scatter pass over the tiles; ties in any order), or, with order_blocks = 0,
+// the order comes from a sort (k_bwd_order_keys); the other workgroups zero g2
+// when a backward has used it since the forward (*dirty) or when force is set.
+// Counts that do not add up to the pass's tiles give the identity order.
 __global__ void __launch_bounds__(1024) k_bwd_prologue(float* __restrict__ g2, size_t n_g2,
                                                        const unsigned long long* __restrict__ dirty, int force,
                                                        const uint32_t* __restrict__ tcost,
                                                        const uint32_t* __restrict__ thist, PassTiles passes,
-                                                       uint32_t* __restrict__ order) {
+                                                       int order_blocks, uint32_t* __restrict__ order) {
     const int k = (int)blockIdx.x;
-    if (k < passes.n) {
+    if (k < order_blocks) {
         __shared__ uint32_t s_pos[kCostBuckets];
         __shared__ uint32_t s_total, s_bad;
         static_assert(kCostBuckets == 16 * 64, "one wave scans the buckets");
@@ -807,14 +808,26 @@ __global__ void __launch_bounds__(1024) k_bwd_prologue(float* __restrict__ g2, s
         return;
     }
     if (!force && *dirty == 0ull) return;  // the records are as the forward left them (uniform)
-    const size_t nb = (size_t)(gridDim.x - passes.n);
-    const size_t i0 = (size_t)(k - passes.n) * blockDim.x + threadIdx.x, step = nb * blockDim.x;
+    const size_t nb = (size_t)(gridDim.x - order_blocks);
+    const size_t i0 = (size_t)(k - order_blocks) * blockDim.x + threadIdx.x, step = nb * blockDim.x;
     if ((reinterpret_cast<uintptr_t>(g2) & 15u) == 0 && (n_g2 & 3) == 0) {  // 16-byte stores
         float4* g4 = reinterpret_cast<float4*>(g2);
         for (size_t i = i0; i < n_g2 / 4; i += step) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     } else {
         for (size_t i = i0; i < n_g2; i += step) g2[i] = 0.0f;
     }
+}
+
+// Sort keys of the backward's tile order when a pass has too many tiles for one
+// workgroup: per global tile t of pass k, key (k, cost bucket), value t - tile0[k].
+__global__ void __launch_bounds__(256) k_bwd_order_keys(const uint32_t* __restrict__ tcost, PassTiles passes,
+                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int t = blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= passes.tile0[passes.n]) return;
+    int k = 0;
+    while (k + 1 < passes.n && passes.tile0[k + 1] <= t) ++k;
+    keys[t] = ((uint32_t)k << 10) | cost_bucket(tcost[t]);
+    vals[t] = (uint32_t)(t - passes.tile0[k]);
 }
 
 __global__ void k_fill_f32(float* p, size_t n, float val) {
@@ -855,11 +868,38 @@ void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long 
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {
     k_ranges<<<2048, 256, 0, st>>>(keys, key_mask, eff_count, base, ranges);
 }
-void launch_bwd_prologue(float* g2, size_t n_g2, const unsigned long long* dirty, int force, const uint32_t* tcost,
-                         const uint32_t* thist, const PassTiles& passes, uint32_t* order, hipStream_t st) {
-    // one 16-byte store per thread (no grid-stride loop)
-    const int fill = (int)std::max<size_t>(1, std::min<size_t>(1u << 20, (n_g2 + 4095) / 4096));
-    k_bwd_prologue<<<passes.n + fill, 1024, 0, st>>>(g2, n_g2, dirty, force, tcost, thist, passes, order);
+bool launch_bwd_prologue(float* g2, size_t n_g2, const unsigned long long* dirty, int force, const uint32_t* tcost,
+                         const uint32_t* thist, const PassTiles& passes, const OrderSort& sort, uint32_t* order,
+                         hipStream_t st) {
+    int most = 0;
+    for (int k = 0; k < passes.n; ++k) most = std::max(most, passes.tile0[k + 1] - passes.tile0[k]);
+    const bool by_sort = most > kOrderBlockTiles;
+    // a grid-stride loop of 16-byte stores over at most 4096 workgroups (which
+    // return at once when nothing is to be cleared)
+    const int fill = (int)std::max<size_t>(1, std::min<size_t>(4096, (n_g2 + 4095) / 4096));
+    const int ob = by_sort ? 0 : passes.n;
+    k_bwd_prologue<<<ob + fill, 1024, 0, st>>>(g2, n_g2, dirty, force, tcost, thist, passes, ob, order);
+    if (!by_sort) return true;
+    // one stable sort of (pass, cost bucket) keys over all tiles: every pass's
+    // tiles in a run of their own, by decreasing cost
+    const int tiles = passes.tile0[passes.n];
+    k_bwd_order_keys<<<(tiles + 255) / 256, 256, 0, st>>>(tcost, passes, sort.keys, sort.vals);
+    int bits = 10;
+    while ((1 << (bits - 10)) < passes.n) ++bits;
+    const int np = (bits + kMaxRadixBits - 1) / kMaxRadixBits;
+    uint32_t *kin = sort.keys, *vin = sort.vals, *kalt = sort.keys2, *valt = sort.vals2;
+    for (int p = 0, shift = 0; p < np; ++p) {
+        const int nb = (bits - shift + (np - p) - 1) / (np - p);
+        uint32_t* vout = p == np - 1 ? order : valt;
+        if (!launch_radix_pass(kin, vin, kalt, vout, nullptr, (uint64_t)tiles, (uint64_t)tiles, shift, nb, sort.hist,
+                               sort.hist_words, sort.totals, sort.totals_words, nullptr, st))
+            return false;
+        std::swap(kin, kalt);
+        vin = vout;
+        valt = (vout == sort.vals2) ? sort.vals : sort.vals2;
+        shift += nb;
+    }
+    return true;
 }
 
 void launch_fill_u64(unsigned long long* p, size_t n, unsigned long long val, hipStream_t st) {
