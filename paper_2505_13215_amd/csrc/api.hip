@@ -119,6 +119,7 @@ h4d_status hip_check(h4d_ctx* c, const char* where) {
 }
 
 constexpr size_t kAlign = 256;
+constexpr size_t kPixelAlign = (size_t)1 << 21;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Carve {
@@ -181,7 +182,7 @@ struct Layout {
         st_tcost, infer_bytes, st_g2, st_tids, state_bytes;
     // scratch, forward use
     size_t sc_dkeys, sc_dvals, sc_dkeys2, sc_dvals2, sc_cnt, sc_rect, sc_offsets, sc_partials, sc_eff, sc_ceff,
-        sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_shape, sc_runs, sc_wcnt, sc_woff, sc_wpart,
+        sc_pkeys, sc_pvals, sc_pkeys2, sc_pvals2, sc_hist, sc_totals, sc_shape, sc_spans, sc_runs, sc_wcnt, sc_woff, sc_wpart,
         fwd_bytes;
     size_t hist_words = 0, totals_words = 0;  // 32-bit words of the radix histogram / digit totals
     // scratch, backward use
@@ -310,6 +311,10 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
     L.st_cvals = s.take(4 * (size_t)L.ccap);
     L.st_cranges = s.take(16 * (size_t)L.total_supers);
     L.st_thist = s.take(4 * (size_t)kCostBuckets * V_);  // one per pass (at most V); cleared with the ranges
+    // the per-pixel arrays and everything after them start on a 2 MiB
+    // boundary, so that their placement does not move with the pair capacity
+    // (the adjoint's time varied with it by up to 2.5 %)
+    s.off = (s.off + kPixelAlign - 1) / kPixelAlign * kPixelAlign;
     L.st_T = s.take(4 * (size_t)pb);
     L.st_nc = s.take(4 * (size_t)pb);
     L.st_C = s.take(12 * (size_t)pb);
@@ -350,6 +355,7 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
     L.sc_hist = f.take(4 * L.hist_words);
     L.sc_totals = f.take(4 * L.totals_words);
     L.sc_shape = cfg->cull ? f.take(sizeof(CullShape) * np) : 0;
+    L.sc_spans = cfg->cull ? f.take(4 * (size_t)kSpanRows * np) : 0;
     L.sc_runs = f.take(4 * ((size_t)L.ccap / 256 + 2));
     // tile lists written out on request (h4dgs_tile_lists): per-tile counts,
     // their offsets and the scan's partial sums
@@ -591,8 +597,9 @@ bool bin_pass(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int cull, vo
     // coarse entries: one per (depth-ordered Gaussian, super-tile), the tile
     // mask in the key's upper half
     CullShape* shapes = cull ? at<CullShape>(scratch, L.sc_shape) : nullptr;
+    uint32_t* spans = cull ? at<uint32_t>(scratch, L.sc_spans) : nullptr;
     unsigned long long* partials = at<unsigned long long>(scratch, L.sc_partials);
-    launch_coarse_count(dv, n, N, sg, recs, vp, P.v0, tile, S, cnt, rect, shapes, partials, st);
+    launch_coarse_count(dv, n, N, sg, recs, vp, P.v0, tile, S, cnt, rect, shapes, spans, partials, st);
     uint32_t* runs = at<uint32_t>(scratch, L.sc_runs);
     launch_coarse_offsets(cnt, n, partials, L.ccap, S, cbase, P.v0, P.v1, status, eff_c, offsets, runs,
                           L.ccap / 256 + 1, st);
@@ -600,7 +607,7 @@ bool bin_pass(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int cull, vo
     uint32_t* pv = at<uint32_t>(scratch, L.sc_pvals);
     uint32_t* pk2 = at<uint32_t>(scratch, L.sc_pkeys2);
     uint32_t* pv2 = at<uint32_t>(scratch, L.sc_pvals2);
-    launch_coarse_emit(offsets, runs, n, sg, rect, shapes, vp, P.v0, tile, S, L.ccap, eff_c, pk, pv, st);
+    launch_coarse_emit(offsets, runs, n, sg, rect, shapes, spans, vp, P.v0, tile, S, L.ccap, eff_c, pk, pv, st);
     // stable sort of the coarse entries by super-tile (depth order kept inside
     // each); the last pass writes the state's coarse arrays from cbase[P.v0]
     // on, with splat ids in place of the depth ranks.  The first pass also

@@ -99,7 +99,7 @@ void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigne
 // The alpha >= 1/255 region of one splat as the binning's tile test needs it:
 // -p2 = a dx^2 - b dx dy + c dy^2 <= t, with dx, dy offsets from the centre (set
 // up in FP64 per splat, tested in FP32 on widened intervals).
-struct CullShape {
+struct __align__(16) CullShape {
     float b, inv2a, four_at, det4;  // det4 = 4ac - b^2
     float y_full, y_ext;            // half-height; height of the rightmost point
     float pad_x, pad_y;
@@ -107,16 +107,23 @@ struct CullShape {
     int px0, px1, py0, py1;         // pixel square
     int mode;                       // 0: keep every tile, 1: test, 2: no pixel can pass
 };
+// Tile rows whose column spans the count kernel tabulates per splat (taller
+// splats keep their CullShape and are tested per coarse entry).
+constexpr int kSpanRows = 16;
 
 // Two-level binning over the views [v0, v1) of one pass; j indexes the pass's
 // depth-ordered entries in the segment layout sg (n entries; sorted_gid[j]:
 // the splat id, relative to its record's view).  Super-tile ids are relative to
 // view v0's first (a pass holds at most kMaxPassSupers of them).
 // partials: coarse_count_blocks(n) + 1 words, each count workgroup's sum.
+// Culling (shapes and spans non-null, n CullShapes and kSpanRows n words): the
+// tile rectangle shrinks to the tiles the alpha >= 1/255 test can keep, and the
+// test's per-row column spans are tabulated (or, for taller splats, the shape
+// kept) for the emission.
 int coarse_count_blocks(int n);
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, SegLayout sg, const Rec* recs,
                          const ViewParams* views, int v0, int tile, int S, uint32_t* cnt, uint64_t* rect_sorted,
-                         CullShape* shapes, unsigned long long* partials, hipStream_t st);
+                         CullShape* shapes, uint32_t* spans, unsigned long long* partials, hipStream_t st);
 // offsets[j] = sum of cnt before j (offsets[n] = C) with run_start as in
 // launch_scan_u32_u64; capacity check: the pass's C coarse entries go to
 // [cbase[v0], cbase[v0] + C) of the call's ccap; cbase[v1] receives the end
@@ -127,9 +134,9 @@ void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* parti
 // Keys carry each entry's tile mask in their upper 16 bits (cull: less the
 // tiles no pixel of which can reach alpha >= 1/255).
 void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, SegLayout sg,
-                        const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
-                        int S, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals,
-                        hipStream_t st);
+                        const uint64_t* rect_sorted, const CullShape* shapes, const uint32_t* spans,
+                        const ViewParams* views, int v0, int tile, int S, uint64_t capacity,
+                        const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st);
 // ranges of the sorted keys keys[*base ..) (compared under key_mask):
 // ranges[2k], ranges[2k+1] = [first, last+1), counted from keys (base may be
 // null: 0)

@@ -369,7 +369,7 @@ void launch_scan_u32_u64(const uint32_t* in, const uint32_t* idx, int n, unsigne
 // ---------------------------------------------------------------------------
 // Two-level binning.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t pack_rect(uint32_t x0, uint32_t x1, uint32_t y0, uint32_t y1) {
+__host__ __device__ __forceinline__ uint64_t pack_rect(uint32_t x0, uint32_t x1, uint32_t y0, uint32_t y1) {
     return (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) | ((uint64_t)y1 << 48);
 }
 
@@ -386,7 +386,7 @@ constexpr double kCullMargin = 1e-3;
 // times the FP32 rounding of the extent (whose worst case, near the ellipse's
 // top and bottom, is about 5e-4 of the half-width).
 
-__device__ inline CullShape cull_shape(const Rec& rec) {
+__host__ __device__ inline CullShape cull_shape(const Rec& rec) {
     CullShape cs;
     const double a = -(double)rec.a.z, b = rec.a.w, c = -(double)rec.b.x, op = rec.b.y;
     cs.ui = rec.c.y; cs.uf = rec.a.x; cs.vi = rec.c.z; cs.vf = rec.a.y;
@@ -416,58 +416,113 @@ __device__ inline CullShape cull_shape(const Rec& rec) {
     return cs;
 }
 
+// Pixel-centre offsets from the splat's centre (x: ui + uf, y: vi + vf) of
+// the first and last pixel column of tile column tx, and of the first and last
+// pixel row of tile row ty, inside its pixel square.
+template <int TILE>
+__host__ __device__ __forceinline__ float col_x0(const CullShape& cs, int tx) {
+    return ((float)max(tx * TILE, cs.px0) + 0.5f - cs.ui) - cs.uf;
+}
+template <int TILE>
+__host__ __device__ __forceinline__ float col_x1(const CullShape& cs, int tx) {
+    return ((float)min(tx * TILE + TILE - 1, cs.px1) + 0.5f - cs.ui) - cs.uf;
+}
+template <int TILE>
+__host__ __device__ __forceinline__ float row_y0(const CullShape& cs, int ty) {
+    return ((float)max(ty * TILE, cs.py0) + 0.5f - cs.vi) - cs.vf;
+}
+template <int TILE>
+__host__ __device__ __forceinline__ float row_y1(const CullShape& cs, int ty) {
+    return ((float)min(ty * TILE + TILE - 1, cs.py1) + 0.5f - cs.vi) - cs.vf;
+}
+// Whether tile row ty's slab of pixel-centre offsets meets the ellipse's
+// height (widened by pad_y).
+template <int TILE>
+__host__ __device__ __forceinline__ bool row_meets(const CullShape& cs, int ty) {
+    return !(row_y1<TILE>(cs, ty) < -cs.y_full - cs.pad_y || row_y0<TILE>(cs, ty) > cs.y_full + cs.pad_y);
+}
+// The ellipse's x-extent [xl, xr] over tile row ty's slab (from its leftmost
+// and rightmost points clamped into the slab), widened by pad_x.
+template <int TILE>
+__host__ __device__ __forceinline__ void row_extent(const CullShape& cs, int ty, float& xl, float& xr) {
+    const float Y0 = row_y0<TILE>(cs, ty), Y1 = row_y1<TILE>(cs, ty);
+    const float yr = fminf(fmaxf(cs.y_ext, Y0), Y1), yl = fminf(fmaxf(-cs.y_ext, Y0), Y1);
+    xr = (cs.b * yr + sqrtf(fmaxf(0.f, cs.four_at - yr * yr * cs.det4))) * cs.inv2a + cs.pad_x;
+    xl = (cs.b * yl - sqrtf(fmaxf(0.f, cs.four_at - yl * yl * cs.det4))) * cs.inv2a - cs.pad_x;
+}
+
 // Tiles (bit ly * S + lx) of the super-tile at tile origin (bx, by) that the
-// splat's tile rectangle [tx0, tx1] x [ty0, ty1] overlaps and, when shape.mode
-// is 1, in which the ellipse's x-extent over the tile row's slab of pixel-centre
-// offsets (from its extreme points clamped into the slab) meets the tile's
-// pixel-centre x-range.
-__device__ inline uint32_t tile_mask(const CullShape& cs, int cull, uint32_t tx0, uint32_t tx1, uint32_t ty0,
-                                     uint32_t ty1, uint32_t bx, uint32_t by, int S, int tile) {
-    const uint32_t lx0 = max(tx0, bx) - bx, lx1 = min(tx1, bx + (uint32_t)S - 1u) - bx;
-    const uint32_t ly0 = max(ty0, by) - by, ly1 = min(ty1, by + (uint32_t)S - 1u) - by;
-    // S <= 4: fixed, unrolled loops over the super-tile's rows and columns (tiles
-    // outside [l0, l1] are masked), so that the lanes of a wave do not diverge
+// splat's tile rectangle [tx0, tx1] x [ty0, ty1] overlaps and, when cull is
+// set, in which the ellipse's x-extent over the tile row's slab meets the
+// tile's pixel-centre x-range (the test of row_span, per entry: splats taller
+// than the span table).
+template <int TILE>
+__host__ __device__ inline uint32_t tile_mask(const CullShape& cs, bool cull, uint32_t tx0, uint32_t tx1, uint32_t ty0,
+                                     uint32_t ty1, uint32_t bx, uint32_t by) {
+    constexpr uint32_t S = (uint32_t)super_factor(TILE);
+    const uint32_t lx0 = max(tx0, bx) - bx, lx1 = min(tx1, bx + S - 1u) - bx;
+    const uint32_t ly0 = max(ty0, by) - by, ly1 = min(ty1, by + S - 1u) - by;
     uint32_t cols = 0u, rows = 0u;  // bit l: column / row l overlaps the rectangle
 #pragma unroll
-    for (uint32_t l = 0; l < 4u; ++l) {
+    for (uint32_t l = 0; l < S; ++l) {
         cols |= (l >= lx0 && l <= lx1) ? 1u << l : 0u;
         rows |= (l >= ly0 && l <= ly1) ? 1u << l : 0u;
     }
-    if (!cull || cs.mode == 0) {
+    if (!cull) {
         uint32_t mask = 0u;
 #pragma unroll
-        for (uint32_t ly = 0; ly < 4u; ++ly)
-            if ((rows >> ly) & 1u) mask |= cols << (ly * (uint32_t)S);
-        return mask & ((S == 4) ? 0xFFFFu : 0xFu);
+        for (uint32_t ly = 0; ly < S; ++ly)
+            if ((rows >> ly) & 1u) mask |= cols << (ly * S);
+        return mask;
     }
-    if (cs.mode == 2) return 0u;
     // the columns' pixel-centre offset intervals do not depend on the row
-    float X0[4], X1[4];
+    float X0[S], X1[S];
 #pragma unroll
-    for (uint32_t lx = 0; lx < 4u; ++lx) {
-        const int tx = (int)(bx + lx);
-        X0[lx] = ((float)max(tx * tile, cs.px0) + 0.5f - cs.ui) - cs.uf;
-        X1[lx] = ((float)min(tx * tile + tile - 1, cs.px1) + 0.5f - cs.ui) - cs.uf;
+    for (uint32_t lx = 0; lx < S; ++lx) {
+        X0[lx] = col_x0<TILE>(cs, (int)(bx + lx));
+        X1[lx] = col_x1<TILE>(cs, (int)(bx + lx));
     }
     uint32_t mask = 0u;
 #pragma unroll
-    for (uint32_t ly = 0; ly < 4u; ++ly) {
+    for (uint32_t ly = 0; ly < S; ++ly) {
         if (!((rows >> ly) & 1u)) continue;
         const int ty = (int)(by + ly);
-        const float Y0 = ((float)max(ty * tile, cs.py0) + 0.5f - cs.vi) - cs.vf;
-        const float Y1 = ((float)min(ty * tile + tile - 1, cs.py1) + 0.5f - cs.vi) - cs.vf;
-        if (Y1 < -cs.y_full - cs.pad_y || Y0 > cs.y_full + cs.pad_y) continue;
-        const float yr = fminf(fmaxf(cs.y_ext, Y0), Y1), yl = fminf(fmaxf(-cs.y_ext, Y0), Y1);
-        const float xr = (cs.b * yr + __builtin_sqrtf(fmaxf(0.f, cs.four_at - yr * yr * cs.det4))) * cs.inv2a +
-                         cs.pad_x;
-        const float xl = (cs.b * yl - __builtin_sqrtf(fmaxf(0.f, cs.four_at - yl * yl * cs.det4))) * cs.inv2a -
-                         cs.pad_x;
+        if (!row_meets<TILE>(cs, ty)) continue;
+        float xl, xr;
+        row_extent<TILE>(cs, ty, xl, xr);
 #pragma unroll
-        for (uint32_t lx = 0; lx < 4u; ++lx)
-            if (((cols >> lx) & 1u) && X1[lx] >= xl && X0[lx] <= xr) mask |= 1u << (ly * (uint32_t)S + lx);
+        for (uint32_t lx = 0; lx < S; ++lx)
+            if (((cols >> lx) & 1u) && X1[lx] >= xl && X0[lx] <= xr) mask |= 1u << (ly * S + lx);
     }
     return mask;
 }
+
+// The tile columns of tile row ty that the test above keeps, as one word:
+// first column | (last + 1) << 16 (0: none).  The columns whose x-range meets
+// [xl, xr] form one run (both ends of a column's range grow with the column):
+// a first guess from the pixel coordinates, then stepped to the exact ends of
+// the same comparisons.
+template <int TILE>
+__host__ __device__ inline uint32_t row_span(const CullShape& cs, int ty, int tx0, int tx1) {
+    if (!row_meets<TILE>(cs, ty)) return 0u;
+    float xl, xr;
+    row_extent<TILE>(cs, ty, xl, xr);
+    const float lo = (float)(tx0 - 1), hi = (float)(tx1 + 1);
+    int cl = (int)fminf(fmaxf(ceilf((xl + cs.ui + cs.uf + 0.5f) * (1.f / TILE)) - 1.f, lo), hi);
+    cl = min(max(cl, tx0), tx1 + 1);
+    while (cl > tx0 && col_x1<TILE>(cs, cl - 1) >= xl) --cl;
+    while (cl <= tx1 && !(col_x1<TILE>(cs, cl) >= xl)) ++cl;
+    int cr = (int)fminf(fmaxf(floorf((xr + cs.ui + cs.uf - 0.5f) * (1.f / TILE)), lo), hi);
+    cr = min(max(cr, tx0 - 1), tx1);
+    while (cr < tx1 && col_x0<TILE>(cs, cr + 1) <= xr) ++cr;
+    while (cr >= tx0 && !(col_x0<TILE>(cs, cr) <= xr)) --cr;
+    return cl <= cr ? (uint32_t)cl | ((uint32_t)(cr + 1) << 16) : 0u;
+}
+
+// Flags in the top bits of a splat's packed tile rectangle (tile coordinates
+// stay below 2^14): the shape test per coarse entry, or no test at all.
+constexpr uint64_t kRectShape = 1ull << 63, kRectFull = 1ull << 62;
+constexpr uint64_t kRectCoords = ~(kRectShape | kRectFull);
 
 // Where depth-ordered entry j of a pass (segment layout sg) belongs: the view
 // whose records hold it and, for its super-tile keys, that view's grid and the
@@ -486,32 +541,166 @@ __device__ __forceinline__ SegPos seg_of(int j, const SegLayout& sg, const ViewP
     return SegPos{leader, views[leader].static_super_base - views[v0].super_base};
 }
 
-// Per depth-ordered entry j of the pass: its tile rectangle, its super-tile
-// count and (shapes != null) the shape of its alpha >= 1/255 region for the
-// tile test.
+// First index i in [lo, hi] with pred(i) (hi + 1 if none), for a predicate
+// that is false up to some index and true from there on, starting from a
+// guess; and the last index with pred (lo - 1 if none) for one that is true up
+// to some index and false after it.
+template <typename P>
+__host__ __device__ inline int first_true(float guess, int lo, int hi, P pred) {
+    int i = (int)fminf(fmaxf(guess, (float)lo), (float)(hi + 1));
+    while (i > lo && pred(i - 1)) --i;
+    while (i <= hi && !pred(i)) ++i;
+    return i;
+}
+template <typename P>
+__host__ __device__ inline int last_true(float guess, int lo, int hi, P pred) {
+    int i = (int)fminf(fmaxf(guess, (float)(lo - 1)), (float)hi);
+    while (i < hi && pred(i + 1)) ++i;
+    while (i >= lo && !pred(i)) --i;
+    return i;
+}
+
+// The tile rows [r0, r1] of [ty0, ty1] whose slab meets the ellipse (a run:
+// both ends of a row's slab grow with the row; r1 < r0 when none).
+template <int TILE>
+__host__ __device__ inline void slab_rows(const CullShape& cs, int ty0, int ty1, int& r0, int& r1) {
+    const float h = cs.y_full + cs.pad_y, cy = cs.vi + cs.vf;
+    r0 = first_true(ceilf((cy - h + 0.5f) * (1.f / TILE)) - 1.f, ty0, ty1,
+                    [&](int ty) { return !(row_y1<TILE>(cs, ty) < -h); });
+    r1 = last_true(floorf((cy + h - 0.5f) * (1.f / TILE)), r0, ty1,
+                   [&](int ty) { return !(row_y0<TILE>(cs, ty) > h); });
+}
+
+// Tiles of the super-tile at tile origin (bx, by) in the tabulated spans of
+// rows [ty0, ty1] (span_row[row - ty0]), as tile_mask's bits.
+template <int TILE>
+__host__ __device__ inline uint32_t span_mask(const uint32_t* span_row, uint32_t ty0, uint32_t ty1, uint32_t bx,
+                                              uint32_t by) {
+    constexpr uint32_t S = (uint32_t)super_factor(TILE);
+    uint32_t m = 0u;
+#pragma unroll
+    for (uint32_t ly = 0; ly < S; ++ly) {
+        const uint32_t ty = by + ly;
+        if (ty < ty0 || ty > ty1) continue;
+        const uint32_t e = span_row[ty - ty0];
+        const uint32_t lo = (e & 0xFFFFu) > bx ? (e & 0xFFFFu) : bx, hi = (e >> 16) < bx + S ? (e >> 16) : bx + S;
+        if (lo < hi) m |= ((1u << (hi - bx)) - (1u << (lo - bx))) << (ly * S);
+    }
+    return m;
+}
+
+// Per depth-ordered entry j of the pass: its tile rectangle and its
+// super-tile count.  With culling (shapes != null) the rectangle shrinks to
+// the rows whose slab meets the ellipse and to the columns any of their spans
+// keeps (the tiles tile_mask can keep; a splat with none emits nothing), and
+// the spans of up to kSpanRows rows are tabulated for the emission
+// (spans[j * kSpanRows + row - first row]); a taller splat keeps its shape
+// (kRectShape: tested per entry) and one without a proper ellipse its square
+// (kRectFull: untested).  The spans of a wave's splats are computed one
+// (splat, row) per lane: a wave's rows are numbered by a prefix sum over its
+// lanes, and each round of 64 finds its rows' splats by a max-scan of the
+// lanes' first rows.
 // One entry per thread; each workgroup also leaves its sum of counts for
 // the offsets' scan (partials[blockIdx.x]).
+template <int TILE>
 __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n, int N,
                                                       SegLayout sg, const Rec* __restrict__ recs,
-                                                      const ViewParams* __restrict__ views, int v0, int tile, int S,
+                                                      const ViewParams* __restrict__ views, int v0,
                                                       uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted,
-                                                      CullShape* __restrict__ shapes,
+                                                      CullShape* __restrict__ shapes, uint32_t* __restrict__ spans,
                                                       unsigned long long* __restrict__ partials) {
+    constexpr uint32_t S = (uint32_t)super_factor(TILE);
     __shared__ unsigned long long s_buf[256];
-    const uint32_t t = (uint32_t)tile, s = (uint32_t)S;
-    const int j = blockIdx.x * 256 + (int)threadIdx.x;
-    uint32_t c = 0u;
+    __shared__ CullShape s_cs[256];
+    __shared__ int s_cmin[256], s_cmax[256];
+    __shared__ int s_slot[4][64];
+    const int tid = (int)threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    const int j = blockIdx.x * 256 + tid;
+    bool keep = false;
+    uint64_t flags = 0ull;
+    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1, r0 = 0, nrows = 0;
+    CullShape cs;
     if (j < n) {
         const SegPos sp = seg_of(j, sg, views, v0);
         const Rec& rec = recs[(size_t)sp.view * N + sorted_gid[j]];
         const uint4 d = rec.d;
-        uint64_t rect = 0ull;
         if (d.w != 0u) {
-            const uint32_t tx0 = (d.x & 0xFFFFu) / t, tx1 = (d.x >> 16) / t, ty0 = (d.y & 0xFFFFu) / t,
-                           ty1 = (d.y >> 16) / t;
-            rect = pack_rect(tx0, tx1, ty0, ty1);
-            c = (tx1 / s - tx0 / s + 1u) * (ty1 / s - ty0 / s + 1u);
-            if (shapes) shapes[j] = cull_shape(rec);
+            keep = true;
+            tx0 = (int)((d.x & 0xFFFFu) / TILE); tx1 = (int)((d.x >> 16) / TILE);
+            ty0 = (int)((d.y & 0xFFFFu) / TILE); ty1 = (int)((d.y >> 16) / TILE);
+            if (shapes) {
+                cs = cull_shape(rec);
+                if (cs.mode == 0) {
+                    flags = kRectFull;
+                } else if (cs.mode == 2) {
+                    keep = false;
+                } else {
+                    int r1;
+                    slab_rows<TILE>(cs, ty0, ty1, r0, r1);
+                    nrows = max(0, r1 - r0 + 1);
+                    keep = nrows > 0;
+                    s_cs[tid] = cs;
+                }
+            }
+        }
+    }
+    if (shapes) {  // uniform
+        s_cmin[tid] = tx1 + 1;
+        s_cmax[tid] = tx0 - 1;
+        int incl = nrows;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        const int total = __shfl(incl, 63), excl = incl - nrows;
+        const bool table = nrows <= kSpanRows;
+        int carry = 0;  // the lane whose rows hold the round's first
+        for (int base = 0; base < total; base += 64) {
+            s_slot[w][lane] = -1;
+            __builtin_amdgcn_wave_barrier();
+            if (nrows > 0 && excl >= base && excl < base + 64) s_slot[w][excl - base] = lane;
+            __builtin_amdgcn_wave_barrier();
+            int o = s_slot[w][lane];
+            if (lane == 0 && o < 0) o = carry;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(o, off);
+                if (lane >= off) o = max(o, y);
+            }
+            carry = __shfl(o, 63);
+            const int g = max(o, 0);
+            const int ex = __shfl(excl, g), gr0 = __shfl(r0, g), gx0 = __shfl(tx0, g), gx1 = __shfl(tx1, g);
+            const int gtab = __shfl((int)table, g);
+            const int k = base + lane;
+            if (k < total) {
+                const int gt = (w << 6) + g;
+                const uint32_t e = row_span<TILE>(s_cs[gt], gr0 + (k - ex), gx0, gx1);
+                if (gtab) spans[((size_t)blockIdx.x * 256 + gt) * kSpanRows + (k - ex)] = e;
+                if (e != 0u) {
+                    atomicMin(&s_cmin[gt], (int)(e & 0xFFFFu));
+                    atomicMax(&s_cmax[gt], (int)(e >> 16) - 1);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        if (keep && nrows > 0) {
+            const int cmin = s_cmin[tid], cmax = s_cmax[tid];
+            keep = cmin <= cmax;
+            if (keep) {
+                tx0 = cmin; tx1 = cmax; ty0 = r0; ty1 = r0 + nrows - 1;
+                if (!table) {
+                    flags = kRectShape;
+                    shapes[j] = cs;
+                }
+            }
+        }
+    }
+    uint32_t c = 0u;
+    if (j < n) {
+        uint64_t rect = 0ull;
+        if (keep) {
+            rect = pack_rect((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1) | flags;
+            c = ((uint32_t)tx1 / S - (uint32_t)tx0 / S + 1u) * ((uint32_t)ty1 / S - (uint32_t)ty0 / S + 1u);
         }
         rect_sorted[j] = rect;
         cnt[j] = c;
@@ -674,13 +863,16 @@ __global__ void __launch_bounds__(1024) k_coarse_top(unsigned long long* __restr
 // depth order).  The key's upper 16 bits carry the entry's tile mask (the
 // super-tile sort reads only the low bits); shapes != null applies the alpha
 // >= 1/255 tile test.
+template <int TILE>
 __global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* __restrict__ offsets,
                                                      const uint32_t* __restrict__ run_start, int n, SegLayout sg,
                                                      const uint64_t* __restrict__ rect_sorted,
                                                      const CullShape* __restrict__ shapes,
-                                                     const ViewParams* __restrict__ views, int v0, int tile, int S,
+                                                     const uint32_t* __restrict__ spans,
+                                                     const ViewParams* __restrict__ views, int v0,
                                                      const unsigned long long* eff_count,
                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    constexpr uint32_t S = (uint32_t)super_factor(TILE);
     __shared__ unsigned long long s_off[257];
     const uint64_t C = *eff_count;
     const int tid = threadIdx.x;
@@ -717,18 +909,28 @@ __global__ void __launch_bounds__(256) k_coarse_emit(const unsigned long long* _
             }
             const SegPos sp = seg_of(j, sg, views, v0);
             const ViewParams& V = views[sp.view];
-            const uint64_t r = rect_sorted[j];
-            const uint32_t s = (uint32_t)S;
+            const uint64_t rf = rect_sorted[j], r = rf & kRectCoords;
             const uint32_t tx0 = (uint32_t)(r & 0xFFFFu), tx1 = (uint32_t)((r >> 16) & 0xFFFFu);
             const uint32_t ty0 = (uint32_t)((r >> 32) & 0xFFFFu), ty1 = (uint32_t)(r >> 48);
-            const uint32_t sx0 = tx0 / s, sw = tx1 / s - sx0 + 1u, sy0 = ty0 / s;
+            const uint32_t sx0 = tx0 / S, sw = tx1 / S - sx0 + 1u, sy0 = ty0 / S;
+            // (row, column) of the entry in the splat's sw-wide block of
+            // super-tiles: a float quotient, exact after one correction
+            // (local < 2^24)
             const uint32_t local = (uint32_t)(p - pj);
-            const uint32_t sy = local / sw, sx = local - sy * sw;
+            uint32_t sy = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)sw));
+            if (sy * sw > local) --sy;
+            else if ((sy + 1u) * sw <= local) ++sy;
+            const uint32_t sx = local - sy * sw;
             uint32_t key = (uint32_t)sp.super0 + (sy0 + sy) * (uint32_t)V.sx + sx0 + sx;
-            CullShape keep_all;
-            keep_all.mode = 0;
-            const uint32_t m = tile_mask(shapes ? shapes[j] : keep_all, shapes != nullptr, tx0, tx1, ty0, ty1,
-                                         (sx0 + sx) * s, (sy0 + sy) * s, S, tile);
+            const uint32_t bx = (sx0 + sx) * S, by = (sy0 + sy) * S;
+            uint32_t m;
+            if (!shapes || (rf & kRectFull)) {
+                m = tile_mask<TILE>(CullShape{}, false, tx0, tx1, ty0, ty1, bx, by);
+            } else if (rf & kRectShape) {
+                m = tile_mask<TILE>(shapes[j], true, tx0, tx1, ty0, ty1, bx, by);
+            } else {
+                m = span_mask<TILE>(spans + (size_t)j * kSpanRows, ty0, ty1, bx, by);
+            }
             key |= m << 16;
             keys[p] = key;
             vals[p] = (uint32_t)j;
@@ -837,10 +1039,15 @@ __global__ void k_fill_f32(float* p, size_t n, float val) {
 int coarse_count_blocks(int n) { return ceil_div(n, 256); }
 void launch_coarse_count(const uint32_t* sorted_gid, int n, int N, SegLayout sg, const Rec* recs,
                          const ViewParams* views, int v0, int tile, int S, uint32_t* cnt, uint64_t* rect_sorted,
-                         CullShape* shapes, unsigned long long* partials, hipStream_t st) {
+                         CullShape* shapes, uint32_t* spans, unsigned long long* partials, hipStream_t st) {
     if (n == 0) return;
-    k_coarse_count<<<coarse_count_blocks(n), 256, 0, st>>>(sorted_gid, n, N, sg, recs, views, v0, tile, S, cnt,
-                                                           rect_sorted, shapes, partials);
+    const int nb = coarse_count_blocks(n);
+#define H4D_COARSE_COUNT(T) \
+    k_coarse_count<T><<<nb, 256, 0, st>>>(sorted_gid, n, N, sg, recs, views, v0, cnt, rect_sorted, shapes, spans, partials)
+    if (tile == 8) H4D_COARSE_COUNT(8);
+    else if (tile == 16) H4D_COARSE_COUNT(16);
+    else H4D_COARSE_COUNT(32);
+#undef H4D_COARSE_COUNT
 }
 void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* partials, uint64_t ccap, int S,
                            unsigned long long* cbase, int v0, int v1, Status* status, unsigned long long* eff_count,
@@ -855,14 +1062,19 @@ void launch_coarse_offsets(const uint32_t* cnt, int n, unsigned long long* parti
     if (n > 0) k_coarse_down<<<nb, 256, 0, st>>>(cnt, n, partials, nb, offsets, run_start, run_cap);
 }
 void launch_coarse_emit(const unsigned long long* offsets, const uint32_t* run_start, int n, SegLayout sg,
-                        const uint64_t* rect_sorted, const CullShape* shapes, const ViewParams* views, int v0, int tile,
-                        int S, uint64_t capacity, const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals,
-                        hipStream_t st) {
+                        const uint64_t* rect_sorted, const CullShape* shapes, const uint32_t* spans,
+                        const ViewParams* views, int v0, int tile, int S, uint64_t capacity,
+                        const unsigned long long* eff_count, uint32_t* keys, uint32_t* vals, hipStream_t st) {
     if (n == 0 || capacity == 0) return;
     // (32 views of 1M Gaussians in one pass: about 25 runs of 256 entries per workgroup)
     const int nb = (int)std::min<uint64_t>(65536, (capacity + 255) / 256);
-    k_coarse_emit<<<nb, 256, 0, st>>>(offsets, run_start, n, sg, rect_sorted, shapes, views, v0, tile, S, eff_count,
-                                      keys, vals);
+#define H4D_COARSE_EMIT(T) \
+    k_coarse_emit<T><<<nb, 256, 0, st>>>(offsets, run_start, n, sg, rect_sorted, shapes, spans, views, v0, eff_count, \
+                                         keys, vals)
+    if (tile == 8) H4D_COARSE_EMIT(8);
+    else if (tile == 16) H4D_COARSE_EMIT(16);
+    else H4D_COARSE_EMIT(32);
+#undef H4D_COARSE_EMIT
 }
 void launch_ranges(const uint32_t* keys, uint32_t key_mask, const unsigned long long* eff_count,
                    const unsigned long long* base, int64_t* ranges, hipStream_t st) {

@@ -107,7 +107,8 @@ def test_shared_static_binning_workspace(L):
     on a super-tile grid of their own: the state grows by that grid's list
     ranges (16 bytes per super-tile: 128 x 96 pixels at 16-pixel tiles is 2 x 2
     super-tiles of 64 pixels, rounded up to the workspace's 256-byte
-    alignment); the scratch does not grow (its depth sorts are over fewer
+    alignment, or absorbed by the 2 MiB alignment of the per-pixel arrays that
+    follow them); the scratch does not grow (its depth sorts are over fewer
     keys)."""
     c = _ctx(L)
     st, sc = C.c_size_t(), C.c_size_t()
@@ -116,7 +117,7 @@ def test_shared_static_binning_workspace(L):
     s_distinct, k_distinct = st.value, sc.value
     assert c.L.h4dgs_workspace_size(c.h, 3000, 1000, _views(L, 4), 4, C.byref(_cfg(L, batched=1)), C.byref(st),
                                     C.byref(sc)) == 0
-    assert 0 < st.value - s_distinct <= 256 and sc.value <= k_distinct
+    assert 0 <= st.value - s_distinct <= (1 << 21) + 256 and sc.value <= k_distinct
     # no 3D Gaussians: nothing to share
     assert c.L.h4dgs_workspace_size(c.h, 0, 4000, _views(L, 4), 4, C.byref(_cfg(L, batched=1)), C.byref(st),
                                     C.byref(sc)) == 0
