@@ -342,9 +342,25 @@ def batched_leg(h4d, torch, sg, steps: int, warmup: int, forms: str = "both") ->
         out["single_view"] = _single_view_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup, out)
     if forms != "single":
         out["batched_graph"] = _batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup)
+        # the launch configuration the autotuner picks for this call (tiles of
+        # 16 and 32 pixels: 8-pixel tiles split the call into two binning
+        # passes, which gives up the shared static binning), replayed the same
+        # way
+        tuner = h4d.Autotuner(candidates=[(t, c) for t in (16, 32) for c in (64, 128, 256, 512)])
+        tile, chunk = tuner.pick(g3, g4, views, batched=True)
+        tuned = {"pick": {"tile": tile, "chunk": chunk},
+                 "eager_ms": {f"{t}x{c}": round(ms, 3) for (t, c), ms in sorted(tuner.last_timings.items())}}
+        if (tile, chunk) == (h4d.DEFAULT_TILE, h4d.DEFAULT_CHUNK):
+            tuned.update(out["batched_graph"])
+        else:
+            tuned.update(_batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup,
+                                       tile=tile, chunk=chunk))
+        out["batched_graph_autotuned"] = tuned
     if forms != "both":
         return out
     out["speedup"] = round(out["single_view"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3)
+    out["speedup_autotuned"] = round(out["single_view"]["ms_per_step"] /
+                                     out["batched_graph_autotuned"]["ms_per_step"], 3)
     # workload counts of the call (the same lists either way) and the share of
     # the HBM roofline of each form: the batched form reads the parameters once
     # per call, the views one after another once per view
@@ -397,9 +413,11 @@ def _single_view_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps,
     return {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
 
 
-def _batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup) -> dict:
+def _batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup, tile=None,
+                  chunk=None) -> dict:
     """All views in one launch per stage, captured once and replayed."""
-    step = h4d.CapturedStep(h4d.Rasterizer(batched=True), g3, g4, views, targets, (gr3, gr4))
+    rast = h4d.Rasterizer(tile=tile or h4d.DEFAULT_TILE, chunk=chunk or h4d.DEFAULT_CHUNK, batched=True)
+    step = h4d.CapturedStep(rast, g3, g4, views, targets, (gr3, gr4))
     for _ in range(warmup):
         step.replay()
     torch.cuda.synchronize()
@@ -409,7 +427,7 @@ def _batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, war
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     step.verify()
-    del step
+    del step, rast
     torch.cuda.empty_cache()
     return {"ms_per_step": round(dt * 1e3, 3), "mpix_s": round(mpix / dt, 2)}
 
