@@ -43,7 +43,8 @@ LR4 = dict(mean=1.6e-4, mean_t=1.6e-4, log_scale=5e-3, quat_l=1e-3, quat_r=1e-3,
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_train_step_250k_1352x1014.md")
 # the blending kernels as built: their sources and the compile flags
-KERNEL_SOURCES = ("paper_2505_13215_amd/csrc/composite.hip", "paper_2505_13215_amd/csrc/common.hpp",
+KERNEL_SOURCES = ("paper_2505_13215_amd/csrc/composite.hip", "paper_2505_13215_amd/csrc/walk.hpp",
+                  "paper_2505_13215_amd/csrc/common.hpp",
                   "paper_2505_13215_amd/build.py")
 
 

@@ -603,7 +603,7 @@ __host__ __device__ inline uint32_t span_mask(const uint32_t* span_row, uint32_t
 // One entry per thread; each workgroup also leaves its sum of counts for
 // the offsets' scan (partials[blockIdx.x]).
 template <int TILE>
-__global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n, int N,
+__global__ void __launch_bounds__(256, 6) k_coarse_count(const uint32_t* __restrict__ sorted_gid, int n, int N,
                                                       SegLayout sg, const Rec* __restrict__ recs,
                                                       const ViewParams* __restrict__ views, int v0,
                                                       uint32_t* __restrict__ cnt, uint64_t* __restrict__ rect_sorted,
@@ -619,7 +619,6 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
     bool keep = false;
     uint64_t flags = 0ull;
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1, r0 = 0, nrows = 0;
-    CullShape cs;
     if (j < n) {
         const SegPos sp = seg_of(j, sg, views, v0);
         const Rec& rec = recs[(size_t)sp.view * N + sorted_gid[j]];
@@ -629,7 +628,7 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
             tx0 = (int)((d.x & 0xFFFFu) / TILE); tx1 = (int)((d.x >> 16) / TILE);
             ty0 = (int)((d.y & 0xFFFFu) / TILE); ty1 = (int)((d.y >> 16) / TILE);
             if (shapes) {
-                cs = cull_shape(rec);
+                const CullShape cs = cull_shape(rec);
                 if (cs.mode == 0) {
                     flags = kRectFull;
                 } else if (cs.mode == 2) {
@@ -690,7 +689,7 @@ __global__ void __launch_bounds__(256) k_coarse_count(const uint32_t* __restrict
                 tx0 = cmin; tx1 = cmax; ty0 = r0; ty1 = r0 + nrows - 1;
                 if (!table) {
                     flags = kRectShape;
-                    shapes[j] = cs;
+                    shapes[j] = s_cs[tid];
                 }
             }
         }
