@@ -343,6 +343,7 @@ def batched_leg(h4d, torch, sg, steps: int, warmup: int, forms: str = "both") ->
         out["single_view"] = _single_view_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup, out)
     if forms != "single":
         out["batched_graph"] = _batched_form(h4d, torch, g3, g4, views, targets, gr3, gr4, mpix, steps, warmup)
+    if forms == "both":
         # the launch configuration the autotuner picks for this call (tiles of
         # 16 and 32 pixels: 8-pixel tiles split the call into two binning
         # passes, which gives up the shared static binning), replayed the same
