@@ -161,14 +161,18 @@ def test_tile_lists_and_ranges_bit_exact(h4d, tile):
         assert np.array_equal(got, ref_ids[start[t]:start[t + 1]]), t
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_culled_tile_lists_drop_only_tiles_without_blending(h4d, tile):
+@pytest.mark.parametrize("tile,W,H,n,max_radius", [(8, 203, 131, 3000, 40), (16, 203, 131, 3000, 40),
+                                                   (32, 203, 131, 3000, 40), (8, 400, 300, 1200, 150),
+                                                   (16, 640, 480, 800, 300)])
+def test_culled_tile_lists_drop_only_tiles_without_blending(h4d, tile, W, H, n, max_radius):
     """With cull, each tile's list is an order-preserving subset of the
     square-overlap list, every dropped splat stays below alpha = 1/255 at
     every pixel centre of the tile inside its square (checked in FP64), and the
-    image is bit-identical to the unculled one."""
-    W, H = 203, 131
-    rec = sg.synthetic_records(3000, W, H, seed=23, max_radius=40)
+    image is bit-identical to the unculled one.  The larger radii give splats
+    taller than the binning's table of per-row tile spans (more than 16 tile
+    rows), whose tiles are tested per coarse entry."""
+    print(f"[culled lists] tile {tile} {W}x{H} n={n} r<={max_radius}", flush=True)
+    rec = sg.synthetic_records(n, W, H, seed=23, max_radius=max_radius)
     full = h4d.Rasterizer(tile=tile, chunk=128, pair_capacity=1 << 20, cull=False)
     img0, T0, _, _ = h4d.rasterize_splats(full, rec, W, H)
     rast = h4d.Rasterizer(tile=tile, chunk=128, pair_capacity=1 << 20, cull=True)
