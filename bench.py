@@ -558,7 +558,7 @@ def main():
         ", ".join(f"{k} {v:.4f}" for k, v in kernel_ms.items()))
 
     # the same steps without the optimiser (render_fwd + loss gradient +
-    # render_bwd, the fwd+bwd step as the survey defines Mpix/s), reported beside
+    # render_bwd, the fwd+bwd step the Mpix/s metric is defined on), reported beside
     def step_fb(i):
         v = sched[i][0]
         h = rast.forward(g3, g4, [v])
