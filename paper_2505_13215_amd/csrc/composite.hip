@@ -15,8 +15,8 @@
 // pixel as R = dot(dL/dC, C_out), less each blended splat's share in turn.  Each lane sums
 // its pixels in registers; the nine per-splat gradients are reduced across the
 // wave by reduce-scatter (lane-half and row swaps, then DPP row sums; skipped
-// when no lane blended the splat) and added to HBM with one global atomic per
-// (splat, component, wave).  Constant factors of the conic and centre
+// when no lane blended the splat) and added to HBM with one global atomic
+// instruction per (splat, wave), one lane per component.  Constant factors of the conic and centre
 // gradients are applied once per splat after the reduction.  Each wave stops
 // at its own last contributor.
 #include <hip/hip_ext.h>
@@ -396,8 +396,8 @@ __device__ __forceinline__ void wave_sum9(float e0, float e1, float e2, float e3
 }
 
 // Per splat of the tile's list (up to its last contributor), the wave's nine
-// gradient sums (wave_sum9) are added into the splat's g2 record with global
-// atomics by four lanes.
+// gradient sums (wave_sum9) are added into the splat's g2 record with one
+// global atomic instruction (nine lanes, one record).
 // static_rows (MERGE): the gradients of the static list's entries go to the
 // records of the static group's view.
 // (registers for 5 waves per SIMD, what the plain adjoint uses anyway: the
@@ -465,18 +465,20 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     const uint32_t wave_nc = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_nc));
     const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;
-    // after wave_sum9, lanes 0, 16, 32, 48 hold (in h0 and h1) the components
-    // 0 2 1 3 and 4 6 5 7 of g2, lane 0 (in h2) component 8; their constant
-    // factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1.  The
-    // centre and conic sums (h0, and h1 in row 0) also take the splat's
-    // opacity (their per-pixel terms are summed without it): h1's factor is
-    // m1 * opacity + c1.
-    const int row = lane >> 4;
-    const bool lead = (lane & 15) == 0;
+    // after wave_sum9, the lanes of 16-lane row r hold (in h0 and h1) the
+    // components 0 2 1 3 (by row) and 4 6 5 7 of g2, those of row 0 (in h2)
+    // component 8.  One atomic instruction adds all nine to the splat's
+    // record: lane 16 r takes h0, lane 16 r + 1 h1, lane 2 h2.  The constant
+    // factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1; the
+    // centre and conic sums also take the splat's opacity (their per-pixel
+    // terms are summed without it), so a lane's factor is fa * opacity + fb.
+    const int row = lane >> 4, lr = lane & 15;
     const int comp0 = ((row & 1) << 1) | (row >> 1);
+    const bool alane = lr < 2 || lane == 2;
+    const int comp = lr == 0 ? comp0 : (lr == 1 ? 4 + comp0 : 8);
     const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
-    const float m1 = comp0 == 0 ? -0.5f : 0.0f, c1 = comp0 == 0 ? 0.0f : 1.0f;
-    const int off0 = comp0, off1 = 4 + comp0;
+    const float fa = lr == 0 ? fac0 : (lr == 1 && comp0 == 0 ? -0.5f : 0.0f);
+    const float fb = lr == 0 ? 0.0f : (lr == 1 && comp0 == 0 ? 0.0f : 1.0f);
     const int tid = (int)threadIdx.x;
     // the forward kept the list's head: a tile whose contributors all lie in
     // it reads them from there, any other walks its list again
@@ -563,12 +565,11 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
                 // the cross-lane operations need the whole wave: consume their
                 // results here, before the lane-divergent atomics below
                 asm volatile("" ::"v"(h0), "v"(h1), "v"(h2));
-                if (lead) {
+                if (alane) {
                     float* const rec = ((MERGE && (gid & kFromStatic)) ? g2s : g2) +
                                        (size_t)(gid & ~kFromStatic) * kG2Stride;
-                    atomicAdd(rec + off0, h0 * (fac0 * s.op));
-                    atomicAdd(rec + off1, h1 * __builtin_fmaf(m1, s.op, c1));
-                    if (row == 0) atomicAdd(rec + 8, h2);
+                    const float hv = lr == 0 ? h0 : (lr == 1 ? h1 : h2);
+                    atomicAdd(rec + comp, hv * __builtin_fmaf(fa, s.op, fb));
                 }
             }
         };
