@@ -14,7 +14,7 @@
 // a splat enters dL/dalpha only through its dot product with dL/dC, kept per
 // pixel as R = dot(dL/dC, C_out), less each blended splat's share in turn.  Each lane sums
 // its pixels in registers; the nine per-splat gradients are reduced across the
-// wave by reduce-scatter (lane-half and row swaps, then DPP row sums; skipped
+// wave by reduce-scatter (lane-half and row swaps, DPP mirrors, quad sums; skipped
 // when no lane blended the splat) and added to HBM with one global atomic
 // instruction per (splat, wave), one lane per component.  Constant factors of the conic and centre
 // gradients are applied once per splat after the reduction.  Each wave stops
@@ -371,28 +371,32 @@ __device__ __forceinline__ float swap16_add(float a, float b) {
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-// Sum over the 16 lanes of each row, in every lane of the row: quad xor 1,
-// quad xor 2, half-row mirror, row mirror.
-__device__ __forceinline__ float row_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
-    return v;
-}
-
 // Wave sums of nine values by reduce-scatter: after two swap levels three
-// registers hold, per 16-lane row, one value summed over 4 lanes; a row sum
-// completes them.  Result layout (rows 0..3):
-//   h0: e0, e2, e1, e3    h1: e4, e6, e5, e7    h2: e8 (row 0 only)
-__device__ __forceinline__ void wave_sum9(float e0, float e1, float e2, float e3, float e4, float e5, float e6,
-                                          float e7, float e8, float& h0, float& h1, float& h2) {
+// registers hold, per 16-lane row, one value summed over 4 lanes (e0 e2 e1 e3,
+// e4 e6 e5 e7 by row, and e8 in row 0); two more levels inside the rows
+// (mirror, half-row mirror) leave one register, whose quad sums finish the
+// row sums.  Result layout in each row r: lanes 0-3 the row's first value (e0
+// e2 e1 e3 for r = 0 1 2 3), lanes 8-11 its second (e4 e6 e5 e7), lanes 4-7
+// (row 0) e8.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum9(float e0, float e1, float e2, float e3, float e4, float e5, float e6,
+                                           float e7, float e8) {
     const float f0 = swap32_add(e0, e1), f1 = swap32_add(e2, e3), f2 = swap32_add(e4, e5), f3 = swap32_add(e6, e7);
     const float f4 = swap32_add(e8, 0.0f);
     const float g0 = swap16_add(f0, f1), g1 = swap16_add(f2, f3), g2 = swap16_add(f4, 0.0f);
-    h0 = row_sum(g0);
-    h1 = row_sum(g1);
-    h2 = row_sum(g2);
+    const int lane = __lane_id();
+    const bool lo = (lane & 8) == 0, q = (lane & 4) == 0;
+    // row mirror: lanes 0-7 pair g0 with lanes 15-8, lanes 8-15 g1; g2 in all
+    const float x = (lo ? g0 : g1) + dpp_f<0x140>(lo ? g1 : g0);
+    const float y = g2 + dpp_f<0x140>(g2);
+    // half-row mirror: lanes 0-3 (8-11) pair x with lanes 7-4 (15-12), lanes 4-7 (12-15) y
+    float z = (q ? x : y) + dpp_f<0x141>(q ? y : x);
+    z += dpp_f<0x4E>(z);  // quad lane ^ 2
+    z += dpp_f<0xB1>(z);  // quad lane ^ 1
+    return z;
 }
 
 // Per splat of the tile's list (up to its last contributor), the wave's nine
@@ -465,20 +469,19 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     const uint32_t wave_nc = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_nc));
     const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;
-    // after wave_sum9, the lanes of 16-lane row r hold (in h0 and h1) the
-    // components 0 2 1 3 (by row) and 4 6 5 7 of g2, those of row 0 (in h2)
-    // component 8.  One atomic instruction adds all nine to the splat's
-    // record: lane 16 r takes h0, lane 16 r + 1 h1, lane 2 h2.  The constant
-    // factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1; the
-    // centre and conic sums also take the splat's opacity (their per-pixel
+    // after wave_sum9, lane 16 r holds component 0 2 1 3 (r = 0 1 2 3) of g2,
+    // lane 16 r + 8 component 4 6 5 7, lane 4 component 8.  One atomic
+    // instruction of these nine lanes adds them to the splat's record.  The
+    // constant factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1;
+    // the centre and conic sums also take the splat's opacity (their per-pixel
     // terms are summed without it), so a lane's factor is fa * opacity + fb.
     const int row = lane >> 4, lr = lane & 15;
     const int comp0 = ((row & 1) << 1) | (row >> 1);
-    const bool alane = lr < 2 || lane == 2;
-    const int comp = lr == 0 ? comp0 : (lr == 1 ? 4 + comp0 : 8);
+    const bool alane = lr == 0 || lr == 8 || lane == 4;
+    const int comp = lr == 0 ? comp0 : (lr == 8 ? 4 + comp0 : 8);
     const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
-    const float fa = lr == 0 ? fac0 : (lr == 1 && comp0 == 0 ? -0.5f : 0.0f);
-    const float fb = lr == 0 ? 0.0f : (lr == 1 && comp0 == 0 ? 0.0f : 1.0f);
+    const float fa = lr == 0 ? fac0 : (lr == 8 && comp0 == 0 ? -0.5f : 0.0f);
+    const float fb = lr == 0 ? 0.0f : (lr == 8 && comp0 == 0 ? 0.0f : 1.0f);
     const int tid = (int)threadIdx.x;
     // the forward kept the list's head: a tile whose contributors all lie in
     // it reads them from there, any other walks its list again
@@ -560,16 +563,14 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
             const float e1 = __builtin_fmaf(s.qb, A, qc2 * sdy);
             const float e2 = c.dx * A, e3 = c.dx * sdy, e4 = syy;
             if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
-                float h0, h1, h2;
-                wave_sum9(e0, e1, e2, e3, e4, e5, e6, e7, e8, h0, h1, h2);
+                const float h = wave_sum9(e0, e1, e2, e3, e4, e5, e6, e7, e8);
                 // the cross-lane operations need the whole wave: consume their
-                // results here, before the lane-divergent atomics below
-                asm volatile("" ::"v"(h0), "v"(h1), "v"(h2));
+                // result here, before the lane-divergent atomic below
+                asm volatile("" ::"v"(h));
                 if (alane) {
                     float* const rec = ((MERGE && (gid & kFromStatic)) ? g2s : g2) +
                                        (size_t)(gid & ~kFromStatic) * kG2Stride;
-                    const float hv = lr == 0 ? h0 : (lr == 1 ? h1 : h2);
-                    atomicAdd(rec + comp, hv * __builtin_fmaf(fa, s.op, fb));
+                    atomicAdd(rec + comp, h * __builtin_fmaf(fa, s.op, fb));
                 }
             }
         };
