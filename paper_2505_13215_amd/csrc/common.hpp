@@ -89,13 +89,15 @@ struct SegLayout {
 };
 
 // Screen-space gradients of one (view, Gaussian) from the blending adjoint:
-// du dv dQ00 dQ01 dQ11 dop dr dg db (conic entries unscaled, Q01 counted once),
-// padded to one 64-byte record so that a splat's nine atomic additions touch a
-// single cache line.  Layout [view][N][kG2Stride].  The forward zeroes the
-// records of its on-screen (view, Gaussian) pairs; with shared static
-// binning and no statistics wanted, the views of a static group add their 3D
-// gradients into the records of the group's view.
+// du dv dQ00 dQ01 dQ11 dop dr dg (conic entries unscaled, Q01 counted once)
+// and db as four parts (slots 8-11, one per 16-lane row of the adjoint's
+// reduction; their sum is db), padded to one 64-byte record so that a splat's
+// atomic additions touch a single cache line.  Layout [view][N][kG2Stride].
+// The forward zeroes the records of its on-screen (view, Gaussian) pairs; with
+// shared static binning and no statistics wanted, the views of a static group
+// add their 3D gradients into the records of the group's view.
 constexpr int kG2Stride = 16;
+constexpr int kG2Slots = 12;
 
 // Per-view device pointers passed by value to the batched kernels.
 struct PtrTable {

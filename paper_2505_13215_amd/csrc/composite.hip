@@ -16,7 +16,7 @@
 // its pixels in registers; the nine per-splat gradients are reduced across the
 // wave by reduce-scatter (lane-half and row swaps, DPP mirrors, quad sums; skipped
 // when no lane blended the splat) and added to HBM with one global atomic
-// instruction per (splat, wave), one lane per component.  Constant factors of the conic and centre
+// instruction per (splat, wave), a lane per record slot.  Constant factors of the conic and centre
 // gradients are applied once per splat after the reduction.  Each wave stops
 // at its own last contributor.
 #include <hip/hip_ext.h>
@@ -371,13 +371,13 @@ __device__ __forceinline__ float swap16_add(float a, float b) {
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-// Wave sums of nine values by reduce-scatter: after two swap levels three
-// registers hold, per 16-lane row, one value summed over 4 lanes (e0 e2 e1 e3,
-// e4 e6 e5 e7 by row, and e8 in row 0); two more levels inside the rows
-// (mirror, half-row mirror) leave one register, whose quad sums finish the
-// row sums.  Result layout in each row r: lanes 0-3 the row's first value (e0
-// e2 e1 e3 for r = 0 1 2 3), lanes 8-11 its second (e4 e6 e5 e7), lanes 4-7
-// (row 0) e8.
+// Wave sums of nine values by reduce-scatter: after two swap levels two
+// registers hold, per 16-lane row, one value summed over 4 lanes (e0 e2 e1 e3
+// and e4 e6 e5 e7 by row); two more levels inside the rows (mirror, half-row
+// mirror, the second also taking e8) leave one register, whose quad sums
+// finish the row sums.  Result layout in each row r: lanes 0-3 the row's first
+// value (e0 e2 e1 e3 for r = 0 1 2 3), lanes 8-11 its second (e4 e6 e5 e7),
+// lanes 4-7 the row's part of e8 (the sum of e8 over its 16 lanes).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
@@ -385,13 +385,12 @@ __device__ __forceinline__ float dpp_f(float v) {
 __device__ __forceinline__ float wave_sum9(float e0, float e1, float e2, float e3, float e4, float e5, float e6,
                                            float e7, float e8) {
     const float f0 = swap32_add(e0, e1), f1 = swap32_add(e2, e3), f2 = swap32_add(e4, e5), f3 = swap32_add(e6, e7);
-    const float f4 = swap32_add(e8, 0.0f);
-    const float g0 = swap16_add(f0, f1), g1 = swap16_add(f2, f3), g2 = swap16_add(f4, 0.0f);
+    const float g0 = swap16_add(f0, f1), g1 = swap16_add(f2, f3);
     const int lane = __lane_id();
     const bool lo = (lane & 8) == 0, q = (lane & 4) == 0;
-    // row mirror: lanes 0-7 pair g0 with lanes 15-8, lanes 8-15 g1; g2 in all
+    // row mirror: lanes 0-7 pair g0 with lanes 15-8, lanes 8-15 g1; e8 in all
     const float x = (lo ? g0 : g1) + dpp_f<0x140>(lo ? g1 : g0);
-    const float y = g2 + dpp_f<0x140>(g2);
+    const float y = e8 + dpp_f<0x140>(e8);
     // half-row mirror: lanes 0-3 (8-11) pair x with lanes 7-4 (15-12), lanes 4-7 (12-15) y
     float z = (q ? x : y) + dpp_f<0x141>(q ? y : x);
     z += dpp_f<0x4E>(z);  // quad lane ^ 2
@@ -401,7 +400,7 @@ __device__ __forceinline__ float wave_sum9(float e0, float e1, float e2, float e
 
 // Per splat of the tile's list (up to its last contributor), the wave's nine
 // gradient sums (wave_sum9) are added into the splat's g2 record with one
-// global atomic instruction (nine lanes, one record).
+// global atomic instruction (twelve lanes, one record).
 // static_rows (MERGE): the gradients of the static list's entries go to the
 // records of the static group's view.
 // (registers for 5 waves per SIMD, what the plain adjoint uses anyway: the
@@ -470,15 +469,17 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;
     // after wave_sum9, lane 16 r holds component 0 2 1 3 (r = 0 1 2 3) of g2,
-    // lane 16 r + 8 component 4 6 5 7, lane 4 component 8.  One atomic
-    // instruction of these nine lanes adds them to the splat's record.  The
+    // lane 16 r + 8 component 4 6 5 7, lane 16 r + 4 row r's part of
+    // component 8, which goes to slot 8 + r of the record (the four parts are
+    // summed where the record is read).  One atomic instruction of these
+    // twelve lanes adds them to the splat's record, no two to one address.  The
     // constant factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1;
     // the centre and conic sums also take the splat's opacity (their per-pixel
     // terms are summed without it), so a lane's factor is fa * opacity + fb.
     const int row = lane >> 4, lr = lane & 15;
     const int comp0 = ((row & 1) << 1) | (row >> 1);
-    const bool alane = lr == 0 || lr == 8 || lane == 4;
-    const int comp = lr == 0 ? comp0 : (lr == 8 ? 4 + comp0 : 8);
+    const bool alane = lr == 0 || lr == 4 || lr == 8;
+    const int comp = lr == 0 ? comp0 : (lr == 8 ? 4 + comp0 : 8 + row);
     const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
     const float fa = lr == 0 ? fac0 : (lr == 8 && comp0 == 0 ? -0.5f : 0.0f);
     const float fb = lr == 0 ? 0.0f : (lr == 8 && comp0 == 0 ? 0.0f : 1.0f);

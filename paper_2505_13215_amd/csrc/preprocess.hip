@@ -352,8 +352,8 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
 // Backward kernel: one thread per Gaussian, looping over the views of the call
 // (no atomics: every view's contribution to a Gaussian lands in one lane).
 // g2: per (view, Gaussian) screen-space gradients from the blending adjoint,
-// layout [view][N][kG2Stride]: du dv dQ00 dQ01 dQ11 dop dr dg db (w.r.t. the
-// unscaled conic entries, Q01 counted once).
+// layout [view][N][kG2Stride]: du dv dQ00 dQ01 dQ11 dop dr dg, then db as
+// four parts (w.r.t. the unscaled conic entries, Q01 counted once).
 //
 // Per view the projection adjoint gives mu_c-bar, Sigma_c-bar and op-bar; the
 // slicing adjoint maps them to the spatial/temporal means and to the symmetric
@@ -370,7 +370,8 @@ __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const Proj
     const double gu = g2[0], gv = g2[gstride], gQa = g2[2 * gstride], gQb = g2[3 * gstride],
                  gQc = g2[4 * gstride];
     gop = g2[5 * gstride];
-    const double grgb[3] = {g2[6 * gstride], g2[7 * gstride], g2[8 * gstride]};
+    const double grgb[3] = {g2[6 * gstride], g2[7 * gstride],
+                            (double)g2[8 * gstride] + g2[9 * gstride] + g2[10 * gstride] + g2[11 * gstride]};
     // colour
     double Y[16], raw[3];
     sh_eval(p.dir[0], p.dir[1], p.dir[2], Y);
@@ -621,8 +622,8 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
         if (recs[(size_t)v * N + gidx].d.w == 0u) continue;  // covers no pixel in this camera
         // (a view alone, or the group's sum already in its record: that record
         // as it is; otherwise the members' records summed here)
-        float e[9];
-        for (int k = 0; k < 9; ++k) e[k] = 0.f;
+        float e[kG2Slots];
+        for (int k = 0; k < kG2Slots; ++k) e[k] = 0.f;
         const float* direct = nullptr;
         if (static_rows || V.static_next < 0) {
             direct = g2 + ((size_t)v * N + gidx) * kG2Stride;
@@ -637,7 +638,7 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
                 stat_g += ndc_grad_norm(g[0], g[1], views[u].W, views[u].H);
                 ++stat_n;
             }
-            for (int k = 0; k < 9; ++k) e[k] += g[k];
+            for (int k = 0; k < kG2Slots; ++k) e[k] += g[k];
         }
         ProjF p;
         project(V, w, p);
