@@ -179,8 +179,8 @@ struct FwdWaves {
 // Pulls the next chunk of the tile's list (up to `need` entries) into s_ids and
 // its length into *s_cnt; called by the first wave only.
 template <bool MERGE, int CHUNK>
-__device__ __forceinline__ void walk_chunk(TileWalk<MERGE>& walk, WalkQueues& q, uint32_t* s_ids, int* s_cnt,
-                                           int need) {
+__device__ __forceinline__ int walk_chunk(TileWalk<MERGE>& walk, WalkQueues& q, uint32_t* s_ids, int* s_cnt,
+                                          int need) {
     const int lane = __lane_id();
     int cnt = 0;
     for (int c0 = 0; c0 < need; c0 += 64) {
@@ -191,6 +191,7 @@ __device__ __forceinline__ void walk_chunk(TileWalk<MERGE>& walk, WalkQueues& q,
         if (got < min(64, need - c0)) break;  // the list ended (wave-uniform)
     }
     if (lane == 0) *s_cnt = cnt;
+    return cnt;
 }
 
 // MERGE: the tile's list merges the static group's 3D list with the view's 4D
@@ -202,10 +203,14 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
     float* __restrict__ Cout, uint32_t* __restrict__ tcost, uint32_t* __restrict__ thist, uint32_t* __restrict__ tids,
     unsigned long long* counters) {
     constexpr int NT = ShapeF<B, SPLIT>::NT, PPL = ShapeF<B, SPLIT>::PPL;
+    // two waves per tile: wave 0 walks the next chunk's entries while wave 1
+    // stages the current chunk's records (the ids double-buffered); one wave
+    // walks and then stages
+    constexpr bool AHEAD = NT > 64;
     __shared__ LSplat s_sp[CHUNK];
-    __shared__ uint32_t s_ids[CHUNK];
+    __shared__ uint32_t s_ids[AHEAD ? 2 : 1][CHUNK];
     __shared__ WalkQueues s_q;
-    __shared__ int s_cnt;
+    __shared__ int s_cnt[2];
     __shared__ uint32_t s_cost;
     const int gt = views[v0].tile_base + dispatch_tile(order);
     const int view = find_view_of_tile(views, v0, v1, gt);
@@ -240,18 +245,32 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
     // masked), so that its per-pixel flags stay lane masks
     bool wave_done = __ballot(!lane_done) == 0ull;
     const int tid = (int)threadIdx.x;
-    uint32_t rel0 = 0;  // list position of the chunk's first entry
+    uint32_t rel0 = 0;    // list position of the chunk's first entry
+    uint32_t walked = 0;  // entries walked (wave 0)
+    int cur = 0;          // the chunk's id buffer
+    if (AHEAD && tid < 64) walked += (uint32_t)walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids[0], &s_cnt[0], CHUNK);
     for (;;) {
         if (__syncthreads_count(wave_done) == NT) break;
-        if (tid < 64) walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids, &s_cnt, CHUNK);
-        __syncthreads();
-        const int cnt = s_cnt;
+        if (!AHEAD) {
+            if (tid < 64) walked += (uint32_t)walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids[0], &s_cnt[0], CHUNK);
+            __syncthreads();
+        }
+        const int cnt = s_cnt[cur];
         if (cnt == 0) break;  // uniform: the list is exhausted
-        for (int k = tid; k < cnt; k += NT) {
-            const uint32_t raw = s_ids[k];
-            stage_splat(walk.record(raw), raw & ~kFromStatic, ty * B, ty * B + B - 1, s_sp[k]);
-            // the list's head, kept for the adjoint
-            if (tids && rel0 + (uint32_t)k < (uint32_t)kTileIds) tids[(size_t)gt * kTileIds + rel0 + k] = raw;
+        if (AHEAD && tid < 64) {
+            if (cnt == CHUNK) {
+                walked += (uint32_t)walk_chunk<MERGE, CHUNK>(walk, s_q, s_ids[cur ^ 1], &s_cnt[cur ^ 1], CHUNK);
+            } else if (tid == 0) {
+                s_cnt[cur ^ 1] = 0;  // the list ended inside this chunk
+            }
+        } else {
+            constexpr int NS = AHEAD ? NT - 64 : NT;  // staging threads
+            for (int k = AHEAD ? tid - 64 : tid; k < cnt; k += NS) {
+                const uint32_t raw = s_ids[cur][k];
+                stage_splat(walk.record(raw), raw & ~kFromStatic, ty * B, ty * B + B - 1, s_sp[k]);
+                // the list's head, kept for the adjoint
+                if (tids && rel0 + (uint32_t)k < (uint32_t)kTileIds) tids[(size_t)gt * kTileIds + rel0 + k] = raw;
+            }
         }
         __syncthreads();
         if (!wave_done) {
@@ -295,6 +314,7 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
             }
         }
         rel0 += (uint32_t)cnt;
+        if (AHEAD) cur ^= 1;
     }
     const size_t HW = (size_t)V.W * V.H;
 #pragma unroll
@@ -343,7 +363,7 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
     }
     if (STATS && threadIdx.x < 64) {
         // the tile's list length: the entries walked and those left
-        const unsigned long long len = (unsigned long long)rel0 + walk.remaining();
+        const unsigned long long len = (unsigned long long)walked + walk.remaining();
         if (threadIdx.x == 0) {
             atomicAdd(&counters[4], len);
             atomicAdd(&counters[5], (unsigned long long)tile_last);
