@@ -150,7 +150,24 @@ int bits_for(int n) {
 constexpr int kDepthDigitBits = 8;
 constexpr int kDepthSortItems = 2;  // 512 keys per block: ~500 blocks for 250k Gaussians
 int n_passes_for(int bits, int width) { return (bits + width - 1) / width; }
-int pass_bits(int bits, int width) { return (bits + n_passes_for(bits, width) - 1) / n_passes_for(bits, width); }
+// Digit width of pass p (shift bits done) of the super-tile sort over `bits`
+// bits: an even split, except that of two passes the first (over the low,
+// evenly spread bits) takes two bits fewer than the second, so that its
+// scatter writes runs of twice the length per digit.
+int coarse_pass_bits(int bits, int p, int shift) {
+    const int passes = n_passes_for(bits, kMaxRadixBits);
+    if (passes == 2 && p == 0) return bits / 2 - 1;
+    return (bits - shift + (passes - p) - 1) / (passes - p);
+}
+int coarse_max_bits(int bits) {
+    int m = 0;
+    for (int p = 0, shift = 0; shift < bits; ++p) {
+        const int nb = coarse_pass_bits(bits, p, shift);
+        m = std::max(m, nb);
+        shift += nb;
+    }
+    return m;
+}
 
 // One pass of binning + blending covers the views [v0, v1): every view alone
 // (views processed one after another), or as many of the call's views as the
@@ -343,7 +360,7 @@ Layout make_layout(int N, int n3, const h4d_view* views, int V, const h4d_config
     // 6-bit passes)
     int cbits = 1;
     for (int k = 0; k < L.n_passes(); ++k)
-        cbits = std::max(cbits, pass_bits(bits_for(L.pass(k).supers), kMaxRadixBits));
+        cbits = std::max(cbits, coarse_max_bits(bits_for(L.pass(k).supers)));
     // the depth sort's segments: a pass's views (all Gaussians, or the 4D ones
     // when shared) and the static groups (3D ones)
     size_t dwords = radix_hist_words(n, max_views, kDepthDigitBits, kDepthSortItems);
@@ -418,7 +435,7 @@ bool plan_fits(const Layout& L) {
         const int bits = bits_for(P.supers);
         const int cp = n_passes_for(bits, kMaxRadixBits);
         for (int p = 0, shift = 0; p < cp; ++p) {
-            const int nb = (bits - shift + (cp - p) - 1) / (cp - p);
+            const int nb = coarse_pass_bits(bits, p, shift);
             if (!radix_pass_fits(L.ccap, 1, nb, kSortItems, L.hist_words, L.totals_words)) return false;
             shift += nb;
         }
@@ -626,7 +643,7 @@ bool bin_pass(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int cull, vo
     const bool drop = L.ccap > 0;  // (the first pass writes the kept count whenever it runs)
     unsigned long long* ceff = drop ? at<unsigned long long>(scratch, L.sc_ceff) : eff_c;  // entries kept
     for (int p = 0; p < passes; ++p) {
-        const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
+        const int nb = coarse_pass_bits(bits, p, shift);
         const bool last = p == passes - 1;
         uint32_t* kout = last ? ckeys : (kin == pk ? pk2 : pk);
         uint32_t* vout = last ? cvals : (vin == pv ? pv2 : pv);
