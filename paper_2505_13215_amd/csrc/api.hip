@@ -406,6 +406,13 @@ struct DepthJob {
     int n_seg;
     int len;
 };
+// Keys per thread of a depth-sort job: two (more, smaller blocks) for short
+// key sets, which are latency-bound; kSortItems from 2^21 keys on, where the
+// longer digit runs of 2048-key blocks coalesce the scatter (32 views of 1M
+// Gaussians: 0.89 -> 0.60 ms; 250k keys: 0.068 -> 0.083 ms with them).
+int depth_items(const DepthJob& j) {
+    return (uint64_t)j.len * (uint64_t)j.n_seg >= (1ull << 21) ? kSortItems : kDepthSortItems;
+}
 int depth_jobs(const Layout& L, const Pass& P, DepthJob* jobs) {
     const int nv = P.v1 - P.v0;
     int n = 0;
@@ -427,7 +434,7 @@ bool plan_fits(const Layout& L) {
         for (int q = 0; q < nj; ++q)
             for (int p = 0, shift = 0; p < passes; ++p) {
                 const int nb = (32 - shift + (passes - p) - 1) / (passes - p);
-                if (!radix_pass_fits((uint64_t)jobs[q].len, jobs[q].n_seg, nb, kDepthSortItems, L.hist_words,
+                if (!radix_pass_fits((uint64_t)jobs[q].len, jobs[q].n_seg, nb, depth_items(jobs[q]), L.hist_words,
                                      L.totals_words))
                     return false;
                 shift += nb;
@@ -592,7 +599,7 @@ bool bin_pass(h4d_ctx* c, const Layout& L, const Pass& P, int tile, int cull, vo
                 if (!launch_radix_pass(dk + o, dv + o, dk2 + o, dv2 + o, nullptr, (uint64_t)jobs[q].len,
                                        (uint64_t)jobs[q].len, shift, nb, hist, L.hist_words, totals, L.totals_words,
                                        nullptr, st, jobs[q].n_seg, (uint64_t)jobs[q].len, nullptr, 0,
-                                       kDepthSortItems))
+                                       depth_items(jobs[q])))
                     return false;
             }
             std::swap(dk, dk2);
