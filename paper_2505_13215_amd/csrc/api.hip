@@ -407,11 +407,12 @@ struct DepthJob {
     int len;
 };
 // Keys per thread of a depth-sort job: two (more, smaller blocks) for short
-// key sets, which are latency-bound; kSortItems from 2^21 keys on, where the
-// longer digit runs of 2048-key blocks coalesce the scatter (32 views of 1M
-// Gaussians: 0.89 -> 0.60 ms; 250k keys: 0.068 -> 0.083 ms with them).
+// key sets, which are latency-bound; kSortItems from 2^19 keys on, where the
+// longer digit runs of 2048-key blocks coalesce the scatter (one view of 1M
+// Gaussians: 0.121 -> 0.100 ms; 32 views of 1M batched: 0.89 -> 0.60 ms;
+// 250k keys: 0.068 -> 0.083 ms with them).
 int depth_items(const DepthJob& j) {
-    return (uint64_t)j.len * (uint64_t)j.n_seg >= (1ull << 21) ? kSortItems : kDepthSortItems;
+    return (uint64_t)j.len * (uint64_t)j.n_seg >= (1ull << 19) ? kSortItems : kDepthSortItems;
 }
 int depth_jobs(const Layout& L, const Pass& P, DepthJob* jobs) {
     const int nv = P.v1 - P.v0;
