@@ -51,9 +51,12 @@ __device__ __forceinline__ void stage_splat(const Rec& r, uint32_t gid, int row0
     const uint32_t y0 = r.d.y & 0xFFFFu, y1 = r.d.y >> 16;
     s.ry = r.d.y | ((y0 <= (uint32_t)row0 && y1 >= (uint32_t)row1) ? kRowsIn : 0u);
     s.ui = r.c.y; s.uf = r.a.x; s.vi = r.c.z; s.vf = r.a.y;
-    s.qa = r.a.z; s.qb = r.a.w; s.qc = r.b.x; s.op = r.b.y;
+    // qc < 0 for every conic (the dilated covariance is positive definite);
+    // the bound keeps it below zero where a vast splat's value would round to
+    // -0, so that a finished pixel's infinite row offset still gives power -inf
+    s.qa = r.a.z; s.qb = r.a.w; s.qc = __builtin_fminf(r.b.x, -1.17549435e-38f); s.op = r.b.y;
     s.cr = r.b.z; s.cg = r.b.w; s.cb = r.c.x;
-    s.qa2 = 2.0f * r.a.z; s.qc2 = 2.0f * r.b.x;
+    s.qa2 = 2.0f * r.a.z; s.qc2 = 2.0f * s.qc;
 }
 
 // (y0, y1 as stored: only meaningful when the rows-in flag is clear)
@@ -89,20 +92,55 @@ __device__ __forceinline__ unsigned long long rows_in_mask(const LSplat* sp, int
     return __ballot(lane < n && (sp[g0 + lane].ry & kRowsIn) != 0u);
 }
 
+// First position at or after j whose bit in m is set, or n (n <= 64).
+__device__ __forceinline__ int next_set(unsigned long long m, int j, int n) {
+    if (j >= n) return n;
+    const unsigned long long r = m >> j;
+    return r ? min(n, j + (int)__builtin_ctzll(r)) : n;
+}
+
 // Calls step(j, tag) for j = 0 .. n-1 in order, tag = std::true_type where bit j
 // of rin is set, else std::false_type; stops early (returning true) when step
-// returns true.  Runs of equal flags go through their own loop, so that the
-// loop-carried pixel state stays in place across each run.
+// returns true.  Runs of equal flags go through their own counted loop (the
+// run's end found once, from the mask), so that the loop-carried pixel state
+// stays in place across each run and a step pays no mask test.
 template <class F>
 __device__ __forceinline__ bool walk_runs(unsigned long long rin, int n, F&& step) {
     int j = 0;
     while (j < n) {
-        for (; j < n && ((rin >> j) & 1ull); ++j)
+        for (const int e = next_set(~rin, j, n); j < e; ++j)
             if (step(j, std::true_type{})) return true;
-        for (; j < n && !((rin >> j) & 1ull); ++j)
+        for (const int e = next_set(rin, j, n); j < e; ++j)
             if (step(j, std::false_type{})) return true;
     }
     return false;
+}
+
+// Splats whose opacity lies below this never reach the 0.99 clamp: every pair
+// that passes the power test has G = exp2(power) <= 1 (up to the exp2
+// rounding, which the margin covers), so alpha = opacity * G < 0.99.
+constexpr float kClampOp = 0.98f;
+
+// Opacity flags of the staged splats [g0, g0 + n) (bit i: splat g0 + i may
+// reach the clamp).
+__device__ __forceinline__ unsigned long long clamp_mask(const LSplat* sp, int g0, int n) {
+    const int lane = __lane_id();
+    return __builtin_amdgcn_ballot_w64(lane < n && sp[g0 + lane].op >= kClampOp);
+}
+
+// The adjoint's walk: calls step(j, tag) for j = 0 .. n-1 in order, tag =
+// std::integral_constant<int, f> with bit 0 of f set where bit j of rin is, bit
+// 1 where bit j of clp is; each run of equal flags goes through its own counted
+// loop.
+template <class F>
+__device__ __forceinline__ void walk_runs2(unsigned long long rin, unsigned long long clp, int n, F&& step) {
+    int j = 0;
+    while (j < n) {
+        for (const int e = next_set(~rin | clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 1>{});
+        for (const int e = next_set(rin | clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 0>{});
+        for (const int e = next_set(~rin | ~clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 3>{});
+        for (const int e = next_set(rin | ~clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 2>{});
+    }
 }
 
 // Square test of one pixel: its column (c.inx) and, unless the square holds
@@ -224,8 +262,11 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
     const int px = tx * B + (int)threadIdx.x % B;
     const float pxc = (float)px + 0.5f;
     int py[PPL];
-    // T > 0: the pixel is live; a finished pixel keeps its final transmittance
-    // as -T (pixels outside the image start finished)
+    // A finished pixel (and one outside the image) has its row centre pyc at
+    // +inf: its offset dy to any splat is +inf, the power -inf (the scaled
+    // conic entry qc is negative), so that no later pair passes the blending
+    // test and the pixel needs no test of its own; T keeps its final
+    // transmittance.
     float pyc[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
     uint32_t last[PPL];
     bool lane_done = true;
@@ -233,9 +274,9 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
     for (int k = 0; k < PPL; ++k) {
         const int p = (int)threadIdx.x + k * NT;
         py[k] = ty * B + p / B;
-        pyc[k] = (float)py[k] + 0.5f;
         const bool inside = px < V.W && py[k] < V.H;
-        T[k] = inside ? 1.0f : -1.0f;
+        pyc[k] = inside ? (float)py[k] + 0.5f : __builtin_inff();
+        T[k] = 1.0f;
         cr[k] = cg[k] = cb[k] = 0.f;
         last[k] = 0u;
         lane_done = lane_done && !inside;
@@ -280,30 +321,37 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
                 constexpr bool RI = decltype(rows_tag)::value;
                 const Splat s = to_splat(s_sp[j]);
                 const ColTerm c = eval_col(s, px, pxc);
-                bool all = true;
+                // lanes with a pixel whose transmittance would fall below the
+                // floor: a pixel finishes only at such a step
+                unsigned long long near = 0ull;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
                     float dy, G, alpha;
                     bool clamped;
-                    const bool live = T[k] > 0.0f;
                     const bool in = square_test<RI>(s, c, py[k]);
-                    const bool ok = eval_pix(s, c, in, pyc[k], dy, G, alpha, clamped) && live;
+                    const bool ok = eval_pix(s, c, in, pyc[k], dy, G, alpha, clamped);  // (false once finished)
                     const float Tn = next_T(T[k], alpha);
-                    const bool stop = ok && Tn < kMinT;
+                    const bool low = Tn < kMinT;
+                    near |= __builtin_amdgcn_ballot_w64(low);
+                    const bool stop = ok && low;
                     const bool bl = ok && !stop;
                     const float w = bl ? alpha * T[k] : 0.0f;
                     cr[k] = __builtin_fmaf(s.cr, w, cr[k]);
                     cg[k] = __builtin_fmaf(s.cg, w, cg[k]);
                     cb[k] = __builtin_fmaf(s.cb, w, cb[k]);
-                    T[k] = bl ? Tn : (stop ? -T[k] : T[k]);
-                    last[k] = bl ? rel0 + (uint32_t)j + 1u : last[k];
                     if (STATS) {
-                        n_eval += (live && in) ? 1u : 0u;
+                        n_eval += (pyc[k] < __builtin_inff() && in) ? 1u : 0u;
                         n_blend += bl ? 1u : 0u;
                     }
-                    all = all && !(live && !stop);
+                    T[k] = bl ? Tn : T[k];
+                    pyc[k] = stop ? __builtin_inff() : pyc[k];
+                    last[k] = bl ? rel0 + (uint32_t)j + 1u : last[k];
                 }
-                return __ballot(!all) == 0ull;
+                if (near == 0ull) return false;  // wave-uniform: no pixel finished here
+                bool act = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) act = act || pyc[k] < __builtin_inff();
+                return __ballot(act) == 0ull;
             };
             // splats whose square holds all of the tile's rows take the step
             // without the row test
@@ -321,7 +369,7 @@ __global__ void __launch_bounds__((ShapeF<B, SPLIT>::NT), (FwdWaves<B, SPLIT, ME
     for (int k = 0; k < PPL; ++k) {
         if (px < V.W && py[k] < V.H) {
             const size_t p = (size_t)py[k] * V.W + px;
-            const float Tk = __builtin_fabsf(T[k]);
+            const float Tk = T[k];
             const float o0 = __builtin_fmaf(Tk, V.bg[0], cr[k]), o1 = __builtin_fmaf(Tk, V.bg[1], cg[k]),
                         o2 = __builtin_fmaf(Tk, V.bg[2], cb[k]);
             image[p] = o0;
@@ -406,13 +454,25 @@ __device__ __forceinline__ float wave_sum9(float e0, float e1, float e2, float e
                                            float e7, float e8) {
     const float f0 = swap32_add(e0, e1), f1 = swap32_add(e2, e3), f2 = swap32_add(e4, e5), f3 = swap32_add(e6, e7);
     const float g0 = swap16_add(f0, f1), g1 = swap16_add(f2, f3);
-    const int lane = __lane_id();
-    const bool lo = (lane & 8) == 0, q = (lane & 4) == 0;
-    // row mirror: lanes 0-7 pair g0 with lanes 15-8, lanes 8-15 g1; e8 in all
-    const float x = (lo ? g0 : g1) + dpp_f<0x140>(lo ? g1 : g0);
+    // row mirror: lanes 0-7 pair g0 with lanes 15-8, lanes 8-15 g1 (each half
+    // of the row written by its own DPP add, the other half's banks masked
+    // off); e8 in all lanes
+    float x;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %1, %1 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %0, %2, %2 row_mirror row_mask:0xf bank_mask:0xc"
+        : "=&v"(x)
+        : "v"(g0), "v"(g1));
     const float y = e8 + dpp_f<0x140>(e8);
     // half-row mirror: lanes 0-3 (8-11) pair x with lanes 7-4 (15-12), lanes 4-7 (12-15) y
-    float z = (q ? x : y) + dpp_f<0x141>(q ? y : x);
+    float z;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %0, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xa"
+        : "=&v"(z)
+        : "v"(x), "v"(y));
     z += dpp_f<0x4E>(z);  // quad lane ^ 2
     z += dpp_f<0xB1>(z);  // quad lane ^ 1
     return z;
@@ -500,6 +560,7 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     const int comp0 = ((row & 1) << 1) | (row >> 1);
     const bool alane = lr == 0 || lr == 4 || lr == 8;
     const int comp = lr == 0 ? comp0 : (lr == 8 ? 4 + comp0 : 8 + row);
+    const uint32_t comp_off = (uint32_t)comp * (uint32_t)sizeof(float);  // bytes into the record
     const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
     const float fa = lr == 0 ? fac0 : (lr == 8 && comp0 == 0 ? -0.5f : 0.0f);
     const float fb = lr == 0 ? 0.0f : (lr == 8 && comp0 == 0 ? 0.0f : 1.0f);
@@ -529,8 +590,11 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
         // entries past this wave's last contributor need no work
         const int jend = wave_nc > rel0 ? (int)min((uint32_t)cnt, wave_nc - rel0) : 0;
         // the adjoint of one blending step with splat j; gid: its splat id
-        auto step = [&](int j, uint32_t gid, auto rows_tag) {
-            constexpr bool RI = decltype(rows_tag)::value;
+        // tag bit 0: the square holds every row of the tile; bit 1: the splat's
+        // opacity may reach the 0.99 clamp
+        auto step = [&](int j, uint32_t gid, auto tag) {
+            constexpr bool RI = (decltype(tag)::value & 1) != 0;
+            constexpr bool CL = (decltype(tag)::value & 2) != 0;
             float qa2, qc2;
             const Splat s = to_splat_wide(s_sp[j], qa2, qc2);
             const ColTerm c = eval_col(s, px, pxc);
@@ -567,7 +631,7 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
                 e7 = __builtin_fmaf(G1[k], w, e7);
                 e8 = __builtin_fmaf(G2[k], w, e8);
                 // no gradient through the 0.99 clamp (da is finite: alpha <= 0.99)
-                const float gz = (ok && !clamped) ? Gk : 0.0f;
+                const float gz = (ok && !(CL && clamped)) ? Gk : 0.0f;
                 const float q = da * gz;  // dL/dopacity share; dL/dpower = opacity * q
                 const float qdy = q * dy;
                 e5 += q;
@@ -583,27 +647,27 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
             const float e0 = __builtin_fmaf(qa2, A, s.qb * sdy);
             const float e1 = __builtin_fmaf(s.qb, A, qc2 * sdy);
             const float e2 = c.dx * A, e3 = c.dx * sdy, e4 = syy;
-            if (__ballot(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
+            if (__builtin_amdgcn_ballot_w64(any) != 0ull) {  // wave-uniform: reduce only when some lane blended
                 const float h = wave_sum9(e0, e1, e2, e3, e4, e5, e6, e7, e8);
                 // the cross-lane operations need the whole wave: consume their
                 // result here, before the lane-divergent atomic below
                 asm volatile("" ::"v"(h));
                 if (alane) {
-                    float* const rec = ((MERGE && (gid & kFromStatic)) ? g2s : g2) +
-                                       (size_t)(gid & ~kFromStatic) * kG2Stride;
-                    atomicAdd(rec + comp, h * __builtin_fmaf(fa, s.op, fb));
+                    char* const rec = reinterpret_cast<char*>(((MERGE && (gid & kFromStatic)) ? g2s : g2) +
+                                                              (size_t)(gid & ~kFromStatic) * kG2Stride);
+                    atomicAdd(reinterpret_cast<float*>(rec + comp_off), h * __builtin_fmaf(fa, s.op, fb));
                 }
             }
         };
         // splats whose square holds all of the tile's rows take the step without
-        // the row test; the group's splat ids sit one per lane and reach the
-        // step as wave-uniform values
+        // the row test, those whose opacity stays below the clamp without the
+        // clamp test; the group's splat ids sit one per lane and reach the step
+        // as wave-uniform values
         for (int g0 = 0; g0 < jend; g0 += 64) {
             const int gn = min(64, jend - g0);
             const uint32_t gids = s_sp[g0 + min(lane, gn - 1)].gid;
-            walk_runs(rows_in_mask(s_sp, g0, gn), gn, [&](int i, auto tag) {
+            walk_runs2(rows_in_mask(s_sp, g0, gn), clamp_mask(s_sp, g0, gn), gn, [&](int i, auto tag) {
                 step(g0 + i, (uint32_t)__builtin_amdgcn_readlane((int)gids, i), tag);
-                return false;
             });
         }
         rel0 += (uint32_t)cnt;

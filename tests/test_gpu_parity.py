@@ -459,3 +459,46 @@ def test_raw_quaternions_forward_and_backward(h4d, seed):
             q = (scene.g4 if gr is gr4 else scene.g3)[k].astype(np.float64)
             dot = np.abs((g * q).sum(0))
             assert dot.max() <= 1e-5 * np.abs(g).max() * np.abs(q).max(), k
+
+
+# ---------------------------------------------------------------------------
+# opacities that reach the 0.99 alpha clamp
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile,chunk", [(16, 64), (8, 64), (32, 256)])
+def test_clamped_alpha_forward_and_backward(h4d, tile, chunk):
+    """Half of the 3D Gaussians (and of the 4D ones) get opacity logits of 5-7
+    (opacity 0.993-0.999), so that pairs near their centres take the 0.99
+    alpha clamp (Sec. 4.3, the 3DGS-lineage blending constants) and carry no
+    gradient through it, while pairs further out and the other Gaussians
+    blend unclamped; the adjoint runs its clamp test only for splats whose
+    opacity can reach the clamp.  Image and every gradient against the oracle
+    (upstream zeroed at flagged pixels)."""
+    print(f"[clamped alpha] tile {tile} chunk {chunk}", flush=True)
+    scene = sg.tiny_scene(seed=7)
+    rng = np.random.default_rng(77)
+    g3, g4 = dict(scene.g3), dict(scene.g4)
+    for d in (g3, g4):
+        op = d["opacity"].astype(np.float64).copy()
+        hi = rng.random(op.shape[0]) < 0.5
+        op[hi] = rng.uniform(5.0, 7.0, size=int(hi.sum()))
+        d["opacity"] = op.astype(np.float32)
+    scene = sg.Scene(g3, g4, list(scene.views), name=scene.name + "_opaque", time_period=scene.time_period)
+    v = scene.views[0]
+    # pairs whose alpha the clamp cuts (pixel centres next to a splat centre,
+    # from the oracle's projection, occlusion aside)
+    P = oracle.project(scene, v)
+    n_clamped = 0
+    for g in np.nonzero((P["visible"] > 0) & (P["culled"] == 0) & (P["op"] > 0.99))[0]:
+        i, j = np.meshgrid(np.arange(-2, 3) + np.floor(P["u"][g]), np.arange(-2, 3) + np.floor(P["v"][g]))
+        dx, dy = i + 0.5 - P["u"][g], j + 0.5 - P["v"][g]
+        pw = -0.5 * (P["q00"][g] * dx * dx + 2 * P["q01"][g] * dx * dy + P["q11"][g] * dy * dy)
+        n_clamped += int((P["op"][g] * np.exp(pw) > 0.99).sum())
+    assert n_clamped > 50, n_clamped
+    ref = oracle.render(scene, v)
+    _, _, _, h = _render(h4d, scene, [v], tile=tile, chunk=chunk)
+    _check_image(h.images[0].cpu().numpy(), ref["img"], ref["amb"])
+    dl = [mask_flagged(sg.upstream_grads([v], seed=50)[0], ref["amb"])]
+    gr3, gr4 = _grads_gpu(h4d, scene, [v], dl, tile=tile, chunk=chunk)
+    r3, r4 = oracle.render_bwd(scene, [v], dl)
+    _check_grads(scene, gr3, gr4, r3, r4, np.zeros(scene.n3 + scene.n4, bool))
