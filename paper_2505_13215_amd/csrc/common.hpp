@@ -19,6 +19,7 @@ constexpr double kMinAlphaD = 1.0 / 255.0;
 constexpr float kMaxAlpha = 0.99f;
 constexpr float kMinT = 1e-4f;
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kLn2 = 0.6931471805599453;  // 1 / log2(e)
 
 constexpr int kMaxViews = 32;
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
@@ -89,8 +90,9 @@ struct SegLayout {
 };
 
 // Screen-space gradients of one (view, Gaussian) from the blending adjoint:
-// du dv dQ00 dQ01 dQ11 dop dr dg (conic entries unscaled, Q01 counted once)
-// and db as four parts (slots 8-11, one per 16-lane row of the adjoint's
+// du dv dQ00 dQ01 dQ11 dop dr dg (conic entries unscaled, Q01 counted once;
+// the first five summed without their constant factors and the effective
+// opacity, which the projection adjoint applies) and db as four parts (slots 8-11, one per 16-lane row of the adjoint's
 // reduction; their sum is db), padded to one 64-byte record so that a splat's
 // atomic additions touch a single cache line.  Layout [view][N][kG2Stride].
 // The forward zeroes the records of its on-screen (view, Gaussian) pairs; with
@@ -170,10 +172,11 @@ struct SetStats {
     uint8_t* step_vis;
 };
 
-// One view's share: the image-plane gradient (pixels) of the centre, e0 and e1,
-// scaled to normalised device coordinates (half the image size per unit).
-__device__ inline double ndc_grad_norm(float e0, float e1, int W, int H) {
-    const double gx = (double)e0 * (0.5 * (double)W), gy = (double)e1 * (0.5 * (double)H);
+// One view's share: the image-plane gradient (pixels) of the centre, scale
+// times (e0, e1), in normalised device coordinates (half the image size per
+// unit).
+__device__ inline double ndc_grad_norm(float e0, float e1, double scale, int W, int H) {
+    const double gx = (double)e0 * scale * (0.5 * (double)W), gy = (double)e1 * scale * (0.5 * (double)H);
     return sqrt(gx * gx + gy * gy);
 }
 

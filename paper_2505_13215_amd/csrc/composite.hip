@@ -17,7 +17,7 @@
 // wave by reduce-scatter (lane-half and row swaps, DPP mirrors, quad sums; skipped
 // when no lane blended the splat) and added to HBM with one global atomic
 // instruction per (splat, wave), a lane per record slot.  Constant factors of the conic and centre
-// gradients are applied once per splat after the reduction.  Each wave stops
+// gradients, and the splat's opacity, are applied where the record is read.  Each wave stops
 // at its own last contributor.
 #include <hip/hip_ext.h>
 #include <type_traits>
@@ -546,24 +546,24 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     // entries)
     const uint32_t total = s_max;
     const uint32_t wave_nc = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_nc));
-    const float kinv = -1.0f / kLog2e;
     unsigned long long n_eval = 0, n_blend = 0;
     // after wave_sum9, lane 16 r holds component 0 2 1 3 (r = 0 1 2 3) of g2,
     // lane 16 r + 8 component 4 6 5 7, lane 16 r + 4 row r's part of
     // component 8, which goes to slot 8 + r of the record (the four parts are
     // summed where the record is read).  One atomic instruction of these
     // twelve lanes adds them to the splat's record, no two to one address.  The
-    // constant factors: du, dv -1/log2 e; dQ00, dQ11 -1/2; dQ01 -1; the rest 1;
-    // the centre and conic sums also take the splat's opacity (their per-pixel
-    // terms are summed without it), so a lane's factor is fa * opacity + fb.
+    // centre and conic slots hold their sums without the constant factors and
+    // the splat's opacity, which the projection adjoint applies where it reads
+    // the record (once per record instead of once per tile).
     const int row = lane >> 4, lr = lane & 15;
     const int comp0 = ((row & 1) << 1) | (row >> 1);
     const bool alane = lr == 0 || lr == 4 || lr == 8;
     const int comp = lr == 0 ? comp0 : (lr == 8 ? 4 + comp0 : 8 + row);
     const uint32_t comp_off = (uint32_t)comp * (uint32_t)sizeof(float);  // bytes into the record
-    const float fac0 = comp0 <= 1 ? kinv : (comp0 == 2 ? -0.5f : -1.0f);
-    const float fa = lr == 0 ? fac0 : (lr == 8 && comp0 == 0 ? -0.5f : 0.0f);
-    const float fb = lr == 0 ? 0.0f : (lr == 8 && comp0 == 0 ? 0.0f : 1.0f);
+    // raw buffer resources over the records (no range limit; data format 32
+    // bits, the gfx9 word 3): record offsets stay below 2^32 bytes per view
+    const __amdgpu_buffer_rsrc_t g2_rsrc = __builtin_amdgcn_make_buffer_rsrc(g2, (short)0, -1, 0x00020000);
+    const __amdgpu_buffer_rsrc_t g2s_rsrc = __builtin_amdgcn_make_buffer_rsrc(g2s, (short)0, -1, 0x00020000);
     const int tid = (int)threadIdx.x;
     // the forward kept the list's head: a tile whose contributors all lie in
     // it reads them from there, any other walks its list again
@@ -653,9 +653,12 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
                 // result here, before the lane-divergent atomic below
                 asm volatile("" ::"v"(h));
                 if (alane) {
-                    char* const rec = reinterpret_cast<char*>(((MERGE && (gid & kFromStatic)) ? g2s : g2) +
-                                                              (size_t)(gid & ~kFromStatic) * kG2Stride);
-                    atomicAdd(reinterpret_cast<float*>(rec + comp_off), h * __builtin_fmaf(fa, s.op, fb));
+                    // buffer atomic: the view's records as the resource, the
+                    // record's offset (scalar) and the lane's slot (vector) added
+                    // by the address unit
+                    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(
+                        h, (MERGE && (gid & kFromStatic)) ? g2s_rsrc : g2_rsrc, (int)comp_off,
+                        (int)((gid & ~kFromStatic) * (uint32_t)(kG2Stride * sizeof(float))), 0);
                 }
             }
         };

@@ -353,7 +353,8 @@ __global__ void __launch_bounds__(256) k_preprocess(G3Ptr g3, G4Ptr g4, const Vi
 // (no atomics: every view's contribution to a Gaussian lands in one lane).
 // g2: per (view, Gaussian) screen-space gradients from the blending adjoint,
 // layout [view][N][kG2Stride]: du dv dQ00 dQ01 dQ11 dop dr dg, then db as
-// four parts (w.r.t. the unscaled conic entries, Q01 counted once).
+// four parts (w.r.t. the unscaled conic entries, Q01 counted once; the first
+// five without their factors -op / log2 e, -op / log2 e, -op / 2, -op, -op / 2).
 //
 // Per view the projection adjoint gives mu_c-bar, Sigma_c-bar and op-bar; the
 // slicing adjoint maps them to the spatial/temporal means and to the symmetric
@@ -367,8 +368,12 @@ template <bool TIME>
 __device__ inline void proj_bwd(const ViewParams& V, const WorldF& w, const ProjF& p, const float* shp, int shn,
                                 int shi, const float* g2, size_t gstride, double gmu[3], double Sb[3][3],
                                 double& gop, float* gsh, const TimeColour* tc = nullptr, double* gmt = nullptr) {
-    const double gu = g2[0], gv = g2[gstride], gQa = g2[2 * gstride], gQb = g2[3 * gstride],
-                 gQc = g2[4 * gstride];
+    // the blending adjoint sums the centre and conic terms without their
+    // constant factors and the effective opacity: du, dv take -op / log2 e,
+    // dQ00, dQ11 -op / 2, dQ01 -op
+    const double ku = -kLn2 * w.op, kq = -0.5 * w.op;
+    const double gu = ku * g2[0], gv = ku * g2[gstride], gQa = kq * g2[2 * gstride], gQb = -w.op * g2[3 * gstride],
+                 gQc = kq * g2[4 * gstride];
     gop = g2[5 * gstride];
     const double grgb[3] = {g2[6 * gstride], g2[7 * gstride],
                             (double)g2[8 * gstride] + g2[9 * gstride] + g2[10 * gstride] + g2[11 * gstride]};
@@ -504,11 +509,6 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
     for (int v = 0; v < n_views; ++v) {
         if (recs[(size_t)v * N + i].d.w == 0u) continue;  // covers no pixel in this view
         const ViewParams& V = views[v];
-        if (st.grad || st.vis || st.step_vis) {
-            const float* e = g2 + ((size_t)v * N + i) * kG2Stride;
-            stat_g += ndc_grad_norm(e[0], e[1], V.W, V.H);
-            ++stat_n;
-        }
         const double delta = V.time - mt;
         const double pt = exp(-(delta * delta) * 0.5 * ic);
         WorldF w;
@@ -516,6 +516,11 @@ __device__ inline void bwd_4d(const G4Ptr& g4, int i, const ViewParams* __restri
         for (int r = 0; r < 3; ++r)
             for (int k = 0; k < 3; ++k) w.S[r][k] = S4[r][k] - b[r] * b[k] * ic;
         w.op = sig * pt;
+        if (st.grad || st.vis || st.step_vis) {
+            const float* e = g2 + ((size_t)v * N + i) * kG2Stride;
+            stat_g += ndc_grad_norm(e[0], e[1], kLn2 * w.op, V.W, V.H);
+            ++stat_n;
+        }
         ProjF p;
         project(V, w, p);
         double gmc[3], Sb[3][3], gop;
@@ -628,14 +633,14 @@ __device__ inline void bwd_3d(const G3Ptr& g3, int i, int gidx, const ViewParams
         if (static_rows || V.static_next < 0) {
             direct = g2 + ((size_t)v * N + gidx) * kG2Stride;
             if (st.grad || st.vis || st.step_vis) {
-                stat_g += ndc_grad_norm(direct[0], direct[1], V.W, V.H);
+                stat_g += ndc_grad_norm(direct[0], direct[1], kLn2 * w.op, V.W, V.H);
                 ++stat_n;
             }
         }
         for (int u = direct ? -1 : v; u >= 0; u = views[u].static_next) {
             const float* g = g2 + ((size_t)u * N + gidx) * kG2Stride;
             if (st.grad || st.vis || st.step_vis) {
-                stat_g += ndc_grad_norm(g[0], g[1], views[u].W, views[u].H);
+                stat_g += ndc_grad_norm(g[0], g[1], kLn2 * w.op, views[u].W, views[u].H);
                 ++stat_n;
             }
             for (int k = 0; k < kG2Slots; ++k) e[k] += g[k];
