@@ -128,18 +128,18 @@ __device__ __forceinline__ unsigned long long clamp_mask(const LSplat* sp, int g
     return __builtin_amdgcn_ballot_w64(lane < n && sp[g0 + lane].op >= kClampOp);
 }
 
-// The adjoint's walk: calls step(j, tag) for j = 0 .. n-1 in order, tag =
-// std::integral_constant<int, f> with bit 0 of f set where bit j of rin is, bit
-// 1 where bit j of clp is; each run of equal flags goes through its own counted
-// loop.
-template <class F>
-__device__ __forceinline__ void walk_runs2(unsigned long long rin, unsigned long long clp, int n, F&& step) {
-    int j = 0;
+// The adjoint's walk: calls step(j, tag) for j = j0 .. n-1 in order, tag =
+// std::integral_constant<int, f | X> with bit 0 of f set where bit j of rin is,
+// bit 1 where bit j of clp is; each run of equal flags goes through its own
+// counted loop.
+template <int X, class F>
+__device__ __forceinline__ void walk_runs2(unsigned long long rin, unsigned long long clp, int j0, int n, F&& step) {
+    int j = j0;
     while (j < n) {
-        for (const int e = next_set(~rin | clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 1>{});
-        for (const int e = next_set(rin | clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 0>{});
-        for (const int e = next_set(~rin | ~clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 3>{});
-        for (const int e = next_set(rin | ~clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 2>{});
+        for (const int e = next_set(~rin | clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 1 | X>{});
+        for (const int e = next_set(rin | clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 0 | X>{});
+        for (const int e = next_set(~rin | ~clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 3 | X>{});
+        for (const int e = next_set(rin | ~clp, j, n); j < e; ++j) step(j, std::integral_constant<int, 2 | X>{});
     }
 }
 
@@ -187,6 +187,11 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // Largest value over the wave.
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    return v;
+}
+// Smallest value over the wave.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off));
     return v;
 }
 
@@ -517,7 +522,7 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     int py[PPL];
     float pyc[PPL], G0[PPL], G1[PPL], G2[PPL], R[PPL], T[PPL];
     uint32_t nc[PPL];
-    uint32_t lane_nc = 0;
+    uint32_t lane_nc = 0, lane_min = 0xFFFFFFFFu;  // (the latter over the pixels inside the image)
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int p = (int)threadIdx.x + k * NT;
@@ -533,6 +538,7 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
             const float c2 = Cout[3 * (size_t)V.pix_base + 2 * HW + q];
             R[k] = G0[k] * c0 + G1[k] * c1 + G2[k] * c2;  // dot(dL/dC, C_out)
             nc[k] = ncontrib[(size_t)V.pix_base + q];
+            lane_min = min(lane_min, nc[k]);
         }
         T[k] = 1.0f;
         lane_nc = max(lane_nc, nc[k]);
@@ -546,6 +552,10 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
     // entries)
     const uint32_t total = s_max;
     const uint32_t wave_nc = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_nc));
+    // entries before the smallest last contributor of the wave's pixels in the
+    // image have every pixel live; pixels outside the image have no upstream
+    // gradient and R = 0, so that their terms are exact zeros in any case
+    const uint32_t wave_min = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32(lane_min));
     unsigned long long n_eval = 0, n_blend = 0;
     // after wave_sum9, lane 16 r holds component 0 2 1 3 (r = 0 1 2 3) of g2,
     // lane 16 r + 8 component 4 6 5 7, lane 16 r + 4 row r's part of
@@ -595,6 +605,7 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
         auto step = [&](int j, uint32_t gid, auto tag) {
             constexpr bool RI = (decltype(tag)::value & 1) != 0;
             constexpr bool CL = (decltype(tag)::value & 2) != 0;
+            constexpr bool AL = (decltype(tag)::value & 4) != 0;  // every pixel live
             float qa2, qc2;
             const Splat s = to_splat_wide(s_sp[j], qa2, qc2);
             const ColTerm c = eval_col(s, px, pxc);
@@ -609,7 +620,7 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
             for (int k = 0; k < PPL; ++k) {
                 float dy, Gk, alpha;
                 bool clamped;
-                const bool live = rel0 + (uint32_t)j < nc[k];
+                const bool live = AL || rel0 + (uint32_t)j < nc[k];
                 const bool in = square_test<RI>(s, c, py[k]);
                 const bool pass = eval_pix(s, c, in, pyc[k], dy, Gk, alpha, clamped);
                 const bool ok = pass && live;
@@ -664,14 +675,28 @@ __global__ void __launch_bounds__(Shape<B>::NT, 5) k_composite_bwd(
         };
         // splats whose square holds all of the tile's rows take the step without
         // the row test, those whose opacity stays below the clamp without the
-        // clamp test; the group's splat ids sit one per lane and reach the step
-        // as wave-uniform values
+        // clamp test; in the merging launches (many more tiles than wave slots,
+        // bound by instruction throughput) those before the wave's smallest last
+        // contributor also without the live test (a single view's launch, bound
+        // by its longest tiles, ran 2 % slower with the extra variants; the
+        // counting instances keep the test, whose counts include it); the
+        // group's splat ids sit one per lane and reach the step as wave-uniform
+        // values
         for (int g0 = 0; g0 < jend; g0 += 64) {
             const int gn = min(64, jend - g0);
             const uint32_t gids = s_sp[g0 + min(lane, gn - 1)].gid;
-            walk_runs2(rows_in_mask(s_sp, g0, gn), clamp_mask(s_sp, g0, gn), gn, [&](int i, auto tag) {
+            const unsigned long long rin = rows_in_mask(s_sp, g0, gn), clp = clamp_mask(s_sp, g0, gn);
+            const auto run = [&](int i, auto tag) {
                 step(g0 + i, (uint32_t)__builtin_amdgcn_readlane((int)gids, i), tag);
-            });
+            };
+            if constexpr (MERGE && !STATS) {
+                const int jall =
+                    (int)max((int64_t)0, min((int64_t)gn, (int64_t)wave_min - (int64_t)(rel0 + (uint32_t)g0)));
+                walk_runs2<4>(rin, clp, 0, jall, run);
+                walk_runs2<0>(rin, clp, jall, gn, run);
+            } else {
+                walk_runs2<0>(rin, clp, 0, gn, run);
+            }
         }
         rel0 += (uint32_t)cnt;
     }
